@@ -1,0 +1,194 @@
+"""Python access to the plain FP64 CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may use it; the product path never does.  This wrapper
+imports nothing from the GPU package: systems are passed as any object with
+the attributes parent, jtype, E_T, r_T, axis, mass, com, Ic (numpy arrays).
+
+ctypes releases the GIL during foreign calls, so ``map_threads`` runs
+independent systems on several host cores.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SOURCES = [os.path.join(_HERE, "aba_oracle.c")]
+DEPS = SOURCES + [os.path.join(_HERE, "aba_fwd.inc"), os.path.join(_HERE, "oracle.h")]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (portable -O2, no host-specific ISA)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp,
+                               *SOURCES, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        for name in ("orc_nq", "orc_nv", "orc_nu"):
+            getattr(L, name).restype = ctypes.c_int
+            getattr(L, name).argtypes = [P]
+        L.orc_fd.argtypes = [P, P, P, P, P]
+        L.orc_fd_c.argtypes = [P, P, P, P, P]
+        L.orc_fd_vjp.argtypes = [P, P, P, P, P, P, P, P]
+        L.orc_step.argtypes = [P, P, P, P, ctypes.c_double, P, P]
+        L.orc_rollout.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int, P, P, P]
+        L.orc_rollout.restype = ctypes.c_int
+        L.orc_rollout_c.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int, P, P]
+        L.orc_rollout_c.restype = ctypes.c_int
+        L.orc_rollout_grad.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_int, P, P, P, P, P, P, P, P]
+        L.orc_rollout_grad.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class _CModel(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int),
+                ("parent", ctypes.c_void_p), ("jtype", ctypes.c_void_p),
+                ("E_T", ctypes.c_void_p), ("r_T", ctypes.c_void_p),
+                ("axis", ctypes.c_void_p), ("mass", ctypes.c_void_p),
+                ("com", ctypes.c_void_p), ("Ic", ctypes.c_void_p),
+                ("gravity", ctypes.c_void_p)]
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Model:
+    """An articulated system prepared for the oracle (FP64 copies)."""
+
+    def __init__(self, system, gravity=(0.0, -9.81, 0.0)):
+        f = lambda x: np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        self.parent = np.ascontiguousarray(np.asarray(system.parent, dtype=np.int32))
+        self.jtype = np.ascontiguousarray(np.asarray(system.jtype, dtype=np.int32))
+        self.E_T = f(system.E_T).reshape(-1)
+        self.r_T = f(system.r_T).reshape(-1)
+        self.axis = f(system.axis).reshape(-1)
+        self.mass = f(system.mass).reshape(-1)
+        self.com = f(system.com).reshape(-1)
+        self.Ic = f(system.Ic).reshape(-1)
+        self.gravity = f(gravity).reshape(3)
+        self.c = _CModel(int(self.parent.shape[0]), _p(self.parent), _p(self.jtype),
+                         _p(self.E_T), _p(self.r_T), _p(self.axis), _p(self.mass),
+                         _p(self.com), _p(self.Ic), _p(self.gravity))
+        self.ref = ctypes.byref(self.c)
+        L = lib()
+        self.nq, self.nv, self.nu = L.orc_nq(self.ref), L.orc_nv(self.ref), L.orc_nu(self.ref)
+
+
+def _f64(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if n is not None:
+        assert a.size == n, (a.size, n)
+    return a
+
+
+def _c128(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.complex128))
+    if n is not None:
+        assert a.size == n, (a.size, n)
+    return a
+
+
+def fd(m: Model, q, qd, tau):
+    """Forward dynamics qdd = FD(q, qd, tau)."""
+    q, qd, tau = _f64(q, m.nq), _f64(qd, m.nv), _f64(tau, m.nu)
+    out = np.zeros(m.nv)
+    lib().orc_fd(m.ref, _p(q), _p(qd), _p(tau), _p(out))
+    return out
+
+
+def fd_complex(m: Model, q, qd, tau):
+    q, qd, tau = _c128(q, m.nq), _c128(qd, m.nv), _c128(tau, m.nu)
+    out = np.zeros(m.nv, dtype=np.complex128)
+    lib().orc_fd_c(m.ref, _p(q), _p(qd), _p(tau), _p(out))
+    return out
+
+
+def fd_vjp(m: Model, q, qd, tau, qdd_bar):
+    """Reverse mode of one forward-dynamics evaluation."""
+    q, qd, tau, qb = _f64(q, m.nq), _f64(qd, m.nv), _f64(tau, m.nu), _f64(qdd_bar, m.nv)
+    gq, gqd, gt = np.zeros(m.nq), np.zeros(m.nv), np.zeros(m.nu)
+    lib().orc_fd_vjp(m.ref, _p(q), _p(qd), _p(tau), _p(qb), _p(gq), _p(gqd), _p(gt))
+    return gq, gqd, gt
+
+
+def step(m: Model, q, qd, tau, dt):
+    q, qd, tau = _f64(q, m.nq), _f64(qd, m.nv), _f64(tau, m.nu)
+    q1, qd1 = np.zeros(m.nq), np.zeros(m.nv)
+    lib().orc_step(m.ref, _p(q), _p(qd), _p(tau), float(dt), _p(q1), _p(qd1))
+    return q1, qd1
+
+
+def rollout(m: Model, q0, qd0, tau, dt, traj: bool = False):
+    """T-step rollout; tau is [T, nu].  Returns qT, qdT (and traj [T, nq+nv])."""
+    tau = _f64(tau).reshape(-1, m.nu) if m.nu else np.zeros((np.asarray(tau).shape[0], 0))
+    T = tau.shape[0]
+    q0, qd0 = _f64(q0, m.nq), _f64(qd0, m.nv)
+    qT, qdT = np.zeros(m.nq), np.zeros(m.nv)
+    tr = np.zeros((T, m.nq + m.nv)) if traj else None
+    rc = lib().orc_rollout(m.ref, _p(q0), _p(qd0), _p(np.ascontiguousarray(tau)), float(dt), T,
+                           _p(qT), _p(qdT), _p(tr) if traj else None)
+    if rc != 0:
+        raise RuntimeError("oracle rollout failed")
+    return (qT, qdT, tr) if traj else (qT, qdT)
+
+
+def rollout_complex(m: Model, q0, qd0, tau, dt):
+    tau = _c128(tau).reshape(-1, m.nu)
+    T = tau.shape[0]
+    q0, qd0 = _c128(q0, m.nq), _c128(qd0, m.nv)
+    qT, qdT = np.zeros(m.nq, dtype=np.complex128), np.zeros(m.nv, dtype=np.complex128)
+    rc = lib().orc_rollout_c(m.ref, _p(q0), _p(qd0), _p(np.ascontiguousarray(tau)), float(dt),
+                             T, _p(qT), _p(qdT))
+    if rc != 0:
+        raise RuntimeError("oracle complex rollout failed")
+    return qT, qdT
+
+
+def rollout_grad(m: Model, q0, qd0, tau, dt, gqT, gqdT, gtraj=None, K: int = 1):
+    """Adjoint-method gradient of <gqT, q^T> + <gqdT, qd^T> + <gtraj, traj>
+    with respect to (q0, qd0, tau).  K >= 1: checkpoint every K steps;
+    K == 0: store every step's intermediates.  Returns gq0, gqd0, gtau, qT, qdT."""
+    tau = np.ascontiguousarray(_f64(tau).reshape(-1, m.nu))
+    T = tau.shape[0]
+    q0, qd0 = _f64(q0, m.nq), _f64(qd0, m.nv)
+    gqT, gqdT = _f64(gqT, m.nq), _f64(gqdT, m.nv)
+    gtr = None if gtraj is None else np.ascontiguousarray(_f64(gtraj).reshape(T, m.nq + m.nv))
+    gq0, gqd0, gtau = np.zeros(m.nq), np.zeros(m.nv), np.zeros((T, m.nu))
+    qT, qdT = np.zeros(m.nq), np.zeros(m.nv)
+    rc = lib().orc_rollout_grad(m.ref, _p(q0), _p(qd0), _p(tau), float(dt), T, int(K),
+                                _p(gqT), _p(gqdT), _p(gtr) if gtr is not None else None,
+                                _p(gq0), _p(gqd0), _p(gtau), _p(qT), _p(qdT))
+    if rc != 0:
+        raise RuntimeError("oracle rollout_grad failed")
+    return gq0, gqd0, gtau, qT, qdT
+
+
+def map_threads(fn, items, threads: int | None = None):
+    """Run fn over items on a thread pool (the C calls release the GIL)."""
+    threads = threads or min(16, os.cpu_count() or 1)
+    if threads <= 1:
+        return [fn(x) for x in items]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, items))

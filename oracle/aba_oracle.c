@@ -1,0 +1,509 @@
+/*
+ * Plain FP64 CPU oracle: ABA forward dynamics, semi-implicit Euler, and the
+ * reverse-time adjoint with checkpointing.  TEST INFRASTRUCTURE ONLY (see
+ * oracle.h): never part of the product path.
+ *
+ * The forward pass (aba_fwd.inc) is instantiated twice: for double and for
+ * double complex (complex-step derivative checks).  The reverse pass below
+ * is real-only.  Every reverse statement is the adjoint of one forward
+ * statement, applied in the exact reverse order of the forward pass
+ * (Sec. 4.1, "Each operation in the forward simulation has its
+ * corresponding adjoint operation in the backward pass"; Sec. 4.2, Eq.
+ * intermediate: recompute Z^k = G(x^{k-1}), then the adjoints of F and G).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "oracle.h"
+
+int orc_nq(const orc_model *m) {
+  int s = 0;
+  for (int i = 0; i < m->n; ++i) s += (m->jtype[i] == ORC_FREE) ? 7 : 1;
+  return s;
+}
+int orc_nv(const orc_model *m) {
+  int s = 0;
+  for (int i = 0; i < m->n; ++i) s += (m->jtype[i] == ORC_FREE) ? 6 : 1;
+  return s;
+}
+int orc_nu(const orc_model *m) {
+  int s = 0;
+  for (int i = 0; i < m->n; ++i) s += (m->jtype[i] == ORC_FREE) ? 0 : 1;
+  return s;
+}
+
+#define CAT_(a, b) a##b
+#define CAT(a, b) CAT_(a, b)
+
+/* real instantiation */
+#define S double
+#define FN(name) CAT(name, _r)
+#define SSIN sin
+#define SCOS cos
+#define SSQRT sqrt
+#include "aba_fwd.inc"
+#undef S
+#undef FN
+#undef SSIN
+#undef SCOS
+#undef SSQRT
+
+/* complex instantiation (analytic continuation; no abs, no comparisons) */
+#define S double complex
+#define FN(name) CAT(name, _c)
+#define SSIN csin
+#define SCOS ccos
+#define SSQRT csqrt
+#include "aba_fwd.inc"
+#undef S
+#undef FN
+#undef SSIN
+#undef SCOS
+#undef SSQRT
+
+typedef link_tape_r tape_t;
+
+/* ---- exported forward entry points ------------------------------------ */
+
+void orc_fd(const orc_model *m, const double *q, const double *qd,
+            const double *tau, double *qdd) {
+  fd_r(m, q, qd, tau, qdd);
+}
+
+void orc_fd_c(const orc_model *m, const void *q, const void *qd,
+              const void *tau, void *qdd) {
+  fd_c(m, (const double complex *)q, (const double complex *)qd,
+       (const double complex *)tau, (double complex *)qdd);
+}
+
+void orc_step(const orc_model *m, const double *q, const double *qd,
+              const double *tau, double dt, double *q1, double *qd1) {
+  const int nv = orc_nv(m);
+  double *qdd = (double *)malloc(sizeof(double) * (size_t)nv);
+  fd_r(m, q, qd, tau, qdd);
+  integrate_r(m, q, qd, qdd, dt, q1, qd1);
+  free(qdd);
+}
+
+int orc_rollout(const orc_model *m, const double *q0, const double *qd0,
+                const double *tau, double dt, int T, double *qT, double *qdT,
+                double *traj) {
+  if (T < 0) return -1;
+  return rollout_r(m, q0, qd0, tau, dt, T, qT, qdT, traj);
+}
+
+int orc_rollout_c(const orc_model *m, const void *q0, const void *qd0,
+                  const void *tau, double dt, int T, void *qT, void *qdT) {
+  if (T < 0) return -1;
+  return rollout_c(m, (const double complex *)q0, (const double complex *)qd0,
+                   (const double complex *)tau, dt, T, (double complex *)qT,
+                   (double complex *)qdT, NULL);
+}
+
+/* ---- reverse mode ----------------------------------------------------- */
+
+typedef struct {
+  double X[36], v[6], vJ[6], c[6], h[6];
+  double IA[36], pA[6], U[6], D, u, Ia[36], pa[6], ap[6], a[6], qdd;
+} link_bar;
+
+/* y += A^T x */
+static void tvec_add(const double *A, const double *x, double *y) {
+  for (int i = 0; i < 6; ++i)
+    for (int k = 0; k < 6; ++k) y[i] += A[6 * k + i] * x[k];
+}
+/* y += A x */
+static void vec_add(const double *A, const double *x, double *y) {
+  for (int i = 0; i < 6; ++i)
+    for (int k = 0; k < 6; ++k) y[i] += A[6 * i + k] * x[k];
+}
+/* M += a b^T */
+static void outer_add(const double *a, const double *b, double *M) {
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) M[6 * i + j] += a[i] * b[j];
+}
+
+/* d R(quat) / d quat_k for R = (w^2 - v.v) I + 2 v v^T + 2 w [v]x. */
+static void quat_R_grad(const double *qt, const double *Rbar, double *qtbar) {
+  double x = qt[0], y = qt[1], z = qt[2], w = qt[3];
+  double v[3] = {x, y, z};
+  for (int k = 0; k < 4; ++k) {
+    double dR[9];
+    if (k < 3) {
+      double e[3] = {0, 0, 0};
+      e[k] = 1;
+      double ex[9];
+      skew3_r(e, ex);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          dR[3 * i + j] = (i == j ? -2.0 * v[k] : 0.0) +
+                          2.0 * (e[i] * v[j] + v[i] * e[j]) + 2.0 * w * ex[3 * i + j];
+    } else {
+      double vx[9];
+      skew3_r(v, vx);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          dR[3 * i + j] = (i == j ? 2.0 * w : 0.0) + 2.0 * vx[3 * i + j];
+    }
+    double s = 0;
+    for (int e = 0; e < 9; ++e) s += Rbar[e] * dR[e];
+    qtbar[k] += s;
+  }
+}
+
+/* Reverse of aba_tape_r: ADD d<qdd_bar, qdd>/d(q, qd, tau). */
+static int aba_vjp(const orc_model *m, const double *q, const double *qd,
+                   const tape_t *L, const double *qdd_bar, double *q_bar,
+                   double *qd_bar, double *tau_bar) {
+  const int n = m->n;
+  int qi[n], vi[n], ui[n];
+  layout_r(m, qi, vi, ui);
+  link_bar *B = (link_bar *)calloc((size_t)n, sizeof(link_bar));
+  if (!B) return -1;
+  const double *g = m->gravity;
+  const double a0[6] = {0, 0, 0, -g[0], -g[1], -g[2]};
+  double E0bar[9] = {0};
+
+  for (int i = 0; i < n; ++i)
+    if (m->jtype[i] != ORC_FREE) B[i].qdd = qdd_bar[vi[i]];
+
+  /* reverse of pass 3, leaves -> root */
+  for (int i = n - 1; i >= 0; --i) {
+    const tape_t *l = &L[i];
+    link_bar *b = &B[i];
+    const int lam = m->parent[i];
+    if (m->jtype[i] == ORC_FREE) {
+      /* abase = ap + [0; E0 g];  a = ap */
+      const double *ab = qdd_bar + vi[i];
+      for (int k = 0; k < 6; ++k) b->ap[k] += ab[k] + b->a[k];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) E0bar[3 * r + c] += ab[3 + r] * g[c];
+      /* ap = -IA^{-1} pA:  w = IA^{-T} ap_bar; pA_bar -= w; IA_bar -= w ap^T */
+      double IAt[36], w[6];
+      mat6_transpose_r(l->IA, IAt);
+      solve6_r(IAt, b->ap, w);
+      for (int k = 0; k < 6; ++k) b->pA[k] -= w[k];
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) b->IA[6 * r + c] -= w[r] * l->ap[c];
+      continue;
+    }
+    const double *ax = m->axis + 3 * i;
+    /* a = ap + S qdd */
+    for (int k = 0; k < 6; ++k) b->ap[k] += b->a[k];
+    b->qdd += ax[0] * b->a[0] + ax[1] * b->a[1] + ax[2] * b->a[2];
+    /* qdd = (u - U^T ap) / D */
+    const double gq = b->qdd / l->D;
+    b->u += gq;
+    for (int k = 0; k < 6; ++k) { b->U[k] -= gq * l->ap[k]; b->ap[k] -= gq * l->U[k]; }
+    b->D -= gq * l->qdd;
+    /* ap = X a_lam + c */
+    const double *al = (lam < 0) ? a0 : L[lam].a;
+    if (lam >= 0) tvec_add(l->X, b->ap, B[lam].a);
+    outer_add(b->ap, al, b->X);
+    for (int k = 0; k < 6; ++k) b->c[k] += b->ap[k];
+  }
+
+  /* reverse of pass 2, root -> leaves */
+  for (int i = 0; i < n; ++i) {
+    if (m->jtype[i] == ORC_FREE) continue;
+    const tape_t *l = &L[i];
+    link_bar *b = &B[i];
+    const int lam = m->parent[i];
+    const double *ax = m->axis + 3 * i;
+    if (lam >= 0) {
+      const link_bar *bl = &B[lam];
+      /* pA_lam += X^T pa */
+      vec_add(l->X, bl->pA, b->pa);
+      outer_add(l->pa, bl->pA, b->X);
+      /* IA_lam += X^T Ia X:  Ia_bar += X IAb X^T;
+         X_bar += Ia X IAb^T + Ia^T X IAb */
+      double T1[36], T2[36], Xt[36], IAbt[36], Iat[36];
+      mat6_transpose_r(l->X, Xt);
+      mat6_mul_r(l->X, bl->IA, T1);
+      mat6_mul_r(T1, Xt, T2);
+      for (int k = 0; k < 36; ++k) b->Ia[k] += T2[k];
+      mat6_transpose_r(bl->IA, IAbt);
+      mat6_transpose_r(l->Ia, Iat);
+      mat6_mul_r(l->Ia, l->X, T1);
+      mat6_mul_r(T1, IAbt, T2);
+      for (int k = 0; k < 36; ++k) b->X[k] += T2[k];
+      mat6_mul_r(Iat, l->X, T1);
+      mat6_mul_r(T1, bl->IA, T2);
+      for (int k = 0; k < 36; ++k) b->X[k] += T2[k];
+      /* pa = pA + Ia c + U u / D */
+      for (int k = 0; k < 6; ++k) b->pA[k] += b->pa[k];
+      outer_add(b->pa, l->c, b->Ia);
+      tvec_add(l->Ia, b->pa, b->c);
+      double Upa = 0;
+      for (int k = 0; k < 6; ++k) { b->U[k] += b->pa[k] * l->u / l->D; Upa += l->U[k] * b->pa[k]; }
+      b->u += Upa / l->D;
+      b->D -= Upa * l->u / (l->D * l->D);
+      /* Ia = IA - U U^T / D */
+      for (int k = 0; k < 36; ++k) b->IA[k] += b->Ia[k];
+      double UIU = 0;
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+          b->U[r] -= (b->Ia[6 * r + c] + b->Ia[6 * c + r]) * l->U[c] / l->D;
+          UIU += l->U[r] * b->Ia[6 * r + c] * l->U[c];
+        }
+      b->D += UIU / (l->D * l->D);
+    }
+    /* u = tau - S^T pA */
+    tau_bar[ui[i]] += b->u;
+    for (int k = 0; k < 3; ++k) b->pA[k] -= ax[k] * b->u;
+    /* D = S^T U */
+    for (int k = 0; k < 3; ++k) b->U[k] += ax[k] * b->D;
+    /* U = IA S */
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 3; ++c) b->IA[6 * r + c] += b->U[r] * ax[c];
+  }
+
+  /* reverse of pass 1, leaves -> root */
+  for (int i = n - 1; i >= 0; --i) {
+    const tape_t *l = &L[i];
+    link_bar *b = &B[i];
+    const int lam = m->parent[i];
+    /* pA(initial) = crf(v) h */
+    double F[36], C[36];
+    crf6_r(l->v, F);
+    tvec_add(F, b->pA, b->h);
+    crm6_r(b->pA, C);
+    tvec_add(C, l->h, b->v);
+    /* h = I v */
+    tvec_add(l->Isp, b->h, b->v);
+    if (m->jtype[i] == ORC_FREE) {
+      for (int k = 0; k < 6; ++k) qd_bar[vi[i] + k] += b->v[k];
+      double Rbar[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Rbar[3 * r + c] = E0bar[3 * c + r];
+      quat_R_grad(q + qi[i] + 3, Rbar, q_bar + qi[i] + 3);
+      continue;
+    }
+    const double *ax = m->axis + 3 * i;
+    /* c = crm(v) vJ */
+    double CJ[36], CJt[36];
+    crm6_r(l->vJ, CJ);
+    mat6_transpose_r(CJ, CJt);
+    for (int r = 0; r < 6; ++r)
+      for (int k = 0; k < 6; ++k) b->v[r] -= CJt[6 * r + k] * b->c[k];
+    crm6_r(l->v, C);
+    tvec_add(C, b->c, b->vJ);
+    /* v = X v_lam + vJ */
+    if (lam >= 0) {
+      tvec_add(l->X, b->v, B[lam].v);
+      outer_add(b->v, L[lam].v, b->X);
+    }
+    for (int k = 0; k < 6; ++k) b->vJ[k] += b->v[k];
+    /* vJ = S qd */
+    qd_bar[vi[i]] += ax[0] * b->vJ[0] + ax[1] * b->vJ[1] + ax[2] * b->vJ[2];
+    /* X = XJ(q) XT:  dX/dq = plucker(dEJ/dq, 0) XT,
+       dEJ/dq = -cos q [a]x + sin q [a]x^2 */
+    {
+      double axx[9], ax2[9], dE[9], zero3[3] = {0, 0, 0}, dXJ[36], XT[36], dX[36];
+      double qq = q[qi[i]], s = sin(qq), c = cos(qq);
+      skew3_r(ax, axx);
+      mat3_mul_r(axx, axx, ax2);
+      for (int k = 0; k < 9; ++k) dE[k] = -c * axx[k] + s * ax2[k];
+      plucker_r(dE, zero3, dXJ);
+      double ET[9], rT[3];
+      for (int k = 0; k < 9; ++k) ET[k] = m->E_T[9 * i + k];
+      for (int k = 0; k < 3; ++k) rT[k] = m->r_T[3 * i + k];
+      plucker_r(ET, rT, XT);
+      mat6_mul_r(dXJ, XT, dX);
+      double sdot = 0;
+      for (int k = 0; k < 36; ++k) sdot += b->X[k] * dX[k];
+      q_bar[qi[i]] += sdot;
+    }
+  }
+  free(B);
+  return 0;
+}
+
+void orc_fd_vjp(const orc_model *m, const double *q, const double *qd,
+                const double *tau, const double *qdd_bar, double *q_bar,
+                double *qd_bar, double *tau_bar) {
+  const int nv = orc_nv(m);
+  tape_t *L = (tape_t *)malloc(sizeof(tape_t) * (size_t)m->n);
+  double *qdd = (double *)malloc(sizeof(double) * (size_t)nv);
+  aba_tape_r(m, q, qd, tau, L, qdd);
+  aba_vjp(m, q, qd, L, qdd_bar, q_bar, qd_bar, tau_bar);
+  free(qdd);
+  free(L);
+}
+
+/* Adjoint of one semi-implicit Euler step taken from x^t = (q, qd) with
+ * forward intermediates L and accelerations qdd.  Input (q1bar, qd1bar) is
+ * the adjoint of x^{t+1}; output (qbar, qdbar) is the adjoint of x^t and
+ * taubar the adjoint of u^t (all overwritten). */
+static int step_vjp(const orc_model *m, const double *q, const double *qd,
+                    const double *qdd, const tape_t *L, double dt,
+                    const double *q1bar, const double *qd1bar, double *qbar,
+                    double *qdbar, double *taubar, double *qddbar) {
+  const int n = m->n, nu = orc_nu(m);
+  int qi[n], vi[n], ui[n];
+  layout_r(m, qi, vi, ui);
+  for (int k = 0; k < nu; ++k) taubar[k] = 0;
+  for (int i = 0; i < n; ++i) {
+    if (m->jtype[i] == ORC_FREE) {
+      const double *p = q + qi[i], *qt = q + qi[i] + 3;
+      (void)p;
+      double v1[6];
+      for (int k = 0; k < 6; ++k) v1[k] = qd[vi[i] + k] + dt * qdd[vi[i] + k];
+      double R[9];
+      quat_R_r(qt, R);
+      double wq[4] = {v1[0], v1[1], v1[2], 0}, dq[4], qr[4], q1[4];
+      quat_mul_r(qt, wq, dq);
+      for (int k = 0; k < 4; ++k) qr[k] = qt[k] + 0.5 * dt * dq[k];
+      double nrm = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+      for (int k = 0; k < 4; ++k) q1[k] = qr[k] / nrm;
+      /* quat1 = qr / |qr| */
+      const double *q1b = q1bar + qi[i] + 3;
+      double dotq = 0, qrbar[4];
+      for (int k = 0; k < 4; ++k) dotq += q1[k] * q1b[k];
+      for (int k = 0; k < 4; ++k) qrbar[k] = (q1b[k] - q1[k] * dotq) / nrm;
+      /* qr = qt + dt/2 * qt (x) (w1, 0) */
+      double *qtb = qbar + qi[i] + 3;
+      for (int k = 0; k < 4; ++k) qtb[k] = qrbar[k];
+      const double h = 0.5 * dt;
+      const double *ob = qrbar; /* ob[0..2] vector part, ob[3] scalar part */
+      const double *w1 = v1;
+      /* o_v = a3 w1 + av x w1; o_w = -av . w1   (a = qt) */
+      double cr[3] = {w1[1] * ob[2] - w1[2] * ob[1], w1[2] * ob[0] - w1[0] * ob[2],
+                      w1[0] * ob[1] - w1[1] * ob[0]}; /* w1 x ob_v */
+      for (int k = 0; k < 3; ++k) qtb[k] += h * (cr[k] - w1[k] * ob[3]);
+      qtb[3] += h * (w1[0] * ob[0] + w1[1] * ob[1] + w1[2] * ob[2]);
+      double v1bar[6];
+      for (int k = 0; k < 6; ++k) v1bar[k] = qd1bar[vi[i] + k];
+      double axo[3] = {qt[1] * ob[2] - qt[2] * ob[1], qt[2] * ob[0] - qt[0] * ob[2],
+                       qt[0] * ob[1] - qt[1] * ob[0]}; /* av x ob_v */
+      for (int k = 0; k < 3; ++k) v1bar[k] += h * (qt[3] * ob[k] - axo[k] - qt[k] * ob[3]);
+      /* p1 = p + dt R(qt) v1_lin */
+      const double *p1b = q1bar + qi[i];
+      for (int k = 0; k < 3; ++k) qbar[qi[i] + k] = p1b[k];
+      double Rbar[9];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Rbar[3 * r + c] = dt * p1b[r] * v1[3 + c];
+      quat_R_grad(qt, Rbar, qtb);
+      for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) v1bar[3 + c] += dt * R[3 * r + c] * p1b[r];
+      /* v1 = v + dt qdd */
+      for (int k = 0; k < 6; ++k) {
+        qdbar[vi[i] + k] = v1bar[k];
+        qddbar[vi[i] + k] = dt * v1bar[k];
+      }
+    } else {
+      const double tot = qd1bar[vi[i]] + dt * q1bar[qi[i]];
+      qddbar[vi[i]] = dt * tot;
+      qbar[qi[i]] = q1bar[qi[i]];
+      qdbar[vi[i]] = tot;
+    }
+  }
+  return aba_vjp(m, q, qd, L, qddbar, qbar, qdbar, taubar);
+}
+
+static void tape_qdd(const orc_model *m, const tape_t *L, double *qdd) {
+  const int n = m->n;
+  int qi[n], vi[n], ui[n];
+  layout_r(m, qi, vi, ui);
+  for (int i = 0; i < n; ++i) {
+    if (m->jtype[i] == ORC_FREE)
+      for (int k = 0; k < 6; ++k) qdd[vi[i] + k] = L[i].abase[k];
+    else
+      qdd[vi[i]] = L[i].qdd;
+  }
+}
+
+int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
+                     const double *tau, double dt, int T, int K,
+                     const double *gqT, const double *gqdT,
+                     const double *gtraj, double *gq0, double *gqd0,
+                     double *gtau, double *qT, double *qdT) {
+  if (T < 0 || K < 0) return -1;
+  const int n = m->n, nq = orc_nq(m), nv = orc_nv(m), nu = orc_nu(m);
+  const int nx = nq + nv;
+  const int ncp = (K >= 1) ? (T + K - 1) / K : 0;
+  double *ck = NULL, *scratch = NULL, *states = NULL;
+  tape_t *tapes = NULL;
+  tape_t *tape = (tape_t *)malloc(sizeof(tape_t) * (size_t)n);
+  double *work = (double *)malloc(sizeof(double) * (size_t)(4 * nx + 3 * nv));
+  if (K >= 1) {
+    ck = (double *)malloc(sizeof(double) * (size_t)(ncp > 0 ? ncp : 1) * nx);
+    scratch = (double *)malloc(sizeof(double) * (size_t)K * nx);
+  } else {
+    states = (double *)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * nx);
+    tapes = (tape_t *)malloc(sizeof(tape_t) * (size_t)(T > 0 ? T : 1) * n);
+  }
+  if (!tape || !work || (K >= 1 && (!ck || !scratch)) || (K == 0 && (!states || !tapes))) {
+    free(tape); free(work); free(ck); free(scratch); free(states); free(tapes);
+    return -1;
+  }
+  double *x = work, *x1 = x + nx, *xb = x1 + nx, *xb1 = xb + nx;
+  double *qdd = xb1 + nx, *qddbar = qdd + nv, *spare = qddbar + nv;
+  (void)spare;
+
+  /* forward sweep: store x^t at every K-th step (or every intermediate) */
+  memcpy(x, q0, sizeof(double) * nq);
+  memcpy(x + nq, qd0, sizeof(double) * nv);
+  for (int t = 0; t < T; ++t) {
+    if (K >= 1 && t % K == 0) memcpy(ck + (size_t)(t / K) * nx, x, sizeof(double) * nx);
+    tape_t *Lt = tape;
+    if (K == 0) {
+      memcpy(states + (size_t)t * nx, x, sizeof(double) * nx);
+      Lt = tapes + (size_t)t * n;
+    }
+    aba_tape_r(m, x, x + nq, tau + (size_t)t * nu, Lt, qdd);
+    integrate_r(m, x, x + nq, qdd, dt, x1, x1 + nq);
+    memcpy(x, x1, sizeof(double) * nx);
+  }
+  if (qT) memcpy(qT, x, sizeof(double) * nq);
+  if (qdT) memcpy(qdT, x + nq, sizeof(double) * nv);
+
+  /* reverse sweep */
+  memcpy(xb, gqT, sizeof(double) * nq);
+  memcpy(xb + nq, gqdT, sizeof(double) * nv);
+  if (gtraj && T > 0)
+    for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(T - 1) * nx + k];
+
+  int rc = 0;
+  if (K >= 1) {
+    for (int s = ncp - 1; s >= 0 && rc == 0; --s) {
+      const int t0 = s * K;
+      const int t1 = (t0 + K < T) ? t0 + K : T;
+      /* replay the segment from its checkpoint */
+      memcpy(scratch, ck + (size_t)s * nx, sizeof(double) * nx);
+      for (int j = 1; j < t1 - t0; ++j) {
+        const double *xp = scratch + (size_t)(j - 1) * nx;
+        double *xn = scratch + (size_t)j * nx;
+        aba_tape_r(m, xp, xp + nq, tau + (size_t)(t0 + j - 1) * nu, tape, qdd);
+        integrate_r(m, xp, xp + nq, qdd, dt, xn, xn + nq);
+      }
+      for (int t = t1 - 1; t >= t0 && rc == 0; --t) {
+        const double *xt = scratch + (size_t)(t - t0) * nx;
+        aba_tape_r(m, xt, xt + nq, tau + (size_t)t * nu, tape, qdd);
+        rc = step_vjp(m, xt, xt + nq, qdd, tape, dt, xb, xb + nq, xb1, xb1 + nq,
+                      gtau + (size_t)t * nu, qddbar);
+        memcpy(xb, xb1, sizeof(double) * nx);
+        if (gtraj && t >= 1)
+          for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(t - 1) * nx + k];
+      }
+    }
+  } else {
+    for (int t = T - 1; t >= 0 && rc == 0; --t) {
+      const double *xt = states + (size_t)t * nx;
+      const tape_t *Lt = tapes + (size_t)t * n;
+      tape_qdd(m, Lt, qdd);
+      rc = step_vjp(m, xt, xt + nq, qdd, Lt, dt, xb, xb + nq, xb1, xb1 + nq,
+                    gtau + (size_t)t * nu, qddbar);
+      memcpy(xb, xb1, sizeof(double) * nx);
+      if (gtraj && t >= 1)
+        for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(t - 1) * nx + k];
+    }
+  }
+  memcpy(gq0, xb, sizeof(double) * nq);
+  memcpy(gqd0, xb + nq, sizeof(double) * nv);
+
+  free(tape); free(work); free(ck); free(scratch); free(states); free(tapes);
+  return rc;
+}

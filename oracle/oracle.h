@@ -1,0 +1,108 @@
+/*
+ * Plain FP64 CPU oracle for articulated-body forward dynamics (ABA),
+ * semi-implicit Euler time stepping and the reverse-time adjoint with
+ * per-step checkpointing.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU path.
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  It shares no code, header, table or helper with the GPU
+ * library; the two meet only through plain arrays produced by the seeded
+ * input generators.
+ *
+ * Everything is written with dense 6x6 matrices and plain loops, in the
+ * order the method states it, so that it can be read against the paper:
+ *   - state x = [q, qdot], control u per step           (Sec. 3, "Articulated
+ *                                                         body dynamics")
+ *   - ABA, three traversals root->leaf, leaf->root,
+ *     root->leaf                                         (Sec. 3; Fig. 1;
+ *                                                         Sec. 4.1, five modules)
+ *   - adjoint recursion R^k through time                 (Sec. 3, Eq. adj_back;
+ *                                                         Sec. 4.1, Eq. adj_r)
+ *   - store the initial state of each step, recompute
+ *     the step's intermediates during backpropagation    (Sec. 4.2,
+ *                                                         Eq. intermediate)
+ *   - checkpoint interval k                              (App. B)
+ *
+ * Conventions (the paper states none; see the readings listed in the design
+ * notes): Featherstone Plucker transforms X = [E 0; -E[r]x E] from parent to
+ * child coordinates, motion vectors [w; v], force vectors [n; f], revolute
+ * joint about a unit axis a with E_J(q) = I - sin q [a]x + (1 - cos q)[a]x^2,
+ * gravity entered as a fictitious base acceleration.
+ *
+ * Free-floating root (joint type 1, only at link 0): q = (p_world[3],
+ * quat[4] stored x,y,z,w), velocity = body-frame spatial velocity [w_b; v_b].
+ * The root is unactuated; tau holds one entry per revolute joint.
+ */
+#ifndef ABA_ORACLE_H
+#define ABA_ORACLE_H
+
+#include <stddef.h>
+
+#define ORC_REVOLUTE 0
+#define ORC_FREE 1
+
+typedef struct {
+  int n;                 /* number of links */
+  const int *parent;     /* parent[i] < i; -1 = attached to the fixed base
+                            (or, for a free root, no parent)               */
+  const int *jtype;      /* ORC_REVOLUTE or ORC_FREE (link 0 only)         */
+  const double *E_T;     /* 9n: fixed rotation parent->joint frame, rowmajor */
+  const double *r_T;     /* 3n: joint origin in parent coordinates          */
+  const double *axis;    /* 3n: unit joint axis in the link frame           */
+  const double *mass;    /* n                                               */
+  const double *com;     /* 3n: centre of mass in the link frame            */
+  const double *Ic;      /* 6n: inertia about the COM: xx yy zz xy xz yz    */
+  const double *gravity; /* 3                                               */
+} orc_model;
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+int orc_nq(const orc_model *m);
+int orc_nv(const orc_model *m);
+int orc_nu(const orc_model *m);
+
+/* Forward dynamics qdd = FD(q, qd, tau).  For a free root the first six
+ * entries of qdd are the body-frame spatial acceleration of the root. */
+void orc_fd(const orc_model *m, const double *q, const double *qd,
+            const double *tau, double *qdd);
+/* Same, complex-valued (used for complex-step derivative checks). */
+void orc_fd_c(const orc_model *m, const void *q, const void *qd,
+              const void *tau, void *qdd);
+
+/* Reverse mode of one forward-dynamics evaluation: given qdd_bar, ADD
+ * d<qdd_bar, qdd>/d(q, qd, tau) into q_bar, qd_bar, tau_bar. */
+void orc_fd_vjp(const orc_model *m, const double *q, const double *qd,
+                const double *tau, const double *qdd_bar, double *q_bar,
+                double *qd_bar, double *tau_bar);
+
+/* One semi-implicit Euler step. */
+void orc_step(const orc_model *m, const double *q, const double *qd,
+              const double *tau, double dt, double *q1, double *qd1);
+
+/* T-step rollout.  tau is [T][nu].  traj (nullable) is [T][nq + nv]:
+ * traj[t] = (q^{t+1}, qd^{t+1}). */
+int orc_rollout(const orc_model *m, const double *q0, const double *qd0,
+                const double *tau, double dt, int T, double *qT, double *qdT,
+                double *traj);
+int orc_rollout_c(const orc_model *m, const void *q0, const void *qd0,
+                  const void *tau, double dt, int T, void *qT, void *qdT);
+
+/* Gradient of a loss L(x^T, traj) through a T-step rollout by the adjoint
+ * method.  K >= 1: store the state every K steps and recompute during the
+ * reverse sweep; K == 0: store every step's intermediates (no recompute).
+ * gtraj may be NULL.  Outputs are overwritten.  qT/qdT (nullable) receive
+ * the final state.  Returns 0 on success, -1 on allocation failure or bad
+ * arguments. */
+int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
+                     const double *tau, double dt, int T, int K,
+                     const double *gqT, const double *gqdT,
+                     const double *gtraj, double *gq0, double *gqd0,
+                     double *gtau, double *qT, double *qdT);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

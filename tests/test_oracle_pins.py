@@ -1,0 +1,403 @@
+"""Pins of the FP64 oracle against things other than itself (CPU only).
+
+Each test ties the oracle to a closed form, an independent textbook
+formalism (world-frame classical Newton-Euler in tests/dyn_ref.py), an
+invariant, or a derivative of the pinned forward map.  Together they are
+chosen so that a dropped term, a wrong sign or index, or a transposed
+operand anywhere in the oracle's ABA, integrator or adjoint fails one of
+them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import dyn_ref as R
+import oracle as O
+from paper_2109_07719_amd import synth
+
+
+def _rand_rot(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    return R._quat_R(q)
+
+
+def _random_tree(parent, rng, random_frames=True):
+    n = len(parent)
+    axis = rng.normal(size=(n, 3))
+    axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+    E_T = np.stack([_rand_rot(rng) if random_frames else np.eye(3) for _ in range(n)])
+    Icd = rng.uniform(0.01, 0.1, (n, 3))
+    Ic = np.concatenate([Icd, rng.uniform(-0.003, 0.003, (n, 3))], axis=1)
+    return synth.System(parent=np.asarray(parent, np.int32), jtype=np.zeros(n, np.int32),
+                        E_T=E_T, r_T=rng.normal(0, 0.4, (n, 3)), axis=axis,
+                        mass=rng.uniform(0.5, 2.0, n), com=rng.uniform(-0.25, 0.25, (n, 3)),
+                        Ic=Ic)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300)
+
+
+# ---------------------------------------------------------------- forward
+
+def all_parent_arrays(n):
+    return itertools.product(*[range(-1, i) for i in range(n)])
+
+
+def test_aba_equals_dense_solve_every_tree_up_to_4_links():
+    """ABA reaches M(q)^-1 (tau - C(q, qd)) exactly (Sec. 3, ABA); M and C
+    from an independent world-frame Newton-Euler.  Every parent array with
+    parent[i] < i for n <= 4 (33 shapes, forests included), random axes,
+    frames, offsets, inertias (with products of inertia) and states."""
+    rng = np.random.default_rng(11)
+    count = 0
+    for n in range(1, 5):
+        for parent in all_parent_arrays(n):
+            s = _random_tree(parent, rng)
+            m = O.Model(s)
+            for _ in range(3):
+                q, qd, tau = rng.normal(0, 1, n), rng.normal(0, 1, n), rng.normal(0, 1, n)
+                assert _rel(O.fd(m, q, qd, tau), R.forward_dynamics(s, q, qd, tau)) < 1e-12
+            count += 1
+    assert count == 33
+
+
+@pytest.mark.parametrize("seed", [2000, 2001, 2002])
+def test_aba_equals_dense_solve_branched_trees(seed):
+    s, q0, qd0, tau = synth.tree_system(seed, 1, random_frames=True)
+    m = O.Model(s)
+    rng = np.random.default_rng(seed)
+    q, qd = rng.normal(0, 1, s.n), rng.normal(0, 1, s.n)
+    assert _rel(O.fd(m, q, qd, tau[0]), R.forward_dynamics(s, q, qd, tau[0])) < 1e-11
+
+
+def test_free_base_dense_solve_and_momentum_balance():
+    """Free-floating root (the quadruped's 19/18 dimensions, Sec. 6.1): the
+    joint rows of inverse dynamics at the oracle's accelerations equal tau,
+    and the six root rows (net wrench of inertial minus gravity forces on
+    the whole tree) vanish -- total momentum changes only by gravity."""
+    for seed in range(3000, 3004):
+        s, q0, qd0, tau = synth.quadruped_system(seed, 1)
+        assert (s.nq, s.nv, s.nu) == (19, 18, 12)
+        rng = np.random.default_rng(seed)
+        qt = rng.normal(size=4)
+        q = q0.copy()
+        q[3:7] = qt / np.linalg.norm(qt)
+        q[7:] = rng.normal(0, 1, 12)
+        qd = rng.normal(0, 1, 18)
+        m = O.Model(s)
+        qdd = O.fd(m, q, qd, tau[0])
+        res = R.inverse_dynamics(s, q, qd, qdd)
+        scale = np.abs(R.inverse_dynamics(s, q, qd, np.zeros(18))).max()
+        assert np.abs(res[:6]).max() < 1e-12 * scale
+        assert np.abs(res[6:] - tau[0]).max() < 1e-12 * scale
+        assert _rel(qdd, R.forward_dynamics(s, q, qd, tau[0])) < 1e-11
+
+
+def _pendulum(m_=1.3, c=0.4, Izz=0.05):
+    return synth.System(parent=np.array([-1], np.int32), jtype=np.zeros(1, np.int32),
+                        E_T=np.eye(3)[None], r_T=np.zeros((1, 3)),
+                        axis=np.array([[0.0, 0.0, 1.0]]), mass=np.array([m_]),
+                        com=np.array([[c, 0.0, 0.0]]), Ic=np.array([[0.01, 0.02, Izz, 0, 0, 0]]))
+
+
+def test_single_pendulum_closed_form():
+    """(Izz + m c^2) th'' = tau - m g c cos(th), th measured from +x, gravity -y."""
+    s = _pendulum()
+    m = O.Model(s)
+    for th, thd, tau in [(0.0, 0.0, 0.0), (0.3, 0.7, 0.5), (-1.2, -2.0, 1.0), (2.0, 5.0, -3.0)]:
+        ref = (tau - 1.3 * 9.81 * 0.4 * np.cos(th)) / (0.05 + 1.3 * 0.4 ** 2)
+        assert abs(O.fd(m, [th], [thd], [tau])[0] - ref) < 1e-13 * max(1, abs(ref))
+
+
+def test_single_pendulum_small_oscillation_period():
+    """Hanging at th = -pi/2, small oscillations have period
+    2 pi sqrt((Izz + m c^2) / (m g c)); checked to O(dt) + O(amplitude^2)."""
+    s = _pendulum()
+    m = O.Model(s)
+    dt, T = 1e-4, 30000
+    q, qd, tr = O.rollout(m, [-np.pi / 2 + 1e-3], [0.0], np.zeros((T, 1)), dt, traj=True)
+    th = tr[:, 0] + np.pi / 2
+    up = np.where((th[:-1] < 0) & (th[1:] >= 0))[0]
+    # linear interpolation of upward zero crossings
+    tc = (up + (-th[up]) / (th[up + 1] - th[up])) * dt
+    period = np.mean(np.diff(tc))
+    ref = 2 * np.pi * np.sqrt((0.05 + 1.3 * 0.16) / (1.3 * 9.81 * 0.4))
+    assert abs(period - ref) / ref < 2e-3
+
+
+def test_double_pendulum_closed_form():
+    """Planar 2R arm (link length l1, COMs c1, c2 on the links): textbook
+    mass matrix, Coriolis and gravity terms."""
+    m1, m2, c1, c2, l1, I1, I2 = 1.1, 0.7, 0.2, 0.3, 0.5, 0.04, 0.03
+    s = synth.System(parent=np.array([-1, 0], np.int32), jtype=np.zeros(2, np.int32),
+                     E_T=np.stack([np.eye(3)] * 2), r_T=np.array([[0, 0, 0], [l1, 0, 0.0]]),
+                     axis=np.array([[0, 0, 1.0], [0, 0, 1.0]]), mass=np.array([m1, m2]),
+                     com=np.array([[c1, 0, 0], [c2, 0, 0.0]]),
+                     Ic=np.array([[0.01, 0.01, I1, 0, 0, 0], [0.01, 0.01, I2, 0, 0, 0]]))
+    m = O.Model(s)
+    g = 9.81
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        q, qd, tau = rng.normal(0, 2, 2), rng.normal(0, 2, 2), rng.normal(0, 2, 2)
+        M11 = I1 + I2 + m1 * c1 ** 2 + m2 * (l1 ** 2 + c2 ** 2 + 2 * l1 * c2 * np.cos(q[1]))
+        M12 = I2 + m2 * (c2 ** 2 + l1 * c2 * np.cos(q[1]))
+        M22 = I2 + m2 * c2 ** 2
+        h = m2 * l1 * c2 * np.sin(q[1])
+        C = np.array([-h * (2 * qd[0] * qd[1] + qd[1] ** 2), h * qd[0] ** 2])
+        G = np.array([(m1 * c1 + m2 * l1) * g * np.cos(q[0]) + m2 * c2 * g * np.cos(q[0] + q[1]),
+                      m2 * c2 * g * np.cos(q[0] + q[1])])
+        ref = np.linalg.solve(np.array([[M11, M12], [M12, M22]]), tau - C - G)
+        assert _rel(O.fd(m, q, qd, tau), ref) < 1e-12
+
+
+def test_gravity_along_joint_axes_is_inert():
+    """With gravity along the z joint axes of a planar chain, gravity does no
+    work: the accelerations equal those with zero gravity."""
+    s, q0, qd0, tau = synth.chain_system(7, 0, 1)
+    a = O.fd(O.Model(s, gravity=(0, 0, -9.81)), q0, qd0, tau[0])
+    b = O.fd(O.Model(s, gravity=(0, 0, 0)), q0, qd0, tau[0])
+    assert _rel(a, b) < 1e-13
+
+
+def test_energy_drift_is_first_order_in_dt():
+    """Semi-implicit Euler on a passive chain: the largest energy deviation
+    over 1 s shrinks linearly with dt (ratio 0.5 +- 0.15 per halving)."""
+    s, q0, qd0, _ = synth.chain_system(7, 0, 1)
+    m = O.Model(s)
+    q0 = q0 + 0.5
+    E0 = R.energy(s, q0, qd0)
+    drifts = []
+    for dt in (1e-3, 5e-4, 2.5e-4):
+        T = int(round(1.0 / dt))
+        _, _, tr = O.rollout(m, q0, qd0, np.zeros((T, 7)), dt, traj=True)
+        idx = np.linspace(0, T - 1, 200).astype(int)
+        drifts.append(max(abs(R.energy(s, tr[k, :7], tr[k, 7:]) - E0) for k in idx))
+    for a, b in zip(drifts, drifts[1:]):
+        assert 0.35 < b / a < 0.65, drifts
+
+
+# ---------------------------------------------------------------- adjoint
+
+def test_single_step_tau_bar_is_Minv_qdd_bar():
+    """dqdd/dtau = M^-1, so the reverse ABA must return tau_bar = M^-1 qdd_bar
+    (M from the independent Newton-Euler)."""
+    rng = np.random.default_rng(3)
+    for parent in [(-1, 0, 1, 2, 3, 4, 5), (-1, 0, 0, 1, 1, 2, -1, 6)]:
+        s = _random_tree(parent, rng)
+        m = O.Model(s)
+        q, qd, tau = rng.normal(0, 1, s.n), rng.normal(0, 1, s.n), rng.normal(0, 1, s.n)
+        qb = rng.normal(0, 1, s.n)
+        _, _, tb = O.fd_vjp(m, q, qd, tau, qb)
+        M = R.mass_matrix(s, q)
+        assert _rel(tb, np.linalg.solve(M.T, qb)) < 1e-11
+
+
+def _id_jacobians(s, q, qd, qdd, h=1e-30):
+    """d ID / dq and d ID / dqd by complex step on the Newton-Euler reference."""
+    n = len(q)
+    Jq = np.zeros((len(qdd), n))
+    Jv = np.zeros((len(qdd), len(qd)))
+    for j in range(n):
+        e = np.zeros(n, complex)
+        e[j] = 1j * h
+        Jq[:, j] = R.inverse_dynamics(s, q + e, qd.astype(complex), qdd.astype(complex)).imag / h
+    for j in range(len(qd)):
+        e = np.zeros(len(qd), complex)
+        e[j] = 1j * h
+        Jv[:, j] = R.inverse_dynamics(s, q.astype(complex), qd + e, qdd.astype(complex)).imag / h
+    return Jq, Jv
+
+
+def test_single_step_state_adjoint_matches_inverse_dynamics_jacobian():
+    """Implicit differentiation of ID(q, qd, FD(q, qd, tau)) = tau gives
+    q_bar = -(dID/dq)^T tau_bar and qd_bar = -(dID/dqd)^T tau_bar.  The
+    reverse ABA reaches the same numbers by a different route."""
+    rng = np.random.default_rng(4)
+    for parent in [(-1, 0, 1, 2, 3), (-1, 0, 0, 1, 2, 2)]:
+        s = _random_tree(parent, rng)
+        m = O.Model(s)
+        q, qd, tau = rng.normal(0, 1, s.n), rng.normal(0, 1, s.n), rng.normal(0, 1, s.n)
+        qb = rng.normal(0, 1, s.n)
+        gq, gqd, tb = O.fd_vjp(m, q, qd, tau, qb)
+        qdd = O.fd(m, q, qd, tau)
+        Jq, Jv = _id_jacobians(s, q, qd, qdd)
+        assert _rel(gq, -Jq.T @ tb) < 1e-10
+        assert _rel(gqd, -Jv.T @ tb) < 1e-10
+
+
+def test_free_base_single_step_adjoint_matches_inverse_dynamics_jacobian():
+    """Same identity with a free root, on the base velocity, the base
+    position and the joint angles (the quaternion has a scale gauge and is
+    checked through complex-step rollouts instead)."""
+    s, q0, qd0, tau = synth.quadruped_system(3007, 1)
+    rng = np.random.default_rng(8)
+    q = q0.copy()
+    qt = rng.normal(size=4)
+    q[3:7] = qt / np.linalg.norm(qt)
+    q[7:] = rng.normal(0, 0.5, 12)
+    qd = rng.normal(0, 1, 18)
+    m = O.Model(s)
+    qb = rng.normal(0, 1, 18)
+    gq, gqd, tb = O.fd_vjp(m, q, qd, tau[0], qb)
+    qdd = O.fd(m, q, qd, tau[0])
+    Jq, Jv = _id_jacobians(s, q, qd, qdd)
+    M = R.mass_matrix(s, q)
+    fb = np.linalg.solve(M.T, qb)       # adjoint of the full generalised force
+    assert _rel(tb, fb[6:]) < 1e-10
+    assert _rel(gqd, -Jv.T @ fb) < 1e-10
+    sel = np.r_[0:3, 7:19]
+    assert _rel(gq[sel], (-Jq.T @ fb)[sel]) < 1e-10
+
+
+def _loss_seed(m, qT):
+    return 2 * qT, np.zeros(m.nv)
+
+
+def test_rollout_gradient_complex_step_chain():
+    """Whole-rollout gradient of L = sum q_T^2 by the adjoint method (Eq.
+    adj_r) against complex-step derivatives of the (pinned) forward rollout,
+    on every q0, qd0 entry and a sample of tau entries."""
+    b = synth.workload("chain7_fp64", T=200)
+    s = b.systems[0]
+    m = O.Model(s)
+    qT, _ = O.rollout(m, b.q0, b.qd0, b.tau, b.dt)
+    gq0, gqd0, gtau, _, _ = O.rollout_grad(m, b.q0, b.qd0, b.tau, b.dt, *_loss_seed(m, qT))
+    h = 1e-30
+
+    def L(q0, qd0, tau):
+        qT, _ = O.rollout_complex(m, q0, qd0, tau, b.dt)
+        return np.sum(qT ** 2)
+
+    for j in range(7):
+        e = np.zeros(7, complex)
+        e[j] = 1j * h
+        assert abs(L(b.q0 + e, b.qd0.astype(complex), b.tau.astype(complex)).imag / h - gq0[j]) \
+            < 1e-10 * max(1, abs(gq0[j]))
+        assert abs(L(b.q0.astype(complex), b.qd0 + e, b.tau.astype(complex)).imag / h - gqd0[j]) \
+            < 1e-10 * max(1, abs(gqd0[j]))
+    rng = np.random.default_rng(0)
+    scale = np.abs(gtau).max()
+    for _ in range(12):
+        t, j = int(rng.integers(0, 200)), int(rng.integers(0, 7))
+        tc = b.tau.astype(complex)
+        tc[t, j] += 1j * h
+        assert abs(L(b.q0.astype(complex), b.qd0.astype(complex), tc).imag / h - gtau[t, j]) \
+            < 1e-10 * scale
+
+
+def test_rollout_vjp_dot_product_tree_and_traj_seed():
+    """<VJP(w), v> = <w, JVP(v)> for the whole rollout of a branched tree,
+    with a dense seed on every intermediate state (traj) and on x^T; the JVP
+    is the complex-step directional derivative of the forward rollout."""
+    s, q0, qd0, tau = synth.tree_system(2005, 60, random_frames=True)
+    m = O.Model(s)
+    rng = np.random.default_rng(1)
+    T, nx = tau.shape[0], s.nq + s.nv
+    gtraj = rng.normal(size=(T, nx))
+    gqT, gqdT = rng.normal(size=s.nq), rng.normal(size=s.nv)
+    gq0, gqd0, gtau, _, _ = O.rollout_grad(m, q0, qd0, tau, 5e-4, gqT, gqdT, gtraj)
+    v0, vd0, vt = rng.normal(size=s.nq), rng.normal(size=s.nv), rng.normal(size=tau.shape)
+    h = 1e-30
+    # JVP of traj and x^T via complex-step rollouts with traj recorded step by step
+    q, qd = q0 + 1j * h * v0, qd0 + 1j * h * vd0
+    dot = 0.0
+    for t in range(T):
+        # one complex step at a time
+        q, qd = O.rollout_complex(m, q, qd, (tau[t] + 1j * h * vt[t])[None, :], 5e-4)
+        dot += gtraj[t] @ np.concatenate([q.imag, qd.imag]) / h
+    dot += gqT @ q.imag / h + gqdT @ qd.imag / h
+    lhs = gq0 @ v0 + gqd0 @ vd0 + np.sum(gtau * vt)
+    assert abs(lhs - dot) < 1e-10 * max(abs(dot), 1.0)
+
+
+def test_free_base_rollout_gradient_complex_step():
+    """Quadruped rollout (quaternion integration and normalisation on the
+    path): adjoint gradient against complex-step derivatives for every
+    entry of q0 (quaternion included: both sides differentiate the same
+    homogeneous rotation formula) and qd0, plus sampled tau entries."""
+    s, q0, qd0, tau = synth.quadruped_system(3001, 150)
+    m = O.Model(s)
+    rng = np.random.default_rng(2)
+    wq, wv = rng.normal(size=19), rng.normal(size=18)
+
+    def Lr(qT, qdT):
+        return wq @ qT + wv @ qdT
+
+    gq0, gqd0, gtau, qT, qdT = O.rollout_grad(m, q0, qd0, tau, 1e-3, wq, wv)
+    h = 1e-30
+
+    def Lc(a, b_, t):
+        qT, qdT = O.rollout_complex(m, a, b_, t, 1e-3)
+        return Lr(qT, qdT)
+
+    scale = max(np.abs(gq0).max(), np.abs(gqd0).max())
+    for j in range(19):
+        e = np.zeros(19, complex)
+        e[j] = 1j * h
+        d = Lc(q0 + e, qd0.astype(complex), tau.astype(complex)).imag / h
+        assert abs(d - gq0[j]) < 1e-9 * scale, j
+    for j in range(18):
+        e = np.zeros(18, complex)
+        e[j] = 1j * h
+        d = Lc(q0.astype(complex), qd0 + e, tau.astype(complex)).imag / h
+        assert abs(d - gqd0[j]) < 1e-9 * scale, j
+    for _ in range(8):
+        t, j = int(rng.integers(0, 150)), int(rng.integers(0, 12))
+        tc = tau.astype(complex)
+        tc[t, j] += 1j * h
+        d = Lc(q0.astype(complex), qd0.astype(complex), tc).imag / h
+        assert abs(d - gtau[t, j]) < 1e-9 * np.abs(gtau).max()
+
+
+def test_rollout_gradient_central_differences_tree():
+    """Central differences (h = 1e-6) on a branched tree with random frames."""
+    s, q0, qd0, tau = synth.tree_system(2003, 100, random_frames=True)
+    m = O.Model(s)
+    dt = 5e-4
+
+    def L(a, b_, t):
+        qT, qdT = O.rollout(m, a, b_, t, dt)
+        return np.sum(qT ** 2) + 0.5 * np.sum(qdT ** 2)
+
+    qT, qdT = O.rollout(m, q0, qd0, tau, dt)
+    gq0, gqd0, gtau, _, _ = O.rollout_grad(m, q0, qd0, tau, dt, 2 * qT, qdT)
+    h = 1e-6
+    for j in range(0, s.n, 3):
+        e = np.zeros(s.n)
+        e[j] = h
+        assert abs((L(q0 + e, qd0, tau) - L(q0 - e, qd0, tau)) / (2 * h) - gq0[j]) < 1e-6 * max(1, abs(gq0[j]))
+        assert abs((L(q0, qd0 + e, tau) - L(q0, qd0 - e, tau)) / (2 * h) - gqd0[j]) < 1e-6 * max(1, abs(gqd0[j]))
+
+
+@pytest.mark.parametrize("which", ["chain", "quad"])
+def test_checkpoint_interval_changes_no_arithmetic(which):
+    """Storing every step, every K steps with segment replay, or every
+    intermediate (store-all) must give bitwise-identical gradients: the
+    recompute repeats the same arithmetic (Sec. 4.2; App. B)."""
+    if which == "chain":
+        s, q0, qd0, tau = synth.chain_system(7, 1000, 237)
+    else:
+        s, q0, qd0, tau = synth.quadruped_system(3000, 237)
+    m = O.Model(s)
+    rng = np.random.default_rng(9)
+    gqT, gqdT = rng.normal(size=s.nq), rng.normal(size=s.nv)
+    gtraj = rng.normal(size=(237, s.nq + s.nv))
+    ref = O.rollout_grad(m, q0, qd0, tau, 1e-3, gqT, gqdT, gtraj, K=1)
+    for K in (0, 2, 10, 100, 237, 500):
+        got = O.rollout_grad(m, q0, qd0, tau, 1e-3, gqT, gqdT, gtraj, K=K)
+        for a, b_ in zip(ref, got):
+            assert np.array_equal(a, b_), K
+
+
+def test_rollout_final_state_matches_stepwise():
+    s, q0, qd0, tau = synth.quadruped_system(3002, 20)
+    m = O.Model(s)
+    q, qd = q0, qd0
+    for t in range(20):
+        q, qd = O.step(m, q, qd, tau[t], 1e-3)
+    qT, qdT = O.rollout(m, q0, qd0, tau, 1e-3)
+    assert np.array_equal(q, qT) and np.array_equal(qd, qdT)
+    assert abs(np.linalg.norm(qT[3:7]) - 1) < 1e-14
