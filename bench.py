@@ -1,0 +1,268 @@
+#!/usr/bin/env python
+"""Benchmark of the hot path on one MI355X.
+
+One "step" is one pass of the whole path over the batch: a T-step forward
+rollout that checkpoints the initial state of every step, then the adjoint
+rollout that recomputes each step and back-propagates (Sec. 4.1-4.2).
+Default workload: 4096 fixed-base 7-DOF revolute chains, dt = 1e-3,
+T = 5000, FP32, checkpoint every step, forward and adjoint each captured in
+a HIP graph.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: fwd+adjoint DOF-steps/s (value), the plain-forward
+rate beside it, the gradient error against the FP64 oracle on sampled
+systems, a roofline entry for the dominant (adjoint) kernel and the FP64
+CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "chain7_4096": "4096 fixed-base 7-DOF revolute chains (z axes, links 0.5 m), dt=1e-3, T=5000, "
+                   "checkpoint every step, forward+adjoint",
+    "trees_8192": "8192 fixed-base uneven revolute trees (6-40 links, depth<=6), dt=5e-4, T=2000, "
+                  "checkpoint every step, forward+adjoint",
+    "quad_1024": "1024 free-floating quadrupeds (base + 4x3 revolute), dt=1e-3, T=50000, "
+                 "checkpoint every step, forward+adjoint",
+}
+FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak (dual-issue); 78.6 without packed issue
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for n in ("spatial.h", "aba_lane.h", "abadj_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2109_07719_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_entry(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    runs, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline_leg(batch, grads, sample_seconds, threads):
+    """The FP64 CPU oracle timed on this host's cores on a bounded sample of
+    the same workload (whole systems, the full horizon); the same oracle runs
+    give the gradient error of the GPU result on those systems."""
+    import oracle as O
+
+    qo, vo, uo = batch.offsets()
+    gq0, gqd0, gtau = grads
+    n = len(batch.systems)
+
+    def one(i):
+        m = O.Model(batch.systems[i], batch.gravity)
+        q0, qd0 = batch.q0[qo[i]:qo[i + 1]], batch.qd0[vo[i]:vo[i + 1]]
+        tau = np.asarray(batch.tau[:, uo[i]:uo[i + 1]], dtype=np.float64)
+        t0 = time.perf_counter()
+        qT, qdT = O.rollout(m, q0, qd0, tau, batch.dt)
+        r = O.rollout_grad(m, q0, qd0, tau, batch.dt, 2 * qT, np.zeros_like(qdT), K=1)
+        return r, time.perf_counter() - t0
+
+    # calibrate on one system, then size the sample to ~sample_seconds of wall time
+    _, t1 = one(0)
+    per_round = max(t1, 1e-3)
+    n_sample = int(max(threads, min(n, threads * max(1, int(sample_seconds / per_round)))))
+    rng = np.random.default_rng(0)
+    idx = sorted(set([0, n - 1] + list(rng.choice(n, size=n_sample, replace=False))))[:n_sample]
+    t0 = time.perf_counter()
+    res = O.map_threads(one, idx, threads=threads)
+    wall = time.perf_counter() - t0
+    dof_steps = sum(batch.systems[i].nv for i in idx) * batch.T
+    errs = []
+    for (r, _), i in zip(res, idx):
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-6))
+        errs.append(max(rel(gq0[qo[i]:qo[i + 1]], r[0]), rel(gqd0[vo[i]:vo[i + 1]], r[1]),
+                        rel(gtau[:, uo[i]:uo[i + 1]], r[2])))
+    import platform
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    base = {"value": dof_steps / wall, "unit": "DOF-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} of {n} systems, full {batch.T}-step forward+adjoint each "
+                      f"(plain dense FP64 C oracle, K=1), {wall:.1f} s wall on {threads} threads, "
+                      f"host CPU: {cpu}"}
+    return base, max(errs), float(np.median(errs)), len(idx)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed steps (each = full forward+adjoint rollout)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="chain7_4096", choices=sorted(WORKLOADS))
+    ap.add_argument("--K", type=int, default=1, help="checkpoint interval")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(systems shard across GPUs with no communication; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": n * 4, "calib_copy_bytes_written": n * 4, "launches": 5}))
+        return
+
+    from paper_2109_07719_amd import synth
+    from paper_2109_07719_amd.sim import Sim
+
+    t_gen = time.perf_counter()
+    b = synth.workload(args.workload, tau_dtype=np.float32)
+    # the oracle and the GPU see the same float32-rounded inputs
+    r = synth.round_to_f32(synth.Batch(systems=b.systems, q0=b.q0, qd0=b.qd0, tau=b.tau[:1], dt=b.dt))
+    b = synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=b.dt, name=b.name)
+    t_gen = time.perf_counter() - t_gen
+
+    sim = Sim(b.systems, b.gravity, dtype=torch.float32)
+    T, K, dt = b.T, args.K, b.dt
+    f32 = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
+    q0, qd0 = f32(b.q0), f32(b.qd0)
+    tau = torch.from_numpy(b.tau).to(dev)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base_mem = torch.cuda.memory_allocated()
+    ws = sim.new_workspace(T, K)
+    qT = torch.empty(sim.nq, dtype=torch.float32, device=dev)
+    qdT = torch.empty(sim.nv, dtype=torch.float32, device=dev)
+    gqdT = torch.zeros(sim.nv, dtype=torch.float32, device=dev)
+    gqT = torch.empty(sim.nq, dtype=torch.float32, device=dev)
+    gq0 = torch.empty(sim.nq, dtype=torch.float32, device=dev)
+    gqd0 = torch.empty(sim.nv, dtype=torch.float32, device=dev)
+    gtau = torch.empty((T, sim.nu), dtype=torch.float32, device=dev)
+    pqT = torch.empty_like(qT)
+    pqdT = torch.empty_like(qdT)
+
+    def fwd():
+        sim.forward(q0, qd0, tau, dt, K=K, workspace=ws, out=(qT, qdT, None))
+        torch.mul(qT, 2.0, out=gqT)   # loss L = sum q_T^2
+
+    def bwd():
+        sim.backward(tau, dt, K, ws, gqT, gqdT, out=(gq0, gqd0, gtau))
+
+    def plain():
+        sim.forward(q0, qd0, tau, dt, K=K, workspace=None, out=(pqT, pqdT, None))
+
+    # warm up eagerly once (also the first correctness pass), then capture
+    fwd(), bwd(), plain()
+    torch.cuda.synchronize()
+    graphs = {}
+    for name, fn in (("fwd", fwd), ("bwd", bwd), ("plain", plain)):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        graphs[name] = g
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graphs["fwd"].replay()
+        graphs["bwd"].replay()
+        graphs["plain"].replay()
+    torch.cuda.synchronize()
+
+    # timed region: forward + adjoint, K steps, events on the launch stream
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        graphs["fwd"].replay()
+        ev[k][1].record()
+        graphs["bwd"].replay()
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = [ev[k][0].elapsed_time(ev[k][1]) for k in range(args.steps)]
+    bwd_ms = [ev[k][1].elapsed_time(ev[k][2]) for k in range(args.steps)]
+    step_ms = [f + g for f, g in zip(fwd_ms, bwd_ms)]
+    peak_mem = torch.cuda.max_memory_allocated() - base_mem
+
+    # plain forward (no checkpoints), same timing method
+    pev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        pev[k][0].record()
+        graphs["plain"].replay()
+        pev[k][1].record()
+    torch.cuda.synchronize()
+    plain_ms = [pev[k][0].elapsed_time(pev[k][1]) for k in range(args.steps)]
+
+    grads = (gq0.cpu().numpy(), gqd0.cpu().numpy(), gtau.cpu().numpy())
+    finite = all(np.all(np.isfinite(g)) for g in grads) and bool(torch.isfinite(qT).all())
+    dof_steps = b.total_dof * T
+    ms_per_step = float(np.mean(step_ms))
+    value = dof_steps / (ms_per_step * 1e-3)
+    plain_rate = dof_steps / (float(np.mean(plain_ms)) * 1e-3)
+
+    bwd_flops = sim.flops(2) * T
+    fwd_flops = sim.flops(1) * T
+    bwd_s = float(np.mean(bwd_ms)) * 1e-3
+    achieved = bwd_flops / bwd_s / 1e12
+    roofline = {"bound": "alu", "kernel": "k_backward", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                "traffic": traffic_entry("k_backward", args.workload),
+                "flops_per_launch": bwd_flops, "kernel_ms": float(np.mean(bwd_ms)),
+                "fwd_kernel_ms": float(np.mean(fwd_ms)),
+                "fwd_achieved_tflops": fwd_flops / (float(np.mean(fwd_ms)) * 1e-3) / 1e12}
+
+    out = {"metric": "fwd+adjoint DOF-steps/sec (FP32, 1 GPU) vs plain fwd; grad rel err",
+           "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": WORKLOADS[args.workload], "systems": len(b.systems), "dof": b.total_dof,
+                      "T": T, "dt": dt, "K": K, "lanes": sim.info["n_slots"], "waves": sim.info["n_waves"],
+                      "lanes_per_system": "one lane per link"},
+           "plain_fwd_dof_steps_per_s": plain_rate, "fwd_adjoint_over_plain_fwd_time": value and plain_rate / value,
+           "peak_mem_bytes": int(peak_mem), "results_finite": finite, "roofline": roofline,
+           "wall_s_timed": wall, "input_gen_s": t_gen}
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        base, emax, emed, ns = cpu_baseline_leg(b, grads, args.cpu_sample_seconds, threads)
+        out["cpu_baseline"] = base
+        out["grad_rel_err"] = {"max": emax, "median": emed, "systems": ns, "vs": "FP64 oracle",
+                               "norm": "per system, ||g - g_ref|| / ||g_ref|| over (gq0, gqd0, gtau)"}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * abadj -- batched differentiable articulated-body dynamics on AMD MI355X
+ * (gfx950): forward dynamics by the Articulated Body Algorithm, semi-implicit
+ * Euler time stepping, and the reverse-time adjoint that stores only each
+ * step's initial state and recomputes the step's intermediates.
+ *
+ * Method references (Qiao, Liang, Koltun, Lin, "Efficient Differentiable
+ * Simulation of Articulated Bodies", ICML 2021):
+ *   - state x = [q, qdot], one control u per step      Sec. 3, "Articulated
+ *                                                       body dynamics"
+ *   - ABA, three tree traversals                        Sec. 3; Fig. 1;
+ *                                                       Sec. 4.1 (modules)
+ *   - adjoint recursion through time                    Sec. 3, Eq. adj_back;
+ *                                                       Sec. 4.1, Eq. adj_r
+ *   - checkpoint the initial state of each step,
+ *     recompute intermediates in the backward pass      Sec. 4.2, Eq.
+ *                                                       intermediate; Fig. 2
+ *   - checkpoint interval K                             App. B
+ *
+ * Conventions
+ *   - Links of a system are given in topological order (parent < child).
+ *     parent = -1 attaches a link to the fixed base; a free-floating root
+ *     (joint type SIM_JOINT_FREE) is allowed only at local index 0, with
+ *     parent -1, and then every other link of that system has a parent.
+ *   - Plucker transform parent -> link: X = [E 0; -E[r]x E] with
+ *     E = E_J(q) E_T, E_J(q) = I - sin q [a]x + (1 - cos q)[a]x^2, r = r_T.
+ *   - Revolute joint: one q, one qdot, one control torque.  Free root:
+ *     q = (p_world[3], quat[4] stored x, y, z, w), velocity = body-frame
+ *     spatial velocity [w; v] (6 entries), unactuated.
+ *   - Gravity enters as a fictitious base acceleration; for a free root the
+ *     base acceleration reported is the true body-frame acceleration.
+ *   - Semi-implicit Euler: qd1 = qd + dt qdd, q1 = q + dt qd1; free root:
+ *     p1 = p + dt R(quat) v1_lin, quat1 = normalize(quat + dt/2 quat x (w1, 0)).
+ *   - Batched vectors are system-concatenated in the order of the
+ *     topology: q [sum nq], qd [sum nv], control rows [sum nu]; a control
+ *     sequence is [T][sum nu], a trajectory [T][sum nq + sum nv] whose row t
+ *     holds (q^{t+1}, qd^{t+1}) (all q first, then all qd).
+ *
+ * Memory and streams
+ *   - Host pointers are marked "host"; all others are DEVICE pointers,
+ *     owned by the caller, of the handle's dtype (float for SIM_F32,
+ *     double for SIM_F64), contiguous.
+ *   - The handle owns only its packed per-link constants (device memory
+ *     allocated by sim_create, freed by sim_destroy).
+ *   - sim_forward / sim_backward / sim_aba only enqueue work on `stream`
+ *     (a hipStream_t; NULL = the default stream).  They never allocate,
+ *     never synchronise and never memset, so they may be captured into a
+ *     HIP graph.  Scratch memory is the caller's workspace.
+ *
+ * Errors: every entry point returns SIM_OK (0) or a negative code; no C++
+ * exception crosses the ABI.  sim_last_error() returns a thread-local
+ * description of the last failure on the calling thread.
+ */
+#ifndef ABADJ_H
+#define ABADJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_OK 0
+#define SIM_ERR_INVALID_ARG (-1)
+#define SIM_ERR_INVALID_TOPOLOGY (-2)
+#define SIM_ERR_WORKSPACE_TOO_SMALL (-3)
+#define SIM_ERR_UNSUPPORTED_DTYPE (-4)
+#define SIM_ERR_HIP (-5)
+
+#define SIM_F32 0
+#define SIM_F64 1
+
+#define SIM_JOINT_REVOLUTE 0
+#define SIM_JOINT_FREE 1
+
+/* Largest number of links in one system (one wavefront of 64 lanes). */
+#define SIM_MAX_LINKS 64
+
+typedef struct sim_handle *sim_t;
+
+/* Tree structure of a batch of independent systems (host arrays). */
+typedef struct {
+  int32_t n_sys;               /* number of systems, >= 1                 */
+  const int32_t *link_offset;  /* [n_sys + 1], links of system s are
+                                  link_offset[s] .. link_offset[s+1]-1    */
+  const int32_t *parent;       /* [n_links] local parent index, -1 = base */
+  const int32_t *jtype;        /* [n_links] SIM_JOINT_*                   */
+} sim_topology;
+
+/* Per-link model parameters (host arrays, double precision). */
+typedef struct {
+  const double *E_T;      /* [9 n_links] row-major rotation parent->joint   */
+  const double *r_T;      /* [3 n_links] joint origin, parent coordinates   */
+  const double *axis;     /* [3 n_links] unit joint axis, link coordinates  */
+  const double *mass;     /* [n_links] > 0                                  */
+  const double *com;      /* [3 n_links] centre of mass, link coordinates   */
+  const double *Ic;       /* [6 n_links] inertia about the COM:
+                             xx yy zz xy xz yz                              */
+  const double *gravity;  /* [3] e.g. (0, -9.81, 0)                         */
+} sim_params;
+
+typedef struct {
+  int32_t n_sys, n_links;
+  int32_t nq, nv, nu;     /* totals over the batch                        */
+  int32_t n_waves;        /* wavefronts per launch (one per workgroup)    */
+  int32_t n_slots;        /* n_waves * 64 lane slots                      */
+  int32_t max_depth;      /* deepest tree level (root = 0)                */
+  int32_t has_free;       /* 1 if any system has a free-floating root      */
+  int32_t dtype;
+} sim_info_t;
+
+/* Build a handle: validates the topology and parameters, orders every
+ * system breadth-first, packs systems into wavefronts (one lane per link),
+ * and uploads the per-link constants in the requested dtype.  topo and
+ * params are host memory, deep-copied; the caller may free them on return.
+ * Errors: SIM_ERR_INVALID_ARG (null pointers, bad dtype value ->
+ * SIM_ERR_UNSUPPORTED_DTYPE), SIM_ERR_INVALID_TOPOLOGY (parent >= own
+ * index, free joint not at a root, more than SIM_MAX_LINKS links, non-unit
+ * axis, non-positive mass, non-finite numbers), SIM_ERR_HIP (device
+ * allocation or copy failed). */
+int sim_create(const sim_topology *topo, const sim_params *params, int dtype, sim_t *out);
+
+/* Release the handle and its device constants.  NULL is ignored. */
+void sim_destroy(sim_t h);
+
+int sim_get_info(sim_t h, sim_info_t *out);
+
+/* Bytes of workspace needed by sim_forward/sim_backward for T steps with a
+ * checkpoint every K >= 1 steps (K > 1 adds a K-state replay buffer).
+ * Pure function of (h, T, K). */
+int sim_workspace_bytes(sim_t h, int T, int K, size_t *bytes);
+
+/* Forward rollout of T steps of size dt (Sec. 3; Sec. 4.1 time
+ * integration).  q0 [nq], qd0 [nv], tau [T][nu] -> qT [nq], qdT [nv];
+ * traj (nullable) [T][nq + nv].  With a workspace, the initial state of
+ * every K-th step is stored there for sim_backward (Sec. 4.2; App. B);
+ * workspace == NULL runs the plain forward pass (no checkpoints).
+ * Errors: SIM_ERR_INVALID_ARG (T < 0, K < 1, dt not finite or <= 0, null
+ * required pointer), SIM_ERR_WORKSPACE_TOO_SMALL, SIM_ERR_HIP (launch). */
+int sim_forward(sim_t h, const void *q0, const void *qd0, const void *tau, double dt, int T, int K,
+                void *qT, void *qdT, void *traj, void *workspace, size_t workspace_bytes,
+                void *stream);
+
+/* Adjoint (reverse-time) pass of the rollout last run by sim_forward on
+ * this workspace with the same tau, dt, T and K (Sec. 3, Eq. adj_back;
+ * Sec. 4.1, Eq. adj_r; Sec. 4.2).  Seeds: gqT [nq], gqdT [nv] = dL/dx^T;
+ * gtraj (nullable) [T][nq + nv] = dL/dtraj.  Outputs (overwritten, not
+ * accumulated): gq0 [nq], gqd0 [nv], gtau [T][nu].  Reads the checkpoints
+ * in the workspace and, for K > 1, uses the rest of it as replay scratch.
+ * For a free root, gq0's quaternion entries are the gradient with respect
+ * to the raw components under the rotation formula
+ * R = (w^2 - u.u) I + 2 u u^T + 2 w [u]x; only their component tangent to
+ * the unit sphere is gauge-independent.
+ * Errors as sim_forward. */
+int sim_backward(sim_t h, const void *tau, double dt, int T, int K, const void *gqT,
+                 const void *gqdT, const void *gtraj, void *gq0, void *gqd0, void *gtau,
+                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* Forward dynamics of every system at one state (Sec. 3, ABA):
+ * q [nq], qd [nv], tau [nu] -> qdd [nv] (a free root's 6 entries are its
+ * true body-frame spatial acceleration).  Errors: SIM_ERR_INVALID_ARG,
+ * SIM_ERR_HIP. */
+int sim_aba(sim_t h, const void *q, const void *qd, const void *tau, void *qdd, void *stream);
+
+/* Algorithmic floating-point operations per time step for the whole batch
+ * (one add, subtract, multiply, divide, square root, sine or cosine = 1),
+ * counted by running the per-link arithmetic once with an operation-
+ * counting scalar type.  kind: 0 = one ABA evaluation, 1 = one forward
+ * step (ABA + integration), 2 = one backward step (recompute + adjoint). */
+int sim_flops(sim_t h, int kind, double *flops_per_step);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *sim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

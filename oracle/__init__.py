@@ -142,8 +142,9 @@ def step(m: Model, q, qd, tau, dt):
 
 def rollout(m: Model, q0, qd0, tau, dt, traj: bool = False):
     """T-step rollout; tau is [T, nu].  Returns qT, qdT (and traj [T, nq+nv])."""
-    tau = _f64(tau).reshape(-1, m.nu) if m.nu else np.zeros((np.asarray(tau).shape[0], 0))
-    T = tau.shape[0]
+    tau = _f64(tau)
+    T = int(tau.shape[0])
+    tau = tau.reshape(T, m.nu)
     q0, qd0 = _f64(q0, m.nq), _f64(qd0, m.nv)
     qT, qdT = np.zeros(m.nq), np.zeros(m.nv)
     tr = np.zeros((T, m.nq + m.nv)) if traj else None
@@ -155,8 +156,9 @@ def rollout(m: Model, q0, qd0, tau, dt, traj: bool = False):
 
 
 def rollout_complex(m: Model, q0, qd0, tau, dt):
-    tau = _c128(tau).reshape(-1, m.nu)
-    T = tau.shape[0]
+    tau = _c128(tau)
+    T = int(tau.shape[0])
+    tau = tau.reshape(T, m.nu)
     q0, qd0 = _c128(q0, m.nq), _c128(qd0, m.nv)
     qT, qdT = np.zeros(m.nq, dtype=np.complex128), np.zeros(m.nv, dtype=np.complex128)
     rc = lib().orc_rollout_c(m.ref, _p(q0), _p(qd0), _p(np.ascontiguousarray(tau)), float(dt),
@@ -170,8 +172,9 @@ def rollout_grad(m: Model, q0, qd0, tau, dt, gqT, gqdT, gtraj=None, K: int = 1):
     """Adjoint-method gradient of <gqT, q^T> + <gqdT, qd^T> + <gtraj, traj>
     with respect to (q0, qd0, tau).  K >= 1: checkpoint every K steps;
     K == 0: store every step's intermediates.  Returns gq0, gqd0, gtau, qT, qdT."""
-    tau = np.ascontiguousarray(_f64(tau).reshape(-1, m.nu))
-    T = tau.shape[0]
+    tau = _f64(tau)
+    T = int(tau.shape[0])
+    tau = np.ascontiguousarray(tau.reshape(T, m.nu))
     q0, qd0 = _f64(q0, m.nq), _f64(qd0, m.nv)
     gqT, gqdT = _f64(gqT, m.nq), _f64(gqdT, m.nv)
     gtr = None if gtraj is None else np.ascontiguousarray(_f64(gtraj).reshape(T, m.nq + m.nv))

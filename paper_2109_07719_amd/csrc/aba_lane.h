@@ -1,0 +1,397 @@
+// Per-link (per-lane) steps of the Articulated Body Algorithm, one
+// semi-implicit Euler step, and the adjoint of each, in structured spatial
+// algebra.  The kernels call these with one lane per link and exchange the
+// parent/child quantities between lanes; a sequential host driver calls the
+// same functions link by link to count algorithmic operations.
+//
+// Method (Sec. 3 "Articulated body dynamics"; Fig. 1; Sec. 4.1, five
+// modules): pass 1 root->leaves (kinematics, velocities, bias forces), pass
+// 2 leaves->root (articulated inertias and bias forces), pass 3
+// root->leaves (accelerations), then time integration.  The adjoint runs the
+// modules in reverse order (Sec. 4.1) after recomputing the step's
+// intermediates from the stored initial state (Sec. 4.2, Eq. intermediate).
+//
+// Joint-angle derivatives use dX/dq = -crm(S) X for a revolute joint
+// (X = X_J(q) X_T, X_J = exp(-q crm(S))), so every statement that applies X
+// contributes a cross-product pairing to q_bar instead of a full X_bar.
+#pragma once
+
+#include "spatial.h"
+
+namespace aba {
+
+// per-link constants
+template <typename S>
+struct LinkC {
+  M3<S> ET;   // fixed rotation parent -> joint frame
+  V3<S> rT;   // joint origin in parent coordinates
+  V3<S> ax;   // unit joint axis (link coordinates)
+  S m;        // mass
+  V3<S> mc;   // mass * centre of mass
+  Sy3<S> Ib;  // rotational inertia about the link origin: Ic - m [c]x^2
+};
+
+// spatial inertia applied to a motion vector: [Ib w + mc x v; m v - mc x w]
+template <typename S>
+ABA_HD V6<S> inertia_mul(const LinkC<S>& L, const V6<S>& v) {
+  return v6<S>(mul(L.Ib, v.a) + cross(L.mc, v.l), L.m * v.l - cross(L.mc, v.a));
+}
+template <typename S>
+ABA_HD SySp<S> inertia_sysp(const LinkC<S>& L) {
+  SySp<S> I;
+  I.A = L.Ib;
+  const V3<S>& c = L.mc;
+  I.B.m[0] = S(0); I.B.m[1] = -c.z; I.B.m[2] = c.y;
+  I.B.m[3] = c.z;  I.B.m[4] = S(0); I.B.m[5] = -c.x;
+  I.B.m[6] = -c.y; I.B.m[7] = c.x;  I.B.m[8] = S(0);
+  I.C = sy3<S>(L.m, L.m, L.m, S(0), S(0), S(0));
+  return I;
+}
+
+// E = E_J(q) E_T with E_J = c I + (1 - c) a a^T - s [a]x
+template <typename S>
+ABA_HD M3<S> joint_E(const LinkC<S>& L, S s, S c) {
+  const V3<S>& a = L.ax;
+  const S k = S(1) - c;
+  M3<S> J;
+  J.m[0] = c + k * a.x * a.x;   J.m[1] = k * a.x * a.y + s * a.z; J.m[2] = k * a.x * a.z - s * a.y;
+  J.m[3] = k * a.y * a.x - s * a.z; J.m[4] = c + k * a.y * a.y;   J.m[5] = k * a.y * a.z + s * a.x;
+  J.m[6] = k * a.z * a.x + s * a.y; J.m[7] = k * a.z * a.y - s * a.x; J.m[8] = c + k * a.z * a.z;
+  return mul(J, L.ET);
+}
+
+// ----------------------------------------------------------------- forward
+// Intermediates of one link kept for the reverse sweep.
+template <typename S>
+struct Tape {
+  M3<S> E;
+  V6<S> v, c;
+  SySp<S> IA;  // final articulated inertia (children included)
+  V6<S> pA;    // final articulated bias force
+  V6<S> U;
+  S Dinv, u;
+  V6<S> pa;    // bias force handed to the parent
+  V6<S> ap;    // X a_parent + c
+  S qdd;
+};
+
+// pass 1 (revolute): v = X v_parent + S qd
+template <typename S>
+ABA_HD V6<S> p1_velocity(const LinkC<S>& L, const M3<S>& E, S qd, const V6<S>& vpar) {
+  V6<S> v = xform(E, L.rT, vpar);
+  v.a = axpy(v.a, qd, L.ax);
+  return v;
+}
+// pass 1 (all links): c = v x S qd, h = I v, pA = v x* h, IA = I
+template <typename S>
+ABA_HD void p1_bias(const LinkC<S>& L, const V6<S>& v, S qd, bool revolute, V6<S>& c, V6<S>& pA,
+                    SySp<S>& IA) {
+  if (revolute) {
+    const V3<S> sq = qd * L.ax;
+    c = v6<S>(cross(v.a, sq), cross(v.l, sq));
+  } else {
+    c = zero6<S>();
+  }
+  const V6<S> h = inertia_mul(L, v);
+  pA = crf(v, h);
+  IA = inertia_sysp(L);
+}
+// pass 2 (revolute): U = IA S, D = S^T U, u = tau - S^T pA
+template <typename S>
+ABA_HD void p2_local(const LinkC<S>& L, Tape<S>& t, S tau) {
+  t.U = v6<S>(mul(t.IA.A, L.ax), mulT(t.IA.B, L.ax));
+  t.Dinv = S(1) / dot(L.ax, t.U.a);
+  t.u = tau - dot(L.ax, t.pA.a);
+}
+// pass 2 (revolute with a parent link): Ia = IA - U U^T / D,
+// pa = pA + Ia c + U u / D; the parent receives X^T Ia X and X^T pa.
+template <typename S>
+ABA_HD void p2_push(const LinkC<S>& L, Tape<S>& t, SySp<S>& IA_up, V6<S>& pA_up) {
+  const SySp<S> Ia = rank1_down(t.IA, t.U, t.Dinv);
+  t.pa = t.pA + mul(Ia, t.c) + (t.u * t.Dinv) * t.U;
+  IA_up = congruence_XT(t.E, L.rT, Ia);
+  pA_up = xformT(t.E, L.rT, t.pa);
+}
+// pass 3 (revolute): a' = X a_parent + c, qdd = (u - U^T a') / D, a = a' + S qdd
+template <typename S>
+ABA_HD V6<S> p3_accel(const LinkC<S>& L, Tape<S>& t, const V6<S>& apar) {
+  t.ap = xform(t.E, L.rT, apar) + t.c;
+  t.qdd = (t.u - dot(t.U, t.ap)) * t.Dinv;
+  V6<S> a = t.ap;
+  a.a = axpy(a.a, t.qdd, L.ax);
+  return a;
+}
+
+// ------------------------------------------------------- free-floating root
+// 6x6 SPD factorisation (lower Cholesky, packed rows)
+template <typename S>
+struct Chol6 {
+  S L[21];
+};
+template <typename S>
+ABA_HD void sysp_dense(const SySp<S>& M, S A[36]) {
+  const M3<S> a = sy_to_m3(M.A), c = sy_to_m3(M.C);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      A[6 * i + j] = a.m[3 * i + j];
+      A[6 * i + j + 3] = M.B.m[3 * i + j];
+      A[6 * (i + 3) + j] = M.B.m[3 * j + i];
+      A[6 * (i + 3) + j + 3] = c.m[3 * i + j];
+    }
+}
+template <typename S>
+ABA_HD Chol6<S> chol6(const SySp<S>& M) {
+  S A[36];
+  sysp_dense(M, A);
+  Chol6<S> f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      S s = A[6 * i + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s = s - f.L[i * (i + 1) / 2 + k] * f.L[j * (j + 1) / 2 + k];
+      if (i == j)
+        f.L[i * (i + 1) / 2 + i] = sqrt(s);
+      else
+        f.L[i * (i + 1) / 2 + j] = s / f.L[j * (j + 1) / 2 + j];
+    }
+  }
+  return f;
+}
+template <typename S>
+ABA_HD V6<S> chol6_solve(const Chol6<S>& f, const V6<S>& b) {
+  S x[6] = {b.a.x, b.a.y, b.a.z, b.l.x, b.l.y, b.l.z};
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    S s = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s = s - f.L[i * (i + 1) / 2 + k] * x[k];
+    x[i] = s / f.L[i * (i + 1) / 2 + i];
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    S s = x[i];
+#pragma unroll
+    for (int k = i + 1; k < 6; ++k) s = s - f.L[k * (k + 1) / 2 + i] * x[k];
+    x[i] = s / f.L[i * (i + 1) / 2 + i];
+  }
+  return v6<S>(v3<S>(x[0], x[1], x[2]), v3<S>(x[3], x[4], x[5]));
+}
+// root acceleration in the gravity-free frame a' = -IA^{-1} pA, and the true
+// body-frame acceleration a' + [0; R^T g]
+template <typename S>
+ABA_HD void root_accel(const SySp<S>& IA, const V6<S>& pA, const Q4<S>& quat, const V3<S>& g, V6<S>& ap,
+                       V6<S>& abase) {
+  const Chol6<S> f = chol6(IA);
+  const V6<S> x = chol6_solve(f, pA);
+  ap = v6<S>(-x.a, -x.l);
+  abase = v6<S>(ap.a, ap.l + quat_rotate_T(quat, g));
+}
+
+// ----------------------------------------------------------------- integrator
+// revolute: qd1 = qd + dt qdd; q1 = q + dt qd1
+template <typename S>
+ABA_HD void integrate_rev(S& q, S& qd, S qdd, S dt) {
+  qd = qd + dt * qdd;
+  q = q + dt * qd;
+}
+// free root: v1 = v + dt a; p1 = p + dt R(quat) v1_lin;
+// quat1 = normalize(quat + dt/2 quat (x) (w1, 0))
+template <typename S>
+ABA_HD void integrate_root(V3<S>& p, Q4<S>& quat, V6<S>& v, const V6<S>& abase, S dt) {
+  v = v + dt * abase;
+  p = axpy(p, dt, quat_rotate(quat, v.l));
+  const V3<S> u = v3<S>(quat.x, quat.y, quat.z);
+  const V3<S> ov = axpy(cross(u, v.a), quat.w, v.a);
+  const S ow = -dot(u, v.a);
+  const S h = S(0.5) * dt;
+  Q4<S> r;
+  r.x = quat.x + h * ov.x;
+  r.y = quat.y + h * ov.y;
+  r.z = quat.z + h * ov.z;
+  r.w = quat.w + h * ow;
+  const S inv = S(1) / sqrt(r.x * r.x + r.y * r.y + r.z * r.z + r.w * r.w);
+  quat.x = r.x * inv;
+  quat.y = r.y * inv;
+  quat.z = r.z * inv;
+  quat.w = r.w * inv;
+}
+
+// ----------------------------------------------------------------- adjoint
+// Per-link adjoint accumulators that live across the three reverse passes.
+template <typename S>
+struct Bar {
+  V6<S> c;     // c_bar
+  V6<S> U;     // U_bar
+  S D, u;      // D_bar, u_bar
+  S q, qd;     // contributions to the joint angle / rate adjoints
+};
+template <typename S>
+ABA_HD void bar_zero(Bar<S>& b) {
+  b.c = zero6<S>();
+  b.U = zero6<S>();
+  b.D = S(0);
+  b.u = S(0);
+  b.q = S(0);
+  b.qd = S(0);
+}
+
+// a . (x_ang x y_ang + x_lin x y_lin): the joint-angle pairing of a
+// statement y = X m (x = y_bar, y = X m) or y = X^T f (x = f, y = X y_bar)
+template <typename S>
+ABA_HD S qpair(const V3<S>& ax, const V6<S>& x, const V6<S>& y) {
+  return dot(ax, cross(x.a, y.a) + cross(x.l, y.l));
+}
+
+// reverse of pass 3 (revolute).  abar: the link's acceleration adjoint with
+// all children's shares added; qddbar: seed from the integrator.  Returns
+// ap_bar (the parent receives X^T ap_bar).
+template <typename S>
+ABA_HD V6<S> r3_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>& abar, S qddbar) {
+  // a = ap + S qdd
+  V6<S> apb = abar;
+  const S qddb = qddbar + dot(L.ax, abar.a);
+  // qdd = (u - U^T ap) / D
+  const S g = qddb * t.Dinv;
+  b.u = b.u + g;
+  b.U = b.U - g * t.ap;
+  apb = apb - g * t.U;
+  b.D = b.D - g * t.qdd;
+  // ap = X a_parent + c
+  b.q = b.q + qpair(L.ax, apb, t.ap - t.c);
+  b.c = b.c + apb;
+  return apb;
+}
+
+// reverse of pass 2 (revolute).  IAbp / pAbp: the parent's adjoints (only
+// used when has_parent).  Produces this link's IA_bar / pA_bar (handed to
+// the children) and tau_bar.
+template <typename S>
+ABA_HD S r2_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent, const SySp<S>& IAbp,
+                 const V6<S>& pAbp, SySp<S>& IAb, V6<S>& pAb) {
+  IAb = zero_sysp<S>();
+  pAb = zero6<S>();
+  if (has_parent) {
+    // pA_parent += X^T pa
+    const V6<S> pab0 = xform(t.E, L.rT, pAbp);
+    b.q = b.q + qpair(L.ax, t.pa, pab0);
+    // IA_parent += X^T Ia X
+    const SySp<S> N = congruence_X(t.E, L.rT, IAbp);
+    const SySp<S> Ia = rank1_down(t.IA, t.U, t.Dinv);
+    b.q = b.q - S(2) * pair_crmS(Ia, N, L.ax);
+    // pa = pA + Ia c + U u / D
+    const V6<S>& pab = pab0;
+    pAb = pAb + pab;
+    SySp<S> Iab = add_sym_outer(N, pab, t.c, S(1));
+    b.c = b.c + mul(Ia, pab);
+    b.U = b.U + (t.u * t.Dinv) * pab;
+    const S Upa = dot(t.U, pab);
+    b.u = b.u + Upa * t.Dinv;
+    b.D = b.D - Upa * t.u * t.Dinv * t.Dinv;
+    // Ia = IA - U U^T / D
+    IAb = IAb + Iab;
+    const V6<S> IU = mul(Iab, t.U);
+    b.U = b.U - (S(2) * t.Dinv) * IU;
+    b.D = b.D + dot(t.U, IU) * t.Dinv * t.Dinv;
+  }
+  // u = tau - S^T pA
+  const S taub = b.u;
+  pAb.a = axpy(pAb.a, -b.u, L.ax);
+  // D = S^T U
+  b.U.a = axpy(b.U.a, b.D, L.ax);
+  // U = IA S   (symmetric part of U_bar S^T)
+  IAb = add_sym_outer(IAb, b.U, v6<S>(L.ax, zero3<S>()), S(1));
+  return taub;
+}
+
+// reverse of pass 1 (revolute).  vbar: the velocity adjoint with all
+// children's shares; pAb: this link's final bias-force adjoint.  Returns
+// the adjoint handed to the parent's velocity, X^T v_bar.
+template <typename S>
+ABA_HD V6<S> r1_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, V6<S> vbar, const V6<S>& pAb, S qd) {
+  // pA(initial) = v x* h, h = I v
+  const V6<S> h = inertia_mul(L, t.v);
+  const V6<S> hb = v6<S>(-cross(t.v.a, pAb.a), -(cross(t.v.a, pAb.l) + cross(t.v.l, pAb.a)));
+  vbar = vbar + crmT(pAb, h) + inertia_mul(L, hb);
+  // c = v x vJ, vJ = [a qd; 0]
+  const V3<S> sq = qd * L.ax;
+  vbar = vbar - v6<S>(cross(b.c.a, sq), cross(b.c.l, sq));
+  const V6<S> vJb = crmT(t.v, b.c) + vbar;
+  b.qd = b.qd + dot(L.ax, vJb.a);
+  // v = X v_parent + vJ
+  const V6<S> Xv = v6<S>(axpy(t.v.a, -qd, L.ax), t.v.l);
+  b.q = b.q + qpair(L.ax, vbar, Xv);
+  return xformT(t.E, L.rT, vbar);
+}
+
+// free root, reverse of pass 3 and of the root solve.  abar: children's
+// shares; qddbar: base-acceleration seed from the integrator.  Adds the
+// gravity term's quaternion adjoint into quatb; returns pA_bar and IA_bar.
+template <typename S>
+ABA_HD void r3_root(const SySp<S>& IA, const V6<S>& ap, const Q4<S>& quat, const V3<S>& g, const V6<S>& abar,
+                    const V6<S>& qddbar, Q4<S>& quatb, SySp<S>& IAb, V6<S>& pAb) {
+  // abase = ap + [0; R^T g]:  <qddbar_lin, R^T g> = g^T R qddbar_lin
+  const Q4<S> gq = quat_rot_grad(quat, g, qddbar.l);
+  quatb.x = quatb.x + gq.x;
+  quatb.y = quatb.y + gq.y;
+  quatb.z = quatb.z + gq.z;
+  quatb.w = quatb.w + gq.w;
+  const V6<S> apb = abar + qddbar;
+  // ap = -IA^{-1} pA
+  const V6<S> w = chol6_solve(chol6(IA), apb);
+  pAb = v6<S>(-w.a, -w.l);
+  IAb = add_sym_outer(zero_sysp<S>(), w, ap, S(-1));
+}
+// free root, reverse of pass 1: returns the body-velocity adjoint
+template <typename S>
+ABA_HD V6<S> r1_root(const LinkC<S>& L, const V6<S>& v, V6<S> vbar, const V6<S>& pAb) {
+  const V6<S> h = inertia_mul(L, v);
+  const V6<S> hb = v6<S>(-cross(v.a, pAb.a), -(cross(v.a, pAb.l) + cross(v.l, pAb.a)));
+  return vbar + crmT(pAb, h) + inertia_mul(L, hb);
+}
+
+// adjoint of integrate_root.  Inputs: state at the start of the step (p,
+// quat, v), the base acceleration, and the adjoints of the new state (pb,
+// quatb, vb: overwritten with the adjoints of the old state's integrator
+// share).  Returns the base-acceleration seed dt * v1_bar.
+template <typename S>
+ABA_HD V6<S> integrate_root_adj(const Q4<S>& quat, const V6<S>& v, const V6<S>& abase, S dt, V3<S>& pb,
+                                Q4<S>& quatb, V6<S>& vb) {
+  (void)pb;  // p1 = p + ...: the position adjoint passes through unchanged
+  const V6<S> v1 = v + dt * abase;
+  const V3<S> u = v3<S>(quat.x, quat.y, quat.z);
+  const V3<S> ov = axpy(cross(u, v1.a), quat.w, v1.a);
+  const S ow = -dot(u, v1.a);
+  const S h = S(0.5) * dt;
+  Q4<S> r;
+  r.x = quat.x + h * ov.x;
+  r.y = quat.y + h * ov.y;
+  r.z = quat.z + h * ov.z;
+  r.w = quat.w + h * ow;
+  const S inv = S(1) / sqrt(r.x * r.x + r.y * r.y + r.z * r.z + r.w * r.w);
+  const Q4<S> q1 = {r.x * inv, r.y * inv, r.z * inv, r.w * inv};
+  // quat1 = r / |r|
+  const S d = q1.x * quatb.x + q1.y * quatb.y + q1.z * quatb.z + q1.w * quatb.w;
+  const V3<S> rbv = v3<S>((quatb.x - q1.x * d) * inv, (quatb.y - q1.y * d) * inv, (quatb.z - q1.z * d) * inv);
+  const S rbw = (quatb.w - q1.w * d) * inv;
+  // r = quat + h * quat (x) (w1, 0):  o_v = qw w1 + u x w1, o_w = -u . w1
+  V6<S> v1b = vb;
+  const V3<S> qvb = rbv + h * (cross(v1.a, rbv) - rbw * v1.a);
+  const S qwb = rbw + h * dot(v1.a, rbv);
+  v1b.a = v1b.a + h * (quat.w * rbv - cross(u, rbv) - rbw * u);
+  // p1 = p + dt R(quat) v1_lin
+  const Q4<S> gq = quat_rot_grad(quat, dt * pb, v1.l);
+  quatb.x = qvb.x + gq.x;
+  quatb.y = qvb.y + gq.y;
+  quatb.z = qvb.z + gq.z;
+  quatb.w = qwb + gq.w;
+  v1b.l = v1b.l + quat_rotate_T(quat, dt * pb);
+  // v1 = v + dt abase
+  vb = v1b;
+  return dt * v1b;
+}
+
+}  // namespace aba

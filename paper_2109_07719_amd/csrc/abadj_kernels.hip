@@ -1,0 +1,576 @@
+// HIP kernels for gfx950: batched ABA forward dynamics + semi-implicit
+// Euler (forward rollout with checkpoints) and the reverse-time adjoint
+// (backward rollout with per-step recompute).
+//
+// Layout on the GPU:
+//   * one wavefront (64 lanes) per workgroup; several systems are packed
+//     into a wave, one lane per link, links of a system contiguous in
+//     breadth-first order (children of a link occupy consecutive lanes);
+//   * each lane keeps its link's constants and its step intermediates in
+//     VGPRs for the whole rollout; the time loop runs inside the kernel;
+//   * the tree recursions of the three ABA passes (and of their adjoints)
+//     are level-synchronous sweeps over tree depth; parent/child quantities
+//     move through a per-wave LDS exchange buffer [field][lane];
+//   * checkpoints are stored per lane slot, [checkpoint][field][slot], so
+//     every store and reload is a coalesced 256-byte row per wave.
+//
+// Method: ABA (Sec. 3; Fig. 1), modules in the order of Sec. 4.1, adjoints
+// in reverse order, intermediates recomputed from the stored initial state
+// of each step (Sec. 4.2, Eq. intermediate), checkpoint interval K with
+// segment replay (App. B).
+#include "aba_lane.h"
+#include "abadj_internal.h"
+
+namespace aba {
+
+namespace {
+
+constexpr int XB = 27;  // exchange-buffer fields per lane
+
+__device__ __forceinline__ void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename S>
+struct Lane {
+  int lane, slot;
+  int par, depth, cfirst, ccount, jtype, qidx, vidx, uidx;
+  __device__ bool active() const { return jtype >= 0; }
+  __device__ bool revolute() const { return jtype == 0; }
+};
+
+template <typename S>
+__device__ __forceinline__ Lane<S> load_lane(const Packed<S>& P) {
+  Lane<S> l;
+  l.lane = threadIdx.x;
+  l.slot = blockIdx.x * kWave + threadIdx.x;
+  const int ns = P.nslots;
+  const int32_t* ci = P.ci;
+  l.par = ci[CI_PARENT * ns + l.slot];
+  l.depth = ci[CI_DEPTH * ns + l.slot];
+  l.cfirst = ci[CI_CFIRST * ns + l.slot];
+  l.ccount = ci[CI_CCOUNT * ns + l.slot];
+  l.jtype = ci[CI_JTYPE * ns + l.slot];
+  l.qidx = ci[CI_QIDX * ns + l.slot];
+  l.vidx = ci[CI_VIDX * ns + l.slot];
+  l.uidx = ci[CI_UIDX * ns + l.slot];
+  return l;
+}
+
+template <typename S>
+__device__ __forceinline__ LinkC<S> load_linkc(const Packed<S>& P, int slot) {
+  const int ns = P.nslots;
+  const S* cf = P.cf;
+  LinkC<S> L;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) L.ET.m[k] = cf[(CF_ET + k) * ns + slot];
+  L.rT = v3<S>(cf[(CF_RT + 0) * ns + slot], cf[(CF_RT + 1) * ns + slot], cf[(CF_RT + 2) * ns + slot]);
+  L.ax = v3<S>(cf[(CF_AX + 0) * ns + slot], cf[(CF_AX + 1) * ns + slot], cf[(CF_AX + 2) * ns + slot]);
+  L.m = cf[CF_M * ns + slot];
+  L.mc = v3<S>(cf[(CF_MC + 0) * ns + slot], cf[(CF_MC + 1) * ns + slot], cf[(CF_MC + 2) * ns + slot]);
+  L.Ib = sy3<S>(cf[(CF_IB + 0) * ns + slot], cf[(CF_IB + 1) * ns + slot], cf[(CF_IB + 2) * ns + slot],
+                cf[(CF_IB + 3) * ns + slot], cf[(CF_IB + 4) * ns + slot], cf[(CF_IB + 5) * ns + slot]);
+  return L;
+}
+
+// ---- exchange buffer [field][lane]
+template <typename S>
+__device__ __forceinline__ void put6(S* xb, int f0, int lane, const V6<S>& v) {
+  xb[(f0 + 0) * kWave + lane] = v.a.x;
+  xb[(f0 + 1) * kWave + lane] = v.a.y;
+  xb[(f0 + 2) * kWave + lane] = v.a.z;
+  xb[(f0 + 3) * kWave + lane] = v.l.x;
+  xb[(f0 + 4) * kWave + lane] = v.l.y;
+  xb[(f0 + 5) * kWave + lane] = v.l.z;
+}
+template <typename S>
+__device__ __forceinline__ V6<S> get6(const S* xb, int f0, int lane) {
+  return v6<S>(v3<S>(xb[(f0 + 0) * kWave + lane], xb[(f0 + 1) * kWave + lane], xb[(f0 + 2) * kWave + lane]),
+               v3<S>(xb[(f0 + 3) * kWave + lane], xb[(f0 + 4) * kWave + lane], xb[(f0 + 5) * kWave + lane]));
+}
+template <typename S>
+__device__ __forceinline__ void put21(S* xb, int f0, int lane, const SySp<S>& M) {
+  const S v[21] = {M.A.xx, M.A.yy, M.A.zz, M.A.xy, M.A.xz, M.A.yz, M.B.m[0], M.B.m[1], M.B.m[2], M.B.m[3], M.B.m[4],
+                   M.B.m[5], M.B.m[6], M.B.m[7], M.B.m[8], M.C.xx, M.C.yy, M.C.zz, M.C.xy, M.C.xz, M.C.yz};
+#pragma unroll
+  for (int k = 0; k < 21; ++k) xb[(f0 + k) * kWave + lane] = v[k];
+}
+template <typename S>
+__device__ __forceinline__ SySp<S> get21(const S* xb, int f0, int lane) {
+  S v[21];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) v[k] = xb[(f0 + k) * kWave + lane];
+  SySp<S> M;
+  M.A = sy3<S>(v[0], v[1], v[2], v[3], v[4], v[5]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) M.B.m[k] = v[6 + k];
+  M.C = sy3<S>(v[15], v[16], v[17], v[18], v[19], v[20]);
+  return M;
+}
+
+// per-lane state: revolute lanes use q[0], qd[0]; a free root uses
+// q = (p, quat) and qd = body velocity [w; v]
+template <typename S, bool FREE>
+struct State {
+  S q[FREE ? 7 : 1];
+  S qd[FREE ? 6 : 1];
+};
+
+template <typename S, bool FREE>
+__device__ __forceinline__ Q4<S> st_quat(const State<S, FREE>& s) {
+  Q4<S> r;
+  if constexpr (FREE) {
+    r.x = s.q[3];
+    r.y = s.q[4];
+    r.z = s.q[5];
+    r.w = s.q[6];
+  } else {
+    r.x = r.y = r.z = S(0);
+    r.w = S(1);
+  }
+  return r;
+}
+template <typename S, bool FREE>
+__device__ __forceinline__ V6<S> st_vel6(const State<S, FREE>& s) {
+  if constexpr (FREE) return v6<S>(v3<S>(s.qd[0], s.qd[1], s.qd[2]), v3<S>(s.qd[3], s.qd[4], s.qd[5]));
+  return zero6<S>();
+}
+
+template <typename S, bool FREE>
+__device__ __forceinline__ void load_state(State<S, FREE>& s, const Lane<S>& l, const S* q, const S* qd) {
+  if (l.revolute()) {
+    s.q[0] = q[l.qidx];
+    s.qd[0] = qd[l.vidx];
+  } else if constexpr (FREE) {
+    if (l.jtype == 1) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) s.q[k] = q[l.qidx + k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s.qd[k] = qd[l.vidx + k];
+    }
+  }
+}
+template <typename S, bool FREE>
+__device__ __forceinline__ void store_state(const State<S, FREE>& s, const Lane<S>& l, S* q, S* qd) {
+  if (l.revolute()) {
+    q[l.qidx] = s.q[0];
+    qd[l.vidx] = s.qd[0];
+  } else if constexpr (FREE) {
+    if (l.jtype == 1) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) q[l.qidx + k] = s.q[k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) qd[l.vidx + k] = s.qd[k];
+    }
+  }
+}
+// lane-slot arrays [field][nslots]
+template <typename S, bool FREE>
+__device__ __forceinline__ void put_slot(const State<S, FREE>& s, S* base, int nslots, int slot) {
+#pragma unroll
+  for (int k = 0; k < (FREE ? 7 : 1); ++k) base[k * nslots + slot] = s.q[k];
+#pragma unroll
+  for (int k = 0; k < (FREE ? 6 : 1); ++k) base[((FREE ? 7 : 1) + k) * nslots + slot] = s.qd[k];
+}
+template <typename S, bool FREE>
+__device__ __forceinline__ void get_slot(State<S, FREE>& s, const S* base, int nslots, int slot) {
+#pragma unroll
+  for (int k = 0; k < (FREE ? 7 : 1); ++k) s.q[k] = base[k * nslots + slot];
+#pragma unroll
+  for (int k = 0; k < (FREE ? 6 : 1); ++k) s.qd[k] = base[((FREE ? 7 : 1) + k) * nslots + slot];
+}
+
+// Everything one ABA evaluation leaves in a lane.
+template <typename S>
+struct Step {
+  Tape<S> t;
+  V6<S> abase;  // free root: true body-frame acceleration
+};
+
+// One ABA evaluation for the whole wave (all three passes).
+template <typename S, bool FREE>
+__device__ __forceinline__ void aba_wave(const Packed<S>& P, const Lane<S>& l, const LinkC<S>& L,
+                                         const State<S, FREE>& st, S tau, int maxd, S* xb, Step<S>& o) {
+  Tape<S>& t = o.t;
+  const bool act = l.active();
+  const bool rev = l.revolute();
+  // pass 1: joint transforms (parallel over links)
+  if (rev) {
+    S s, c;
+    sincos_(st.q[0], &s, &c);
+    t.E = joint_E(L, s, c);
+  }
+  // pass 1: velocities, root -> leaves
+  for (int d = 0; d <= maxd; ++d) {
+    if (act && l.depth == d) {
+      if (rev) {
+        const V6<S> vp = (l.par >= 0) ? get6(xb, 0, l.par) : zero6<S>();
+        t.v = p1_velocity(L, t.E, st.qd[0], vp);
+      } else {
+        t.v = st_vel6(st);
+      }
+      put6(xb, 0, l.lane, t.v);
+    }
+    __syncthreads();
+  }
+  // pass 1: bias terms (parallel over links)
+  if (act) p1_bias(L, t.v, st.qd[0], rev, t.c, t.pA, t.IA);
+  // pass 2: articulated inertias, leaves -> root
+  for (int d = maxd; d >= 0; --d) {
+    if (act && l.depth == d) {
+      for (int k = 0; k < l.ccount; ++k) {
+        t.IA = t.IA + get21(xb, 0, l.cfirst + k);
+        t.pA = t.pA + get6(xb, 21, l.cfirst + k);
+      }
+      if (rev) {
+        p2_local(L, t, tau);
+        if (l.par >= 0) {
+          SySp<S> IAu;
+          V6<S> pAu;
+          p2_push(L, t, IAu, pAu);
+          put21(xb, 0, l.lane, IAu);
+          put6(xb, 21, l.lane, pAu);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // pass 3: accelerations, root -> leaves
+  const V6<S> a0 = v6<S>(zero3<S>(), v3<S>(-P.g[0], -P.g[1], -P.g[2]));
+  for (int d = 0; d <= maxd; ++d) {
+    if (act && l.depth == d) {
+      if (rev) {
+        const V6<S> ap = (l.par >= 0) ? get6(xb, 0, l.par) : a0;
+        put6(xb, 0, l.lane, p3_accel(L, t, ap));
+      } else if constexpr (FREE) {
+        root_accel(t.IA, t.pA, st_quat(st), v3<S>(P.g[0], P.g[1], P.g[2]), t.ap, o.abase);
+        put6(xb, 0, l.lane, t.ap);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename S, bool FREE>
+__device__ __forceinline__ void integrate_lane(State<S, FREE>& st, const Lane<S>& l, const Step<S>& o, S dt) {
+  if (l.revolute()) {
+    integrate_rev(st.q[0], st.qd[0], o.t.qdd, dt);
+  } else if constexpr (FREE) {
+    if (l.jtype == 1) {
+      V3<S> p = v3<S>(st.q[0], st.q[1], st.q[2]);
+      Q4<S> qt = st_quat(st);
+      V6<S> v = st_vel6(st);
+      integrate_root(p, qt, v, o.abase, dt);
+      st.q[0] = p.x; st.q[1] = p.y; st.q[2] = p.z;
+      st.q[3] = qt.x; st.q[4] = qt.y; st.q[5] = qt.z; st.q[6] = qt.w;
+      st.qd[0] = v.a.x; st.qd[1] = v.a.y; st.qd[2] = v.a.z;
+      st.qd[3] = v.l.x; st.qd[4] = v.l.y; st.qd[5] = v.l.z;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <typename S, bool FREE>
+__global__ __launch_bounds__(64) void k_aba(AbaArgs<S> A) {
+  __shared__ S xb[XB * kWave];
+  const Lane<S> l = load_lane(A.P);
+  const int maxd = A.P.wmaxd[blockIdx.x];
+  LinkC<S> L = {};
+  State<S, FREE> st = {};
+  S tau = S(0);
+  if (l.active()) {
+    L = load_linkc(A.P, l.slot);
+    load_state(st, l, A.q, A.qd);
+    if (l.revolute()) tau = A.tau[l.uidx];
+  }
+  Step<S> o;
+  aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+  if (l.revolute()) {
+    A.qdd[l.vidx] = o.t.qdd;
+  } else if constexpr (FREE) {
+    if (l.jtype == 1) {
+      const S a[6] = {o.abase.a.x, o.abase.a.y, o.abase.a.z, o.abase.l.x, o.abase.l.y, o.abase.l.z};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) A.qdd[l.vidx + k] = a[k];
+    }
+  }
+}
+
+// Forward rollout.  CK: store the initial state of every K-th step.
+// TRAJ: also write x^{t+1} for every step.
+template <typename S, bool FREE, bool CK, bool TRAJ>
+__global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
+  __shared__ S xb[XB * kWave];
+  const Lane<S> l = load_lane(A.P);
+  const int maxd = A.P.wmaxd[blockIdx.x];
+  const int ns = A.P.nslots;
+  const int nu = A.P.nu;
+  LinkC<S> L = {};
+  State<S, FREE> st = {};
+  if (l.active()) {
+    L = load_linkc(A.P, l.slot);
+    load_state(st, l, A.q0, A.qd0);
+  }
+  const bool has_tau = l.revolute();
+  S tau_next = (has_tau && A.T > 0) ? A.tau[l.uidx] : S(0);
+  constexpr int W = state_width(FREE);
+  for (int t = 0; t < A.T; ++t) {
+    if constexpr (CK) {
+      if (l.active() && (t % A.K) == 0) put_slot(st, A.ck + (size_t)(t / A.K) * W * ns, ns, l.slot);
+    }
+    const S tau = tau_next;
+    if (has_tau && t + 1 < A.T) tau_next = A.tau[(size_t)(t + 1) * nu + l.uidx];
+    Step<S> o;
+    aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+    if (l.active()) integrate_lane(st, l, o, A.dt);
+    if constexpr (TRAJ) {
+      if (l.active()) {
+        S* row = A.traj + (size_t)t * (A.P.nq + A.P.nv);
+        store_state(st, l, row, row + A.P.nq);
+      }
+    }
+  }
+  if (l.active()) store_state(st, l, A.qT, A.qdT);
+}
+
+// One reverse step: recompute the ABA intermediates of step t from its
+// initial state st, then run the adjoints of the integrator, pass 3, pass 2
+// and pass 1.  xb1 holds the adjoint of x^{t+1} on entry and that of x^t on
+// exit; tau_bar^t is written to gtau.
+template <typename S, bool FREE>
+__device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
+                                         S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1) {
+  const bool act = l.active();
+  const bool rev = l.revolute();
+  const V3<S> g = v3<S>(A.P.g[0], A.P.g[1], A.P.g[2]);
+  Step<S> o;
+  aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+  const Tape<S>& tp = o.t;
+
+  // adjoint of the integrator
+  S acc_q = S(0), acc_qd = S(0), qddb = S(0);
+  V6<S> qddb6 = zero6<S>();
+  V3<S> pb = zero3<S>();
+  Q4<S> quatb = {S(0), S(0), S(0), S(0)};
+  V6<S> vb6 = zero6<S>();
+  if (rev) {
+    const S tot = xb1.qd[0] + A.dt * xb1.q[0];
+    qddb = A.dt * tot;
+    acc_q = xb1.q[0];
+    acc_qd = tot;
+  } else if constexpr (FREE) {
+    if (l.jtype == 1) {
+      pb = v3<S>(xb1.q[0], xb1.q[1], xb1.q[2]);
+      quatb.x = xb1.q[3]; quatb.y = xb1.q[4]; quatb.z = xb1.q[5]; quatb.w = xb1.q[6];
+      vb6 = st_vel6(xb1);
+      qddb6 = integrate_root_adj(st_quat(st), st_vel6(st), o.abase, A.dt, pb, quatb, vb6);
+    }
+  }
+  Bar<S> b;
+  bar_zero(b);
+  // reverse of pass 3, leaves -> root
+  SySp<S> IAb = zero_sysp<S>();
+  V6<S> pAb = zero6<S>();
+  for (int d = maxd; d >= 0; --d) {
+    if (act && l.depth == d) {
+      V6<S> ab = zero6<S>();
+      for (int k = 0; k < l.ccount; ++k) ab = ab + get6(xb, 0, l.cfirst + k);
+      if (rev) {
+        const V6<S> apb = r3_link(L, tp, b, ab, qddb);
+        if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, apb));
+      } else if constexpr (FREE) {
+        r3_root(tp.IA, tp.ap, st_quat(st), g, ab, qddb6, quatb, IAb, pAb);
+      }
+    }
+    __syncthreads();
+  }
+  // reverse of pass 2, root -> leaves
+  S taub = S(0);
+  for (int d = 0; d <= maxd; ++d) {
+    if (act && l.depth == d) {
+      if (rev) {
+        const bool hp = l.par >= 0;
+        const SySp<S> IAbp = hp ? get21(xb, 0, l.par) : zero_sysp<S>();
+        const V6<S> pAbp = hp ? get6(xb, 21, l.par) : zero6<S>();
+        taub = r2_link(L, tp, b, hp, IAbp, pAbp, IAb, pAb);
+      }
+      put21(xb, 0, l.lane, IAb);
+      put6(xb, 21, l.lane, pAb);
+    }
+    __syncthreads();
+  }
+  // reverse of pass 1, leaves -> root
+  for (int d = maxd; d >= 0; --d) {
+    if (act && l.depth == d) {
+      V6<S> vb = zero6<S>();
+      for (int k = 0; k < l.ccount; ++k) vb = vb + get6(xb, 0, l.cfirst + k);
+      if (rev) {
+        const V6<S> up = r1_link(L, tp, b, vb, pAb, st.qd[0]);
+        if (l.par >= 0) put6(xb, 0, l.lane, up);
+      } else if constexpr (FREE) {
+        vb6 = vb6 + r1_root(L, tp.v, vb, pAb);
+      }
+    }
+    __syncthreads();
+  }
+  // adjoint of the step's initial state; tau_bar
+  if (rev) {
+    xb1.q[0] = acc_q + b.q;
+    xb1.qd[0] = acc_qd + b.qd;
+    A.gtau[(size_t)t * A.P.nu + l.uidx] = taub;
+  } else if constexpr (FREE) {
+    if (l.jtype == 1) {
+      xb1.q[0] = pb.x; xb1.q[1] = pb.y; xb1.q[2] = pb.z;
+      xb1.q[3] = quatb.x; xb1.q[4] = quatb.y; xb1.q[5] = quatb.z; xb1.q[6] = quatb.w;
+      xb1.qd[0] = vb6.a.x; xb1.qd[1] = vb6.a.y; xb1.qd[2] = vb6.a.z;
+      xb1.qd[3] = vb6.l.x; xb1.qd[4] = vb6.l.y; xb1.qd[5] = vb6.l.z;
+    }
+  }
+  if (act && A.gtraj != nullptr && t >= 1) {
+    State<S, FREE> gt;
+    const S* row = A.gtraj + (size_t)(t - 1) * (A.P.nq + A.P.nv);
+    load_state(gt, l, row, row + A.P.nq);
+#pragma unroll
+    for (int k = 0; k < (FREE ? 7 : 1); ++k) xb1.q[k] += gt.q[k];
+#pragma unroll
+    for (int k = 0; k < (FREE ? 6 : 1); ++k) xb1.qd[k] += gt.qd[k];
+  }
+}
+
+// Backward (adjoint) rollout, reverse time.  K == 1 reloads every step's
+// checkpoint; K > 1 replays each K-step segment from its checkpoint into
+// the scratch buffer first.  The next state and control are fetched one
+// step ahead.
+template <typename S, bool FREE>
+__global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
+  __shared__ S xb[XB * kWave];
+  const Lane<S> l = load_lane(A.P);
+  const int maxd = A.P.wmaxd[blockIdx.x];
+  const int ns = A.P.nslots;
+  const int nu = A.P.nu;
+  const bool act = l.active();
+  const bool rev = l.revolute();
+  constexpr int W = state_width(FREE);
+  LinkC<S> L = {};
+  State<S, FREE> xb1 = {};
+  if (act) {
+    L = load_linkc(A.P, l.slot);
+    load_state(xb1, l, A.gqT, A.gqdT);
+    if (A.gtraj != nullptr && A.T > 0) {
+      State<S, FREE> gt;
+      const S* row = A.gtraj + (size_t)(A.T - 1) * (A.P.nq + A.P.nv);
+      load_state(gt, l, row, row + A.P.nq);
+#pragma unroll
+      for (int k = 0; k < (FREE ? 7 : 1); ++k) xb1.q[k] += gt.q[k];
+#pragma unroll
+      for (int k = 0; k < (FREE ? 6 : 1); ++k) xb1.qd[k] += gt.qd[k];
+    }
+  }
+  if (A.K == 1) {
+    State<S, FREE> nxt = {};
+    S tau_nxt = S(0);
+    if (A.T > 0) {
+      if (act) get_slot(nxt, A.ck + (size_t)(A.T - 1) * W * ns, ns, l.slot);
+      if (rev) tau_nxt = A.tau[(size_t)(A.T - 1) * nu + l.uidx];
+    }
+    for (int t = A.T - 1; t >= 0; --t) {
+      const State<S, FREE> st = nxt;
+      const S tau = tau_nxt;
+      if (t > 0) {
+        if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * W * ns, ns, l.slot);
+        if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
+      }
+      bwd_step<S, FREE>(A, l, L, maxd, xb, st, tau, t, xb1);
+    }
+  } else {
+    const int ncp = (A.T + A.K - 1) / A.K;
+    for (int s = ncp - 1; s >= 0; --s) {
+      const int t0 = s * A.K;
+      const int t1 = min(t0 + A.K, A.T);
+      // replay the segment from its checkpoint into the scratch buffer
+      State<S, FREE> st = {};
+      if (act) {
+        get_slot(st, A.ck + (size_t)s * W * ns, ns, l.slot);
+        put_slot(st, A.scratch, ns, l.slot);
+      }
+      S tau_nxt = (rev && t1 - t0 > 1) ? A.tau[(size_t)t0 * nu + l.uidx] : S(0);
+      for (int j = 1; j < t1 - t0; ++j) {
+        const S tau = tau_nxt;
+        if (rev && j + 1 < t1 - t0) tau_nxt = A.tau[(size_t)(t0 + j) * nu + l.uidx];
+        Step<S> o;
+        aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+        if (act) {
+          integrate_lane(st, l, o, A.dt);
+          put_slot(st, A.scratch + (size_t)j * W * ns, ns, l.slot);
+        }
+      }
+      State<S, FREE> nxt = {};
+      if (act) get_slot(nxt, A.scratch + (size_t)(t1 - 1 - t0) * W * ns, ns, l.slot);
+      tau_nxt = rev ? A.tau[(size_t)(t1 - 1) * nu + l.uidx] : S(0);
+      for (int t = t1 - 1; t >= t0; --t) {
+        const State<S, FREE> cur = nxt;
+        const S tau = tau_nxt;
+        if (t > t0) {
+          if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * W * ns, ns, l.slot);
+          if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
+        }
+        bwd_step<S, FREE>(A, l, L, maxd, xb, cur, tau, t, xb1);
+      }
+    }
+  }
+  if (act) store_state(xb1, l, A.gq0, A.gqd0);
+}
+
+}  // namespace
+
+template <typename S>
+hipError_t launch_aba(const AbaArgs<S>& a, bool has_free, hipStream_t st) {
+  if (a.P.nwaves == 0) return hipSuccess;
+  dim3 grid(a.P.nwaves), block(kWave);
+  if (has_free)
+    hipLaunchKernelGGL((k_aba<S, true>), grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_aba<S, false>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_forward(const FwdArgs<S>& a, bool has_free, hipStream_t st) {
+  if (a.P.nwaves == 0) return hipSuccess;
+  dim3 grid(a.P.nwaves), block(kWave);
+  const bool ck = a.ck != nullptr, tr = a.traj != nullptr;
+#define ABA_FWD(F, C, R) hipLaunchKernelGGL((k_forward<S, F, C, R>), grid, block, 0, st, a)
+  if (has_free) {
+    if (ck && tr) ABA_FWD(true, true, true);
+    else if (ck) ABA_FWD(true, true, false);
+    else if (tr) ABA_FWD(true, false, true);
+    else ABA_FWD(true, false, false);
+  } else {
+    if (ck && tr) ABA_FWD(false, true, true);
+    else if (ck) ABA_FWD(false, true, false);
+    else if (tr) ABA_FWD(false, false, true);
+    else ABA_FWD(false, false, false);
+  }
+#undef ABA_FWD
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_backward(const BwdArgs<S>& a, bool has_free, hipStream_t st) {
+  if (a.P.nwaves == 0) return hipSuccess;
+  dim3 grid(a.P.nwaves), block(kWave);
+  if (has_free)
+    hipLaunchKernelGGL((k_backward<S, true>), grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_backward<S, false>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_aba<float>(const AbaArgs<float>&, bool, hipStream_t);
+template hipError_t launch_aba<double>(const AbaArgs<double>&, bool, hipStream_t);
+template hipError_t launch_forward<float>(const FwdArgs<float>&, bool, hipStream_t);
+template hipError_t launch_forward<double>(const FwdArgs<double>&, bool, hipStream_t);
+template hipError_t launch_backward<float>(const BwdArgs<float>&, bool, hipStream_t);
+template hipError_t launch_backward<double>(const BwdArgs<double>&, bool, hipStream_t);
+
+}  // namespace aba

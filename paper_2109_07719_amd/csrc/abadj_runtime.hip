@@ -1,0 +1,599 @@
+// Host runtime behind the C ABI of include/abadj.h: validation, breadth-first
+// ordering, packing of systems into wavefronts (one lane per link), upload of
+// the per-link constants, workspace sizing, kernel launches, error codes, and
+// algorithmic operation counts.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/abadj.h"
+#include "aba_lane.h"
+#include "abadj_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct sim_handle {
+  int dtype = SIM_F32;
+  int n_sys = 0, n_links = 0, nq = 0, nv = 0, nu = 0;
+  int nwaves = 0, nslots = 0, max_depth = 0;
+  bool has_free = false;
+  double g[3] = {0, 0, 0};
+  int32_t* d_ci = nullptr;
+  void* d_cf = nullptr;
+  int32_t* d_wmaxd = nullptr;
+  // host-side structure summary for operation counting
+  std::vector<int32_t> jtype, parent, nchild;
+};
+
+namespace {
+
+template <typename S>
+aba::Packed<S> packed(const sim_handle* h) {
+  aba::Packed<S> P;
+  P.ci = h->d_ci;
+  P.cf = static_cast<const S*>(h->d_cf);
+  P.wmaxd = h->d_wmaxd;
+  P.nslots = h->nslots;
+  P.nwaves = h->nwaves;
+  for (int k = 0; k < 3; ++k) P.g[k] = static_cast<S>(h->g[k]);
+  P.nq = h->nq;
+  P.nv = h->nv;
+  P.nu = h->nu;
+  return P;
+}
+
+size_t elem(const sim_handle* h) { return h->dtype == SIM_F64 ? sizeof(double) : sizeof(float); }
+
+size_t ckpt_bytes(const sim_handle* h, int T, int K) {
+  const size_t W = aba::state_width(h->has_free);
+  const size_t ncp = (T > 0) ? (size_t)((T + K - 1) / K) : 0;
+  return align256(ncp * W * h->nslots * elem(h));
+}
+size_t scratch_bytes(const sim_handle* h, int K) {
+  if (K <= 1) return 0;
+  return align256((size_t)K * aba::state_width(h->has_free) * h->nslots * elem(h));
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+template <typename S>
+int upload(sim_handle* h, const std::vector<int32_t>& ci, const std::vector<double>& cf,
+           const std::vector<int32_t>& wmaxd) {
+  std::vector<S> cfs(cf.size());
+  for (size_t i = 0; i < cf.size(); ++i) cfs[i] = static_cast<S>(cf[i]);
+  if (hipMalloc(&h->d_ci, ci.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&h->d_cf, cfs.size() * sizeof(S)) != hipSuccess ||
+      hipMalloc(&h->d_wmaxd, wmaxd.size() * sizeof(int32_t)) != hipSuccess)
+    return fail(SIM_ERR_HIP, "sim_create: device allocation failed");
+  if (hipMemcpy(h->d_ci, ci.data(), ci.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_cf, cfs.data(), cfs.size() * sizeof(S), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_wmaxd, wmaxd.data(), wmaxd.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(SIM_ERR_HIP, "sim_create: upload failed");
+  return SIM_OK;
+}
+
+void release(sim_handle* h) {
+  if (!h) return;
+  if (h->d_ci) (void)hipFree(h->d_ci);
+  if (h->d_cf) (void)hipFree(h->d_cf);
+  if (h->d_wmaxd) (void)hipFree(h->d_wmaxd);
+  h->d_ci = nullptr;
+  h->d_cf = nullptr;
+  h->d_wmaxd = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sim_last_error(void) { return g_err.c_str(); }
+
+int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t* out) {
+  g_err.clear();
+  if (!topo || !prm || !out) return fail(SIM_ERR_INVALID_ARG, "sim_create: null argument");
+  *out = nullptr;
+  if (dtype != SIM_F32 && dtype != SIM_F64) return fail(SIM_ERR_UNSUPPORTED_DTYPE, "sim_create: dtype must be SIM_F32 or SIM_F64");
+  if (topo->n_sys < 1 || !topo->link_offset || !topo->parent || !topo->jtype)
+    return fail(SIM_ERR_INVALID_ARG, "sim_create: empty batch or null topology array");
+  if (!prm->E_T || !prm->r_T || !prm->axis || !prm->mass || !prm->com || !prm->Ic || !prm->gravity)
+    return fail(SIM_ERR_INVALID_ARG, "sim_create: null parameter array");
+  const int ns = topo->n_sys;
+  const int32_t* off = topo->link_offset;
+  if (off[0] != 0) return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: link_offset[0] must be 0");
+  for (int s = 0; s < ns; ++s) {
+    const int n = off[s + 1] - off[s];
+    if (n < 1 || n > SIM_MAX_LINKS)
+      return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: system " + std::to_string(s) + " has " +
+                                                std::to_string(n) + " links (allowed 1.." +
+                                                std::to_string(SIM_MAX_LINKS) + ")");
+  }
+  const int nl = off[ns];
+  if (!finite_all(prm->E_T, 9 * (size_t)nl) || !finite_all(prm->r_T, 3 * (size_t)nl) ||
+      !finite_all(prm->axis, 3 * (size_t)nl) || !finite_all(prm->mass, nl) || !finite_all(prm->com, 3 * (size_t)nl) ||
+      !finite_all(prm->Ic, 6 * (size_t)nl) || !finite_all(prm->gravity, 3))
+    return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: non-finite parameter");
+
+  sim_handle* h = new (std::nothrow) sim_handle();
+  if (!h) return fail(SIM_ERR_INVALID_ARG, "sim_create: out of host memory");
+  h->dtype = dtype;
+  h->n_sys = ns;
+  h->n_links = nl;
+  for (int k = 0; k < 3; ++k) h->g[k] = prm->gravity[k];
+  h->jtype.assign(topo->jtype, topo->jtype + nl);
+  h->parent.assign(topo->parent, topo->parent + nl);
+  h->nchild.assign(nl, 0);
+
+  // per system: validation, breadth-first order, depth, offsets
+  std::vector<int> sys_q(ns + 1, 0), sys_v(ns + 1, 0), sys_u(ns + 1, 0), sys_depth(ns, 0);
+  std::vector<int> loc_q(nl), loc_v(nl), loc_u(nl), depth(nl), bfs(nl), bfs_pos(nl);
+  for (int s = 0; s < ns; ++s) {
+    const int b = off[s], n = off[s + 1] - off[s];
+    int q = 0, v = 0, u = 0;
+    for (int i = 0; i < n; ++i) {
+      const int p = topo->parent[b + i], jt = topo->jtype[b + i];
+      if (p < -1 || p >= i) {
+        delete h;
+        return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: system " + std::to_string(s) + " link " + std::to_string(i) +
+                                                  ": parent must satisfy -1 <= parent < index");
+      }
+      if (jt != SIM_JOINT_REVOLUTE && jt != SIM_JOINT_FREE) {
+        delete h;
+        return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: unknown joint type");
+      }
+      if (jt == SIM_JOINT_FREE && (i != 0 || p != -1)) {
+        delete h;
+        return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: a free joint is allowed only at local index 0 with parent -1");
+      }
+      if (i > 0 && p == -1 && topo->jtype[b] == SIM_JOINT_FREE) {
+        delete h;
+        return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: with a free root every other link needs a parent");
+      }
+      if (!(prm->mass[b + i] > 0)) {
+        delete h;
+        return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: mass must be positive");
+      }
+      if (jt == SIM_JOINT_REVOLUTE) {
+        const double* a = prm->axis + 3 * (size_t)(b + i);
+        const double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        if (std::fabs(nrm - 1.0) > 1e-6) {
+          delete h;
+          return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: joint axes must be unit vectors");
+        }
+      }
+      depth[b + i] = (p < 0) ? 0 : depth[b + p] + 1;
+      sys_depth[s] = std::max(sys_depth[s], depth[b + i]);
+      if (p >= 0) h->nchild[b + p] += 1;
+      loc_q[b + i] = q;
+      loc_v[b + i] = v;
+      loc_u[b + i] = (jt == SIM_JOINT_FREE) ? -1 : u;
+      if (jt == SIM_JOINT_FREE) {
+        q += 7;
+        v += 6;
+        h->has_free = true;
+      } else {
+        q += 1;
+        v += 1;
+        u += 1;
+      }
+    }
+    sys_q[s + 1] = sys_q[s] + q;
+    sys_v[s + 1] = sys_v[s] + v;
+    sys_u[s + 1] = sys_u[s] + u;
+    // breadth-first order: roots, then children of each dequeued link
+    int w = 0;
+    for (int i = 0; i < n; ++i)
+      if (topo->parent[b + i] < 0) bfs[b + w++] = i;
+    for (int r = 0; r < w; ++r) {
+      const int cur = bfs[b + r];
+      for (int i = cur + 1; i < n; ++i)
+        if (topo->parent[b + i] == cur) bfs[b + w++] = i;
+    }
+    for (int k = 0; k < n; ++k) bfs_pos[b + bfs[b + k]] = k;
+  }
+  h->nq = sys_q[ns];
+  h->nv = sys_v[ns];
+  h->nu = sys_u[ns];
+
+  // pack systems into wavefronts: group by tree depth (so a wave's
+  // level-synchronous sweeps are not stretched by one deep system), largest
+  // first, first fit
+  std::vector<int> order(ns);
+  for (int s = 0; s < ns; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    if (sys_depth[a] != sys_depth[c]) return sys_depth[a] > sys_depth[c];
+    return (off[a + 1] - off[a]) > (off[c + 1] - off[c]);
+  });
+  std::vector<int> wave_used, wave_depth, sys_wave(ns), sys_lane0(ns);
+  int group_start = 0;
+  for (int k = 0; k < ns; ++k) {
+    const int s = order[k];
+    const int n = off[s + 1] - off[s];
+    if (k > 0 && sys_depth[s] != sys_depth[order[k - 1]]) group_start = (int)wave_used.size();
+    int w = -1;
+    for (int c = group_start; c < (int)wave_used.size(); ++c)
+      if (wave_used[c] + n <= aba::kWave) {
+        w = c;
+        break;
+      }
+    if (w < 0) {
+      w = (int)wave_used.size();
+      wave_used.push_back(0);
+      wave_depth.push_back(0);
+    }
+    sys_wave[s] = w;
+    sys_lane0[s] = wave_used[w];
+    wave_used[w] += n;
+    wave_depth[w] = std::max(wave_depth[w], sys_depth[s]);
+  }
+  h->nwaves = (int)wave_used.size();
+  h->nslots = h->nwaves * aba::kWave;
+  h->max_depth = 0;
+  for (int d : wave_depth) h->max_depth = std::max(h->max_depth, d);
+
+  const int NS = h->nslots;
+  std::vector<int32_t> ci((size_t)aba::CI_COUNT * NS, 0);
+  std::vector<double> cf((size_t)aba::CF_COUNT * NS, 0.0);
+  for (int slot = 0; slot < NS; ++slot) ci[(size_t)aba::CI_JTYPE * NS + slot] = -1;
+  for (int slot = 0; slot < NS; ++slot) ci[(size_t)aba::CI_PARENT * NS + slot] = -1;
+  for (int s = 0; s < ns; ++s) {
+    const int b = off[s], n = off[s + 1] - off[s];
+    const int base_slot = sys_wave[s] * aba::kWave + sys_lane0[s];
+    for (int i = 0; i < n; ++i) {
+      const int L = b + i;
+      const int slot = base_slot + bfs_pos[L];
+      const int lane = slot % aba::kWave;
+      auto CI = [&](int f) -> int32_t& { return ci[(size_t)f * NS + slot]; };
+      auto CF = [&](int f) -> double& { return cf[(size_t)f * NS + slot]; };
+      const int p = topo->parent[L];
+      CI(aba::CI_PARENT) = (p < 0) ? -1 : (lane - bfs_pos[L] + bfs_pos[b + p]);
+      CI(aba::CI_DEPTH) = depth[L];
+      int first = -1, cnt = 0;
+      for (int j = i + 1; j < n; ++j)
+        if (topo->parent[b + j] == i) {
+          const int lj = lane - bfs_pos[L] + bfs_pos[b + j];
+          if (first < 0 || lj < first) first = lj;
+          ++cnt;
+        }
+      CI(aba::CI_CFIRST) = (cnt > 0) ? first : 0;
+      CI(aba::CI_CCOUNT) = cnt;
+      CI(aba::CI_JTYPE) = topo->jtype[L];
+      CI(aba::CI_QIDX) = sys_q[s] + loc_q[L];
+      CI(aba::CI_VIDX) = sys_v[s] + loc_v[L];
+      CI(aba::CI_UIDX) = (loc_u[L] < 0) ? -1 : sys_u[s] + loc_u[L];
+      for (int k = 0; k < 9; ++k) CF(aba::CF_ET + k) = prm->E_T[9 * (size_t)L + k];
+      for (int k = 0; k < 3; ++k) CF(aba::CF_RT + k) = prm->r_T[3 * (size_t)L + k];
+      for (int k = 0; k < 3; ++k) CF(aba::CF_AX + k) = prm->axis[3 * (size_t)L + k];
+      const double m = prm->mass[L];
+      const double* c = prm->com + 3 * (size_t)L;
+      const double* I = prm->Ic + 6 * (size_t)L;
+      CF(aba::CF_M) = m;
+      for (int k = 0; k < 3; ++k) CF(aba::CF_MC + k) = m * c[k];
+      // inertia about the link origin: Ic - m [c]x^2 = Ic + m (|c|^2 1 - c c^T)
+      CF(aba::CF_IB + 0) = I[0] + m * (c[1] * c[1] + c[2] * c[2]);
+      CF(aba::CF_IB + 1) = I[1] + m * (c[0] * c[0] + c[2] * c[2]);
+      CF(aba::CF_IB + 2) = I[2] + m * (c[0] * c[0] + c[1] * c[1]);
+      CF(aba::CF_IB + 3) = I[3] - m * c[0] * c[1];
+      CF(aba::CF_IB + 4) = I[4] - m * c[0] * c[2];
+      CF(aba::CF_IB + 5) = I[5] - m * c[1] * c[2];
+    }
+  }
+  // children of a link are consecutive lanes in breadth-first order
+  for (int slot = 0; slot < NS; ++slot) {
+    const int cnt = ci[(size_t)aba::CI_CCOUNT * NS + slot];
+    const int first = ci[(size_t)aba::CI_CFIRST * NS + slot];
+    const int w = slot / aba::kWave;
+    for (int k = 0; k < cnt; ++k) {
+      const int cs = w * aba::kWave + first + k;
+      if (ci[(size_t)aba::CI_PARENT * NS + cs] != slot % aba::kWave) {
+        delete h;
+        return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: internal packing error (children not contiguous)");
+      }
+    }
+  }
+  std::vector<int32_t> wmaxd(wave_depth.begin(), wave_depth.end());
+  const int rc = (dtype == SIM_F64) ? upload<double>(h, ci, cf, wmaxd) : upload<float>(h, ci, cf, wmaxd);
+  if (rc != SIM_OK) {
+    release(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SIM_OK;
+}
+
+void sim_destroy(sim_t h) {
+  if (!h) return;
+  release(h);
+  delete h;
+}
+
+int sim_get_info(sim_t h, sim_info_t* o) {
+  if (!h || !o) return fail(SIM_ERR_INVALID_ARG, "sim_get_info: null argument");
+  o->n_sys = h->n_sys;
+  o->n_links = h->n_links;
+  o->nq = h->nq;
+  o->nv = h->nv;
+  o->nu = h->nu;
+  o->n_waves = h->nwaves;
+  o->n_slots = h->nslots;
+  o->max_depth = h->max_depth;
+  o->has_free = h->has_free ? 1 : 0;
+  o->dtype = h->dtype;
+  return SIM_OK;
+}
+
+int sim_workspace_bytes(sim_t h, int T, int K, size_t* bytes) {
+  if (!h || !bytes) return fail(SIM_ERR_INVALID_ARG, "sim_workspace_bytes: null argument");
+  if (T < 0 || K < 1) return fail(SIM_ERR_INVALID_ARG, "sim_workspace_bytes: need T >= 0 and K >= 1");
+  *bytes = ckpt_bytes(h, T, K) + scratch_bytes(h, K);
+  return SIM_OK;
+}
+
+static int check_run(sim_t h, double dt, int T, int K, const char* who) {
+  if (!h) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": null handle");
+  if (T < 0) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": T must be >= 0");
+  if (K < 1) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": K must be >= 1");
+  if (!std::isfinite(dt) || !(dt > 0)) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": dt must be finite and > 0");
+  return SIM_OK;
+}
+
+int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, double dt, int T, int K, void* qT,
+                void* qdT, void* traj, void* workspace, size_t workspace_bytes, void* stream) {
+  g_err.clear();
+  int rc = check_run(h, dt, T, K, "sim_forward");
+  if (rc) return rc;
+  if (!q0 || !qd0 || !qT || !qdT || (T > 0 && h->nu > 0 && !tau))
+    return fail(SIM_ERR_INVALID_ARG, "sim_forward: null array argument");
+  if (workspace) {
+    size_t need = 0;
+    sim_workspace_bytes(h, T, K, &need);
+    if (workspace_bytes < need)
+      return fail(SIM_ERR_WORKSPACE_TOO_SMALL, "sim_forward: workspace of " + std::to_string(workspace_bytes) +
+                                                   " bytes, need " + std::to_string(need));
+  }
+  hipError_t e;
+  if (h->dtype == SIM_F64) {
+    aba::FwdArgs<double> a;
+    a.P = packed<double>(h);
+    a.dt = dt;
+    a.T = T;
+    a.K = K;
+    a.q0 = (const double*)q0;
+    a.qd0 = (const double*)qd0;
+    a.tau = (const double*)tau;
+    a.qT = (double*)qT;
+    a.qdT = (double*)qdT;
+    a.traj = (double*)traj;
+    a.ck = (double*)workspace;
+    e = aba::launch_forward(a, h->has_free, (hipStream_t)stream);
+  } else {
+    aba::FwdArgs<float> a;
+    a.P = packed<float>(h);
+    a.dt = (float)dt;
+    a.T = T;
+    a.K = K;
+    a.q0 = (const float*)q0;
+    a.qd0 = (const float*)qd0;
+    a.tau = (const float*)tau;
+    a.qT = (float*)qT;
+    a.qdT = (float*)qdT;
+    a.traj = (float*)traj;
+    a.ck = (float*)workspace;
+    e = aba::launch_forward(a, h->has_free, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_forward: launch failed: ") + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* gqT, const void* gqdT,
+                 const void* gtraj, void* gq0, void* gqd0, void* gtau, void* workspace, size_t workspace_bytes,
+                 void* stream) {
+  g_err.clear();
+  int rc = check_run(h, dt, T, K, "sim_backward");
+  if (rc) return rc;
+  if (!gqT || !gqdT || !gq0 || !gqd0 || (T > 0 && h->nu > 0 && (!tau || !gtau)) || (T > 0 && !workspace))
+    return fail(SIM_ERR_INVALID_ARG, "sim_backward: null array argument");
+  size_t need = 0;
+  sim_workspace_bytes(h, T, K, &need);
+  if (T > 0 && workspace_bytes < need)
+    return fail(SIM_ERR_WORKSPACE_TOO_SMALL, "sim_backward: workspace of " + std::to_string(workspace_bytes) +
+                                                 " bytes, need " + std::to_string(need));
+  const size_t ck = ckpt_bytes(h, T, K);
+  hipError_t e;
+  if (h->dtype == SIM_F64) {
+    aba::BwdArgs<double> a;
+    a.P = packed<double>(h);
+    a.dt = dt;
+    a.T = T;
+    a.K = K;
+    a.tau = (const double*)tau;
+    a.gqT = (const double*)gqT;
+    a.gqdT = (const double*)gqdT;
+    a.gtraj = (const double*)gtraj;
+    a.gq0 = (double*)gq0;
+    a.gqd0 = (double*)gqd0;
+    a.gtau = (double*)gtau;
+    a.ck = (const double*)workspace;
+    a.scratch = (K > 1) ? (double*)((char*)workspace + ck) : nullptr;
+    e = aba::launch_backward(a, h->has_free, (hipStream_t)stream);
+  } else {
+    aba::BwdArgs<float> a;
+    a.P = packed<float>(h);
+    a.dt = (float)dt;
+    a.T = T;
+    a.K = K;
+    a.tau = (const float*)tau;
+    a.gqT = (const float*)gqT;
+    a.gqdT = (const float*)gqdT;
+    a.gtraj = (const float*)gtraj;
+    a.gq0 = (float*)gq0;
+    a.gqd0 = (float*)gqd0;
+    a.gtau = (float*)gtau;
+    a.ck = (const float*)workspace;
+    a.scratch = (K > 1) ? (float*)((char*)workspace + ck) : nullptr;
+    e = aba::launch_backward(a, h->has_free, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_backward: launch failed: ") + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+int sim_aba(sim_t h, const void* q, const void* qd, const void* tau, void* qdd, void* stream) {
+  g_err.clear();
+  if (!h || !q || !qd || !qdd || (h->nu > 0 && !tau)) return fail(SIM_ERR_INVALID_ARG, "sim_aba: null argument");
+  hipError_t e;
+  if (h->dtype == SIM_F64) {
+    aba::AbaArgs<double> a;
+    a.P = packed<double>(h);
+    a.q = (const double*)q;
+    a.qd = (const double*)qd;
+    a.tau = (const double*)tau;
+    a.qdd = (double*)qdd;
+    e = aba::launch_aba(a, h->has_free, (hipStream_t)stream);
+  } else {
+    aba::AbaArgs<float> a;
+    a.P = packed<float>(h);
+    a.q = (const float*)q;
+    a.qd = (const float*)qd;
+    a.tau = (const float*)tau;
+    a.qdd = (float*)qdd;
+    e = aba::launch_aba(a, h->has_free, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_aba: launch failed: ") + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ operation counts
+namespace {
+
+thread_local long long g_ops = 0;
+
+struct Op {
+  Op() = default;
+  Op(double) {}
+};
+inline Op operator+(Op, Op) { ++g_ops; return {}; }
+inline Op operator-(Op, Op) { ++g_ops; return {}; }
+inline Op operator*(Op, Op) { ++g_ops; return {}; }
+inline Op operator/(Op, Op) { ++g_ops; return {}; }
+inline Op operator-(Op) { return {}; }
+inline Op sqrt(Op) { ++g_ops; return {}; }
+
+template <typename F>
+long long count(F&& f) {
+  g_ops = 0;
+  f();
+  return g_ops;
+}
+
+struct LinkOps {
+  long long fd_rev, fd_rev_push, p1_root_rev_extra, child_fwd, integ_rev;
+  long long fd_free, integ_free;
+  long long bwd_rev, bwd_rev_push, child_bwd, integ_adj_rev;
+  long long bwd_free;
+};
+
+LinkOps link_ops() {
+  using namespace aba;
+  LinkOps o{};
+  LinkC<Op> L{};
+  Tape<Op> t{};
+  V6<Op> v{}, w{};
+  SySp<Op> M{}, M2{};
+  Q4<Op> qt{};
+  V3<Op> g{};
+  Bar<Op> b{};
+  // one revolute ABA evaluation (sin and cos counted as one operation each)
+  o.fd_rev = 2 + count([&] {
+               t.E = joint_E(L, Op(), Op());
+               t.v = p1_velocity(L, t.E, Op(), v);
+               p1_bias(L, t.v, Op(), true, t.c, t.pA, t.IA);
+               p2_local(L, t, Op());
+               (void)p3_accel(L, t, v);
+             });
+  o.fd_rev_push = count([&] { p2_push(L, t, M, w); });
+  o.child_fwd = 27;  // IA (21) and pA (6) of each child added to its parent
+  o.integ_rev = count([&] {
+    Op q, qd;
+    integrate_rev(q, qd, Op(), Op());
+  });
+  o.fd_free = count([&] {
+    p1_bias(L, v, Op(), false, t.c, t.pA, t.IA);
+    root_accel(t.IA, t.pA, qt, g, t.ap, w);
+  });
+  o.integ_free = count([&] {
+    V3<Op> p{};
+    integrate_root(p, qt, v, w, Op());
+  });
+  o.integ_adj_rev = 3;  // qd_tot = qd_bar + dt q_bar; qdd_bar = dt qd_tot
+  o.bwd_rev = count([&] {
+    (void)r3_link(L, t, b, v, Op());
+    (void)r2_link(L, t, b, false, M, v, M2, w);
+    (void)r1_link(L, t, b, v, w, Op());
+  });
+  o.bwd_rev_push = count([&] {
+                     (void)xformT(t.E, L.rT, v);                  // a_bar to the parent
+                     (void)r2_link(L, t, b, true, M, v, M2, w);  // parent share of pass 2
+                   }) -
+                   count([&] { (void)r2_link(L, t, b, false, M, v, M2, w); });
+  o.child_bwd = 12;  // a_bar (6) and v_bar (6) of each child added to its parent
+  o.bwd_free = count([&] {
+    V3<Op> pb{};
+    Q4<Op> qb{};
+    V6<Op> vb{};
+    (void)integrate_root_adj(qt, v, w, Op(), pb, qb, vb);
+    r3_root(M, v, qt, g, v, w, qb, M2, w);
+    (void)r1_root(L, v, w, w);
+  });
+  return o;
+}
+
+}  // namespace
+
+extern "C" int sim_flops(sim_t h, int kind, double* flops) {
+  if (!h || !flops) return fail(SIM_ERR_INVALID_ARG, "sim_flops: null argument");
+  if (kind < 0 || kind > 2) return fail(SIM_ERR_INVALID_ARG, "sim_flops: kind must be 0, 1 or 2");
+  const LinkOps o = link_ops();
+  double fd = 0, fwd = 0, bwd = 0;
+  for (int i = 0; i < h->n_links; ++i) {
+    if (h->jtype[i] == SIM_JOINT_FREE) {
+      fd += (double)o.fd_free;
+      fwd += (double)(o.fd_free + o.integ_free);
+      bwd += (double)o.bwd_free;
+    } else {
+      const bool push = h->parent[i] >= 0;
+      const double f = (double)(o.fd_rev + (push ? o.fd_rev_push : 0));
+      fd += f;
+      fwd += f + (double)o.integ_rev;
+      bwd += (double)(o.integ_adj_rev + o.bwd_rev + (push ? o.bwd_rev_push : 0));
+    }
+    fd += (double)(o.child_fwd * h->nchild[i]);
+    fwd += (double)(o.child_fwd * h->nchild[i]);
+    bwd += (double)(o.child_bwd * h->nchild[i]);
+  }
+  // the backward step recomputes one forward dynamics evaluation
+  bwd += fd;
+  *flops = (kind == 0) ? fd : (kind == 1) ? fwd : bwd;
+  return SIM_OK;
+}

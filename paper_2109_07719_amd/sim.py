@@ -1,0 +1,192 @@
+"""Python front end of the C ABI: a batch handle and a differentiable rollout.
+
+PyTorch supplies device memory and the stream; all arithmetic of the
+forward rollout, the adjoint pass and single forward-dynamics evaluations
+runs in the HIP kernels behind ``include/abadj.h``.
+
+  sim = Sim(systems, gravity, dtype=torch.float32)
+  qT, qdT = rollout(sim, q0, qd0, tau, dt, K=1)          # differentiable
+  qdd = sim.aba(q, qd, tau)                              # forward dynamics
+
+Method: ABA forward dynamics (Sec. 3), semi-implicit Euler, adjoint method
+through time (Sec. 3, Eq. adj_back; Sec. 4.1, Eq. adj_r) with the initial
+state of each step checkpointed and the step recomputed in the backward pass
+(Sec. 4.2, Eq. intermediate), checkpoint interval K (App. B).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Sim:
+    """A batch of articulated systems packed for the GPU.
+
+    systems: sequence of objects with numpy attributes parent, jtype, E_T
+    (n,3,3), r_T (n,3), axis (n,3), mass (n,), com (n,3), Ic (n,6); links in
+    topological order.  The handle's dtype (float32 or float64) is the
+    arithmetic type of every kernel.
+    """
+
+    def __init__(self, systems, gravity=(0.0, -9.81, 0.0), dtype=torch.float32,
+                 device="cuda"):
+        L = N.lib()
+        self.dtype = dtype
+        self.device = torch.device(device)
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be torch.float32 or torch.float64")
+        cat = lambda name, shape: np.ascontiguousarray(
+            np.concatenate([np.asarray(getattr(s, name), dtype=np.float64).reshape(-1, *shape)
+                            for s in systems]).reshape(-1))
+        self._parent = np.ascontiguousarray(np.concatenate(
+            [np.asarray(s.parent, dtype=np.int32) for s in systems]))
+        self._jtype = np.ascontiguousarray(np.concatenate(
+            [np.asarray(s.jtype, dtype=np.int32) for s in systems]))
+        sizes = [len(s.parent) for s in systems]
+        self._off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32))
+        self._E_T = cat("E_T", (9,))
+        self._r_T = cat("r_T", (3,))
+        self._axis = cat("axis", (3,))
+        self._mass = cat("mass", ())
+        self._com = cat("com", (3,))
+        self._Ic = cat("Ic", (6,))
+        self._g = np.ascontiguousarray(np.asarray(gravity, dtype=np.float64).reshape(3))
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        topo = N.SimTopology(len(systems), p(self._off), p(self._parent), p(self._jtype))
+        prm = N.SimParams(p(self._E_T), p(self._r_T), p(self._axis), p(self._mass), p(self._com),
+                          p(self._Ic), p(self._g))
+        h = ctypes.c_void_p()
+        N.check(L.sim_create(ctypes.byref(topo), ctypes.byref(prm),
+                             N.SIM_F64 if dtype == torch.float64 else N.SIM_F32, ctypes.byref(h)))
+        self._h = h
+        info = N.SimInfo()
+        N.check(L.sim_get_info(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in N.SimInfo._fields_}
+        self.nq, self.nv, self.nu = info.nq, info.nv, info.nu
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            N.lib().sim_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------------ checks
+    def _t(self, x, n, name, allow_none=False):
+        if x is None:
+            if allow_none:
+                return None
+            raise ValueError(f"{name} is required")
+        if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if x.dtype != self.dtype:
+            raise TypeError(f"{name} must have dtype {self.dtype}")
+        if not x.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if x.numel() != n:
+            raise ValueError(f"{name} has {x.numel()} elements, expected {n}")
+        return x
+
+    def workspace_bytes(self, T: int, K: int = 1) -> int:
+        b = ctypes.c_size_t()
+        N.check(N.lib().sim_workspace_bytes(self._h, int(T), int(K), ctypes.byref(b)))
+        return int(b.value)
+
+    def new_workspace(self, T: int, K: int = 1):
+        return torch.empty(max(self.workspace_bytes(T, K), 1), dtype=torch.uint8, device=self.device)
+
+    def flops(self, kind: int) -> float:
+        f = ctypes.c_double()
+        N.check(N.lib().sim_flops(self._h, int(kind), ctypes.byref(f)))
+        return float(f.value)
+
+    # ------------------------------------------------------------------ calls
+    def aba(self, q, qd, tau, out=None):
+        """Forward dynamics qdd = FD(q, qd, tau) for every system."""
+        self._t(q, self.nq, "q"), self._t(qd, self.nv, "qd"), self._t(tau, self.nu, "tau")
+        qdd = out if out is not None else torch.empty(self.nv, dtype=self.dtype, device=q.device)
+        N.check(N.lib().sim_aba(self._h, _ptr(q), _ptr(qd), _ptr(tau), _ptr(qdd), _stream()))
+        return qdd
+
+    def forward(self, q0, qd0, tau, dt, K=1, workspace=None, traj=False, out=None):
+        """Rollout of T = tau.shape[0] steps.  workspace=None: plain forward
+        (no checkpoints).  Returns (qT, qdT, traj or None)."""
+        tau = tau.reshape(-1, self.nu) if self.nu else tau
+        T = int(tau.shape[0])
+        self._t(q0, self.nq, "q0"), self._t(qd0, self.nv, "qd0"), self._t(tau, T * self.nu, "tau")
+        dev = q0.device
+        if out is None:
+            qT = torch.empty(self.nq, dtype=self.dtype, device=dev)
+            qdT = torch.empty(self.nv, dtype=self.dtype, device=dev)
+            tr = torch.empty((T, self.nq + self.nv), dtype=self.dtype, device=dev) if traj else None
+        else:
+            qT, qdT, tr = out
+        wsb = workspace.numel() if workspace is not None else 0
+        N.check(N.lib().sim_forward(self._h, _ptr(q0), _ptr(qd0), _ptr(tau), float(dt), T, int(K),
+                                    _ptr(qT), _ptr(qdT), _ptr(tr), _ptr(workspace), wsb, _stream()))
+        return qT, qdT, tr
+
+    def backward(self, tau, dt, K, workspace, gqT, gqdT, gtraj=None, out=None):
+        """Adjoint pass after forward() on the same workspace.  Returns
+        (gq0, gqd0, gtau)."""
+        tau = tau.reshape(-1, self.nu) if self.nu else tau
+        T = int(tau.shape[0])
+        self._t(gqT, self.nq, "gqT"), self._t(gqdT, self.nv, "gqdT")
+        self._t(gtraj, T * (self.nq + self.nv), "gtraj", allow_none=True)
+        dev = gqT.device
+        if out is None:
+            gq0 = torch.empty(self.nq, dtype=self.dtype, device=dev)
+            gqd0 = torch.empty(self.nv, dtype=self.dtype, device=dev)
+            gtau = torch.empty((T, self.nu), dtype=self.dtype, device=dev)
+        else:
+            gq0, gqd0, gtau = out
+        N.check(N.lib().sim_backward(self._h, _ptr(tau), float(dt), T, int(K), _ptr(gqT), _ptr(gqdT),
+                                     _ptr(gtraj), _ptr(gq0), _ptr(gqd0), _ptr(gtau), _ptr(workspace),
+                                     workspace.numel(), _stream()))
+        return gq0, gqd0, gtau
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, sim, q0, qd0, tau, dt, K, want_traj):
+        q0, qd0, tau = q0.contiguous(), qd0.contiguous(), tau.contiguous()
+        T = int(tau.shape[0])
+        ws = sim.new_workspace(T, K)
+        qT, qdT, tr = sim.forward(q0, qd0, tau, dt, K=K, workspace=ws, traj=want_traj)
+        ctx.sim, ctx.dt, ctx.K, ctx.want_traj = sim, dt, K, want_traj
+        ctx.save_for_backward(tau, ws)
+        if want_traj:
+            return qT, qdT, tr
+        return qT, qdT
+
+    @staticmethod
+    def backward(ctx, *grads):
+        tau, ws = ctx.saved_tensors
+        sim = ctx.sim
+        gqT, gqdT = grads[0], grads[1]
+        gtraj = grads[2] if ctx.want_traj else None
+        z = lambda n: torch.zeros(n, dtype=sim.dtype, device=tau.device)
+        gqT = z(sim.nq) if gqT is None else gqT.contiguous()
+        gqdT = z(sim.nv) if gqdT is None else gqdT.contiguous()
+        if gtraj is not None:
+            gtraj = gtraj.contiguous()
+        gq0, gqd0, gtau = sim.backward(tau, ctx.dt, ctx.K, ws, gqT, gqdT, gtraj)
+        return None, gq0, gqd0, gtau.reshape(tau.shape), None, None, None
+
+
+def rollout(sim: Sim, q0, qd0, tau, dt: float, K: int = 1, traj: bool = False):
+    """Differentiable T-step rollout (T = tau.shape[0]); gradients flow to
+    q0, qd0 and tau through the adjoint kernel.  Returns (qT, qdT) or
+    (qT, qdT, traj)."""
+    return _Rollout.apply(sim, q0, qd0, tau, float(dt), int(K), bool(traj))

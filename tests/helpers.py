@@ -1,0 +1,136 @@
+"""Shared test helpers: per-system errors, batched oracle calls, host
+emulation bindings, GPU tensor helpers."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# Tolerances (per system, norm-wise: ||x - ref|| / max(||ref||, floor)).
+TOL_QDD_F32 = 1e-5      # forward dynamics per step, FP32
+TOL_STATE_F32 = 1e-3    # state after 1000 steps, FP32
+TOL_GRAD_F32 = 1e-3     # gradients, FP32
+FLOOR_F32 = 1e-6
+FLOOR_F64 = 1e-12
+
+
+def rel(x, ref, floor=FLOOR_F32):
+    x, ref = np.asarray(x, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), floor))
+
+
+def split(vec, off):
+    return [vec[..., off[i]:off[i + 1]] for i in range(len(off) - 1)]
+
+
+def models(batch):
+    return [O.Model(s, batch.gravity) for s in batch.systems]
+
+
+def oracle_fd(batch, q, qd, tau):
+    qo, vo, uo = batch.offsets()
+    ms = models(batch)
+    out = O.map_threads(lambda i: O.fd(ms[i], q[qo[i]:qo[i + 1]], qd[vo[i]:vo[i + 1]], tau[uo[i]:uo[i + 1]]),
+                        range(len(ms)))
+    return out
+
+
+def oracle_grads(batch, gq_fn, gtraj=None, K=1, idx=None):
+    """Per-system oracle (gq0, gqd0, gtau, qT, qdT); gq_fn(i, qT, qdT) gives
+    the seeds (gqT, gqdT) of system i."""
+    qo, vo, uo = batch.offsets()
+    ms = models(batch)
+    idx = range(len(ms)) if idx is None else idx
+
+    def one(i):
+        q0, qd0 = batch.q0[qo[i]:qo[i + 1]], batch.qd0[vo[i]:vo[i + 1]]
+        tau = np.asarray(batch.tau[:, uo[i]:uo[i + 1]], dtype=np.float64)
+        qT, qdT = O.rollout(ms[i], q0, qd0, tau, batch.dt)
+        gqT, gqdT = gq_fn(i, qT, qdT)
+        gt = None
+        if gtraj is not None:
+            gt = gtraj[i]
+        return O.rollout_grad(ms[i], q0, qd0, tau, batch.dt, gqT, gqdT, gt, K=K)
+
+    return O.map_threads(one, list(idx))
+
+
+# ---------------------------------------------------------------- host emulation
+_emu = None
+
+
+def emu():
+    global _emu
+    if _emu is None:
+        path = os.path.join(HERE, "hostemu", "libhostemu.so")
+        if not os.path.exists(path):
+            import subprocess
+            subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wno-unknown-pragmas",
+                                   "-o", path, os.path.join(HERE, "hostemu", "hostemu.cpp")])
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        L.emu_fd_d.argtypes = [ctypes.c_int] + [P] * 8
+        L.emu_fd_f.argtypes = [ctypes.c_int] + [P] * 8
+        for n in ("emu_rollout_grad_d", "emu_rollout_grad_f"):
+            getattr(L, n).argtypes = [ctypes.c_int] + [P] * 7 + [ctypes.c_double, ctypes.c_int] + [P] * 7
+        _emu = L
+    return _emu
+
+
+def link_constants(s):
+    """The 25 per-link constants in the kernels' order: E_T, r_T, axis, m,
+    m*c, inertia about the link origin (xx yy zz xy xz yz)."""
+    n = s.n
+    cf = np.zeros((n, 25))
+    cf[:, 0:9] = np.asarray(s.E_T).reshape(n, 9)
+    cf[:, 9:12] = s.r_T
+    cf[:, 12:15] = s.axis
+    m = np.asarray(s.mass, dtype=np.float64)
+    c = np.asarray(s.com, dtype=np.float64)
+    I = np.asarray(s.Ic, dtype=np.float64)
+    cf[:, 15] = m
+    cf[:, 16:19] = m[:, None] * c
+    cf[:, 19] = I[:, 0] + m * (c[:, 1] ** 2 + c[:, 2] ** 2)
+    cf[:, 20] = I[:, 1] + m * (c[:, 0] ** 2 + c[:, 2] ** 2)
+    cf[:, 21] = I[:, 2] + m * (c[:, 0] ** 2 + c[:, 1] ** 2)
+    cf[:, 22] = I[:, 3] - m * c[:, 0] * c[:, 1]
+    cf[:, 23] = I[:, 4] - m * c[:, 0] * c[:, 2]
+    cf[:, 24] = I[:, 5] - m * c[:, 1] * c[:, 2]
+    return np.ascontiguousarray(cf)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def emu_fd(s, q, qd, tau, gravity=(0.0, -9.81, 0.0), f32=False):
+    dt = np.float32 if f32 else np.float64
+    par = np.ascontiguousarray(s.parent, np.int32)
+    jt = np.ascontiguousarray(s.jtype, np.int32)
+    cf, g = link_constants(s), np.ascontiguousarray(gravity, np.float64)
+    q, qd, tau = (np.ascontiguousarray(x, dt) for x in (q, qd, tau))
+    out = np.zeros(s.nv, dt)
+    (emu().emu_fd_f if f32 else emu().emu_fd_d)(s.n, _p(par), _p(jt), _p(cf), _p(g), _p(q), _p(qd), _p(tau),
+                                                _p(out))
+    return out
+
+
+def emu_rollout_grad(s, q0, qd0, tau, dt_, gqT, gqdT, gravity=(0.0, -9.81, 0.0), f32=False):
+    dt = np.float32 if f32 else np.float64
+    par = np.ascontiguousarray(s.parent, np.int32)
+    jt = np.ascontiguousarray(s.jtype, np.int32)
+    cf, g = link_constants(s), np.ascontiguousarray(gravity, np.float64)
+    T = int(np.asarray(tau).shape[0])
+    q0, qd0, tau, gqT, gqdT = (np.ascontiguousarray(x, dt) for x in (q0, qd0, tau, gqT, gqdT))
+    gq0, gqd0 = np.zeros(s.nq, dt), np.zeros(s.nv, dt)
+    gtau = np.zeros((T, s.nu), dt)
+    qT, qdT = np.zeros(s.nq, dt), np.zeros(s.nv, dt)
+    (emu().emu_rollout_grad_f if f32 else emu().emu_rollout_grad_d)(
+        s.n, _p(par), _p(jt), _p(cf), _p(g), _p(q0), _p(qd0), _p(tau), float(dt_), T, _p(gqT), _p(gqdT),
+        _p(gq0), _p(gqd0), _p(gtau), _p(qT), _p(qdT))
+    return gq0, gqd0, gtau, qT, qdT

@@ -1,0 +1,154 @@
+"""CPU-only checks of the C ABI library, the host logic and the GPU path's
+per-link arithmetic (through the test-only host emulation)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from helpers import emu_fd, emu_rollout_grad, rel
+from paper_2109_07719_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+# ---------------------------------------------------------------- C ABI library
+
+def _declared_symbols():
+    with open(os.path.join(ROOT, "include", "abadj.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^(?:int|void|const char \*)\s*\*?\s*(sim_\w+)\s*\(", text, re.M)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    from paper_2109_07719_amd import _native
+    L = _native.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 9
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(_native.EXPORTED)
+
+
+def _create(parent, jtype, n_sys_offsets, axis=None, mass=None, dtype=0):
+    from paper_2109_07719_amd import _native as N
+    nl = len(parent)
+    arr = lambda a, t: np.ascontiguousarray(np.asarray(a, dtype=t))
+    off = arr(n_sys_offsets, np.int32)
+    par = arr(parent, np.int32)
+    jt = arr(jtype, np.int32)
+    E = arr(np.tile(np.eye(3).reshape(-1), nl), np.float64)
+    r = arr(np.zeros(3 * nl), np.float64)
+    ax = arr(np.tile([0, 0, 1.0], nl) if axis is None else axis, np.float64)
+    m = arr(np.ones(nl) if mass is None else mass, np.float64)
+    com = arr(np.zeros(3 * nl), np.float64)
+    Ic = arr(np.tile([0.1, 0.1, 0.1, 0, 0, 0], nl), np.float64)
+    g = arr([0, -9.81, 0], np.float64)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    topo = N.SimTopology(len(off) - 1, p(off), p(par), p(jt))
+    prm = N.SimParams(p(E), p(r), p(ax), p(m), p(com), p(Ic), p(g))
+    h = ctypes.c_void_p()
+    rc = N.lib().sim_create(ctypes.byref(topo), ctypes.byref(prm), dtype, ctypes.byref(h))
+    return rc, N.lib().sim_last_error().decode()
+
+
+@pytest.mark.parametrize("parent,jtype,offsets,kw,code", [
+    ([0, 0], [0, 0], [0, 2], {}, -2),                       # parent not < index
+    ([-1, 1], [0, 0], [0, 2], {}, -2),                      # parent == index
+    ([-1, -2], [0, 0], [0, 2], {}, -2),                     # parent < -1
+    ([-1, 0], [0, 1], [0, 2], {}, -2),                      # free joint not at the root
+    ([-1, -1], [1, 0], [0, 2], {}, -2),                     # free root plus a second base link
+    ([-1, 0], [0, 7], [0, 2], {}, -2),                      # unknown joint type
+    ([-1] * 65, [0] * 65, [0, 65], {}, -2),                  # more than 64 links
+    ([-1, 0], [0, 0], [0, 2], {"axis": [0, 0, 2.0, 0, 0, 1.0]}, -2),  # non-unit axis
+    ([-1, 0], [0, 0], [0, 2], {"mass": [1.0, 0.0]}, -2),    # non-positive mass
+    ([-1, 0], [0, 0], [0, 2], {"mass": [1.0, np.nan]}, -2),  # non-finite parameter
+    ([-1, 0], [0, 0], [1, 2], {}, -2),                      # link_offset[0] != 0
+    ([-1, 0], [0, 0], [0, 2], {"dtype": 5}, -4),            # unsupported dtype
+])
+def test_create_rejects_invalid_input_before_touching_the_gpu(parent, jtype, offsets, kw, code):
+    rc, msg = _create(parent, jtype, offsets, **kw)
+    assert rc == code, msg
+    assert msg
+
+
+def test_null_arguments_are_rejected():
+    from paper_2109_07719_amd import _native as N
+    L = N.lib()
+    h = ctypes.c_void_p()
+    assert L.sim_create(None, None, 0, ctypes.byref(h)) == N.SIM_ERR_INVALID_ARG
+    b = ctypes.c_size_t()
+    assert L.sim_workspace_bytes(None, 10, 1, ctypes.byref(b)) == N.SIM_ERR_INVALID_ARG
+    assert L.sim_forward(None, None, None, None, 1e-3, 1, 1, None, None, None, None, 0, None) == \
+        N.SIM_ERR_INVALID_ARG
+    assert L.sim_backward(None, None, 1e-3, 1, 1, None, None, None, None, None, None, None, 0, None) == \
+        N.SIM_ERR_INVALID_ARG
+    assert L.sim_aba(None, None, None, None, None, None) == N.SIM_ERR_INVALID_ARG
+    f = ctypes.c_double()
+    assert L.sim_flops(None, 0, ctypes.byref(f)) == N.SIM_ERR_INVALID_ARG
+    L.sim_destroy(None)
+
+
+# ---------------------------------------------------------------- generators
+
+def test_generators_are_deterministic_and_shaped():
+    a = synth.workload("chain7_4096", n_systems=3, T=20)
+    b = synth.workload("chain7_4096", n_systems=3, T=20)
+    assert np.array_equal(a.tau, b.tau) and np.array_equal(a.q0, b.q0)
+    assert a.tau.shape == (20, 21) and a.total_dof == 21
+    s = a.systems[0]
+    assert list(s.parent) == [-1, 0, 1, 2, 3, 4, 5]
+    assert np.allclose(s.r_T[1:], [0.5, 0, 0]) and np.allclose(s.com, [0.25, 0, 0])
+    q = synth.workload("quad_1024", n_systems=2, T=3)
+    assert (q.systems[0].nq, q.systems[0].nv, q.systems[0].nu) == (19, 18, 12)
+    assert q.tau.shape == (3, 24)
+
+
+def test_tree_generator_respects_size_and_depth():
+    sizes, depths = [], []
+    for i in range(200):
+        s, _, _, _ = synth.tree_system(2000 + i, 1)
+        sizes.append(s.n)
+        depths.append(int(s.depth().max()))
+        assert all(s.parent[k] < k for k in range(s.n))
+        assert np.allclose(np.linalg.norm(s.axis, axis=1), 1)
+    assert min(sizes) >= 6 and max(sizes) <= 40 and max(depths) <= 5
+    assert 18 < np.mean(sizes) < 28
+
+
+# ---------------------------------------------------------------- host emulation
+
+@pytest.mark.parametrize("which", ["chain", "tree", "quad"])
+def test_lane_arithmetic_matches_oracle_fp64(which):
+    """The per-link functions the kernels call, driven link by link on the
+    host in FP64, reproduce the oracle's accelerations and rollout gradients
+    to round-off (independent dense 6x6 arithmetic on the oracle side)."""
+    if which == "chain":
+        s, q0, qd0, tau = synth.chain_system(7, 1000, 120)
+    elif which == "tree":
+        s, q0, qd0, tau = synth.tree_system(2002, 120, random_frames=True)
+    else:
+        s, q0, qd0, tau = synth.quadruped_system(3003, 120)
+    m = O.Model(s)
+    assert rel(emu_fd(s, q0, qd0, tau[0]), O.fd(m, q0, qd0, tau[0]), 1e-12) < 1e-13
+    rng = np.random.default_rng(1)
+    gqT, gqdT = rng.normal(size=s.nq), rng.normal(size=s.nv)
+    a = emu_rollout_grad(s, q0, qd0, tau, 1e-3, gqT, gqdT)
+    b = O.rollout_grad(m, q0, qd0, tau, 1e-3, gqT, gqdT)
+    for x, y in zip(a, b):
+        assert rel(x, y, 1e-12) < 1e-11
+
+
+def test_lane_arithmetic_fp32_forward_dynamics_error():
+    """The same per-link arithmetic in FP32 stays within the 1e-5 per-step
+    bar on the chain workload (the GPU's arithmetic type)."""
+    b = synth.round_to_f32(synth.workload("chain7_4096", n_systems=32, T=1))
+    qo, vo, uo = b.offsets()
+    errs = []
+    for i, s in enumerate(b.systems):
+        q, qd, tau = b.q0[qo[i]:qo[i + 1]], b.qd0[vo[i]:vo[i + 1]], b.tau[0, uo[i]:uo[i + 1]]
+        ref = O.fd(O.Model(s), q, qd, tau)
+        errs.append(rel(emu_fd(s, q, qd, tau, f32=True), ref))
+    assert max(errs) < 1e-5, max(errs)
