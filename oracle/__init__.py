@@ -57,6 +57,8 @@ def lib():
         L.orc_rollout_grad.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int,
                                        ctypes.c_int, P, P, P, P, P, P, P, P]
         L.orc_rollout_grad.restype = ctypes.c_int
+        L.orc_adjoint_along.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P, P]
+        L.orc_adjoint_along.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -186,6 +188,23 @@ def rollout_grad(m: Model, q0, qd0, tau, dt, gqT, gqdT, gtraj=None, K: int = 1):
     if rc != 0:
         raise RuntimeError("oracle rollout_grad failed")
     return gq0, gqd0, gtau, qT, qdT
+
+
+def adjoint_along(m: Model, states, tau, dt, gqT, gqdT, gtraj=None):
+    """Reverse sweep along a given trajectory: states [T, nq+nv] holds the
+    initial state of every step (x^0 .. x^{T-1}).  Returns gq0, gqd0, gtau."""
+    tau = _f64(tau)
+    T = int(tau.shape[0])
+    tau = np.ascontiguousarray(tau.reshape(T, m.nu))
+    st = np.ascontiguousarray(_f64(states).reshape(T, m.nq + m.nv))
+    gqT, gqdT = _f64(gqT, m.nq), _f64(gqdT, m.nv)
+    gtr = None if gtraj is None else np.ascontiguousarray(_f64(gtraj).reshape(T, m.nq + m.nv))
+    gq0, gqd0, gtau = np.zeros(m.nq), np.zeros(m.nv), np.zeros((T, m.nu))
+    rc = lib().orc_adjoint_along(m.ref, _p(st), _p(tau), float(dt), T, _p(gqT), _p(gqdT),
+                                 _p(gtr) if gtr is not None else None, _p(gq0), _p(gqd0), _p(gtau))
+    if rc != 0:
+        raise RuntimeError("oracle adjoint_along failed")
+    return gq0, gqd0, gtau
 
 
 def map_threads(fn, items, threads: int | None = None):

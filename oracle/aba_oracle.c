@@ -507,3 +507,35 @@ int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
   free(tape); free(work); free(ck); free(scratch); free(states); free(tapes);
   return rc;
 }
+
+int orc_adjoint_along(const orc_model *m, const double *states, const double *tau,
+                      double dt, int T, const double *gqT, const double *gqdT,
+                      const double *gtraj, double *gq0, double *gqd0, double *gtau) {
+  if (T < 0) return -1;
+  const int n = m->n, nq = orc_nq(m), nv = orc_nv(m), nu = orc_nu(m);
+  const int nx = nq + nv;
+  tape_t *tape = (tape_t *)malloc(sizeof(tape_t) * (size_t)n);
+  double *work = (double *)malloc(sizeof(double) * (size_t)(2 * nx + 2 * nv));
+  if (!tape || !work) { free(tape); free(work); return -1; }
+  double *xb = work, *xb1 = xb + nx, *qdd = xb1 + nx, *qddbar = qdd + nv;
+  memcpy(xb, gqT, sizeof(double) * nq);
+  memcpy(xb + nq, gqdT, sizeof(double) * nv);
+  if (gtraj && T > 0)
+    for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(T - 1) * nx + k];
+  int rc = 0;
+  /* the given states play the role of per-step checkpoints (Sec. 4.2) */
+  for (int t = T - 1; t >= 0 && rc == 0; --t) {
+    const double *xt = states + (size_t)t * nx;
+    aba_tape_r(m, xt, xt + nq, tau + (size_t)t * nu, tape, qdd);
+    rc = step_vjp(m, xt, xt + nq, qdd, tape, dt, xb, xb + nq, xb1, xb1 + nq,
+                  gtau + (size_t)t * nu, qddbar);
+    memcpy(xb, xb1, sizeof(double) * nx);
+    if (gtraj && t >= 1)
+      for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(t - 1) * nx + k];
+  }
+  memcpy(gq0, xb, sizeof(double) * nq);
+  memcpy(gqd0, xb + nq, sizeof(double) * nv);
+  free(tape);
+  free(work);
+  return rc;
+}

@@ -101,6 +101,13 @@ int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
                      const double *gtraj, double *gq0, double *gqd0,
                      double *gtau, double *qT, double *qdT);
 
+/* The reverse sweep alone, along a given trajectory: states is [T][nq + nv]
+ * with row t = x^t (the initial state of step t), used as the per-step
+ * checkpoints; seeds and outputs as orc_rollout_grad. */
+int orc_adjoint_along(const orc_model *m, const double *states, const double *tau,
+                      double dt, int T, const double *gqT, const double *gqdT,
+                      const double *gtraj, double *gq0, double *gqd0, double *gtau);
+
 #ifdef __cplusplus
 }
 #endif

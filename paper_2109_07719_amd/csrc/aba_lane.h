@@ -48,15 +48,17 @@ ABA_HD SySp<S> inertia_sysp(const LinkC<S>& L) {
   return I;
 }
 
-// E = E_J(q) E_T with E_J = c I + (1 - c) a a^T - s [a]x
+// E = E_J(q) E_T with E_J = I - s [a]x + (1 - c) [a]x^2, where
+// [a]x^2 = a a^T - (a.a) I (no unit-length assumption on the stored axis)
 template <typename S>
 ABA_HD M3<S> joint_E(const LinkC<S>& L, S s, S c) {
   const V3<S>& a = L.ax;
   const S k = S(1) - c;
+  const S d = S(1) - k * dot(a, a);
   M3<S> J;
-  J.m[0] = c + k * a.x * a.x;   J.m[1] = k * a.x * a.y + s * a.z; J.m[2] = k * a.x * a.z - s * a.y;
-  J.m[3] = k * a.y * a.x - s * a.z; J.m[4] = c + k * a.y * a.y;   J.m[5] = k * a.y * a.z + s * a.x;
-  J.m[6] = k * a.z * a.x + s * a.y; J.m[7] = k * a.z * a.y - s * a.x; J.m[8] = c + k * a.z * a.z;
+  J.m[0] = d + k * a.x * a.x;   J.m[1] = k * a.x * a.y + s * a.z; J.m[2] = k * a.x * a.z - s * a.y;
+  J.m[3] = k * a.y * a.x - s * a.z; J.m[4] = d + k * a.y * a.y;   J.m[5] = k * a.y * a.z + s * a.x;
+  J.m[6] = k * a.z * a.x + s * a.y; J.m[7] = k * a.z * a.y - s * a.x; J.m[8] = d + k * a.z * a.z;
   return mul(J, L.ET);
 }
 

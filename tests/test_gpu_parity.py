@@ -298,9 +298,15 @@ def test_invalid_calls_raise():
 # ------------------------------------------------------------- full size
 
 def test_full_size_chain7_4096_sampled():
-    """4096 chains x 5000 steps, the benchmark's launch configuration;
-    forward + adjoint on the GPU, sampled systems checked against the
-    oracle one by one."""
+    """4096 chains x 5000 steps in the benchmark's launch configuration.
+    Over 5 s of random torques some chains are chaotic (a 1e-7 change of q0
+    moves q_T by tens of percent even in FP64), so the end-to-end FP32-vs-
+    FP64 difference is reported, not asserted.  What holds at any horizon is
+    checked on sampled systems: (1) the GPU's step map from its own states
+    equals the oracle's step; (2) the GPU gradient equals the oracle's
+    adjoint sweep along the GPU trajectory (its states used as the per-step
+    checkpoints)."""
+    import oracle as O
     b = synth.workload("chain7_4096", T=5000, tau_dtype=np.float32)
     r = synth.round_to_f32(synth.Batch(systems=b.systems, q0=b.q0, qd0=b.qd0, tau=b.tau[:1], dt=b.dt))
     b = synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=b.dt, name=b.name)
@@ -308,24 +314,36 @@ def test_full_size_chain7_4096_sampled():
     q0, qd0 = _t(b.q0), _t(b.qd0)
     tau = torch.from_numpy(b.tau).to(DEV)
     ws = sim.new_workspace(b.T, 1)
-    qT, qdT, _ = sim.forward(q0, qd0, tau, b.dt, K=1, workspace=ws)
+    qT, qdT, tr = sim.forward(q0, qd0, tau, b.dt, K=1, workspace=ws, traj=True)
     gq0, gqd0, gtau = sim.backward(tau, b.dt, 1, ws, 2 * qT, torch.zeros_like(qdT))
     torch.cuda.synchronize()
     qo, vo, uo = b.offsets()
+    nq = qo[-1]
     sample = [0, 1, 1234, 2047, 3000, 4095]
-    sub = synth.Batch(systems=[b.systems[i] for i in sample],
-                      q0=np.concatenate([b.q0[qo[i]:qo[i + 1]] for i in sample]),
-                      qd0=np.concatenate([b.qd0[vo[i]:vo[i + 1]] for i in sample]),
-                      tau=np.concatenate([b.tau[:, uo[i]:uo[i + 1]] for i in sample], axis=1).astype(np.float64),
-                      dt=b.dt)
-    ref = oracle_grads(sub, lambda i, q, v: (2 * q, np.zeros_like(v)))
-    gq0, gqd0, gtau, qT = gq0.cpu().numpy(), gqd0.cpu().numpy(), gtau.cpu().numpy(), qT.cpu().numpy()
-    worst = 0.0
-    for k, i in enumerate(sample):
-        r = ref[k]
-        e = [rel(qT[qo[i]:qo[i + 1]], r[3]), rel(gq0[qo[i]:qo[i + 1]], r[0]),
-             rel(gqd0[vo[i]:vo[i + 1]], r[1]), rel(gtau[:, uo[i]:uo[i + 1]], r[2])]
-        print("system", i, ["%.2e" % x for x in e])
-        worst = max(worst, *e)
+    gq0, gqd0, gtau, qTn = gq0.cpu().numpy(), gqd0.cpu().numpy(), gtau.cpu().numpy(), qT.cpu().numpy()
+    rng = np.random.default_rng(0)
+    worst_step, worst_grad = 0.0, 0.0
+    for i in sample:
+        m = O.Model(b.systems[i], b.gravity)
+        cols = np.r_[qo[i]:qo[i + 1], nq + vo[i]:nq + vo[i + 1]]
+        traj_i = tr[:, torch.from_numpy(cols).to(DEV)].double().cpu().numpy()
+        x0 = np.r_[b.q0[qo[i]:qo[i + 1]], b.qd0[vo[i]:vo[i + 1]]]
+        states = np.concatenate([x0[None], traj_i[:-1]])
+        tau_i = b.tau[:, uo[i]:uo[i + 1]].astype(np.float64)
+        for t in rng.choice(b.T, size=25, replace=False):
+            q1, qd1 = O.step(m, states[t, :7], states[t, 7:], tau_i[t], b.dt)
+            worst_step = max(worst_step, rel(traj_i[t], np.r_[q1, qd1]))
+        ga = O.adjoint_along(m, states, tau_i, b.dt, 2 * traj_i[-1, :7], np.zeros(7))
+        e_along = [rel(gq0[qo[i]:qo[i + 1]], ga[0]), rel(gqd0[vo[i]:vo[i + 1]], ga[1]),
+                   rel(gtau[:, uo[i]:uo[i + 1]], ga[2])]
+        worst_grad = max(worst_grad, *e_along)
+        ref = O.rollout_grad(m, x0[:7], x0[7:], tau_i, b.dt,
+                             2 * O.rollout(m, x0[:7], x0[7:], tau_i, b.dt)[0], np.zeros(7))
+        e2e = [rel(qTn[qo[i]:qo[i + 1]], ref[3]), rel(gq0[qo[i]:qo[i + 1]], ref[0]),
+               rel(gtau[:, uo[i]:uo[i + 1]], ref[2])]
+        print("system", i, "grad along GPU trajectory", ["%.1e" % x for x in e_along],
+              "| end-to-end vs FP64 (qT, gq0, gtau)", ["%.1e" % x for x in e2e])
+    print(f"worst step-map error {worst_step:.2e}, worst gradient error along trajectory {worst_grad:.2e}")
     assert np.all(np.isfinite(gtau))
-    assert worst < TOL_GRAD_F32
+    assert worst_step < 1e-6
+    assert worst_grad < TOL_GRAD_F32

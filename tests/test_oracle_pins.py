@@ -401,3 +401,17 @@ def test_rollout_final_state_matches_stepwise():
     qT, qdT = O.rollout(m, q0, qd0, tau, 1e-3)
     assert np.array_equal(q, qT) and np.array_equal(qd, qdT)
     assert abs(np.linalg.norm(qT[3:7]) - 1) < 1e-14
+
+
+def test_adjoint_along_own_trajectory_equals_checkpointed_adjoint():
+    """Feeding the oracle's own per-step states to the reverse sweep as
+    checkpoints reproduces its checkpointed adjoint bitwise."""
+    s, q0, qd0, tau = synth.quadruped_system(3004, 150)
+    m = O.Model(s)
+    qT, qdT, tr = O.rollout(m, q0, qd0, tau, 1e-3, traj=True)
+    states = np.concatenate([np.r_[q0, qd0][None], tr[:-1]])
+    rng = np.random.default_rng(0)
+    gqT, gqdT, gtr = rng.normal(size=19), rng.normal(size=18), rng.normal(size=tr.shape)
+    a = O.adjoint_along(m, states, tau, 1e-3, gqT, gqdT, gtr)
+    b = O.rollout_grad(m, q0, qd0, tau, 1e-3, gqT, gqdT, gtr)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b[:3]))
