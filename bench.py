@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
+    "chains_2048": "2048 fixed-base revolute chains of 5-50 links, dt=1e-3, T=1000, trajectory optimisation "
+                   "of tau by Adam on ||end-effector - target||^2 + 1e-4 ||tau||^2",
     "chain7_4096": "4096 fixed-base 7-DOF revolute chains (z axes, links 0.5 m), dt=1e-3, T=5000, "
                    "checkpoint every step, forward+adjoint",
     "trees_8192": "8192 fixed-base uneven revolute trees (6-40 links, depth<=6), dt=5e-4, T=2000, "
@@ -137,6 +139,127 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
     return base, err
 
 
+def memory_sweep(args, torch, dev, sim, b):
+    """Forward+adjoint time and peak device memory for checkpoint intervals
+    K = 1, 10, 100 and store-all (App. B ablation; Sec. 6 memory tables)."""
+    T, dt = b.T, b.dt
+    f32 = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
+    q0, qd0 = f32(b.q0), f32(b.qd0)
+    tau = torch.from_numpy(b.tau).to(dev)
+    rows = []
+    for K in (1, 10, 100, 0):
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        need = sim.workspace_bytes(T, K)
+        row = {"K": K if K else "store-all", "workspace_bytes": need}
+        try:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        except RuntimeError as e:
+            row["result"] = f"does not fit on the device ({need / 2**30:.1f} GiB workspace): {str(e)[:80]}"
+            rows.append(row)
+            continue
+        times = []
+        for rep in range(1 + args.steps):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            qT, qdT, _ = sim.forward(q0, qd0, tau, dt, K=K, workspace=ws)
+            e1.record()
+            g = sim.backward(tau, dt, K, ws, 2 * qT, torch.zeros_like(qdT))
+            e2.record()
+            torch.cuda.synchronize()
+            if rep:
+                times.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
+            del g
+        fwd_ms = float(np.mean([t[0] for t in times]))
+        bwd_ms = float(np.mean([t[1] for t in times]))
+        row.update({"fwd_ms": fwd_ms, "bwd_ms": bwd_ms, "bwd_ms_per_step": bwd_ms / T,
+                    "dof_steps_per_s": b.total_dof * T / ((fwd_ms + bwd_ms) * 1e-3),
+                    "peak_bytes_over_inputs": int(torch.cuda.max_memory_allocated() - base),
+                    "inputs_bytes": int(base)})
+        rows.append(row)
+        del ws
+    print(json.dumps({"metric": "fwd+adjoint DOF-steps/sec and peak memory vs checkpoint interval",
+                      "config": {"workload": WORKLOADS.get(b.name, b.name), "T": T, "dt": dt,
+                                 "systems": len(b.systems), "dof": b.total_dof},
+                      "dtype": "f32", "data": "synthetic", "sweep": rows}))
+
+
+def trajopt_bench(args, torch, dev):
+    """Trajectory optimisation: 2048 chains of 5-50 links, T=1000, Adam on
+    tau; reports DOF-steps/s per iteration (forward+adjoint of every chain),
+    the loss curve and FP64 oracle gradient spot-checks."""
+    from paper_2109_07719_amd.trajopt import TrajOpt, chains_problem
+
+    T = args.T or 1000
+    b, targets = chains_problem(n_systems=2048, T=T)
+    opt = TrajOpt(b, targets, [s.n - 1 for s in b.systems], np.tile([0.5, 0, 0], (2048, 1)), K=args.K)
+    checks = {0, args.trajopt // 2, args.trajopt - 1}
+    losses, it_ms, spot = [], [], []
+    for it in range(args.trajopt):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        opt.opt.zero_grad()
+        L, _ = opt.loss()
+        L.backward()
+        e1.record()
+        torch.cuda.synchronize()
+        it_ms.append(e0.elapsed_time(e1))
+        losses.append(float(L.detach()))
+        if it in checks and not args.no_cpu_baseline:
+            spot.append({"iteration": it, **_trajopt_spot_check(opt, b, targets, torch)})
+        opt.opt.step()
+    torch.cuda.synchronize()
+    ms = float(np.mean(it_ms[1:] if len(it_ms) > 1 else it_ms))
+    print(json.dumps({"metric": "fwd+adjoint DOF-steps/sec (FP32, 1 GPU) in trajectory optimisation",
+                      "value": b.total_dof * T / (ms * 1e-3), "unit": "DOF-steps/s", "ms_per_iteration": ms,
+                      "iterations": args.trajopt, "loss_first": losses[0], "loss_last": losses[-1],
+                      "loss_every_10": losses[::10], "fp64_spot_checks": spot, "dtype": "f32",
+                      "config": {"workload": WORKLOADS["chains_2048"], "systems": 2048, "dof": b.total_dof,
+                                 "T": T, "K": args.K}}))
+
+
+def _trajopt_spot_check(opt, b, targets, torch):
+    """dL/dtau of 16 random chains against the FP64 oracle: (a) along the
+    GPU's own trajectory (its states as per-step checkpoints, seed from torch
+    FP64 forward kinematics at the GPU's q^T), (b) end to end (the oracle's
+    own FP64 rollout; long chains falling under gravity are chaotic, so (b)
+    includes trajectory divergence)."""
+    import oracle as O
+    from paper_2109_07719_amd.fk import LinkPoints
+    qo, vo, uo = b.offsets()
+    tau_dev = opt.tau.detach()
+    tau = tau_dev.double().cpu().numpy()
+    g = opt.tau.grad.detach().cpu().numpy()
+    _, _, tr = opt.sim.forward(opt.q0, opt.qd0, tau_dev, b.dt, K=1, workspace=None, traj=True)
+    nq = opt.sim.nq
+    rng = np.random.default_rng(1)
+    along, e2e = 0.0, 0.0
+    rel = lambda a, r: float(np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-6))
+    for i in rng.choice(len(b.systems), size=16, replace=False):
+        s = b.systems[i]
+        m = O.Model(s, b.gravity)
+        ti = tau[:, uo[i]:uo[i + 1]]
+        fk = LinkPoints([s], [s.n - 1], [[0.5, 0, 0]], dtype=torch.float64, device="cpu")
+        cols = torch.from_numpy(np.r_[qo[i]:qo[i + 1], nq + vo[i]:nq + vo[i + 1]]).to(tr.device)
+        traj_i = tr[:, cols].double().cpu().numpy()
+        x0 = np.r_[b.q0[qo[i]:qo[i + 1]], b.qd0[vo[i]:vo[i + 1]]]
+        states = np.concatenate([x0[None], traj_i[:-1]])
+
+        def seed(qT):
+            qt = torch.tensor(qT, requires_grad=True)
+            ((fk(qt) - torch.tensor(targets[i:i + 1])) ** 2).sum().backward()
+            return qt.grad.numpy()
+
+        ga = O.adjoint_along(m, states, ti, b.dt, seed(traj_i[-1, :s.nq]), np.zeros(s.nv))
+        along = max(along, rel(g[:, uo[i]:uo[i + 1]], ga[2] + 2 * opt.w * ti))
+        qT, _ = O.rollout(m, x0[:s.nq], x0[s.nq:], ti, b.dt)
+        ref = O.rollout_grad(m, x0[:s.nq], x0[s.nq:], ti, b.dt, seed(qT), np.zeros(s.nv))
+        e2e = max(e2e, rel(g[:, uo[i]:uo[i + 1]], ref[2] + 2 * opt.w * ti))
+    return {"along_gpu_trajectory_max": along, "end_to_end_vs_fp64_max": e2e}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +269,11 @@ def main():
     ap.add_argument("--K", type=int, default=1, help="checkpoint interval")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
+    ap.add_argument("--memory-sweep", action="store_true",
+                    help="time forward+adjoint and record peak memory for K in 1,10,100 and store-all")
+    ap.add_argument("--trajopt", type=int, default=0,
+                    help="run this many Adam iterations of trajectory optimisation (chains_2048 workload)")
+    ap.add_argument("--T", type=int, default=None, help="override the horizon (reduced runs only)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -173,14 +301,19 @@ def main():
     from paper_2109_07719_amd import synth
     from paper_2109_07719_amd.sim import Sim
 
+    if args.trajopt:
+        return trajopt_bench(args, torch, dev)
+
     t_gen = time.perf_counter()
-    b = synth.workload(args.workload, tau_dtype=np.float32)
+    b = synth.workload(args.workload, T=args.T, tau_dtype=np.float32)
     # the oracle and the GPU see the same float32-rounded inputs
     r = synth.round_to_f32(synth.Batch(systems=b.systems, q0=b.q0, qd0=b.qd0, tau=b.tau[:1], dt=b.dt))
     b = synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=b.dt, name=b.name)
     t_gen = time.perf_counter() - t_gen
 
     sim = Sim(b.systems, b.gravity, dtype=torch.float32)
+    if args.memory_sweep:
+        return memory_sweep(args, torch, dev, sim, b)
     T, K, dt = b.T, args.K, b.dt
     f32 = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
     q0, qd0 = f32(b.q0), f32(b.qd0)

@@ -127,16 +127,20 @@ void sim_destroy(sim_t h);
 int sim_get_info(sim_t h, sim_info_t *out);
 
 /* Bytes of workspace needed by sim_forward/sim_backward for T steps with a
- * checkpoint every K >= 1 steps (K > 1 adds a K-state replay buffer).
- * Pure function of (h, T, K). */
+ * checkpoint every K >= 1 steps (K > 1 adds a K-state replay buffer), or,
+ * for K == 0 (store-all), every step's initial state and all per-link
+ * intermediates the reverse passes read (75 numbers per link and step), so
+ * the backward pass recomputes nothing.  Pure function of (h, T, K). */
 int sim_workspace_bytes(sim_t h, int T, int K, size_t *bytes);
 
 /* Forward rollout of T steps of size dt (Sec. 3; Sec. 4.1 time
  * integration).  q0 [nq], qd0 [nv], tau [T][nu] -> qT [nq], qdT [nv];
  * traj (nullable) [T][nq + nv].  With a workspace, the initial state of
- * every K-th step is stored there for sim_backward (Sec. 4.2; App. B);
- * workspace == NULL runs the plain forward pass (no checkpoints).
- * Errors: SIM_ERR_INVALID_ARG (T < 0, K < 1, dt not finite or <= 0, null
+ * every K-th step (K >= 1) is stored there for sim_backward (Sec. 4.2;
+ * App. B), or with K == 0 every step's state and intermediates (store-all,
+ * the memory-hungry alternative the checkpointing replaces);
+ * workspace == NULL runs the plain forward pass (nothing stored).
+ * Errors: SIM_ERR_INVALID_ARG (T < 0, K < 0, dt not finite or <= 0, null
  * required pointer), SIM_ERR_WORKSPACE_TOO_SMALL, SIM_ERR_HIP (launch). */
 int sim_forward(sim_t h, const void *q0, const void *qd0, const void *tau, double dt, int T, int K,
                 void *qT, void *qdT, void *traj, void *workspace, size_t workspace_bytes,

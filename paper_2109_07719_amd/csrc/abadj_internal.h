@@ -9,7 +9,8 @@ namespace aba {
 constexpr int kWave = 64;
 
 // integer per-lane fields, stored [field][slot]
-enum CiField { CI_PARENT = 0, CI_DEPTH, CI_CFIRST, CI_CCOUNT, CI_JTYPE, CI_QIDX, CI_VIDX, CI_UIDX, CI_COUNT };
+// CI_FIDX: index of a free root among the batch's free roots (-1 otherwise)
+enum CiField { CI_PARENT = 0, CI_DEPTH, CI_CFIRST, CI_CCOUNT, CI_JTYPE, CI_QIDX, CI_VIDX, CI_UIDX, CI_FIDX, CI_COUNT };
 // floating per-lane fields, stored [field][slot]
 enum CfField {
   CF_ET = 0,          // 9
@@ -28,6 +29,7 @@ struct Packed {
   const int32_t* wmaxd;  // [nwaves] deepest level present in each wave
   int nslots;
   int nwaves;
+  int nfree;             // number of free-floating roots in the batch
   S g[3];                // gravity
   int nq, nv, nu;        // totals over the batch
 };
@@ -43,7 +45,9 @@ struct FwdArgs {
   S* qT;
   S* qdT;
   S* traj;       // nullable [T][nq + nv]
-  S* ck;         // nullable: checkpoints [ceil(T/K)][state width][nslots]
+  S* ck;         // nullable: K >= 1 checkpoints [ceil(T/K)][state width][nslots];
+                 // K == 0 every step's state and intermediates
+                 // [T][state width + kTapeFields][nslots]
 };
 
 template <typename S>
@@ -71,8 +75,12 @@ struct AbaArgs {
   S* qdd;
 };
 
-// state width per lane slot in checkpoint / scratch arrays
-constexpr int state_width(bool has_free) { return has_free ? 13 : 2; }
+// A stored state record: two numbers per lane slot ([2][nslots]: q, qd of a
+// revolute link; p.x, p.y of a free root) followed by the remaining eleven
+// numbers of every free root ([11][nfree]).
+__host__ __device__ inline size_t state_record(int nslots, int nfree) { return 2 * (size_t)nslots + 11 * (size_t)nfree; }
+// per-lane intermediates stored per step in store-all mode (K == 0)
+constexpr int tape_width() { return 75; }
 
 template <typename S>
 hipError_t launch_forward(const FwdArgs<S>& a, bool has_free, hipStream_t st);

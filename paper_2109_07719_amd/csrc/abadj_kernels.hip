@@ -33,7 +33,7 @@ __device__ __forceinline__ void sincos_(double x, double* s, double* c) { sincos
 template <typename S>
 struct Lane {
   int lane, slot;
-  int par, depth, cfirst, ccount, jtype, qidx, vidx, uidx;
+  int par, depth, cfirst, ccount, jtype, qidx, vidx, uidx, fidx;
   __device__ bool active() const { return jtype >= 0; }
   __device__ bool revolute() const { return jtype == 0; }
 };
@@ -53,6 +53,7 @@ __device__ __forceinline__ Lane<S> load_lane(const Packed<S>& P) {
   l.qidx = ci[CI_QIDX * ns + l.slot];
   l.vidx = ci[CI_VIDX * ns + l.slot];
   l.uidx = ci[CI_UIDX * ns + l.slot];
+  l.fidx = ci[CI_FIDX * ns + l.slot];
   return l;
 }
 
@@ -163,20 +164,42 @@ __device__ __forceinline__ void store_state(const State<S, FREE>& s, const Lane<
     }
   }
 }
-// lane-slot arrays [field][nslots]
+// stored state records (see state_record): [2][nslots] then [11][nfree]
 template <typename S, bool FREE>
-__device__ __forceinline__ void put_slot(const State<S, FREE>& s, S* base, int nslots, int slot) {
+__device__ __forceinline__ void put_slot(const State<S, FREE>& s, S* base, int nslots, int nfree, int slot,
+                                         int fidx) {
+  if constexpr (FREE) {
+    if (fidx >= 0) {
+      base[slot] = s.q[0];
+      base[nslots + slot] = s.q[1];
+      S* ex = base + 2 * (size_t)nslots;
 #pragma unroll
-  for (int k = 0; k < (FREE ? 7 : 1); ++k) base[k * nslots + slot] = s.q[k];
+      for (int k = 0; k < 5; ++k) ex[(size_t)k * nfree + fidx] = s.q[2 + k];
 #pragma unroll
-  for (int k = 0; k < (FREE ? 6 : 1); ++k) base[((FREE ? 7 : 1) + k) * nslots + slot] = s.qd[k];
+      for (int k = 0; k < 6; ++k) ex[(size_t)(5 + k) * nfree + fidx] = s.qd[k];
+      return;
+    }
+  }
+  base[slot] = s.q[0];
+  base[nslots + slot] = s.qd[0];
 }
 template <typename S, bool FREE>
-__device__ __forceinline__ void get_slot(State<S, FREE>& s, const S* base, int nslots, int slot) {
+__device__ __forceinline__ void get_slot(State<S, FREE>& s, const S* base, int nslots, int nfree, int slot,
+                                         int fidx) {
+  if constexpr (FREE) {
+    if (fidx >= 0) {
+      s.q[0] = base[slot];
+      s.q[1] = base[nslots + slot];
+      const S* ex = base + 2 * (size_t)nslots;
 #pragma unroll
-  for (int k = 0; k < (FREE ? 7 : 1); ++k) s.q[k] = base[k * nslots + slot];
+      for (int k = 0; k < 5; ++k) s.q[2 + k] = ex[(size_t)k * nfree + fidx];
 #pragma unroll
-  for (int k = 0; k < (FREE ? 6 : 1); ++k) s.qd[k] = base[((FREE ? 7 : 1) + k) * nslots + slot];
+      for (int k = 0; k < 6; ++k) s.qd[k] = ex[(size_t)(5 + k) * nfree + fidx];
+      return;
+    }
+  }
+  s.q[0] = base[slot];
+  s.qd[0] = base[nslots + slot];
 }
 
 // Everything one ABA evaluation leaves in a lane.
@@ -185,6 +208,41 @@ struct Step {
   Tape<S> t;
   V6<S> abase;  // free root: true body-frame acceleration
 };
+
+// Store-all mode: every intermediate of a step that the reverse passes read,
+// per lane slot, [field][nslots].
+constexpr int kTapeFields = tape_width();
+
+template <typename S>
+__device__ __forceinline__ void put_tape(const Step<S>& o, S* base, int ns, int slot) {
+  const Tape<S>& t = o.t;
+  int f = 0;
+  auto w = [&](S x) { base[(size_t)(f++) * ns + slot] = x; };
+#pragma unroll
+  for (int k = 0; k < 9; ++k) w(t.E.m[k]);
+  auto w6 = [&](const V6<S>& v) { w(v.a.x); w(v.a.y); w(v.a.z); w(v.l.x); w(v.l.y); w(v.l.z); };
+  w6(t.v); w6(t.c);
+  w(t.IA.A.xx); w(t.IA.A.yy); w(t.IA.A.zz); w(t.IA.A.xy); w(t.IA.A.xz); w(t.IA.A.yz);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) w(t.IA.B.m[k]);
+  w(t.IA.C.xx); w(t.IA.C.yy); w(t.IA.C.zz); w(t.IA.C.xy); w(t.IA.C.xz); w(t.IA.C.yz);
+  w6(t.pA); w6(t.U); w(t.Dinv); w(t.u); w6(t.pa); w6(t.ap); w(t.qdd); w6(o.abase);
+}
+template <typename S>
+__device__ __forceinline__ void get_tape(Step<S>& o, const S* base, int ns, int slot) {
+  Tape<S>& t = o.t;
+  int f = 0;
+  auto r = [&]() { return base[(size_t)(f++) * ns + slot]; };
+#pragma unroll
+  for (int k = 0; k < 9; ++k) t.E.m[k] = r();
+  auto r6 = [&](V6<S>& v) { v.a.x = r(); v.a.y = r(); v.a.z = r(); v.l.x = r(); v.l.y = r(); v.l.z = r(); };
+  r6(t.v); r6(t.c);
+  t.IA.A.xx = r(); t.IA.A.yy = r(); t.IA.A.zz = r(); t.IA.A.xy = r(); t.IA.A.xz = r(); t.IA.A.yz = r();
+#pragma unroll
+  for (int k = 0; k < 9; ++k) t.IA.B.m[k] = r();
+  t.IA.C.xx = r(); t.IA.C.yy = r(); t.IA.C.zz = r(); t.IA.C.xy = r(); t.IA.C.xz = r(); t.IA.C.yz = r();
+  r6(t.pA); r6(t.U); t.Dinv = r(); t.u = r(); r6(t.pa); r6(t.ap); t.qdd = r(); r6(o.abase);
+}
 
 // One ABA evaluation for the whole wave (all three passes).
 template <typename S, bool FREE>
@@ -296,9 +354,10 @@ __global__ __launch_bounds__(64) void k_aba(AbaArgs<S> A) {
   }
 }
 
-// Forward rollout.  CK: store the initial state of every K-th step.
-// TRAJ: also write x^{t+1} for every step.
-template <typename S, bool FREE, bool CK, bool TRAJ>
+// Forward rollout.  MODE 0: plain; 1: store the initial state of every
+// K-th step; 2: store every step's initial state and intermediates
+// (store-all).  TRAJ: also write x^{t+1} for every step.
+template <typename S, bool FREE, int MODE, bool TRAJ>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
   __shared__ S xb[XB * kWave];
   const Lane<S> l = load_lane(A.P);
@@ -313,15 +372,23 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
   }
   const bool has_tau = l.revolute();
   S tau_next = (has_tau && A.T > 0) ? A.tau[l.uidx] : S(0);
-  constexpr int W = state_width(FREE);
+  const size_t RW = state_record(ns, A.P.nfree);
+  const int nf = A.P.nfree;
   for (int t = 0; t < A.T; ++t) {
-    if constexpr (CK) {
-      if (l.active() && (t % A.K) == 0) put_slot(st, A.ck + (size_t)(t / A.K) * W * ns, ns, l.slot);
+    if constexpr (MODE == 1) {
+      if (l.active() && (t % A.K) == 0) put_slot(st, A.ck + (size_t)(t / A.K) * RW, ns, nf, l.slot, l.fidx);
     }
     const S tau = tau_next;
     if (has_tau && t + 1 < A.T) tau_next = A.tau[(size_t)(t + 1) * nu + l.uidx];
     Step<S> o;
     aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+    if constexpr (MODE == 2) {
+      if (l.active()) {
+        S* row = A.ck + (size_t)t * (RW + (size_t)kTapeFields * ns);
+        put_slot(st, row, ns, nf, l.slot, l.fidx);
+        put_tape(o, row + RW, ns, l.slot);
+      }
+    }
     if (l.active()) integrate_lane(st, l, o, A.dt);
     if constexpr (TRAJ) {
       if (l.active()) {
@@ -338,13 +405,12 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
 // and pass 1.  xb1 holds the adjoint of x^{t+1} on entry and that of x^t on
 // exit; tau_bar^t is written to gtau.
 template <typename S, bool FREE>
-__device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
-                                         S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1) {
+__device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
+                                            S* xb, const State<S, FREE>& st, const Step<S>& o, int t,
+                                            State<S, FREE>& xb1) {
   const bool act = l.active();
   const bool rev = l.revolute();
   const V3<S> g = v3<S>(A.P.g[0], A.P.g[1], A.P.g[2]);
-  Step<S> o;
-  aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
   const Tape<S>& tp = o.t;
 
   // adjoint of the integrator
@@ -437,6 +503,14 @@ __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, 
   }
 }
 
+template <typename S, bool FREE>
+__device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
+                                         S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1) {
+  Step<S> o;
+  aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+  bwd_reverse<S, FREE>(A, l, L, maxd, xb, st, o, t, xb1);
+}
+
 // Backward (adjoint) rollout, reverse time.  K == 1 reloads every step's
 // checkpoint; K > 1 replays each K-step segment from its checkpoint into
 // the scratch buffer first.  The next state and control are fetched one
@@ -450,7 +524,8 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
   const int nu = A.P.nu;
   const bool act = l.active();
   const bool rev = l.revolute();
-  constexpr int W = state_width(FREE);
+  const size_t RW = state_record(ns, A.P.nfree);
+  const int nf = A.P.nfree;
   LinkC<S> L = {};
   State<S, FREE> xb1 = {};
   if (act) {
@@ -466,18 +541,30 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
       for (int k = 0; k < (FREE ? 6 : 1); ++k) xb1.qd[k] += gt.qd[k];
     }
   }
-  if (A.K == 1) {
+  if (A.K == 0) {
+    // store-all: read every step's intermediates instead of recomputing
+    for (int t = A.T - 1; t >= 0; --t) {
+      State<S, FREE> st = {};
+      Step<S> o;
+      if (act) {
+        const S* row = A.ck + (size_t)t * (RW + (size_t)kTapeFields * ns);
+        get_slot(st, row, ns, nf, l.slot, l.fidx);
+        get_tape(o, row + RW, ns, l.slot);
+      }
+      bwd_reverse<S, FREE>(A, l, L, maxd, xb, st, o, t, xb1);
+    }
+  } else if (A.K == 1) {
     State<S, FREE> nxt = {};
     S tau_nxt = S(0);
     if (A.T > 0) {
-      if (act) get_slot(nxt, A.ck + (size_t)(A.T - 1) * W * ns, ns, l.slot);
+      if (act) get_slot(nxt, A.ck + (size_t)(A.T - 1) * RW, ns, nf, l.slot, l.fidx);
       if (rev) tau_nxt = A.tau[(size_t)(A.T - 1) * nu + l.uidx];
     }
     for (int t = A.T - 1; t >= 0; --t) {
       const State<S, FREE> st = nxt;
       const S tau = tau_nxt;
       if (t > 0) {
-        if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * W * ns, ns, l.slot);
+        if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
         if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
       }
       bwd_step<S, FREE>(A, l, L, maxd, xb, st, tau, t, xb1);
@@ -490,8 +577,8 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
       // replay the segment from its checkpoint into the scratch buffer
       State<S, FREE> st = {};
       if (act) {
-        get_slot(st, A.ck + (size_t)s * W * ns, ns, l.slot);
-        put_slot(st, A.scratch, ns, l.slot);
+        get_slot(st, A.ck + (size_t)s * RW, ns, nf, l.slot, l.fidx);
+        put_slot(st, A.scratch, ns, nf, l.slot, l.fidx);
       }
       S tau_nxt = (rev && t1 - t0 > 1) ? A.tau[(size_t)t0 * nu + l.uidx] : S(0);
       for (int j = 1; j < t1 - t0; ++j) {
@@ -501,17 +588,17 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
         aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
         if (act) {
           integrate_lane(st, l, o, A.dt);
-          put_slot(st, A.scratch + (size_t)j * W * ns, ns, l.slot);
+          put_slot(st, A.scratch + (size_t)j * RW, ns, nf, l.slot, l.fidx);
         }
       }
       State<S, FREE> nxt = {};
-      if (act) get_slot(nxt, A.scratch + (size_t)(t1 - 1 - t0) * W * ns, ns, l.slot);
+      if (act) get_slot(nxt, A.scratch + (size_t)(t1 - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
       tau_nxt = rev ? A.tau[(size_t)(t1 - 1) * nu + l.uidx] : S(0);
       for (int t = t1 - 1; t >= t0; --t) {
         const State<S, FREE> cur = nxt;
         const S tau = tau_nxt;
         if (t > t0) {
-          if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * W * ns, ns, l.slot);
+          if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
         bwd_step<S, FREE>(A, l, L, maxd, xb, cur, tau, t, xb1);
@@ -538,19 +625,26 @@ template <typename S>
 hipError_t launch_forward(const FwdArgs<S>& a, bool has_free, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
   dim3 grid(a.P.nwaves), block(kWave);
-  const bool ck = a.ck != nullptr, tr = a.traj != nullptr;
-#define ABA_FWD(F, C, R) hipLaunchKernelGGL((k_forward<S, F, C, R>), grid, block, 0, st, a)
-  if (has_free) {
-    if (ck && tr) ABA_FWD(true, true, true);
-    else if (ck) ABA_FWD(true, true, false);
-    else if (tr) ABA_FWD(true, false, true);
-    else ABA_FWD(true, false, false);
-  } else {
-    if (ck && tr) ABA_FWD(false, true, true);
-    else if (ck) ABA_FWD(false, true, false);
-    else if (tr) ABA_FWD(false, false, true);
-    else ABA_FWD(false, false, false);
+  const int mode = (a.ck == nullptr) ? 0 : (a.K == 0) ? 2 : 1;
+  const bool tr = a.traj != nullptr;
+#define ABA_FWD(F, M, R) hipLaunchKernelGGL((k_forward<S, F, M, R>), grid, block, 0, st, a)
+#define ABA_FWD_MODES(F)           \
+  if (mode == 0) {                 \
+    if (tr) ABA_FWD(F, 0, true);   \
+    else ABA_FWD(F, 0, false);     \
+  } else if (mode == 1) {          \
+    if (tr) ABA_FWD(F, 1, true);   \
+    else ABA_FWD(F, 1, false);     \
+  } else {                         \
+    if (tr) ABA_FWD(F, 2, true);   \
+    else ABA_FWD(F, 2, false);     \
   }
+  if (has_free) {
+    ABA_FWD_MODES(true)
+  } else {
+    ABA_FWD_MODES(false)
+  }
+#undef ABA_FWD_MODES
 #undef ABA_FWD
   return hipGetLastError();
 }

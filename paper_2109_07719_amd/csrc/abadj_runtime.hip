@@ -31,7 +31,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct sim_handle {
   int dtype = SIM_F32;
   int n_sys = 0, n_links = 0, nq = 0, nv = 0, nu = 0;
-  int nwaves = 0, nslots = 0, max_depth = 0;
+  int nwaves = 0, nslots = 0, max_depth = 0, nfree = 0;
   bool has_free = false;
   double g[3] = {0, 0, 0};
   int32_t* d_ci = nullptr;
@@ -51,6 +51,7 @@ aba::Packed<S> packed(const sim_handle* h) {
   P.wmaxd = h->d_wmaxd;
   P.nslots = h->nslots;
   P.nwaves = h->nwaves;
+  P.nfree = h->nfree;
   for (int k = 0; k < 3; ++k) P.g[k] = static_cast<S>(h->g[k]);
   P.nq = h->nq;
   P.nv = h->nv;
@@ -61,13 +62,14 @@ aba::Packed<S> packed(const sim_handle* h) {
 size_t elem(const sim_handle* h) { return h->dtype == SIM_F64 ? sizeof(double) : sizeof(float); }
 
 size_t ckpt_bytes(const sim_handle* h, int T, int K) {
-  const size_t W = aba::state_width(h->has_free);
+  const size_t rec = aba::state_record(h->nslots, h->nfree);
+  if (K == 0) return align256((size_t)T * (rec + (size_t)aba::tape_width() * h->nslots) * elem(h));
   const size_t ncp = (T > 0) ? (size_t)((T + K - 1) / K) : 0;
-  return align256(ncp * W * h->nslots * elem(h));
+  return align256(ncp * rec * elem(h));
 }
 size_t scratch_bytes(const sim_handle* h, int K) {
   if (K <= 1) return 0;
-  return align256((size_t)K * aba::state_width(h->has_free) * h->nslots * elem(h));
+  return align256((size_t)K * aba::state_record(h->nslots, h->nfree) * elem(h));
 }
 
 bool finite_all(const double* p, size_t n) {
@@ -255,6 +257,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
   std::vector<double> cf((size_t)aba::CF_COUNT * NS, 0.0);
   for (int slot = 0; slot < NS; ++slot) ci[(size_t)aba::CI_JTYPE * NS + slot] = -1;
   for (int slot = 0; slot < NS; ++slot) ci[(size_t)aba::CI_PARENT * NS + slot] = -1;
+  for (int slot = 0; slot < NS; ++slot) ci[(size_t)aba::CI_FIDX * NS + slot] = -1;
   for (int s = 0; s < ns; ++s) {
     const int b = off[s], n = off[s + 1] - off[s];
     const int base_slot = sys_wave[s] * aba::kWave + sys_lane0[s];
@@ -280,6 +283,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       CI(aba::CI_QIDX) = sys_q[s] + loc_q[L];
       CI(aba::CI_VIDX) = sys_v[s] + loc_v[L];
       CI(aba::CI_UIDX) = (loc_u[L] < 0) ? -1 : sys_u[s] + loc_u[L];
+      if (topo->jtype[L] == SIM_JOINT_FREE) CI(aba::CI_FIDX) = h->nfree++;
       for (int k = 0; k < 9; ++k) CF(aba::CF_ET + k) = prm->E_T[9 * (size_t)L + k];
       for (int k = 0; k < 3; ++k) CF(aba::CF_RT + k) = prm->r_T[3 * (size_t)L + k];
       for (int k = 0; k < 3; ++k) CF(aba::CF_AX + k) = prm->axis[3 * (size_t)L + k];
@@ -344,7 +348,7 @@ int sim_get_info(sim_t h, sim_info_t* o) {
 
 int sim_workspace_bytes(sim_t h, int T, int K, size_t* bytes) {
   if (!h || !bytes) return fail(SIM_ERR_INVALID_ARG, "sim_workspace_bytes: null argument");
-  if (T < 0 || K < 1) return fail(SIM_ERR_INVALID_ARG, "sim_workspace_bytes: need T >= 0 and K >= 1");
+  if (T < 0 || K < 0) return fail(SIM_ERR_INVALID_ARG, "sim_workspace_bytes: need T >= 0 and K >= 0");
   *bytes = ckpt_bytes(h, T, K) + scratch_bytes(h, K);
   return SIM_OK;
 }
@@ -352,7 +356,7 @@ int sim_workspace_bytes(sim_t h, int T, int K, size_t* bytes) {
 static int check_run(sim_t h, double dt, int T, int K, const char* who) {
   if (!h) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": null handle");
   if (T < 0) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": T must be >= 0");
-  if (K < 1) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": K must be >= 1");
+  if (K < 0) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": K must be >= 0 (0 = store-all)");
   if (!std::isfinite(dt) || !(dt > 0)) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": dt must be finite and > 0");
   return SIM_OK;
 }
