@@ -108,6 +108,10 @@ typedef struct {
   int32_t max_depth;      /* deepest tree level (root = 0)                */
   int32_t has_free;       /* 1 if any system has a free-floating root      */
   int32_t dtype;
+  int32_t frames_identity; /* 1 if, after the library rotates every link
+                              frame so that its joint axis is z, every
+                              parent->joint rotation is the identity (the
+                              kernels then use a specialised variant)     */
 } sim_info_t;
 
 /* Build a handle: validates the topology and parameters, orders every

@@ -85,7 +85,9 @@ class Model:
         self.jtype = np.ascontiguousarray(np.asarray(system.jtype, dtype=np.int32))
         self.E_T = f(system.E_T).reshape(-1)
         self.r_T = f(system.r_T).reshape(-1)
-        self.axis = f(system.axis).reshape(-1)
+        # a joint axis is a direction: the joint rotates about a / |a|
+        ax = f(system.axis).reshape(-1, 3)
+        self.axis = np.ascontiguousarray((ax / np.linalg.norm(ax, axis=1, keepdims=True)).reshape(-1))
         self.mass = f(system.mass).reshape(-1)
         self.com = f(system.com).reshape(-1)
         self.Ic = f(system.Ic).reshape(-1)

@@ -48,7 +48,8 @@ typedef struct {
   const int *jtype;      /* ORC_REVOLUTE or ORC_FREE (link 0 only)         */
   const double *E_T;     /* 9n: fixed rotation parent->joint frame, rowmajor */
   const double *r_T;     /* 3n: joint origin in parent coordinates          */
-  const double *axis;    /* 3n: unit joint axis in the link frame           */
+  const double *axis;    /* 3n: joint axis in the link frame, unit length
+                            (the Python wrapper normalises it)             */
   const double *mass;    /* n                                               */
   const double *com;     /* 3n: centre of mass in the link frame            */
   const double *Ic;      /* 6n: inertia about the COM: xx yy zz xy xz yz    */

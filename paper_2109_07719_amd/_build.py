@@ -16,6 +16,10 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # device code only: let the compiler fold x*0, x+0, x*1 (structural
+    # zeros of canonicalised joints); no reassociation.  The host runtime
+    # keeps IEEE semantics (its input validation tests for non-finite numbers)
+    "-Xarch_device", "-fno-signed-zeros", "-Xarch_device", "-ffinite-math-only",
 ]
 
 

@@ -40,7 +40,8 @@ class SimParams(ctypes.Structure):
 
 class SimInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_sys", "n_links", "nq", "nv", "nu", "n_waves",
-                                               "n_slots", "max_depth", "has_free", "dtype")]
+                                               "n_slots", "max_depth", "has_free", "dtype",
+                                               "frames_identity")]
 
 
 class SimError(RuntimeError):

@@ -25,7 +25,7 @@ template <typename S>
 struct LinkC {
   M3<S> ET;   // fixed rotation parent -> joint frame
   V3<S> rT;   // joint origin in parent coordinates
-  V3<S> ax;   // unit joint axis (link coordinates)
+  V3<S> ax;   // joint axis (link coordinates); e_z after canonicalisation
   S m;        // mass
   V3<S> mc;   // mass * centre of mass
   Sy3<S> Ib;  // rotational inertia about the link origin: Ic - m [c]x^2
@@ -48,17 +48,15 @@ ABA_HD SySp<S> inertia_sysp(const LinkC<S>& L) {
   return I;
 }
 
-// E = E_J(q) E_T with E_J = I - s [a]x + (1 - c) [a]x^2, where
-// [a]x^2 = a a^T - (a.a) I (no unit-length assumption on the stored axis)
+// E = E_J(q) E_T for a joint about the link's z axis (the host rotates
+// every link frame so that its joint axis is e_z):
+// E_J = I - sin q [e_z]x + (1 - cos q)[e_z]x^2 = [[c, s, 0], [-s, c, 0], [0, 0, 1]].
 template <typename S>
 ABA_HD M3<S> joint_E(const LinkC<S>& L, S s, S c) {
-  const V3<S>& a = L.ax;
-  const S k = S(1) - c;
-  const S d = S(1) - k * dot(a, a);
   M3<S> J;
-  J.m[0] = d + k * a.x * a.x;   J.m[1] = k * a.x * a.y + s * a.z; J.m[2] = k * a.x * a.z - s * a.y;
-  J.m[3] = k * a.y * a.x - s * a.z; J.m[4] = d + k * a.y * a.y;   J.m[5] = k * a.y * a.z + s * a.x;
-  J.m[6] = k * a.z * a.x + s * a.y; J.m[7] = k * a.z * a.y - s * a.x; J.m[8] = d + k * a.z * a.z;
+  J.m[0] = c;     J.m[1] = s;    J.m[2] = S(0);
+  J.m[3] = -s;    J.m[4] = c;    J.m[5] = S(0);
+  J.m[6] = S(0);  J.m[7] = S(0); J.m[8] = S(1);
   return mul(J, L.ET);
 }
 
@@ -102,7 +100,7 @@ ABA_HD void p1_bias(const LinkC<S>& L, const V6<S>& v, S qd, bool revolute, V6<S
 template <typename S>
 ABA_HD void p2_local(const LinkC<S>& L, Tape<S>& t, S tau) {
   t.U = v6<S>(mul(t.IA.A, L.ax), mulT(t.IA.B, L.ax));
-  t.Dinv = S(1) / dot(L.ax, t.U.a);
+  t.Dinv = rcp(dot(L.ax, t.U.a));
   t.u = tau - dot(L.ax, t.pA.a);
 }
 // pass 2 (revolute with a parent link): Ia = IA - U U^T / D,

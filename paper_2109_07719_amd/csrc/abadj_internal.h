@@ -82,11 +82,13 @@ __host__ __device__ inline size_t state_record(int nslots, int nfree) { return 2
 // per-lane intermediates stored per step in store-all mode (K == 0)
 constexpr int tape_width() { return 75; }
 
+// has_free: the batch contains free-floating roots; eti: every revolute
+// joint frame is the identity after axis canonicalisation
 template <typename S>
-hipError_t launch_forward(const FwdArgs<S>& a, bool has_free, hipStream_t st);
+hipError_t launch_forward(const FwdArgs<S>& a, bool has_free, bool eti, hipStream_t st);
 template <typename S>
-hipError_t launch_backward(const BwdArgs<S>& a, bool has_free, hipStream_t st);
+hipError_t launch_backward(const BwdArgs<S>& a, bool has_free, bool eti, hipStream_t st);
 template <typename S>
-hipError_t launch_aba(const AbaArgs<S>& a, bool has_free, hipStream_t st);
+hipError_t launch_aba(const AbaArgs<S>& a, bool has_free, bool eti, hipStream_t st);
 
 }  // namespace aba

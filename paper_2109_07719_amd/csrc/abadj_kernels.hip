@@ -57,15 +57,25 @@ __device__ __forceinline__ Lane<S> load_lane(const Packed<S>& P) {
   return l;
 }
 
-template <typename S>
+// Per-link constants.  The host canonicalises every revolute joint axis to
+// e_z, so the axis is a compile-time constant here; with ETI (every joint
+// frame the identity after canonicalisation) so is E_T.  The build's
+// no-signed-zeros / finite-math flags let the compiler fold the resulting
+// structural zeros and ones through the generic spatial-algebra code.
+template <typename S, bool ETI>
 __device__ __forceinline__ LinkC<S> load_linkc(const Packed<S>& P, int slot) {
   const int ns = P.nslots;
   const S* cf = P.cf;
   LinkC<S> L;
+  if constexpr (ETI) {
 #pragma unroll
-  for (int k = 0; k < 9; ++k) L.ET.m[k] = cf[(CF_ET + k) * ns + slot];
+    for (int k = 0; k < 9; ++k) L.ET.m[k] = (k % 4 == 0) ? S(1) : S(0);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) L.ET.m[k] = cf[(CF_ET + k) * ns + slot];
+  }
   L.rT = v3<S>(cf[(CF_RT + 0) * ns + slot], cf[(CF_RT + 1) * ns + slot], cf[(CF_RT + 2) * ns + slot]);
-  L.ax = v3<S>(cf[(CF_AX + 0) * ns + slot], cf[(CF_AX + 1) * ns + slot], cf[(CF_AX + 2) * ns + slot]);
+  L.ax = v3<S>(S(0), S(0), S(1));
   L.m = cf[CF_M * ns + slot];
   L.mc = v3<S>(cf[(CF_MC + 0) * ns + slot], cf[(CF_MC + 1) * ns + slot], cf[(CF_MC + 2) * ns + slot]);
   L.Ib = sy3<S>(cf[(CF_IB + 0) * ns + slot], cf[(CF_IB + 1) * ns + slot], cf[(CF_IB + 2) * ns + slot],
@@ -328,16 +338,17 @@ __device__ __forceinline__ void integrate_lane(State<S, FREE>& st, const Lane<S>
 
 // ------------------------------------------------------------------ kernels
 
-template <typename S, bool FREE>
+template <typename S, bool FREE, bool ETI>
 __global__ __launch_bounds__(64) void k_aba(AbaArgs<S> A) {
   __shared__ S xb[XB * kWave];
   const Lane<S> l = load_lane(A.P);
   const int maxd = A.P.wmaxd[blockIdx.x];
-  LinkC<S> L = {};
+  // every lane slot holds valid constants, so load them unconditionally
+  // (keeps the compile-time axis and frame constants visible to folding)
+  const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
   State<S, FREE> st = {};
   S tau = S(0);
   if (l.active()) {
-    L = load_linkc(A.P, l.slot);
     load_state(st, l, A.q, A.qd);
     if (l.revolute()) tau = A.tau[l.uidx];
   }
@@ -357,19 +368,16 @@ __global__ __launch_bounds__(64) void k_aba(AbaArgs<S> A) {
 // Forward rollout.  MODE 0: plain; 1: store the initial state of every
 // K-th step; 2: store every step's initial state and intermediates
 // (store-all).  TRAJ: also write x^{t+1} for every step.
-template <typename S, bool FREE, int MODE, bool TRAJ>
+template <typename S, bool FREE, bool ETI, int MODE, bool TRAJ>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
   __shared__ S xb[XB * kWave];
   const Lane<S> l = load_lane(A.P);
   const int maxd = A.P.wmaxd[blockIdx.x];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
-  LinkC<S> L = {};
+  const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
   State<S, FREE> st = {};
-  if (l.active()) {
-    L = load_linkc(A.P, l.slot);
-    load_state(st, l, A.q0, A.qd0);
-  }
+  if (l.active()) load_state(st, l, A.q0, A.qd0);
   const bool has_tau = l.revolute();
   S tau_next = (has_tau && A.T > 0) ? A.tau[l.uidx] : S(0);
   const size_t RW = state_record(ns, A.P.nfree);
@@ -515,7 +523,7 @@ __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, 
 // checkpoint; K > 1 replays each K-step segment from its checkpoint into
 // the scratch buffer first.  The next state and control are fetched one
 // step ahead.
-template <typename S, bool FREE>
+template <typename S, bool FREE, bool ETI>
 __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
   __shared__ S xb[XB * kWave];
   const Lane<S> l = load_lane(A.P);
@@ -526,10 +534,9 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
   const bool rev = l.revolute();
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
-  LinkC<S> L = {};
+  const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
   State<S, FREE> xb1 = {};
   if (act) {
-    L = load_linkc(A.P, l.slot);
     load_state(xb1, l, A.gqT, A.gqdT);
     if (A.gtraj != nullptr && A.T > 0) {
       State<S, FREE> gt;
@@ -611,60 +618,74 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
 }  // namespace
 
 template <typename S>
-hipError_t launch_aba(const AbaArgs<S>& a, bool has_free, hipStream_t st) {
+hipError_t launch_aba(const AbaArgs<S>& a, bool has_free, bool eti, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
   dim3 grid(a.P.nwaves), block(kWave);
-  if (has_free)
-    hipLaunchKernelGGL((k_aba<S, true>), grid, block, 0, st, a);
-  else
-    hipLaunchKernelGGL((k_aba<S, false>), grid, block, 0, st, a);
+#define ABA_K(F, E) hipLaunchKernelGGL((k_aba<S, F, E>), grid, block, 0, st, a)
+  if (has_free) {
+    if (eti) ABA_K(true, true);
+    else ABA_K(true, false);
+  } else {
+    if (eti) ABA_K(false, true);
+    else ABA_K(false, false);
+  }
+#undef ABA_K
   return hipGetLastError();
 }
 
-template <typename S>
-hipError_t launch_forward(const FwdArgs<S>& a, bool has_free, hipStream_t st) {
-  if (a.P.nwaves == 0) return hipSuccess;
+template <typename S, bool F, bool E>
+void launch_forward_fe(const FwdArgs<S>& a, hipStream_t st) {
   dim3 grid(a.P.nwaves), block(kWave);
   const int mode = (a.ck == nullptr) ? 0 : (a.K == 0) ? 2 : 1;
   const bool tr = a.traj != nullptr;
-#define ABA_FWD(F, M, R) hipLaunchKernelGGL((k_forward<S, F, M, R>), grid, block, 0, st, a)
-#define ABA_FWD_MODES(F)           \
-  if (mode == 0) {                 \
-    if (tr) ABA_FWD(F, 0, true);   \
-    else ABA_FWD(F, 0, false);     \
-  } else if (mode == 1) {          \
-    if (tr) ABA_FWD(F, 1, true);   \
-    else ABA_FWD(F, 1, false);     \
-  } else {                         \
-    if (tr) ABA_FWD(F, 2, true);   \
-    else ABA_FWD(F, 2, false);     \
-  }
-  if (has_free) {
-    ABA_FWD_MODES(true)
+#define ABA_FWD(M, R) hipLaunchKernelGGL((k_forward<S, F, E, M, R>), grid, block, 0, st, a)
+  if (mode == 0) {
+    if (tr) ABA_FWD(0, true);
+    else ABA_FWD(0, false);
+  } else if (mode == 1) {
+    if (tr) ABA_FWD(1, true);
+    else ABA_FWD(1, false);
   } else {
-    ABA_FWD_MODES(false)
+    if (tr) ABA_FWD(2, true);
+    else ABA_FWD(2, false);
   }
-#undef ABA_FWD_MODES
 #undef ABA_FWD
+}
+
+template <typename S>
+hipError_t launch_forward(const FwdArgs<S>& a, bool has_free, bool eti, hipStream_t st) {
+  if (a.P.nwaves == 0) return hipSuccess;
+  if (has_free) {
+    if (eti) launch_forward_fe<S, true, true>(a, st);
+    else launch_forward_fe<S, true, false>(a, st);
+  } else {
+    if (eti) launch_forward_fe<S, false, true>(a, st);
+    else launch_forward_fe<S, false, false>(a, st);
+  }
   return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_backward(const BwdArgs<S>& a, bool has_free, hipStream_t st) {
+hipError_t launch_backward(const BwdArgs<S>& a, bool has_free, bool eti, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
   dim3 grid(a.P.nwaves), block(kWave);
-  if (has_free)
-    hipLaunchKernelGGL((k_backward<S, true>), grid, block, 0, st, a);
-  else
-    hipLaunchKernelGGL((k_backward<S, false>), grid, block, 0, st, a);
+#define ABA_BWD(F, E) hipLaunchKernelGGL((k_backward<S, F, E>), grid, block, 0, st, a)
+  if (has_free) {
+    if (eti) ABA_BWD(true, true);
+    else ABA_BWD(true, false);
+  } else {
+    if (eti) ABA_BWD(false, true);
+    else ABA_BWD(false, false);
+  }
+#undef ABA_BWD
   return hipGetLastError();
 }
 
-template hipError_t launch_aba<float>(const AbaArgs<float>&, bool, hipStream_t);
-template hipError_t launch_aba<double>(const AbaArgs<double>&, bool, hipStream_t);
-template hipError_t launch_forward<float>(const FwdArgs<float>&, bool, hipStream_t);
-template hipError_t launch_forward<double>(const FwdArgs<double>&, bool, hipStream_t);
-template hipError_t launch_backward<float>(const BwdArgs<float>&, bool, hipStream_t);
-template hipError_t launch_backward<double>(const BwdArgs<double>&, bool, hipStream_t);
+template hipError_t launch_aba<float>(const AbaArgs<float>&, bool, bool, hipStream_t);
+template hipError_t launch_aba<double>(const AbaArgs<double>&, bool, bool, hipStream_t);
+template hipError_t launch_forward<float>(const FwdArgs<float>&, bool, bool, hipStream_t);
+template hipError_t launch_forward<double>(const FwdArgs<double>&, bool, bool, hipStream_t);
+template hipError_t launch_backward<float>(const BwdArgs<float>&, bool, bool, hipStream_t);
+template hipError_t launch_backward<double>(const BwdArgs<double>&, bool, bool, hipStream_t);
 
 }  // namespace aba

@@ -33,6 +33,7 @@ struct sim_handle {
   int n_sys = 0, n_links = 0, nq = 0, nv = 0, nu = 0;
   int nwaves = 0, nslots = 0, max_depth = 0, nfree = 0;
   bool has_free = false;
+  bool eti = false;  // every revolute joint frame is the identity after canonicalisation
   double g[3] = {0, 0, 0};
   int32_t* d_ci = nullptr;
   void* d_cf = nullptr;
@@ -70,6 +71,38 @@ size_t ckpt_bytes(const sim_handle* h, int T, int K) {
 size_t scratch_bytes(const sim_handle* h, int K) {
   if (K <= 1) return 0;
   return align256((size_t)K * aba::state_record(h->nslots, h->nfree) * elem(h));
+}
+
+// Rotation R with R a = e_z for a unit axis a (Rodrigues about a x e_z).
+void axis_to_z(const double* a_in, double R[9]) {
+  const double n = std::sqrt(a_in[0] * a_in[0] + a_in[1] * a_in[1] + a_in[2] * a_in[2]);
+  const double a[3] = {a_in[0] / n, a_in[1] / n, a_in[2] / n};
+  const double c = a[2];
+  for (int k = 0; k < 9; ++k) R[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  if (c > 1.0 - 1e-15) return;
+  if (c < -1.0 + 1e-15) {  // half turn about x
+    R[4] = -1.0;
+    R[8] = -1.0;
+    return;
+  }
+  double k[3] = {a[1], -a[0], 0.0};  // a x e_z
+  const double s = std::sqrt(k[0] * k[0] + k[1] * k[1]);
+  k[0] /= s;
+  k[1] /= s;
+  const double K[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+  double K2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+  for (int e = 0; e < 9; ++e) R[e] += s * K[e] + (1.0 - c) * K2[e];
+}
+
+void mat3_mul(const double* A, const double* B, double* C) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+void mat3_mul_bt(const double* A, const double* B, double* C) {  // A B^T
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[3 * j] + A[3 * i + 1] * B[3 * j + 1] + A[3 * i + 2] * B[3 * j + 2];
 }
 
 bool finite_all(const double* p, size_t n) {
@@ -253,6 +286,15 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
   for (int d : wave_depth) h->max_depth = std::max(h->max_depth, d);
 
   const int NS = h->nslots;
+  static const double I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  std::vector<double> Rcan(9 * (size_t)nl);
+  for (int L = 0; L < nl; ++L) {
+    if (topo->jtype[L] == SIM_JOINT_REVOLUTE)
+      axis_to_z(prm->axis + 3 * (size_t)L, Rcan.data() + 9 * (size_t)L);
+    else
+      for (int k = 0; k < 9; ++k) Rcan[9 * (size_t)L + k] = I3[k];
+  }
+  bool eti = true;
   std::vector<int32_t> ci((size_t)aba::CI_COUNT * NS, 0);
   std::vector<double> cf((size_t)aba::CF_COUNT * NS, 0.0);
   for (int slot = 0; slot < NS; ++slot) ci[(size_t)aba::CI_JTYPE * NS + slot] = -1;
@@ -284,12 +326,34 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       CI(aba::CI_VIDX) = sys_v[s] + loc_v[L];
       CI(aba::CI_UIDX) = (loc_u[L] < 0) ? -1 : sys_u[s] + loc_u[L];
       if (topo->jtype[L] == SIM_JOINT_FREE) CI(aba::CI_FIDX) = h->nfree++;
-      for (int k = 0; k < 9; ++k) CF(aba::CF_ET + k) = prm->E_T[9 * (size_t)L + k];
-      for (int k = 0; k < 3; ++k) CF(aba::CF_RT + k) = prm->r_T[3 * (size_t)L + k];
-      for (int k = 0; k < 3; ++k) CF(aba::CF_AX + k) = prm->axis[3 * (size_t)L + k];
+      // joint-axis canonicalisation: rotate the link frame by Rl so that its
+      // axis becomes e_z (the parent frame was rotated by Rp):
+      //   E_T' = Rl E_T Rp^T, r_T' = Rp r_T, c' = Rl c, Ic' = Rl Ic Rl^T.
+      // Joint angles, velocities, torques and everything the caller sees are
+      // unchanged.
+      const double* Rl = Rcan.data() + 9 * (size_t)L;
+      const double* Rp = (p < 0) ? I3 : Rcan.data() + 9 * (size_t)(b + p);
+      double T1[9], ETn[9];
+      mat3_mul(Rl, prm->E_T + 9 * (size_t)L, T1);
+      mat3_mul_bt(T1, Rp, ETn);
+      for (int k = 0; k < 9; ++k) CF(aba::CF_ET + k) = ETn[k];
+      const double* rt = prm->r_T + 3 * (size_t)L;
+      for (int k = 0; k < 3; ++k) CF(aba::CF_RT + k) = Rp[3 * k] * rt[0] + Rp[3 * k + 1] * rt[1] + Rp[3 * k + 2] * rt[2];
+      CF(aba::CF_AX + 0) = 0.0;
+      CF(aba::CF_AX + 1) = 0.0;
+      CF(aba::CF_AX + 2) = 1.0;
       const double m = prm->mass[L];
-      const double* c = prm->com + 3 * (size_t)L;
-      const double* I = prm->Ic + 6 * (size_t)L;
+      const double* c0 = prm->com + 3 * (size_t)L;
+      const double c[3] = {Rl[0] * c0[0] + Rl[1] * c0[1] + Rl[2] * c0[2], Rl[3] * c0[0] + Rl[4] * c0[1] + Rl[5] * c0[2],
+                           Rl[6] * c0[0] + Rl[7] * c0[1] + Rl[8] * c0[2]};
+      const double* I0 = prm->Ic + 6 * (size_t)L;
+      const double J[9] = {I0[0], I0[3], I0[4], I0[3], I0[1], I0[5], I0[4], I0[5], I0[2]};
+      double T2[9], Jn[9];
+      mat3_mul(Rl, J, T2);
+      mat3_mul_bt(T2, Rl, Jn);
+      const double I[6] = {Jn[0], Jn[4], Jn[8], Jn[1], Jn[2], Jn[5]};
+      if (topo->jtype[L] == SIM_JOINT_REVOLUTE)
+        for (int k = 0; k < 9; ++k) eti = eti && std::fabs(ETn[k] - I3[k]) < 1e-12;
       CF(aba::CF_M) = m;
       for (int k = 0; k < 3; ++k) CF(aba::CF_MC + k) = m * c[k];
       // inertia about the link origin: Ic - m [c]x^2 = Ic + m (|c|^2 1 - c c^T)
@@ -300,6 +364,12 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       CF(aba::CF_IB + 4) = I[4] - m * c[0] * c[2];
       CF(aba::CF_IB + 5) = I[5] - m * c[1] * c[2];
     }
+  }
+  h->eti = eti;
+  if (eti) {  // make the identity exact
+    for (int slot = 0; slot < NS; ++slot)
+      if (ci[(size_t)aba::CI_JTYPE * NS + slot] == SIM_JOINT_REVOLUTE)
+        for (int k = 0; k < 9; ++k) cf[(size_t)(aba::CF_ET + k) * NS + slot] = I3[k];
   }
   // children of a link are consecutive lanes in breadth-first order
   for (int slot = 0; slot < NS; ++slot) {
@@ -342,6 +412,7 @@ int sim_get_info(sim_t h, sim_info_t* o) {
   o->n_slots = h->nslots;
   o->max_depth = h->max_depth;
   o->has_free = h->has_free ? 1 : 0;
+  o->frames_identity = h->eti ? 1 : 0;
   o->dtype = h->dtype;
   return SIM_OK;
 }
@@ -389,7 +460,7 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
     a.qdT = (double*)qdT;
     a.traj = (double*)traj;
     a.ck = (double*)workspace;
-    e = aba::launch_forward(a, h->has_free, (hipStream_t)stream);
+    e = aba::launch_forward(a, h->has_free, h->eti, (hipStream_t)stream);
   } else {
     aba::FwdArgs<float> a;
     a.P = packed<float>(h);
@@ -403,7 +474,7 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
     a.qdT = (float*)qdT;
     a.traj = (float*)traj;
     a.ck = (float*)workspace;
-    e = aba::launch_forward(a, h->has_free, (hipStream_t)stream);
+    e = aba::launch_forward(a, h->has_free, h->eti, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_forward: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
@@ -439,7 +510,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (double*)gtau;
     a.ck = (const double*)workspace;
     a.scratch = (K > 1) ? (double*)((char*)workspace + ck) : nullptr;
-    e = aba::launch_backward(a, h->has_free, (hipStream_t)stream);
+    e = aba::launch_backward(a, h->has_free, h->eti, (hipStream_t)stream);
   } else {
     aba::BwdArgs<float> a;
     a.P = packed<float>(h);
@@ -455,7 +526,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (float*)gtau;
     a.ck = (const float*)workspace;
     a.scratch = (K > 1) ? (float*)((char*)workspace + ck) : nullptr;
-    e = aba::launch_backward(a, h->has_free, (hipStream_t)stream);
+    e = aba::launch_backward(a, h->has_free, h->eti, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_backward: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
@@ -472,7 +543,7 @@ int sim_aba(sim_t h, const void* q, const void* qd, const void* tau, void* qdd, 
     a.qd = (const double*)qd;
     a.tau = (const double*)tau;
     a.qdd = (double*)qdd;
-    e = aba::launch_aba(a, h->has_free, (hipStream_t)stream);
+    e = aba::launch_aba(a, h->has_free, h->eti, (hipStream_t)stream);
   } else {
     aba::AbaArgs<float> a;
     a.P = packed<float>(h);
@@ -480,7 +551,7 @@ int sim_aba(sim_t h, const void* q, const void* qd, const void* tau, void* qdd, 
     a.qd = (const float*)qd;
     a.tau = (const float*)tau;
     a.qdd = (float*)qdd;
-    e = aba::launch_aba(a, h->has_free, (hipStream_t)stream);
+    e = aba::launch_aba(a, h->has_free, h->eti, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_aba: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
@@ -493,16 +564,49 @@ namespace {
 
 thread_local long long g_ops = 0;
 
+// Counting scalar with the constant folding the kernels' build flags allow
+// (x*0 -> 0, x+0 -> x, x*1 -> x, x-0 -> x, 0-x -> -x): operations with a
+// known zero or one operand are free, every other +, -, *, /, sqrt counts 1.
 struct Op {
+  int k = 2;  // 0: the constant 0, 1: the constant 1, 2: any other value
   Op() = default;
-  Op(double) {}
+  Op(double x) : k(x == 0.0 ? 0 : (x == 1.0 ? 1 : 2)) {}
 };
-inline Op operator+(Op, Op) { ++g_ops; return {}; }
-inline Op operator-(Op, Op) { ++g_ops; return {}; }
-inline Op operator*(Op, Op) { ++g_ops; return {}; }
-inline Op operator/(Op, Op) { ++g_ops; return {}; }
-inline Op operator-(Op) { return {}; }
-inline Op sqrt(Op) { ++g_ops; return {}; }
+inline Op var_() {
+  Op o;
+  o.k = 2;
+  return o;
+}
+inline Op operator+(Op a, Op b) {
+  if (a.k == 0) return b;
+  if (b.k == 0) return a;
+  ++g_ops;
+  return var_();
+}
+inline Op operator-(Op a, Op b) {
+  if (b.k == 0) return a;
+  if (a.k == 0) return var_();
+  ++g_ops;
+  return var_();
+}
+inline Op operator*(Op a, Op b) {
+  if (a.k == 0 || b.k == 0) return Op(0.0);
+  if (a.k == 1) return b;
+  if (b.k == 1) return a;
+  ++g_ops;
+  return var_();
+}
+inline Op operator/(Op a, Op b) {
+  if (a.k == 0) return Op(0.0);
+  if (b.k == 1) return a;
+  ++g_ops;
+  return var_();
+}
+inline Op operator-(Op a) { return a.k == 0 ? a : var_(); }
+inline Op sqrt(Op) {
+  ++g_ops;
+  return var_();
+}
 
 template <typename F>
 long long count(F&& f) {
@@ -518,10 +622,13 @@ struct LinkOps {
   long long bwd_free;
 };
 
-LinkOps link_ops() {
+LinkOps link_ops(bool eti) {
   using namespace aba;
   LinkOps o{};
   LinkC<Op> L{};
+  L.ax = v3<Op>(Op(0.0), Op(0.0), Op(1.0));  // canonicalised joint axis
+  if (eti)
+    for (int k = 0; k < 9; ++k) L.ET.m[k] = Op((k % 4 == 0) ? 1.0 : 0.0);
   Tape<Op> t{};
   V6<Op> v{}, w{};
   SySp<Op> M{}, M2{};
@@ -578,7 +685,7 @@ LinkOps link_ops() {
 extern "C" int sim_flops(sim_t h, int kind, double* flops) {
   if (!h || !flops) return fail(SIM_ERR_INVALID_ARG, "sim_flops: null argument");
   if (kind < 0 || kind > 2) return fail(SIM_ERR_INVALID_ARG, "sim_flops: kind must be 0, 1 or 2");
-  const LinkOps o = link_ops();
+  const LinkOps o = link_ops(h->eti);
   double fd = 0, fwd = 0, bwd = 0;
   for (int i = 0; i < h->n_links; ++i) {
     if (h->jtype[i] == SIM_JOINT_FREE) {

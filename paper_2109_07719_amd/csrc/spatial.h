@@ -48,6 +48,21 @@ struct SySp {  // [A B; B^T C]
   Sy3<S> C;
 };
 
+// reciprocal: one v_rcp_f32 (1 ulp) on the GPU in single precision, an exact
+// division otherwise
+ABA_HD float rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+ABA_HD double rcp(double x) { return 1.0 / x; }
+template <typename S>
+ABA_HD S rcp(S x) {
+  return S(1) / x;
+}
+
 // ---------------------------------------------------------------- 3-vectors
 template <typename S>
 ABA_HD V3<S> v3(S x, S y, S z) {

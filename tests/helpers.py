@@ -82,25 +82,50 @@ def emu():
     return _emu
 
 
+def _axis_to_z(a):
+    """Rotation R with R a = e_z (the library's joint-axis canonicalisation)."""
+    a = np.asarray(a, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    c = a[2]
+    if c > 1 - 1e-15:
+        return np.eye(3)
+    if c < -1 + 1e-15:
+        return np.diag([1.0, -1.0, -1.0])
+    k = np.array([a[1], -a[0], 0.0])
+    sn = np.linalg.norm(k)
+    k = k / sn
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + sn * K + (1 - c) * (K @ K)
+
+
 def link_constants(s):
-    """The 25 per-link constants in the kernels' order: E_T, r_T, axis, m,
-    m*c, inertia about the link origin (xx yy zz xy xz yz)."""
+    """The 25 per-link constants in the kernels' order after the library's
+    joint-axis canonicalisation (every link frame rotated so that its joint
+    axis is e_z): E_T' = Rl E_T Rp^T, r_T' = Rp r_T, axis' = e_z, m, m*c',
+    inertia about the link origin (xx yy zz xy xz yz) with c' = Rl c,
+    Ic' = Rl Ic Rl^T."""
     n = s.n
+    Rs = [np.eye(3) if s.jtype[i] == 1 else _axis_to_z(s.axis[i]) for i in range(n)]
     cf = np.zeros((n, 25))
-    cf[:, 0:9] = np.asarray(s.E_T).reshape(n, 9)
-    cf[:, 9:12] = s.r_T
-    cf[:, 12:15] = s.axis
-    m = np.asarray(s.mass, dtype=np.float64)
-    c = np.asarray(s.com, dtype=np.float64)
-    I = np.asarray(s.Ic, dtype=np.float64)
-    cf[:, 15] = m
-    cf[:, 16:19] = m[:, None] * c
-    cf[:, 19] = I[:, 0] + m * (c[:, 1] ** 2 + c[:, 2] ** 2)
-    cf[:, 20] = I[:, 1] + m * (c[:, 0] ** 2 + c[:, 2] ** 2)
-    cf[:, 21] = I[:, 2] + m * (c[:, 0] ** 2 + c[:, 1] ** 2)
-    cf[:, 22] = I[:, 3] - m * c[:, 0] * c[:, 1]
-    cf[:, 23] = I[:, 4] - m * c[:, 0] * c[:, 2]
-    cf[:, 24] = I[:, 5] - m * c[:, 1] * c[:, 2]
+    for i in range(n):
+        Rl = Rs[i]
+        Rp = np.eye(3) if s.parent[i] < 0 else Rs[s.parent[i]]
+        cf[i, 0:9] = (Rl @ np.asarray(s.E_T[i]) @ Rp.T).reshape(9)
+        cf[i, 9:12] = Rp @ np.asarray(s.r_T[i])
+        cf[i, 12:15] = [0.0, 0.0, 1.0]
+        m = float(s.mass[i])
+        c = Rl @ np.asarray(s.com[i], dtype=np.float64)
+        Ic = np.asarray(s.Ic[i], dtype=np.float64)
+        J = np.array([[Ic[0], Ic[3], Ic[4]], [Ic[3], Ic[1], Ic[5]], [Ic[4], Ic[5], Ic[2]]])
+        J = Rl @ J @ Rl.T
+        cf[i, 15] = m
+        cf[i, 16:19] = m * c
+        cf[i, 19] = J[0, 0] + m * (c[1] ** 2 + c[2] ** 2)
+        cf[i, 20] = J[1, 1] + m * (c[0] ** 2 + c[2] ** 2)
+        cf[i, 21] = J[2, 2] + m * (c[0] ** 2 + c[1] ** 2)
+        cf[i, 22] = J[0, 1] - m * c[0] * c[1]
+        cf[i, 23] = J[0, 2] - m * c[0] * c[2]
+        cf[i, 24] = J[1, 2] - m * c[1] * c[2]
     return np.ascontiguousarray(cf)
 
 
