@@ -27,6 +27,17 @@ namespace {
 
 constexpr int XB = 27;  // exchange-buffer fields per lane
 
+// Synchronisation of the lanes of one wavefront around the LDS exchange
+// buffer: the wave executes its LDS operations in order, so a compiler
+// barrier with wavefront-scope release/acquire fences suffices (the same
+// construction as HIP's __syncwarp).  Workgroup barriers stay free for the
+// producer/consumer hand-off of the pipelined adjoint.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
 
@@ -41,8 +52,8 @@ struct Lane {
 template <typename S>
 __device__ __forceinline__ Lane<S> load_lane(const Packed<S>& P) {
   Lane<S> l;
-  l.lane = threadIdx.x;
-  l.slot = blockIdx.x * kWave + threadIdx.x;
+  l.lane = threadIdx.x % kWave;
+  l.slot = blockIdx.x * kWave + l.lane;
   const int ns = P.nslots;
   const int32_t* ci = P.ci;
   l.par = ci[CI_PARENT * ns + l.slot];
@@ -278,7 +289,7 @@ __device__ __forceinline__ void aba_wave(const Packed<S>& P, const Lane<S>& l, c
       }
       put6(xb, 0, l.lane, t.v);
     }
-    __syncthreads();
+    wave_sync();
   }
   // pass 1: bias terms (parallel over links)
   if (act) p1_bias(L, t.v, st.qd[0], rev, t.c, t.pA, t.IA);
@@ -300,7 +311,7 @@ __device__ __forceinline__ void aba_wave(const Packed<S>& P, const Lane<S>& l, c
         }
       }
     }
-    __syncthreads();
+    wave_sync();
   }
   // pass 3: accelerations, root -> leaves
   const V6<S> a0 = v6<S>(zero3<S>(), v3<S>(-P.g[0], -P.g[1], -P.g[2]));
@@ -314,7 +325,7 @@ __device__ __forceinline__ void aba_wave(const Packed<S>& P, const Lane<S>& l, c
         put6(xb, 0, l.lane, t.ap);
       }
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -456,7 +467,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
         r3_root(tp.IA, tp.ap, st_quat(st), g, ab, qddb6, quatb, IAb, pAb);
       }
     }
-    __syncthreads();
+    wave_sync();
   }
   // reverse of pass 2, root -> leaves
   S taub = S(0);
@@ -471,7 +482,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
       put21(xb, 0, l.lane, IAb);
       put6(xb, 21, l.lane, pAb);
     }
-    __syncthreads();
+    wave_sync();
   }
   // reverse of pass 1, leaves -> root
   for (int d = maxd; d >= 0; --d) {
@@ -485,7 +496,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
         vb6 = vb6 + r1_root(L, tp.v, vb, pAb);
       }
     }
-    __syncthreads();
+    wave_sync();
   }
   // adjoint of the step's initial state; tau_bar
   if (rev) {
@@ -615,6 +626,89 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
   if (act) store_state(xb1, l, A.gq0, A.gqd0);
 }
 
+// Pipelined adjoint for K == 1: two wavefronts per workgroup on the same
+// systems.  Wave 0 (producer) reloads step t-1's checkpoint and recomputes
+// its ABA intermediates while wave 1 (consumer) runs the reverse passes of
+// step t; the intermediates move through a double-buffered LDS tape.  Phase
+// k: the producer recomputes step T-1-k into buffer k%2 while the consumer
+// reverses step T-k from buffer (k-1)%2; one workgroup barrier ends every
+// phase (both waves execute exactly T+1 of them).
+template <typename S, bool FREE, bool ETI>
+__global__ __launch_bounds__(128) void k_backward_pipe(BwdArgs<S> A) {
+  constexpr int TW = kTapeFields + (FREE ? 13 : 2);  // tape + state per lane
+  __shared__ S xbs[2][XB * kWave];
+  __shared__ S tbuf[2][TW * kWave];
+  const int wid = threadIdx.x / kWave;
+  const Lane<S> l = load_lane(A.P);
+  const int maxd = A.P.wmaxd[blockIdx.x];
+  const int ns = A.P.nslots;
+  const int nu = A.P.nu;
+  const bool act = l.active();
+  const bool rev = l.revolute();
+  const size_t RW = state_record(ns, A.P.nfree);
+  const int nf = A.P.nfree;
+  const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
+  S* xb = xbs[wid];
+  if (wid == 0) {
+    State<S, FREE> nxt = {};
+    S tau_nxt = S(0);
+    if (A.T > 0) {
+      if (act) get_slot(nxt, A.ck + (size_t)(A.T - 1) * RW, ns, nf, l.slot, l.fidx);
+      if (rev) tau_nxt = A.tau[(size_t)(A.T - 1) * nu + l.uidx];
+    }
+    for (int k = 0; k <= A.T; ++k) {
+      if (k < A.T) {
+        const int t = A.T - 1 - k;
+        const State<S, FREE> st = nxt;
+        const S tau = tau_nxt;
+        if (t > 0) {
+          if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
+          if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
+        }
+        Step<S> o;
+        aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+        S* tb = tbuf[k & 1];
+#pragma unroll
+        for (int j = 0; j < (FREE ? 7 : 1); ++j) tb[(size_t)j * kWave + l.lane] = st.q[j];
+#pragma unroll
+        for (int j = 0; j < (FREE ? 6 : 1); ++j) tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane] = st.qd[j];
+        put_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane);
+      }
+      __syncthreads();
+    }
+  } else {
+    State<S, FREE> xb1 = {};
+    if (act) {
+      load_state(xb1, l, A.gqT, A.gqdT);
+      if (A.gtraj != nullptr && A.T > 0) {
+        State<S, FREE> gt;
+        const S* row = A.gtraj + (size_t)(A.T - 1) * (A.P.nq + A.P.nv);
+        load_state(gt, l, row, row + A.P.nq);
+#pragma unroll
+        for (int k = 0; k < (FREE ? 7 : 1); ++k) xb1.q[k] += gt.q[k];
+#pragma unroll
+        for (int k = 0; k < (FREE ? 6 : 1); ++k) xb1.qd[k] += gt.qd[k];
+      }
+    }
+    for (int k = 0; k <= A.T; ++k) {
+      if (k >= 1) {
+        const int t = A.T - k;
+        const S* tb = tbuf[(k - 1) & 1];
+        State<S, FREE> st;
+#pragma unroll
+        for (int j = 0; j < (FREE ? 7 : 1); ++j) st.q[j] = tb[(size_t)j * kWave + l.lane];
+#pragma unroll
+        for (int j = 0; j < (FREE ? 6 : 1); ++j) st.qd[j] = tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane];
+        Step<S> o;
+        get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane);
+        bwd_reverse<S, FREE>(A, l, L, maxd, xb, st, o, t, xb1);
+      }
+      __syncthreads();
+    }
+    if (act) store_state(xb1, l, A.gq0, A.gqd0);
+  }
+}
+
 }  // namespace
 
 template <typename S>
@@ -669,7 +763,13 @@ template <typename S>
 hipError_t launch_backward(const BwdArgs<S>& a, bool has_free, bool eti, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
   dim3 grid(a.P.nwaves), block(kWave);
-#define ABA_BWD(F, E) hipLaunchKernelGGL((k_backward<S, F, E>), grid, block, 0, st, a)
+#define ABA_BWD(F, E)                                                                         \
+  do {                                                                                        \
+    if (a.K == 1)                                                                             \
+      hipLaunchKernelGGL((k_backward_pipe<S, F, E>), grid, dim3(2 * kWave), 0, st, a);       \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_backward<S, F, E>), grid, block, 0, st, a);                      \
+  } while (0)
   if (has_free) {
     if (eti) ABA_BWD(true, true);
     else ABA_BWD(true, false);
