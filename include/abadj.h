@@ -133,8 +133,9 @@ int sim_get_info(sim_t h, sim_info_t *out);
 /* Bytes of workspace needed by sim_forward/sim_backward for T steps with a
  * checkpoint every K >= 1 steps (K > 1 adds a K-state replay buffer), or,
  * for K == 0 (store-all), every step's initial state and all per-link
- * intermediates the reverse passes read (75 numbers per link and step), so
- * the backward pass recomputes nothing.  Pure function of (h, T, K). */
+ * intermediates the reverse passes read (56 numbers per link and step;
+ * three cheap by-products are rebuilt from them), so the backward pass
+ * reruns none of the ABA sweeps.  Pure function of (h, T, K). */
 int sim_workspace_bytes(sim_t h, int T, int K, size_t *bytes);
 
 /* Forward rollout of T steps of size dt (Sec. 3; Sec. 4.1 time

@@ -64,6 +64,7 @@ ABA_HD M3<S> joint_E(const LinkC<S>& L, S s, S c) {
 // Intermediates of one link kept for the reverse sweep.
 template <typename S>
 struct Tape {
+  S sq, cq;    // sin q, cos q
   M3<S> E;
   V6<S> v, c;
   SySp<S> IA;  // final articulated inertia (children included)

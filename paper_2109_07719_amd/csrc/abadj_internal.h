@@ -80,7 +80,7 @@ struct AbaArgs {
 // numbers of every free root ([11][nfree]).
 __host__ __device__ inline size_t state_record(int nslots, int nfree) { return 2 * (size_t)nslots + 11 * (size_t)nfree; }
 // per-lane intermediates stored per step in store-all mode (K == 0)
-constexpr int tape_width() { return 75; }
+constexpr int tape_width() { return 56; }
 
 // has_free: the batch contains free-floating roots; eti: every revolute
 // joint frame is the identity after axis canonicalisation

@@ -230,8 +230,12 @@ struct Step {
   V6<S> abase;  // free root: true body-frame acceleration
 };
 
-// Store-all mode: every intermediate of a step that the reverse passes read,
-// per lane slot, [field][nslots].
+// Step intermediates handed to the reverse passes (store-all records in HBM
+// and the pipelined adjoint's LDS tape), per lane slot, [field][stride]:
+// sin q, cos q, v, I^A, p^A, 1/D, u, p^a, a', qdd, base acceleration.  E
+// (from sin q, cos q), U (entries of I^A for a z-axis joint) and c (from v
+// and qd) are rebuilt by the reader in a few operations, which also keeps
+// their structural zeros visible to the compiler.
 constexpr int kTapeFields = tape_width();
 
 template <typename S>
@@ -239,30 +243,37 @@ __device__ __forceinline__ void put_tape(const Step<S>& o, S* base, int ns, int 
   const Tape<S>& t = o.t;
   int f = 0;
   auto w = [&](S x) { base[(size_t)(f++) * ns + slot] = x; };
-#pragma unroll
-  for (int k = 0; k < 9; ++k) w(t.E.m[k]);
   auto w6 = [&](const V6<S>& v) { w(v.a.x); w(v.a.y); w(v.a.z); w(v.l.x); w(v.l.y); w(v.l.z); };
-  w6(t.v); w6(t.c);
+  w(t.sq); w(t.cq);
+  w6(t.v);
   w(t.IA.A.xx); w(t.IA.A.yy); w(t.IA.A.zz); w(t.IA.A.xy); w(t.IA.A.xz); w(t.IA.A.yz);
 #pragma unroll
   for (int k = 0; k < 9; ++k) w(t.IA.B.m[k]);
   w(t.IA.C.xx); w(t.IA.C.yy); w(t.IA.C.zz); w(t.IA.C.xy); w(t.IA.C.xz); w(t.IA.C.yz);
-  w6(t.pA); w6(t.U); w(t.Dinv); w(t.u); w6(t.pa); w6(t.ap); w(t.qdd); w6(o.abase);
+  w6(t.pA); w(t.Dinv); w(t.u); w6(t.pa); w6(t.ap); w(t.qdd); w6(o.abase);
 }
 template <typename S>
-__device__ __forceinline__ void get_tape(Step<S>& o, const S* base, int ns, int slot) {
+__device__ __forceinline__ void get_tape(Step<S>& o, const S* base, int ns, int slot, const LinkC<S>& L, S qd,
+                                         bool rev) {
   Tape<S>& t = o.t;
   int f = 0;
   auto r = [&]() { return base[(size_t)(f++) * ns + slot]; };
-#pragma unroll
-  for (int k = 0; k < 9; ++k) t.E.m[k] = r();
   auto r6 = [&](V6<S>& v) { v.a.x = r(); v.a.y = r(); v.a.z = r(); v.l.x = r(); v.l.y = r(); v.l.z = r(); };
-  r6(t.v); r6(t.c);
+  t.sq = r(); t.cq = r();
+  r6(t.v);
   t.IA.A.xx = r(); t.IA.A.yy = r(); t.IA.A.zz = r(); t.IA.A.xy = r(); t.IA.A.xz = r(); t.IA.A.yz = r();
 #pragma unroll
   for (int k = 0; k < 9; ++k) t.IA.B.m[k] = r();
   t.IA.C.xx = r(); t.IA.C.yy = r(); t.IA.C.zz = r(); t.IA.C.xy = r(); t.IA.C.xz = r(); t.IA.C.yz = r();
-  r6(t.pA); r6(t.U); t.Dinv = r(); t.u = r(); r6(t.pa); r6(t.ap); t.qdd = r(); r6(o.abase);
+  r6(t.pA); t.Dinv = r(); t.u = r(); r6(t.pa); r6(t.ap); t.qdd = r(); r6(o.abase);
+  t.E = joint_E(L, t.sq, t.cq);
+  t.U = v6<S>(mul(t.IA.A, L.ax), mulT(t.IA.B, L.ax));
+  if (rev) {
+    const V3<S> sqd = qd * L.ax;
+    t.c = v6<S>(cross(t.v.a, sqd), cross(t.v.l, sqd));
+  } else {
+    t.c = zero6<S>();
+  }
 }
 
 // One ABA evaluation for the whole wave (all three passes).
@@ -274,9 +285,8 @@ __device__ __forceinline__ void aba_wave(const Packed<S>& P, const Lane<S>& l, c
   const bool rev = l.revolute();
   // pass 1: joint transforms (parallel over links)
   if (rev) {
-    S s, c;
-    sincos_(st.q[0], &s, &c);
-    t.E = joint_E(L, s, c);
+    sincos_(st.q[0], &t.sq, &t.cq);
+    t.E = joint_E(L, t.sq, t.cq);
   }
   // pass 1: velocities, root -> leaves
   for (int d = 0; d <= maxd; ++d) {
@@ -567,7 +577,7 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
       if (act) {
         const S* row = A.ck + (size_t)t * (RW + (size_t)kTapeFields * ns);
         get_slot(st, row, ns, nf, l.slot, l.fidx);
-        get_tape(o, row + RW, ns, l.slot);
+        get_tape(o, row + RW, ns, l.slot, L, st.qd[0], rev);
       }
       bwd_reverse<S, FREE>(A, l, L, maxd, xb, st, o, t, xb1);
     }
@@ -700,7 +710,7 @@ __global__ __launch_bounds__(128) void k_backward_pipe(BwdArgs<S> A) {
 #pragma unroll
         for (int j = 0; j < (FREE ? 6 : 1); ++j) st.qd[j] = tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane];
         Step<S> o;
-        get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane);
+        get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, L, st.qd[0], rev);
         bwd_reverse<S, FREE>(A, l, L, maxd, xb, st, o, t, xb1);
       }
       __syncthreads();
