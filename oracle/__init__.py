@@ -36,31 +36,54 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def _configure(L):
+    P = ctypes.c_void_p
+    for name in ("orc_nq", "orc_nv", "orc_nu"):
+        getattr(L, name).restype = ctypes.c_int
+        getattr(L, name).argtypes = [P]
+    L.orc_fd.argtypes = [P, P, P, P, P]
+    L.orc_fd_c.argtypes = [P, P, P, P, P]
+    L.orc_fd_vjp.argtypes = [P, P, P, P, P, P, P, P]
+    L.orc_step.argtypes = [P, P, P, P, ctypes.c_double, P, P]
+    L.orc_rollout.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int, P, P, P]
+    L.orc_rollout.restype = ctypes.c_int
+    L.orc_rollout_c.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int, P, P]
+    L.orc_rollout_c.restype = ctypes.c_int
+    L.orc_rollout_grad.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, P, P, P, P, P, P, P, P]
+    L.orc_rollout_grad.restype = ctypes.c_int
+    L.orc_adjoint_along.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P, P]
+    L.orc_adjoint_along.restype = ctypes.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build(force=False)
-        L = ctypes.CDLL(LIB_PATH)
-        P = ctypes.c_void_p
-        for name in ("orc_nq", "orc_nv", "orc_nu"):
-            getattr(L, name).restype = ctypes.c_int
-            getattr(L, name).argtypes = [P]
-        L.orc_fd.argtypes = [P, P, P, P, P]
-        L.orc_fd_c.argtypes = [P, P, P, P, P]
-        L.orc_fd_vjp.argtypes = [P, P, P, P, P, P, P, P]
-        L.orc_step.argtypes = [P, P, P, P, ctypes.c_double, P, P]
-        L.orc_rollout.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int, P, P, P]
-        L.orc_rollout.restype = ctypes.c_int
-        L.orc_rollout_c.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int, P, P]
-        L.orc_rollout_c.restype = ctypes.c_int
-        L.orc_rollout_grad.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int,
-                                       ctypes.c_int, P, P, P, P, P, P, P, P]
-        L.orc_rollout_grad.restype = ctypes.c_int
-        L.orc_adjoint_along.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P, P]
-        L.orc_adjoint_along.restype = ctypes.c_int
-        _lib = L
+        _lib = _configure(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+class use_library:
+    """Context manager: route every oracle call through another build of the
+    oracle (used by the mutation tests to check that the pins catch planted
+    mistakes)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = _configure(ctypes.CDLL(self.path))
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
 
 
 class _CModel(ctypes.Structure):

@@ -1,0 +1,78 @@
+"""The pins must catch plausible mistakes in the oracle (CPU only).
+
+Each case plants one mistake (a flipped sign, a dropped term, a transposed
+operand, an off-by-one index, a different integrator) in a private copy of
+the oracle's C sources, builds it, routes the oracle through that build and
+runs the pin tests; at least one pin must fail.
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+import oracle as O
+import test_oracle_pins as pins
+
+SRC = os.path.dirname(os.path.abspath(O.__file__))
+
+MUTATIONS = [
+    ("aba_fwd.inc", "- s * ax[k] + (1.0 - c) * ax2[k]", "+ s * ax[k] + (1.0 - c) * ax2[k]", "joint rotation sign"),
+    ("aba_fwd.inc", "J[3 * i + j] - m * cx2[3 * i + j]", "J[3 * i + j] + m * cx2[3 * i + j]", "inertia shift sign"),
+    ("aba_fwd.inc", "l->qdd = (l->u - Uap) / l->D;", "l->qdd = (l->u + Uap) / l->D;", "pass-3 sign"),
+    ("aba_fwd.inc", "l->pa[k] = l->pA[k] + Iac[k] + l->U[k] * l->u / l->D;",
+     "l->pa[k] = l->pA[k] + l->U[k] * l->u / l->D;", "dropped I^a c term"),
+    ("aba_fwd.inc", "FN(mat6_mul)(XT_, l->Ia, T1);\n      FN(mat6_mul)(T1, l->X, T2);",
+     "FN(mat6_mul)(l->X, l->Ia, T1);\n      FN(mat6_mul)(T1, XT_, T2);", "transposed congruence"),
+    ("aba_fwd.inc", "q1[qi[i]] = q[qi[i]] + dt * qd1[vi[i]];", "q1[qi[i]] = q[qi[i]] + dt * qd[vi[i]];",
+     "explicit instead of semi-implicit Euler"),
+    ("aba_fwd.inc", "l->abase[k + 3] = l->ap[k + 3] + Eg[k];", "l->abase[k + 3] = l->ap[k + 3] - Eg[k];",
+     "free-root gravity sign"),
+    ("aba_oracle.c", "b->U[k] -= gq * l->ap[k];", "b->U[k] += gq * l->ap[k];", "adjoint sign (U_bar)"),
+    ("aba_oracle.c", "b->D -= Upa * l->u / (l->D * l->D);", "b->D -= 0.0;", "dropped D_bar term"),
+    ("aba_oracle.c", "tvec_add(F, b->pA, b->h);", "vec_add(F, b->pA, b->h);", "transposed crf adjoint"),
+    ("aba_oracle.c", "const double tot = qd1bar[vi[i]] + dt * q1bar[qi[i]];", "const double tot = qd1bar[vi[i]];",
+     "dropped integrator coupling"),
+    ("aba_oracle.c", "E0bar[3 * r + c] += ab[3 + r] * g[c];", "E0bar[3 * c + r] += ab[3 + r] * g[c];",
+     "transposed gravity adjoint index"),
+    ("aba_oracle.c", "qtb[k] += h * (cr[k] - w1[k] * ob[3]);", "qtb[k] += h * (cr[k] + w1[k] * ob[3]);",
+     "quaternion product adjoint sign"),
+    ("aba_oracle.c", "tau + (size_t)(t0 + j - 1) * nu, tape, qdd);", "tau + (size_t)(t0 + j) * nu, tape, qdd);",
+     "off-by-one in the segment replay"),
+    ("aba_oracle.c", "outer_add(b->ap, al, b->X);", "outer_add(al, b->ap, b->X);", "transposed X_bar outer product"),
+]
+
+PINS = [
+    pins.test_aba_equals_dense_solve_every_tree_up_to_4_links,
+    pins.test_free_base_dense_solve_and_momentum_balance,
+    pins.test_single_pendulum_closed_form,
+    pins.test_semi_implicit_euler_step_and_no_secular_energy_growth,
+    pins.test_single_step_tau_bar_is_Minv_qdd_bar,
+    pins.test_single_step_state_adjoint_matches_inverse_dynamics_jacobian,
+    pins.test_free_base_single_step_adjoint_matches_inverse_dynamics_jacobian,
+    pins.test_rollout_gradient_complex_step_chain,
+    pins.test_free_base_rollout_gradient_complex_step,
+    lambda: pins.test_checkpoint_interval_changes_no_arithmetic("quad"),
+]
+
+
+@pytest.mark.parametrize("fname,old,new,what", MUTATIONS, ids=[m[3] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(tmp_path, fname, old, new, what):
+    for f in ("aba_oracle.c", "aba_fwd.inc", "oracle.h"):
+        shutil.copy(os.path.join(SRC, f), tmp_path / f)
+    path = tmp_path / fname
+    text = path.read_text()
+    assert text.count(old) == 1, f"mutation site for '{what}' not found exactly once"
+    path.write_text(text.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", str(so),
+                           str(tmp_path / "aba_oracle.c"), "-lm"])
+    caught = None
+    with O.use_library(str(so)):
+        for pin in PINS:
+            try:
+                pin()
+            except (AssertionError, RuntimeError, FloatingPointError, ValueError) as e:
+                caught = getattr(pin, "__name__", "checkpoint invariance")
+                break
+    assert caught is not None, f"no pin caught the planted mistake: {what}"

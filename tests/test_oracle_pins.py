@@ -179,6 +179,26 @@ def test_energy_drift_is_first_order_in_dt():
         assert 0.35 < b / a < 0.65, drifts
 
 
+def test_semi_implicit_euler_step_and_no_secular_energy_growth():
+    """One step is q1 = q + dt (qd + dt qdd), qd1 = qd + dt qdd (the
+    semi-implicit scheme), and, being symplectic, it keeps the energy of a
+    passive pendulum bounded over 20 s (an explicit Euler step would let it
+    grow steadily)."""
+    s = _pendulum()
+    m = O.Model(s)
+    q, qd, tau, dt = np.array([0.4]), np.array([-1.3]), np.array([0.2]), 1e-3
+    qdd = O.fd(m, q, qd, tau)
+    q1, qd1 = O.step(m, q, qd, tau, dt)
+    assert abs(qd1[0] - (qd[0] + dt * qdd[0])) < 1e-15
+    assert abs(q1[0] - (q[0] + dt * qd1[0])) < 1e-15
+    T = 20000
+    _, _, tr = O.rollout(m, [0.3], [0.0], np.zeros((T, 1)), dt, traj=True)
+    E = np.array([R.energy(s, tr[k, :1], tr[k, 1:]) for k in range(0, T, 50)])
+    dE = np.abs(E - R.energy(s, np.array([0.3]), np.array([0.0])))
+    first = dE[: len(dE) // 10].max()
+    assert dE[-len(dE) // 10:].max() < 2.0 * first
+
+
 # ---------------------------------------------------------------- adjoint
 
 def test_single_step_tau_bar_is_Minv_qdd_bar():
