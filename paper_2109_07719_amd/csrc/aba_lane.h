@@ -247,47 +247,52 @@ ABA_HD S qpair(const V3<S>& ax, const V6<S>& x, const V6<S>& y) {
   return dot(ax, cross(x.a, y.a) + cross(x.l, y.l));
 }
 
-// reverse of pass 3 (revolute).  abar: the link's acceleration adjoint with
-// all children's shares added; qddbar: seed from the integrator.  Returns
-// ap_bar (the parent receives X^T ap_bar).
+// reverse of pass 3 (revolute), in two parts for the level sweep.  The
+// serial part needs abar, the link's acceleration adjoint with all
+// children's shares added, and qddbar, the integrator's seed; it returns
+// ap_bar (the parent receives X^T ap_bar) and g = qdd_bar / D.  The local
+// part updates the link's own accumulators once the sweep is done.
 template <typename S>
-ABA_HD V6<S> r3_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>& abar, S qddbar) {
-  // a = ap + S qdd
-  V6<S> apb = abar;
-  const S qddb = qddbar + dot(L.ax, abar.a);
-  // qdd = (u - U^T ap) / D
-  const S g = qddb * t.Dinv;
+ABA_HD V6<S> r3_path(const LinkC<S>& L, const Tape<S>& t, const V6<S>& abar, S qddbar, S& g) {
+  // a = ap + S qdd;  qdd = (u - U^T ap) / D
+  g = (qddbar + dot(L.ax, abar.a)) * t.Dinv;
+  return abar - g * t.U;
+}
+template <typename S>
+ABA_HD void r3_local(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>& apb, S g) {
   b.u = b.u + g;
   b.U = b.U - g * t.ap;
-  apb = apb - g * t.U;
   b.D = b.D - g * t.qdd;
   // ap = X a_parent + c
   b.q = b.q + qpair(L.ax, apb, t.ap - t.c);
   b.c = b.c + apb;
+}
+template <typename S>
+ABA_HD V6<S> r3_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>& abar, S qddbar) {
+  S g;
+  const V6<S> apb = r3_path(L, t, abar, qddbar, g);
+  r3_local(L, t, b, apb, g);
   return apb;
 }
 
-// reverse of pass 2 (revolute).  IAbp / pAbp: the parent's adjoints (only
-// used when has_parent).  Produces this link's IA_bar / pA_bar (handed to
-// the children) and tau_bar.
+// reverse of pass 2 (revolute), in two parts.  The serial part takes the
+// parent's adjoints IAbp / pAbp (used only when has_parent), completes
+// U_bar, u_bar and D_bar, and produces this link's IA_bar / pA_bar (handed
+// to the children) and tau_bar; it also returns N = X IAbp X^T and
+// pab = X pAbp for the local part, which adds the joint-angle pairings of
+// the shift and the Ia c term's share of c_bar.
 template <typename S>
-ABA_HD S r2_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent, const SySp<S>& IAbp,
-                 const V6<S>& pAbp, SySp<S>& IAb, V6<S>& pAb) {
+ABA_HD S r2_path(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent, const SySp<S>& IAbp,
+                 const V6<S>& pAbp, SySp<S>& N, V6<S>& pab, SySp<S>& IAb, V6<S>& pAb) {
   IAb = zero_sysp<S>();
   pAb = zero6<S>();
   if (has_parent) {
-    // pA_parent += X^T pa
-    const V6<S> pab0 = xform(t.E, L.rT, pAbp);
-    b.q = b.q + qpair(L.ax, t.pa, pab0);
-    // IA_parent += X^T Ia X
-    const SySp<S> N = congruence_X(t.E, L.rT, IAbp);
-    const SySp<S> Ia = rank1_down(t.IA, t.U, t.Dinv);
-    b.q = b.q - S(2) * pair_crmS(Ia, N, L.ax);
+    // pA_parent += X^T pa;  IA_parent += X^T Ia X
+    pab = xform(t.E, L.rT, pAbp);
+    N = congruence_X(t.E, L.rT, IAbp);
     // pa = pA + Ia c + U u / D
-    const V6<S>& pab = pab0;
     pAb = pAb + pab;
-    SySp<S> Iab = add_sym_outer(N, pab, t.c, S(1));
-    b.c = b.c + mul(Ia, pab);
+    const SySp<S> Iab = add_sym_outer(N, pab, t.c, S(1));
     b.U = b.U + (t.u * t.Dinv) * pab;
     const S Upa = dot(t.U, pab);
     b.u = b.u + Upa * t.Dinv;
@@ -307,24 +312,54 @@ ABA_HD S r2_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent
   IAb = add_sym_outer(IAb, b.U, v6<S>(L.ax, zero3<S>()), S(1));
   return taub;
 }
-
-// reverse of pass 1 (revolute).  vbar: the velocity adjoint with all
-// children's shares; pAb: this link's final bias-force adjoint.  Returns
-// the adjoint handed to the parent's velocity, X^T v_bar.
 template <typename S>
-ABA_HD V6<S> r1_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, V6<S> vbar, const V6<S>& pAb, S qd) {
+ABA_HD void r2_local(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const SySp<S>& N, const V6<S>& pab) {
+  b.q = b.q + qpair(L.ax, t.pa, pab);
+  const SySp<S> Ia = rank1_down(t.IA, t.U, t.Dinv);
+  b.q = b.q - S(2) * pair_crmS(Ia, N, L.ax);
+  b.c = b.c + mul(Ia, pab);
+}
+template <typename S>
+ABA_HD S r2_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent, const SySp<S>& IAbp,
+                 const V6<S>& pAbp, SySp<S>& IAb, V6<S>& pAb) {
+  SySp<S> N;
+  V6<S> pab;
+  const S taub = r2_path(L, t, b, has_parent, IAbp, pAbp, N, pab, IAb, pAb);
+  if (has_parent) r2_local(L, t, b, N, pab);
+  return taub;
+}
+
+// reverse of pass 1, in three parts.  r1_own: the link's own share of its
+// velocity adjoint (from pA = v x* I v and, for a revolute joint,
+// c = v x S qd), which needs only the link's final pA_bar and c_bar.  The
+// serial part adds the children's shares and hands X^T v_bar to the parent.
+// r1_local: qd_bar and q_bar from the complete v_bar.
+template <typename S>
+ABA_HD V6<S> r1_own(const LinkC<S>& L, const V6<S>& v, const Bar<S>& b, const V6<S>& pAb, S qd, bool revolute) {
   // pA(initial) = v x* h, h = I v
-  const V6<S> h = inertia_mul(L, t.v);
-  const V6<S> hb = v6<S>(-cross(t.v.a, pAb.a), -(cross(t.v.a, pAb.l) + cross(t.v.l, pAb.a)));
-  vbar = vbar + crmT(pAb, h) + inertia_mul(L, hb);
-  // c = v x vJ, vJ = [a qd; 0]
-  const V3<S> sq = qd * L.ax;
-  vbar = vbar - v6<S>(cross(b.c.a, sq), cross(b.c.l, sq));
+  const V6<S> h = inertia_mul(L, v);
+  const V6<S> hb = v6<S>(-cross(v.a, pAb.a), -(cross(v.a, pAb.l) + cross(v.l, pAb.a)));
+  V6<S> own = crmT(pAb, h) + inertia_mul(L, hb);
+  if (revolute) {
+    // c = v x vJ, vJ = [a qd; 0]
+    const V3<S> sq = qd * L.ax;
+    own = own - v6<S>(cross(b.c.a, sq), cross(b.c.l, sq));
+  }
+  return own;
+}
+template <typename S>
+ABA_HD void r1_local(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>& vbar, S qd) {
   const V6<S> vJb = crmT(t.v, b.c) + vbar;
   b.qd = b.qd + dot(L.ax, vJb.a);
   // v = X v_parent + vJ
   const V6<S> Xv = v6<S>(axpy(t.v.a, -qd, L.ax), t.v.l);
   b.q = b.q + qpair(L.ax, vbar, Xv);
+}
+// revolute: vbar holds the children's shares; returns X^T v_bar
+template <typename S>
+ABA_HD V6<S> r1_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, V6<S> vbar, const V6<S>& pAb, S qd) {
+  vbar = vbar + r1_own(L, t.v, b, pAb, qd, true);
+  r1_local(L, t, b, vbar, qd);
   return xformT(t.E, L.rT, vbar);
 }
 
@@ -348,10 +383,10 @@ ABA_HD void r3_root(const SySp<S>& IA, const V6<S>& ap, const Q4<S>& quat, const
 }
 // free root, reverse of pass 1: returns the body-velocity adjoint
 template <typename S>
-ABA_HD V6<S> r1_root(const LinkC<S>& L, const V6<S>& v, V6<S> vbar, const V6<S>& pAb) {
-  const V6<S> h = inertia_mul(L, v);
-  const V6<S> hb = v6<S>(-cross(v.a, pAb.a), -(cross(v.a, pAb.l) + cross(v.l, pAb.a)));
-  return vbar + crmT(pAb, h) + inertia_mul(L, hb);
+ABA_HD V6<S> r1_root(const LinkC<S>& L, const V6<S>& v, const V6<S>& vbar, const V6<S>& pAb) {
+  Bar<S> b;
+  bar_zero(b);
+  return vbar + r1_own(L, v, b, pAb, S(0), false);
 }
 
 // adjoint of integrate_root.  Inputs: state at the start of the step (p,

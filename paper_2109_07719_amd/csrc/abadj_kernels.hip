@@ -463,15 +463,20 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
   }
   Bar<S> b;
   bar_zero(b);
+  // Each reverse sweep keeps only what a parent or child needs inside the
+  // level loop; the statements that update a link's own accumulators run
+  // once for all lanes outside it.
   // reverse of pass 3, leaves -> root
   SySp<S> IAb = zero_sysp<S>();
   V6<S> pAb = zero6<S>();
+  V6<S> apb = zero6<S>();
+  S g3 = S(0);
   for (int d = maxd; d >= 0; --d) {
     if (act && l.depth == d) {
       V6<S> ab = zero6<S>();
       for (int k = 0; k < l.ccount; ++k) ab = ab + get6(xb, 0, l.cfirst + k);
       if (rev) {
-        const V6<S> apb = r3_link(L, tp, b, ab, qddb);
+        apb = r3_path(L, tp, ab, qddb, g3);
         if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, apb));
       } else if constexpr (FREE) {
         r3_root(tp.IA, tp.ap, st_quat(st), g, ab, qddb6, quatb, IAb, pAb);
@@ -479,35 +484,42 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
     }
     wave_sync();
   }
+  if (rev) r3_local(L, tp, b, apb, g3);
   // reverse of pass 2, root -> leaves
   S taub = S(0);
+  SySp<S> N = zero_sysp<S>();
+  V6<S> pab = zero6<S>();
   for (int d = 0; d <= maxd; ++d) {
     if (act && l.depth == d) {
       if (rev) {
         const bool hp = l.par >= 0;
         const SySp<S> IAbp = hp ? get21(xb, 0, l.par) : zero_sysp<S>();
         const V6<S> pAbp = hp ? get6(xb, 21, l.par) : zero6<S>();
-        taub = r2_link(L, tp, b, hp, IAbp, pAbp, IAb, pAb);
+        taub = r2_path(L, tp, b, hp, IAbp, pAbp, N, pab, IAb, pAb);
       }
       put21(xb, 0, l.lane, IAb);
       put6(xb, 21, l.lane, pAb);
     }
     wave_sync();
   }
+  if (rev && l.par >= 0) r2_local(L, tp, b, N, pab);
   // reverse of pass 1, leaves -> root
+  const V6<S> own = act ? r1_own(L, tp.v, b, pAb, st.qd[0], rev) : zero6<S>();
+  V6<S> vbar = zero6<S>();
   for (int d = maxd; d >= 0; --d) {
     if (act && l.depth == d) {
       V6<S> vb = zero6<S>();
       for (int k = 0; k < l.ccount; ++k) vb = vb + get6(xb, 0, l.cfirst + k);
+      vbar = vb + own;
       if (rev) {
-        const V6<S> up = r1_link(L, tp, b, vb, pAb, st.qd[0]);
-        if (l.par >= 0) put6(xb, 0, l.lane, up);
+        if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, vbar));
       } else if constexpr (FREE) {
-        vb6 = vb6 + r1_root(L, tp.v, vb, pAb);
+        vb6 = vb6 + vbar;
       }
     }
     wave_sync();
   }
+  if (rev) r1_local(L, tp, b, vbar, st.qd[0]);
   // adjoint of the step's initial state; tau_bar
   if (rev) {
     xb1.q[0] = acc_q + b.q;
