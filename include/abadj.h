@@ -112,6 +112,10 @@ typedef struct {
                               frame so that its joint axis is z, every
                               parent->joint rotation is the identity (the
                               kernels then use a specialised variant)     */
+  int32_t chain;          /* 1 if every system is a fixed-base serial chain
+                              (parent of link i is link i-1); the kernels
+                              then pass parent/child quantities between
+                              neighbouring lanes' registers               */
 } sim_info_t;
 
 /* Build a handle: validates the topology and parameters, orders every

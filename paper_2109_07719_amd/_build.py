@@ -13,7 +13,7 @@ HEADERS = [os.path.join(HERE, "csrc", n) for n in ("spatial.h", "aba_lane.h", "a
     [os.path.join(ROOT, "include", "abadj.h")]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # device code only: let the compiler fold x*0, x+0, x*1 (structural

@@ -41,7 +41,7 @@ class SimParams(ctypes.Structure):
 class SimInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_sys", "n_links", "nq", "nv", "nu", "n_waves",
                                                "n_slots", "max_depth", "has_free", "dtype",
-                                               "frames_identity")]
+                                               "frames_identity", "chain")]
 
 
 class SimError(RuntimeError):

@@ -82,13 +82,21 @@ __host__ __device__ inline size_t state_record(int nslots, int nfree) { return 2
 // per-lane intermediates stored per step in store-all mode (K == 0)
 constexpr int tape_width() { return 56; }
 
-// has_free: the batch contains free-floating roots; eti: every revolute
-// joint frame is the identity after axis canonicalisation
+// What the kernels may specialise on.  has_free: the batch contains
+// free-floating roots; eti: every revolute joint frame is the identity after
+// axis canonicalisation; chain: every system is a fixed-base serial chain
+// (in every wave, a non-root link's parent is the previous lane).
+struct Shape {
+  bool has_free = false;
+  bool eti = false;
+  bool chain = false;
+};
+
 template <typename S>
-hipError_t launch_forward(const FwdArgs<S>& a, bool has_free, bool eti, hipStream_t st);
+hipError_t launch_forward(const FwdArgs<S>& a, const Shape& sh, hipStream_t st);
 template <typename S>
-hipError_t launch_backward(const BwdArgs<S>& a, bool has_free, bool eti, hipStream_t st);
+hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, hipStream_t st);
 template <typename S>
-hipError_t launch_aba(const AbaArgs<S>& a, bool has_free, bool eti, hipStream_t st);
+hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, hipStream_t st);
 
 }  // namespace aba

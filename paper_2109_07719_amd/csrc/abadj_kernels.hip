@@ -38,6 +38,47 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Cross-lane moves for batches of serial chains, where the parent of every
+// non-root link sits in the previous lane and its only child in the next:
+// from_prev gives lane i the value of lane i-1 (DPP wave_shr:1), from_next
+// that of lane i+1 (wave_shl:1); a lane without a source gets 0.  DPP reads
+// the registers of the whole wavefront, so these run with every lane
+// active (outside the per-depth branches).
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  return __builtin_amdgcn_update_dpp(0.0, x, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL, typename S>
+__device__ __forceinline__ V6<S> dpp6(const V6<S>& v) {
+  return v6<S>(v3<S>(dpp_mov<CTRL>(v.a.x), dpp_mov<CTRL>(v.a.y), dpp_mov<CTRL>(v.a.z)),
+               v3<S>(dpp_mov<CTRL>(v.l.x), dpp_mov<CTRL>(v.l.y), dpp_mov<CTRL>(v.l.z)));
+}
+template <int CTRL, typename S>
+__device__ __forceinline__ SySp<S> dpp21(const SySp<S>& M) {
+  SySp<S> R;
+  R.A = sy3<S>(dpp_mov<CTRL>(M.A.xx), dpp_mov<CTRL>(M.A.yy), dpp_mov<CTRL>(M.A.zz), dpp_mov<CTRL>(M.A.xy),
+               dpp_mov<CTRL>(M.A.xz), dpp_mov<CTRL>(M.A.yz));
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R.B.m[k] = dpp_mov<CTRL>(M.B.m[k]);
+  R.C = sy3<S>(dpp_mov<CTRL>(M.C.xx), dpp_mov<CTRL>(M.C.yy), dpp_mov<CTRL>(M.C.zz), dpp_mov<CTRL>(M.C.xy),
+               dpp_mov<CTRL>(M.C.xz), dpp_mov<CTRL>(M.C.yz));
+  return R;
+}
+template <typename S>
+__device__ __forceinline__ V6<S> from_prev(const V6<S>& v) { return dpp6<kDppWaveShr1>(v); }
+template <typename S>
+__device__ __forceinline__ SySp<S> from_prev(const SySp<S>& M) { return dpp21<kDppWaveShr1>(M); }
+template <typename S>
+__device__ __forceinline__ V6<S> from_next(const V6<S>& v) { return dpp6<kDppWaveShl1>(v); }
+template <typename S>
+__device__ __forceinline__ SySp<S> from_next(const SySp<S>& M) { return dpp21<kDppWaveShl1>(M); }
+
 __device__ __forceinline__ void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
 
@@ -276,10 +317,57 @@ __device__ __forceinline__ void get_tape(Step<S>& o, const S* base, int ns, int 
   }
 }
 
+// The three ABA passes for a wave of serial chains with fixed bases (every
+// active lane revolute): parent/child quantities move between neighbouring
+// lanes in registers.  A root never pushes to its parent, so the lane after
+// a chain's leaf always hands the leaf zeros.
+template <typename S>
+__device__ __forceinline__ void aba_wave_chain(const Packed<S>& P, const Lane<S>& l, const LinkC<S>& L,
+                                               const State<S, false>& st, S tau, int maxd, Step<S>& o) {
+  Tape<S>& t = o.t;
+  const bool act = l.active();
+  const bool hp = l.par >= 0;
+  sincos_(st.q[0], &t.sq, &t.cq);
+  t.E = joint_E(L, t.sq, t.cq);
+  // pass 1: velocities, root -> leaves
+  t.v = zero6<S>();
+  for (int d = 0; d <= maxd; ++d) {
+    const V6<S> vp = from_prev(t.v);
+    if (act && l.depth == d) t.v = p1_velocity(L, t.E, st.qd[0], hp ? vp : zero6<S>());
+  }
+  // pass 1: bias terms (parallel over links)
+  if (act) p1_bias(L, t.v, st.qd[0], true, t.c, t.pA, t.IA);
+  // pass 2: articulated inertias, leaves -> root
+  SySp<S> IAu = zero_sysp<S>();
+  V6<S> pAu = zero6<S>();
+  for (int d = maxd; d >= 0; --d) {
+    const SySp<S> cI = from_next(IAu);
+    const V6<S> cp = from_next(pAu);
+    if (act && l.depth == d) {
+      t.IA = t.IA + cI;
+      t.pA = t.pA + cp;
+      p2_local(L, t, tau);
+      if (hp) p2_push(L, t, IAu, pAu);
+    }
+  }
+  // pass 3: accelerations, root -> leaves
+  const V6<S> a0 = v6<S>(zero3<S>(), v3<S>(-P.g[0], -P.g[1], -P.g[2]));
+  V6<S> a = zero6<S>();
+  for (int d = 0; d <= maxd; ++d) {
+    const V6<S> ap = from_prev(a);
+    if (act && l.depth == d) a = p3_accel(L, t, hp ? ap : a0);
+  }
+}
+
 // One ABA evaluation for the whole wave (all three passes).
-template <typename S, bool FREE>
+template <typename S, bool FREE, bool CHAIN>
 __device__ __forceinline__ void aba_wave(const Packed<S>& P, const Lane<S>& l, const LinkC<S>& L,
                                          const State<S, FREE>& st, S tau, int maxd, S* xb, Step<S>& o) {
+  if constexpr (CHAIN) {
+    static_assert(!FREE, "the chain variant has fixed bases only");
+    aba_wave_chain<S>(P, l, L, st, tau, maxd, o);
+    return;
+  }
   Tape<S>& t = o.t;
   const bool act = l.active();
   const bool rev = l.revolute();
@@ -359,7 +447,7 @@ __device__ __forceinline__ void integrate_lane(State<S, FREE>& st, const Lane<S>
 
 // ------------------------------------------------------------------ kernels
 
-template <typename S, bool FREE, bool ETI>
+template <typename S, bool FREE, bool ETI, bool CHAIN>
 __global__ __launch_bounds__(64) void k_aba(AbaArgs<S> A) {
   __shared__ S xb[XB * kWave];
   const Lane<S> l = load_lane(A.P);
@@ -374,7 +462,7 @@ __global__ __launch_bounds__(64) void k_aba(AbaArgs<S> A) {
     if (l.revolute()) tau = A.tau[l.uidx];
   }
   Step<S> o;
-  aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+  aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
   if (l.revolute()) {
     A.qdd[l.vidx] = o.t.qdd;
   } else if constexpr (FREE) {
@@ -388,8 +476,8 @@ __global__ __launch_bounds__(64) void k_aba(AbaArgs<S> A) {
 
 // Forward rollout.  MODE 0: plain; 1: store the initial state of every
 // K-th step; 2: store every step's initial state and intermediates
-// (store-all).  TRAJ: also write x^{t+1} for every step.
-template <typename S, bool FREE, bool ETI, int MODE, bool TRAJ>
+// (store-all).  With a trajectory buffer, also write x^{t+1} for every step.
+template <typename S, bool FREE, bool ETI, bool CHAIN, int MODE>
 __global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
   __shared__ S xb[XB * kWave];
   const Lane<S> l = load_lane(A.P);
@@ -410,7 +498,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
     const S tau = tau_next;
     if (has_tau && t + 1 < A.T) tau_next = A.tau[(size_t)(t + 1) * nu + l.uidx];
     Step<S> o;
-    aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+    aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
     if constexpr (MODE == 2) {
       if (l.active()) {
         S* row = A.ck + (size_t)t * (RW + (size_t)kTapeFields * ns);
@@ -419,7 +507,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
       }
     }
     if (l.active()) integrate_lane(st, l, o, A.dt);
-    if constexpr (TRAJ) {
+    if (A.traj != nullptr) {
       if (l.active()) {
         S* row = A.traj + (size_t)t * (A.P.nq + A.P.nv);
         store_state(st, l, row, row + A.P.nq);
@@ -433,7 +521,7 @@ __global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
 // initial state st, then run the adjoints of the integrator, pass 3, pass 2
 // and pass 1.  xb1 holds the adjoint of x^{t+1} on entry and that of x^t on
 // exit; tau_bar^t is written to gtau.
-template <typename S, bool FREE>
+template <typename S, bool FREE, bool CHAIN>
 __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
                                             S* xb, const State<S, FREE>& st, const Step<S>& o, int t,
                                             State<S, FREE>& xb1) {
@@ -471,53 +559,83 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
   V6<S> pAb = zero6<S>();
   V6<S> apb = zero6<S>();
   S g3 = S(0);
-  for (int d = maxd; d >= 0; --d) {
-    if (act && l.depth == d) {
-      V6<S> ab = zero6<S>();
-      for (int k = 0; k < l.ccount; ++k) ab = ab + get6(xb, 0, l.cfirst + k);
-      if (rev) {
+  if constexpr (CHAIN) {
+    V6<S> up = zero6<S>();
+    for (int d = maxd; d >= 0; --d) {
+      const V6<S> ab = from_next(up);
+      if (act && l.depth == d) {
         apb = r3_path(L, tp, ab, qddb, g3);
-        if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, apb));
-      } else if constexpr (FREE) {
-        r3_root(tp.IA, tp.ap, st_quat(st), g, ab, qddb6, quatb, IAb, pAb);
+        if (l.par >= 0) up = xformT(tp.E, L.rT, apb);
       }
     }
-    wave_sync();
+  } else {
+    for (int d = maxd; d >= 0; --d) {
+      if (act && l.depth == d) {
+        V6<S> ab = zero6<S>();
+        for (int k = 0; k < l.ccount; ++k) ab = ab + get6(xb, 0, l.cfirst + k);
+        if (rev) {
+          apb = r3_path(L, tp, ab, qddb, g3);
+          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, apb));
+        } else if constexpr (FREE) {
+          r3_root(tp.IA, tp.ap, st_quat(st), g, ab, qddb6, quatb, IAb, pAb);
+        }
+      }
+      wave_sync();
+    }
   }
   if (rev) r3_local(L, tp, b, apb, g3);
   // reverse of pass 2, root -> leaves
   S taub = S(0);
   SySp<S> N = zero_sysp<S>();
   V6<S> pab = zero6<S>();
-  for (int d = 0; d <= maxd; ++d) {
-    if (act && l.depth == d) {
-      if (rev) {
-        const bool hp = l.par >= 0;
-        const SySp<S> IAbp = hp ? get21(xb, 0, l.par) : zero_sysp<S>();
-        const V6<S> pAbp = hp ? get6(xb, 21, l.par) : zero6<S>();
-        taub = r2_path(L, tp, b, hp, IAbp, pAbp, N, pab, IAb, pAb);
-      }
-      put21(xb, 0, l.lane, IAb);
-      put6(xb, 21, l.lane, pAb);
+  if constexpr (CHAIN) {
+    for (int d = 0; d <= maxd; ++d) {
+      const SySp<S> IAbp = from_prev(IAb);
+      const V6<S> pAbp = from_prev(pAb);
+      if (act && l.depth == d) taub = r2_path(L, tp, b, l.par >= 0, IAbp, pAbp, N, pab, IAb, pAb);
     }
-    wave_sync();
+  } else {
+    for (int d = 0; d <= maxd; ++d) {
+      if (act && l.depth == d) {
+        if (rev) {
+          const bool hp = l.par >= 0;
+          const SySp<S> IAbp = hp ? get21(xb, 0, l.par) : zero_sysp<S>();
+          const V6<S> pAbp = hp ? get6(xb, 21, l.par) : zero6<S>();
+          taub = r2_path(L, tp, b, hp, IAbp, pAbp, N, pab, IAb, pAb);
+        }
+        put21(xb, 0, l.lane, IAb);
+        put6(xb, 21, l.lane, pAb);
+      }
+      wave_sync();
+    }
   }
   if (rev && l.par >= 0) r2_local(L, tp, b, N, pab);
   // reverse of pass 1, leaves -> root
   const V6<S> own = act ? r1_own(L, tp.v, b, pAb, st.qd[0], rev) : zero6<S>();
   V6<S> vbar = zero6<S>();
-  for (int d = maxd; d >= 0; --d) {
-    if (act && l.depth == d) {
-      V6<S> vb = zero6<S>();
-      for (int k = 0; k < l.ccount; ++k) vb = vb + get6(xb, 0, l.cfirst + k);
-      vbar = vb + own;
-      if (rev) {
-        if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, vbar));
-      } else if constexpr (FREE) {
-        vb6 = vb6 + vbar;
+  if constexpr (CHAIN) {
+    V6<S> up = zero6<S>();
+    for (int d = maxd; d >= 0; --d) {
+      const V6<S> vb = from_next(up);
+      if (act && l.depth == d) {
+        vbar = vb + own;
+        if (l.par >= 0) up = xformT(tp.E, L.rT, vbar);
       }
     }
-    wave_sync();
+  } else {
+    for (int d = maxd; d >= 0; --d) {
+      if (act && l.depth == d) {
+        V6<S> vb = zero6<S>();
+        for (int k = 0; k < l.ccount; ++k) vb = vb + get6(xb, 0, l.cfirst + k);
+        vbar = vb + own;
+        if (rev) {
+          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, vbar));
+        } else if constexpr (FREE) {
+          vb6 = vb6 + vbar;
+        }
+      }
+      wave_sync();
+    }
   }
   if (rev) r1_local(L, tp, b, vbar, st.qd[0]);
   // adjoint of the step's initial state; tau_bar
@@ -544,19 +662,19 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
   }
 }
 
-template <typename S, bool FREE>
+template <typename S, bool FREE, bool CHAIN>
 __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
                                          S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1) {
   Step<S> o;
-  aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
-  bwd_reverse<S, FREE>(A, l, L, maxd, xb, st, o, t, xb1);
+  aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
+  bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1);
 }
 
 // Backward (adjoint) rollout, reverse time.  K == 1 reloads every step's
 // checkpoint; K > 1 replays each K-step segment from its checkpoint into
 // the scratch buffer first.  The next state and control are fetched one
 // step ahead.
-template <typename S, bool FREE, bool ETI>
+template <typename S, bool FREE, bool ETI, bool CHAIN>
 __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
   __shared__ S xb[XB * kWave];
   const Lane<S> l = load_lane(A.P);
@@ -591,7 +709,7 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
         get_slot(st, row, ns, nf, l.slot, l.fidx);
         get_tape(o, row + RW, ns, l.slot, L, st.qd[0], rev);
       }
-      bwd_reverse<S, FREE>(A, l, L, maxd, xb, st, o, t, xb1);
+      bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1);
     }
   } else if (A.K == 1) {
     State<S, FREE> nxt = {};
@@ -607,7 +725,7 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
         if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
         if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
       }
-      bwd_step<S, FREE>(A, l, L, maxd, xb, st, tau, t, xb1);
+      bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, st, tau, t, xb1);
     }
   } else {
     const int ncp = (A.T + A.K - 1) / A.K;
@@ -625,7 +743,7 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
         const S tau = tau_nxt;
         if (rev && j + 1 < t1 - t0) tau_nxt = A.tau[(size_t)(t0 + j) * nu + l.uidx];
         Step<S> o;
-        aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+        aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
         if (act) {
           integrate_lane(st, l, o, A.dt);
           put_slot(st, A.scratch + (size_t)j * RW, ns, nf, l.slot, l.fidx);
@@ -641,7 +759,7 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
           if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
-        bwd_step<S, FREE>(A, l, L, maxd, xb, cur, tau, t, xb1);
+        bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, cur, tau, t, xb1);
       }
     }
   }
@@ -655,7 +773,7 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
 // k: the producer recomputes step T-1-k into buffer k%2 while the consumer
 // reverses step T-k from buffer (k-1)%2; one workgroup barrier ends every
 // phase (both waves execute exactly T+1 of them).
-template <typename S, bool FREE, bool ETI>
+template <typename S, bool FREE, bool ETI, bool CHAIN>
 __global__ __launch_bounds__(128) void k_backward_pipe(BwdArgs<S> A) {
   constexpr int TW = kTapeFields + (FREE ? 13 : 2);  // tape + state per lane
   __shared__ S xbs[2][XB * kWave];
@@ -688,7 +806,7 @@ __global__ __launch_bounds__(128) void k_backward_pipe(BwdArgs<S> A) {
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
         Step<S> o;
-        aba_wave<S, FREE>(A.P, l, L, st, tau, maxd, xb, o);
+        aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
         S* tb = tbuf[k & 1];
 #pragma unroll
         for (int j = 0; j < (FREE ? 7 : 1); ++j) tb[(size_t)j * kWave + l.lane] = st.q[j];
@@ -723,7 +841,7 @@ __global__ __launch_bounds__(128) void k_backward_pipe(BwdArgs<S> A) {
         for (int j = 0; j < (FREE ? 6 : 1); ++j) st.qd[j] = tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane];
         Step<S> o;
         get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, L, st.qd[0], rev);
-        bwd_reverse<S, FREE>(A, l, L, maxd, xb, st, o, t, xb1);
+        bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1);
       }
       __syncthreads();
     }
@@ -733,81 +851,70 @@ __global__ __launch_bounds__(128) void k_backward_pipe(BwdArgs<S> A) {
 
 }  // namespace
 
-template <typename S>
-hipError_t launch_aba(const AbaArgs<S>& a, bool has_free, bool eti, hipStream_t st) {
-  if (a.P.nwaves == 0) return hipSuccess;
-  dim3 grid(a.P.nwaves), block(kWave);
-#define ABA_K(F, E) hipLaunchKernelGGL((k_aba<S, F, E>), grid, block, 0, st, a)
-  if (has_free) {
-    if (eti) ABA_K(true, true);
-    else ABA_K(true, false);
-  } else {
-    if (eti) ABA_K(false, true);
-    else ABA_K(false, false);
+// Kernel variants: FREE (some system has a free-floating root), ETI (every
+// joint frame is the identity after canonicalisation), CHAIN (every system
+// is a fixed-base serial chain; register exchange between lanes).
+enum class Variant { kFree, kFreeEti, kTree, kTreeEti, kChain, kChainEti };
+
+Variant variant(const Shape& sh) {
+  if (sh.has_free) return sh.eti ? Variant::kFreeEti : Variant::kFree;
+  if (sh.chain) return sh.eti ? Variant::kChainEti : Variant::kChain;
+  return sh.eti ? Variant::kTreeEti : Variant::kTree;
+}
+
+// calls f.template operator()<FREE, ETI, CHAIN>()
+template <typename F>
+void dispatch(const Shape& sh, F&& f) {
+  switch (variant(sh)) {
+    case Variant::kFree: f.template operator()<true, false, false>(); break;
+    case Variant::kFreeEti: f.template operator()<true, true, false>(); break;
+    case Variant::kTree: f.template operator()<false, false, false>(); break;
+    case Variant::kTreeEti: f.template operator()<false, true, false>(); break;
+    case Variant::kChain: f.template operator()<false, false, true>(); break;
+    case Variant::kChainEti: f.template operator()<false, true, true>(); break;
   }
-#undef ABA_K
+}
+
+template <typename S>
+hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, hipStream_t st) {
+  if (a.P.nwaves == 0) return hipSuccess;
+  dispatch(sh, [&]<bool F, bool E, bool C>() {
+    hipLaunchKernelGGL((k_aba<S, F, E, C>), dim3(a.P.nwaves), dim3(kWave), 0, st, a);
+  });
   return hipGetLastError();
 }
 
-template <typename S, bool F, bool E>
-void launch_forward_fe(const FwdArgs<S>& a, hipStream_t st) {
-  dim3 grid(a.P.nwaves), block(kWave);
+template <typename S>
+hipError_t launch_forward(const FwdArgs<S>& a, const Shape& sh, hipStream_t st) {
+  if (a.P.nwaves == 0) return hipSuccess;
   const int mode = (a.ck == nullptr) ? 0 : (a.K == 0) ? 2 : 1;
-  const bool tr = a.traj != nullptr;
-#define ABA_FWD(M, R) hipLaunchKernelGGL((k_forward<S, F, E, M, R>), grid, block, 0, st, a)
-  if (mode == 0) {
-    if (tr) ABA_FWD(0, true);
-    else ABA_FWD(0, false);
-  } else if (mode == 1) {
-    if (tr) ABA_FWD(1, true);
-    else ABA_FWD(1, false);
-  } else {
-    if (tr) ABA_FWD(2, true);
-    else ABA_FWD(2, false);
-  }
-#undef ABA_FWD
-}
-
-template <typename S>
-hipError_t launch_forward(const FwdArgs<S>& a, bool has_free, bool eti, hipStream_t st) {
-  if (a.P.nwaves == 0) return hipSuccess;
-  if (has_free) {
-    if (eti) launch_forward_fe<S, true, true>(a, st);
-    else launch_forward_fe<S, true, false>(a, st);
-  } else {
-    if (eti) launch_forward_fe<S, false, true>(a, st);
-    else launch_forward_fe<S, false, false>(a, st);
-  }
+  dispatch(sh, [&]<bool F, bool E, bool C>() {
+    const dim3 grid(a.P.nwaves), block(kWave);
+    if (mode == 0) hipLaunchKernelGGL((k_forward<S, F, E, C, 0>), grid, block, 0, st, a);
+    else if (mode == 1) hipLaunchKernelGGL((k_forward<S, F, E, C, 1>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_forward<S, F, E, C, 2>), grid, block, 0, st, a);
+  });
   return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_backward(const BwdArgs<S>& a, bool has_free, bool eti, hipStream_t st) {
+hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
-  dim3 grid(a.P.nwaves), block(kWave);
-#define ABA_BWD(F, E)                                                                         \
-  do {                                                                                        \
-    if (a.K == 1)                                                                             \
-      hipLaunchKernelGGL((k_backward_pipe<S, F, E>), grid, dim3(2 * kWave), 0, st, a);       \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_backward<S, F, E>), grid, block, 0, st, a);                      \
-  } while (0)
-  if (has_free) {
-    if (eti) ABA_BWD(true, true);
-    else ABA_BWD(true, false);
-  } else {
-    if (eti) ABA_BWD(false, true);
-    else ABA_BWD(false, false);
-  }
-#undef ABA_BWD
+  dispatch(sh, [&]<bool F, bool E, bool C>() {
+    const dim3 grid(a.P.nwaves);
+    if (a.K == 1)
+      hipLaunchKernelGGL((k_backward_pipe<S, F, E, C>), grid, dim3(2 * kWave), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_backward<S, F, E, C>), grid, dim3(kWave), 0, st, a);
+  });
   return hipGetLastError();
 }
 
-template hipError_t launch_aba<float>(const AbaArgs<float>&, bool, bool, hipStream_t);
-template hipError_t launch_aba<double>(const AbaArgs<double>&, bool, bool, hipStream_t);
-template hipError_t launch_forward<float>(const FwdArgs<float>&, bool, bool, hipStream_t);
-template hipError_t launch_forward<double>(const FwdArgs<double>&, bool, bool, hipStream_t);
-template hipError_t launch_backward<float>(const BwdArgs<float>&, bool, bool, hipStream_t);
-template hipError_t launch_backward<double>(const BwdArgs<double>&, bool, bool, hipStream_t);
+template hipError_t launch_aba<float>(const AbaArgs<float>&, const Shape&, hipStream_t);
+template hipError_t launch_aba<double>(const AbaArgs<double>&, const Shape&, hipStream_t);
+template hipError_t launch_forward<float>(const FwdArgs<float>&, const Shape&, hipStream_t);
+template hipError_t launch_forward<double>(const FwdArgs<double>&, const Shape&, hipStream_t);
+template hipError_t launch_backward<float>(const BwdArgs<float>&, const Shape&, hipStream_t);
+template hipError_t launch_backward<double>(const BwdArgs<double>&, const Shape&, hipStream_t);
 
 }  // namespace aba

@@ -34,6 +34,7 @@ struct sim_handle {
   int nwaves = 0, nslots = 0, max_depth = 0, nfree = 0;
   bool has_free = false;
   bool eti = false;  // every revolute joint frame is the identity after canonicalisation
+  bool chain = false;  // every system is a fixed-base serial chain
   double g[3] = {0, 0, 0};
   int32_t* d_ci = nullptr;
   void* d_cf = nullptr;
@@ -43,6 +44,14 @@ struct sim_handle {
 };
 
 namespace {
+
+aba::Shape shape(const sim_handle* h) {
+  aba::Shape sh;
+  sh.has_free = h->has_free;
+  sh.eti = h->eti;
+  sh.chain = h->chain;
+  return sh;
+}
 
 template <typename S>
 aba::Packed<S> packed(const sim_handle* h) {
@@ -384,6 +393,15 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       }
     }
   }
+  // serial chains: if every non-root link's parent sits in the previous
+  // lane, a lane's only possible child is the next lane, and the kernels
+  // exchange parent/child quantities between neighbouring lanes' registers
+  bool chain = !h->has_free;
+  for (int slot = 0; chain && slot < NS; ++slot) {
+    const int p = ci[(size_t)aba::CI_PARENT * NS + slot];
+    if (ci[(size_t)aba::CI_JTYPE * NS + slot] >= 0 && p >= 0 && p != slot % aba::kWave - 1) chain = false;
+  }
+  h->chain = chain;
   std::vector<int32_t> wmaxd(wave_depth.begin(), wave_depth.end());
   const int rc = (dtype == SIM_F64) ? upload<double>(h, ci, cf, wmaxd) : upload<float>(h, ci, cf, wmaxd);
   if (rc != SIM_OK) {
@@ -413,6 +431,7 @@ int sim_get_info(sim_t h, sim_info_t* o) {
   o->max_depth = h->max_depth;
   o->has_free = h->has_free ? 1 : 0;
   o->frames_identity = h->eti ? 1 : 0;
+  o->chain = h->chain ? 1 : 0;
   o->dtype = h->dtype;
   return SIM_OK;
 }
@@ -460,7 +479,7 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
     a.qdT = (double*)qdT;
     a.traj = (double*)traj;
     a.ck = (double*)workspace;
-    e = aba::launch_forward(a, h->has_free, h->eti, (hipStream_t)stream);
+    e = aba::launch_forward(a, shape(h), (hipStream_t)stream);
   } else {
     aba::FwdArgs<float> a;
     a.P = packed<float>(h);
@@ -474,7 +493,7 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
     a.qdT = (float*)qdT;
     a.traj = (float*)traj;
     a.ck = (float*)workspace;
-    e = aba::launch_forward(a, h->has_free, h->eti, (hipStream_t)stream);
+    e = aba::launch_forward(a, shape(h), (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_forward: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
@@ -510,7 +529,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (double*)gtau;
     a.ck = (const double*)workspace;
     a.scratch = (K > 1) ? (double*)((char*)workspace + ck) : nullptr;
-    e = aba::launch_backward(a, h->has_free, h->eti, (hipStream_t)stream);
+    e = aba::launch_backward(a, shape(h), (hipStream_t)stream);
   } else {
     aba::BwdArgs<float> a;
     a.P = packed<float>(h);
@@ -526,7 +545,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (float*)gtau;
     a.ck = (const float*)workspace;
     a.scratch = (K > 1) ? (float*)((char*)workspace + ck) : nullptr;
-    e = aba::launch_backward(a, h->has_free, h->eti, (hipStream_t)stream);
+    e = aba::launch_backward(a, shape(h), (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_backward: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
@@ -543,7 +562,7 @@ int sim_aba(sim_t h, const void* q, const void* qd, const void* tau, void* qdd, 
     a.qd = (const double*)qd;
     a.tau = (const double*)tau;
     a.qdd = (double*)qdd;
-    e = aba::launch_aba(a, h->has_free, h->eti, (hipStream_t)stream);
+    e = aba::launch_aba(a, shape(h), (hipStream_t)stream);
   } else {
     aba::AbaArgs<float> a;
     a.P = packed<float>(h);
@@ -551,7 +570,7 @@ int sim_aba(sim_t h, const void* q, const void* qd, const void* tau, void* qdd, 
     a.qd = (const float*)qd;
     a.tau = (const float*)tau;
     a.qdd = (float*)qdd;
-    e = aba::launch_aba(a, h->has_free, h->eti, (hipStream_t)stream);
+    e = aba::launch_aba(a, shape(h), (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_aba: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
