@@ -154,6 +154,9 @@ def memory_sweep(args, torch, dev, sim, b):
         base = torch.cuda.memory_allocated()
         need = sim.workspace_bytes(T, K)
         row = {"K": K if K else "store-all", "workspace_bytes": need}
+        if args.tiling == "auto":
+            row["autotune"] = sim.autotune(K=K, T_probe=min(T, 200))
+        row["tiling"] = sim.tiling
         try:
             ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
         except RuntimeError as e:
@@ -195,6 +198,7 @@ def trajopt_bench(args, torch, dev):
     T = args.T or 1000
     b, targets = chains_problem(n_systems=2048, T=T)
     opt = TrajOpt(b, targets, [s.n - 1 for s in b.systems], np.tile([0.5, 0, 0], (2048, 1)), K=args.K)
+    tune = opt.sim.autotune(K=args.K, T_probe=min(T, 200)) if args.tiling == "auto" else None
     checks = {0, args.trajopt // 2, args.trajopt - 1}
     losses, it_ms, spot = [], [], []
     for it in range(args.trajopt):
@@ -217,7 +221,7 @@ def trajopt_bench(args, torch, dev):
                       "iterations": args.trajopt, "loss_first": losses[0], "loss_last": losses[-1],
                       "loss_every_10": losses[::10], "fp64_spot_checks": spot, "dtype": "f32",
                       "config": {"workload": WORKLOADS["chains_2048"], "systems": 2048, "dof": b.total_dof,
-                                 "T": T, "K": args.K}}))
+                                 "T": T, "K": args.K, "tiling": opt.sim.tiling, "autotune": tune}}))
 
 
 def _trajopt_spot_check(opt, b, targets, torch):
@@ -274,6 +278,10 @@ def main():
     ap.add_argument("--trajopt", type=int, default=0,
                     help="run this many Adam iterations of trajectory optimisation (chains_2048 workload)")
     ap.add_argument("--T", type=int, default=None, help="override the horizon (reduced runs only)")
+    ap.add_argument("--tiling", default="auto",
+                    help="launch geometry: 'auto' (the library's autotuner, before the timed region), 'default' "
+                         "(occupancy rule), or W,P,PIPE = waves per workgroup, producer/consumer pairs per "
+                         "workgroup, pipelined adjoint (1/0)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -312,6 +320,14 @@ def main():
     t_gen = time.perf_counter() - t_gen
 
     sim = Sim(b.systems, b.gravity, dtype=torch.float32)
+    tune = None
+    if args.tiling == "auto":
+        t0 = time.perf_counter()
+        tune = sim.autotune(K=args.K, T_probe=min(b.T, 200))
+        tune["seconds"] = time.perf_counter() - t0
+    elif args.tiling != "default":
+        w, p_, pipe = (int(x) for x in args.tiling.split(","))
+        sim.set_tiling(w, p_, bool(pipe))
     if args.memory_sweep:
         return memory_sweep(args, torch, dev, sim, b)
     T, K, dt = b.T, args.K, b.dt
@@ -408,7 +424,8 @@ def main():
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": WORKLOADS[args.workload], "systems": len(b.systems), "dof": b.total_dof,
                       "T": T, "dt": dt, "K": K, "lanes": sim.info["n_slots"], "waves": sim.info["n_waves"],
-                      "lanes_per_system": "one lane per link"},
+                      "lanes_per_system": "one lane per link", "tiling": sim.tiling,
+                      "autotune": tune},
            "plain_fwd_dof_steps_per_s": plain_rate, "fwd_adjoint_over_plain_fwd_time": value and plain_rate / value,
            "peak_mem_bytes": int(peak_mem), "results_finite": finite, "roofline": roofline,
            "wall_s_timed": wall, "input_gen_s": t_gen}

@@ -134,6 +134,45 @@ void sim_destroy(sim_t h);
 
 int sim_get_info(sim_t h, sim_info_t *out);
 
+/* Launch geometry of the handle's kernels (the autotuner's knobs; they
+ * change no arithmetic, only how wavefronts are grouped into workgroups and
+ * so where they run and how much LDS a workgroup takes).
+ *   waves_per_block: 1, 2 or 4 wavefronts per workgroup in the forward,
+ *     single-evaluation and non-pipelined adjoint kernels;
+ *   pairs_per_block: 1 or 2 producer/consumer wavefront pairs per
+ *     workgroup in the pipelined adjoint;
+ *   pipelined: 1 = K == 1 adjoints use the pipelined kernel (one wavefront
+ *     recomputes step t-1 while another reverses step t), 0 = one wavefront
+ *     does both.
+ * A choice whose LDS would exceed the device's per-workgroup limit is
+ * reduced at launch.  Default (from occupancy): 4 waves per block;
+ * pipelined with 2 pairs per block while the pipelined pairs fit one
+ * wavefront per SIMD, otherwise not pipelined.  Not thread-safe against
+ * concurrent launches on the same handle.  Errors: SIM_ERR_INVALID_ARG. */
+typedef struct {
+  int32_t waves_per_block;
+  int32_t pairs_per_block;
+  int32_t pipelined;
+} sim_tiling_t;
+int sim_get_tiling(sim_t h, sim_tiling_t *out);
+int sim_set_tiling(sim_t h, const sim_tiling_t *tiling);
+
+/* Autotuner: time every launch geometry on this device for a forward plus
+ * backward rollout of T_probe steps with checkpoint interval K (a probe
+ * rollout from the zero state with unit quaternions and zero torques; run
+ * time does not depend on the values), then keep the fastest on the handle
+ * (as sim_set_tiling would).  The forward and the one-wave adjoint share
+ * waves_per_block, so whole pairs of choices are compared.  Store-all
+ * probes (K == 0) are shortened to at most 2 GiB of workspace.  Allocates
+ * and frees its own probe buffers, synchronises `stream` (a hipStream_t,
+ * NULL = default), and must not be called during stream capture.
+ * chosen (nullable) receives the winner, ms_per_step (nullable) its
+ * forward+backward time per probe step.  Arithmetic is unaffected by the
+ * choice.  Errors: SIM_ERR_INVALID_ARG (K < 0, T_probe outside 1..100000),
+ * SIM_ERR_HIP (probe allocation or launch failed; the tiling is left as it
+ * was). */
+int sim_autotune(sim_t h, int K, int T_probe, void *stream, sim_tiling_t *chosen, double *ms_per_step);
+
 /* Bytes of workspace needed by sim_forward/sim_backward for T steps with a
  * checkpoint every K >= 1 steps (K > 1 adds a K-state replay buffer), or,
  * for K == 0 (store-all), every step's initial state and all per-link

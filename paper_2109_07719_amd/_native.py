@@ -23,7 +23,9 @@ SIM_JOINT_REVOLUTE = 0
 SIM_JOINT_FREE = 1
 SIM_MAX_LINKS = 64
 
-EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_workspace_bytes", "sim_forward",
+EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_get_tiling", "sim_set_tiling", "sim_autotune",
+            "sim_workspace_bytes",
+            "sim_forward",
             "sim_backward", "sim_aba", "sim_flops", "sim_last_error")
 
 
@@ -42,6 +44,10 @@ class SimInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_sys", "n_links", "nq", "nv", "nu", "n_waves",
                                                "n_slots", "max_depth", "has_free", "dtype",
                                                "frames_identity", "chain")]
+
+
+class SimTiling(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("waves_per_block", "pairs_per_block", "pipelined")]
 
 
 class SimError(RuntimeError):
@@ -69,6 +75,12 @@ def lib():
         L.sim_destroy.restype = None
         L.sim_get_info.argtypes = [P, ctypes.POINTER(SimInfo)]
         L.sim_get_info.restype = I
+        L.sim_get_tiling.argtypes = [P, ctypes.POINTER(SimTiling)]
+        L.sim_get_tiling.restype = I
+        L.sim_set_tiling.argtypes = [P, ctypes.POINTER(SimTiling)]
+        L.sim_set_tiling.restype = I
+        L.sim_autotune.argtypes = [P, I, I, P, ctypes.POINTER(SimTiling), ctypes.POINTER(D)]
+        L.sim_autotune.restype = I
         L.sim_workspace_bytes.argtypes = [P, I, I, ctypes.POINTER(Z)]
         L.sim_workspace_bytes.restype = I
         L.sim_forward.argtypes = [P, P, P, P, D, I, I, P, P, P, P, Z, P]

@@ -92,11 +92,25 @@ struct Shape {
   bool chain = false;
 };
 
+// Launch geometry.  waves_per_block: wavefronts per workgroup in the
+// single-wave kernels (each wavefront on its own systems); pairs_per_block:
+// producer/consumer wavefront pairs per workgroup in the pipelined adjoint;
+// pipelined: whether K == 1 uses the pipelined adjoint at all.  The host
+// pads the wave count to a multiple of kMaxWavesPerBlock with empty
+// wavefronts, so every choice divides it.
+constexpr int kMaxWavesPerBlock = 4;
+constexpr int kMaxPairsPerBlock = 2;
+struct Tiling {
+  int waves_per_block = 1;
+  int pairs_per_block = 1;
+  bool pipelined = true;
+};
+
 template <typename S>
-hipError_t launch_forward(const FwdArgs<S>& a, const Shape& sh, hipStream_t st);
+hipError_t launch_forward(const FwdArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
 template <typename S>
-hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, hipStream_t st);
+hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
 template <typename S>
-hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, hipStream_t st);
+hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
 
 }  // namespace aba

@@ -90,11 +90,12 @@ struct Lane {
   __device__ bool revolute() const { return jtype == 0; }
 };
 
+// wb: the wave batch (64 lane slots) this wavefront works on
 template <typename S>
-__device__ __forceinline__ Lane<S> load_lane(const Packed<S>& P) {
+__device__ __forceinline__ Lane<S> load_lane(const Packed<S>& P, int wb) {
   Lane<S> l;
   l.lane = threadIdx.x % kWave;
-  l.slot = blockIdx.x * kWave + l.lane;
+  l.slot = wb * kWave + l.lane;
   const int ns = P.nslots;
   const int32_t* ci = P.ci;
   l.par = ci[CI_PARENT * ns + l.slot];
@@ -134,6 +135,18 @@ __device__ __forceinline__ LinkC<S> load_linkc(const Packed<S>& P, int slot) {
                 cf[(CF_IB + 3) * ns + slot], cf[(CF_IB + 4) * ns + slot], cf[(CF_IB + 5) * ns + slot]);
   return L;
 }
+
+// Dynamic LDS of a workgroup, sized by the launcher: one exchange buffer per
+// wavefront (single-wave kernels), or per producer/consumer pair two
+// exchange buffers and the double-buffered tape (pipelined adjoint).
+extern __shared__ __align__(16) unsigned char abadj_lds[];
+template <typename S>
+__device__ __forceinline__ S* lds() {
+  return reinterpret_cast<S*>(abadj_lds);
+}
+// wave batch of a single-wave kernel's wavefront, and its place in the block
+__device__ __forceinline__ int wave_in_block() { return threadIdx.x / kWave; }
+__device__ __forceinline__ int wave_batch() { return blockIdx.x * (blockDim.x / kWave) + wave_in_block(); }
 
 // ---- exchange buffer [field][lane]
 template <typename S>
@@ -448,10 +461,11 @@ __device__ __forceinline__ void integrate_lane(State<S, FREE>& st, const Lane<S>
 // ------------------------------------------------------------------ kernels
 
 template <typename S, bool FREE, bool ETI, bool CHAIN>
-__global__ __launch_bounds__(64) void k_aba(AbaArgs<S> A) {
-  __shared__ S xb[XB * kWave];
-  const Lane<S> l = load_lane(A.P);
-  const int maxd = A.P.wmaxd[blockIdx.x];
+__global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A) {
+  S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
+  const int wb = wave_batch();
+  const Lane<S> l = load_lane(A.P, wb);
+  const int maxd = A.P.wmaxd[wb];
   // every lane slot holds valid constants, so load them unconditionally
   // (keeps the compile-time axis and frame constants visible to folding)
   const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
@@ -478,10 +492,11 @@ __global__ __launch_bounds__(64) void k_aba(AbaArgs<S> A) {
 // K-th step; 2: store every step's initial state and intermediates
 // (store-all).  With a trajectory buffer, also write x^{t+1} for every step.
 template <typename S, bool FREE, bool ETI, bool CHAIN, int MODE>
-__global__ __launch_bounds__(64) void k_forward(FwdArgs<S> A) {
-  __shared__ S xb[XB * kWave];
-  const Lane<S> l = load_lane(A.P);
-  const int maxd = A.P.wmaxd[blockIdx.x];
+__global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S> A) {
+  S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
+  const int wb = wave_batch();
+  const Lane<S> l = load_lane(A.P, wb);
+  const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
   const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
@@ -675,10 +690,11 @@ __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, 
 // the scratch buffer first.  The next state and control are fetched one
 // step ahead.
 template <typename S, bool FREE, bool ETI, bool CHAIN>
-__global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
-  __shared__ S xb[XB * kWave];
-  const Lane<S> l = load_lane(A.P);
-  const int maxd = A.P.wmaxd[blockIdx.x];
+__global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<S> A) {
+  S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
+  const int wb = wave_batch();
+  const Lane<S> l = load_lane(A.P, wb);
+  const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
   const bool act = l.active();
@@ -774,13 +790,22 @@ __global__ __launch_bounds__(64) void k_backward(BwdArgs<S> A) {
 // reverses step T-k from buffer (k-1)%2; one workgroup barrier ends every
 // phase (both waves execute exactly T+1 of them).
 template <typename S, bool FREE, bool ETI, bool CHAIN>
-__global__ __launch_bounds__(128) void k_backward_pipe(BwdArgs<S> A) {
+__host__ __device__ constexpr size_t pipe_lds_per_pair() {
   constexpr int TW = kTapeFields + (FREE ? 13 : 2);  // tape + state per lane
-  __shared__ S xbs[2][XB * kWave];
-  __shared__ S tbuf[2][TW * kWave];
-  const int wid = threadIdx.x / kWave;
-  const Lane<S> l = load_lane(A.P);
-  const int maxd = A.P.wmaxd[blockIdx.x];
+  return (size_t)((CHAIN ? 0 : 2 * XB) + 2 * TW) * kWave * sizeof(S);
+}
+
+template <typename S, bool FREE, bool ETI, bool CHAIN>
+__global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe(BwdArgs<S> A) {
+  constexpr int TW = kTapeFields + (FREE ? 13 : 2);
+  const int pair = threadIdx.x / (2 * kWave);
+  const int wid = (threadIdx.x / kWave) & 1;
+  S* const base = lds<S>() + pair * (pipe_lds_per_pair<S, FREE, ETI, CHAIN>() / sizeof(S));
+  S* const xb = CHAIN ? nullptr : base + wid * (XB * kWave);
+  S* const tbuf[2] = {base + (CHAIN ? 0 : 2 * XB * kWave), base + (CHAIN ? 0 : 2 * XB * kWave) + TW * kWave};
+  const int wb = blockIdx.x * (blockDim.x / (2 * kWave)) + pair;
+  const Lane<S> l = load_lane(A.P, wb);
+  const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
   const bool act = l.active();
@@ -788,7 +813,6 @@ __global__ __launch_bounds__(128) void k_backward_pipe(BwdArgs<S> A) {
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
   const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
-  S* xb = xbs[wid];
   if (wid == 0) {
     State<S, FREE> nxt = {};
     S tau_nxt = S(0);
@@ -875,46 +899,78 @@ void dispatch(const Shape& sh, F&& f) {
   }
 }
 
+// Largest dynamic LDS one workgroup may take on the current device.
+size_t lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    return 64 * 1024;
+  return (size_t)v;
+}
+
+// waves per block of the single-wave kernels, reduced until the exchange
+// buffers fit (the wave count is a multiple of every power of two up to
+// kMaxWavesPerBlock)
+template <typename S, bool C>
+int single_wpb(const Tiling& tl, int nwaves, size_t& lds) {
+  int w = tl.waves_per_block;
+  if (w != 1 && w != 2 && w != 4) w = 1;
+  const size_t per = C ? 0 : (size_t)XB * kWave * sizeof(S);
+  while (w > 1 && (per * w > lds_limit() || nwaves % w != 0)) w /= 2;
+  lds = per * w;
+  return w;
+}
+
 template <typename S>
-hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, hipStream_t st) {
+hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
   dispatch(sh, [&]<bool F, bool E, bool C>() {
-    hipLaunchKernelGGL((k_aba<S, F, E, C>), dim3(a.P.nwaves), dim3(kWave), 0, st, a);
+    size_t lds = 0;
+    const int w = single_wpb<S, C>(tl, a.P.nwaves, lds);
+    hipLaunchKernelGGL((k_aba<S, F, E, C>), dim3(a.P.nwaves / w), dim3(kWave * w), lds, st, a);
   });
   return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_forward(const FwdArgs<S>& a, const Shape& sh, hipStream_t st) {
+hipError_t launch_forward(const FwdArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
   const int mode = (a.ck == nullptr) ? 0 : (a.K == 0) ? 2 : 1;
   dispatch(sh, [&]<bool F, bool E, bool C>() {
-    const dim3 grid(a.P.nwaves), block(kWave);
-    if (mode == 0) hipLaunchKernelGGL((k_forward<S, F, E, C, 0>), grid, block, 0, st, a);
-    else if (mode == 1) hipLaunchKernelGGL((k_forward<S, F, E, C, 1>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_forward<S, F, E, C, 2>), grid, block, 0, st, a);
+    size_t lds = 0;
+    const int w = single_wpb<S, C>(tl, a.P.nwaves, lds);
+    const dim3 grid(a.P.nwaves / w), block(kWave * w);
+    if (mode == 0) hipLaunchKernelGGL((k_forward<S, F, E, C, 0>), grid, block, lds, st, a);
+    else if (mode == 1) hipLaunchKernelGGL((k_forward<S, F, E, C, 1>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((k_forward<S, F, E, C, 2>), grid, block, lds, st, a);
   });
   return hipGetLastError();
 }
 
 template <typename S>
-hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, hipStream_t st) {
+hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
   dispatch(sh, [&]<bool F, bool E, bool C>() {
-    const dim3 grid(a.P.nwaves);
-    if (a.K == 1)
-      hipLaunchKernelGGL((k_backward_pipe<S, F, E, C>), grid, dim3(2 * kWave), 0, st, a);
-    else
-      hipLaunchKernelGGL((k_backward<S, F, E, C>), grid, dim3(kWave), 0, st, a);
+    if (a.K == 1 && tl.pipelined) {
+      const size_t per = pipe_lds_per_pair<S, F, E, C>();
+      int p = tl.pairs_per_block == 2 ? 2 : 1;
+      while (p > 1 && (per * p > lds_limit() || a.P.nwaves % p != 0)) p /= 2;
+      hipLaunchKernelGGL((k_backward_pipe<S, F, E, C>), dim3(a.P.nwaves / p), dim3(2 * kWave * p), per * p, st,
+                         a);
+    } else {
+      size_t lds = 0;
+      const int w = single_wpb<S, C>(tl, a.P.nwaves, lds);
+      hipLaunchKernelGGL((k_backward<S, F, E, C>), dim3(a.P.nwaves / w), dim3(kWave * w), lds, st, a);
+    }
   });
   return hipGetLastError();
 }
 
-template hipError_t launch_aba<float>(const AbaArgs<float>&, const Shape&, hipStream_t);
-template hipError_t launch_aba<double>(const AbaArgs<double>&, const Shape&, hipStream_t);
-template hipError_t launch_forward<float>(const FwdArgs<float>&, const Shape&, hipStream_t);
-template hipError_t launch_forward<double>(const FwdArgs<double>&, const Shape&, hipStream_t);
-template hipError_t launch_backward<float>(const BwdArgs<float>&, const Shape&, hipStream_t);
-template hipError_t launch_backward<double>(const BwdArgs<double>&, const Shape&, hipStream_t);
+template hipError_t launch_aba<float>(const AbaArgs<float>&, const Shape&, const Tiling&, hipStream_t);
+template hipError_t launch_aba<double>(const AbaArgs<double>&, const Shape&, const Tiling&, hipStream_t);
+template hipError_t launch_forward<float>(const FwdArgs<float>&, const Shape&, const Tiling&, hipStream_t);
+template hipError_t launch_forward<double>(const FwdArgs<double>&, const Shape&, const Tiling&, hipStream_t);
+template hipError_t launch_backward<float>(const BwdArgs<float>&, const Shape&, const Tiling&, hipStream_t);
+template hipError_t launch_backward<double>(const BwdArgs<double>&, const Shape&, const Tiling&, hipStream_t);
 
 }  // namespace aba

@@ -35,6 +35,7 @@ struct sim_handle {
   bool has_free = false;
   bool eti = false;  // every revolute joint frame is the identity after canonicalisation
   bool chain = false;  // every system is a fixed-base serial chain
+  aba::Tiling tiling;  // launch geometry
   double g[3] = {0, 0, 0};
   int32_t* d_ci = nullptr;
   void* d_cf = nullptr;
@@ -44,6 +45,26 @@ struct sim_handle {
 };
 
 namespace {
+
+// Launch geometry before any tuning, from occupancy alone.  While the
+// producer/consumer pairs of the pipelined adjoint fit one wavefront per
+// SIMD, the adjoint is pipelined with two pairs per workgroup (a workgroup
+// spreads its wavefronts over the CU's SIMDs, while separate one-pair
+// workgroups on one CU may share SIMDs); beyond that the pipelining only
+// oversubscribes the SIMDs and one wavefront per step is used.
+aba::Tiling default_tiling(int nwaves) {
+  aba::Tiling t;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  const int simds = 4 * cus;
+  t.waves_per_block = 4;
+  t.pipelined = 2 * nwaves <= simds;
+  t.pairs_per_block = 2;
+  return t;
+}
 
 aba::Shape shape(const sim_handle* h) {
   aba::Shape sh;
@@ -289,6 +310,11 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
     wave_used[w] += n;
     wave_depth[w] = std::max(wave_depth[w], sys_depth[s]);
   }
+  // pad with empty wavefronts so that every launch geometry divides the count
+  while (wave_used.size() % aba::kMaxWavesPerBlock != 0) {
+    wave_used.push_back(0);
+    wave_depth.push_back(0);
+  }
   h->nwaves = (int)wave_used.size();
   h->nslots = h->nwaves * aba::kWave;
   h->max_depth = 0;
@@ -402,6 +428,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
     if (ci[(size_t)aba::CI_JTYPE * NS + slot] >= 0 && p >= 0 && p != slot % aba::kWave - 1) chain = false;
   }
   h->chain = chain;
+  h->tiling = default_tiling(h->nwaves);
   std::vector<int32_t> wmaxd(wave_depth.begin(), wave_depth.end());
   const int rc = (dtype == SIM_F64) ? upload<double>(h, ci, cf, wmaxd) : upload<float>(h, ci, cf, wmaxd);
   if (rc != SIM_OK) {
@@ -433,6 +460,26 @@ int sim_get_info(sim_t h, sim_info_t* o) {
   o->frames_identity = h->eti ? 1 : 0;
   o->chain = h->chain ? 1 : 0;
   o->dtype = h->dtype;
+  return SIM_OK;
+}
+
+int sim_get_tiling(sim_t h, sim_tiling_t* t) {
+  if (!h || !t) return fail(SIM_ERR_INVALID_ARG, "sim_get_tiling: null argument");
+  t->waves_per_block = h->tiling.waves_per_block;
+  t->pairs_per_block = h->tiling.pairs_per_block;
+  t->pipelined = h->tiling.pipelined ? 1 : 0;
+  return SIM_OK;
+}
+
+int sim_set_tiling(sim_t h, const sim_tiling_t* t) {
+  if (!h || !t) return fail(SIM_ERR_INVALID_ARG, "sim_set_tiling: null argument");
+  const int w = t->waves_per_block, p = t->pairs_per_block;
+  if ((w != 1 && w != 2 && w != 4) || (p != 1 && p != 2) || (t->pipelined != 0 && t->pipelined != 1))
+    return fail(SIM_ERR_INVALID_ARG,
+                "sim_set_tiling: waves_per_block must be 1, 2 or 4, pairs_per_block 1 or 2, pipelined 0 or 1");
+  h->tiling.waves_per_block = w;
+  h->tiling.pairs_per_block = p;
+  h->tiling.pipelined = t->pipelined != 0;
   return SIM_OK;
 }
 
@@ -479,7 +526,7 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
     a.qdT = (double*)qdT;
     a.traj = (double*)traj;
     a.ck = (double*)workspace;
-    e = aba::launch_forward(a, shape(h), (hipStream_t)stream);
+    e = aba::launch_forward(a, shape(h), h->tiling, (hipStream_t)stream);
   } else {
     aba::FwdArgs<float> a;
     a.P = packed<float>(h);
@@ -493,7 +540,7 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
     a.qdT = (float*)qdT;
     a.traj = (float*)traj;
     a.ck = (float*)workspace;
-    e = aba::launch_forward(a, shape(h), (hipStream_t)stream);
+    e = aba::launch_forward(a, shape(h), h->tiling, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_forward: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
@@ -529,7 +576,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (double*)gtau;
     a.ck = (const double*)workspace;
     a.scratch = (K > 1) ? (double*)((char*)workspace + ck) : nullptr;
-    e = aba::launch_backward(a, shape(h), (hipStream_t)stream);
+    e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   } else {
     aba::BwdArgs<float> a;
     a.P = packed<float>(h);
@@ -545,7 +592,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (float*)gtau;
     a.ck = (const float*)workspace;
     a.scratch = (K > 1) ? (float*)((char*)workspace + ck) : nullptr;
-    e = aba::launch_backward(a, shape(h), (hipStream_t)stream);
+    e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_backward: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
@@ -562,7 +609,7 @@ int sim_aba(sim_t h, const void* q, const void* qd, const void* tau, void* qdd, 
     a.qd = (const double*)qd;
     a.tau = (const double*)tau;
     a.qdd = (double*)qdd;
-    e = aba::launch_aba(a, shape(h), (hipStream_t)stream);
+    e = aba::launch_aba(a, shape(h), h->tiling, (hipStream_t)stream);
   } else {
     aba::AbaArgs<float> a;
     a.P = packed<float>(h);
@@ -570,9 +617,131 @@ int sim_aba(sim_t h, const void* q, const void* qd, const void* tau, void* qdd, 
     a.qd = (const float*)qd;
     a.tau = (const float*)tau;
     a.qdd = (float*)qdd;
-    e = aba::launch_aba(a, shape(h), (hipStream_t)stream);
+    e = aba::launch_aba(a, shape(h), h->tiling, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_aba: launch failed: ") + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+int sim_autotune(sim_t h, int K, int T_probe, void* stream, sim_tiling_t* chosen, double* ms_per_step) {
+  g_err.clear();
+  if (!h) return fail(SIM_ERR_INVALID_ARG, "sim_autotune: null handle");
+  if (K < 0 || T_probe < 1 || T_probe > 100000)
+    return fail(SIM_ERR_INVALID_ARG, "sim_autotune: need K >= 0 and 1 <= T_probe <= 100000");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t es = elem(h);
+  // store-all probes are capped at 2 GiB of workspace
+  int T = T_probe;
+  if (K == 0) {
+    size_t per = 0;
+    sim_workspace_bytes(h, 1, 0, &per);
+    while (T > 8 && (size_t)T * per > (size_t(2) << 30)) T /= 2;
+  }
+  size_t ws_bytes = 0;
+  sim_workspace_bytes(h, T, K, &ws_bytes);
+  const size_t nq = h->nq, nv = h->nv, nu = h->nu;
+  // probe rollout: zero state (unit quaternions on free roots), zero
+  // torques, zero seeds; the kernels' run time does not depend on values
+  std::vector<double> q0h(nq, 0.0);
+  for (size_t L = 0, qi = 0; L < h->jtype.size(); ++L) {
+    if (h->jtype[L] == SIM_JOINT_FREE) {
+      q0h[qi + 6] = 1.0;
+      qi += 7;
+    } else {
+      qi += 1;
+    }
+  }
+  std::vector<unsigned char> q0b(nq * es);
+  for (size_t i = 0; i < nq; ++i) {
+    if (es == sizeof(double)) {
+      std::memcpy(q0b.data() + i * es, &q0h[i], es);
+    } else {
+      const float f = (float)q0h[i];
+      std::memcpy(q0b.data() + i * es, &f, es);
+    }
+  }
+  const size_t sizes[] = {nq, nv, nu * T, nq, nv, nq, nv, nq, nv, nu * T};
+  void* buf[10] = {};
+  void* ws = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  const aba::Tiling saved = h->tiling;
+  auto cleanup = [&]() {
+    for (void* b : buf) if (b) (void)hipFree(b);
+    if (ws) (void)hipFree(ws);
+    for (hipEvent_t x : ev) if (x) (void)hipEventDestroy(x);
+  };
+  bool ok = hipEventCreate(&ev[0]) == hipSuccess && hipEventCreate(&ev[1]) == hipSuccess;
+  for (int i = 0; ok && i < 10; ++i) ok = hipMalloc(&buf[i], std::max<size_t>(sizes[i], 1) * es) == hipSuccess;
+  ok = ok && hipMalloc(&ws, std::max<size_t>(ws_bytes, 1)) == hipSuccess;
+  for (int i = 0; ok && i < 10; ++i) ok = hipMemsetAsync(buf[i], 0, std::max<size_t>(sizes[i], 1) * es, st) == hipSuccess;
+  ok = ok && (nq == 0 || hipMemcpyAsync(buf[0], q0b.data(), nq * es, hipMemcpyHostToDevice, st) == hipSuccess);
+  ok = ok && hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) {
+    cleanup();
+    return fail(SIM_ERR_HIP, "sim_autotune: could not allocate or initialise the probe buffers");
+  }
+  void *q0 = buf[0], *qd0 = buf[1], *tau = buf[2], *qT = buf[3], *qdT = buf[4], *gqT = buf[5], *gqdT = buf[6],
+       *gq0 = buf[7], *gqd0 = buf[8], *gtau = buf[9];
+  const double dt = 1e-3;
+  // best of three timed launches after one untimed
+  auto timed = [&](auto&& launch, double& best) -> bool {
+    if (launch() != SIM_OK) return false;
+    best = 1e300;
+    for (int r = 0; r < 3; ++r) {
+      if (hipEventRecord(ev[0], st) != hipSuccess || launch() != SIM_OK || hipEventRecord(ev[1], st) != hipSuccess ||
+          hipEventSynchronize(ev[1]) != hipSuccess)
+        return false;
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) return false;
+      best = std::min(best, (double)ms);
+    }
+    return true;
+  };
+  auto fwd = [&]() { return sim_forward(h, q0, qd0, tau, dt, T, K, qT, qdT, nullptr, ws, ws_bytes, stream); };
+  auto bwd = [&]() {
+    return sim_backward(h, tau, dt, T, K, gqT, gqdT, nullptr, gq0, gqd0, gtau, ws, ws_bytes, stream);
+  };
+  const int wpbs[3] = {1, 2, 4};
+  double F[3], Bnp[3], Bp[2] = {1e300, 1e300};
+  ok = true;
+  for (int i = 0; ok && i < 3; ++i) {
+    h->tiling.waves_per_block = wpbs[i];
+    h->tiling.pipelined = false;
+    ok = timed(fwd, F[i]) && timed(bwd, Bnp[i]);
+  }
+  for (int p = 1; ok && K == 1 && p <= 2; ++p) {
+    h->tiling.pipelined = true;
+    h->tiling.pairs_per_block = p;
+    ok = timed(bwd, Bp[p - 1]);
+  }
+  if (!ok) {
+    h->tiling = saved;
+    const std::string msg = g_err.empty() ? std::string("HIP call failed") : g_err;
+    cleanup();
+    return fail(SIM_ERR_HIP, "sim_autotune: probe failed: " + msg);
+  }
+  // forward and non-pipelined adjoint share waves_per_block
+  double best = 1e300;
+  aba::Tiling win;
+  for (int i = 0; i < 3; ++i) {
+    for (int c = 0; c < 3; ++c) {  // c = 0: one-wave adjoint; 1, 2: pipelined with c pairs
+      const double b = (c == 0) ? Bnp[i] : Bp[c - 1];
+      if (F[i] + b < best) {
+        best = F[i] + b;
+        win.waves_per_block = wpbs[i];
+        win.pipelined = c > 0;
+        win.pairs_per_block = c > 0 ? c : saved.pairs_per_block;
+      }
+    }
+  }
+  h->tiling = win;
+  cleanup();
+  if (chosen) {
+    chosen->waves_per_block = win.waves_per_block;
+    chosen->pairs_per_block = win.pairs_per_block;
+    chosen->pipelined = win.pipelined ? 1 : 0;
+  }
+  if (ms_per_step) *ms_per_step = best / T;
   return SIM_OK;
 }
 

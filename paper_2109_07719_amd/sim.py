@@ -98,6 +98,28 @@ class Sim:
             raise ValueError(f"{name} has {x.numel()} elements, expected {n}")
         return x
 
+    @property
+    def tiling(self) -> dict:
+        """Launch geometry: waves_per_block, pairs_per_block, pipelined."""
+        t = N.SimTiling()
+        N.check(N.lib().sim_get_tiling(self._h, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in N.SimTiling._fields_}
+
+    def set_tiling(self, waves_per_block: int = 1, pairs_per_block: int = 1, pipelined: bool = True) -> None:
+        t = N.SimTiling(int(waves_per_block), int(pairs_per_block), int(bool(pipelined)))
+        N.check(N.lib().sim_set_tiling(self._h, ctypes.byref(t)))
+
+    def autotune(self, K: int = 1, T_probe: int = 200) -> dict:
+        """Time every launch geometry on probe rollouts and keep the fastest
+        (sim_autotune); returns the chosen tiling and its ms per probe step."""
+        t, ms = N.SimTiling(), ctypes.c_double()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        N.check(N.lib().sim_autotune(self._h, int(K), int(T_probe), ctypes.c_void_p(stream), ctypes.byref(t),
+                                     ctypes.byref(ms)))
+        out = {f: getattr(t, f) for f, _ in N.SimTiling._fields_}
+        out["ms_per_probe_step"] = ms.value
+        return out
+
     def workspace_bytes(self, T: int, K: int = 1) -> int:
         b = ctypes.c_size_t()
         N.check(N.lib().sim_workspace_bytes(self._h, int(T), int(K), ctypes.byref(b)))

@@ -406,3 +406,66 @@ def test_trajectory_optimisation_gradients_match_fp64_oracle():
         opt.opt.step()
     print("loss", ["%.3g" % x for x in losses])
     assert losses[-1] < losses[0]
+
+
+@pytest.mark.parametrize("kind", ["mixed", "chains"])
+def test_launch_geometry_changes_no_arithmetic(kind):
+    """Every launch geometry (wavefronts per workgroup, producer/consumer
+    pairs per workgroup, pipelined or one-wave adjoint) gives bitwise the
+    same rollout, gradients and forward dynamics."""
+    if kind == "mixed":
+        b = _mixed_batch(60)
+    else:
+        b = synth.round_to_f32(synth.make_batch([synth.chain_system(n, 6000 + n, 60) for n in (1, 3, 7, 7, 9, 30)],
+                                                1e-3))
+    sim = _sim(b)
+    q, qd, tau1 = _random_state(b, np.random.default_rng(9))
+    results = {}
+    for tl in [(1, 1, 1), (2, 1, 1), (4, 2, 1), (4, 1, 0), (2, 2, 1)]:
+        sim.set_tiling(*tl)
+        assert sim.tiling == dict(zip(("waves_per_block", "pairs_per_block", "pipelined"), tl))
+        out = []
+        for K in (1, 3):
+            q0, qd0, tau, ws, qT, qdT, _ = _rollout(sim, b, K=K)
+            g = sim.backward(tau, b.dt, K, ws, 2 * qT, torch.zeros_like(qdT))
+            out += [x.cpu().numpy() for x in (qT, qdT, *g)]
+        out.append(sim.aba(_t(q), _t(qd), _t(tau1)).cpu().numpy())
+        results[tl] = out
+    ref = results[(1, 1, 1)]
+    for tl, out in results.items():
+        for j, (a, c) in enumerate(zip(ref, out)):
+            if tl[2] == 0 and j < 5:
+                # K = 1 without the pipelined kernel: the reverse passes read
+                # the recomputed intermediates from registers instead of the
+                # LDS tape, so the compiler may contract differently
+                assert rel(c, a) < 1e-5, tl
+            else:
+                assert np.array_equal(a, c), tl
+    with pytest.raises(Exception):
+        sim.set_tiling(3, 1, 1)
+    with pytest.raises(Exception):
+        sim.set_tiling(1, 4, 1)
+
+
+@pytest.mark.parametrize("K", [1, 0, 5])
+def test_autotune_keeps_a_valid_geometry_and_the_results(K):
+    b = _mixed_batch(40)
+    sim = _sim(b)
+    out0 = None
+    for phase in range(2):
+        if phase == 1:
+            t = sim.autotune(K=K, T_probe=30)
+            assert t["waves_per_block"] in (1, 2, 4) and t["pairs_per_block"] in (1, 2) and t["pipelined"] in (0, 1)
+            assert t["ms_per_probe_step"] > 0
+            assert {k: t[k] for k in sim.tiling} == sim.tiling
+        q0, qd0, tau, ws, qT, qdT, _ = _rollout(sim, b, K=K)
+        g = sim.backward(tau, b.dt, K, ws, 2 * qT, torch.zeros_like(qdT))
+        out = [x.cpu().numpy() for x in (qT, qdT, *g)]
+        if out0 is None:
+            out0 = out
+    for a, c in zip(out0, out):
+        assert rel(c, a) < 1e-5
+    with pytest.raises(Exception):
+        sim.autotune(K=-1)
+    with pytest.raises(Exception):
+        sim.autotune(K=1, T_probe=0)
