@@ -411,9 +411,10 @@ def main():
     fwd_flops = sim.flops(1) * T
     bwd_s = float(np.mean(bwd_ms)) * 1e-3
     achieved = bwd_flops / bwd_s / 1e12
-    roofline = {"bound": "alu", "kernel": "k_backward", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+    bwd_kernel = "k_backward_pipe" if (K == 1 and sim.tiling["pipelined"]) else "k_backward"
+    roofline = {"bound": "alu", "kernel": bwd_kernel, "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
-                "traffic": traffic_entry("k_backward", args.workload),
+                "traffic": traffic_entry(bwd_kernel, args.workload),
                 "flops_per_launch": bwd_flops, "kernel_ms": float(np.mean(bwd_ms)),
                 "fwd_kernel_ms": float(np.mean(fwd_ms)),
                 "fwd_achieved_tflops": fwd_flops / (float(np.mean(fwd_ms)) * 1e-3) / 1e12}
