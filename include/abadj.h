@@ -134,6 +134,18 @@ void sim_destroy(sim_t h);
 
 int sim_get_info(sim_t h, sim_info_t *out);
 
+/* Health of the results: *nonfinite_count receives the number of
+ * non-finite numbers (NaN or infinity) that the kernels enqueued on this
+ * handle wrote to their outputs (qT, qdT, traj, qdd, gq0, gqd0, gtau) since
+ * the previous sim_status call, and the counter is reset.  A diverging
+ * rollout propagates NaN to its final state, so a zero count after
+ * sim_forward + sim_backward means every output is finite.  Synchronises
+ * `stream` (the stream the kernels were enqueued on); not for use during
+ * stream capture.  Kernels of one handle running concurrently on several
+ * streams share the counter.  Errors: SIM_ERR_INVALID_ARG (null handle or
+ * pointer), SIM_ERR_HIP. */
+int sim_status(sim_t h, void *stream, int *nonfinite_count);
+
 /* Launch geometry of the handle's kernels (the autotuner's knobs; they
  * change no arithmetic, only how wavefronts are grouped into workgroups and
  * so where they run and how much LDS a workgroup takes).

@@ -23,7 +23,7 @@ SIM_JOINT_REVOLUTE = 0
 SIM_JOINT_FREE = 1
 SIM_MAX_LINKS = 64
 
-EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_get_tiling", "sim_set_tiling", "sim_autotune",
+EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_status", "sim_get_tiling", "sim_set_tiling", "sim_autotune",
             "sim_workspace_bytes",
             "sim_forward",
             "sim_backward", "sim_aba", "sim_flops", "sim_last_error")
@@ -79,6 +79,8 @@ def lib():
         L.sim_get_tiling.restype = I
         L.sim_set_tiling.argtypes = [P, ctypes.POINTER(SimTiling)]
         L.sim_set_tiling.restype = I
+        L.sim_status.argtypes = [P, P, ctypes.POINTER(I)]
+        L.sim_status.restype = I
         L.sim_autotune.argtypes = [P, I, I, P, ctypes.POINTER(SimTiling), ctypes.POINTER(D)]
         L.sim_autotune.restype = I
         L.sim_workspace_bytes.argtypes = [P, I, I, ctypes.POINTER(Z)]

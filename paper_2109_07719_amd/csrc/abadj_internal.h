@@ -32,6 +32,7 @@ struct Packed {
   int nfree;             // number of free-floating roots in the batch
   S g[3];                // gravity
   int nq, nv, nu;        // totals over the batch
+  int* status;           // device counter of non-finite numbers written to outputs
 };
 
 template <typename S>

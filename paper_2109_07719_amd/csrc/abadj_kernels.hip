@@ -239,6 +239,43 @@ __device__ __forceinline__ void store_state(const State<S, FREE>& s, const Lane<
     }
   }
 }
+// Non-finite outputs are counted with integer tests on the bit pattern.
+// The device code is built with finite-math folding, under which the
+// compiler may assume the exponent field is never all ones and remove even
+// an integer test, so the bits first pass through a register move the
+// compiler cannot see into.  Each kernel adds its count to the handle's
+// counter once at the end.
+__device__ __forceinline__ unsigned opaque_u32(unsigned u) {
+  unsigned r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(u));
+  return r;
+}
+__device__ __forceinline__ int nonfinite(float x) {
+  return (opaque_u32(__float_as_uint(x)) & 0x7f800000u) == 0x7f800000u;
+}
+__device__ __forceinline__ int nonfinite(double x) {
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(x) >> 32);
+  return (opaque_u32(hi) & 0x7ff00000u) == 0x7ff00000u;
+}
+template <typename S, bool FREE>
+__device__ __forceinline__ int nonfinite_state(const State<S, FREE>& s, const Lane<S>& l) {
+  int n = 0;
+  if (l.revolute()) {
+    n = nonfinite(s.q[0]) + nonfinite(s.qd[0]);
+  } else if constexpr (FREE) {
+    if (l.jtype == 1) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) n += nonfinite(s.q[k]);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) n += nonfinite(s.qd[k]);
+    }
+  }
+  return n;
+}
+__device__ __forceinline__ void report_nonfinite(int* status, int n) {
+  if (n > 0) atomicAdd(status, n);
+}
+
 // stored state records (see state_record): [2][nslots] then [11][nfree]
 template <typename S, bool FREE>
 __device__ __forceinline__ void put_slot(const State<S, FREE>& s, S* base, int nslots, int nfree, int slot,
@@ -477,15 +514,21 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A)
   }
   Step<S> o;
   aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
+  int nonfin = 0;
   if (l.revolute()) {
     A.qdd[l.vidx] = o.t.qdd;
+    nonfin = nonfinite(o.t.qdd);
   } else if constexpr (FREE) {
     if (l.jtype == 1) {
       const S a[6] = {o.abase.a.x, o.abase.a.y, o.abase.a.z, o.abase.l.x, o.abase.l.y, o.abase.l.z};
 #pragma unroll
-      for (int k = 0; k < 6; ++k) A.qdd[l.vidx + k] = a[k];
+      for (int k = 0; k < 6; ++k) {
+        A.qdd[l.vidx + k] = a[k];
+        nonfin += nonfinite(a[k]);
+      }
     }
   }
+  report_nonfinite(A.P.status, nonfin);
 }
 
 // Forward rollout.  MODE 0: plain; 1: store the initial state of every
@@ -506,6 +549,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
   S tau_next = (has_tau && A.T > 0) ? A.tau[l.uidx] : S(0);
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
+  int nonfin = 0;  // non-finite outputs
   for (int t = 0; t < A.T; ++t) {
     if constexpr (MODE == 1) {
       if (l.active() && (t % A.K) == 0) put_slot(st, A.ck + (size_t)(t / A.K) * RW, ns, nf, l.slot, l.fidx);
@@ -526,10 +570,15 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
       if (l.active()) {
         S* row = A.traj + (size_t)t * (A.P.nq + A.P.nv);
         store_state(st, l, row, row + A.P.nq);
+        nonfin += nonfinite_state(st, l);
       }
     }
   }
-  if (l.active()) store_state(st, l, A.qT, A.qdT);
+  if (l.active()) {
+    store_state(st, l, A.qT, A.qdT);
+    nonfin += nonfinite_state(st, l);
+  }
+  report_nonfinite(A.P.status, nonfin);
 }
 
 // One reverse step: recompute the ABA intermediates of step t from its
@@ -539,7 +588,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
 template <typename S, bool FREE, bool CHAIN>
 __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
                                             S* xb, const State<S, FREE>& st, const Step<S>& o, int t,
-                                            State<S, FREE>& xb1) {
+                                            State<S, FREE>& xb1, int& nonfin) {
   const bool act = l.active();
   const bool rev = l.revolute();
   const V3<S> g = v3<S>(A.P.g[0], A.P.g[1], A.P.g[2]);
@@ -658,6 +707,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
     xb1.q[0] = acc_q + b.q;
     xb1.qd[0] = acc_qd + b.qd;
     A.gtau[(size_t)t * A.P.nu + l.uidx] = taub;
+    nonfin += nonfinite(taub);
   } else if constexpr (FREE) {
     if (l.jtype == 1) {
       xb1.q[0] = pb.x; xb1.q[1] = pb.y; xb1.q[2] = pb.z;
@@ -679,10 +729,11 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
 
 template <typename S, bool FREE, bool CHAIN>
 __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
-                                         S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1) {
+                                         S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1,
+                                         int& nonfin) {
   Step<S> o;
   aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
-  bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1);
+  bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin);
 }
 
 // Backward (adjoint) rollout, reverse time.  K == 1 reloads every step's
@@ -702,6 +753,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
   const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
+  int nonfin = 0;  // non-finite outputs
   State<S, FREE> xb1 = {};
   if (act) {
     load_state(xb1, l, A.gqT, A.gqdT);
@@ -725,7 +777,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
         get_slot(st, row, ns, nf, l.slot, l.fidx);
         get_tape(o, row + RW, ns, l.slot, L, st.qd[0], rev);
       }
-      bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1);
+      bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin);
     }
   } else if (A.K == 1) {
     State<S, FREE> nxt = {};
@@ -741,7 +793,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
         if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
         if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
       }
-      bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, st, tau, t, xb1);
+      bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, st, tau, t, xb1, nonfin);
     }
   } else {
     const int ncp = (A.T + A.K - 1) / A.K;
@@ -775,11 +827,15 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
           if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
-        bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, cur, tau, t, xb1);
+        bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, cur, tau, t, xb1, nonfin);
       }
     }
   }
-  if (act) store_state(xb1, l, A.gq0, A.gqd0);
+  if (act) {
+    store_state(xb1, l, A.gq0, A.gqd0);
+    nonfin += nonfinite_state(xb1, l);
+  }
+  report_nonfinite(A.P.status, nonfin);
 }
 
 // Pipelined adjoint for K == 1: two wavefronts per workgroup on the same
@@ -841,6 +897,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
       __syncthreads();
     }
   } else {
+    int nonfin = 0;  // non-finite outputs
     State<S, FREE> xb1 = {};
     if (act) {
       load_state(xb1, l, A.gqT, A.gqdT);
@@ -865,11 +922,15 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
         for (int j = 0; j < (FREE ? 6 : 1); ++j) st.qd[j] = tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane];
         Step<S> o;
         get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, L, st.qd[0], rev);
-        bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1);
+        bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin);
       }
       __syncthreads();
     }
-    if (act) store_state(xb1, l, A.gq0, A.gqd0);
+    if (act) {
+      store_state(xb1, l, A.gq0, A.gqd0);
+      nonfin += nonfinite_state(xb1, l);
+    }
+    report_nonfinite(A.P.status, nonfin);
   }
 }
 

@@ -40,6 +40,7 @@ struct sim_handle {
   int32_t* d_ci = nullptr;
   void* d_cf = nullptr;
   int32_t* d_wmaxd = nullptr;
+  int* d_status = nullptr;  // non-finite outputs written since the last sim_status
   // host-side structure summary for operation counting
   std::vector<int32_t> jtype, parent, nchild;
 };
@@ -80,6 +81,7 @@ aba::Packed<S> packed(const sim_handle* h) {
   P.ci = h->d_ci;
   P.cf = static_cast<const S*>(h->d_cf);
   P.wmaxd = h->d_wmaxd;
+  P.status = h->d_status;
   P.nslots = h->nslots;
   P.nwaves = h->nwaves;
   P.nfree = h->nfree;
@@ -148,11 +150,14 @@ int upload(sim_handle* h, const std::vector<int32_t>& ci, const std::vector<doub
   for (size_t i = 0; i < cf.size(); ++i) cfs[i] = static_cast<S>(cf[i]);
   if (hipMalloc(&h->d_ci, ci.size() * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&h->d_cf, cfs.size() * sizeof(S)) != hipSuccess ||
-      hipMalloc(&h->d_wmaxd, wmaxd.size() * sizeof(int32_t)) != hipSuccess)
+      hipMalloc(&h->d_wmaxd, wmaxd.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&h->d_status, sizeof(int)) != hipSuccess)
     return fail(SIM_ERR_HIP, "sim_create: device allocation failed");
+  const int zero = 0;
   if (hipMemcpy(h->d_ci, ci.data(), ci.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->d_cf, cfs.data(), cfs.size() * sizeof(S), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(h->d_wmaxd, wmaxd.data(), wmaxd.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(h->d_wmaxd, wmaxd.data(), wmaxd.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->d_status, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
     return fail(SIM_ERR_HIP, "sim_create: upload failed");
   return SIM_OK;
 }
@@ -162,6 +167,8 @@ void release(sim_handle* h) {
   if (h->d_ci) (void)hipFree(h->d_ci);
   if (h->d_cf) (void)hipFree(h->d_cf);
   if (h->d_wmaxd) (void)hipFree(h->d_wmaxd);
+  if (h->d_status) (void)hipFree(h->d_status);
+  h->d_status = nullptr;
   h->d_ci = nullptr;
   h->d_cf = nullptr;
   h->d_wmaxd = nullptr;
@@ -460,6 +467,18 @@ int sim_get_info(sim_t h, sim_info_t* o) {
   o->frames_identity = h->eti ? 1 : 0;
   o->chain = h->chain ? 1 : 0;
   o->dtype = h->dtype;
+  return SIM_OK;
+}
+
+int sim_status(sim_t h, void* stream, int* nonfinite_count) {
+  g_err.clear();
+  if (!h || !nonfinite_count) return fail(SIM_ERR_INVALID_ARG, "sim_status: null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int v = 0;
+  if (hipMemcpyAsync(&v, h->d_status, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess || hipMemsetAsync(h->d_status, 0, sizeof(int), st) != hipSuccess)
+    return fail(SIM_ERR_HIP, "sim_status: could not read the counter");
+  *nonfinite_count = v;
   return SIM_OK;
 }
 

@@ -98,6 +98,14 @@ class Sim:
             raise ValueError(f"{name} has {x.numel()} elements, expected {n}")
         return x
 
+    def status(self) -> int:
+        """Non-finite numbers written to outputs since the last call (resets
+        the counter; synchronises the current stream)."""
+        n = ctypes.c_int()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        N.check(N.lib().sim_status(self._h, ctypes.c_void_p(stream), ctypes.byref(n)))
+        return int(n.value)
+
     @property
     def tiling(self) -> dict:
         """Launch geometry: waves_per_block, pairs_per_block, pipelined."""

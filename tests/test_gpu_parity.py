@@ -469,3 +469,28 @@ def test_autotune_keeps_a_valid_geometry_and_the_results(K):
         sim.autotune(K=-1)
     with pytest.raises(Exception):
         sim.autotune(K=1, T_probe=0)
+
+
+def test_status_counts_nonfinite_outputs():
+    b = _mixed_batch(50)
+    sim = _sim(b)
+    assert sim.status() == 0
+    q0, qd0, tau, ws, qT, qdT, _ = _rollout(sim, b)
+    sim.backward(tau, b.dt, 1, ws, 2 * qT, torch.zeros_like(qdT))
+    assert sim.status() == 0
+    # a NaN torque at step 20 of one chain poisons that chain's final state
+    # and its gradients, and nothing else
+    tau_bad = tau.clone()
+    tau_bad[20, 0] = float("nan")
+    qT2, qdT2, _ = sim.forward(q0, qd0, tau_bad, b.dt, K=1, workspace=ws)
+    n_fwd = sim.status()
+    s0 = b.systems[0]
+    assert n_fwd == s0.nq + s0.nv
+    assert torch.isfinite(qT2[s0.nq:]).all() and torch.isfinite(qdT2[s0.nv:]).all()
+    sim.backward(tau_bad, b.dt, 1, ws, torch.zeros_like(qT2), torch.zeros_like(qdT2))
+    assert sim.status() > 0
+    assert sim.status() == 0
+    qd_bad = qd0.clone()
+    qd_bad[1] = float("inf")
+    sim.aba(q0, qd_bad, tau[0].contiguous())
+    assert sim.status() > 0

@@ -88,6 +88,12 @@ def test_null_arguments_are_rejected():
     assert L.sim_aba(None, None, None, None, None, None) == N.SIM_ERR_INVALID_ARG
     f = ctypes.c_double()
     assert L.sim_flops(None, 0, ctypes.byref(f)) == N.SIM_ERR_INVALID_ARG
+    n = ctypes.c_int()
+    assert L.sim_status(None, None, ctypes.byref(n)) == N.SIM_ERR_INVALID_ARG
+    t = N.SimTiling(1, 1, 1)
+    assert L.sim_get_tiling(None, ctypes.byref(t)) == N.SIM_ERR_INVALID_ARG
+    assert L.sim_set_tiling(None, ctypes.byref(t)) == N.SIM_ERR_INVALID_ARG
+    assert L.sim_autotune(None, 1, 10, None, None, None) == N.SIM_ERR_INVALID_ARG
     L.sim_destroy(None)
 
 
