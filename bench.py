@@ -84,8 +84,11 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
         r = O.rollout_grad(m, q0, qd0, tau, batch.dt, 2 * qT, np.zeros_like(qdT), K=1)
         return r, time.perf_counter() - t0
 
-    # calibrate on one system, then size the sample to ~sample_seconds of wall time
+    # calibrate on one system, then size the sample to ~sample_seconds of wall time; the second
+    # single-threaded run of system 0 gives the single-core figure
     _, t1 = one(0)
+    _, t1 = one(0)
+    single_core = batch.systems[0].nv * batch.T / t1
     per_round = max(t1, 1e-3)
     n_sample = int(max(threads, min(n, threads * max(1, int(sample_seconds / per_round)))))
     rng = np.random.default_rng(0)
@@ -130,7 +133,10 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
     base = {"value": dof_steps / wall, "unit": "DOF-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(idx)} of {n} systems, full {batch.T}-step forward+adjoint each "
                       f"(plain dense FP64 C oracle, K=1), {wall:.1f} s wall on {threads} threads, "
-                      f"host CPU: {cpu}"}
+                      f"host CPU: {cpu}",
+            "single_core_value": single_core,
+            "single_core_sample": f"system 0 ({batch.systems[0].nv} DOF), full {batch.T}-step forward+adjoint, "
+                                  f"one thread, {t1:.2f} s"}
     err = {"along_gpu_trajectory_max": max(e_along), "along_gpu_trajectory_median": float(np.median(e_along)),
            "along_gpu_trajectory_p99": float(np.percentile(e_along, 99)),
            "along_gpu_trajectory_frac_above_1e-3": float(np.mean(np.asarray(e_along) > 1e-3)),
@@ -420,11 +426,14 @@ def main():
                 "traffic": traffic_entry(bwd_kernel, args.workload),
                 "flops_per_launch": bwd_flops, "kernel_ms": float(np.mean(bwd_ms)),
                 "fwd_kernel_ms": float(np.mean(fwd_ms)),
-                "fwd_achieved_tflops": fwd_flops / (float(np.mean(fwd_ms)) * 1e-3) / 1e12}
+                "fwd_achieved_tflops": fwd_flops / (float(np.mean(fwd_ms)) * 1e-3) / 1e12,
+                "kernel_ms_median": float(np.median(bwd_ms)), "fwd_kernel_ms_median": float(np.median(fwd_ms))}
+    if roofline["traffic"] is not None:
+        roofline["hbm_gb_per_s"] = roofline["traffic"] / bwd_s / 1e9
 
     out = {"metric": "fwd+adjoint DOF-steps/sec (FP32, 1 GPU) vs plain fwd; grad rel err",
            "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "ms_per_step": ms_per_step, "ms_per_step_median": float(np.median(step_ms)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": WORKLOADS[args.workload], "systems": len(b.systems), "dof": b.total_dof,
                       "T": T, "dt": dt, "K": K, "lanes": sim.info["n_slots"], "waves": sim.info["n_waves"],
