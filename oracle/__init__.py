@@ -54,6 +54,11 @@ def _configure(L):
     L.orc_rollout_grad.restype = ctypes.c_int
     L.orc_adjoint_along.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P, P]
     L.orc_adjoint_along.restype = ctypes.c_int
+    L.orc_rollout_grad_params.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_int, P, P, P, P, P, P, P, P, P]
+    L.orc_rollout_grad_params.restype = ctypes.c_int
+    L.orc_adjoint_along_params.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P, P, P]
+    L.orc_adjoint_along_params.restype = ctypes.c_int
     return L
 
 
@@ -121,6 +126,7 @@ class Model:
         self.ref = ctypes.byref(self.c)
         L = lib()
         self.nq, self.nv, self.nu = L.orc_nq(self.ref), L.orc_nv(self.ref), L.orc_nu(self.ref)
+        self.n = int(self.parent.shape[0])
 
 
 def _f64(x, n=None):
@@ -213,6 +219,46 @@ def rollout_grad(m: Model, q0, qd0, tau, dt, gqT, gqdT, gtraj=None, K: int = 1):
     if rc != 0:
         raise RuntimeError("oracle rollout_grad failed")
     return gq0, gqd0, gtau, qT, qdT
+
+
+def rollout_grad_params(m: Model, q0, qd0, tau, dt, gqT, gqdT, gtraj=None, K: int = 1):
+    """As rollout_grad, plus the gradient with respect to every link's ten
+    inertial parameters (m, h = m c, I about the link origin: xx yy zz xy xz
+    yz; link frame), summed over the rollout.  Returns gq0, gqd0, gtau,
+    gparam [n, 10], qT, qdT."""
+    tau = _f64(tau)
+    T = int(tau.shape[0])
+    tau = np.ascontiguousarray(tau.reshape(T, m.nu))
+    q0, qd0 = _f64(q0, m.nq), _f64(qd0, m.nv)
+    gqT, gqdT = _f64(gqT, m.nq), _f64(gqdT, m.nv)
+    gtr = None if gtraj is None else np.ascontiguousarray(_f64(gtraj).reshape(T, m.nq + m.nv))
+    gq0, gqd0, gtau = np.zeros(m.nq), np.zeros(m.nv), np.zeros((T, m.nu))
+    gparam = np.zeros((m.n, 10))
+    qT, qdT = np.zeros(m.nq), np.zeros(m.nv)
+    rc = lib().orc_rollout_grad_params(m.ref, _p(q0), _p(qd0), _p(tau), float(dt), T, int(K),
+                                       _p(gqT), _p(gqdT), _p(gtr) if gtr is not None else None,
+                                       _p(gq0), _p(gqd0), _p(gtau), _p(gparam), _p(qT), _p(qdT))
+    if rc != 0:
+        raise RuntimeError("oracle rollout_grad_params failed")
+    return gq0, gqd0, gtau, gparam, qT, qdT
+
+
+def adjoint_along_params(m: Model, states, tau, dt, gqT, gqdT, gtraj=None):
+    """adjoint_along plus the inertial-parameter gradient [n, 10]."""
+    tau = _f64(tau)
+    T = int(tau.shape[0])
+    tau = np.ascontiguousarray(tau.reshape(T, m.nu))
+    st = np.ascontiguousarray(_f64(states).reshape(T, m.nq + m.nv))
+    gqT, gqdT = _f64(gqT, m.nq), _f64(gqdT, m.nv)
+    gtr = None if gtraj is None else np.ascontiguousarray(_f64(gtraj).reshape(T, m.nq + m.nv))
+    gq0, gqd0, gtau = np.zeros(m.nq), np.zeros(m.nv), np.zeros((T, m.nu))
+    gparam = np.zeros((m.n, 10))
+    rc = lib().orc_adjoint_along_params(m.ref, _p(st), _p(tau), float(dt), T, _p(gqT), _p(gqdT),
+                                        _p(gtr) if gtr is not None else None, _p(gq0), _p(gqd0),
+                                        _p(gtau), _p(gparam))
+    if rc != 0:
+        raise RuntimeError("oracle adjoint_along_params failed")
+    return gq0, gqd0, gtau, gparam
 
 
 def adjoint_along(m: Model, states, tau, dt, gqT, gqdT, gtraj=None):

@@ -153,10 +153,35 @@ static void quat_R_grad(const double *qt, const double *Rbar, double *qtbar) {
   }
 }
 
-/* Reverse of aba_tape_r: ADD d<qdd_bar, qdd>/d(q, qd, tau). */
+/* Adjoint of the spatial inertia of link i, Ibar (dense 6x6, every entry
+ * taken as an independent variable), expressed in the ten inertial
+ * parameters of the link (link frame): mass m, first moment h = m c, and
+ * the rotational inertia about the link origin I_O = I_c - m [c]x^2, i.e.
+ * I = [I_O, [h]x; [h]x^T, m 1].  Output order: m, h (3), I_O xx yy zz xy
+ * xz yz, where an off-diagonal parameter stands for both of its entries.
+ * ADDS into pbar[10]. */
+static void inertia_params_add(const double *Ibar, double *pbar) {
+  pbar[0] += Ibar[6 * 3 + 3] + Ibar[6 * 4 + 4] + Ibar[6 * 5 + 5];
+  double P[9]; /* top-right block minus bottom-left block */
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) P[3 * r + c] = Ibar[6 * r + 3 + c] - Ibar[6 * (3 + r) + c];
+  pbar[1] += P[3 * 2 + 1] - P[3 * 1 + 2];
+  pbar[2] += P[3 * 0 + 2] - P[3 * 2 + 0];
+  pbar[3] += P[3 * 1 + 0] - P[3 * 0 + 1];
+  pbar[4] += Ibar[0];
+  pbar[5] += Ibar[7];
+  pbar[6] += Ibar[14];
+  pbar[7] += Ibar[1] + Ibar[6];
+  pbar[8] += Ibar[2] + Ibar[12];
+  pbar[9] += Ibar[8] + Ibar[13];
+}
+
+/* Reverse of aba_tape_r: ADD d<qdd_bar, qdd>/d(q, qd, tau), and, when
+ * param_bar is not NULL, the adjoint of every link's inertial parameters
+ * ([n][10], see inertia_params_add). */
 static int aba_vjp(const orc_model *m, const double *q, const double *qd,
                    const tape_t *L, const double *qdd_bar, double *q_bar,
-                   double *qd_bar, double *tau_bar) {
+                   double *qd_bar, double *tau_bar, double *param_bar) {
   const int n = m->n;
   int qi[n], vi[n], ui[n];
   layout_r(m, qi, vi, ui);
@@ -273,6 +298,14 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
     tvec_add(C, l->h, b->v);
     /* h = I v */
     tvec_add(l->Isp, b->h, b->v);
+    /* the link's spatial inertia enters twice: IA = I + children's shares,
+       and h = I v */
+    if (param_bar) {
+      double Ibar[36];
+      for (int k = 0; k < 36; ++k) Ibar[k] = b->IA[k];
+      outer_add(b->h, l->v, Ibar);
+      inertia_params_add(Ibar, param_bar + 10 * i);
+    }
     if (m->jtype[i] == ORC_FREE) {
       for (int k = 0; k < 6; ++k) qd_bar[vi[i] + k] += b->v[k];
       double Rbar[9];
@@ -328,7 +361,7 @@ void orc_fd_vjp(const orc_model *m, const double *q, const double *qd,
   tape_t *L = (tape_t *)malloc(sizeof(tape_t) * (size_t)m->n);
   double *qdd = (double *)malloc(sizeof(double) * (size_t)nv);
   aba_tape_r(m, q, qd, tau, L, qdd);
-  aba_vjp(m, q, qd, L, qdd_bar, q_bar, qd_bar, tau_bar);
+  aba_vjp(m, q, qd, L, qdd_bar, q_bar, qd_bar, tau_bar, NULL);
   free(qdd);
   free(L);
 }
@@ -340,7 +373,7 @@ void orc_fd_vjp(const orc_model *m, const double *q, const double *qd,
 static int step_vjp(const orc_model *m, const double *q, const double *qd,
                     const double *qdd, const tape_t *L, double dt,
                     const double *q1bar, const double *qd1bar, double *qbar,
-                    double *qdbar, double *taubar, double *qddbar) {
+                    double *qdbar, double *taubar, double *qddbar, double *pbar) {
   const int n = m->n, nu = orc_nu(m);
   int qi[n], vi[n], ui[n];
   layout_r(m, qi, vi, ui);
@@ -400,7 +433,7 @@ static int step_vjp(const orc_model *m, const double *q, const double *qd,
       qdbar[vi[i]] = tot;
     }
   }
-  return aba_vjp(m, q, qd, L, qddbar, qbar, qdbar, taubar);
+  return aba_vjp(m, q, qd, L, qddbar, qbar, qdbar, taubar, pbar);
 }
 
 static void tape_qdd(const orc_model *m, const tape_t *L, double *qdd) {
@@ -415,12 +448,14 @@ static void tape_qdd(const orc_model *m, const tape_t *L, double *qdd) {
   }
 }
 
-int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
-                     const double *tau, double dt, int T, int K,
-                     const double *gqT, const double *gqdT,
-                     const double *gtraj, double *gq0, double *gqd0,
-                     double *gtau, double *qT, double *qdT) {
+int orc_rollout_grad_params(const orc_model *m, const double *q0, const double *qd0,
+                            const double *tau, double dt, int T, int K,
+                            const double *gqT, const double *gqdT,
+                            const double *gtraj, double *gq0, double *gqd0,
+                            double *gtau, double *gparam, double *qT, double *qdT) {
   if (T < 0 || K < 0) return -1;
+  if (gparam)
+    for (int k = 0; k < 10 * m->n; ++k) gparam[k] = 0;
   const int n = m->n, nq = orc_nq(m), nv = orc_nv(m), nu = orc_nu(m);
   const int nx = nq + nv;
   const int ncp = (K >= 1) ? (T + K - 1) / K : 0;
@@ -483,7 +518,7 @@ int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
         const double *xt = scratch + (size_t)(t - t0) * nx;
         aba_tape_r(m, xt, xt + nq, tau + (size_t)t * nu, tape, qdd);
         rc = step_vjp(m, xt, xt + nq, qdd, tape, dt, xb, xb + nq, xb1, xb1 + nq,
-                      gtau + (size_t)t * nu, qddbar);
+                      gtau + (size_t)t * nu, qddbar, gparam);
         memcpy(xb, xb1, sizeof(double) * nx);
         if (gtraj && t >= 1)
           for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(t - 1) * nx + k];
@@ -495,7 +530,7 @@ int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
       const tape_t *Lt = tapes + (size_t)t * n;
       tape_qdd(m, Lt, qdd);
       rc = step_vjp(m, xt, xt + nq, qdd, Lt, dt, xb, xb + nq, xb1, xb1 + nq,
-                    gtau + (size_t)t * nu, qddbar);
+                    gtau + (size_t)t * nu, qddbar, gparam);
       memcpy(xb, xb1, sizeof(double) * nx);
       if (gtraj && t >= 1)
         for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(t - 1) * nx + k];
@@ -508,10 +543,22 @@ int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
   return rc;
 }
 
-int orc_adjoint_along(const orc_model *m, const double *states, const double *tau,
-                      double dt, int T, const double *gqT, const double *gqdT,
-                      const double *gtraj, double *gq0, double *gqd0, double *gtau) {
+int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
+                     const double *tau, double dt, int T, int K,
+                     const double *gqT, const double *gqdT,
+                     const double *gtraj, double *gq0, double *gqd0,
+                     double *gtau, double *qT, double *qdT) {
+  return orc_rollout_grad_params(m, q0, qd0, tau, dt, T, K, gqT, gqdT, gtraj, gq0, gqd0, gtau, NULL,
+                                 qT, qdT);
+}
+
+int orc_adjoint_along_params(const orc_model *m, const double *states, const double *tau,
+                             double dt, int T, const double *gqT, const double *gqdT,
+                             const double *gtraj, double *gq0, double *gqd0, double *gtau,
+                             double *gparam) {
   if (T < 0) return -1;
+  if (gparam)
+    for (int k = 0; k < 10 * m->n; ++k) gparam[k] = 0;
   const int n = m->n, nq = orc_nq(m), nv = orc_nv(m), nu = orc_nu(m);
   const int nx = nq + nv;
   tape_t *tape = (tape_t *)malloc(sizeof(tape_t) * (size_t)n);
@@ -528,7 +575,7 @@ int orc_adjoint_along(const orc_model *m, const double *states, const double *ta
     const double *xt = states + (size_t)t * nx;
     aba_tape_r(m, xt, xt + nq, tau + (size_t)t * nu, tape, qdd);
     rc = step_vjp(m, xt, xt + nq, qdd, tape, dt, xb, xb + nq, xb1, xb1 + nq,
-                  gtau + (size_t)t * nu, qddbar);
+                  gtau + (size_t)t * nu, qddbar, gparam);
     memcpy(xb, xb1, sizeof(double) * nx);
     if (gtraj && t >= 1)
       for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(t - 1) * nx + k];
@@ -538,4 +585,10 @@ int orc_adjoint_along(const orc_model *m, const double *states, const double *ta
   free(tape);
   free(work);
   return rc;
+}
+
+int orc_adjoint_along(const orc_model *m, const double *states, const double *tau,
+                      double dt, int T, const double *gqT, const double *gqdT,
+                      const double *gtraj, double *gq0, double *gqd0, double *gtau) {
+  return orc_adjoint_along_params(m, states, tau, dt, T, gqT, gqdT, gtraj, gq0, gqd0, gtau, NULL);
 }

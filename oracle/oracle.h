@@ -102,12 +102,30 @@ int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
                      const double *gtraj, double *gq0, double *gqd0,
                      double *gtau, double *qT, double *qdT);
 
+/* As orc_rollout_grad, and also the gradient with respect to every link's
+ * ten inertial parameters, summed over all steps: gparam is [n][10], per
+ * link (m, h_x, h_y, h_z, I_xx, I_yy, I_zz, I_xy, I_xz, I_yz) with h = m c
+ * the first moment and I the rotational inertia about the link origin
+ * (I_c - m [c]x^2), all in the link frame; an off-diagonal parameter stands
+ * for both of its matrix entries.  Sec. 4.1, after Eq. adj_r: the gradient
+ * of any other parameter follows from the same per-step adjoints as the
+ * control gradient; Sec. 6.3 (parameter estimation). */
+int orc_rollout_grad_params(const orc_model *m, const double *q0, const double *qd0,
+                            const double *tau, double dt, int T, int K,
+                            const double *gqT, const double *gqdT,
+                            const double *gtraj, double *gq0, double *gqd0,
+                            double *gtau, double *gparam, double *qT, double *qdT);
+
 /* The reverse sweep alone, along a given trajectory: states is [T][nq + nv]
  * with row t = x^t (the initial state of step t), used as the per-step
  * checkpoints; seeds and outputs as orc_rollout_grad. */
 int orc_adjoint_along(const orc_model *m, const double *states, const double *tau,
                       double dt, int T, const double *gqT, const double *gqdT,
                       const double *gtraj, double *gq0, double *gqd0, double *gtau);
+int orc_adjoint_along_params(const orc_model *m, const double *states, const double *tau,
+                             double dt, int T, const double *gqT, const double *gqdT,
+                             const double *gtraj, double *gq0, double *gqd0, double *gtau,
+                             double *gparam);
 
 #ifdef __cplusplus
 }

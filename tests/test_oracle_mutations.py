@@ -40,6 +40,12 @@ MUTATIONS = [
     ("aba_oracle.c", "tau + (size_t)(t0 + j - 1) * nu, tape, qdd);", "tau + (size_t)(t0 + j) * nu, tape, qdd);",
      "off-by-one in the segment replay"),
     ("aba_oracle.c", "outer_add(b->ap, al, b->X);", "outer_add(al, b->ap, b->X);", "transposed X_bar outer product"),
+    ("aba_oracle.c", "      outer_add(b->h, l->v, Ibar);\n", "", "dropped h = I v term of the inertia adjoint"),
+    ("aba_oracle.c", "pbar[7] += Ibar[1] + Ibar[6];", "pbar[7] += Ibar[1];", "off-diagonal inertia counted once"),
+    ("aba_oracle.c", "pbar[1] += P[3 * 2 + 1] - P[3 * 1 + 2];", "pbar[1] += P[3 * 1 + 2] - P[3 * 2 + 1];",
+     "first-moment adjoint sign"),
+    ("aba_oracle.c", "pbar[0] += Ibar[6 * 3 + 3] + Ibar[6 * 4 + 4] + Ibar[6 * 5 + 5];",
+     "pbar[0] += Ibar[6 * 3 + 3] + Ibar[6 * 4 + 4];", "dropped mass-block term"),
 ]
 
 PINS = [
@@ -53,6 +59,9 @@ PINS = [
     pins.test_rollout_gradient_complex_step_chain,
     pins.test_free_base_rollout_gradient_complex_step,
     lambda: pins.test_checkpoint_interval_changes_no_arithmetic("quad"),
+    lambda: pins.test_inertial_parameter_gradient_scaling_identity(0),
+    lambda: pins.test_inertial_parameter_gradient_central_differences(0),
+    lambda: pins.test_inertial_parameter_gradient_central_differences(1),
 ]
 
 

@@ -435,3 +435,100 @@ def test_adjoint_along_own_trajectory_equals_checkpointed_adjoint():
     a = O.adjoint_along(m, states, tau, 1e-3, gqT, gqdT, gtr)
     b = O.rollout_grad(m, q0, qd0, tau, 1e-3, gqT, gqdT, gtr)
     assert all(np.array_equal(x, y) for x, y in zip(a, b[:3]))
+
+
+# ------------------------------------------------------- inertial-parameter gradients
+
+def _inertial_params(s):
+    """Per link (m, h = m c, I_O = I_c - m [c]x^2 as xx yy zz xy xz yz)."""
+    th = np.zeros((s.n, 10))
+    for i in range(s.n):
+        m, c = float(s.mass[i]), np.asarray(s.com[i], dtype=float)
+        Ic = np.asarray(s.Ic[i], dtype=float)
+        J = np.array([[Ic[0], Ic[3], Ic[4]], [Ic[3], Ic[1], Ic[5]], [Ic[4], Ic[5], Ic[2]]])
+        IO = J + m * (np.dot(c, c) * np.eye(3) - np.outer(c, c))
+        th[i] = [m, *(m * c), IO[0, 0], IO[1, 1], IO[2, 2], IO[0, 1], IO[0, 2], IO[1, 2]]
+    return th
+
+
+def _with_inertial_params(s, th):
+    """The same system with the links' inertial parameters replaced."""
+    mass, com, Ic = np.zeros(s.n), np.zeros((s.n, 3)), np.zeros((s.n, 6))
+    for i in range(s.n):
+        m, h = th[i, 0], th[i, 1:4]
+        IO = np.array([[th[i, 4], th[i, 7], th[i, 8]], [th[i, 7], th[i, 5], th[i, 9]], [th[i, 8], th[i, 9], th[i, 6]]])
+        J = IO - (np.dot(h, h) * np.eye(3) - np.outer(h, h)) / m
+        mass[i], com[i] = m, h / m
+        Ic[i] = [J[0, 0], J[1, 1], J[2, 2], J[0, 1], J[0, 2], J[1, 2]]
+    return synth.System(parent=s.parent, jtype=s.jtype, E_T=s.E_T, r_T=s.r_T, axis=s.axis, mass=mass, com=com,
+                        Ic=Ic)
+
+
+def _param_problems():
+    tree = synth.tree_system(2005, 120, random_frames=True)
+    quad = synth.quadruped_system(3007, 120)
+    chain = synth.chain_system(5, 11, 120)
+    return [("tree", tree, 5e-4), ("quad", quad, 1e-3), ("chain", chain, 1e-3)]
+
+
+def _param_loss(s, q0, qd0, tau, dt):
+    m = O.Model(s)
+    qT, qdT = O.rollout(m, q0, qd0, tau, dt)
+    return float(np.sum(qT ** 2) + 0.5 * np.sum(qdT ** 2)), qT, qdT
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_inertial_parameter_gradient_central_differences(k):
+    """Gradient of L = |q_T|^2 + |qd_T|^2 / 2 with respect to every inertial
+    parameter of a few links against central differences of the (pinned)
+    forward rollout, on a branched tree with random frames, a free-floating
+    quadruped and a chain (Sec. 4.1, after Eq. adj_r)."""
+    name, (s, q0, qd0, tau), dt = _param_problems()[k]
+    _, qT, qdT = _param_loss(s, q0, qd0, tau, dt)
+    g = O.rollout_grad_params(O.Model(s), q0, qd0, tau, dt, 2 * qT, qdT)[3]
+    th = _inertial_params(s)
+    rng = np.random.default_rng(k)
+    links = sorted(set([0, s.n - 1] + list(rng.choice(s.n, size=min(3, s.n), replace=False))))
+    for i in links:
+        for j in range(10):
+            if name == "chain" and j not in (0, 1, 2, 6):
+                continue   # planar chain: the other parameters do not enter (checked below)
+            h = 1e-6 * max(1.0, abs(th[i, j]))
+            tp, tm = th.copy(), th.copy()
+            tp[i, j] += h
+            tm[i, j] -= h
+            fd = (_param_loss(_with_inertial_params(s, tp), q0, qd0, tau, dt)[0] -
+                  _param_loss(_with_inertial_params(s, tm), q0, qd0, tau, dt)[0]) / (2 * h)
+            assert abs(fd - g[i, j]) < 2e-6 * max(1.0, abs(g[i, j]), np.abs(g).max()), (name, i, j, fd, g[i, j])
+    if name == "chain":
+        # z-axis joints, in-plane gravity: out-of-plane parameters are inert
+        assert np.abs(g[:, [3, 4, 5, 7, 8, 9]]).max() < 1e-12 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_inertial_parameter_gradient_scaling_identity(k):
+    """Scaling every inertial parameter and every torque by the same factor
+    leaves the motion unchanged (M, C and gravity terms are linear in the
+    inertial parameters), so <theta, dL/dtheta> + <tau, dL/dtau> = 0 exactly."""
+    name, (s, q0, qd0, tau), dt = _param_problems()[k]
+    _, qT, qdT = _param_loss(s, q0, qd0, tau, dt)
+    _, _, gtau, g, _, _ = O.rollout_grad_params(O.Model(s), q0, qd0, tau, dt, 2 * qT, qdT)
+    th = _inertial_params(s)
+    a, b = float(np.sum(th * g)), float(np.sum(tau * gtau))
+    assert abs(a + b) < 1e-9 * max(abs(a), abs(b)), (a, b)
+    assert abs(a) > 1e-6
+
+
+def test_inertial_parameter_gradient_checkpointing_and_along():
+    """K and store-all give bitwise-identical parameter gradients, and the
+    sweep along the oracle's own trajectory reproduces them."""
+    s, q0, qd0, tau = synth.quadruped_system(3008, 90)
+    m = O.Model(s)
+    qT, qdT = O.rollout(m, q0, qd0, tau, 1e-3)
+    ref = O.rollout_grad_params(m, q0, qd0, tau, 1e-3, 2 * qT, qdT, K=1)[3]
+    for K in (0, 7, 90):
+        assert np.array_equal(O.rollout_grad_params(m, q0, qd0, tau, 1e-3, 2 * qT, qdT, K=K)[3], ref)
+    _, _, traj = O.rollout(m, q0, qd0, tau, 1e-3, traj=True)
+    states = np.concatenate([np.r_[q0, qd0][None], traj[:-1]])
+    along = O.adjoint_along_params(m, states, tau, 1e-3, 2 * qT, qdT)[3]
+    assert np.array_equal(along, ref)
