@@ -216,10 +216,17 @@ int sim_forward(sim_t h, const void *q0, const void *qd0, const void *tau, doubl
  * to the raw components under the rotation formula
  * R = (w^2 - u.u) I + 2 u u^T + 2 w [u]x; only their component tangent to
  * the unit sphere is gauge-independent.
+ * gparam (nullable) [n_links][10]: the gradient with respect to every
+ * link's ten inertial parameters, summed over the rollout (Sec. 4.1, after
+ * Eq. adj_r: other parameters follow from the same per-step adjoints as the
+ * controls), per link in the caller's link order and link frame:
+ * (m, h_x, h_y, h_z, I_xx, I_yy, I_zz, I_xy, I_xz, I_yz) with h = m c the
+ * first moment and I = I_c - m [c]x^2 the rotational inertia about the link
+ * origin; an off-diagonal parameter stands for both of its matrix entries.
  * Errors as sim_forward. */
 int sim_backward(sim_t h, const void *tau, double dt, int T, int K, const void *gqT,
                  const void *gqdT, const void *gtraj, void *gq0, void *gqd0, void *gtau,
-                 void *workspace, size_t workspace_bytes, void *stream);
+                 void *gparam, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Forward dynamics of every system at one state (Sec. 3, ABA):
  * q [nq], qd [nv], tau [nu] -> qdd [nv] (a free root's 6 entries are its

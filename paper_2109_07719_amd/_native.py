@@ -87,7 +87,7 @@ def lib():
         L.sim_workspace_bytes.restype = I
         L.sim_forward.argtypes = [P, P, P, P, D, I, I, P, P, P, P, Z, P]
         L.sim_forward.restype = I
-        L.sim_backward.argtypes = [P, P, D, I, I, P, P, P, P, P, P, P, Z, P]
+        L.sim_backward.argtypes = [P, P, D, I, I, P, P, P, P, P, P, P, P, Z, P]
         L.sim_backward.restype = I
         L.sim_aba.argtypes = [P, P, P, P, P, P]
         L.sim_aba.restype = I

@@ -363,6 +363,44 @@ ABA_HD V6<S> r1_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, V6<S> vbar,
   return xformT(t.E, L.rT, vbar);
 }
 
+// Adjoint of a link's ten inertial parameters: mass m, first moment
+// mc (m times the centre of mass) and rotational inertia about the link
+// origin Ib (unique entries xx yy zz xy xz yz; an off-diagonal parameter
+// stands for both of its matrix entries), in the kernels' link frame.  The
+// spatial inertia I = [Ib, [mc]x; [mc]x^T, m 1] enters a step twice: as the
+// start of the articulated inertia (IA = I + children's shares, so its
+// adjoint is the link's final IA_bar) and in h = I v of the bias force (h_bar
+// follows from pA_bar as in r1_own).  IAb is a symmetric adjoint: the
+// pairing with a symmetric change counts the B block twice.
+// (Sec. 4.1, after Eq. adj_r: other parameters follow from the same
+// per-step adjoints as the controls.)
+template <typename S>
+struct ParamBar {
+  S m;
+  V3<S> mc;
+  Sy3<S> Ib;
+};
+template <typename S>
+ABA_HD void param_bar_zero(ParamBar<S>& g) {
+  g.m = S(0);
+  g.mc = zero3<S>();
+  g.Ib = sy3<S>(S(0), S(0), S(0), S(0), S(0), S(0));
+}
+template <typename S>
+ABA_HD void param_bar_add(ParamBar<S>& g, const SySp<S>& IAb, const V6<S>& v, const V6<S>& pAb) {
+  const M3<S>& B = IAb.B;
+  g.m = g.m + (IAb.C.xx + IAb.C.yy + IAb.C.zz);
+  g.mc = g.mc + S(2) * v3<S>(B.m[7] - B.m[5], B.m[2] - B.m[6], B.m[3] - B.m[1]);
+  g.Ib = g.Ib + sy3<S>(IAb.A.xx, IAb.A.yy, IAb.A.zz, S(2) * IAb.A.xy, S(2) * IAb.A.xz, S(2) * IAb.A.yz);
+  // h = I v = [Ib w + mc x vl; m vl - mc x w]
+  const V6<S> hb = v6<S>(-cross(v.a, pAb.a), -(cross(v.a, pAb.l) + cross(v.l, pAb.a)));
+  const V3<S>& w = v.a;
+  g.m = g.m + dot(hb.l, v.l);
+  g.mc = g.mc + (cross(v.l, hb.a) - cross(w, hb.l));
+  g.Ib = g.Ib + sy3<S>(hb.a.x * w.x, hb.a.y * w.y, hb.a.z * w.z, hb.a.x * w.y + hb.a.y * w.x,
+                       hb.a.x * w.z + hb.a.z * w.x, hb.a.y * w.z + hb.a.z * w.y);
+}
+
 // free root, reverse of pass 3 and of the root solve.  abar: children's
 // shares; qddbar: base-acceleration seed from the integrator.  Adds the
 // gravity term's quaternion adjoint into quatb; returns pA_bar and IA_bar.

@@ -9,8 +9,11 @@ namespace aba {
 constexpr int kWave = 64;
 
 // integer per-lane fields, stored [field][slot]
-// CI_FIDX: index of a free root among the batch's free roots (-1 otherwise)
-enum CiField { CI_PARENT = 0, CI_DEPTH, CI_CFIRST, CI_CCOUNT, CI_JTYPE, CI_QIDX, CI_VIDX, CI_UIDX, CI_FIDX, CI_COUNT };
+// CI_FIDX: index of a free root among the batch's free roots (-1 otherwise);
+// CI_LINK: the link's index in the caller's batch-concatenated link order
+enum CiField {
+  CI_PARENT = 0, CI_DEPTH, CI_CFIRST, CI_CCOUNT, CI_JTYPE, CI_QIDX, CI_VIDX, CI_UIDX, CI_FIDX, CI_LINK, CI_COUNT
+};
 // floating per-lane fields, stored [field][slot]
 enum CfField {
   CF_ET = 0,          // 9
@@ -19,7 +22,8 @@ enum CfField {
   CF_M = 15,          // 1
   CF_MC = 16,         // 3
   CF_IB = 19,         // 6: xx yy zz xy xz yz
-  CF_COUNT = 25
+  CF_RL = 25,         // 9: rotation from the caller's link frame to the kernels' (joint axis = z)
+  CF_COUNT = 34
 };
 
 template <typename S>
@@ -65,6 +69,7 @@ struct BwdArgs {
   S* gtau;
   const S* ck;
   S* scratch;      // K > 1: [K][state width][nslots]
+  S* gparam;       // nullable: [n_links][10] inertial-parameter gradients
 };
 
 template <typename S>

@@ -85,7 +85,7 @@ __device__ __forceinline__ void sincos_(double x, double* s, double* c) { sincos
 template <typename S>
 struct Lane {
   int lane, slot;
-  int par, depth, cfirst, ccount, jtype, qidx, vidx, uidx, fidx;
+  int par, depth, cfirst, ccount, jtype, qidx, vidx, uidx, fidx, link;
   __device__ bool active() const { return jtype >= 0; }
   __device__ bool revolute() const { return jtype == 0; }
 };
@@ -107,6 +107,7 @@ __device__ __forceinline__ Lane<S> load_lane(const Packed<S>& P, int wb) {
   l.vidx = ci[CI_VIDX * ns + l.slot];
   l.uidx = ci[CI_UIDX * ns + l.slot];
   l.fidx = ci[CI_FIDX * ns + l.slot];
+  l.link = ci[CI_LINK * ns + l.slot];
   return l;
 }
 
@@ -312,6 +313,32 @@ __device__ __forceinline__ void get_slot(State<S, FREE>& s, const S* base, int n
   }
   s.q[0] = base[slot];
   s.qd[0] = base[nslots + slot];
+}
+
+// Writes a link's inertial-parameter gradient, turned from the kernels'
+// link frame back to the caller's: the kernels' parameters are
+// mc' = Rl mc and Ib' = Rl Ib Rl^T, so mc_bar = Rl^T mc'_bar and, with the
+// symmetric matrix G of the Ib adjoint (off-diagonals halved), G = Rl^T G' Rl.
+// Returns the number of non-finite values written.
+template <typename S>
+__device__ __forceinline__ int store_param_bar(const ParamBar<S>& g, const Packed<S>& P, const Lane<S>& l,
+                                               S* out) {
+  const int ns = P.nslots;
+  M3<S> Rl;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Rl.m[k] = P.cf[(CF_RL + k) * ns + l.slot];
+  const V3<S> mc = mulT(Rl, g.mc);
+  const Sy3<S> G = congT(Rl, sy3<S>(g.Ib.xx, g.Ib.yy, g.Ib.zz, S(0.5) * g.Ib.xy, S(0.5) * g.Ib.xz,
+                                      S(0.5) * g.Ib.yz));
+  const S v[10] = {g.m, mc.x, mc.y, mc.z, G.xx, G.yy, G.zz, S(2) * G.xy, S(2) * G.xz, S(2) * G.yz};
+  S* o = out + (size_t)l.link * 10;
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    o[k] = v[k];
+    n += nonfinite(v[k]);
+  }
+  return n;
 }
 
 // Everything one ABA evaluation leaves in a lane.
@@ -588,7 +615,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
 template <typename S, bool FREE, bool CHAIN>
 __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
                                             S* xb, const State<S, FREE>& st, const Step<S>& o, int t,
-                                            State<S, FREE>& xb1, int& nonfin) {
+                                            State<S, FREE>& xb1, int& nonfin, ParamBar<S>& pg) {
   const bool act = l.active();
   const bool rev = l.revolute();
   const V3<S> g = v3<S>(A.P.g[0], A.P.g[1], A.P.g[2]);
@@ -674,6 +701,8 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
     }
   }
   if (rev && l.par >= 0) r2_local(L, tp, b, N, pab);
+  // inertial-parameter adjoint of this step: IAb and pAb are final here
+  if (A.gparam != nullptr && act) param_bar_add(pg, IAb, tp.v, pAb);
   // reverse of pass 1, leaves -> root
   const V6<S> own = act ? r1_own(L, tp.v, b, pAb, st.qd[0], rev) : zero6<S>();
   V6<S> vbar = zero6<S>();
@@ -730,10 +759,10 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
 template <typename S, bool FREE, bool CHAIN>
 __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
                                          S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1,
-                                         int& nonfin) {
+                                         int& nonfin, ParamBar<S>& pg) {
   Step<S> o;
   aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
-  bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin);
+  bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
 }
 
 // Backward (adjoint) rollout, reverse time.  K == 1 reloads every step's
@@ -754,6 +783,8 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
   const int nf = A.P.nfree;
   const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
   int nonfin = 0;  // non-finite outputs
+  ParamBar<S> pg;
+  param_bar_zero(pg);
   State<S, FREE> xb1 = {};
   if (act) {
     load_state(xb1, l, A.gqT, A.gqdT);
@@ -777,7 +808,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
         get_slot(st, row, ns, nf, l.slot, l.fidx);
         get_tape(o, row + RW, ns, l.slot, L, st.qd[0], rev);
       }
-      bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin);
+      bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
     }
   } else if (A.K == 1) {
     State<S, FREE> nxt = {};
@@ -793,7 +824,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
         if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
         if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
       }
-      bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, st, tau, t, xb1, nonfin);
+      bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, st, tau, t, xb1, nonfin, pg);
     }
   } else {
     const int ncp = (A.T + A.K - 1) / A.K;
@@ -827,13 +858,14 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
           if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
-        bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, cur, tau, t, xb1, nonfin);
+        bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, cur, tau, t, xb1, nonfin, pg);
       }
     }
   }
   if (act) {
     store_state(xb1, l, A.gq0, A.gqd0);
     nonfin += nonfinite_state(xb1, l);
+    if (A.gparam != nullptr) nonfin += store_param_bar(pg, A.P, l, A.gparam);
   }
   report_nonfinite(A.P.status, nonfin);
 }
@@ -898,6 +930,8 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
     }
   } else {
     int nonfin = 0;  // non-finite outputs
+    ParamBar<S> pg;
+    param_bar_zero(pg);
     State<S, FREE> xb1 = {};
     if (act) {
       load_state(xb1, l, A.gqT, A.gqdT);
@@ -922,13 +956,14 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
         for (int j = 0; j < (FREE ? 6 : 1); ++j) st.qd[j] = tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane];
         Step<S> o;
         get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, L, st.qd[0], rev);
-        bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin);
+        bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
       }
       __syncthreads();
     }
     if (act) {
       store_state(xb1, l, A.gq0, A.gqd0);
       nonfin += nonfinite_state(xb1, l);
+      if (A.gparam != nullptr) nonfin += store_param_bar(pg, A.P, l, A.gparam);
     }
     report_nonfinite(A.P.status, nonfin);
   }

@@ -368,6 +368,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       CI(aba::CI_VIDX) = sys_v[s] + loc_v[L];
       CI(aba::CI_UIDX) = (loc_u[L] < 0) ? -1 : sys_u[s] + loc_u[L];
       if (topo->jtype[L] == SIM_JOINT_FREE) CI(aba::CI_FIDX) = h->nfree++;
+      CI(aba::CI_LINK) = L;
       // joint-axis canonicalisation: rotate the link frame by Rl so that its
       // axis becomes e_z (the parent frame was rotated by Rp):
       //   E_T' = Rl E_T Rp^T, r_T' = Rp r_T, c' = Rl c, Ic' = Rl Ic Rl^T.
@@ -405,6 +406,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       CF(aba::CF_IB + 3) = I[3] - m * c[0] * c[1];
       CF(aba::CF_IB + 4) = I[4] - m * c[0] * c[2];
       CF(aba::CF_IB + 5) = I[5] - m * c[1] * c[2];
+      for (int k = 0; k < 9; ++k) CF(aba::CF_RL + k) = Rl[k];
     }
   }
   h->eti = eti;
@@ -566,8 +568,8 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
 }
 
 int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* gqT, const void* gqdT,
-                 const void* gtraj, void* gq0, void* gqd0, void* gtau, void* workspace, size_t workspace_bytes,
-                 void* stream) {
+                 const void* gtraj, void* gq0, void* gqd0, void* gtau, void* gparam, void* workspace,
+                 size_t workspace_bytes, void* stream) {
   g_err.clear();
   int rc = check_run(h, dt, T, K, "sim_backward");
   if (rc) return rc;
@@ -595,6 +597,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (double*)gtau;
     a.ck = (const double*)workspace;
     a.scratch = (K > 1) ? (double*)((char*)workspace + ck) : nullptr;
+    a.gparam = (double*)gparam;
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   } else {
     aba::BwdArgs<float> a;
@@ -611,6 +614,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (float*)gtau;
     a.ck = (const float*)workspace;
     a.scratch = (K > 1) ? (float*)((char*)workspace + ck) : nullptr;
+    a.gparam = (float*)gparam;
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_backward: launch failed: ") + hipGetErrorString(e));
@@ -718,7 +722,7 @@ int sim_autotune(sim_t h, int K, int T_probe, void* stream, sim_tiling_t* chosen
   };
   auto fwd = [&]() { return sim_forward(h, q0, qd0, tau, dt, T, K, qT, qdT, nullptr, ws, ws_bytes, stream); };
   auto bwd = [&]() {
-    return sim_backward(h, tau, dt, T, K, gqT, gqdT, nullptr, gq0, gqd0, gtau, ws, ws_bytes, stream);
+    return sim_backward(h, tau, dt, T, K, gqT, gqdT, nullptr, gq0, gqd0, gtau, nullptr, ws, ws_bytes, stream);
   };
   const int wpbs[3] = {1, 2, 4};
   double F[3], Bnp[3], Bp[2] = {1e300, 1e300};

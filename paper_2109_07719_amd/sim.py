@@ -167,9 +167,12 @@ class Sim:
                                     _ptr(qT), _ptr(qdT), _ptr(tr), _ptr(workspace), wsb, _stream()))
         return qT, qdT, tr
 
-    def backward(self, tau, dt, K, workspace, gqT, gqdT, gtraj=None, out=None):
+    def backward(self, tau, dt, K, workspace, gqT, gqdT, gtraj=None, out=None, params=False):
         """Adjoint pass after forward() on the same workspace.  Returns
-        (gq0, gqd0, gtau)."""
+        (gq0, gqd0, gtau), and with params=True also the gradient with
+        respect to every link's ten inertial parameters [n_links, 10]
+        (m, h = m c, I about the link origin xx yy zz xy xz yz; caller's
+        link frames), summed over the rollout."""
         tau = tau.reshape(-1, self.nu) if self.nu else tau
         T = int(tau.shape[0])
         self._t(gqT, self.nq, "gqT"), self._t(gqdT, self.nv, "gqdT")
@@ -181,10 +184,11 @@ class Sim:
             gtau = torch.empty((T, self.nu), dtype=self.dtype, device=dev)
         else:
             gq0, gqd0, gtau = out
+        gparam = torch.empty((self.info["n_links"], 10), dtype=self.dtype, device=dev) if params else None
         N.check(N.lib().sim_backward(self._h, _ptr(tau), float(dt), T, int(K), _ptr(gqT), _ptr(gqdT),
-                                     _ptr(gtraj), _ptr(gq0), _ptr(gqd0), _ptr(gtau), _ptr(workspace),
-                                     workspace.numel(), _stream()))
-        return gq0, gqd0, gtau
+                                     _ptr(gtraj), _ptr(gq0), _ptr(gqd0), _ptr(gtau), _ptr(gparam),
+                                     _ptr(workspace), workspace.numel(), _stream()))
+        return (gq0, gqd0, gtau, gparam) if params else (gq0, gqd0, gtau)
 
 
 class _Rollout(torch.autograd.Function):

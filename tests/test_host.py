@@ -83,7 +83,7 @@ def test_null_arguments_are_rejected():
     assert L.sim_workspace_bytes(None, 10, 1, ctypes.byref(b)) == N.SIM_ERR_INVALID_ARG
     assert L.sim_forward(None, None, None, None, 1e-3, 1, 1, None, None, None, None, 0, None) == \
         N.SIM_ERR_INVALID_ARG
-    assert L.sim_backward(None, None, 1e-3, 1, 1, None, None, None, None, None, None, None, 0, None) == \
+    assert L.sim_backward(None, None, 1e-3, 1, 1, None, None, None, None, None, None, None, None, 0, None) == \
         N.SIM_ERR_INVALID_ARG
     assert L.sim_aba(None, None, None, None, None, None) == N.SIM_ERR_INVALID_ARG
     f = ctypes.c_double()
