@@ -72,7 +72,8 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
     import oracle as O
 
     qo, vo, uo = batch.offsets()
-    gq0, gqd0, gtau = grads
+    gq0, gqd0, gtau, gparam = grads
+    lo = np.cumsum([0] + [s.n for s in batch.systems])
     n = len(batch.systems)
 
     def one(i):
@@ -115,11 +116,13 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
         states = np.concatenate([x0[None], trajs[k][:-1]])
         nqi = qo[i + 1] - qo[i]
         tau = np.asarray(batch.tau[:, uo[i]:uo[i + 1]], dtype=np.float64)
-        g = O.adjoint_along(m, states, tau, batch.dt, 2 * trajs[k][-1, :nqi], np.zeros(vo[i + 1] - vo[i]))
-        return max(rel(gq0[qo[i]:qo[i + 1]], g[0]), rel(gqd0[vo[i]:vo[i + 1]], g[1]),
-                   rel(gtau[:, uo[i]:uo[i + 1]], g[2]))
+        g = O.adjoint_along_params(m, states, tau, batch.dt, 2 * trajs[k][-1, :nqi], np.zeros(vo[i + 1] - vo[i]))
+        return (max(rel(gq0[qo[i]:qo[i + 1]], g[0]), rel(gqd0[vo[i]:vo[i + 1]], g[1]),
+                    rel(gtau[:, uo[i]:uo[i + 1]], g[2])), rel(gparam[lo[i]:lo[i + 1]], g[3]))
 
-    e_along = O.map_threads(along, range(len(idx)), threads=threads)
+    both = O.map_threads(along, range(len(idx)), threads=threads)
+    e_along = [a for a, _ in both]
+    e_param = [p_ for _, p_ in both]
     import platform
     cpu = platform.processor() or platform.machine()
     try:
@@ -141,6 +144,8 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
            "along_gpu_trajectory_p99": float(np.percentile(e_along, 99)),
            "along_gpu_trajectory_frac_above_1e-3": float(np.mean(np.asarray(e_along) > 1e-3)),
            "end_to_end_vs_fp64_max": max(e2e), "end_to_end_vs_fp64_median": float(np.median(e2e)),
+           "param_grads_along_gpu_trajectory_max": max(e_param),
+           "param_grads_along_gpu_trajectory_median": float(np.median(e_param)),
            "systems": len(idx), "norm": "per system ||g - g_ref|| / ||g_ref||, max over (gq0, gqd0, gtau)",
            "note": "end-to-end differences on long horizons come from chaotic divergence of FP32 and FP64 "
                    "trajectories; along the GPU's own trajectory what remains is FP32 round-off of the "
@@ -364,14 +369,19 @@ def main():
     def bwd():
         sim.backward(tau, dt, K, ws, gqT, gqdT, out=(gq0, gqd0, gtau))
 
+    gparam = torch.empty((sim.info["n_links"], 10), dtype=torch.float32, device=dev)
+
+    def bwd_params():
+        sim.backward(tau, dt, K, ws, gqT, gqdT, out=(gq0, gqd0, gtau, gparam), params=True)
+
     def plain():
         sim.forward(q0, qd0, tau, dt, K=K, workspace=None, out=(pqT, pqdT, None))
 
     # warm up eagerly once (also the first correctness pass), then capture
-    fwd(), bwd(), plain()
+    fwd(), bwd(), plain(), bwd_params()
     torch.cuda.synchronize()
     graphs = {}
-    for name, fn in (("fwd", fwd), ("bwd", bwd), ("plain", plain)):
+    for name, fn in (("fwd", fwd), ("bwd", bwd), ("plain", plain), ("bwd_params", bwd_params)):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             fn()
@@ -408,9 +418,21 @@ def main():
         pev[k][1].record()
     torch.cuda.synchronize()
     plain_ms = [pev[k][0].elapsed_time(pev[k][1]) for k in range(args.steps)]
+    # adjoint with inertial-parameter gradients (outside the headline value)
+    graphs["fwd"].replay()
+    for k in range(args.steps):
+        pev[k][0].record()
+        graphs["bwd_params"].replay()
+        pev[k][1].record()
+    torch.cuda.synchronize()
+    bwd_params_ms = [pev[k][0].elapsed_time(pev[k][1]) for k in range(args.steps)]
+    # leave the graphs' gradient buffers as the plain adjoint wrote them
+    graphs["bwd"].replay()
+    torch.cuda.synchronize()
 
-    grads = (gq0.cpu().numpy(), gqd0.cpu().numpy(), gtau.cpu().numpy())
+    grads = (gq0.cpu().numpy(), gqd0.cpu().numpy(), gtau.cpu().numpy(), gparam.cpu().numpy())
     finite = all(np.all(np.isfinite(g)) for g in grads) and bool(torch.isfinite(qT).all())
+    nonfinite_outputs = sim.status()
     dof_steps = b.total_dof * T
     ms_per_step = float(np.mean(step_ms))
     value = dof_steps / (ms_per_step * 1e-3)
@@ -439,8 +461,13 @@ def main():
                       "T": T, "dt": dt, "K": K, "lanes": sim.info["n_slots"], "waves": sim.info["n_waves"],
                       "lanes_per_system": "one lane per link", "tiling": sim.tiling,
                       "autotune": tune},
-           "plain_fwd_dof_steps_per_s": plain_rate, "fwd_adjoint_over_plain_fwd_time": value and plain_rate / value,
-           "peak_mem_bytes": int(peak_mem), "results_finite": finite, "roofline": roofline,
+           "plain_fwd_dof_steps_per_s": plain_rate,
+           "adjoint_with_param_grads": {"kernel_ms": float(np.mean(bwd_params_ms)),
+                                        "fwd_adjoint_dof_steps_per_s":
+                                            dof_steps / ((float(np.mean(fwd_ms)) + float(np.mean(bwd_params_ms))) * 1e-3),
+                                        "what": "gradient with respect to every link's 10 inertial parameters "
+                                                "as well, summed over the rollout"}, "fwd_adjoint_over_plain_fwd_time": value and plain_rate / value,
+           "peak_mem_bytes": int(peak_mem), "results_finite": finite, "nonfinite_outputs": nonfinite_outputs, "roofline": roofline,
            "wall_s_timed": wall, "input_gen_s": t_gen}
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)

@@ -182,9 +182,10 @@ class Sim:
             gq0 = torch.empty(self.nq, dtype=self.dtype, device=dev)
             gqd0 = torch.empty(self.nv, dtype=self.dtype, device=dev)
             gtau = torch.empty((T, self.nu), dtype=self.dtype, device=dev)
+            gparam = torch.empty((self.info["n_links"], 10), dtype=self.dtype, device=dev) if params else None
         else:
-            gq0, gqd0, gtau = out
-        gparam = torch.empty((self.info["n_links"], 10), dtype=self.dtype, device=dev) if params else None
+            gq0, gqd0, gtau = out[:3]
+            gparam = out[3] if params else None
         N.check(N.lib().sim_backward(self._h, _ptr(tau), float(dt), T, int(K), _ptr(gqT), _ptr(gqdT),
                                      _ptr(gtraj), _ptr(gq0), _ptr(gqd0), _ptr(gtau), _ptr(gparam),
                                      _ptr(workspace), workspace.numel(), _stream()))
