@@ -228,6 +228,22 @@ int sim_backward(sim_t h, const void *tau, double dt, int T, int K, const void *
                  const void *gqdT, const void *gtraj, void *gq0, void *gqd0, void *gtau,
                  void *gparam, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Forward-mode (tangent) rollout: the T-step rollout of sim_forward with
+ * one input direction (dq0 [nq], dqd0 [nv], dtau [T][nu]) carried along,
+ * giving the final state and its directional derivative
+ * dqT, dqdT = d(q^T, qd^T)/d(q^0, qd^0, u) . (dq0, dqd0, dtau); traj and
+ * dtraj (both given or both NULL) [T][nq + nv] receive every step's state
+ * and tangent.  No workspace: forward mode needs no checkpoints.  With
+ * T = 1 this is the one-step Jacobian-vector product ds'/da . da of the
+ * sample enhancement in Sec. 5; sim_backward with T = 1 gives the
+ * vector-Jacobian product used by the policy enhancement.  All arrays are
+ * device memory of the handle's dtype.  Errors: SIM_ERR_INVALID_ARG (T < 0,
+ * dt not finite or <= 0, null required pointer, only one of traj/dtraj),
+ * SIM_ERR_HIP. */
+int sim_forward_jvp(sim_t h, const void *q0, const void *qd0, const void *tau, const void *dq0,
+                    const void *dqd0, const void *dtau, double dt, int T, void *qT, void *qdT,
+                    void *dqT, void *dqdT, void *traj, void *dtraj, void *stream);
+
 /* Forward dynamics of every system at one state (Sec. 3, ABA):
  * q [nq], qd [nv], tau [nu] -> qdd [nv] (a free root's 6 entries are its
  * true body-frame spatial acceleration).  Errors: SIM_ERR_INVALID_ARG,

@@ -72,6 +72,26 @@ struct BwdArgs {
   S* gparam;       // nullable: [n_links][10] inertial-parameter gradients
 };
 
+// forward-mode (tangent) rollout: values and one tangent direction
+template <typename S>
+struct JvpArgs {
+  Packed<S> P;
+  S dt;
+  int T;
+  const S* q0;
+  const S* qd0;
+  const S* tau;   // [T][nu]
+  const S* dq0;   // tangents of the inputs (same layouts)
+  const S* dqd0;
+  const S* dtau;
+  S* qT;
+  S* qdT;
+  S* dqT;         // tangents of the final state
+  S* dqdT;
+  S* traj;        // nullable [T][nq + nv]
+  S* dtraj;       // nullable [T][nq + nv]
+};
+
 template <typename S>
 struct AbaArgs {
   Packed<S> P;
@@ -118,5 +138,7 @@ template <typename S>
 hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
 template <typename S>
 hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
+template <typename S>
+hipError_t launch_forward_jvp(const JvpArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
 
 }  // namespace aba

@@ -20,6 +20,7 @@
 // segment replay (App. B).
 #include "aba_lane.h"
 #include "abadj_internal.h"
+#include "dual.h"
 
 namespace aba {
 
@@ -55,6 +56,10 @@ __device__ __forceinline__ double dpp_mov(double x) {
   return __builtin_amdgcn_update_dpp(0.0, x, CTRL, 0xf, 0xf, true);
 }
 template <int CTRL, typename S>
+__device__ __forceinline__ Dual<S> dpp_mov(const Dual<S>& x) {
+  return Dual<S>(dpp_mov<CTRL>(x.v), dpp_mov<CTRL>(x.d));
+}
+template <int CTRL, typename S>
 __device__ __forceinline__ V6<S> dpp6(const V6<S>& v) {
   return v6<S>(v3<S>(dpp_mov<CTRL>(v.a.x), dpp_mov<CTRL>(v.a.y), dpp_mov<CTRL>(v.a.z)),
                v3<S>(dpp_mov<CTRL>(v.l.x), dpp_mov<CTRL>(v.l.y), dpp_mov<CTRL>(v.l.z)));
@@ -81,8 +86,14 @@ __device__ __forceinline__ SySp<S> from_next(const SySp<S>& M) { return dpp21<kD
 
 __device__ __forceinline__ void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
-
 template <typename S>
+__device__ __forceinline__ void sincos_(const Dual<S>& x, Dual<S>* s, Dual<S>* c) {
+  S sv, cv;
+  sincos_(x.v, &sv, &cv);
+  *s = Dual<S>(sv, cv * x.d);
+  *c = Dual<S>(cv, -sv * x.d);
+}
+
 struct Lane {
   int lane, slot;
   int par, depth, cfirst, ccount, jtype, qidx, vidx, uidx, fidx, link;
@@ -92,8 +103,8 @@ struct Lane {
 
 // wb: the wave batch (64 lane slots) this wavefront works on
 template <typename S>
-__device__ __forceinline__ Lane<S> load_lane(const Packed<S>& P, int wb) {
-  Lane<S> l;
+__device__ __forceinline__ Lane load_lane(const Packed<S>& P, int wb) {
+  Lane l;
   l.lane = threadIdx.x % kWave;
   l.slot = wb * kWave + l.lane;
   const int ns = P.nslots;
@@ -144,6 +155,10 @@ extern __shared__ __align__(16) unsigned char abadj_lds[];
 template <typename S>
 __device__ __forceinline__ S* lds() {
   return reinterpret_cast<S*>(abadj_lds);
+}
+template <typename S>
+__device__ __forceinline__ V3<S> gravity(const Packed<S>& P) {
+  return v3<S>(P.g[0], P.g[1], P.g[2]);
 }
 // wave batch of a single-wave kernel's wavefront, and its place in the block
 __device__ __forceinline__ int wave_in_block() { return threadIdx.x / kWave; }
@@ -213,7 +228,7 @@ __device__ __forceinline__ V6<S> st_vel6(const State<S, FREE>& s) {
 }
 
 template <typename S, bool FREE>
-__device__ __forceinline__ void load_state(State<S, FREE>& s, const Lane<S>& l, const S* q, const S* qd) {
+__device__ __forceinline__ void load_state(State<S, FREE>& s, const Lane& l, const S* q, const S* qd) {
   if (l.revolute()) {
     s.q[0] = q[l.qidx];
     s.qd[0] = qd[l.vidx];
@@ -227,7 +242,7 @@ __device__ __forceinline__ void load_state(State<S, FREE>& s, const Lane<S>& l, 
   }
 }
 template <typename S, bool FREE>
-__device__ __forceinline__ void store_state(const State<S, FREE>& s, const Lane<S>& l, S* q, S* qd) {
+__device__ __forceinline__ void store_state(const State<S, FREE>& s, const Lane& l, S* q, S* qd) {
   if (l.revolute()) {
     q[l.qidx] = s.q[0];
     qd[l.vidx] = s.qd[0];
@@ -259,7 +274,7 @@ __device__ __forceinline__ int nonfinite(double x) {
   return (opaque_u32(hi) & 0x7ff00000u) == 0x7ff00000u;
 }
 template <typename S, bool FREE>
-__device__ __forceinline__ int nonfinite_state(const State<S, FREE>& s, const Lane<S>& l) {
+__device__ __forceinline__ int nonfinite_state(const State<S, FREE>& s, const Lane& l) {
   int n = 0;
   if (l.revolute()) {
     n = nonfinite(s.q[0]) + nonfinite(s.qd[0]);
@@ -321,7 +336,7 @@ __device__ __forceinline__ void get_slot(State<S, FREE>& s, const S* base, int n
 // symmetric matrix G of the Ib adjoint (off-diagonals halved), G = Rl^T G' Rl.
 // Returns the number of non-finite values written.
 template <typename S>
-__device__ __forceinline__ int store_param_bar(const ParamBar<S>& g, const Packed<S>& P, const Lane<S>& l,
+__device__ __forceinline__ int store_param_bar(const ParamBar<S>& g, const Packed<S>& P, const Lane& l,
                                                S* out) {
   const int ns = P.nslots;
   M3<S> Rl;
@@ -399,7 +414,7 @@ __device__ __forceinline__ void get_tape(Step<S>& o, const S* base, int ns, int 
 // lanes in registers.  A root never pushes to its parent, so the lane after
 // a chain's leaf always hands the leaf zeros.
 template <typename S>
-__device__ __forceinline__ void aba_wave_chain(const Packed<S>& P, const Lane<S>& l, const LinkC<S>& L,
+__device__ __forceinline__ void aba_wave_chain(const V3<S>& g, const Lane& l, const LinkC<S>& L,
                                                const State<S, false>& st, S tau, int maxd, Step<S>& o) {
   Tape<S>& t = o.t;
   const bool act = l.active();
@@ -428,7 +443,7 @@ __device__ __forceinline__ void aba_wave_chain(const Packed<S>& P, const Lane<S>
     }
   }
   // pass 3: accelerations, root -> leaves
-  const V6<S> a0 = v6<S>(zero3<S>(), v3<S>(-P.g[0], -P.g[1], -P.g[2]));
+  const V6<S> a0 = v6<S>(zero3<S>(), -g);
   V6<S> a = zero6<S>();
   for (int d = 0; d <= maxd; ++d) {
     const V6<S> ap = from_prev(a);
@@ -438,11 +453,11 @@ __device__ __forceinline__ void aba_wave_chain(const Packed<S>& P, const Lane<S>
 
 // One ABA evaluation for the whole wave (all three passes).
 template <typename S, bool FREE, bool CHAIN>
-__device__ __forceinline__ void aba_wave(const Packed<S>& P, const Lane<S>& l, const LinkC<S>& L,
+__device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const LinkC<S>& L,
                                          const State<S, FREE>& st, S tau, int maxd, S* xb, Step<S>& o) {
   if constexpr (CHAIN) {
     static_assert(!FREE, "the chain variant has fixed bases only");
-    aba_wave_chain<S>(P, l, L, st, tau, maxd, o);
+    aba_wave_chain<S>(g, l, L, st, tau, maxd, o);
     return;
   }
   Tape<S>& t = o.t;
@@ -489,14 +504,14 @@ __device__ __forceinline__ void aba_wave(const Packed<S>& P, const Lane<S>& l, c
     wave_sync();
   }
   // pass 3: accelerations, root -> leaves
-  const V6<S> a0 = v6<S>(zero3<S>(), v3<S>(-P.g[0], -P.g[1], -P.g[2]));
+  const V6<S> a0 = v6<S>(zero3<S>(), -g);
   for (int d = 0; d <= maxd; ++d) {
     if (act && l.depth == d) {
       if (rev) {
         const V6<S> ap = (l.par >= 0) ? get6(xb, 0, l.par) : a0;
         put6(xb, 0, l.lane, p3_accel(L, t, ap));
       } else if constexpr (FREE) {
-        root_accel(t.IA, t.pA, st_quat(st), v3<S>(P.g[0], P.g[1], P.g[2]), t.ap, o.abase);
+        root_accel(t.IA, t.pA, st_quat(st), g, t.ap, o.abase);
         put6(xb, 0, l.lane, t.ap);
       }
     }
@@ -505,7 +520,7 @@ __device__ __forceinline__ void aba_wave(const Packed<S>& P, const Lane<S>& l, c
 }
 
 template <typename S, bool FREE>
-__device__ __forceinline__ void integrate_lane(State<S, FREE>& st, const Lane<S>& l, const Step<S>& o, S dt) {
+__device__ __forceinline__ void integrate_lane(State<S, FREE>& st, const Lane& l, const Step<S>& o, S dt) {
   if (l.revolute()) {
     integrate_rev(st.q[0], st.qd[0], o.t.qdd, dt);
   } else if constexpr (FREE) {
@@ -528,7 +543,7 @@ template <typename S, bool FREE, bool ETI, bool CHAIN>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A) {
   S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
   const int wb = wave_batch();
-  const Lane<S> l = load_lane(A.P, wb);
+  const Lane l = load_lane(A.P, wb);
   const int maxd = A.P.wmaxd[wb];
   // every lane slot holds valid constants, so load them unconditionally
   // (keeps the compile-time axis and frame constants visible to folding)
@@ -540,7 +555,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A)
     if (l.revolute()) tau = A.tau[l.uidx];
   }
   Step<S> o;
-  aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
+  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
   int nonfin = 0;
   if (l.revolute()) {
     A.qdd[l.vidx] = o.t.qdd;
@@ -565,7 +580,7 @@ template <typename S, bool FREE, bool ETI, bool CHAIN, int MODE>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S> A) {
   S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
   const int wb = wave_batch();
-  const Lane<S> l = load_lane(A.P, wb);
+  const Lane l = load_lane(A.P, wb);
   const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
@@ -584,7 +599,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
     const S tau = tau_next;
     if (has_tau && t + 1 < A.T) tau_next = A.tau[(size_t)(t + 1) * nu + l.uidx];
     Step<S> o;
-    aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
+    aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
     if constexpr (MODE == 2) {
       if (l.active()) {
         S* row = A.ck + (size_t)t * (RW + (size_t)kTapeFields * ns);
@@ -613,7 +628,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
 // and pass 1.  xb1 holds the adjoint of x^{t+1} on entry and that of x^t on
 // exit; tau_bar^t is written to gtau.
 template <typename S, bool FREE, bool CHAIN>
-__device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
+__device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, const LinkC<S>& L, int maxd,
                                             S* xb, const State<S, FREE>& st, const Step<S>& o, int t,
                                             State<S, FREE>& xb1, int& nonfin, ParamBar<S>& pg) {
   const bool act = l.active();
@@ -757,11 +772,11 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane<S>& 
 }
 
 template <typename S, bool FREE, bool CHAIN>
-__device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane<S>& l, const LinkC<S>& L, int maxd,
+__device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, const LinkC<S>& L, int maxd,
                                          S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1,
                                          int& nonfin, ParamBar<S>& pg) {
   Step<S> o;
-  aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
+  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
   bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
 }
 
@@ -773,7 +788,7 @@ template <typename S, bool FREE, bool ETI, bool CHAIN>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<S> A) {
   S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
   const int wb = wave_batch();
-  const Lane<S> l = load_lane(A.P, wb);
+  const Lane l = load_lane(A.P, wb);
   const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
@@ -842,7 +857,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
         const S tau = tau_nxt;
         if (rev && j + 1 < t1 - t0) tau_nxt = A.tau[(size_t)(t0 + j) * nu + l.uidx];
         Step<S> o;
-        aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
+        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
         if (act) {
           integrate_lane(st, l, o, A.dt);
           put_slot(st, A.scratch + (size_t)j * RW, ns, nf, l.slot, l.fidx);
@@ -892,7 +907,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
   S* const xb = CHAIN ? nullptr : base + wid * (XB * kWave);
   S* const tbuf[2] = {base + (CHAIN ? 0 : 2 * XB * kWave), base + (CHAIN ? 0 : 2 * XB * kWave) + TW * kWave};
   const int wb = blockIdx.x * (blockDim.x / (2 * kWave)) + pair;
-  const Lane<S> l = load_lane(A.P, wb);
+  const Lane l = load_lane(A.P, wb);
   const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
@@ -918,7 +933,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
         Step<S> o;
-        aba_wave<S, FREE, CHAIN>(A.P, l, L, st, tau, maxd, xb, o);
+        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
         S* tb = tbuf[k & 1];
 #pragma unroll
         for (int j = 0; j < (FREE ? 7 : 1); ++j) tb[(size_t)j * kWave + l.lane] = st.q[j];
@@ -967,6 +982,85 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
     }
     report_nonfinite(A.P.status, nonfin);
   }
+}
+
+// Forward-mode rollout: the same step as k_forward with every value carried
+// as a dual number (value, derivative along the given input direction), so
+// it returns x^T and d x^T = (dx^T/dx^0) dx^0 + sum_t (dx^T/du^t) du^t, and
+// optionally both trajectories.  With T = 1 this is the one-step
+// Jacobian-vector product behind the sample enhancement of Sec. 5.
+template <typename S>
+__device__ __forceinline__ LinkC<Dual<S>> dual_const(const LinkC<S>& L) {
+  LinkC<Dual<S>> D;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) D.ET.m[k] = Dual<S>(L.ET.m[k], S(0));
+  D.rT = v3<Dual<S>>(Dual<S>(L.rT.x, S(0)), Dual<S>(L.rT.y, S(0)), Dual<S>(L.rT.z, S(0)));
+  D.ax = v3<Dual<S>>(Dual<S>(L.ax.x, S(0)), Dual<S>(L.ax.y, S(0)), Dual<S>(L.ax.z, S(0)));
+  D.m = Dual<S>(L.m, S(0));
+  D.mc = v3<Dual<S>>(Dual<S>(L.mc.x, S(0)), Dual<S>(L.mc.y, S(0)), Dual<S>(L.mc.z, S(0)));
+  D.Ib = sy3<Dual<S>>(Dual<S>(L.Ib.xx, S(0)), Dual<S>(L.Ib.yy, S(0)), Dual<S>(L.Ib.zz, S(0)),
+                      Dual<S>(L.Ib.xy, S(0)), Dual<S>(L.Ib.xz, S(0)), Dual<S>(L.Ib.yz, S(0)));
+  return D;
+}
+
+template <typename S, bool FREE>
+__device__ __forceinline__ void split_state(const State<Dual<S>, FREE>& x, State<S, FREE>& v, State<S, FREE>& d) {
+#pragma unroll
+  for (int k = 0; k < (FREE ? 7 : 1); ++k) {
+    v.q[k] = x.q[k].v;
+    d.q[k] = x.q[k].d;
+  }
+#pragma unroll
+  for (int k = 0; k < (FREE ? 6 : 1); ++k) {
+    v.qd[k] = x.qd[k].v;
+    d.qd[k] = x.qd[k].d;
+  }
+}
+
+template <typename S, bool FREE, bool ETI, bool CHAIN>
+__global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward_jvp(JvpArgs<S> A) {
+  using D = Dual<S>;
+  D* xb = CHAIN ? nullptr : lds<D>() + wave_in_block() * (XB * kWave);
+  const int wb = wave_batch();
+  const Lane l = load_lane(A.P, wb);
+  const int maxd = A.P.wmaxd[wb];
+  const int nu = A.P.nu;
+  const LinkC<D> L = dual_const(load_linkc<S, ETI>(A.P, l.slot));
+  const V3<D> g = v3<D>(D(A.P.g[0], S(0)), D(A.P.g[1], S(0)), D(A.P.g[2], S(0)));
+  const D dt = D(A.dt, S(0));
+  State<S, FREE> sv = {}, sd = {};
+  if (l.active()) {
+    load_state(sv, l, A.q0, A.qd0);
+    load_state(sd, l, A.dq0, A.dqd0);
+  }
+  State<D, FREE> st;
+#pragma unroll
+  for (int k = 0; k < (FREE ? 7 : 1); ++k) st.q[k] = D(sv.q[k], sd.q[k]);
+#pragma unroll
+  for (int k = 0; k < (FREE ? 6 : 1); ++k) st.qd[k] = D(sv.qd[k], sd.qd[k]);
+  const bool has_tau = l.revolute();
+  int nonfin = 0;
+  for (int t = 0; t < A.T; ++t) {
+    const D tau = has_tau ? D(A.tau[(size_t)t * nu + l.uidx], A.dtau[(size_t)t * nu + l.uidx]) : D(S(0), S(0));
+    Step<D> o;
+    aba_wave<D, FREE, CHAIN>(g, l, L, st, tau, maxd, xb, o);
+    if (l.active()) integrate_lane(st, l, o, dt);
+    if (A.traj != nullptr && l.active()) {
+      split_state(st, sv, sd);
+      S* row = A.traj + (size_t)t * (A.P.nq + A.P.nv);
+      S* drow = A.dtraj + (size_t)t * (A.P.nq + A.P.nv);
+      store_state(sv, l, row, row + A.P.nq);
+      store_state(sd, l, drow, drow + A.P.nq);
+      nonfin += nonfinite_state(sv, l) + nonfinite_state(sd, l);
+    }
+  }
+  if (l.active()) {
+    split_state(st, sv, sd);
+    store_state(sv, l, A.qT, A.qdT);
+    store_state(sd, l, A.dqT, A.dqdT);
+    nonfin += nonfinite_state(sv, l) + nonfinite_state(sd, l);
+  }
+  report_nonfinite(A.P.status, nonfin);
 }
 
 }  // namespace
@@ -1062,7 +1156,21 @@ hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, const Tiling& t
   return hipGetLastError();
 }
 
+template <typename S>
+hipError_t launch_forward_jvp(const JvpArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st) {
+  if (a.P.nwaves == 0) return hipSuccess;
+  dispatch(sh, [&]<bool F, bool E, bool C>() {
+    // the exchange buffers hold dual numbers
+    size_t lds = 0;
+    const int w = single_wpb<Dual<S>, C>(tl, a.P.nwaves, lds);
+    hipLaunchKernelGGL((k_forward_jvp<S, F, E, C>), dim3(a.P.nwaves / w), dim3(kWave * w), lds, st, a);
+  });
+  return hipGetLastError();
+}
+
 template hipError_t launch_aba<float>(const AbaArgs<float>&, const Shape&, const Tiling&, hipStream_t);
+template hipError_t launch_forward_jvp<float>(const JvpArgs<float>&, const Shape&, const Tiling&, hipStream_t);
+template hipError_t launch_forward_jvp<double>(const JvpArgs<double>&, const Shape&, const Tiling&, hipStream_t);
 template hipError_t launch_aba<double>(const AbaArgs<double>&, const Shape&, const Tiling&, hipStream_t);
 template hipError_t launch_forward<float>(const FwdArgs<float>&, const Shape&, const Tiling&, hipStream_t);
 template hipError_t launch_forward<double>(const FwdArgs<double>&, const Shape&, const Tiling&, hipStream_t);

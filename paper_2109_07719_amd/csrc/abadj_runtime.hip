@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/abadj.h"
@@ -618,6 +619,48 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_backward: launch failed: ") + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+int sim_forward_jvp(sim_t h, const void* q0, const void* qd0, const void* tau, const void* dq0, const void* dqd0,
+                    const void* dtau, double dt, int T, void* qT, void* qdT, void* dqT, void* dqdT, void* traj,
+                    void* dtraj, void* stream) {
+  g_err.clear();
+  int rc = check_run(h, dt, T, 1, "sim_forward_jvp");
+  if (rc) return rc;
+  if (!q0 || !qd0 || !dq0 || !dqd0 || !qT || !qdT || !dqT || !dqdT || (T > 0 && h->nu > 0 && (!tau || !dtau)))
+    return fail(SIM_ERR_INVALID_ARG, "sim_forward_jvp: null array argument");
+  if ((traj == nullptr) != (dtraj == nullptr))
+    return fail(SIM_ERR_INVALID_ARG, "sim_forward_jvp: traj and dtraj must both be given or both be NULL");
+  hipError_t e;
+  auto fill = [&](auto& a, auto* tag) {
+    using S = std::remove_pointer_t<decltype(tag)>;
+    a.P = packed<S>(h);
+    a.dt = (S)dt;
+    a.T = T;
+    a.q0 = (const S*)q0;
+    a.qd0 = (const S*)qd0;
+    a.tau = (const S*)tau;
+    a.dq0 = (const S*)dq0;
+    a.dqd0 = (const S*)dqd0;
+    a.dtau = (const S*)dtau;
+    a.qT = (S*)qT;
+    a.qdT = (S*)qdT;
+    a.dqT = (S*)dqT;
+    a.dqdT = (S*)dqdT;
+    a.traj = (S*)traj;
+    a.dtraj = (S*)dtraj;
+  };
+  if (h->dtype == SIM_F64) {
+    aba::JvpArgs<double> a;
+    fill(a, (double*)nullptr);
+    e = aba::launch_forward_jvp(a, shape(h), h->tiling, (hipStream_t)stream);
+  } else {
+    aba::JvpArgs<float> a;
+    fill(a, (float*)nullptr);
+    e = aba::launch_forward_jvp(a, shape(h), h->tiling, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_forward_jvp: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
 }
 

@@ -167,6 +167,22 @@ class Sim:
                                     _ptr(qT), _ptr(qdT), _ptr(tr), _ptr(workspace), wsb, _stream()))
         return qT, qdT, tr
 
+    def forward_jvp(self, q0, qd0, tau, dq0, dqd0, dtau, dt, traj=False):
+        """Forward-mode rollout along the input direction (dq0, dqd0, dtau).
+        Returns (qT, qdT, dqT, dqdT) and, with traj=True, also (traj, dtraj)."""
+        tau = tau.reshape(-1, self.nu) if self.nu else tau
+        T = int(tau.shape[0])
+        self._t(q0, self.nq, "q0"), self._t(qd0, self.nv, "qd0"), self._t(tau, T * self.nu, "tau")
+        self._t(dq0, self.nq, "dq0"), self._t(dqd0, self.nv, "dqd0")
+        self._t(dtau.reshape(-1), T * self.nu, "dtau")
+        e = lambda *shape: torch.empty(shape, dtype=self.dtype, device=q0.device)
+        qT, qdT, dqT, dqdT = e(self.nq), e(self.nv), e(self.nq), e(self.nv)
+        tr, dtr = (e(T, self.nq + self.nv), e(T, self.nq + self.nv)) if traj else (None, None)
+        N.check(N.lib().sim_forward_jvp(self._h, _ptr(q0), _ptr(qd0), _ptr(tau), _ptr(dq0), _ptr(dqd0),
+                                        _ptr(dtau), float(dt), T, _ptr(qT), _ptr(qdT), _ptr(dqT), _ptr(dqdT),
+                                        _ptr(tr), _ptr(dtr), _stream()))
+        return (qT, qdT, dqT, dqdT, tr, dtr) if traj else (qT, qdT, dqT, dqdT)
+
     def backward(self, tau, dt, K, workspace, gqT, gqdT, gtraj=None, out=None, params=False):
         """Adjoint pass after forward() on the same workspace.  Returns
         (gq0, gqd0, gtau), and with params=True also the gradient with
