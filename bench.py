@@ -203,6 +203,100 @@ def memory_sweep(args, torch, dev, sim, b):
                       "dtype": "f32", "data": "synthetic", "sweep": rows}))
 
 
+def rl_bench(args, torch, dev):
+    """One-step derivatives for RL (Sec. 5): N samples of one quadruped
+    (free base + 12 revolute joints) at random states.  Times, per batch of
+    samples, the plain step, the one-step Jacobian-vector product along a
+    random action perturbation (sample enhancement: s' + ds'/da . da) and
+    the one-step vector-Jacobian product (policy enhancement:
+    dQ/ds' . ds'/da), each as one graph replay; checks 16 random samples
+    against the FP64 oracle (complex step for the JVP, the adjoint for the
+    VJP)."""
+    import oracle as O
+    from paper_2109_07719_amd import synth
+    from paper_2109_07719_amd.sim import Sim
+
+    n = args.rl
+    s, _, _, _ = synth.quadruped_system(3000, 1)
+    s = synth.round_to_f32(synth.make_batch([(s, np.zeros(s.nq), np.zeros(s.nv), np.zeros((1, s.nu)))], 1e-3)).systems[0]
+    rng = np.random.default_rng(17)
+    r32 = lambda x: x.astype(np.float32).astype(np.float64)
+    q = np.zeros((n, s.nq))
+    q[:, :3] = rng.normal(0, 0.2, (n, 3)) + [0, 0.5, 0]
+    qt = rng.normal(size=(n, 4))
+    q[:, 3:7] = qt / np.linalg.norm(qt, axis=1, keepdims=True)
+    q[:, 7:] = rng.normal(0, 0.3, (n, s.nq - 7))
+    q = r32(q)
+    qd, tau, dtau = r32(rng.normal(0, 0.5, (n, s.nv))), r32(rng.normal(0, 1, (n, s.nu))), r32(rng.normal(0, 1, (n, s.nu)))
+    wq, wqd = r32(rng.normal(size=(n, s.nq))), r32(rng.normal(size=(n, s.nv)))
+    t0 = time.perf_counter()
+    sim = Sim([s] * n, synth.GRAVITY, dtype=torch.float32)
+    t_create = time.perf_counter() - t0
+    tune = sim.autotune(K=1, T_probe=1) if args.tiling == "auto" else None
+    f = lambda x: torch.tensor(np.ascontiguousarray(x).reshape(-1), dtype=torch.float32, device=dev)
+    Q, QD, TAU, DTAU, WQ, WQD = f(q), f(qd), f(tau).reshape(1, -1), f(dtau).reshape(1, -1), f(wq), f(wqd)
+    Z0, Z1 = torch.zeros_like(Q), torch.zeros_like(QD)
+    dt = 1e-3
+    ws = sim.new_workspace(1, 1)
+    outs = {}
+
+    def plain():
+        outs["plain"] = sim.forward(Q, QD, TAU, dt, workspace=None)
+
+    def jvp():
+        outs["jvp"] = sim.forward_jvp(Q, QD, TAU, Z0, Z1, DTAU, dt)
+
+    def vjp():
+        sim.forward(Q, QD, TAU, dt, K=1, workspace=ws)
+        outs["vjp"] = sim.backward(TAU, dt, 1, ws, WQ, WQD)
+
+    fns = {"plain": plain, "jvp": jvp, "vjp": vjp}
+    for fn in fns.values():
+        fn()
+    torch.cuda.synchronize()
+    graphs = {}
+    for k, fn in fns.items():
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        graphs[k] = g
+    res = {}
+    for k, g in graphs.items():
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for a, b_ in evs:
+            a.record()
+            g.replay()
+            b_.record()
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b_) for a, b_ in evs]))
+        res[k] = {"ms_per_batch": ms, "samples_per_s": n / (ms * 1e-3)}
+    # FP64 oracle checks on 16 samples
+    m = O.Model(s, synth.GRAVITY)
+    (_, _, dqT, dqdT) = [x.cpu().numpy().reshape(n, -1) for x in outs["jvp"]]
+    gq0, gqd0, gtau = [x.cpu().numpy().reshape(n, -1) for x in outs["vjp"]]
+    ej, ev = [], []
+    h = 1e-30
+    for i in rng.choice(n, 16, replace=False):
+        cq, cqd = O.rollout_complex(m, q[i].astype(complex), qd[i].astype(complex), (tau[i] + 1j * h * dtau[i])[None], dt)
+        ej.append(max(_rel(dqT[i], cq.imag / h), _rel(dqdT[i], cqd.imag / h)))
+        g = O.rollout_grad(m, q[i], qd[i], tau[i][None], dt, wq[i], wqd[i])
+        ev.append(max(_rel(gq0[i], g[0]), _rel(gqd0[i], g[1]), _rel(gtau[i], g[2][0])))
+    print(json.dumps({"metric": "one-step derivative samples/s (FP32, 1 GPU) for RL sample and policy enhancement",
+                      "config": {"workload": f"{n} samples of one free-floating quadruped (base + 4x3 revolute, "
+                                             "13 bodies, n_q=19, n_v=18) at random states, one step dt=1e-3",
+                                 "samples": n, "tiling": sim.tiling, "autotune": tune, "create_s": t_create},
+                      "dtype": "f32", "data": "synthetic", "results": res,
+                      "fp64_oracle_rel_err_16_samples": {"jvp_max": max(ej), "vjp_max": max(ev)},
+                      "nonfinite_outputs": sim.status()}))
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-6))
+
+
 def trajopt_bench(args, torch, dev):
     """Trajectory optimisation: 2048 chains of 5-50 links, T=1000, Adam on
     tau; reports DOF-steps/s per iteration (forward+adjoint of every chain),
@@ -291,6 +385,8 @@ def main():
                     help="time forward+adjoint and record peak memory for K in 1,10,100 and store-all")
     ap.add_argument("--trajopt", type=int, default=0,
                     help="run this many Adam iterations of trajectory optimisation (chains_2048 workload)")
+    ap.add_argument("--rl", type=int, default=0,
+                    help="one-step JVP/VJP throughput for RL on this many quadruped samples (Sec. 5)")
     ap.add_argument("--T", type=int, default=None, help="override the horizon (reduced runs only)")
     ap.add_argument("--tiling", default="auto",
                     help="launch geometry: 'auto' (the library's autotuner, before the timed region), 'default' "
@@ -325,6 +421,8 @@ def main():
 
     if args.trajopt:
         return trajopt_bench(args, torch, dev)
+    if args.rl:
+        return rl_bench(args, torch, dev)
 
     t_gen = time.perf_counter()
     b = synth.workload(args.workload, T=args.T, tau_dtype=np.float32)
