@@ -227,17 +227,21 @@ __device__ __forceinline__ V6<S> st_vel6(const State<S, FREE>& s) {
   return zero6<S>();
 }
 
+// Every member is assigned on every path (value selects, masked loads), so
+// the compiler keeps the state in registers instead of selecting which
+// member a load goes to.
 template <typename S, bool FREE>
 __device__ __forceinline__ void load_state(State<S, FREE>& s, const Lane& l, const S* q, const S* qd) {
-  if (l.revolute()) {
-    s.q[0] = q[l.qidx];
-    s.qd[0] = qd[l.vidx];
-  } else if constexpr (FREE) {
-    if (l.jtype == 1) {
+  if constexpr (FREE) {
+    const bool rev = l.revolute(), fr = l.jtype == 1;
 #pragma unroll
-      for (int k = 0; k < 7; ++k) s.q[k] = q[l.qidx + k];
+    for (int k = 0; k < 7; ++k) s.q[k] = ((k == 0 && rev) || fr) ? q[l.qidx + k] : s.q[k];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) s.qd[k] = qd[l.vidx + k];
+    for (int k = 0; k < 6; ++k) s.qd[k] = ((k == 0 && rev) || fr) ? qd[l.vidx + k] : s.qd[k];
+  } else {
+    if (l.revolute()) {
+      s.q[0] = q[l.qidx];
+      s.qd[0] = qd[l.vidx];
     }
   }
 }
@@ -292,42 +296,47 @@ __device__ __forceinline__ void report_nonfinite(int* status, int n) {
   if (n > 0) atomicAdd(status, n);
 }
 
-// stored state records (see state_record): [2][nslots] then [11][nfree]
+// stored state records (see state_record): [2][nslots] then [11][nfree].
+// The second row holds p.y of a free root or qd of a revolute link; it is
+// chosen by value selects, not by selecting which member to address, so
+// that the state stays in registers.
 template <typename S, bool FREE>
 __device__ __forceinline__ void put_slot(const State<S, FREE>& s, S* base, int nslots, int nfree, int slot,
                                          int fidx) {
+  base[slot] = s.q[0];
   if constexpr (FREE) {
-    if (fidx >= 0) {
-      base[slot] = s.q[0];
-      base[nslots + slot] = s.q[1];
+    const bool fr = fidx >= 0;
+    base[nslots + slot] = fr ? s.q[1] : s.qd[0];
+    if (fr) {
       S* ex = base + 2 * (size_t)nslots;
 #pragma unroll
       for (int k = 0; k < 5; ++k) ex[(size_t)k * nfree + fidx] = s.q[2 + k];
 #pragma unroll
       for (int k = 0; k < 6; ++k) ex[(size_t)(5 + k) * nfree + fidx] = s.qd[k];
-      return;
     }
+  } else {
+    base[nslots + slot] = s.qd[0];
   }
-  base[slot] = s.q[0];
-  base[nslots + slot] = s.qd[0];
 }
 template <typename S, bool FREE>
 __device__ __forceinline__ void get_slot(State<S, FREE>& s, const S* base, int nslots, int nfree, int slot,
                                          int fidx) {
+  s.q[0] = base[slot];
+  const S second = base[nslots + slot];
   if constexpr (FREE) {
-    if (fidx >= 0) {
-      s.q[0] = base[slot];
-      s.q[1] = base[nslots + slot];
+    const bool fr = fidx >= 0;
+    s.q[1] = fr ? second : s.q[1];
+    s.qd[0] = fr ? s.qd[0] : second;
+    if (fr) {
       const S* ex = base + 2 * (size_t)nslots;
 #pragma unroll
       for (int k = 0; k < 5; ++k) s.q[2 + k] = ex[(size_t)k * nfree + fidx];
 #pragma unroll
       for (int k = 0; k < 6; ++k) s.qd[k] = ex[(size_t)(5 + k) * nfree + fidx];
-      return;
     }
+  } else {
+    s.qd[0] = second;
   }
-  s.q[0] = base[slot];
-  s.qd[0] = base[nslots + slot];
 }
 
 // Writes a link's inertial-parameter gradient, turned from the kernels'
