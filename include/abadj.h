@@ -186,22 +186,44 @@ int sim_set_tiling(sim_t h, const sim_tiling_t *tiling);
 int sim_autotune(sim_t h, int K, int T_probe, void *stream, sim_tiling_t *chosen, double *ms_per_step);
 
 /* Bytes of workspace needed by sim_forward/sim_backward for T steps with a
- * checkpoint every K >= 1 steps (K > 1 adds a K-state replay buffer), or,
+ * checkpoint every K >= 1 steps (K > 1 adds a K-state replay buffer); for
+ * K < 0, binomial checkpointing with s = -K snapshots (s + 1 state records:
+ * the backward pass rebuilds every state from x^0 and the snapshots on the
+ * schedule of sim_checkpoint_schedule, the memory floor of App. B's
+ * trade-off); or,
  * for K == 0 (store-all), every step's initial state and all per-link
  * intermediates the reverse passes read (56 numbers per link and step;
  * three cheap by-products are rebuilt from them), so the backward pass
  * reruns none of the ABA sweeps.  Pure function of (h, T, K). */
 int sim_workspace_bytes(sim_t h, int T, int K, size_t *bytes);
 
+/* Binomial checkpointing schedule for reversing T steps with s snapshots
+ * (the recursion of Griewank's "revolve": a segment of l steps is advanced
+ * to a split point m, snapshotted there, its tail reversed with one
+ * snapshot fewer and then its head with all of them; m is taken from the
+ * binomial bound beta(s, t) = C(s + t, s) so that no step is advanced more
+ * than the minimal number of times).  Pure host function, used by
+ * sim_backward for K = -s and exposed for planning and testing.  actions
+ * (nullable, capacity pairs) receives (op, arg) int32 pairs: op & 7 =
+ * 0 RESTORE (slot op >> 3, time arg), 1 ADVANCE (arg steps), 2 TAKESHOT
+ * (slot op >> 3), 3 ADJOINT (reverse step arg); slot 0 holds x^0.
+ * *n_actions receives the count, *advanced (nullable) the number of plain
+ * steps advanced (the recompute beyond one re-evaluation per step).
+ * Errors: SIM_ERR_INVALID_ARG (T < 0, s outside 1..4096, capacity too
+ * small). */
+int sim_checkpoint_schedule(int T, int s, int32_t *actions, int capacity, int *n_actions,
+                            long long *advanced);
+
 /* Forward rollout of T steps of size dt (Sec. 3; Sec. 4.1 time
  * integration).  q0 [nq], qd0 [nv], tau [T][nu] -> qT [nq], qdT [nv];
  * traj (nullable) [T][nq + nv].  With a workspace, the initial state of
  * every K-th step (K >= 1) is stored there for sim_backward (Sec. 4.2;
  * App. B), or with K == 0 every step's state and intermediates (store-all,
- * the memory-hungry alternative the checkpointing replaces);
+ * the memory-hungry alternative the checkpointing replaces), or with K < 0
+ * (binomial checkpointing) only x^0;
  * workspace == NULL runs the plain forward pass (nothing stored).
- * Errors: SIM_ERR_INVALID_ARG (T < 0, K < 0, dt not finite or <= 0, null
- * required pointer), SIM_ERR_WORKSPACE_TOO_SMALL, SIM_ERR_HIP (launch). */
+ * Errors: SIM_ERR_INVALID_ARG (T < 0, K < -4096, dt not finite or <= 0,
+ * null required pointer), SIM_ERR_WORKSPACE_TOO_SMALL, SIM_ERR_HIP. */
 int sim_forward(sim_t h, const void *q0, const void *qd0, const void *tau, double dt, int T, int K,
                 void *qT, void *qdT, void *traj, void *workspace, size_t workspace_bytes,
                 void *stream);
@@ -212,6 +234,10 @@ int sim_forward(sim_t h, const void *q0, const void *qd0, const void *tau, doubl
  * gtraj (nullable) [T][nq + nv] = dL/dtraj.  Outputs (overwritten, not
  * accumulated): gq0 [nq], gqd0 [nv], gtau [T][nu].  Reads the checkpoints
  * in the workspace and, for K > 1, uses the rest of it as replay scratch.
+ * For K < 0 it runs the binomial schedule of sim_checkpoint_schedule(T, -K)
+ * with the workspace's snapshot slots; the schedule is built and uploaded
+ * (synchronously) on the first call with a new (T, K) and cached on the
+ * handle, so that first call must not be made during stream capture.
  * For a free root, gq0's quaternion entries are the gradient with respect
  * to the raw components under the rotation formula
  * R = (w^2 - u.u) I + 2 u u^T + 2 w [u]x; only their component tangent to

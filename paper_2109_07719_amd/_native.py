@@ -25,7 +25,7 @@ SIM_MAX_LINKS = 64
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_status", "sim_get_tiling", "sim_set_tiling", "sim_autotune",
             "sim_workspace_bytes",
-            "sim_forward", "sim_forward_jvp",
+            "sim_checkpoint_schedule", "sim_forward", "sim_forward_jvp",
             "sim_backward", "sim_aba", "sim_flops", "sim_last_error")
 
 
@@ -89,6 +89,8 @@ def lib():
         L.sim_forward.restype = I
         L.sim_backward.argtypes = [P, P, D, I, I, P, P, P, P, P, P, P, P, Z, P]
         L.sim_backward.restype = I
+        L.sim_checkpoint_schedule.argtypes = [I, I, P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong)]
+        L.sim_checkpoint_schedule.restype = I
         L.sim_forward_jvp.argtypes = [P, P, P, P, P, P, P, D, I, P, P, P, P, P, P, P]
         L.sim_forward_jvp.restype = I
         L.sim_aba.argtypes = [P, P, P, P, P, P]

@@ -67,10 +67,20 @@ struct BwdArgs {
   S* gq0;
   S* gqd0;
   S* gtau;
-  const S* ck;
+  S* ck;           // checkpoints (K < 0: x^0 and the snapshot slots, written here)
   S* scratch;      // K > 1: [K][state width][nslots]
   S* gparam;       // nullable: [n_links][10] inertial-parameter gradients
+  const int32_t* sched;  // K < 0: binomial checkpointing actions, (op, arg) pairs
+  int nsched;
 };
+
+// Actions of a binomial checkpointing schedule (K < 0, s = -K snapshots).
+// op & 7 is the action, op >> 3 a snapshot slot (slot 0 holds x^0):
+//   RESTORE slot, t : the current state becomes the snapshot (x^t)
+//   ADVANCE n       : n plain steps from the current state
+//   TAKESHOT slot   : store the current state in the slot
+//   ADJOINT t       : reverse step t from the current state x^t
+enum SchedOp { SCH_RESTORE = 0, SCH_ADVANCE = 1, SCH_TAKESHOT = 2, SCH_ADJOINT = 3 };
 
 // forward-mode (tangent) rollout: values and one tangent direction
 template <typename S>

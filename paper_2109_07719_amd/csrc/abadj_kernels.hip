@@ -850,6 +850,31 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
       }
       bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, st, tau, t, xb1, nonfin, pg);
     }
+  } else if (A.K < 0) {
+    // binomial checkpointing: every wave runs the same host-built schedule
+    // (uniform control flow; the actions are read through the scalar path)
+    State<S, FREE> cur = {};
+    int tc = 0;
+    for (int i = 0; i < A.nsched; ++i) {
+      const int op = A.sched[2 * i], arg = A.sched[2 * i + 1];
+      const int what = op & 7, slot = op >> 3;
+      if (what == SCH_RESTORE) {
+        if (act) get_slot(cur, A.ck + (size_t)slot * RW, ns, nf, l.slot, l.fidx);
+        tc = arg;
+      } else if (what == SCH_ADVANCE) {
+        for (int j = 0; j < arg; ++j, ++tc) {
+          const S tau = rev ? A.tau[(size_t)tc * nu + l.uidx] : S(0);
+          Step<S> o;
+          aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, cur, tau, maxd, xb, o);
+          if (act) integrate_lane(cur, l, o, A.dt);
+        }
+      } else if (what == SCH_TAKESHOT) {
+        if (act) put_slot(cur, A.ck + (size_t)slot * RW, ns, nf, l.slot, l.fidx);
+      } else {
+        const S tau = rev ? A.tau[(size_t)arg * nu + l.uidx] : S(0);
+        bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, cur, tau, arg, xb1, nonfin, pg);
+      }
+    }
   } else {
     const int ncp = (A.T + A.K - 1) / A.K;
     for (int s = ncp - 1; s >= 0; --s) {

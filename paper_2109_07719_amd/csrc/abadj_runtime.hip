@@ -26,6 +26,7 @@ int fail(int code, const std::string& msg) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr int kMaxSnapshots = 4096;
 
 }  // namespace
 
@@ -37,6 +38,10 @@ struct sim_handle {
   bool eti = false;  // every revolute joint frame is the identity after canonicalisation
   bool chain = false;  // every system is a fixed-base serial chain
   aba::Tiling tiling;  // launch geometry
+  // binomial checkpointing schedule cached on the device for (sched_T, sched_s)
+  int32_t* d_sched = nullptr;
+  size_t d_sched_cap = 0;
+  int sched_T = -1, sched_s = -1, sched_n = 0;
   double g[3] = {0, 0, 0};
   int32_t* d_ci = nullptr;
   void* d_cf = nullptr;
@@ -97,6 +102,7 @@ size_t elem(const sim_handle* h) { return h->dtype == SIM_F64 ? sizeof(double) :
 
 size_t ckpt_bytes(const sim_handle* h, int T, int K) {
   const size_t rec = aba::state_record(h->nslots, h->nfree);
+  if (K < 0) return align256((size_t)(1 - K) * rec * elem(h));  // x^0 and -K snapshots
   if (K == 0) return align256((size_t)T * (rec + (size_t)aba::tape_width() * h->nslots) * elem(h));
   const size_t ncp = (T > 0) ? (size_t)((T + K - 1) / K) : 0;
   return align256(ncp * rec * elem(h));
@@ -104,6 +110,78 @@ size_t ckpt_bytes(const sim_handle* h, int T, int K) {
 size_t scratch_bytes(const sim_handle* h, int K) {
   if (K <= 1) return 0;
   return align256((size_t)K * aba::state_record(h->nslots, h->nfree) * elem(h));
+}
+
+// ---- binomial checkpointing (App. B's trade-off taken to its limit: T
+// steps reversed with s snapshots).  beta(s, t) = C(s + t, s) is the number
+// of steps that s free snapshots can reverse when no step is advanced more
+// than t times; a segment of l steps is split at m with
+// l - beta(s - 1, t) <= m <= beta(s, t - 1) (t minimal with beta(s, t) >= l):
+// advance m steps, snapshot, reverse the last l - m steps with s - 1 free
+// snapshots, then the first m with s (the binomial recursion of Griewank's
+// "revolve" checkpointing).
+struct Schedule {
+  std::vector<int32_t> a;  // (op, arg) pairs, see aba::SchedOp
+  long long advanced = 0;  // plain steps advanced (the recompute count)
+  int cur = 0;             // time of the state the schedule holds in registers
+  int s_total = 0;
+  void op(int what, int slot, int arg) {
+    a.push_back(what + 8 * slot);
+    a.push_back(arg);
+  }
+  void restore(int slot, int t) {
+    if (cur != t) op(aba::SCH_RESTORE, slot, t);
+    cur = t;
+  }
+};
+double beta_(int s, int t) {
+  double b = 1.0;  // C(s + t, s), saturating
+  for (int k = 1; k <= s; ++k) {
+    b = b * (double)(t + k) / (double)k;
+    if (b > 1e18) return 1e18;
+  }
+  return b;
+}
+void revolve_(Schedule& S, int a, int l, int s, int slot_a) {
+  while (l > 0) {
+    if (l == 1) {
+      S.restore(slot_a, a);
+      S.op(aba::SCH_ADJOINT, 0, a);
+      return;
+    }
+    if (s == 0) {
+      for (int k = l - 1; k >= 0; --k) {
+        S.restore(slot_a, a);
+        if (k > 0) {
+          S.op(aba::SCH_ADVANCE, 0, k);
+          S.advanced += k;
+          S.cur = a + k;
+        }
+        S.op(aba::SCH_ADJOINT, 0, a + k);
+      }
+      return;
+    }
+    int t = 1;
+    while (beta_(s, t) < l) ++t;
+    int m = l - (int)std::min<double>(beta_(s - 1, t), (double)l);
+    m = std::max(1, std::min(m, l - 1));
+    const int slot = S.s_total - s + 1;
+    S.restore(slot_a, a);
+    S.op(aba::SCH_ADVANCE, 0, m);
+    S.advanced += m;
+    S.cur = a + m;
+    S.op(aba::SCH_TAKESHOT, slot, 0);
+    revolve_(S, a + m, l - m, s - 1, slot);
+    l = m;  // then the first m steps, with all s snapshots free again
+  }
+}
+Schedule make_schedule(int T, int s) {
+  Schedule S;
+  S.s_total = s;
+  S.cur = 0;  // the kernel starts from x^0 (slot 0) loaded explicitly
+  S.op(aba::SCH_RESTORE, 0, 0);
+  revolve_(S, 0, T, s, 0);
+  return S;
 }
 
 // Rotation R with R a = e_z for a unit axis a (Rodrigues about a x e_z).
@@ -170,6 +248,8 @@ void release(sim_handle* h) {
   if (h->d_wmaxd) (void)hipFree(h->d_wmaxd);
   if (h->d_status) (void)hipFree(h->d_status);
   h->d_status = nullptr;
+  if (h->d_sched) (void)hipFree(h->d_sched);
+  h->d_sched = nullptr;
   h->d_ci = nullptr;
   h->d_cf = nullptr;
   h->d_wmaxd = nullptr;
@@ -507,15 +587,59 @@ int sim_set_tiling(sim_t h, const sim_tiling_t* t) {
 
 int sim_workspace_bytes(sim_t h, int T, int K, size_t* bytes) {
   if (!h || !bytes) return fail(SIM_ERR_INVALID_ARG, "sim_workspace_bytes: null argument");
-  if (T < 0 || K < 0) return fail(SIM_ERR_INVALID_ARG, "sim_workspace_bytes: need T >= 0 and K >= 0");
+  if (T < 0 || K < -kMaxSnapshots)
+    return fail(SIM_ERR_INVALID_ARG, "sim_workspace_bytes: need T >= 0 and K >= -" + std::to_string(kMaxSnapshots));
   *bytes = ckpt_bytes(h, T, K) + scratch_bytes(h, K);
+  return SIM_OK;
+}
+
+// The device copy of the binomial schedule for (T, s), built and uploaded
+// (synchronously) the first time that pair is used; later calls, and graph
+// captures of them, reuse it.
+static int ensure_schedule(sim_handle* h, int T, int s, hipStream_t stream) {
+  if (h->sched_T == T && h->sched_s == s) return SIM_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(SIM_ERR_INVALID_ARG, "sim_backward: the first call with a new (T, K < 0) uploads its checkpointing "
+                                     "schedule and cannot be captured; run it once outside the capture");
+  const Schedule S = make_schedule(T, s);
+  const size_t bytes = std::max<size_t>(S.a.size(), 2) * sizeof(int32_t);
+  if (bytes > h->d_sched_cap) {
+    if (h->d_sched) (void)hipFree(h->d_sched);
+    h->d_sched = nullptr;
+    h->d_sched_cap = 0;
+    if (hipMalloc(&h->d_sched, bytes) != hipSuccess) return fail(SIM_ERR_HIP, "sim_backward: schedule allocation failed");
+    h->d_sched_cap = bytes;
+  }
+  if (!S.a.empty() && hipMemcpy(h->d_sched, S.a.data(), S.a.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(SIM_ERR_HIP, "sim_backward: schedule upload failed");
+  h->sched_T = T;
+  h->sched_s = s;
+  h->sched_n = (int)(S.a.size() / 2);
+  return SIM_OK;
+}
+
+int sim_checkpoint_schedule(int T, int s, int32_t* actions, int capacity, int* n_actions, long long* advanced) {
+  g_err.clear();
+  if (T < 0 || s < 1 || s > kMaxSnapshots || !n_actions)
+    return fail(SIM_ERR_INVALID_ARG, "sim_checkpoint_schedule: need T >= 0, 1 <= s <= " +
+                                         std::to_string(kMaxSnapshots) + " and n_actions");
+  const Schedule S = make_schedule(T, s);
+  *n_actions = (int)(S.a.size() / 2);
+  if (advanced) *advanced = S.advanced;
+  if (actions) {
+    if (capacity < *n_actions) return fail(SIM_ERR_INVALID_ARG, "sim_checkpoint_schedule: capacity too small");
+    std::memcpy(actions, S.a.data(), S.a.size() * sizeof(int32_t));
+  }
   return SIM_OK;
 }
 
 static int check_run(sim_t h, double dt, int T, int K, const char* who) {
   if (!h) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": null handle");
   if (T < 0) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": T must be >= 0");
-  if (K < 0) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": K must be >= 0 (0 = store-all)");
+  if (K < -kMaxSnapshots)
+    return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": K must be >= -" + std::to_string(kMaxSnapshots) +
+                                         " (K < 0: binomial checkpointing with -K snapshots; 0: store-all)");
   if (!std::isfinite(dt) || !(dt > 0)) return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": dt must be finite and > 0");
   return SIM_OK;
 }
@@ -540,7 +664,7 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
     a.P = packed<double>(h);
     a.dt = dt;
     a.T = T;
-    a.K = K;
+    a.K = (K < 0) ? std::max(T, 1) : K;  // K < 0: only x^0 is stored
     a.q0 = (const double*)q0;
     a.qd0 = (const double*)qd0;
     a.tau = (const double*)tau;
@@ -554,7 +678,7 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
     a.P = packed<float>(h);
     a.dt = (float)dt;
     a.T = T;
-    a.K = K;
+    a.K = (K < 0) ? std::max(T, 1) : K;  // K < 0: only x^0 is stored
     a.q0 = (const float*)q0;
     a.qd0 = (const float*)qd0;
     a.tau = (const float*)tau;
@@ -582,6 +706,10 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     return fail(SIM_ERR_WORKSPACE_TOO_SMALL, "sim_backward: workspace of " + std::to_string(workspace_bytes) +
                                                  " bytes, need " + std::to_string(need));
   const size_t ck = ckpt_bytes(h, T, K);
+  if (K < 0) {
+    rc = ensure_schedule(h, T, -K, (hipStream_t)stream);
+    if (rc) return rc;
+  }
   hipError_t e;
   if (h->dtype == SIM_F64) {
     aba::BwdArgs<double> a;
@@ -596,8 +724,10 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gq0 = (double*)gq0;
     a.gqd0 = (double*)gqd0;
     a.gtau = (double*)gtau;
-    a.ck = (const double*)workspace;
+    a.ck = (double*)workspace;
     a.scratch = (K > 1) ? (double*)((char*)workspace + ck) : nullptr;
+    a.sched = (K < 0) ? h->d_sched : nullptr;
+    a.nsched = (K < 0) ? h->sched_n : 0;
     a.gparam = (double*)gparam;
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   } else {
@@ -613,8 +743,10 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gq0 = (float*)gq0;
     a.gqd0 = (float*)gqd0;
     a.gtau = (float*)gtau;
-    a.ck = (const float*)workspace;
+    a.ck = (float*)workspace;
     a.scratch = (K > 1) ? (float*)((char*)workspace + ck) : nullptr;
+    a.sched = (K < 0) ? h->d_sched : nullptr;
+    a.nsched = (K < 0) ? h->sched_n : 0;
     a.gparam = (float*)gparam;
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   }

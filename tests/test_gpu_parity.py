@@ -308,7 +308,7 @@ def test_invalid_calls_raise():
     with pytest.raises(SimError):
         sim.forward(q0, qd0, tau, -1.0)
     with pytest.raises(SimError):
-        sim.forward(q0, qd0, tau, b.dt, K=-1)
+        sim.forward(q0, qd0, tau, b.dt, K=-5000)   # K < 0 is binomial checkpointing with at most 4096 snapshots
     small = torch.empty(8, dtype=torch.uint8, device=DEV)
     with pytest.raises(SimError):
         sim.forward(q0, qd0, tau, b.dt, K=1, workspace=small)
@@ -494,3 +494,46 @@ def test_status_counts_nonfinite_outputs():
     qd_bad[1] = float("inf")
     sim.aba(q0, qd_bad, tau[0].contiguous())
     assert sim.status() > 0
+
+
+@pytest.mark.parametrize("s", [1, 3, 8])
+@pytest.mark.parametrize("kind", ["mixed", "chains"])
+def test_binomial_checkpointing_matches_uniform_checkpoints(kind, s):
+    """K = -s (binomial schedule, s snapshots) repeats the same step
+    arithmetic as segment replay, so gradients (and parameter gradients)
+    are bitwise those of K = 3 on the same one-wave kernel."""
+    if kind == "mixed":
+        b = _mixed_batch(70)
+    else:
+        b = synth.round_to_f32(synth.make_batch([synth.chain_system(n, 6100 + n, 70) for n in (1, 4, 7, 12)], 1e-3))
+    sim = _sim(b)
+    sim.set_tiling(4, 1, 0)
+    outs = []
+    for K in (3, -s):
+        q0, qd0, tau, ws, qT, qdT, _ = _rollout(sim, b, K=K)
+        g = sim.backward(tau, b.dt, K, ws, 2 * qT, torch.zeros_like(qdT), params=True)
+        outs.append([x.cpu().numpy() for x in (qT, qdT, *g)])
+        assert sim.status() == 0
+    for a, c in zip(*outs):
+        assert np.array_equal(a, c)
+    assert sim.workspace_bytes(70, -s) < sim.workspace_bytes(70, 1)
+
+
+def test_binomial_checkpointing_against_oracle_and_in_a_graph():
+    b = _batch("quad_1024", 4, 150)
+    gq0, gqd0, gtau = _grad_parity(b, K=-5)
+    # after one call outside capture (schedule upload), the pass can be captured
+    sim = _sim(b)
+    q0, qd0, tau, ws, qT, qdT, _ = _rollout(sim, b, K=-5)
+    gqT, gqdT = 2 * qT, torch.zeros_like(qdT)
+    out = sim.backward(tau, b.dt, -5, ws, gqT, gqdT)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cap = sim.backward(tau, b.dt, -5, ws, gqT, gqdT)
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        for x, y in zip(out, cap):
+            assert torch.equal(x, y)
+    assert np.allclose(out[2].cpu().numpy(), gtau, rtol=1e-4, atol=1e-6)

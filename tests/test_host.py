@@ -158,3 +158,54 @@ def test_lane_arithmetic_fp32_forward_dynamics_error():
         ref = O.fd(O.Model(s), q, qd, tau)
         errs.append(rel(emu_fd(s, q, qd, tau, f32=True), ref))
     assert max(errs) < 1e-5, max(errs)
+
+
+def _simulate_schedule(T, s):
+    """Run a binomial checkpointing schedule symbolically: every ADJOINT
+    must come in the order T-1, ..., 0 with the state at its own time."""
+    from paper_2109_07719_amd import _native
+    L = _native.lib()
+    n, adv = ctypes.c_int(), ctypes.c_longlong()
+    assert L.sim_checkpoint_schedule(T, s, None, 0, ctypes.byref(n), ctypes.byref(adv)) == 0
+    buf = (ctypes.c_int32 * (2 * max(n.value, 1)))()
+    assert L.sim_checkpoint_schedule(T, s, buf, n.value, ctypes.byref(n), ctypes.byref(adv)) == 0
+    acts = [(buf[2 * i], buf[2 * i + 1]) for i in range(n.value)]
+    slots = {0: 0}
+    cur, adjoints, advanced = None, [], 0
+    for op, arg in acts:
+        what, slot = op & 7, op >> 3
+        if what == 0:
+            assert slots.get(slot) == arg, (T, s, "restore of a slot that does not hold that time")
+            cur = arg
+        elif what == 1:
+            assert cur is not None and arg > 0
+            cur += arg
+            advanced += arg
+        elif what == 2:
+            assert 1 <= slot <= s and cur is not None
+            slots[slot] = cur
+        else:
+            assert what == 3 and cur == arg, (T, s, "adjoint away from its state")
+            adjoints.append(arg)
+    assert adjoints == list(range(T - 1, -1, -1))
+    assert advanced == adv.value
+    return advanced
+
+
+def test_binomial_schedule_reverses_every_step_in_order():
+    for T in range(0, 40):
+        for s in range(1, 6):
+            _simulate_schedule(T, s)
+
+
+def test_binomial_schedule_recompute_bound():
+    """With s snapshots and repetition number r (the least r with
+    C(s + r, s) >= T), no step is advanced more than r times, so the schedule
+    advances at most r * T steps; one snapshot gives the quadratic count."""
+    from math import comb
+    for T, s in [(1000, 4), (5000, 10), (50000, 16), (50000, 3), (200, 1)]:
+        r = next(r for r in range(1, T + 1) if comb(s + r, s) >= T)
+        adv = _simulate_schedule(T, s)
+        assert adv <= r * T, (T, s, adv, r)
+        if s == 1:
+            assert adv == T * (T - 1) // 2
