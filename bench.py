@@ -155,19 +155,20 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
 
 def memory_sweep(args, torch, dev, sim, b):
     """Forward+adjoint time and peak device memory for checkpoint intervals
-    K = 1, 10, 100 and store-all (App. B ablation; Sec. 6 memory tables)."""
+    K = 1, 10, 100, store-all and binomial checkpointing with 64 and 16
+    snapshots (App. B ablation; Sec. 6 memory tables)."""
     T, dt = b.T, b.dt
     f32 = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
     q0, qd0 = f32(b.q0), f32(b.qd0)
     tau = torch.from_numpy(b.tau).to(dev)
     rows = []
-    for K in (1, 10, 100, 0):
+    for K in (1, 10, 100, 0, -64, -16):
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         torch.cuda.reset_peak_memory_stats()
         base = torch.cuda.memory_allocated()
         need = sim.workspace_bytes(T, K)
-        row = {"K": K if K else "store-all", "workspace_bytes": need}
+        row = {"K": K if K > 0 else ("store-all" if K == 0 else f"binomial, {-K} snapshots"), "workspace_bytes": need}
         if args.tiling == "auto":
             row["autotune"] = sim.autotune(K=K, T_probe=min(T, 200))
         row["tiling"] = sim.tiling

@@ -180,7 +180,7 @@ int sim_set_tiling(sim_t h, const sim_tiling_t *tiling);
  * NULL = default), and must not be called during stream capture.
  * chosen (nullable) receives the winner, ms_per_step (nullable) its
  * forward+backward time per probe step.  Arithmetic is unaffected by the
- * choice.  Errors: SIM_ERR_INVALID_ARG (K < 0, T_probe outside 1..100000),
+ * choice.  Errors: SIM_ERR_INVALID_ARG (K < -4096, T_probe outside 1..100000),
  * SIM_ERR_HIP (probe allocation or launch failed; the tiling is left as it
  * was). */
 int sim_autotune(sim_t h, int K, int T_probe, void *stream, sim_tiling_t *chosen, double *ms_per_step);

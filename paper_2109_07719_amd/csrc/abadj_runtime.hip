@@ -824,8 +824,9 @@ int sim_aba(sim_t h, const void* q, const void* qd, const void* tau, void* qdd, 
 int sim_autotune(sim_t h, int K, int T_probe, void* stream, sim_tiling_t* chosen, double* ms_per_step) {
   g_err.clear();
   if (!h) return fail(SIM_ERR_INVALID_ARG, "sim_autotune: null handle");
-  if (K < 0 || T_probe < 1 || T_probe > 100000)
-    return fail(SIM_ERR_INVALID_ARG, "sim_autotune: need K >= 0 and 1 <= T_probe <= 100000");
+  if (K < -kMaxSnapshots || T_probe < 1 || T_probe > 100000)
+    return fail(SIM_ERR_INVALID_ARG, "sim_autotune: need K >= -" + std::to_string(kMaxSnapshots) +
+                                         " and 1 <= T_probe <= 100000");
   hipStream_t st = (hipStream_t)stream;
   const size_t es = elem(h);
   // store-all probes are capped at 2 GiB of workspace

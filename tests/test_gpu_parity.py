@@ -466,7 +466,7 @@ def test_autotune_keeps_a_valid_geometry_and_the_results(K):
     for a, c in zip(out0, out):
         assert rel(c, a) < 1e-5
     with pytest.raises(Exception):
-        sim.autotune(K=-1)
+        sim.autotune(K=-5000)
     with pytest.raises(Exception):
         sim.autotune(K=1, T_probe=0)
 
