@@ -214,10 +214,11 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
         for (int c = 0; c < 6; ++c) b->IA[6 * r + c] -= w[r] * l->ap[c];
       continue;
     }
-    const double *ax = m->axis + 3 * i;
+    double Sv[6];
+    motion_subspace_r(m, i, Sv);
     /* a = ap + S qdd */
     for (int k = 0; k < 6; ++k) b->ap[k] += b->a[k];
-    b->qdd += ax[0] * b->a[0] + ax[1] * b->a[1] + ax[2] * b->a[2];
+    for (int k = 0; k < 6; ++k) b->qdd += Sv[k] * b->a[k];
     /* qdd = (u - U^T ap) / D */
     const double gq = b->qdd / l->D;
     b->u += gq;
@@ -236,7 +237,8 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
     const tape_t *l = &L[i];
     link_bar *b = &B[i];
     const int lam = m->parent[i];
-    const double *ax = m->axis + 3 * i;
+    double Sv[6];
+    motion_subspace_r(m, i, Sv);
     if (lam >= 0) {
       const link_bar *bl = &B[lam];
       /* pA_lam += X^T pa */
@@ -277,12 +279,12 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
     }
     /* u = tau - S^T pA */
     tau_bar[ui[i]] += b->u;
-    for (int k = 0; k < 3; ++k) b->pA[k] -= ax[k] * b->u;
+    for (int k = 0; k < 6; ++k) b->pA[k] -= Sv[k] * b->u;
     /* D = S^T U */
-    for (int k = 0; k < 3; ++k) b->U[k] += ax[k] * b->D;
+    for (int k = 0; k < 6; ++k) b->U[k] += Sv[k] * b->D;
     /* U = IA S */
     for (int r = 0; r < 6; ++r)
-      for (int c = 0; c < 3; ++c) b->IA[6 * r + c] += b->U[r] * ax[c];
+      for (int c = 0; c < 6; ++c) b->IA[6 * r + c] += b->U[r] * Sv[c];
   }
 
   /* reverse of pass 1, leaves -> root */
@@ -330,16 +332,25 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
     }
     for (int k = 0; k < 6; ++k) b->vJ[k] += b->v[k];
     /* vJ = S qd */
-    qd_bar[vi[i]] += ax[0] * b->vJ[0] + ax[1] * b->vJ[1] + ax[2] * b->vJ[2];
-    /* X = XJ(q) XT:  dX/dq = plucker(dEJ/dq, 0) XT,
-       dEJ/dq = -cos q [a]x + sin q [a]x^2 */
+    double Sv[6];
+    motion_subspace_r(m, i, Sv);
+    for (int k = 0; k < 6; ++k) qd_bar[vi[i]] += Sv[k] * b->vJ[k];
+    /* X = XJ(q) XT.  Revolute: dX/dq = plucker(dEJ/dq, 0) XT with
+       dEJ/dq = -cos q [a]x + sin q [a]x^2.  Prismatic: XJ = [I 0; -[q a]x I],
+       dXJ/dq = [0 0; -[a]x 0]. */
     {
       double axx[9], ax2[9], dE[9], zero3[3] = {0, 0, 0}, dXJ[36], XT[36], dX[36];
       double qq = q[qi[i]], s = sin(qq), c = cos(qq);
       skew3_r(ax, axx);
-      mat3_mul_r(axx, axx, ax2);
-      for (int k = 0; k < 9; ++k) dE[k] = -c * axx[k] + s * ax2[k];
-      plucker_r(dE, zero3, dXJ);
+      if (m->jtype[i] == ORC_PRISMATIC) {
+        for (int k = 0; k < 36; ++k) dXJ[k] = 0;
+        for (int r = 0; r < 3; ++r)
+          for (int cc = 0; cc < 3; ++cc) dXJ[6 * (3 + r) + cc] = -axx[3 * r + cc];
+      } else {
+        mat3_mul_r(axx, axx, ax2);
+        for (int k = 0; k < 9; ++k) dE[k] = -c * axx[k] + s * ax2[k];
+        plucker_r(dE, zero3, dXJ);
+      }
       double ET[9], rT[3];
       for (int k = 0; k < 9; ++k) ET[k] = m->E_T[9 * i + k];
       for (int k = 0; k < 3; ++k) rT[k] = m->r_T[3 * i + k];

@@ -29,9 +29,13 @@
  * joint about a unit axis a with E_J(q) = I - sin q [a]x + (1 - cos q)[a]x^2,
  * gravity entered as a fictitious base acceleration.
  *
+ * Prismatic joint (type 2): the link slides by q along the unit axis a of
+ * the joint frame, X_J(q) = [I 0; -[q a]x I], motion subspace S = [0; a].
+ *
  * Free-floating root (joint type 1, only at link 0): q = (p_world[3],
  * quat[4] stored x,y,z,w), velocity = body-frame spatial velocity [w_b; v_b].
- * The root is unactuated; tau holds one entry per revolute joint.
+ * The root is unactuated; tau holds one entry per revolute or prismatic
+ * joint.
  */
 #ifndef ABA_ORACLE_H
 #define ABA_ORACLE_H
@@ -40,12 +44,14 @@
 
 #define ORC_REVOLUTE 0
 #define ORC_FREE 1
+#define ORC_PRISMATIC 2
 
 typedef struct {
   int n;                 /* number of links */
   const int *parent;     /* parent[i] < i; -1 = attached to the fixed base
                             (or, for a free root, no parent)               */
-  const int *jtype;      /* ORC_REVOLUTE or ORC_FREE (link 0 only)         */
+  const int *jtype;      /* ORC_REVOLUTE, ORC_PRISMATIC, or ORC_FREE (link 0
+                            only)                                          */
   const double *E_T;     /* 9n: fixed rotation parent->joint frame, rowmajor */
   const double *r_T;     /* 3n: joint origin in parent coordinates          */
   const double *axis;    /* 3n: joint axis in the link frame, unit length

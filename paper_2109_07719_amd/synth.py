@@ -31,6 +31,7 @@ import numpy as np
 
 REVOLUTE = 0
 FREE = 1
+PRISMATIC = 2
 GRAVITY = np.array([0.0, -9.81, 0.0])
 
 
@@ -61,7 +62,7 @@ class System:
 
     @property
     def nu(self) -> int:
-        return int(np.sum(self.jtype == REVOLUTE))
+        return int(np.sum(self.jtype != FREE))
 
     def depth(self) -> np.ndarray:
         d = np.zeros(self.n, dtype=np.int64)
@@ -145,14 +146,17 @@ def chain_system(n: int, seed: int, T: int):
 # --------------------------------------------------------------------------
 
 def tree_system(seed: int, T: int, nmin: int = 6, nmax: int = 40,
-                max_depth: int = 6, random_frames: bool = False):
+                max_depth: int = 6, random_frames: bool = False, prismatic: float = 0.0):
     """Fixed-base tree: n ~ U{nmin..nmax}; breadth-first growth where every
     node below the depth limit gets b ~ U{1,2,3} children; the first n nodes
     in BFS order are kept (the growth is redrawn if fewer than n exist).
     Axes normalize(N(0, I3)); r_T = 0.5 * random unit vector; COM ~
     U[-0.25, 0.25]^3; masses and inertias as for chains; q0, qd0 ~
     N(0, 0.1^2); tau ~ N(0, 1).  With random_frames, E_T is a random
-    rotation (not part of the benchmark workload; used to widen tests)."""
+    rotation (not part of the benchmark workload; used to widen tests).
+    With prismatic > 0, every joint becomes prismatic with that probability,
+    drawn from a separate stream (seed + 10^6) so that the other draws are
+    unchanged."""
     rng = np.random.default_rng(seed)
     n = int(rng.integers(nmin, nmax + 1))
     while True:
@@ -189,9 +193,29 @@ def tree_system(seed: int, T: int, nmin: int = 6, nmax: int = 40,
     q0 = rng.normal(0.0, 0.1, n)
     qd0 = rng.normal(0.0, 0.1, n)
     tau = rng.normal(0.0, 1.0, (T, n))
-    sys_ = System(parent=parent, jtype=np.zeros(n, dtype=np.int32), E_T=E_T,
+    jtype = np.zeros(n, dtype=np.int32)
+    if prismatic > 0:
+        jtype[np.random.default_rng(seed + 1_000_000).uniform(size=n) < prismatic] = PRISMATIC
+    sys_ = System(parent=parent, jtype=jtype, E_T=E_T,
                   r_T=r_T, axis=axis, mass=mass, com=com, Ic=Ic)
     return sys_, q0, qd0, tau
+
+
+def cartpole_system(seed: int, T: int):
+    """A cart sliding along x (prismatic root, axis (1, 0, 0)) carrying a
+    pole on a z-axis revolute joint at the cart origin; pole COM (l, 0, 0)
+    with l ~ U(0.3, 0.8); cart mass U(0.5, 2), pole mass U(0.1, 0.5), pole
+    inertias U(0.001, 0.01); q0, qd0 ~ N(0, 0.1^2); tau ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    l = rng.uniform(0.3, 0.8)
+    mass = np.array([rng.uniform(0.5, 2.0), rng.uniform(0.1, 0.5)])
+    Ic = np.zeros((2, 6))
+    Ic[:, :3] = rng.uniform(0.001, 0.01, (2, 3))
+    com = np.array([[0.0, 0.0, 0.0], [l, 0.0, 0.0]])
+    axis = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    sys_ = System(parent=np.array([-1, 0], dtype=np.int32), jtype=np.array([PRISMATIC, REVOLUTE], dtype=np.int32),
+                  E_T=_eye(2), r_T=np.zeros((2, 3)), axis=axis, mass=mass, com=com, Ic=Ic)
+    return sys_, rng.normal(0.0, 0.1, 2), rng.normal(0.0, 0.1, 2), rng.normal(0.0, 1.0, (T, 2))
 
 
 # --------------------------------------------------------------------------

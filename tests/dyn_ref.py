@@ -15,7 +15,8 @@ complex arrays (complex-step derivatives of inverse dynamics).
 Joint kinematics follow the package convention: a link frame is reached from
 its parent by the fixed rotation E_T and offset r_T, then a rotation by q
 about the unit axis a (coordinates map by E = E_J(q) E_T, so the
-link-to-parent rotation matrix is E^T).
+link-to-parent rotation matrix is E^T), or, for a prismatic joint (type 2),
+a translation by q along a.
 """
 from __future__ import annotations
 
@@ -81,15 +82,25 @@ def kinematics(sys_, q, qd, qdd, gravity):
             Rl, ol, wl, wdl, vl, al = R[lam], o[lam], w[lam], wd[lam], vo[lam], ao[lam]
         ET = np.asarray(sys_.E_T[i], dtype=float)
         a = np.asarray(sys_.axis[i], dtype=float)
-        rij = Rl @ np.asarray(sys_.r_T[i], dtype=float)
-        oi = ol + rij
         Rpre = Rl @ ET.T                # pre-joint frame -> world
         zi = Rpre @ a                   # world joint axis
-        Ri = Rpre @ _rot_axis(a, q[k])  # link frame -> world
-        wi = wl + zi * qd[kv]
-        wdi = wdl + zi * qdd[kv] + np.cross(wl, zi) * qd[kv]
-        voi = vl + np.cross(wl, rij)
-        aoi = al + np.cross(wdl, rij) + np.cross(wl, np.cross(wl, rij))
+        if sys_.jtype[i] == 2:
+            # prismatic: the link origin slides by q along the axis, no rotation
+            rij = Rl @ np.asarray(sys_.r_T[i], dtype=float) + zi * q[k]
+            oi = ol + rij
+            Ri = Rpre
+            wi, wdi = wl, wdl
+            voi = vl + np.cross(wl, rij) + zi * qd[kv]
+            aoi = (al + np.cross(wdl, rij) + np.cross(wl, np.cross(wl, rij)) + 2 * np.cross(wl, zi) * qd[kv]
+                   + zi * qdd[kv])
+        else:
+            rij = Rl @ np.asarray(sys_.r_T[i], dtype=float)
+            oi = ol + rij
+            Ri = Rpre @ _rot_axis(a, q[k])  # link frame -> world
+            wi = wl + zi * qd[kv]
+            wdi = wdl + zi * qdd[kv] + np.cross(wl, zi) * qd[kv]
+            voi = vl + np.cross(wl, rij)
+            aoi = al + np.cross(wdl, rij) + np.cross(wl, np.cross(wl, rij))
         R[i], o[i], w[i], wd[i], vo[i], ao[i], z[i] = Ri, oi, wi, wdi, voi, aoi, zi
         k += 1
         kv += 1
@@ -122,6 +133,8 @@ def inverse_dynamics(sys_, q, qd, qdd, gravity=(0.0, -9.81, 0.0)):
     for i in range(n):
         if sys_.jtype[i] == 1:
             out.extend(list(R[i].T @ nm[i]) + list(R[i].T @ f[i]))
+        elif sys_.jtype[i] == 2:
+            out.append(z[i] @ f[i])
         else:
             out.append(z[i] @ nm[i])
     return np.array(out)

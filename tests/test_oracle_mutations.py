@@ -46,6 +46,11 @@ MUTATIONS = [
      "first-moment adjoint sign"),
     ("aba_oracle.c", "pbar[0] += Ibar[6 * 3 + 3] + Ibar[6 * 4 + 4] + Ibar[6 * 5 + 5];",
      "pbar[0] += Ibar[6 * 3 + 3] + Ibar[6 * 4 + 4];", "dropped mass-block term"),
+    ("aba_oracle.c", "dXJ[6 * (3 + r) + cc] = -axx[3 * r + cc];", "dXJ[6 * (3 + r) + cc] = axx[3 * r + cc];",
+     "prismatic joint-transform derivative sign"),
+    ("aba_fwd.inc", "Sv[k] = prism ? 0.0 : ax[k];", "Sv[k] = ax[k];", "prismatic motion subspace with an angular part"),
+    ("aba_fwd.inc", "l->vJ[k] = 0; l->vJ[k + 3] = m->axis[3 * i + k] * qd[vi[i]];",
+     "l->vJ[k] = m->axis[3 * i + k] * qd[vi[i]]; l->vJ[k + 3] = 0;", "prismatic joint velocity as a rotation"),
 ]
 
 PINS = [
@@ -62,6 +67,8 @@ PINS = [
     lambda: pins.test_inertial_parameter_gradient_scaling_identity(0),
     lambda: pins.test_inertial_parameter_gradient_central_differences(0),
     lambda: pins.test_inertial_parameter_gradient_central_differences(1),
+    pins.test_cartpole_closed_form,
+    pins.test_rollout_gradient_complex_step_with_prismatic_joints,
 ]
 
 

@@ -23,14 +23,15 @@ def _rand_rot(rng):
     return R._quat_R(q)
 
 
-def _random_tree(parent, rng, random_frames=True):
+def _random_tree(parent, rng, random_frames=True, prismatic=False):
     n = len(parent)
     axis = rng.normal(size=(n, 3))
     axis /= np.linalg.norm(axis, axis=1, keepdims=True)
     E_T = np.stack([_rand_rot(rng) if random_frames else np.eye(3) for _ in range(n)])
     Icd = rng.uniform(0.01, 0.1, (n, 3))
     Ic = np.concatenate([Icd, rng.uniform(-0.003, 0.003, (n, 3))], axis=1)
-    return synth.System(parent=np.asarray(parent, np.int32), jtype=np.zeros(n, np.int32),
+    jtype = (rng.uniform(size=n) < 0.5).astype(np.int32) * synth.PRISMATIC if prismatic else np.zeros(n, np.int32)
+    return synth.System(parent=np.asarray(parent, np.int32), jtype=jtype,
                         E_T=E_T, r_T=rng.normal(0, 0.4, (n, 3)), axis=axis,
                         mass=rng.uniform(0.5, 2.0, n), com=rng.uniform(-0.25, 0.25, (n, 3)),
                         Ic=Ic)
@@ -532,3 +533,76 @@ def test_inertial_parameter_gradient_checkpointing_and_along():
     states = np.concatenate([np.r_[q0, qd0][None], traj[:-1]])
     along = O.adjoint_along_params(m, states, tau, 1e-3, 2 * qT, qdT)[3]
     assert np.array_equal(along, ref)
+
+
+
+# ------------------------------------------------------------- prismatic joints
+
+def test_aba_equals_dense_solve_every_tree_with_prismatic_joints():
+    """As the revolute pin, with every joint of every tree of up to 4 links
+    revolute or prismatic at random (X_J = translation by q a, S = [0; a])."""
+    rng = np.random.default_rng(12)
+    n_prism = 0
+    for n in range(1, 5):
+        for parent in all_parent_arrays(n):
+            for _ in range(2):
+                s = _random_tree(parent, rng, prismatic=True)
+                n_prism += int(np.sum(s.jtype == synth.PRISMATIC))
+                m = O.Model(s)
+                q, qd, tau = rng.normal(0, 1, n), rng.normal(0, 1, n), rng.normal(0, 1, n)
+                assert _rel(O.fd(m, q, qd, tau), R.forward_dynamics(s, q, qd, tau)) < 1e-12
+    assert n_prism > 40
+
+
+def test_cartpole_closed_form():
+    """Cart (prismatic along x) and pole (revolute about z, COM at distance l):
+    M = [[mc + mp, -mp l s], [-mp l s, Ip + mp l^2]], bias
+    [-mp l c thd^2, mp g l c] with s, c = sin, cos of the pole angle."""
+    s, _, _, _ = synth.cartpole_system(5, 1)
+    m = O.Model(s)
+    mc, mp, l, Ip, g = s.mass[0], s.mass[1], s.com[1][0], s.Ic[1][2], 9.81
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        q, qd, tau = rng.normal(0, 1.5, 2), rng.normal(0, 2, 2), rng.normal(0, 1, 2)
+        sn, cs = np.sin(q[1]), np.cos(q[1])
+        M = np.array([[mc + mp, -mp * l * sn], [-mp * l * sn, Ip + mp * l * l]])
+        h = np.array([-mp * l * cs * qd[1] ** 2, mp * g * l * cs])
+        assert _rel(O.fd(m, q, qd, tau), np.linalg.solve(M, tau - h)) < 1e-12
+
+
+def test_rollout_gradient_complex_step_with_prismatic_joints():
+    """Adjoint rollout gradient (prismatic dX/dq = -crm(S) X with S = [0; a])
+    against complex-step derivatives, on a tree with random frames and
+    prismatic joints, and on the cart-pole; parameter gradients against
+    central differences."""
+    for s, q0, qd0, tau, dt in (synth.tree_system(2011, 80, nmax=14, random_frames=True, prismatic=0.4) + (5e-4,),
+                                synth.cartpole_system(6, 150) + (1e-3,)):
+        assert np.any(s.jtype == synth.PRISMATIC)
+        m = O.Model(s)
+        qT, qdT = O.rollout(m, q0, qd0, tau, dt)
+        gq0, gqd0, gtau, gp, _, _ = O.rollout_grad_params(m, q0, qd0, tau, dt, 2 * qT, qdT)
+        h = 1e-30
+
+        def L(a, b_, t):
+            cq, cqd = O.rollout_complex(m, a, b_, t, dt)
+            return np.sum(cq ** 2) + 0.5 * np.sum(cqd ** 2)
+
+        for j in range(s.n):
+            e = np.zeros(s.n, complex)
+            e[j] = 1j * h
+            assert abs(L(q0 + e, qd0.astype(complex), tau.astype(complex)).imag / h - gq0[j]) < 1e-9 * max(1, abs(gq0[j]))
+            assert abs(L(q0.astype(complex), qd0 + e, tau.astype(complex)).imag / h - gqd0[j]) < 1e-9 * max(1, abs(gqd0[j]))
+        t0 = np.zeros_like(tau, dtype=complex)
+        t0[len(tau) // 2, s.n - 1] = 1j * h
+        assert abs(L(q0.astype(complex), qd0.astype(complex), tau + t0).imag / h - gtau[len(tau) // 2, s.n - 1]) \
+            < 1e-9 * max(1, np.abs(gtau).max())
+        th = _inertial_params(s)
+        for i in (0, s.n - 1):
+            for j in (0, 1, 4, 7):
+                hh = 1e-6 * max(1.0, abs(th[i, j]))
+                tp, tm = th.copy(), th.copy()
+                tp[i, j] += hh
+                tm[i, j] -= hh
+                fd = (_param_loss(_with_inertial_params(s, tp), q0, qd0, tau, dt)[0] -
+                      _param_loss(_with_inertial_params(s, tm), q0, qd0, tau, dt)[0]) / (2 * hh)
+                assert abs(fd - gp[i, j]) < 2e-6 * max(1.0, np.abs(gp).max())
