@@ -36,6 +36,8 @@ WORKLOADS = {
                   "checkpoint every step, forward+adjoint",
     "quad_1024": "1024 free-floating quadrupeds (base + 4x3 revolute), dt=1e-3, T=50000, "
                  "checkpoint every step, forward+adjoint",
+    "trees_prismatic_8192": "the 8192 uneven trees of trees_8192 with each joint prismatic with probability 0.3, "
+                            "dt=5e-4, T=2000, checkpoint every step, forward+adjoint",
 }
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak (dual-issue); 78.6 without packed issue
 

@@ -23,8 +23,14 @@
  *     (joint type SIM_JOINT_FREE) is allowed only at local index 0, with
  *     parent -1, and then every other link of that system has a parent.
  *   - Plucker transform parent -> link: X = [E 0; -E[r]x E] with
- *     E = E_J(q) E_T, E_J(q) = I - sin q [a]x + (1 - cos q)[a]x^2, r = r_T.
- *   - Revolute joint: one q, one qdot, one control torque.  Free root:
+ *     revolute joint (motion subspace S = [a; 0]):
+ *       E = E_J(q) E_T, E_J(q) = I - sin q [a]x + (1 - cos q)[a]x^2, r = r_T;
+ *     prismatic joint (S = [0; a], translation by q a in link coordinates):
+ *       E = E_T, r = r_T + q E_T^T a.
+ *     Both are X = X_J(q) X_T with X_J(q) = exp(-q crm(S))   (Sec. 3; the
+ *     joint models of Featherstone's spatial algebra, which Sec. 3 follows).
+ *   - Revolute or prismatic joint: one q, one qdot, one control (torque or
+ *     force).  Free root:
  *     q = (p_world[3], quat[4] stored x, y, z, w), velocity = body-frame
  *     spatial velocity [w; v] (6 entries), unactuated.
  *   - Gravity enters as a fictitious base acceleration; for a free root the
@@ -73,6 +79,7 @@ extern "C" {
 
 #define SIM_JOINT_REVOLUTE 0
 #define SIM_JOINT_FREE 1
+#define SIM_JOINT_PRISMATIC 2
 
 /* Largest number of links in one system (one wavefront of 64 lanes). */
 #define SIM_MAX_LINKS 64
@@ -113,9 +120,12 @@ typedef struct {
                               parent->joint rotation is the identity (the
                               kernels then use a specialised variant)     */
   int32_t chain;          /* 1 if every system is a fixed-base serial chain
-                              (parent of link i is link i-1); the kernels
-                              then pass parent/child quantities between
-                              neighbouring lanes' registers               */
+                              of revolute joints (parent of link i is link
+                              i-1); the kernels then pass parent/child
+                              quantities between neighbouring lanes'
+                              registers                                   */
+  int32_t has_prism;      /* 1 if any joint is prismatic (the kernels then
+                              use their general variant)                  */
 } sim_info_t;
 
 /* Build a handle: validates the topology and parameters, orders every

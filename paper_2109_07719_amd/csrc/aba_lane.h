@@ -11,9 +11,10 @@
 // modules in reverse order (Sec. 4.1) after recomputing the step's
 // intermediates from the stored initial state (Sec. 4.2, Eq. intermediate).
 //
-// Joint-angle derivatives use dX/dq = -crm(S) X for a revolute joint
-// (X = X_J(q) X_T, X_J = exp(-q crm(S))), so every statement that applies X
-// contributes a cross-product pairing to q_bar instead of a full X_bar.
+// Joint-coordinate derivatives use dX/dq = -crm(S) X, which holds for a
+// revolute and a prismatic joint alike (X = X_J(q) X_T, X_J = exp(-q crm(S))),
+// so every statement that applies X contributes a cross-product pairing to
+// q_bar instead of a full X_bar.
 #pragma once
 
 #include "spatial.h"
@@ -25,7 +26,9 @@ template <typename S>
 struct LinkC {
   M3<S> ET;   // fixed rotation parent -> joint frame
   V3<S> rT;   // joint origin in parent coordinates
-  V3<S> ax;   // joint axis (link coordinates); e_z after canonicalisation
+  V6<S> sm;   // motion subspace of the 1-dof joint: [e_z; 0] revolute, [0; e_z]
+              // prismatic (link coordinates, after canonicalisation)
+  bool prism; // prismatic joint: the link slides along e_z instead of turning
   S m;        // mass
   V3<S> mc;   // mass * centre of mass
   Sy3<S> Ib;  // rotational inertia about the link origin: Ic - m [c]x^2
@@ -48,24 +51,13 @@ ABA_HD SySp<S> inertia_sysp(const LinkC<S>& L) {
   return I;
 }
 
-// E = E_J(q) E_T for a joint about the link's z axis (the host rotates
-// every link frame so that its joint axis is e_z):
-// E_J = I - sin q [e_z]x + (1 - cos q)[e_z]x^2 = [[c, s, 0], [-s, c, 0], [0, 0, 1]].
-template <typename S>
-ABA_HD M3<S> joint_E(const LinkC<S>& L, S s, S c) {
-  M3<S> J;
-  J.m[0] = c;     J.m[1] = s;    J.m[2] = S(0);
-  J.m[3] = -s;    J.m[4] = c;    J.m[5] = S(0);
-  J.m[6] = S(0);  J.m[7] = S(0); J.m[8] = S(1);
-  return mul(J, L.ET);
-}
-
 // ----------------------------------------------------------------- forward
 // Intermediates of one link kept for the reverse sweep.
 template <typename S>
 struct Tape {
-  S sq, cq;    // sin q, cos q
+  S sq, cq;    // joint coordinate as X_J needs it: sin q, cos q (revolute); q, 1 (prismatic)
   M3<S> E;
+  V3<S> r;     // X = X_J(q) X_T = (E, r)
   V6<S> v, c;
   SySp<S> IA;  // final articulated inertia (children included)
   V6<S> pA;    // final articulated bias force
@@ -76,51 +68,63 @@ struct Tape {
   S qdd;
 };
 
-// pass 1 (revolute): v = X v_parent + S qd
+// X = X_J(q) X_T = (E, r) for a joint about or along the link's z axis
+// (the host rotates every link frame so that its joint axis is e_z), from
+// the tape's joint coordinate.
+// Revolute: E = E_J(q) E_T with E_J = I - sin q [e_z]x + (1 - cos q)[e_z]x^2
+// = [[c, s, 0], [-s, c, 0], [0, 0, 1]], r = r_T.  Prismatic: X_J is the
+// translation by q e_z, so E = E_T and r = r_T + q E_T^T e_z.
 template <typename S>
-ABA_HD V6<S> p1_velocity(const LinkC<S>& L, const M3<S>& E, S qd, const V6<S>& vpar) {
-  V6<S> v = xform(E, L.rT, vpar);
-  v.a = axpy(v.a, qd, L.ax);
-  return v;
+ABA_HD void joint_X(const LinkC<S>& L, Tape<S>& t) {
+  if (L.prism) {
+    t.E = L.ET;
+    t.r = axpy(L.rT, t.sq, row(L.ET, 2));
+  } else {
+    M3<S> J;
+    J.m[0] = t.cq;  J.m[1] = t.sq; J.m[2] = S(0);
+    J.m[3] = -t.sq; J.m[4] = t.cq; J.m[5] = S(0);
+    J.m[6] = S(0);  J.m[7] = S(0); J.m[8] = S(1);
+    t.E = mul(J, L.ET);
+    t.r = L.rT;
+  }
+}
+
+// pass 1 (1-dof joint): v = X v_parent + S qd
+template <typename S>
+ABA_HD V6<S> p1_velocity(const LinkC<S>& L, const Tape<S>& t, S qd, const V6<S>& vpar) {
+  return xform(t.E, t.r, vpar) + qd * L.sm;
 }
 // pass 1 (all links): c = v x S qd, h = I v, pA = v x* h, IA = I
 template <typename S>
-ABA_HD void p1_bias(const LinkC<S>& L, const V6<S>& v, S qd, bool revolute, V6<S>& c, V6<S>& pA,
+ABA_HD void p1_bias(const LinkC<S>& L, const V6<S>& v, S qd, bool onedof, V6<S>& c, V6<S>& pA,
                     SySp<S>& IA) {
-  if (revolute) {
-    const V3<S> sq = qd * L.ax;
-    c = v6<S>(cross(v.a, sq), cross(v.l, sq));
-  } else {
-    c = zero6<S>();
-  }
+  c = onedof ? crm(v, qd * L.sm) : zero6<S>();
   const V6<S> h = inertia_mul(L, v);
   pA = crf(v, h);
   IA = inertia_sysp(L);
 }
-// pass 2 (revolute): U = IA S, D = S^T U, u = tau - S^T pA
+// pass 2 (1-dof joint): U = IA S, D = S^T U, u = tau - S^T pA
 template <typename S>
 ABA_HD void p2_local(const LinkC<S>& L, Tape<S>& t, S tau) {
-  t.U = v6<S>(mul(t.IA.A, L.ax), mulT(t.IA.B, L.ax));
-  t.Dinv = rcp(dot(L.ax, t.U.a));
-  t.u = tau - dot(L.ax, t.pA.a);
+  t.U = mul(t.IA, L.sm);
+  t.Dinv = rcp(dot(L.sm, t.U));
+  t.u = tau - dot(L.sm, t.pA);
 }
-// pass 2 (revolute with a parent link): Ia = IA - U U^T / D,
+// pass 2 (1-dof joint with a parent link): Ia = IA - U U^T / D,
 // pa = pA + Ia c + U u / D; the parent receives X^T Ia X and X^T pa.
 template <typename S>
 ABA_HD void p2_push(const LinkC<S>& L, Tape<S>& t, SySp<S>& IA_up, V6<S>& pA_up) {
   const SySp<S> Ia = rank1_down(t.IA, t.U, t.Dinv);
   t.pa = t.pA + mul(Ia, t.c) + (t.u * t.Dinv) * t.U;
-  IA_up = congruence_XT(t.E, L.rT, Ia);
-  pA_up = xformT(t.E, L.rT, t.pa);
+  IA_up = congruence_XT(t.E, t.r, Ia);
+  pA_up = xformT(t.E, t.r, t.pa);
 }
-// pass 3 (revolute): a' = X a_parent + c, qdd = (u - U^T a') / D, a = a' + S qdd
+// pass 3 (1-dof joint): a' = X a_parent + c, qdd = (u - U^T a') / D, a = a' + S qdd
 template <typename S>
 ABA_HD V6<S> p3_accel(const LinkC<S>& L, Tape<S>& t, const V6<S>& apar) {
-  t.ap = xform(t.E, L.rT, apar) + t.c;
+  t.ap = xform(t.E, t.r, apar) + t.c;
   t.qdd = (t.u - dot(t.U, t.ap)) * t.Dinv;
-  V6<S> a = t.ap;
-  a.a = axpy(a.a, t.qdd, L.ax);
-  return a;
+  return t.ap + t.qdd * L.sm;
 }
 
 // ------------------------------------------------------- free-floating root
@@ -193,9 +197,9 @@ ABA_HD void root_accel(const SySp<S>& IA, const V6<S>& pA, const Q4<S>& quat, co
 }
 
 // ----------------------------------------------------------------- integrator
-// revolute: qd1 = qd + dt qdd; q1 = q + dt qd1
+// 1-dof joint: qd1 = qd + dt qdd; q1 = q + dt qd1
 template <typename S>
-ABA_HD void integrate_rev(S& q, S& qd, S qdd, S dt) {
+ABA_HD void integrate_joint(S& q, S& qd, S qdd, S dt) {
   qd = qd + dt * qdd;
   q = q + dt * qd;
 }
@@ -240,14 +244,15 @@ ABA_HD void bar_zero(Bar<S>& b) {
   b.qd = S(0);
 }
 
-// a . (x_ang x y_ang + x_lin x y_lin): the joint-angle pairing of a
-// statement y = X m (x = y_bar, y = X m) or y = X^T f (x = f, y = X y_bar)
+// The joint-coordinate pairing -x^T crm(S) y of a statement y = X m
+// (x = y_bar) or y = X^T f (x = f, y = X y_bar), from dX/dq = -crm(S) X:
+// s_ang . (x_ang x y_ang + x_lin x y_lin) + s_lin . (x_lin x y_ang).
 template <typename S>
-ABA_HD S qpair(const V3<S>& ax, const V6<S>& x, const V6<S>& y) {
-  return dot(ax, cross(x.a, y.a) + cross(x.l, y.l));
+ABA_HD S qpair(const V6<S>& sm, const V6<S>& x, const V6<S>& y) {
+  return dot(sm.a, cross(x.a, y.a) + cross(x.l, y.l)) + dot(sm.l, cross(x.l, y.a));
 }
 
-// reverse of pass 3 (revolute), in two parts for the level sweep.  The
+// reverse of pass 3 (1-dof joint), in two parts for the level sweep.  The
 // serial part needs abar, the link's acceleration adjoint with all
 // children's shares added, and qddbar, the integrator's seed; it returns
 // ap_bar (the parent receives X^T ap_bar) and g = qdd_bar / D.  The local
@@ -255,7 +260,7 @@ ABA_HD S qpair(const V3<S>& ax, const V6<S>& x, const V6<S>& y) {
 template <typename S>
 ABA_HD V6<S> r3_path(const LinkC<S>& L, const Tape<S>& t, const V6<S>& abar, S qddbar, S& g) {
   // a = ap + S qdd;  qdd = (u - U^T ap) / D
-  g = (qddbar + dot(L.ax, abar.a)) * t.Dinv;
+  g = (qddbar + dot(L.sm, abar)) * t.Dinv;
   return abar - g * t.U;
 }
 template <typename S>
@@ -264,7 +269,7 @@ ABA_HD void r3_local(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>
   b.U = b.U - g * t.ap;
   b.D = b.D - g * t.qdd;
   // ap = X a_parent + c
-  b.q = b.q + qpair(L.ax, apb, t.ap - t.c);
+  b.q = b.q + qpair(L.sm, apb, t.ap - t.c);
   b.c = b.c + apb;
 }
 template <typename S>
@@ -275,7 +280,7 @@ ABA_HD V6<S> r3_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>
   return apb;
 }
 
-// reverse of pass 2 (revolute), in two parts.  The serial part takes the
+// reverse of pass 2 (1-dof joint), in two parts.  The serial part takes the
 // parent's adjoints IAbp / pAbp (used only when has_parent), completes
 // U_bar, u_bar and D_bar, and produces this link's IA_bar / pA_bar (handed
 // to the children) and tau_bar; it also returns N = X IAbp X^T and
@@ -288,8 +293,8 @@ ABA_HD S r2_path(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent
   pAb = zero6<S>();
   if (has_parent) {
     // pA_parent += X^T pa;  IA_parent += X^T Ia X
-    pab = xform(t.E, L.rT, pAbp);
-    N = congruence_X(t.E, L.rT, IAbp);
+    pab = xform(t.E, t.r, pAbp);
+    N = congruence_X(t.E, t.r, IAbp);
     // pa = pA + Ia c + U u / D
     pAb = pAb + pab;
     const SySp<S> Iab = add_sym_outer(N, pab, t.c, S(1));
@@ -305,18 +310,18 @@ ABA_HD S r2_path(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent
   }
   // u = tau - S^T pA
   const S taub = b.u;
-  pAb.a = axpy(pAb.a, -b.u, L.ax);
+  pAb = pAb - b.u * L.sm;
   // D = S^T U
-  b.U.a = axpy(b.U.a, b.D, L.ax);
+  b.U = b.U + b.D * L.sm;
   // U = IA S   (symmetric part of U_bar S^T)
-  IAb = add_sym_outer(IAb, b.U, v6<S>(L.ax, zero3<S>()), S(1));
+  IAb = add_sym_outer(IAb, b.U, L.sm, S(1));
   return taub;
 }
 template <typename S>
 ABA_HD void r2_local(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const SySp<S>& N, const V6<S>& pab) {
-  b.q = b.q + qpair(L.ax, t.pa, pab);
+  b.q = b.q + qpair(L.sm, t.pa, pab);
   const SySp<S> Ia = rank1_down(t.IA, t.U, t.Dinv);
-  b.q = b.q - S(2) * pair_crmS(Ia, N, L.ax);
+  b.q = b.q - S(2) * pair_crmS(Ia, N, L.sm);
   b.c = b.c + mul(Ia, pab);
 }
 template <typename S>
@@ -330,37 +335,36 @@ ABA_HD S r2_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent
 }
 
 // reverse of pass 1, in three parts.  r1_own: the link's own share of its
-// velocity adjoint (from pA = v x* I v and, for a revolute joint,
+// velocity adjoint (from pA = v x* I v and, for a 1-dof joint,
 // c = v x S qd), which needs only the link's final pA_bar and c_bar.  The
 // serial part adds the children's shares and hands X^T v_bar to the parent.
 // r1_local: qd_bar and q_bar from the complete v_bar.
 template <typename S>
-ABA_HD V6<S> r1_own(const LinkC<S>& L, const V6<S>& v, const Bar<S>& b, const V6<S>& pAb, S qd, bool revolute) {
+ABA_HD V6<S> r1_own(const LinkC<S>& L, const V6<S>& v, const Bar<S>& b, const V6<S>& pAb, S qd, bool onedof) {
   // pA(initial) = v x* h, h = I v
   const V6<S> h = inertia_mul(L, v);
   const V6<S> hb = v6<S>(-cross(v.a, pAb.a), -(cross(v.a, pAb.l) + cross(v.l, pAb.a)));
   V6<S> own = crmT(pAb, h) + inertia_mul(L, hb);
-  if (revolute) {
-    // c = v x vJ, vJ = [a qd; 0]
-    const V3<S> sq = qd * L.ax;
-    own = own - v6<S>(cross(b.c.a, sq), cross(b.c.l, sq));
+  if (onedof) {
+    // c = v x vJ = -crm(vJ) v, vJ = S qd
+    own = own - crmT(qd * L.sm, b.c);
   }
   return own;
 }
 template <typename S>
 ABA_HD void r1_local(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>& vbar, S qd) {
   const V6<S> vJb = crmT(t.v, b.c) + vbar;
-  b.qd = b.qd + dot(L.ax, vJb.a);
+  b.qd = b.qd + dot(L.sm, vJb);
   // v = X v_parent + vJ
-  const V6<S> Xv = v6<S>(axpy(t.v.a, -qd, L.ax), t.v.l);
-  b.q = b.q + qpair(L.ax, vbar, Xv);
+  const V6<S> Xv = t.v - qd * L.sm;
+  b.q = b.q + qpair(L.sm, vbar, Xv);
 }
-// revolute: vbar holds the children's shares; returns X^T v_bar
+// 1-dof joint: vbar holds the children's shares; returns X^T v_bar
 template <typename S>
 ABA_HD V6<S> r1_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, V6<S> vbar, const V6<S>& pAb, S qd) {
   vbar = vbar + r1_own(L, t.v, b, pAb, qd, true);
   r1_local(L, t, b, vbar, qd);
-  return xformT(t.E, L.rT, vbar);
+  return xformT(t.E, t.r, vbar);
 }
 
 // Adjoint of a link's ten inertial parameters: mass m, first moment

@@ -126,6 +126,7 @@ struct Shape {
   bool has_free = false;
   bool eti = false;
   bool chain = false;
+  bool has_prism = false;  // some joint is prismatic
 };
 
 // Launch geometry.  waves_per_block: wavefronts per workgroup in the

@@ -98,7 +98,8 @@ struct Lane {
   int lane, slot;
   int par, depth, cfirst, ccount, jtype, qidx, vidx, uidx, fidx, link;
   __device__ bool active() const { return jtype >= 0; }
-  __device__ bool revolute() const { return jtype == 0; }
+  // revolute or prismatic (jtype 0 or 2; -1 marks an idle lane, 1 a free root)
+  __device__ bool onedof() const { return (jtype & 1) == 0; }
 };
 
 // wb: the wave batch (64 lane slots) this wavefront works on
@@ -122,17 +123,23 @@ __device__ __forceinline__ Lane load_lane(const Packed<S>& P, int wb) {
   return l;
 }
 
-// Per-link constants.  The host canonicalises every revolute joint axis to
-// e_z, so the axis is a compile-time constant here; with ETI (every joint
-// frame the identity after canonicalisation) so is E_T.  The build's
-// no-signed-zeros / finite-math flags let the compiler fold the resulting
-// structural zeros and ones through the generic spatial-algebra code.
-template <typename S, bool ETI>
-__device__ __forceinline__ LinkC<S> load_linkc(const Packed<S>& P, int slot) {
-  const int ns = P.nslots;
+// Link-frame kinds of a kernel variant.  kFrIdentity: every E_T the
+// identity after canonicalisation, every joint revolute; kFrGeneral: any
+// E_T, every joint revolute; kFrPrismatic: any E_T, and prismatic joints
+// among the revolute ones (the joint type becomes a per-lane value).
+enum : int { kFrIdentity = 0, kFrGeneral = 1, kFrPrismatic = 2 };
+
+// Per-link constants.  The host canonicalises every joint axis to e_z, so
+// the motion subspace is a compile-time constant unless prismatic joints
+// are present; with kFrIdentity so is E_T.  The build's no-signed-zeros /
+// finite-math flags let the compiler fold the resulting structural zeros
+// and ones through the generic spatial-algebra code.
+template <typename S, int FR>
+__device__ __forceinline__ LinkC<S> load_linkc(const Packed<S>& P, const Lane& l) {
+  const int ns = P.nslots, slot = l.slot;
   const S* cf = P.cf;
   LinkC<S> L;
-  if constexpr (ETI) {
+  if constexpr (FR == kFrIdentity) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) L.ET.m[k] = (k % 4 == 0) ? S(1) : S(0);
   } else {
@@ -140,12 +147,32 @@ __device__ __forceinline__ LinkC<S> load_linkc(const Packed<S>& P, int slot) {
     for (int k = 0; k < 9; ++k) L.ET.m[k] = cf[(CF_ET + k) * ns + slot];
   }
   L.rT = v3<S>(cf[(CF_RT + 0) * ns + slot], cf[(CF_RT + 1) * ns + slot], cf[(CF_RT + 2) * ns + slot]);
-  L.ax = v3<S>(S(0), S(0), S(1));
+  if constexpr (FR == kFrPrismatic) {
+    L.prism = l.jtype == 2;
+    const S ang = L.prism ? S(0) : S(1);
+    L.sm = v6<S>(v3<S>(S(0), S(0), ang), v3<S>(S(0), S(0), S(1) - ang));
+  } else {
+    L.prism = false;
+    L.sm = v6<S>(v3<S>(S(0), S(0), S(1)), zero3<S>());
+  }
   L.m = cf[CF_M * ns + slot];
   L.mc = v3<S>(cf[(CF_MC + 0) * ns + slot], cf[(CF_MC + 1) * ns + slot], cf[(CF_MC + 2) * ns + slot]);
   L.Ib = sy3<S>(cf[(CF_IB + 0) * ns + slot], cf[(CF_IB + 1) * ns + slot], cf[(CF_IB + 2) * ns + slot],
                 cf[(CF_IB + 3) * ns + slot], cf[(CF_IB + 4) * ns + slot], cf[(CF_IB + 5) * ns + slot]);
   return L;
+}
+
+// Joint transform of a 1-dof lane from its coordinate q (the tape keeps
+// sin q, cos q of a revolute joint and q itself of a prismatic one).
+template <typename S>
+__device__ __forceinline__ void joint_transform(const LinkC<S>& L, S q, Tape<S>& t) {
+  if (L.prism) {
+    t.sq = q;
+    t.cq = S(1);
+  } else {
+    sincos_(q, &t.sq, &t.cq);
+  }
+  joint_X(L, t);
 }
 
 // Dynamic LDS of a workgroup, sized by the launcher: one exchange buffer per
@@ -199,7 +226,7 @@ __device__ __forceinline__ SySp<S> get21(const S* xb, int f0, int lane) {
   return M;
 }
 
-// per-lane state: revolute lanes use q[0], qd[0]; a free root uses
+// per-lane state: 1-dof lanes use q[0], qd[0]; a free root uses
 // q = (p, quat) and qd = body velocity [w; v]
 template <typename S, bool FREE>
 struct State {
@@ -233,13 +260,13 @@ __device__ __forceinline__ V6<S> st_vel6(const State<S, FREE>& s) {
 template <typename S, bool FREE>
 __device__ __forceinline__ void load_state(State<S, FREE>& s, const Lane& l, const S* q, const S* qd) {
   if constexpr (FREE) {
-    const bool rev = l.revolute(), fr = l.jtype == 1;
+    const bool rev = l.onedof(), fr = l.jtype == 1;
 #pragma unroll
     for (int k = 0; k < 7; ++k) s.q[k] = ((k == 0 && rev) || fr) ? q[l.qidx + k] : s.q[k];
 #pragma unroll
     for (int k = 0; k < 6; ++k) s.qd[k] = ((k == 0 && rev) || fr) ? qd[l.vidx + k] : s.qd[k];
   } else {
-    if (l.revolute()) {
+    if (l.onedof()) {
       s.q[0] = q[l.qidx];
       s.qd[0] = qd[l.vidx];
     }
@@ -247,7 +274,7 @@ __device__ __forceinline__ void load_state(State<S, FREE>& s, const Lane& l, con
 }
 template <typename S, bool FREE>
 __device__ __forceinline__ void store_state(const State<S, FREE>& s, const Lane& l, S* q, S* qd) {
-  if (l.revolute()) {
+  if (l.onedof()) {
     q[l.qidx] = s.q[0];
     qd[l.vidx] = s.qd[0];
   } else if constexpr (FREE) {
@@ -280,7 +307,7 @@ __device__ __forceinline__ int nonfinite(double x) {
 template <typename S, bool FREE>
 __device__ __forceinline__ int nonfinite_state(const State<S, FREE>& s, const Lane& l) {
   int n = 0;
-  if (l.revolute()) {
+  if (l.onedof()) {
     n = nonfinite(s.q[0]) + nonfinite(s.qd[0]);
   } else if constexpr (FREE) {
     if (l.jtype == 1) {
@@ -297,7 +324,7 @@ __device__ __forceinline__ void report_nonfinite(int* status, int n) {
 }
 
 // stored state records (see state_record): [2][nslots] then [11][nfree].
-// The second row holds p.y of a free root or qd of a revolute link; it is
+// The second row holds p.y of a free root or qd of a 1-dof link; it is
 // chosen by value selects, not by selecting which member to address, so
 // that the state stays in registers.
 template <typename S, bool FREE>
@@ -408,18 +435,13 @@ __device__ __forceinline__ void get_tape(Step<S>& o, const S* base, int ns, int 
   for (int k = 0; k < 9; ++k) t.IA.B.m[k] = r();
   t.IA.C.xx = r(); t.IA.C.yy = r(); t.IA.C.zz = r(); t.IA.C.xy = r(); t.IA.C.xz = r(); t.IA.C.yz = r();
   r6(t.pA); t.Dinv = r(); t.u = r(); r6(t.pa); r6(t.ap); t.qdd = r(); r6(o.abase);
-  t.E = joint_E(L, t.sq, t.cq);
-  t.U = v6<S>(mul(t.IA.A, L.ax), mulT(t.IA.B, L.ax));
-  if (rev) {
-    const V3<S> sqd = qd * L.ax;
-    t.c = v6<S>(cross(t.v.a, sqd), cross(t.v.l, sqd));
-  } else {
-    t.c = zero6<S>();
-  }
+  joint_X(L, t);
+  t.U = mul(t.IA, L.sm);
+  t.c = rev ? crm(t.v, qd * L.sm) : zero6<S>();
 }
 
 // The three ABA passes for a wave of serial chains with fixed bases (every
-// active lane revolute): parent/child quantities move between neighbouring
+// active lane a 1-dof joint): parent/child quantities move between neighbouring
 // lanes in registers.  A root never pushes to its parent, so the lane after
 // a chain's leaf always hands the leaf zeros.
 template <typename S>
@@ -428,13 +450,12 @@ __device__ __forceinline__ void aba_wave_chain(const V3<S>& g, const Lane& l, co
   Tape<S>& t = o.t;
   const bool act = l.active();
   const bool hp = l.par >= 0;
-  sincos_(st.q[0], &t.sq, &t.cq);
-  t.E = joint_E(L, t.sq, t.cq);
+  joint_transform(L, st.q[0], t);
   // pass 1: velocities, root -> leaves
   t.v = zero6<S>();
   for (int d = 0; d <= maxd; ++d) {
     const V6<S> vp = from_prev(t.v);
-    if (act && l.depth == d) t.v = p1_velocity(L, t.E, st.qd[0], hp ? vp : zero6<S>());
+    if (act && l.depth == d) t.v = p1_velocity(L, t, st.qd[0], hp ? vp : zero6<S>());
   }
   // pass 1: bias terms (parallel over links)
   if (act) p1_bias(L, t.v, st.qd[0], true, t.c, t.pA, t.IA);
@@ -471,18 +492,15 @@ __device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const Li
   }
   Tape<S>& t = o.t;
   const bool act = l.active();
-  const bool rev = l.revolute();
+  const bool rev = l.onedof();
   // pass 1: joint transforms (parallel over links)
-  if (rev) {
-    sincos_(st.q[0], &t.sq, &t.cq);
-    t.E = joint_E(L, t.sq, t.cq);
-  }
+  if (rev) joint_transform(L, st.q[0], t);
   // pass 1: velocities, root -> leaves
   for (int d = 0; d <= maxd; ++d) {
     if (act && l.depth == d) {
       if (rev) {
         const V6<S> vp = (l.par >= 0) ? get6(xb, 0, l.par) : zero6<S>();
-        t.v = p1_velocity(L, t.E, st.qd[0], vp);
+        t.v = p1_velocity(L, t, st.qd[0], vp);
       } else {
         t.v = st_vel6(st);
       }
@@ -530,8 +548,8 @@ __device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const Li
 
 template <typename S, bool FREE>
 __device__ __forceinline__ void integrate_lane(State<S, FREE>& st, const Lane& l, const Step<S>& o, S dt) {
-  if (l.revolute()) {
-    integrate_rev(st.q[0], st.qd[0], o.t.qdd, dt);
+  if (l.onedof()) {
+    integrate_joint(st.q[0], st.qd[0], o.t.qdd, dt);
   } else if constexpr (FREE) {
     if (l.jtype == 1) {
       V3<S> p = v3<S>(st.q[0], st.q[1], st.q[2]);
@@ -548,7 +566,7 @@ __device__ __forceinline__ void integrate_lane(State<S, FREE>& st, const Lane& l
 
 // ------------------------------------------------------------------ kernels
 
-template <typename S, bool FREE, bool ETI, bool CHAIN>
+template <typename S, bool FREE, int FR, bool CHAIN>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A) {
   S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
   const int wb = wave_batch();
@@ -556,17 +574,17 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A)
   const int maxd = A.P.wmaxd[wb];
   // every lane slot holds valid constants, so load them unconditionally
   // (keeps the compile-time axis and frame constants visible to folding)
-  const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
+  const LinkC<S> L = load_linkc<S, FR>(A.P, l);
   State<S, FREE> st = {};
   S tau = S(0);
   if (l.active()) {
     load_state(st, l, A.q, A.qd);
-    if (l.revolute()) tau = A.tau[l.uidx];
+    if (l.onedof()) tau = A.tau[l.uidx];
   }
   Step<S> o;
   aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
   int nonfin = 0;
-  if (l.revolute()) {
+  if (l.onedof()) {
     A.qdd[l.vidx] = o.t.qdd;
     nonfin = nonfinite(o.t.qdd);
   } else if constexpr (FREE) {
@@ -585,7 +603,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A)
 // Forward rollout.  MODE 0: plain; 1: store the initial state of every
 // K-th step; 2: store every step's initial state and intermediates
 // (store-all).  With a trajectory buffer, also write x^{t+1} for every step.
-template <typename S, bool FREE, bool ETI, bool CHAIN, int MODE>
+template <typename S, bool FREE, int FR, bool CHAIN, int MODE>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S> A) {
   S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
   const int wb = wave_batch();
@@ -593,10 +611,10 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
   const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
-  const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
+  const LinkC<S> L = load_linkc<S, FR>(A.P, l);
   State<S, FREE> st = {};
   if (l.active()) load_state(st, l, A.q0, A.qd0);
-  const bool has_tau = l.revolute();
+  const bool has_tau = l.onedof();
   S tau_next = (has_tau && A.T > 0) ? A.tau[l.uidx] : S(0);
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
@@ -641,7 +659,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
                                             S* xb, const State<S, FREE>& st, const Step<S>& o, int t,
                                             State<S, FREE>& xb1, int& nonfin, ParamBar<S>& pg) {
   const bool act = l.active();
-  const bool rev = l.revolute();
+  const bool rev = l.onedof();
   const V3<S> g = v3<S>(A.P.g[0], A.P.g[1], A.P.g[2]);
   const Tape<S>& tp = o.t;
 
@@ -680,7 +698,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
       const V6<S> ab = from_next(up);
       if (act && l.depth == d) {
         apb = r3_path(L, tp, ab, qddb, g3);
-        if (l.par >= 0) up = xformT(tp.E, L.rT, apb);
+        if (l.par >= 0) up = xformT(tp.E, tp.r, apb);
       }
     }
   } else {
@@ -690,7 +708,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
         for (int k = 0; k < l.ccount; ++k) ab = ab + get6(xb, 0, l.cfirst + k);
         if (rev) {
           apb = r3_path(L, tp, ab, qddb, g3);
-          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, apb));
+          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, tp.r, apb));
         } else if constexpr (FREE) {
           r3_root(tp.IA, tp.ap, st_quat(st), g, ab, qddb6, quatb, IAb, pAb);
         }
@@ -736,7 +754,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
       const V6<S> vb = from_next(up);
       if (act && l.depth == d) {
         vbar = vb + own;
-        if (l.par >= 0) up = xformT(tp.E, L.rT, vbar);
+        if (l.par >= 0) up = xformT(tp.E, tp.r, vbar);
       }
     }
   } else {
@@ -746,7 +764,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
         for (int k = 0; k < l.ccount; ++k) vb = vb + get6(xb, 0, l.cfirst + k);
         vbar = vb + own;
         if (rev) {
-          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, vbar));
+          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, tp.r, vbar));
         } else if constexpr (FREE) {
           vb6 = vb6 + vbar;
         }
@@ -793,7 +811,7 @@ __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, con
 // checkpoint; K > 1 replays each K-step segment from its checkpoint into
 // the scratch buffer first.  The next state and control are fetched one
 // step ahead.
-template <typename S, bool FREE, bool ETI, bool CHAIN>
+template <typename S, bool FREE, int FR, bool CHAIN>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<S> A) {
   S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
   const int wb = wave_batch();
@@ -802,10 +820,10 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
   const bool act = l.active();
-  const bool rev = l.revolute();
+  const bool rev = l.onedof();
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
-  const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
+  const LinkC<S> L = load_linkc<S, FR>(A.P, l);
   int nonfin = 0;  // non-finite outputs
   ParamBar<S> pg;
   param_bar_zero(pg);
@@ -926,18 +944,18 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<
 // k: the producer recomputes step T-1-k into buffer k%2 while the consumer
 // reverses step T-k from buffer (k-1)%2; one workgroup barrier ends every
 // phase (both waves execute exactly T+1 of them).
-template <typename S, bool FREE, bool ETI, bool CHAIN>
+template <typename S, bool FREE, int FR, bool CHAIN>
 __host__ __device__ constexpr size_t pipe_lds_per_pair() {
   constexpr int TW = kTapeFields + (FREE ? 13 : 2);  // tape + state per lane
   return (size_t)((CHAIN ? 0 : 2 * XB) + 2 * TW) * kWave * sizeof(S);
 }
 
-template <typename S, bool FREE, bool ETI, bool CHAIN>
+template <typename S, bool FREE, int FR, bool CHAIN>
 __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe(BwdArgs<S> A) {
   constexpr int TW = kTapeFields + (FREE ? 13 : 2);
   const int pair = threadIdx.x / (2 * kWave);
   const int wid = (threadIdx.x / kWave) & 1;
-  S* const base = lds<S>() + pair * (pipe_lds_per_pair<S, FREE, ETI, CHAIN>() / sizeof(S));
+  S* const base = lds<S>() + pair * (pipe_lds_per_pair<S, FREE, FR, CHAIN>() / sizeof(S));
   S* const xb = CHAIN ? nullptr : base + wid * (XB * kWave);
   S* const tbuf[2] = {base + (CHAIN ? 0 : 2 * XB * kWave), base + (CHAIN ? 0 : 2 * XB * kWave) + TW * kWave};
   const int wb = blockIdx.x * (blockDim.x / (2 * kWave)) + pair;
@@ -946,10 +964,10 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
   const bool act = l.active();
-  const bool rev = l.revolute();
+  const bool rev = l.onedof();
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
-  const LinkC<S> L = load_linkc<S, ETI>(A.P, l.slot);
+  const LinkC<S> L = load_linkc<S, FR>(A.P, l);
   if (wid == 0) {
     State<S, FREE> nxt = {};
     S tau_nxt = S(0);
@@ -1029,7 +1047,9 @@ __device__ __forceinline__ LinkC<Dual<S>> dual_const(const LinkC<S>& L) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) D.ET.m[k] = Dual<S>(L.ET.m[k], S(0));
   D.rT = v3<Dual<S>>(Dual<S>(L.rT.x, S(0)), Dual<S>(L.rT.y, S(0)), Dual<S>(L.rT.z, S(0)));
-  D.ax = v3<Dual<S>>(Dual<S>(L.ax.x, S(0)), Dual<S>(L.ax.y, S(0)), Dual<S>(L.ax.z, S(0)));
+  D.sm = v6<Dual<S>>(v3<Dual<S>>(Dual<S>(L.sm.a.x, S(0)), Dual<S>(L.sm.a.y, S(0)), Dual<S>(L.sm.a.z, S(0))),
+                     v3<Dual<S>>(Dual<S>(L.sm.l.x, S(0)), Dual<S>(L.sm.l.y, S(0)), Dual<S>(L.sm.l.z, S(0))));
+  D.prism = L.prism;
   D.m = Dual<S>(L.m, S(0));
   D.mc = v3<Dual<S>>(Dual<S>(L.mc.x, S(0)), Dual<S>(L.mc.y, S(0)), Dual<S>(L.mc.z, S(0)));
   D.Ib = sy3<Dual<S>>(Dual<S>(L.Ib.xx, S(0)), Dual<S>(L.Ib.yy, S(0)), Dual<S>(L.Ib.zz, S(0)),
@@ -1051,7 +1071,7 @@ __device__ __forceinline__ void split_state(const State<Dual<S>, FREE>& x, State
   }
 }
 
-template <typename S, bool FREE, bool ETI, bool CHAIN>
+template <typename S, bool FREE, int FR, bool CHAIN>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward_jvp(JvpArgs<S> A) {
   using D = Dual<S>;
   D* xb = CHAIN ? nullptr : lds<D>() + wave_in_block() * (XB * kWave);
@@ -1059,7 +1079,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward_jvp(JvpAr
   const Lane l = load_lane(A.P, wb);
   const int maxd = A.P.wmaxd[wb];
   const int nu = A.P.nu;
-  const LinkC<D> L = dual_const(load_linkc<S, ETI>(A.P, l.slot));
+  const LinkC<D> L = dual_const(load_linkc<S, FR>(A.P, l));
   const V3<D> g = v3<D>(D(A.P.g[0], S(0)), D(A.P.g[1], S(0)), D(A.P.g[2], S(0)));
   const D dt = D(A.dt, S(0));
   State<S, FREE> sv = {}, sd = {};
@@ -1072,7 +1092,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward_jvp(JvpAr
   for (int k = 0; k < (FREE ? 7 : 1); ++k) st.q[k] = D(sv.q[k], sd.q[k]);
 #pragma unroll
   for (int k = 0; k < (FREE ? 6 : 1); ++k) st.qd[k] = D(sv.qd[k], sd.qd[k]);
-  const bool has_tau = l.revolute();
+  const bool has_tau = l.onedof();
   int nonfin = 0;
   for (int t = 0; t < A.T; ++t) {
     const D tau = has_tau ? D(A.tau[(size_t)t * nu + l.uidx], A.dtau[(size_t)t * nu + l.uidx]) : D(S(0), S(0));
@@ -1099,27 +1119,32 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward_jvp(JvpAr
 
 }  // namespace
 
-// Kernel variants: FREE (some system has a free-floating root), ETI (every
-// joint frame is the identity after canonicalisation), CHAIN (every system
-// is a fixed-base serial chain; register exchange between lanes).
-enum class Variant { kFree, kFreeEti, kTree, kTreeEti, kChain, kChainEti };
+// Kernel variants: FREE (some system has a free-floating root), the
+// link-frame kind FR (kFrIdentity: every joint frame the identity after
+// canonicalisation; kFrPrismatic: some joint is prismatic), CHAIN (every
+// system is a fixed-base serial chain of revolute joints; register exchange
+// between lanes).  Batches with prismatic joints take the one general
+// variant (FREE, kFrPrismatic), which handles every joint type.
+enum class Variant { kFree, kFreeEti, kTree, kTreeEti, kChain, kChainEti, kGeneral };
 
 Variant variant(const Shape& sh) {
+  if (sh.has_prism) return Variant::kGeneral;
   if (sh.has_free) return sh.eti ? Variant::kFreeEti : Variant::kFree;
   if (sh.chain) return sh.eti ? Variant::kChainEti : Variant::kChain;
   return sh.eti ? Variant::kTreeEti : Variant::kTree;
 }
 
-// calls f.template operator()<FREE, ETI, CHAIN>()
+// calls f.template operator()<FREE, FR, CHAIN>()
 template <typename F>
 void dispatch(const Shape& sh, F&& f) {
   switch (variant(sh)) {
-    case Variant::kFree: f.template operator()<true, false, false>(); break;
-    case Variant::kFreeEti: f.template operator()<true, true, false>(); break;
-    case Variant::kTree: f.template operator()<false, false, false>(); break;
-    case Variant::kTreeEti: f.template operator()<false, true, false>(); break;
-    case Variant::kChain: f.template operator()<false, false, true>(); break;
-    case Variant::kChainEti: f.template operator()<false, true, true>(); break;
+    case Variant::kFree: f.template operator()<true, kFrGeneral, false>(); break;
+    case Variant::kFreeEti: f.template operator()<true, kFrIdentity, false>(); break;
+    case Variant::kTree: f.template operator()<false, kFrGeneral, false>(); break;
+    case Variant::kTreeEti: f.template operator()<false, kFrIdentity, false>(); break;
+    case Variant::kChain: f.template operator()<false, kFrGeneral, true>(); break;
+    case Variant::kChainEti: f.template operator()<false, kFrIdentity, true>(); break;
+    case Variant::kGeneral: f.template operator()<true, kFrPrismatic, false>(); break;
   }
 }
 
@@ -1148,7 +1173,7 @@ int single_wpb(const Tiling& tl, int nwaves, size_t& lds) {
 template <typename S>
 hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
-  dispatch(sh, [&]<bool F, bool E, bool C>() {
+  dispatch(sh, [&]<bool F, int E, bool C>() {
     size_t lds = 0;
     const int w = single_wpb<S, C>(tl, a.P.nwaves, lds);
     hipLaunchKernelGGL((k_aba<S, F, E, C>), dim3(a.P.nwaves / w), dim3(kWave * w), lds, st, a);
@@ -1160,7 +1185,7 @@ template <typename S>
 hipError_t launch_forward(const FwdArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
   const int mode = (a.ck == nullptr) ? 0 : (a.K == 0) ? 2 : 1;
-  dispatch(sh, [&]<bool F, bool E, bool C>() {
+  dispatch(sh, [&]<bool F, int E, bool C>() {
     size_t lds = 0;
     const int w = single_wpb<S, C>(tl, a.P.nwaves, lds);
     const dim3 grid(a.P.nwaves / w), block(kWave * w);
@@ -1174,7 +1199,7 @@ hipError_t launch_forward(const FwdArgs<S>& a, const Shape& sh, const Tiling& tl
 template <typename S>
 hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
-  dispatch(sh, [&]<bool F, bool E, bool C>() {
+  dispatch(sh, [&]<bool F, int E, bool C>() {
     if (a.K == 1 && tl.pipelined) {
       const size_t per = pipe_lds_per_pair<S, F, E, C>();
       int p = tl.pairs_per_block == 2 ? 2 : 1;
@@ -1193,7 +1218,7 @@ hipError_t launch_backward(const BwdArgs<S>& a, const Shape& sh, const Tiling& t
 template <typename S>
 hipError_t launch_forward_jvp(const JvpArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
-  dispatch(sh, [&]<bool F, bool E, bool C>() {
+  dispatch(sh, [&]<bool F, int E, bool C>() {
     // the exchange buffers hold dual numbers
     size_t lds = 0;
     const int w = single_wpb<Dual<S>, C>(tl, a.P.nwaves, lds);

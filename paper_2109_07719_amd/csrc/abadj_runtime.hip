@@ -35,8 +35,9 @@ struct sim_handle {
   int n_sys = 0, n_links = 0, nq = 0, nv = 0, nu = 0;
   int nwaves = 0, nslots = 0, max_depth = 0, nfree = 0;
   bool has_free = false;
-  bool eti = false;  // every revolute joint frame is the identity after canonicalisation
-  bool chain = false;  // every system is a fixed-base serial chain
+  bool eti = false;  // every joint frame is the identity after canonicalisation
+  bool chain = false;  // every system is a fixed-base serial chain of revolute joints
+  bool has_prism = false;  // some joint is prismatic
   aba::Tiling tiling;  // launch geometry
   // binomial checkpointing schedule cached on the device for (sched_T, sched_s)
   int32_t* d_sched = nullptr;
@@ -78,6 +79,7 @@ aba::Shape shape(const sim_handle* h) {
   sh.has_free = h->has_free;
   sh.eti = h->eti;
   sh.chain = h->chain;
+  sh.has_prism = h->has_prism;
   return sh;
 }
 
@@ -309,7 +311,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
         return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: system " + std::to_string(s) + " link " + std::to_string(i) +
                                                   ": parent must satisfy -1 <= parent < index");
       }
-      if (jt != SIM_JOINT_REVOLUTE && jt != SIM_JOINT_FREE) {
+      if (jt != SIM_JOINT_REVOLUTE && jt != SIM_JOINT_FREE && jt != SIM_JOINT_PRISMATIC) {
         delete h;
         return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: unknown joint type");
       }
@@ -325,7 +327,8 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
         delete h;
         return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: mass must be positive");
       }
-      if (jt == SIM_JOINT_REVOLUTE) {
+      if (jt == SIM_JOINT_PRISMATIC) h->has_prism = true;
+      if (jt != SIM_JOINT_FREE) {
         const double* a = prm->axis + 3 * (size_t)(b + i);
         const double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
         if (std::fabs(nrm - 1.0) > 1e-6) {
@@ -412,7 +415,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
   static const double I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   std::vector<double> Rcan(9 * (size_t)nl);
   for (int L = 0; L < nl; ++L) {
-    if (topo->jtype[L] == SIM_JOINT_REVOLUTE)
+    if (topo->jtype[L] != SIM_JOINT_FREE)
       axis_to_z(prm->axis + 3 * (size_t)L, Rcan.data() + 9 * (size_t)L);
     else
       for (int k = 0; k < 9; ++k) Rcan[9 * (size_t)L + k] = I3[k];
@@ -476,7 +479,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       mat3_mul(Rl, J, T2);
       mat3_mul_bt(T2, Rl, Jn);
       const double I[6] = {Jn[0], Jn[4], Jn[8], Jn[1], Jn[2], Jn[5]};
-      if (topo->jtype[L] == SIM_JOINT_REVOLUTE)
+      if (topo->jtype[L] != SIM_JOINT_FREE)
         for (int k = 0; k < 9; ++k) eti = eti && std::fabs(ETn[k] - I3[k]) < 1e-12;
       CF(aba::CF_M) = m;
       for (int k = 0; k < 3; ++k) CF(aba::CF_MC + k) = m * c[k];
@@ -493,7 +496,8 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
   h->eti = eti;
   if (eti) {  // make the identity exact
     for (int slot = 0; slot < NS; ++slot)
-      if (ci[(size_t)aba::CI_JTYPE * NS + slot] == SIM_JOINT_REVOLUTE)
+      if (ci[(size_t)aba::CI_JTYPE * NS + slot] == SIM_JOINT_REVOLUTE ||
+          ci[(size_t)aba::CI_JTYPE * NS + slot] == SIM_JOINT_PRISMATIC)
         for (int k = 0; k < 9; ++k) cf[(size_t)(aba::CF_ET + k) * NS + slot] = I3[k];
   }
   // children of a link are consecutive lanes in breadth-first order
@@ -509,10 +513,11 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       }
     }
   }
-  // serial chains: if every non-root link's parent sits in the previous
-  // lane, a lane's only possible child is the next lane, and the kernels
-  // exchange parent/child quantities between neighbouring lanes' registers
-  bool chain = !h->has_free;
+  // serial chains of revolute joints: if every non-root link's parent sits
+  // in the previous lane, a lane's only possible child is the next lane, and
+  // the kernels exchange parent/child quantities between neighbouring lanes'
+  // registers
+  bool chain = !h->has_free && !h->has_prism;
   for (int slot = 0; chain && slot < NS; ++slot) {
     const int p = ci[(size_t)aba::CI_PARENT * NS + slot];
     if (ci[(size_t)aba::CI_JTYPE * NS + slot] >= 0 && p >= 0 && p != slot % aba::kWave - 1) chain = false;
@@ -549,6 +554,7 @@ int sim_get_info(sim_t h, sim_info_t* o) {
   o->has_free = h->has_free ? 1 : 0;
   o->frames_identity = h->eti ? 1 : 0;
   o->chain = h->chain ? 1 : 0;
+  o->has_prism = h->has_prism ? 1 : 0;
   o->dtype = h->dtype;
   return SIM_OK;
 }
@@ -1009,11 +1015,14 @@ struct LinkOps {
   long long bwd_free;
 };
 
-LinkOps link_ops(bool eti) {
+// prism: count a prismatic joint's link instead of a revolute one
+LinkOps link_ops(bool eti, bool prism) {
   using namespace aba;
   LinkOps o{};
   LinkC<Op> L{};
-  L.ax = v3<Op>(Op(0.0), Op(0.0), Op(1.0));  // canonicalised joint axis
+  L.prism = prism;  // canonicalised joint axis e_z: S = [e_z; 0] or [0; e_z]
+  L.sm = prism ? v6<Op>(zero3<Op>(), v3<Op>(Op(0.0), Op(0.0), Op(1.0)))
+               : v6<Op>(v3<Op>(Op(0.0), Op(0.0), Op(1.0)), zero3<Op>());
   if (eti)
     for (int k = 0; k < 9; ++k) L.ET.m[k] = Op((k % 4 == 0) ? 1.0 : 0.0);
   Tape<Op> t{};
@@ -1022,10 +1031,10 @@ LinkOps link_ops(bool eti) {
   Q4<Op> qt{};
   V3<Op> g{};
   Bar<Op> b{};
-  // one revolute ABA evaluation (sin and cos counted as one operation each)
-  o.fd_rev = 2 + count([&] {
-               t.E = joint_E(L, Op(), Op());
-               t.v = p1_velocity(L, t.E, Op(), v);
+  // one 1-dof ABA evaluation (sin and cos counted as one operation each)
+  o.fd_rev = (prism ? 0 : 2) + count([&] {
+               joint_X(L, t);
+               t.v = p1_velocity(L, t, Op(), v);
                p1_bias(L, t.v, Op(), true, t.c, t.pA, t.IA);
                p2_local(L, t, Op());
                (void)p3_accel(L, t, v);
@@ -1034,7 +1043,7 @@ LinkOps link_ops(bool eti) {
   o.child_fwd = 27;  // IA (21) and pA (6) of each child added to its parent
   o.integ_rev = count([&] {
     Op q, qd;
-    integrate_rev(q, qd, Op(), Op());
+    integrate_joint(q, qd, Op(), Op());
   });
   o.fd_free = count([&] {
     p1_bias(L, v, Op(), false, t.c, t.pA, t.IA);
@@ -1051,7 +1060,7 @@ LinkOps link_ops(bool eti) {
     (void)r1_link(L, t, b, v, w, Op());
   });
   o.bwd_rev_push = count([&] {
-                     (void)xformT(t.E, L.rT, v);                  // a_bar to the parent
+                     (void)xformT(t.E, t.r, v);                   // a_bar to the parent
                      (void)r2_link(L, t, b, true, M, v, M2, w);  // parent share of pass 2
                    }) -
                    count([&] { (void)r2_link(L, t, b, false, M, v, M2, w); });
@@ -1072,9 +1081,10 @@ LinkOps link_ops(bool eti) {
 extern "C" int sim_flops(sim_t h, int kind, double* flops) {
   if (!h || !flops) return fail(SIM_ERR_INVALID_ARG, "sim_flops: null argument");
   if (kind < 0 || kind > 2) return fail(SIM_ERR_INVALID_ARG, "sim_flops: kind must be 0, 1 or 2");
-  const LinkOps o = link_ops(h->eti);
+  const LinkOps orev = link_ops(h->eti, false), opri = link_ops(h->eti, true);
   double fd = 0, fwd = 0, bwd = 0;
   for (int i = 0; i < h->n_links; ++i) {
+    const LinkOps& o = (h->jtype[i] == SIM_JOINT_PRISMATIC) ? opri : orev;
     if (h->jtype[i] == SIM_JOINT_FREE) {
       fd += (double)o.fd_free;
       fwd += (double)(o.fd_free + o.integ_free);

@@ -439,14 +439,17 @@ ABA_HD M3<S> transpose(const M3<S>& A) {
   return R;
 }
 
-// <M N, crm([a; 0])> for symmetric spatial dyads M, N:
+// <M N, crm([a; l])> for symmetric spatial dyads M, N.  crm([a; l]) has
+// [a]x in both diagonal blocks and [l]x in the lower-left one, so
 //   = a . avec(M_A N_A + M_B N_B^T + M_B^T N_B + M_C N_C)
+//   + l . avec(M_B^T N_A + M_C N_B^T)
 template <typename S>
-ABA_HD S pair_crmS(const SySp<S>& M, const SySp<S>& N, const V3<S>& a) {
+ABA_HD S pair_crmS(const SySp<S>& M, const SySp<S>& N, const V6<S>& s) {
   const M3<S> MA = sy_to_m3(M.A), NA = sy_to_m3(N.A), MC = sy_to_m3(M.C), NC = sy_to_m3(N.C);
-  const V3<S> w = avec_prod(MA, NA) + avec_prod(M.B, transpose(N.B)) + avec_prod(transpose(M.B), N.B) +
-                  avec_prod(MC, NC);
-  return dot(a, w);
+  const M3<S> MBt = transpose(M.B), NBt = transpose(N.B);
+  const V3<S> w = avec_prod(MA, NA) + avec_prod(M.B, NBt) + avec_prod(MBt, N.B) + avec_prod(MC, NC);
+  const V3<S> wl = avec_prod(MBt, NA) + avec_prod(MC, NBt);
+  return dot(s.a, w) + dot(s.l, wl);
 }
 
 // ---------------------------------------------------------------- quaternions (x, y, z, w)

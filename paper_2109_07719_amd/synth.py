@@ -11,7 +11,7 @@ for the quadruped).
 
 Conventions shared with the rest of the package:
   * per link: parent index local to the system (-1 = fixed base / none),
-    joint type (0 revolute, 1 free; free only at local index 0), fixed
+    joint type (0 revolute, 1 free, 2 prismatic; free only at local index 0), fixed
     rotation E_T (3x3, parent -> joint frame), joint origin r_T in parent
     coordinates, unit joint axis, mass, centre of mass, rotational inertia
     about the COM as (xx, yy, zz, xy, xz, yz);
@@ -25,7 +25,7 @@ values widened back to float64.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -271,6 +271,31 @@ def quadruped_system(seed: int, T: int):
     return sys_, q0, v, tau
 
 
+def telescoping_quadruped_system(seed: int, T: int):
+    """quadruped_system(seed, T) with every knee replaced by a prismatic
+    joint sliding along the leg (axis (0, 1, 0)): a free-floating base over
+    revolute and prismatic joints.  Same draws as quadruped_system."""
+    sys_, q0, v, tau = quadruped_system(seed, T)
+    jtype = sys_.jtype.copy()
+    axis = sys_.axis.copy()
+    for calf in (3, 6, 9, 12):
+        jtype[calf] = PRISMATIC
+        axis[calf] = [0.0, 1.0, 0.0]
+    return replace(sys_, jtype=jtype, axis=axis), q0, v, tau
+
+
+def prismatic_chain_system(n: int, seed: int, T: int):
+    """chain_system(n, seed, T) with every third joint (local index 2, 5,
+    ...) prismatic, sliding along the link (axis (1, 0, 0)): a serial chain
+    that is not all revolute.  Same draws as chain_system."""
+    sys_, q0, qd0, tau = chain_system(n, seed, T)
+    jtype = sys_.jtype.copy()
+    axis = sys_.axis.copy()
+    jtype[2::3] = PRISMATIC
+    axis[2::3] = [1.0, 0.0, 0.0]
+    return replace(sys_, jtype=jtype, axis=axis), q0, qd0, tau
+
+
 # --------------------------------------------------------------------------
 # batches
 # --------------------------------------------------------------------------
@@ -303,7 +328,7 @@ def round_to_f32(b: Batch) -> Batch:
 
 def workload(name: str, n_systems: int | None = None, T: int | None = None,
              tau_dtype=np.float64) -> Batch:
-    """The five workloads by name:
+    """The workloads by name:
       chain7_fp64   1 chain of 7 revolute joints, seed 0, dt 1e-3, T 1000
       chain7_4096   4096 such chains (seed 1000+i), dt 1e-3, T 5000
       trees_8192    8192 uneven trees of 6-40 links, depth <= 6 (seed 2000+i),
@@ -311,6 +336,9 @@ def workload(name: str, n_systems: int | None = None, T: int | None = None,
       quad_1024     1024 quadrupeds (seed 3000+i), dt 1e-3, T 50000
       chains_2048   2048 chains of 5-50 links (seed 4000+i), dt 1e-3, T 1000,
                     q0 = qd0 = 0 and tau = 0 (optimisation start)
+      trees_prismatic_8192
+                    the trees_8192 systems with each joint prismatic with
+                    probability 0.3 (same shapes and draws otherwise)
     n_systems / T shrink a workload for tests (the seeds stay the same)."""
     if name == "chain7_fp64":
         ns, TT, dt = 1, 1000, 1e-3
@@ -324,6 +352,10 @@ def workload(name: str, n_systems: int | None = None, T: int | None = None,
         ns, TT, dt = 8192, 2000, 5e-4
         ns, TT = n_systems or ns, T or TT
         draws = [tree_system(2000 + i, TT) for i in range(ns)]
+    elif name == "trees_prismatic_8192":
+        ns, TT, dt = 8192, 2000, 5e-4
+        ns, TT = n_systems or ns, T or TT
+        draws = [tree_system(2000 + i, TT, prismatic=0.3) for i in range(ns)]
     elif name == "quad_1024":
         ns, TT, dt = 1024, 50000, 1e-3
         ns, TT = n_systems or ns, T or TT

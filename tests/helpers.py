@@ -68,7 +68,10 @@ def emu():
     global _emu
     if _emu is None:
         path = os.path.join(HERE, "hostemu", "libhostemu.so")
-        if not os.path.exists(path):
+        csrc = os.path.join(HERE, "..", "paper_2109_07719_amd", "csrc")
+        srcs = [os.path.join(HERE, "hostemu", "hostemu.cpp")] + [os.path.join(csrc, f) for f in
+                                                                  ("aba_lane.h", "spatial.h")]
+        if not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(f) for f in srcs):
             import subprocess
             subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wno-unknown-pragmas",
                                    "-o", path, os.path.join(HERE, "hostemu", "hostemu.cpp")])

@@ -36,7 +36,11 @@ Sys<S> make_sys(int n, const int* parent, const int* jtype, const double* cf, co
     LinkC<S>& L = s.L[i];
     for (int k = 0; k < 9; ++k) L.ET.m[k] = (S)c[k];
     L.rT = v3<S>((S)c[9], (S)c[10], (S)c[11]);
-    L.ax = v3<S>((S)c[12], (S)c[13], (S)c[14]);
+    // c[12..14] is the canonicalised joint axis e_z: S = [a; 0] revolute,
+    // [0; a] prismatic
+    const V3<S> ax = v3<S>((S)c[12], (S)c[13], (S)c[14]);
+    L.prism = jtype[i] == 2;
+    L.sm = L.prism ? v6<S>(zero3<S>(), ax) : v6<S>(ax, zero3<S>());
     L.m = (S)c[15];
     L.mc = v3<S>((S)c[16], (S)c[17], (S)c[18]);
     L.Ib = sy3<S>((S)c[19], (S)c[20], (S)c[21], (S)c[22], (S)c[23], (S)c[24]);
@@ -77,20 +81,22 @@ void fd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, Out<S>& o, S
   for (int i = 0; i < n; ++i) {
     Tape<S>& t = o.t[i];
     const LinkC<S>& L = s.L[i];
-    if (s.jtype[i] == 0) {
+    if (s.jtype[i] != 1) {
       const S qq = q[s.qi[i]];
-      t.E = joint_E(L, (S)std::sin(qq), (S)std::cos(qq));
+      t.sq = L.prism ? qq : (S)std::sin(qq);
+      t.cq = L.prism ? S(1) : (S)std::cos(qq);
+      joint_X(L, t);
       const V6<S> vp = s.parent[i] >= 0 ? o.t[s.parent[i]].v : zero6<S>();
-      t.v = p1_velocity(L, t.E, qd[s.vi[i]], vp);
+      t.v = p1_velocity(L, t, qd[s.vi[i]], vp);
     } else {
       const S* v = qd + s.vi[i];
       t.v = v6<S>(v3<S>(v[0], v[1], v[2]), v3<S>(v[3], v[4], v[5]));
     }
-    p1_bias(L, t.v, s.jtype[i] == 0 ? qd[s.vi[i]] : S(0), s.jtype[i] == 0, t.c, t.pA, t.IA);
+    p1_bias(L, t.v, s.jtype[i] != 1 ? qd[s.vi[i]] : S(0), s.jtype[i] != 1, t.c, t.pA, t.IA);
   }
   for (int i = n - 1; i >= 0; --i) {
     Tape<S>& t = o.t[i];
-    if (s.jtype[i] != 0) continue;
+    if (s.jtype[i] == 1) continue;
     p2_local(s.L[i], t, tau[s.ui[i]]);
     if (s.parent[i] >= 0) {
       SySp<S> IAu;
@@ -104,7 +110,7 @@ void fd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, Out<S>& o, S
   std::vector<V6<S>> acc(n);
   for (int i = 0; i < n; ++i) {
     Tape<S>& t = o.t[i];
-    if (s.jtype[i] == 0) {
+    if (s.jtype[i] != 1) {
       acc[i] = p3_accel(s.L[i], t, s.parent[i] >= 0 ? acc[s.parent[i]] : a0);
       qdd[s.vi[i]] = t.qdd;
     } else {
@@ -119,8 +125,8 @@ void fd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, Out<S>& o, S
 template <typename S>
 void integrate_seq(const Sys<S>& s, S* q, S* qd, const S* qdd, const Out<S>& o, S dt) {
   for (int i = 0; i < s.n; ++i) {
-    if (s.jtype[i] == 0) {
-      integrate_rev(q[s.qi[i]], qd[s.vi[i]], qdd[s.vi[i]], dt);
+    if (s.jtype[i] != 1) {
+      integrate_joint(q[s.qi[i]], qd[s.vi[i]], qdd[s.vi[i]], dt);
     } else {
       S* qq = q + s.qi[i];
       S* v = qd + s.vi[i];
@@ -153,7 +159,7 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
   Q4<S> quatb{};
   int root = -1;
   for (int i = 0; i < n; ++i) {
-    if (s.jtype[i] == 0) {
+    if (s.jtype[i] != 1) {
       const S tot = qdb[s.vi[i]] + dt * qb[s.qi[i]];
       qddb[i] = dt * tot;
       acc_q[i] = qb[s.qi[i]];
@@ -174,22 +180,22 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
   std::vector<SySp<S>> IAb(n, zero_sysp<S>());
   const V3<S> g = v3<S>(s.g[0], s.g[1], s.g[2]);
   for (int i = n - 1; i >= 0; --i) {
-    if (s.jtype[i] == 0) {
+    if (s.jtype[i] != 1) {
       const V6<S> apb = r3_link(s.L[i], o.t[i], b[i], ab[i], qddb[i]);
-      if (s.parent[i] >= 0) ab[s.parent[i]] = ab[s.parent[i]] + xformT(o.t[i].E, s.L[i].rT, apb);
+      if (s.parent[i] >= 0) ab[s.parent[i]] = ab[s.parent[i]] + xformT(o.t[i].E, o.t[i].r, apb);
     } else {
       r3_root(o.t[i].IA, o.t[i].ap, quat_of(q + s.qi[i]), g, ab[i], qddb6, quatb, IAb[i], pAb[i]);
     }
   }
   for (int i = 0; i < n; ++i) {
-    if (s.jtype[i] != 0) continue;
+    if (s.jtype[i] == 1) continue;
     const int p = s.parent[i];
     const bool hp = p >= 0;
     taub[s.ui[i]] = r2_link(s.L[i], o.t[i], b[i], hp, hp ? IAb[p] : zero_sysp<S>(), hp ? pAb[p] : zero6<S>(),
                             IAb[i], pAb[i]);
   }
   for (int i = n - 1; i >= 0; --i) {
-    if (s.jtype[i] == 0) {
+    if (s.jtype[i] != 1) {
       const V6<S> up = r1_link(s.L[i], o.t[i], b[i], vb[i], pAb[i], qd[s.vi[i]]);
       if (s.parent[i] >= 0) vb[s.parent[i]] = vb[s.parent[i]] + up;
     } else {
@@ -197,7 +203,7 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
     }
   }
   for (int i = 0; i < n; ++i) {
-    if (s.jtype[i] == 0) {
+    if (s.jtype[i] != 1) {
       qb[s.qi[i]] = acc_q[i] + b[i].q;
       qdb[s.vi[i]] = acc_qd[i] + b[i].qd;
     }

@@ -63,6 +63,7 @@ def _create(parent, jtype, n_sys_offsets, axis=None, mass=None, dtype=0):
     ([-1, 0], [0, 7], [0, 2], {}, -2),                      # unknown joint type
     ([-1] * 65, [0] * 65, [0, 65], {}, -2),                  # more than 64 links
     ([-1, 0], [0, 0], [0, 2], {"axis": [0, 0, 2.0, 0, 0, 1.0]}, -2),  # non-unit axis
+    ([-1, 0], [2, 2], [0, 2], {"axis": [0, 0, 1.0, 0, 0.5, 0]}, -2),  # non-unit prismatic axis
     ([-1, 0], [0, 0], [0, 2], {"mass": [1.0, 0.0]}, -2),    # non-positive mass
     ([-1, 0], [0, 0], [0, 2], {"mass": [1.0, np.nan]}, -2),  # non-finite parameter
     ([-1, 0], [0, 0], [1, 2], {}, -2),                      # link_offset[0] != 0
@@ -126,7 +127,8 @@ def test_tree_generator_respects_size_and_depth():
 
 # ---------------------------------------------------------------- host emulation
 
-@pytest.mark.parametrize("which", ["chain", "tree", "quad"])
+@pytest.mark.parametrize("which", ["chain", "tree", "quad", "prismatic_tree", "cartpole", "telescoping_quad",
+                                   "prismatic_chain"])
 def test_lane_arithmetic_matches_oracle_fp64(which):
     """The per-link functions the kernels call, driven link by link on the
     host in FP64, reproduce the oracle's accelerations and rollout gradients
@@ -135,8 +137,17 @@ def test_lane_arithmetic_matches_oracle_fp64(which):
         s, q0, qd0, tau = synth.chain_system(7, 1000, 120)
     elif which == "tree":
         s, q0, qd0, tau = synth.tree_system(2002, 120, random_frames=True)
-    else:
+    elif which == "quad":
         s, q0, qd0, tau = synth.quadruped_system(3003, 120)
+    elif which == "prismatic_tree":
+        s, q0, qd0, tau = synth.tree_system(2003, 120, random_frames=True, prismatic=0.4)
+        assert (s.jtype == synth.PRISMATIC).sum() >= 3
+    elif which == "cartpole":
+        s, q0, qd0, tau = synth.cartpole_system(5, 120)
+    elif which == "telescoping_quad":
+        s, q0, qd0, tau = synth.telescoping_quadruped_system(3004, 120)
+    else:
+        s, q0, qd0, tau = synth.prismatic_chain_system(8, 1001, 120)
     m = O.Model(s)
     assert rel(emu_fd(s, q0, qd0, tau[0]), O.fd(m, q0, qd0, tau[0]), 1e-12) < 1e-13
     rng = np.random.default_rng(1)
