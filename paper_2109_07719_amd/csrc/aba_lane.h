@@ -56,8 +56,7 @@ ABA_HD SySp<S> inertia_sysp(const LinkC<S>& L) {
 template <typename S>
 struct Tape {
   S sq, cq;    // joint coordinate as X_J needs it: sin q, cos q (revolute); q, 1 (prismatic)
-  M3<S> E;
-  V3<S> r;     // X = X_J(q) X_T = (E, r)
+  M3<S> E;     // rotation of X = X_J(q) X_T (its translation: joint_r)
   V6<S> v, c;
   SySp<S> IA;  // final articulated inertia (children included)
   V6<S> pA;    // final articulated bias force
@@ -74,25 +73,29 @@ struct Tape {
 // Revolute: E = E_J(q) E_T with E_J = I - sin q [e_z]x + (1 - cos q)[e_z]x^2
 // = [[c, s, 0], [-s, c, 0], [0, 0, 1]], r = r_T.  Prismatic: X_J is the
 // translation by q e_z, so E = E_T and r = r_T + q E_T^T e_z.
+// joint_X sets E; joint_r gives r where it is used, so that the revolute
+// kernels keep r_T as the link constant it is.
 template <typename S>
 ABA_HD void joint_X(const LinkC<S>& L, Tape<S>& t) {
   if (L.prism) {
     t.E = L.ET;
-    t.r = axpy(L.rT, t.sq, row(L.ET, 2));
   } else {
     M3<S> J;
     J.m[0] = t.cq;  J.m[1] = t.sq; J.m[2] = S(0);
     J.m[3] = -t.sq; J.m[4] = t.cq; J.m[5] = S(0);
     J.m[6] = S(0);  J.m[7] = S(0); J.m[8] = S(1);
     t.E = mul(J, L.ET);
-    t.r = L.rT;
   }
+}
+template <typename S>
+ABA_HD V3<S> joint_r(const LinkC<S>& L, const Tape<S>& t) {
+  return L.prism ? axpy(L.rT, t.sq, row(L.ET, 2)) : L.rT;
 }
 
 // pass 1 (1-dof joint): v = X v_parent + S qd
 template <typename S>
 ABA_HD V6<S> p1_velocity(const LinkC<S>& L, const Tape<S>& t, S qd, const V6<S>& vpar) {
-  return xform(t.E, t.r, vpar) + qd * L.sm;
+  return xform(t.E, joint_r(L, t), vpar) + qd * L.sm;
 }
 // pass 1 (all links): c = v x S qd, h = I v, pA = v x* h, IA = I
 template <typename S>
@@ -116,13 +119,13 @@ template <typename S>
 ABA_HD void p2_push(const LinkC<S>& L, Tape<S>& t, SySp<S>& IA_up, V6<S>& pA_up) {
   const SySp<S> Ia = rank1_down(t.IA, t.U, t.Dinv);
   t.pa = t.pA + mul(Ia, t.c) + (t.u * t.Dinv) * t.U;
-  IA_up = congruence_XT(t.E, t.r, Ia);
-  pA_up = xformT(t.E, t.r, t.pa);
+  IA_up = congruence_XT(t.E, joint_r(L, t), Ia);
+  pA_up = xformT(t.E, joint_r(L, t), t.pa);
 }
 // pass 3 (1-dof joint): a' = X a_parent + c, qdd = (u - U^T a') / D, a = a' + S qdd
 template <typename S>
 ABA_HD V6<S> p3_accel(const LinkC<S>& L, Tape<S>& t, const V6<S>& apar) {
-  t.ap = xform(t.E, t.r, apar) + t.c;
+  t.ap = xform(t.E, joint_r(L, t), apar) + t.c;
   t.qdd = (t.u - dot(t.U, t.ap)) * t.Dinv;
   return t.ap + t.qdd * L.sm;
 }
@@ -293,8 +296,8 @@ ABA_HD S r2_path(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent
   pAb = zero6<S>();
   if (has_parent) {
     // pA_parent += X^T pa;  IA_parent += X^T Ia X
-    pab = xform(t.E, t.r, pAbp);
-    N = congruence_X(t.E, t.r, IAbp);
+    pab = xform(t.E, joint_r(L, t), pAbp);
+    N = congruence_X(t.E, joint_r(L, t), IAbp);
     // pa = pA + Ia c + U u / D
     pAb = pAb + pab;
     const SySp<S> Iab = add_sym_outer(N, pab, t.c, S(1));
@@ -364,7 +367,7 @@ template <typename S>
 ABA_HD V6<S> r1_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, V6<S> vbar, const V6<S>& pAb, S qd) {
   vbar = vbar + r1_own(L, t.v, b, pAb, qd, true);
   r1_local(L, t, b, vbar, qd);
-  return xformT(t.E, t.r, vbar);
+  return xformT(t.E, joint_r(L, t), vbar);
 }
 
 // Adjoint of a link's ten inertial parameters: mass m, first moment

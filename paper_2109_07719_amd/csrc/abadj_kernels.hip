@@ -698,7 +698,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
       const V6<S> ab = from_next(up);
       if (act && l.depth == d) {
         apb = r3_path(L, tp, ab, qddb, g3);
-        if (l.par >= 0) up = xformT(tp.E, tp.r, apb);
+        if (l.par >= 0) up = xformT(tp.E, joint_r(L, tp), apb);
       }
     }
   } else {
@@ -708,7 +708,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
         for (int k = 0; k < l.ccount; ++k) ab = ab + get6(xb, 0, l.cfirst + k);
         if (rev) {
           apb = r3_path(L, tp, ab, qddb, g3);
-          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, tp.r, apb));
+          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, joint_r(L, tp), apb));
         } else if constexpr (FREE) {
           r3_root(tp.IA, tp.ap, st_quat(st), g, ab, qddb6, quatb, IAb, pAb);
         }
@@ -754,7 +754,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
       const V6<S> vb = from_next(up);
       if (act && l.depth == d) {
         vbar = vb + own;
-        if (l.par >= 0) up = xformT(tp.E, tp.r, vbar);
+        if (l.par >= 0) up = xformT(tp.E, joint_r(L, tp), vbar);
       }
     }
   } else {
@@ -764,7 +764,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
         for (int k = 0; k < l.ccount; ++k) vb = vb + get6(xb, 0, l.cfirst + k);
         vbar = vb + own;
         if (rev) {
-          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, tp.r, vbar));
+          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, joint_r(L, tp), vbar));
         } else if constexpr (FREE) {
           vb6 = vb6 + vbar;
         }
@@ -811,8 +811,14 @@ __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, con
 // checkpoint; K > 1 replays each K-step segment from its checkpoint into
 // the scratch buffer first.  The next state and control are fetched one
 // step ahead.
+// In FP32, fixed-base batches (trees, chains) run several wavefronts per
+// SIMD, so the kernel is held to two waves per SIMD (at most 256 VGPRs; it
+// needs a few more, which spill): otherwise the occupancy would halve.
+// Free-root batches pack few lanes per system and run at most one
+// wavefront per SIMD; FP64 would spill heavily under the limit.
 template <typename S, bool FREE, int FR, bool CHAIN>
-__global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_backward(BwdArgs<S> A) {
+__global__ __launch_bounds__(kWave * kMaxWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_backward(BwdArgs<S> A) {
   S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
   const int wb = wave_batch();
   const Lane l = load_lane(A.P, wb);

@@ -1060,7 +1060,7 @@ LinkOps link_ops(bool eti, bool prism) {
     (void)r1_link(L, t, b, v, w, Op());
   });
   o.bwd_rev_push = count([&] {
-                     (void)xformT(t.E, t.r, v);                   // a_bar to the parent
+                     (void)xformT(t.E, joint_r(L, t), v);         // a_bar to the parent
                      (void)r2_link(L, t, b, true, M, v, M2, w);  // parent share of pass 2
                    }) -
                    count([&] { (void)r2_link(L, t, b, false, M, v, M2, w); });

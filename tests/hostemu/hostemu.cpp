@@ -182,7 +182,7 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
   for (int i = n - 1; i >= 0; --i) {
     if (s.jtype[i] != 1) {
       const V6<S> apb = r3_link(s.L[i], o.t[i], b[i], ab[i], qddb[i]);
-      if (s.parent[i] >= 0) ab[s.parent[i]] = ab[s.parent[i]] + xformT(o.t[i].E, o.t[i].r, apb);
+      if (s.parent[i] >= 0) ab[s.parent[i]] = ab[s.parent[i]] + xformT(o.t[i].E, joint_r(s.L[i], o.t[i]), apb);
     } else {
       r3_root(o.t[i].IA, o.t[i].ap, quat_of(q + s.qi[i]), g, ab[i], qddb6, quatb, IAb[i], pAb[i]);
     }
