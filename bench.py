@@ -42,10 +42,16 @@ WORKLOADS = {
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak (dual-issue); 78.6 without packed issue
 
 
+KERNEL_SOURCES = ("csrc/spatial.h", "csrc/aba_lane.h", "csrc/dual.h", "csrc/abadj_device.h", "csrc/abadj_kernels.hip",
+                  "csrc/abadj_kernels_chain.hip", "_build.py")
+
+
 def kernel_source_hash():
+    """Hash of everything that decides the kernels' machine code (device
+    sources and build options)."""
     h = hashlib.sha256()
-    for n in ("spatial.h", "aba_lane.h", "abadj_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_2109_07719_amd", "csrc", n), "rb") as f:
+    for n in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2109_07719_amd", n), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 

@@ -143,6 +143,16 @@ struct Tiling {
   bool pipelined = true;
 };
 
+// Link-frame kinds of a kernel variant.  kFrIdentity: every E_T the
+// identity after canonicalisation, every joint revolute; kFrGeneral: any
+// E_T, every joint revolute; kFrPrismatic: any E_T, and prismatic joints
+// among the revolute ones (the joint type becomes a per-lane value).
+enum : int { kFrIdentity = 0, kFrGeneral = 1, kFrPrismatic = 2 };
+
+// Launchers: pick the kernel variant for the handle's shape and launch it on
+// `stream` (abadj_kernels.hip).  The serial-chain variants live in their own
+// translation unit (abadj_kernels_chain.hip), reached through the *_chain
+// launchers for frame kinds kFrIdentity and kFrGeneral.
 template <typename S>
 hipError_t launch_forward(const FwdArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
 template <typename S>
@@ -151,5 +161,13 @@ template <typename S>
 hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
 template <typename S>
 hipError_t launch_forward_jvp(const JvpArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
+template <typename S, int FR>
+hipError_t launch_forward_chain(const FwdArgs<S>& a, const Tiling& tl, hipStream_t st);
+template <typename S, int FR>
+hipError_t launch_backward_chain(const BwdArgs<S>& a, const Tiling& tl, hipStream_t st);
+template <typename S, int FR>
+hipError_t launch_aba_chain(const AbaArgs<S>& a, const Tiling& tl, hipStream_t st);
+template <typename S, int FR>
+hipError_t launch_forward_jvp_chain(const JvpArgs<S>& a, const Tiling& tl, hipStream_t st);
 
 }  // namespace aba
