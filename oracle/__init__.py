@@ -55,9 +55,9 @@ def _configure(L):
     L.orc_adjoint_along.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P, P]
     L.orc_adjoint_along.restype = ctypes.c_int
     L.orc_rollout_grad_params.argtypes = [P, P, P, P, ctypes.c_double, ctypes.c_int,
-                                          ctypes.c_int, P, P, P, P, P, P, P, P, P]
+                                          ctypes.c_int, P, P, P, P, P, P, P, P, P, P]
     L.orc_rollout_grad_params.restype = ctypes.c_int
-    L.orc_adjoint_along_params.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P, P, P]
+    L.orc_adjoint_along_params.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P, P, P, P]
     L.orc_adjoint_along_params.restype = ctypes.c_int
     return L
 
@@ -222,10 +222,12 @@ def rollout_grad(m: Model, q0, qd0, tau, dt, gqT, gqdT, gtraj=None, K: int = 1):
 
 
 def rollout_grad_params(m: Model, q0, qd0, tau, dt, gqT, gqdT, gtraj=None, K: int = 1):
-    """As rollout_grad, plus the gradient with respect to every link's ten
-    inertial parameters (m, h = m c, I about the link origin: xx yy zz xy xz
-    yz; link frame), summed over the rollout.  Returns gq0, gqd0, gtau,
-    gparam [n, 10], qT, qdT."""
+    """As rollout_grad, plus gradients with respect to model parameters,
+    summed over the rollout.  Returns gq0, gqd0, gtau, gparam [n, 10],
+    gframe [n, 9], qT, qdT.  gparam: every link's ten inertial parameters
+    (m, h = m c, I about the link origin: xx yy zz xy xz yz; link frame).
+    gframe: every 1-dof link's placement and axis (phi_bar, r_T_bar,
+    axis_bar; zero for a free root), as orc_rollout_grad_params states."""
     tau = _f64(tau)
     T = int(tau.shape[0])
     tau = np.ascontiguousarray(tau.reshape(T, m.nu))
@@ -233,18 +235,19 @@ def rollout_grad_params(m: Model, q0, qd0, tau, dt, gqT, gqdT, gtraj=None, K: in
     gqT, gqdT = _f64(gqT, m.nq), _f64(gqdT, m.nv)
     gtr = None if gtraj is None else np.ascontiguousarray(_f64(gtraj).reshape(T, m.nq + m.nv))
     gq0, gqd0, gtau = np.zeros(m.nq), np.zeros(m.nv), np.zeros((T, m.nu))
-    gparam = np.zeros((m.n, 10))
+    gparam, gframe = np.zeros((m.n, 10)), np.zeros((m.n, 9))
     qT, qdT = np.zeros(m.nq), np.zeros(m.nv)
     rc = lib().orc_rollout_grad_params(m.ref, _p(q0), _p(qd0), _p(tau), float(dt), T, int(K),
                                        _p(gqT), _p(gqdT), _p(gtr) if gtr is not None else None,
-                                       _p(gq0), _p(gqd0), _p(gtau), _p(gparam), _p(qT), _p(qdT))
+                                       _p(gq0), _p(gqd0), _p(gtau), _p(gparam), _p(gframe), _p(qT), _p(qdT))
     if rc != 0:
         raise RuntimeError("oracle rollout_grad_params failed")
-    return gq0, gqd0, gtau, gparam, qT, qdT
+    return gq0, gqd0, gtau, gparam, gframe, qT, qdT
 
 
 def adjoint_along_params(m: Model, states, tau, dt, gqT, gqdT, gtraj=None):
-    """adjoint_along plus the inertial-parameter gradient [n, 10]."""
+    """adjoint_along plus the parameter gradients gparam [n, 10] and
+    gframe [n, 9] (see rollout_grad_params)."""
     tau = _f64(tau)
     T = int(tau.shape[0])
     tau = np.ascontiguousarray(tau.reshape(T, m.nu))
@@ -252,13 +255,13 @@ def adjoint_along_params(m: Model, states, tau, dt, gqT, gqdT, gtraj=None):
     gqT, gqdT = _f64(gqT, m.nq), _f64(gqdT, m.nv)
     gtr = None if gtraj is None else np.ascontiguousarray(_f64(gtraj).reshape(T, m.nq + m.nv))
     gq0, gqd0, gtau = np.zeros(m.nq), np.zeros(m.nv), np.zeros((T, m.nu))
-    gparam = np.zeros((m.n, 10))
+    gparam, gframe = np.zeros((m.n, 10)), np.zeros((m.n, 9))
     rc = lib().orc_adjoint_along_params(m.ref, _p(st), _p(tau), float(dt), T, _p(gqT), _p(gqdT),
                                         _p(gtr) if gtr is not None else None, _p(gq0), _p(gqd0),
-                                        _p(gtau), _p(gparam))
+                                        _p(gtau), _p(gparam), _p(gframe))
     if rc != 0:
         raise RuntimeError("oracle adjoint_along_params failed")
-    return gq0, gqd0, gtau, gparam
+    return gq0, gqd0, gtau, gparam, gframe
 
 
 def adjoint_along(m: Model, states, tau, dt, gqT, gqdT, gtraj=None):

@@ -107,6 +107,7 @@ int orc_rollout_c(const orc_model *m, const void *q0, const void *qd0,
 typedef struct {
   double X[36], v[6], vJ[6], c[6], h[6];
   double IA[36], pA[6], U[6], D, u, Ia[36], pa[6], ap[6], a[6], qdd;
+  double S[6]; /* adjoint of the motion subspace */
 } link_bar;
 
 /* y += A^T x */
@@ -176,12 +177,102 @@ static void inertia_params_add(const double *Ibar, double *pbar) {
   pbar[9] += Ibar[8] + Ibar[13];
 }
 
+/* Adjoint of one 1-dof link's placement and axis, ADDED into fb[9], from
+ * the link's dense transform adjoint Xbar and motion-subspace adjoint Sbar
+ * at joint coordinate q (see orc_rollout_grad_params for the three
+ * parameter directions).  X = XJ(q; a) XT(E_T, r_T), XT = plucker(E_T, r_T):
+ *   r_T:  dXT/dr_k = [0 0; -E_T [e_k]x 0];
+ *   E_T -> exp(-[phi]x) E_T:  dXT/dphi_k = plucker'(-[e_k]x E_T, r_T);
+ *   a -> exp([w]x) a, da = e_k x a:
+ *     revolute  EJ = I - sin q [a]x + (1 - cos q)[a]x^2, S = [a; 0],
+ *       dEJ = -sin q [da]x + (1 - cos q)([da]x [a]x + [a]x [da]x);
+ *     prismatic XJ = [I 0; -[q a]x I], S = [0; a], dXJ = [0 0; -q [da]x 0];
+ *   and the axis output is w_bar x a, the gradient with respect to the axis
+ *   vector along the unit sphere. */
+static void frame_params_add(const orc_model *m, int i, double q, const double *Xbar, const double *Sbar,
+                             double *fb) {
+  const double *ax = m->axis + 3 * i, *ET = m->E_T + 9 * i, *rT = m->r_T + 3 * i;
+  const int prism = m->jtype[i] == ORC_PRISMATIC;
+  double XJ[36], XT[36], zero3[3] = {0, 0, 0}, I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  if (prism) {
+    double ra[3] = {q * ax[0], q * ax[1], q * ax[2]};
+    plucker_r(I3, ra, XJ);
+  } else {
+    double EJ[9];
+    joint_rot_r(q, ax, EJ);
+    plucker_r(EJ, zero3, XJ);
+  }
+  plucker_r(ET, rT, XT);
+  for (int k = 0; k < 3; ++k) {
+    double ek[3] = {0, 0, 0}, ekx[9], dXT[36], dX[36];
+    ek[k] = 1;
+    skew3_r(ek, ekx);
+    /* r_T */
+    for (int j = 0; j < 36; ++j) dXT[j] = 0;
+    double Ee[9];
+    mat3_mul_r(ET, ekx, Ee);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) dXT[6 * (3 + r) + c] = -Ee[3 * r + c];
+    mat6_mul_r(XJ, dXT, dX);
+    double sr = 0;
+    for (int j = 0; j < 36; ++j) sr += Xbar[j] * dX[j];
+    fb[3 + k] += sr;
+    /* E_T rotation: d(plucker(E, r)) = [dE 0; -dE [r]x dE] with dE = -[e_k]x E_T */
+    double dE[9], rx[9], dErx[9];
+    mat3_mul_r(ekx, ET, dE);
+    for (int j = 0; j < 9; ++j) dE[j] = -dE[j];
+    skew3_r(rT, rx);
+    mat3_mul_r(dE, rx, dErx);
+    for (int j = 0; j < 36; ++j) dXT[j] = 0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        dXT[6 * r + c] = dE[3 * r + c];
+        dXT[6 * (3 + r) + 3 + c] = dE[3 * r + c];
+        dXT[6 * (3 + r) + c] = -dErx[3 * r + c];
+      }
+    mat6_mul_r(XJ, dXT, dX);
+    double sp = 0;
+    for (int j = 0; j < 36; ++j) sp += Xbar[j] * dX[j];
+    fb[k] += sp;
+  }
+  /* axis: w_bar_k = <Xbar, dXJ_k XT> + Sbar . dS_k */
+  double wb[3];
+  for (int k = 0; k < 3; ++k) {
+    double da[3] = {0, 0, 0}, dax[9], dXJ[36], dX[36];
+    /* da = e_k x a */
+    da[(k + 1) % 3] = -ax[(k + 2) % 3];
+    da[(k + 2) % 3] = ax[(k + 1) % 3];
+    skew3_r(da, dax);
+    for (int j = 0; j < 36; ++j) dXJ[j] = 0;
+    if (prism) {
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) dXJ[6 * (3 + r) + c] = -q * dax[3 * r + c];
+    } else {
+      double axx[9], t1[9], t2[9], dEJ[9];
+      skew3_r(ax, axx);
+      mat3_mul_r(dax, axx, t1);
+      mat3_mul_r(axx, dax, t2);
+      for (int j = 0; j < 9; ++j) dEJ[j] = -sin(q) * dax[j] + (1.0 - cos(q)) * (t1[j] + t2[j]);
+      plucker_r(dEJ, zero3, dXJ);
+    }
+    mat6_mul_r(dXJ, XT, dX);
+    double sw = 0;
+    for (int j = 0; j < 36; ++j) sw += Xbar[j] * dX[j];
+    for (int j = 0; j < 3; ++j) sw += Sbar[prism ? 3 + j : j] * da[j];
+    wb[k] = sw;
+  }
+  fb[6] += wb[1] * ax[2] - wb[2] * ax[1];
+  fb[7] += wb[2] * ax[0] - wb[0] * ax[2];
+  fb[8] += wb[0] * ax[1] - wb[1] * ax[0];
+}
+
 /* Reverse of aba_tape_r: ADD d<qdd_bar, qdd>/d(q, qd, tau), and, when
  * param_bar is not NULL, the adjoint of every link's inertial parameters
- * ([n][10], see inertia_params_add). */
+ * ([n][10], see inertia_params_add), when frame_bar is not NULL that of
+ * every 1-dof link's placement and axis ([n][9], see frame_params_add). */
 static int aba_vjp(const orc_model *m, const double *q, const double *qd,
                    const tape_t *L, const double *qdd_bar, double *q_bar,
-                   double *qd_bar, double *tau_bar, double *param_bar) {
+                   double *qd_bar, double *tau_bar, double *param_bar, double *frame_bar) {
   const int n = m->n;
   int qi[n], vi[n], ui[n];
   layout_r(m, qi, vi, ui);
@@ -219,6 +310,7 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
     /* a = ap + S qdd */
     for (int k = 0; k < 6; ++k) b->ap[k] += b->a[k];
     for (int k = 0; k < 6; ++k) b->qdd += Sv[k] * b->a[k];
+    for (int k = 0; k < 6; ++k) b->S[k] += b->a[k] * l->qdd;
     /* qdd = (u - U^T ap) / D */
     const double gq = b->qdd / l->D;
     b->u += gq;
@@ -280,11 +372,15 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
     /* u = tau - S^T pA */
     tau_bar[ui[i]] += b->u;
     for (int k = 0; k < 6; ++k) b->pA[k] -= Sv[k] * b->u;
+    for (int k = 0; k < 6; ++k) b->S[k] -= b->u * l->pA[k];
     /* D = S^T U */
     for (int k = 0; k < 6; ++k) b->U[k] += Sv[k] * b->D;
+    for (int k = 0; k < 6; ++k) b->S[k] += b->D * l->U[k];
     /* U = IA S */
     for (int r = 0; r < 6; ++r)
       for (int c = 0; c < 6; ++c) b->IA[6 * r + c] += b->U[r] * Sv[c];
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) b->S[c] += l->IA[6 * r + c] * b->U[r];
   }
 
   /* reverse of pass 1, leaves -> root */
@@ -335,6 +431,7 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
     double Sv[6];
     motion_subspace_r(m, i, Sv);
     for (int k = 0; k < 6; ++k) qd_bar[vi[i]] += Sv[k] * b->vJ[k];
+    for (int k = 0; k < 6; ++k) b->S[k] += b->vJ[k] * qd[vi[i]];
     /* X = XJ(q) XT.  Revolute: dX/dq = plucker(dEJ/dq, 0) XT with
        dEJ/dq = -cos q [a]x + sin q [a]x^2.  Prismatic: XJ = [I 0; -[q a]x I],
        dXJ/dq = [0 0; -[a]x 0]. */
@@ -360,6 +457,7 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
       for (int k = 0; k < 36; ++k) sdot += b->X[k] * dX[k];
       q_bar[qi[i]] += sdot;
     }
+    if (frame_bar) frame_params_add(m, i, q[qi[i]], b->X, b->S, frame_bar + 9 * i);
   }
   free(B);
   return 0;
@@ -372,7 +470,7 @@ void orc_fd_vjp(const orc_model *m, const double *q, const double *qd,
   tape_t *L = (tape_t *)malloc(sizeof(tape_t) * (size_t)m->n);
   double *qdd = (double *)malloc(sizeof(double) * (size_t)nv);
   aba_tape_r(m, q, qd, tau, L, qdd);
-  aba_vjp(m, q, qd, L, qdd_bar, q_bar, qd_bar, tau_bar, NULL);
+  aba_vjp(m, q, qd, L, qdd_bar, q_bar, qd_bar, tau_bar, NULL, NULL);
   free(qdd);
   free(L);
 }
@@ -384,7 +482,7 @@ void orc_fd_vjp(const orc_model *m, const double *q, const double *qd,
 static int step_vjp(const orc_model *m, const double *q, const double *qd,
                     const double *qdd, const tape_t *L, double dt,
                     const double *q1bar, const double *qd1bar, double *qbar,
-                    double *qdbar, double *taubar, double *qddbar, double *pbar) {
+                    double *qdbar, double *taubar, double *qddbar, double *pbar, double *fbar) {
   const int n = m->n, nu = orc_nu(m);
   int qi[n], vi[n], ui[n];
   layout_r(m, qi, vi, ui);
@@ -444,7 +542,7 @@ static int step_vjp(const orc_model *m, const double *q, const double *qd,
       qdbar[vi[i]] = tot;
     }
   }
-  return aba_vjp(m, q, qd, L, qddbar, qbar, qdbar, taubar, pbar);
+  return aba_vjp(m, q, qd, L, qddbar, qbar, qdbar, taubar, pbar, fbar);
 }
 
 static void tape_qdd(const orc_model *m, const tape_t *L, double *qdd) {
@@ -463,10 +561,12 @@ int orc_rollout_grad_params(const orc_model *m, const double *q0, const double *
                             const double *tau, double dt, int T, int K,
                             const double *gqT, const double *gqdT,
                             const double *gtraj, double *gq0, double *gqd0,
-                            double *gtau, double *gparam, double *qT, double *qdT) {
+                            double *gtau, double *gparam, double *gframe, double *qT, double *qdT) {
   if (T < 0 || K < 0) return -1;
   if (gparam)
     for (int k = 0; k < 10 * m->n; ++k) gparam[k] = 0;
+  if (gframe)
+    for (int k = 0; k < 9 * m->n; ++k) gframe[k] = 0;
   const int n = m->n, nq = orc_nq(m), nv = orc_nv(m), nu = orc_nu(m);
   const int nx = nq + nv;
   const int ncp = (K >= 1) ? (T + K - 1) / K : 0;
@@ -529,7 +629,7 @@ int orc_rollout_grad_params(const orc_model *m, const double *q0, const double *
         const double *xt = scratch + (size_t)(t - t0) * nx;
         aba_tape_r(m, xt, xt + nq, tau + (size_t)t * nu, tape, qdd);
         rc = step_vjp(m, xt, xt + nq, qdd, tape, dt, xb, xb + nq, xb1, xb1 + nq,
-                      gtau + (size_t)t * nu, qddbar, gparam);
+                      gtau + (size_t)t * nu, qddbar, gparam, gframe);
         memcpy(xb, xb1, sizeof(double) * nx);
         if (gtraj && t >= 1)
           for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(t - 1) * nx + k];
@@ -541,7 +641,7 @@ int orc_rollout_grad_params(const orc_model *m, const double *q0, const double *
       const tape_t *Lt = tapes + (size_t)t * n;
       tape_qdd(m, Lt, qdd);
       rc = step_vjp(m, xt, xt + nq, qdd, Lt, dt, xb, xb + nq, xb1, xb1 + nq,
-                    gtau + (size_t)t * nu, qddbar, gparam);
+                    gtau + (size_t)t * nu, qddbar, gparam, gframe);
       memcpy(xb, xb1, sizeof(double) * nx);
       if (gtraj && t >= 1)
         for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(t - 1) * nx + k];
@@ -560,16 +660,18 @@ int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
                      const double *gtraj, double *gq0, double *gqd0,
                      double *gtau, double *qT, double *qdT) {
   return orc_rollout_grad_params(m, q0, qd0, tau, dt, T, K, gqT, gqdT, gtraj, gq0, gqd0, gtau, NULL,
-                                 qT, qdT);
+                                 NULL, qT, qdT);
 }
 
 int orc_adjoint_along_params(const orc_model *m, const double *states, const double *tau,
                              double dt, int T, const double *gqT, const double *gqdT,
                              const double *gtraj, double *gq0, double *gqd0, double *gtau,
-                             double *gparam) {
+                             double *gparam, double *gframe) {
   if (T < 0) return -1;
   if (gparam)
     for (int k = 0; k < 10 * m->n; ++k) gparam[k] = 0;
+  if (gframe)
+    for (int k = 0; k < 9 * m->n; ++k) gframe[k] = 0;
   const int n = m->n, nq = orc_nq(m), nv = orc_nv(m), nu = orc_nu(m);
   const int nx = nq + nv;
   tape_t *tape = (tape_t *)malloc(sizeof(tape_t) * (size_t)n);
@@ -586,7 +688,7 @@ int orc_adjoint_along_params(const orc_model *m, const double *states, const dou
     const double *xt = states + (size_t)t * nx;
     aba_tape_r(m, xt, xt + nq, tau + (size_t)t * nu, tape, qdd);
     rc = step_vjp(m, xt, xt + nq, qdd, tape, dt, xb, xb + nq, xb1, xb1 + nq,
-                  gtau + (size_t)t * nu, qddbar, gparam);
+                  gtau + (size_t)t * nu, qddbar, gparam, gframe);
     memcpy(xb, xb1, sizeof(double) * nx);
     if (gtraj && t >= 1)
       for (int k = 0; k < nx; ++k) xb[k] += gtraj[(size_t)(t - 1) * nx + k];
@@ -601,5 +703,5 @@ int orc_adjoint_along_params(const orc_model *m, const double *states, const dou
 int orc_adjoint_along(const orc_model *m, const double *states, const double *tau,
                       double dt, int T, const double *gqT, const double *gqdT,
                       const double *gtraj, double *gq0, double *gqd0, double *gtau) {
-  return orc_adjoint_along_params(m, states, tau, dt, T, gqT, gqdT, gtraj, gq0, gqd0, gtau, NULL);
+  return orc_adjoint_along_params(m, states, tau, dt, T, gqT, gqdT, gtraj, gq0, gqd0, gtau, NULL, NULL);
 }

@@ -108,19 +108,28 @@ int orc_rollout_grad(const orc_model *m, const double *q0, const double *qd0,
                      const double *gtraj, double *gq0, double *gqd0,
                      double *gtau, double *qT, double *qdT);
 
-/* As orc_rollout_grad, and also the gradient with respect to every link's
- * ten inertial parameters, summed over all steps: gparam is [n][10], per
- * link (m, h_x, h_y, h_z, I_xx, I_yy, I_zz, I_xy, I_xz, I_yz) with h = m c
- * the first moment and I the rotational inertia about the link origin
- * (I_c - m [c]x^2), all in the link frame; an off-diagonal parameter stands
- * for both of its matrix entries.  Sec. 4.1, after Eq. adj_r: the gradient
- * of any other parameter follows from the same per-step adjoints as the
- * control gradient; Sec. 6.3 (parameter estimation). */
+/* As orc_rollout_grad, and also gradients with respect to model
+ * parameters, summed over all steps (each output nullable).  Sec. 4.1,
+ * after Eq. adj_r: the gradient of any other parameter follows from the same
+ * per-step adjoints as the control gradient; Sec. 6.3 (parameter
+ * estimation).
+ *   gparam [n][10]: every link's ten inertial parameters (m, h_x, h_y, h_z,
+ *     I_xx, I_yy, I_zz, I_xy, I_xz, I_yz) with h = m c the first moment and
+ *     I the rotational inertia about the link origin (I_c - m [c]x^2), all
+ *     in the link frame; an off-diagonal parameter stands for both of its
+ *     matrix entries.
+ *   gframe [n][9]: every 1-dof link's placement and axis (zero for a free
+ *     root): (phi_bar[3], r_T_bar[3], axis_bar[3]).  phi: rotation of the
+ *     joint frame, E_T -> exp(-[phi]x) E_T, phi in joint-frame coordinates;
+ *     r_T_bar: the gradient with respect to r_T (parent coordinates);
+ *     axis_bar: the gradient with respect to the axis vector along the unit
+ *     sphere (link coordinates, orthogonal to the axis): a change da
+ *     orthogonal to the axis changes the loss by axis_bar . da. */
 int orc_rollout_grad_params(const orc_model *m, const double *q0, const double *qd0,
                             const double *tau, double dt, int T, int K,
                             const double *gqT, const double *gqdT,
                             const double *gtraj, double *gq0, double *gqd0,
-                            double *gtau, double *gparam, double *qT, double *qdT);
+                            double *gtau, double *gparam, double *gframe, double *qT, double *qdT);
 
 /* The reverse sweep alone, along a given trajectory: states is [T][nq + nv]
  * with row t = x^t (the initial state of step t), used as the per-step
@@ -131,7 +140,7 @@ int orc_adjoint_along(const orc_model *m, const double *states, const double *ta
 int orc_adjoint_along_params(const orc_model *m, const double *states, const double *tau,
                              double dt, int T, const double *gqT, const double *gqdT,
                              const double *gtraj, double *gq0, double *gqd0, double *gtau,
-                             double *gparam);
+                             double *gparam, double *gframe);
 
 #ifdef __cplusplus
 }

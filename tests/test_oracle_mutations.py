@@ -51,6 +51,15 @@ MUTATIONS = [
     ("aba_fwd.inc", "Sv[k] = prism ? 0.0 : ax[k];", "Sv[k] = ax[k];", "prismatic motion subspace with an angular part"),
     ("aba_fwd.inc", "l->vJ[k] = 0; l->vJ[k + 3] = m->axis[3 * i + k] * qd[vi[i]];",
      "l->vJ[k] = m->axis[3 * i + k] * qd[vi[i]]; l->vJ[k + 3] = 0;", "prismatic joint velocity as a rotation"),
+    ("aba_oracle.c", "    for (int j = 0; j < 3; ++j) sw += Sbar[prism ? 3 + j : j] * da[j];\n", "",
+     "dropped motion-subspace term of the axis gradient"),
+    ("aba_oracle.c", "dEJ[j] = -sin(q) * dax[j] + (1.0 - cos(q)) * (t1[j] + t2[j]);",
+     "dEJ[j] = sin(q) * dax[j] + (1.0 - cos(q)) * (t1[j] + t2[j]);", "joint-rotation axis derivative sign"),
+    ("aba_oracle.c", "mat3_mul_r(ET, ekx, Ee);", "mat3_mul_r(ekx, ET, Ee);", "transposed joint-origin derivative"),
+    ("aba_oracle.c", "        dXT[6 * (3 + r) + c] = -dErx[3 * r + c];\n", "",
+     "dropped translation term of the frame-rotation derivative"),
+    ("aba_oracle.c", "      for (int c = 0; c < 6; ++c) b->S[c] += l->IA[6 * r + c] * b->U[r];",
+     "      for (int c = 0; c < 6; ++c) b->S[c] += 0.0;", "dropped U = IA S term of the motion-subspace adjoint"),
 ]
 
 PINS = [
@@ -69,6 +78,8 @@ PINS = [
     lambda: pins.test_inertial_parameter_gradient_central_differences(1),
     pins.test_cartpole_closed_form,
     pins.test_rollout_gradient_complex_step_with_prismatic_joints,
+    pins.test_frame_gradient_invariances_of_a_fixed_base_tree,
+    lambda: pins.test_frame_and_axis_gradients_central_differences(0),
 ]
 
 

@@ -513,7 +513,7 @@ def test_inertial_parameter_gradient_scaling_identity(k):
     inertial parameters), so <theta, dL/dtheta> + <tau, dL/dtau> = 0 exactly."""
     name, (s, q0, qd0, tau), dt = _param_problems()[k]
     _, qT, qdT = _param_loss(s, q0, qd0, tau, dt)
-    _, _, gtau, g, _, _ = O.rollout_grad_params(O.Model(s), q0, qd0, tau, dt, 2 * qT, qdT)
+    _, _, gtau, g, _, _, _ = O.rollout_grad_params(O.Model(s), q0, qd0, tau, dt, 2 * qT, qdT)
     th = _inertial_params(s)
     a, b = float(np.sum(th * g)), float(np.sum(tau * gtau))
     assert abs(a + b) < 1e-9 * max(abs(a), abs(b)), (a, b)
@@ -580,7 +580,7 @@ def test_rollout_gradient_complex_step_with_prismatic_joints():
         assert np.any(s.jtype == synth.PRISMATIC)
         m = O.Model(s)
         qT, qdT = O.rollout(m, q0, qd0, tau, dt)
-        gq0, gqd0, gtau, gp, _, _ = O.rollout_grad_params(m, q0, qd0, tau, dt, 2 * qT, qdT)
+        gq0, gqd0, gtau, gp, _, _, _ = O.rollout_grad_params(m, q0, qd0, tau, dt, 2 * qT, qdT)
         h = 1e-30
 
         def L(a, b_, t):
@@ -606,3 +606,107 @@ def test_rollout_gradient_complex_step_with_prismatic_joints():
                 fd = (_param_loss(_with_inertial_params(s, tp), q0, qd0, tau, dt)[0] -
                       _param_loss(_with_inertial_params(s, tm), q0, qd0, tau, dt)[0]) / (2 * hh)
                 assert abs(fd - gp[i, j]) < 2e-6 * max(1.0, np.abs(gp).max())
+
+
+# ------------------------------------------------------------- placement and axis gradients
+
+def _rodrigues(w):
+    """exp([w]x) for a rotation vector w."""
+    th = float(np.linalg.norm(w))
+    if th < 1e-300:
+        return np.eye(3)
+    k = w / th
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * (K @ K)
+
+
+def _with_frame(s, i, which, d):
+    """The same system with link i's joint frame rotated (E_T -> exp(-[d]x) E_T),
+    its joint origin moved (r_T + d) or its axis rotated (exp([d]x) a)."""
+    E, r, a = s.E_T.copy(), s.r_T.copy(), s.axis.copy()
+    if which == "phi":
+        E[i] = _rodrigues(-np.asarray(d)) @ E[i]
+    elif which == "r":
+        r[i] = r[i] + d
+    else:
+        a[i] = _rodrigues(np.asarray(d)) @ a[i]
+    return synth.System(parent=s.parent, jtype=s.jtype, E_T=E, r_T=r, axis=a, mass=s.mass, com=s.com, Ic=s.Ic)
+
+
+def _frame_problems():
+    tree = synth.tree_system(2012, 100, nmax=16, random_frames=True, prismatic=0.4)
+    quad = synth.telescoping_quadruped_system(3009, 100)
+    chain = synth.chain_system(5, 12, 100)
+    return [("tree", tree, 5e-4), ("quad", quad, 1e-3), ("chain", chain, 1e-3)]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_frame_and_axis_gradients_central_differences(k):
+    """Gradients with respect to each 1-dof link's joint-frame rotation, joint
+    origin and joint axis against central differences of the (pinned) forward
+    rollout: a branched tree with random frames and prismatic joints, a
+    free-floating quadruped with sliding knees, a chain.  The axis output is
+    the gradient along the unit sphere, so a rotation w of the axis changes
+    the loss by (a x axis_bar) . w (Sec. 4.1, after Eq. adj_r)."""
+    name, (s, q0, qd0, tau), dt = _frame_problems()[k]
+    _, qT, qdT = _param_loss(s, q0, qd0, tau, dt)
+    gf = O.rollout_grad_params(O.Model(s), q0, qd0, tau, dt, 2 * qT, qdT)[4]
+    scale = np.abs(gf).max()
+    assert scale > 1e-3
+    rng = np.random.default_rng(20 + k)
+    links = [i for i in range(s.n) if s.jtype[i] != synth.FREE]
+    links = sorted(set([links[0], links[-1]] + list(rng.choice(links, size=min(3, len(links)), replace=False))))
+    h = 1e-6
+    for i in links:
+        a = s.axis[i] / np.linalg.norm(s.axis[i])
+        for which, off in (("phi", 0), ("r", 3), ("w", 6)):
+            for j in range(3):
+                d = np.zeros(3)
+                d[j] = h
+                fd = (_param_loss(_with_frame(s, i, which, d), q0, qd0, tau, dt)[0] -
+                      _param_loss(_with_frame(s, i, which, -d), q0, qd0, tau, dt)[0]) / (2 * h)
+                if which == "w":
+                    ref = np.cross(a, gf[i, 6:9])[j]
+                else:
+                    ref = gf[i, off + j]
+                assert abs(fd - ref) < 2e-6 * max(1.0, scale), (name, i, which, j, fd, ref)
+        # the axis gradient is tangent to the unit sphere
+        assert abs(np.dot(gf[i, 6:9], a)) < 1e-12 * max(1.0, scale)
+    # a free root has no placement or axis
+    for i in range(s.n):
+        if s.jtype[i] == synth.FREE:
+            assert not np.any(gf[i])
+
+
+def test_frame_gradient_invariances_of_a_fixed_base_tree():
+    """Moving a fixed-base system's only root joint (all links with it) leaves
+    the joint-space motion unchanged, and so does turning it about the
+    gravity direction: r_T_bar of the root is zero and phi_bar of the root
+    is orthogonal to E_T g.  Exact, not within a difference quotient."""
+    for s, q0, qd0, tau, dt in (synth.tree_system(2013, 100, nmax=16, random_frames=True, prismatic=0.3) + (5e-4,),
+                                synth.chain_system(6, 13, 100) + (1e-3,)):
+        assert np.sum(s.parent < 0) == 1
+        m = O.Model(s)
+        qT, qdT = O.rollout(m, q0, qd0, tau, dt)
+        gf = O.rollout_grad_params(m, q0, qd0, tau, dt, 2 * qT, qdT)[4]
+        scale = np.abs(gf).max()
+        assert scale > 1e-3
+        assert np.abs(gf[0, 3:6]).max() < 1e-10 * scale
+        gdir = np.asarray(synth.GRAVITY) / np.linalg.norm(synth.GRAVITY)
+        assert abs(np.dot(gf[0, 0:3], s.E_T[0] @ gdir)) < 1e-10 * scale
+        # and the other two rotation directions do matter
+        assert np.abs(gf[0, 0:3]).max() > 1e-6 * scale
+
+
+def test_frame_gradients_checkpointing_and_along():
+    """K and store-all give bitwise-identical placement and axis gradients,
+    and the sweep along the oracle's own trajectory reproduces them."""
+    s, q0, qd0, tau = synth.telescoping_quadruped_system(3010, 60)
+    m = O.Model(s)
+    qT, qdT = O.rollout(m, q0, qd0, tau, 1e-3)
+    ref = O.rollout_grad_params(m, q0, qd0, tau, 1e-3, 2 * qT, qdT, K=1)[4]
+    for K in (0, 7, 60):
+        assert np.array_equal(O.rollout_grad_params(m, q0, qd0, tau, 1e-3, 2 * qT, qdT, K=K)[4], ref)
+    _, _, traj = O.rollout(m, q0, qd0, tau, 1e-3, traj=True)
+    states = np.concatenate([np.r_[q0, qd0][None], traj[:-1]])
+    assert np.array_equal(O.adjoint_along_params(m, states, tau, 1e-3, 2 * qT, qdT)[4], ref)
