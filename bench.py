@@ -80,7 +80,7 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
     import oracle as O
 
     qo, vo, uo = batch.offsets()
-    gq0, gqd0, gtau, gparam = grads
+    gq0, gqd0, gtau, gparam, gframe = grads
     lo = np.cumsum([0] + [s.n for s in batch.systems])
     n = len(batch.systems)
 
@@ -126,7 +126,8 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
         tau = np.asarray(batch.tau[:, uo[i]:uo[i + 1]], dtype=np.float64)
         g = O.adjoint_along_params(m, states, tau, batch.dt, 2 * trajs[k][-1, :nqi], np.zeros(vo[i + 1] - vo[i]))
         return (max(rel(gq0[qo[i]:qo[i + 1]], g[0]), rel(gqd0[vo[i]:vo[i + 1]], g[1]),
-                    rel(gtau[:, uo[i]:uo[i + 1]], g[2])), rel(gparam[lo[i]:lo[i + 1]], g[3]))
+                    rel(gtau[:, uo[i]:uo[i + 1]], g[2])),
+                max(rel(gparam[lo[i]:lo[i + 1]], g[3]), rel(gframe[lo[i]:lo[i + 1]], g[4])))
 
     both = O.map_threads(along, range(len(idx)), threads=threads)
     e_along = [a for a, _ in both]
@@ -153,6 +154,7 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
            "along_gpu_trajectory_frac_above_1e-3": float(np.mean(np.asarray(e_along) > 1e-3)),
            "end_to_end_vs_fp64_max": max(e2e), "end_to_end_vs_fp64_median": float(np.median(e2e)),
            "param_grads_along_gpu_trajectory_max": max(e_param),
+           "param_grads_what": "max over the inertial-parameter and the placement/axis gradients",
            "param_grads_along_gpu_trajectory_median": float(np.median(e_param)),
            "systems": len(idx), "norm": "per system ||g - g_ref|| / ||g_ref||, max over (gq0, gqd0, gtau)",
            "note": "end-to-end differences on long horizons come from chaotic divergence of FP32 and FP64 "
@@ -477,9 +479,10 @@ def main():
         sim.backward(tau, dt, K, ws, gqT, gqdT, out=(gq0, gqd0, gtau))
 
     gparam = torch.empty((sim.info["n_links"], 10), dtype=torch.float32, device=dev)
+    gframe = torch.empty((sim.info["n_links"], 9), dtype=torch.float32, device=dev)
 
     def bwd_params():
-        sim.backward(tau, dt, K, ws, gqT, gqdT, out=(gq0, gqd0, gtau, gparam), params=True)
+        sim.backward(tau, dt, K, ws, gqT, gqdT, out=(gq0, gqd0, gtau, gparam, gframe), params=True)
 
     def plain():
         sim.forward(q0, qd0, tau, dt, K=K, workspace=None, out=(pqT, pqdT, None))
@@ -525,7 +528,7 @@ def main():
         pev[k][1].record()
     torch.cuda.synchronize()
     plain_ms = [pev[k][0].elapsed_time(pev[k][1]) for k in range(args.steps)]
-    # adjoint with inertial-parameter gradients (outside the headline value)
+    # adjoint with model-parameter gradients (outside the headline value)
     graphs["fwd"].replay()
     for k in range(args.steps):
         pev[k][0].record()
@@ -537,7 +540,7 @@ def main():
     graphs["bwd"].replay()
     torch.cuda.synchronize()
 
-    grads = (gq0.cpu().numpy(), gqd0.cpu().numpy(), gtau.cpu().numpy(), gparam.cpu().numpy())
+    grads = (gq0.cpu().numpy(), gqd0.cpu().numpy(), gtau.cpu().numpy(), gparam.cpu().numpy(), gframe.cpu().numpy())
     finite = all(np.all(np.isfinite(g)) for g in grads) and bool(torch.isfinite(qT).all())
     nonfinite_outputs = sim.status()
     dof_steps = b.total_dof * T
@@ -572,8 +575,9 @@ def main():
            "adjoint_with_param_grads": {"kernel_ms": float(np.mean(bwd_params_ms)),
                                         "fwd_adjoint_dof_steps_per_s":
                                             dof_steps / ((float(np.mean(fwd_ms)) + float(np.mean(bwd_params_ms))) * 1e-3),
-                                        "what": "gradient with respect to every link's 10 inertial parameters "
-                                                "as well, summed over the rollout"}, "fwd_adjoint_over_plain_fwd_time": value and plain_rate / value,
+                                        "what": "gradients with respect to every link's 10 inertial parameters "
+                                                "and its joint placement and axis (9) as well, summed over the "
+                                                "rollout"}, "fwd_adjoint_over_plain_fwd_time": value and plain_rate / value,
            "peak_mem_bytes": int(peak_mem), "results_finite": finite, "nonfinite_outputs": nonfinite_outputs, "roofline": roofline,
            "wall_s_timed": wall, "input_gen_s": t_gen}
     if not args.no_cpu_baseline:

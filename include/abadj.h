@@ -259,10 +259,23 @@ int sim_forward(sim_t h, const void *q0, const void *qd0, const void *tau, doubl
  * (m, h_x, h_y, h_z, I_xx, I_yy, I_zz, I_xy, I_xz, I_yz) with h = m c the
  * first moment and I = I_c - m [c]x^2 the rotational inertia about the link
  * origin; an off-diagonal parameter stands for both of its matrix entries.
+ * gframe (nullable) [n_links][9]: the gradient with respect to every
+ * revolute or prismatic link's joint placement X_T = (E_T, r_T) and joint
+ * axis a, summed over the rollout, per link in the caller's link order
+ * (zeros for a free root): (phi_bar[3], r_T_bar[3], axis_bar[3]).
+ *   phi_bar: a rotation of the joint frame, E_T -> exp(-[phi]x) E_T with phi
+ *     in joint-frame coordinates, changes the loss by phi_bar . phi;
+ *   r_T_bar: the gradient with respect to r_T (parent coordinates);
+ *   axis_bar: the gradient with respect to the axis vector along the unit
+ *     sphere (link coordinates, orthogonal to a): a change da orthogonal
+ *     to a changes the loss by axis_bar . da.
+ * Either parameter output selects kernels that accumulate the model
+ * parameters' adjoints; without them the adjoint runs without that work.
  * Errors as sim_forward. */
 int sim_backward(sim_t h, const void *tau, double dt, int T, int K, const void *gqT,
                  const void *gqdT, const void *gtraj, void *gq0, void *gqd0, void *gtau,
-                 void *gparam, void *workspace, size_t workspace_bytes, void *stream);
+                 void *gparam, void *gframe, void *workspace, size_t workspace_bytes,
+                 void *stream);
 
 /* Forward-mode (tangent) rollout: the T-step rollout of sim_forward with
  * one input direction (dq0 [nq], dqd0 [nv], dtau [T][nu]) carried along,

@@ -88,7 +88,7 @@ def lib():
         L.sim_workspace_bytes.restype = I
         L.sim_forward.argtypes = [P, P, P, P, D, I, I, P, P, P, P, Z, P]
         L.sim_forward.restype = I
-        L.sim_backward.argtypes = [P, P, D, I, I, P, P, P, P, P, P, P, P, Z, P]
+        L.sim_backward.argtypes = [P, P, D, I, I, P, P, P, P, P, P, P, P, P, Z, P]
         L.sim_backward.restype = I
         L.sim_checkpoint_schedule.argtypes = [I, I, P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong)]
         L.sim_checkpoint_schedule.restype = I

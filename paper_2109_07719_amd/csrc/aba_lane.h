@@ -236,23 +236,36 @@ struct Bar {
   V6<S> U;     // U_bar
   S D, u;      // D_bar, u_bar
   S q, qd;     // contributions to the joint angle / rate adjoints
+  // Model-parameter adjoints of the step, formed only when params is set
+  // (a compile-time constant in the kernels):
+  bool params;
+  V6<S> G;     // the link transform's: X -> exp(-crm(z)) X changes the loss by G . z
+  V6<S> Sb;    // the motion subspace's
 };
 template <typename S>
-ABA_HD void bar_zero(Bar<S>& b) {
+ABA_HD void bar_zero(Bar<S>& b, bool params = false) {
+  b.params = params;
   b.c = zero6<S>();
   b.U = zero6<S>();
   b.D = S(0);
   b.u = S(0);
   b.q = S(0);
   b.qd = S(0);
+  b.G = zero6<S>();
+  b.Sb = zero6<S>();
 }
 
-// The joint-coordinate pairing -x^T crm(S) y of a statement y = X m
-// (x = y_bar) or y = X^T f (x = f, y = X y_bar), from dX/dq = -crm(S) X:
-// s_ang . (x_ang x y_ang + x_lin x y_lin) + s_lin . (x_lin x y_ang).
+// The pairing of a statement y = X m (x = y_bar) or y = X^T f (x = f,
+// y = X y_bar) with a change X -> exp(-crm(z)) X is -x^T crm(z) y = z . qvec(x, y),
+// qvec(x, y) = [x_ang x y_ang + x_lin x y_lin; x_lin x y_ang].  With
+// dX/dq = -crm(S) X the joint-coordinate pairing is S . qvec(x, y).
+template <typename S>
+ABA_HD V6<S> qvec(const V6<S>& x, const V6<S>& y) {
+  return v6<S>(cross(x.a, y.a) + cross(x.l, y.l), cross(x.l, y.a));
+}
 template <typename S>
 ABA_HD S qpair(const V6<S>& sm, const V6<S>& x, const V6<S>& y) {
-  return dot(sm.a, cross(x.a, y.a) + cross(x.l, y.l)) + dot(sm.l, cross(x.l, y.a));
+  return dot(sm, qvec(x, y));
 }
 
 // reverse of pass 3 (1-dof joint), in two parts for the level sweep.  The
@@ -272,8 +285,14 @@ ABA_HD void r3_local(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>
   b.U = b.U - g * t.ap;
   b.D = b.D - g * t.qdd;
   // ap = X a_parent + c
-  b.q = b.q + qpair(L.sm, apb, t.ap - t.c);
+  const V6<S> xv = qvec(apb, t.ap - t.c);
+  b.q = b.q + dot(L.sm, xv);
   b.c = b.c + apb;
+  if (b.params) {
+    b.G = b.G + xv;
+    // a = ap + S qdd, with a_bar = ap_bar + g U
+    b.Sb = b.Sb + t.qdd * (apb + g * t.U);
+  }
 }
 template <typename S>
 ABA_HD V6<S> r3_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>& abar, S qddbar) {
@@ -322,10 +341,17 @@ ABA_HD S r2_path(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent
 }
 template <typename S>
 ABA_HD void r2_local(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const SySp<S>& N, const V6<S>& pab) {
-  b.q = b.q + qpair(L.sm, t.pa, pab);
   const SySp<S> Ia = rank1_down(t.IA, t.U, t.Dinv);
-  b.q = b.q - S(2) * pair_crmS(Ia, N, L.sm);
+  const V6<S> xv = qvec(t.pa, pab) - S(2) * crmS_vec(Ia, N);
+  b.q = b.q + dot(L.sm, xv);
+  if (b.params) b.G = b.G + xv;
   b.c = b.c + mul(Ia, pab);
+}
+// motion-subspace adjoint of pass 2 (every 1-dof link, once its U_bar,
+// D_bar and u_bar are final): u = tau - S^T pA, D = S^T U, U = IA S
+template <typename S>
+ABA_HD void r2_sbar(const Tape<S>& t, Bar<S>& b) {
+  b.Sb = b.Sb - b.u * t.pA + b.D * t.U + mul(t.IA, b.U);
 }
 template <typename S>
 ABA_HD S r2_link(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, bool has_parent, const SySp<S>& IAbp,
@@ -360,7 +386,13 @@ ABA_HD void r1_local(const LinkC<S>& L, const Tape<S>& t, Bar<S>& b, const V6<S>
   b.qd = b.qd + dot(L.sm, vJb);
   // v = X v_parent + vJ
   const V6<S> Xv = t.v - qd * L.sm;
-  b.q = b.q + qpair(L.sm, vbar, Xv);
+  const V6<S> xv = qvec(vbar, Xv);
+  b.q = b.q + dot(L.sm, xv);
+  if (b.params) {
+    b.G = b.G + xv;
+    // vJ = S qd
+    b.Sb = b.Sb + qd * vJb;
+  }
 }
 // 1-dof joint: vbar holds the children's shares; returns X^T v_bar
 template <typename S>
@@ -386,12 +418,48 @@ struct ParamBar {
   S m;
   V3<S> mc;
   Sy3<S> Ib;
+  // placement and axis of a 1-dof joint (frame_bar_add)
+  V6<S> xi;  // joint-frame perturbation of X_T
+  V3<S> w;   // axis rotation, beyond xi's angular part
 };
 template <typename S>
 ABA_HD void param_bar_zero(ParamBar<S>& g) {
   g.m = S(0);
   g.mc = zero3<S>();
   g.Ib = sy3<S>(S(0), S(0), S(0), S(0), S(0), S(0));
+  g.xi = zero6<S>();
+  g.w = zero3<S>();
+}
+
+// X_J^T f for the joint transform of the tape (revolute: rot(E_J) with
+// E_J = [[c, s, 0], [-s, c, 0], [0, 0, 1]]; prismatic: xlt(q e_z), whose
+// transpose is [1 [q e_z]x; 0 1]).
+template <typename S>
+ABA_HD V6<S> joint_XT_mul(const LinkC<S>& L, const Tape<S>& t, const V6<S>& f) {
+  if (L.prism) {
+    const V3<S> r = v3<S>(S(0), S(0), t.sq);
+    return v6<S>(f.a + cross(r, f.l), f.l);
+  }
+  auto rotT = [&](const V3<S>& x) {
+    return v3<S>(t.cq * x.x - t.sq * x.y, t.sq * x.x + t.cq * x.y, x.z);
+  };
+  return v6<S>(rotT(f.a), rotT(f.l));
+}
+
+// Adds one step's placement and axis adjoint of a 1-dof link, in the
+// kernels' joint frame (axis e_z), from the step's transform adjoint G and
+// motion-subspace adjoint Sb (Bar).  With X = X_J(q) X_T:
+//   X_T -> exp(-crm(xi)) X_T moves X by -crm(X_J xi) X, so xi_bar += X_J^T G;
+//   rotating the axis by w (a -> exp([w]x) a) turns X_J into
+//   rot(R) X_J rot(R)^T, which moves X by -crm(X_J w - w) X (w = [w; 0]),
+//   and S by [w x a; 0] (revolute) or [0; w x a] (prismatic):
+//   w_bar += (X_J^T G)_ang - G_ang + a x Sb_(ang or lin).
+// The first term is xi_bar's angular part, so only the rest is kept in w.
+template <typename S>
+ABA_HD void frame_bar_add(ParamBar<S>& g, const LinkC<S>& L, const Tape<S>& t, const Bar<S>& b) {
+  g.xi = g.xi + joint_XT_mul(L, t, b.G);
+  const V3<S> sb = L.prism ? b.Sb.l : b.Sb.a;
+  g.w = g.w - b.G.a + v3<S>(-sb.y, sb.x, S(0));
 }
 template <typename S>
 ABA_HD void param_bar_add(ParamBar<S>& g, const SySp<S>& IAb, const V6<S>& v, const V6<S>& pAb) {

@@ -391,6 +391,46 @@ __device__ __forceinline__ int store_param_bar(const ParamBar<S>& g, const Packe
   return n;
 }
 
+// Writes a link's placement and axis gradient (phi_bar, r_T_bar, axis_bar)
+// in the caller's frames from the accumulators in the kernels' joint frame
+// (xi, w; frame_bar_add).  The kernels' X_T' = rot(Rl) X_T rot(Rp)^T, so a
+// joint-frame perturbation xi of the caller's X_T is rot(Rl) xi here:
+// xi = [Rl^T xi'_a; Rl^T xi'_l], phi_bar = xi_a and r_T_bar = E_T^T xi_l =
+// Rp^T E_T'^T xi'_l.  The axis rotation adjoint is w = Rl^T (xi'_a + w'),
+// and the gradient along the unit sphere is w x a = Rl^T ((xi'_a + w') x e_z).
+// A free root has none: zeros.  Returns the number of non-finite values.
+template <typename S>
+__device__ __forceinline__ int store_frame_bar(const ParamBar<S>& g, const Packed<S>& P, const Lane& l,
+                                               const LinkC<S>& L, S* out) {
+  const int ns = P.nslots;
+  S v[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) v[k] = S(0);
+  if (l.onedof()) {
+    M3<S> Rl, Rp;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rl.m[k] = P.cf[(CF_RL + k) * ns + l.slot];
+    const int ps = l.slot - l.lane + l.par;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rp.m[k] = (l.par >= 0) ? P.cf[(CF_RL + k) * ns + ps] : ((k % 4 == 0) ? S(1) : S(0));
+    const V3<S> phi = mulT(Rl, g.xi.a);
+    const V3<S> rb = mulT(Rp, mulT(L.ET, g.xi.l));
+    const V3<S> w = g.xi.a + g.w;
+    const V3<S> ab = mulT(Rl, v3<S>(w.y, -w.x, S(0)));
+    v[0] = phi.x; v[1] = phi.y; v[2] = phi.z;
+    v[3] = rb.x; v[4] = rb.y; v[5] = rb.z;
+    v[6] = ab.x; v[7] = ab.y; v[8] = ab.z;
+  }
+  S* o = out + (size_t)l.link * 9;
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    o[k] = v[k];
+    n += nonfinite(v[k]);
+  }
+  return n;
+}
+
 // Everything one ABA evaluation leaves in a lane.
 template <typename S>
 struct Step {
@@ -653,7 +693,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
 // initial state st, then run the adjoints of the integrator, pass 3, pass 2
 // and pass 1.  xb1 holds the adjoint of x^{t+1} on entry and that of x^t on
 // exit; tau_bar^t is written to gtau.
-template <typename S, bool FREE, bool CHAIN>
+template <typename S, bool FREE, bool CHAIN, bool PARAMS>
 __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, const LinkC<S>& L, int maxd,
                                             S* xb, const State<S, FREE>& st, const Step<S>& o, int t,
                                             State<S, FREE>& xb1, int& nonfin, ParamBar<S>& pg) {
@@ -682,7 +722,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
     }
   }
   Bar<S> b;
-  bar_zero(b);
+  bar_zero(b, PARAMS);
   // Each reverse sweep keeps only what a parent or child needs inside the
   // level loop; the statements that update a link's own accumulators run
   // once for all lanes outside it.
@@ -743,7 +783,9 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
   }
   if (rev && l.par >= 0) r2_local(L, tp, b, N, pab);
   // inertial-parameter adjoint of this step: IAb and pAb are final here
-  if (A.gparam != nullptr && act) param_bar_add(pg, IAb, tp.v, pAb);
+  if constexpr (PARAMS) {
+    if (A.gparam != nullptr && act) param_bar_add(pg, IAb, tp.v, pAb);
+  }
   // reverse of pass 1, leaves -> root
   const V6<S> own = act ? r1_own(L, tp.v, b, pAb, st.qd[0], rev) : zero6<S>();
   V6<S> vbar = zero6<S>();
@@ -772,6 +814,13 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
     }
   }
   if (rev) r1_local(L, tp, b, vbar, st.qd[0]);
+  // placement and axis adjoint of this step (every 1-dof link)
+  if constexpr (PARAMS) {
+    if (A.gframe != nullptr && rev) {
+      r2_sbar(tp, b);
+      frame_bar_add(pg, L, tp, b);
+    }
+  }
   // adjoint of the step's initial state; tau_bar
   if (rev) {
     xb1.q[0] = acc_q + b.q;
@@ -797,13 +846,13 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
   }
 }
 
-template <typename S, bool FREE, bool CHAIN>
+template <typename S, bool FREE, bool CHAIN, bool PARAMS>
 __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, const LinkC<S>& L, int maxd,
                                          S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1,
                                          int& nonfin, ParamBar<S>& pg) {
   Step<S> o;
   aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
-  bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
+  bwd_reverse<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
 }
 
 // Backward (adjoint) rollout, reverse time.  K == 1 reloads every step's
@@ -815,7 +864,8 @@ __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, con
 // needs a few more, which spill): otherwise the occupancy would halve.
 // Free-root batches pack few lanes per system and run at most one
 // wavefront per SIMD; FP64 would spill heavily under the limit.
-template <typename S, bool FREE, int FR, bool CHAIN>
+// PARAMS: the variant that also accumulates model-parameter gradients.
+template <typename S, bool FREE, int FR, bool CHAIN, bool PARAMS>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock)
 __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_backward(BwdArgs<S> A) {
   S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
@@ -855,7 +905,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         get_slot(st, row, ns, nf, l.slot, l.fidx);
         get_tape(o, row + RW, ns, l.slot, L, st.qd[0], rev);
       }
-      bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
+      bwd_reverse<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
     }
   } else if (A.K == 1) {
     State<S, FREE> nxt = {};
@@ -871,7 +921,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
         if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
       }
-      bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, st, tau, t, xb1, nonfin, pg);
+      bwd_step<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, st, tau, t, xb1, nonfin, pg);
     }
   } else if (A.K < 0) {
     // binomial checkpointing: every wave runs the same host-built schedule
@@ -895,7 +945,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         if (act) put_slot(cur, A.ck + (size_t)slot * RW, ns, nf, l.slot, l.fidx);
       } else {
         const S tau = rev ? A.tau[(size_t)arg * nu + l.uidx] : S(0);
-        bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, cur, tau, arg, xb1, nonfin, pg);
+        bwd_step<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, cur, tau, arg, xb1, nonfin, pg);
       }
     }
   } else {
@@ -930,14 +980,20 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
           if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
-        bwd_step<S, FREE, CHAIN>(A, l, L, maxd, xb, cur, tau, t, xb1, nonfin, pg);
+        bwd_step<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, cur, tau, t, xb1, nonfin, pg);
       }
     }
   }
   if (act) {
     store_state(xb1, l, A.gq0, A.gqd0);
     nonfin += nonfinite_state(xb1, l);
-    if (A.gparam != nullptr) nonfin += store_param_bar(pg, A.P, l, A.gparam);
+    if constexpr (PARAMS) {
+      if constexpr (PARAMS) {
+        if (A.gparam != nullptr) nonfin += store_param_bar(pg, A.P, l, A.gparam);
+        if (A.gframe != nullptr) nonfin += store_frame_bar(pg, A.P, l, L, A.gframe);
+      }
+      if (A.gframe != nullptr) nonfin += store_frame_bar(pg, A.P, l, L, A.gframe);
+    }
   }
   report_nonfinite(A.P.status, nonfin);
 }
@@ -955,7 +1011,7 @@ __host__ __device__ constexpr size_t pipe_lds_per_pair() {
   return (size_t)((CHAIN ? 0 : 2 * XB) + 2 * TW) * kWave * sizeof(S);
 }
 
-template <typename S, bool FREE, int FR, bool CHAIN>
+template <typename S, bool FREE, int FR, bool CHAIN, bool PARAMS>
 __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe(BwdArgs<S> A) {
   constexpr int TW = kTapeFields + (FREE ? 13 : 2);
   const int pair = threadIdx.x / (2 * kWave);
@@ -1028,14 +1084,20 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
         for (int j = 0; j < (FREE ? 6 : 1); ++j) st.qd[j] = tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane];
         Step<S> o;
         get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, L, st.qd[0], rev);
-        bwd_reverse<S, FREE, CHAIN>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
+        bwd_reverse<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
       }
       __syncthreads();
     }
     if (act) {
       store_state(xb1, l, A.gq0, A.gqd0);
       nonfin += nonfinite_state(xb1, l);
-      if (A.gparam != nullptr) nonfin += store_param_bar(pg, A.P, l, A.gparam);
+      if constexpr (PARAMS) {
+      if constexpr (PARAMS) {
+        if (A.gparam != nullptr) nonfin += store_param_bar(pg, A.P, l, A.gparam);
+        if (A.gframe != nullptr) nonfin += store_frame_bar(pg, A.P, l, L, A.gframe);
+      }
+      if (A.gframe != nullptr) nonfin += store_frame_bar(pg, A.P, l, L, A.gframe);
+    }
     }
     report_nonfinite(A.P.status, nonfin);
   }
@@ -1169,20 +1231,27 @@ hipError_t launch_forward_v(const FwdArgs<S>& a, const Tiling& tl, hipStream_t s
   return hipGetLastError();
 }
 
-template <typename S, bool F, int E, bool C>
-hipError_t launch_backward_v(const BwdArgs<S>& a, const Tiling& tl, hipStream_t st) {
-  if (a.P.nwaves == 0) return hipSuccess;
+template <typename S, bool F, int E, bool C, bool PARAMS>
+hipError_t launch_backward_p(const BwdArgs<S>& a, const Tiling& tl, hipStream_t st) {
   if (a.K == 1 && tl.pipelined) {
     const size_t per = pipe_lds_per_pair<S, F, E, C>();
     int p = tl.pairs_per_block == 2 ? 2 : 1;
     while (p > 1 && (per * p > lds_limit() || a.P.nwaves % p != 0)) p /= 2;
-    hipLaunchKernelGGL((k_backward_pipe<S, F, E, C>), dim3(a.P.nwaves / p), dim3(2 * kWave * p), per * p, st, a);
+    hipLaunchKernelGGL((k_backward_pipe<S, F, E, C, PARAMS>), dim3(a.P.nwaves / p), dim3(2 * kWave * p), per * p,
+                       st, a);
   } else {
     size_t lds = 0;
     const int w = single_wpb<S, C>(tl, a.P.nwaves, lds);
-    hipLaunchKernelGGL((k_backward<S, F, E, C>), dim3(a.P.nwaves / w), dim3(kWave * w), lds, st, a);
+    hipLaunchKernelGGL((k_backward<S, F, E, C, PARAMS>), dim3(a.P.nwaves / w), dim3(kWave * w), lds, st, a);
   }
   return hipGetLastError();
+}
+// the kernels that accumulate model-parameter gradients only when asked for
+template <typename S, bool F, int E, bool C>
+hipError_t launch_backward_v(const BwdArgs<S>& a, const Tiling& tl, hipStream_t st) {
+  if (a.P.nwaves == 0) return hipSuccess;
+  if (a.gparam != nullptr || a.gframe != nullptr) return launch_backward_p<S, F, E, C, true>(a, tl, st);
+  return launch_backward_p<S, F, E, C, false>(a, tl, st);
 }
 
 template <typename S, bool F, int E, bool C>

@@ -70,6 +70,7 @@ struct BwdArgs {
   S* ck;           // checkpoints (K < 0: x^0 and the snapshot slots, written here)
   S* scratch;      // K > 1: [K][state width][nslots]
   S* gparam;       // nullable: [n_links][10] inertial-parameter gradients
+  S* gframe;       // nullable: [n_links][9] placement and axis gradients
   const int32_t* sched;  // K < 0: binomial checkpointing actions, (op, arg) pairs
   int nsched;
 };

@@ -699,8 +699,8 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
 }
 
 int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* gqT, const void* gqdT,
-                 const void* gtraj, void* gq0, void* gqd0, void* gtau, void* gparam, void* workspace,
-                 size_t workspace_bytes, void* stream) {
+                 const void* gtraj, void* gq0, void* gqd0, void* gtau, void* gparam, void* gframe,
+                 void* workspace, size_t workspace_bytes, void* stream) {
   g_err.clear();
   int rc = check_run(h, dt, T, K, "sim_backward");
   if (rc) return rc;
@@ -735,6 +735,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.sched = (K < 0) ? h->d_sched : nullptr;
     a.nsched = (K < 0) ? h->sched_n : 0;
     a.gparam = (double*)gparam;
+    a.gframe = (double*)gframe;
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   } else {
     aba::BwdArgs<float> a;
@@ -754,6 +755,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.sched = (K < 0) ? h->d_sched : nullptr;
     a.nsched = (K < 0) ? h->sched_n : 0;
     a.gparam = (float*)gparam;
+    a.gframe = (float*)gframe;
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   }
   if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_backward: launch failed: ") + hipGetErrorString(e));
@@ -904,7 +906,8 @@ int sim_autotune(sim_t h, int K, int T_probe, void* stream, sim_tiling_t* chosen
   };
   auto fwd = [&]() { return sim_forward(h, q0, qd0, tau, dt, T, K, qT, qdT, nullptr, ws, ws_bytes, stream); };
   auto bwd = [&]() {
-    return sim_backward(h, tau, dt, T, K, gqT, gqdT, nullptr, gq0, gqd0, gtau, nullptr, ws, ws_bytes, stream);
+    return sim_backward(h, tau, dt, T, K, gqT, gqdT, nullptr, gq0, gqd0, gtau, nullptr, nullptr, ws, ws_bytes,
+                        stream);
   };
   const int wpbs[3] = {1, 2, 4};
   double F[3], Bnp[3], Bp[2] = {1e300, 1e300};

@@ -443,13 +443,19 @@ ABA_HD M3<S> transpose(const M3<S>& A) {
 // [a]x in both diagonal blocks and [l]x in the lower-left one, so
 //   = a . avec(M_A N_A + M_B N_B^T + M_B^T N_B + M_C N_C)
 //   + l . avec(M_B^T N_A + M_C N_B^T)
+// crmS_vec(M, N) is the vector [w; wl] of those two avec terms, so that the
+// pairing is linear in s: <M N, crm(s)> = s . crmS_vec(M, N).
 template <typename S>
-ABA_HD S pair_crmS(const SySp<S>& M, const SySp<S>& N, const V6<S>& s) {
+ABA_HD V6<S> crmS_vec(const SySp<S>& M, const SySp<S>& N) {
   const M3<S> MA = sy_to_m3(M.A), NA = sy_to_m3(N.A), MC = sy_to_m3(M.C), NC = sy_to_m3(N.C);
   const M3<S> MBt = transpose(M.B), NBt = transpose(N.B);
   const V3<S> w = avec_prod(MA, NA) + avec_prod(M.B, NBt) + avec_prod(MBt, N.B) + avec_prod(MC, NC);
   const V3<S> wl = avec_prod(MBt, NA) + avec_prod(MC, NBt);
-  return dot(s.a, w) + dot(s.l, wl);
+  return v6<S>(w, wl);
+}
+template <typename S>
+ABA_HD S pair_crmS(const SySp<S>& M, const SySp<S>& N, const V6<S>& s) {
+  return dot(s, crmS_vec(M, N));
 }
 
 // ---------------------------------------------------------------- quaternions (x, y, z, w)

@@ -185,10 +185,13 @@ class Sim:
 
     def backward(self, tau, dt, K, workspace, gqT, gqdT, gtraj=None, out=None, params=False):
         """Adjoint pass after forward() on the same workspace.  Returns
-        (gq0, gqd0, gtau), and with params=True also the gradient with
-        respect to every link's ten inertial parameters [n_links, 10]
-        (m, h = m c, I about the link origin xx yy zz xy xz yz; caller's
-        link frames), summed over the rollout."""
+        (gq0, gqd0, gtau), and with params=True also, summed over the
+        rollout, the gradient with respect to every link's ten inertial
+        parameters [n_links, 10] (m, h = m c, I about the link origin xx yy
+        zz xy xz yz; caller's link frames) and with respect to every 1-dof
+        link's placement and axis [n_links, 9] (phi_bar: rotation of the
+        joint frame E_T -> exp(-[phi]x) E_T; r_T_bar; axis_bar along the unit
+        sphere; zeros for a free root)."""
         tau = tau.reshape(-1, self.nu) if self.nu else tau
         T = int(tau.shape[0])
         self._t(gqT, self.nq, "gqT"), self._t(gqdT, self.nv, "gqdT")
@@ -199,13 +202,14 @@ class Sim:
             gqd0 = torch.empty(self.nv, dtype=self.dtype, device=dev)
             gtau = torch.empty((T, self.nu), dtype=self.dtype, device=dev)
             gparam = torch.empty((self.info["n_links"], 10), dtype=self.dtype, device=dev) if params else None
+            gframe = torch.empty((self.info["n_links"], 9), dtype=self.dtype, device=dev) if params else None
         else:
             gq0, gqd0, gtau = out[:3]
-            gparam = out[3] if params else None
+            gparam, gframe = (out[3], out[4]) if params else (None, None)
         N.check(N.lib().sim_backward(self._h, _ptr(tau), float(dt), T, int(K), _ptr(gqT), _ptr(gqdT),
-                                     _ptr(gtraj), _ptr(gq0), _ptr(gqd0), _ptr(gtau), _ptr(gparam),
+                                     _ptr(gtraj), _ptr(gq0), _ptr(gqd0), _ptr(gtau), _ptr(gparam), _ptr(gframe),
                                      _ptr(workspace), workspace.numel(), _stream()))
-        return (gq0, gqd0, gtau, gparam) if params else (gq0, gqd0, gtau)
+        return (gq0, gqd0, gtau, gparam, gframe) if params else (gq0, gqd0, gtau)
 
 
 class _Rollout(torch.autograd.Function):

@@ -80,7 +80,7 @@ def emu():
         L.emu_fd_d.argtypes = [ctypes.c_int] + [P] * 8
         L.emu_fd_f.argtypes = [ctypes.c_int] + [P] * 8
         for n in ("emu_rollout_grad_d", "emu_rollout_grad_f"):
-            getattr(L, n).argtypes = [ctypes.c_int] + [P] * 7 + [ctypes.c_double, ctypes.c_int] + [P] * 7
+            getattr(L, n).argtypes = [ctypes.c_int] + [P] * 7 + [ctypes.c_double, ctypes.c_int] + [P] * 8
         _emu = L
     return _emu
 
@@ -99,6 +99,33 @@ def _axis_to_z(a):
     k = k / sn
     K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
     return np.eye(3) + sn * K + (1 - c) * (K @ K)
+
+
+def canonical_rotations(s):
+    """Per link, the rotation Rl of the library's joint-axis canonicalisation
+    (identity for a free root)."""
+    return [np.eye(3) if s.jtype[i] == 1 else _axis_to_z(s.axis[i]) for i in range(s.n)]
+
+
+def frame_grad_to_user(s, acc):
+    """Placement and axis gradients (phi_bar, r_T_bar, axis_bar) per link, in
+    the caller's frames, from the accumulators in the kernels' canonical
+    joint frames: xi (6) and w (3).  xi_user = [Rl^T xi_a; Rl^T xi_l];
+    r_T_bar = E_T^T xi_user_l; the axis rotation adjoint is
+    w_user = Rl^T (xi_a + w), and the axis gradient is w_user x a."""
+    Rs = canonical_rotations(s)
+    out = np.zeros((s.n, 9))
+    for i in range(s.n):
+        if s.jtype[i] == 1:
+            continue
+        R = Rs[i]
+        xa, xl = R.T @ acc[i, 0:3], R.T @ acc[i, 3:6]
+        a = np.asarray(s.axis[i], dtype=np.float64)
+        a = a / np.linalg.norm(a)
+        out[i, 0:3] = xa
+        out[i, 3:6] = np.asarray(s.E_T[i]).T @ xl
+        out[i, 6:9] = np.cross(R.T @ (acc[i, 0:3] + acc[i, 6:9]), a)
+    return out
 
 
 def link_constants(s):
@@ -148,7 +175,7 @@ def emu_fd(s, q, qd, tau, gravity=(0.0, -9.81, 0.0), f32=False):
     return out
 
 
-def emu_rollout_grad(s, q0, qd0, tau, dt_, gqT, gqdT, gravity=(0.0, -9.81, 0.0), f32=False):
+def emu_rollout_grad(s, q0, qd0, tau, dt_, gqT, gqdT, gravity=(0.0, -9.81, 0.0), f32=False, frame=False):
     dt = np.float32 if f32 else np.float64
     par = np.ascontiguousarray(s.parent, np.int32)
     jt = np.ascontiguousarray(s.jtype, np.int32)
@@ -158,7 +185,10 @@ def emu_rollout_grad(s, q0, qd0, tau, dt_, gqT, gqdT, gravity=(0.0, -9.81, 0.0),
     gq0, gqd0 = np.zeros(s.nq, dt), np.zeros(s.nv, dt)
     gtau = np.zeros((T, s.nu), dt)
     qT, qdT = np.zeros(s.nq, dt), np.zeros(s.nv, dt)
+    acc = np.zeros((s.n, 9), dt)
     (emu().emu_rollout_grad_f if f32 else emu().emu_rollout_grad_d)(
         s.n, _p(par), _p(jt), _p(cf), _p(g), _p(q0), _p(qd0), _p(tau), float(dt_), T, _p(gqT), _p(gqdT),
-        _p(gq0), _p(gqd0), _p(gtau), _p(qT), _p(qdT))
+        _p(gq0), _p(gqd0), _p(gtau), _p(qT), _p(qdT), _p(acc) if frame else None)
+    if frame:
+        return gq0, gqd0, gtau, qT, qdT, frame_grad_to_user(s, acc.astype(np.float64))
     return gq0, gqd0, gtau, qT, qdT

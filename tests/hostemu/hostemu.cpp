@@ -142,8 +142,11 @@ void integrate_seq(const Sys<S>& s, S* q, S* qd, const S* qdd, const Out<S>& o, 
 }
 
 // one reverse step, mirrors the kernel's bwd_step (sequential tree order)
+// pg (nullable): per-link parameter accumulators; the placement and axis
+// part (frame_bar_add) is formed when it is given
 template <typename S>
-void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb, S* qdb, S* taub) {
+void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb, S* qdb, S* taub,
+             std::vector<ParamBar<S>>* pg) {
   const int n = s.n;
   Out<S> o;
   std::vector<S> qdd(qdb ? 0 : 0);
@@ -152,7 +155,7 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
   qdd.assign(nv, S(0));
   fd_seq(s, q, qd, tau, o, qdd.data());
   std::vector<Bar<S>> b(n);
-  for (auto& x : b) bar_zero(x);
+  for (auto& x : b) bar_zero(x, pg != nullptr);
   std::vector<S> acc_q(n), acc_qd(n), qddb(n);
   V6<S> qddb6 = zero6<S>(), vb6 = zero6<S>();
   V3<S> pb = zero3<S>();
@@ -202,6 +205,12 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
       vb6 = vb6 + r1_root(s.L[i], o.t[i].v, vb[i], pAb[i]);
     }
   }
+  if (pg)
+    for (int i = 0; i < n; ++i)
+      if (s.jtype[i] != 1) {
+        r2_sbar(o.t[i], b[i]);
+        frame_bar_add((*pg)[i], s.L[i], o.t[i], b[i]);
+      }
   for (int i = 0; i < n; ++i) {
     if (s.jtype[i] != 1) {
       qb[s.qi[i]] = acc_q[i] + b[i].q;
@@ -220,7 +229,7 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
 template <typename S>
 void rollout_grad(int n, const int* parent, const int* jtype, const double* cf, const double* g, const S* q0,
                   const S* qd0, const S* tau, double dt_, int T, const S* gqT, const S* gqdT, S* gq0, S* gqd0,
-                  S* gtau, S* qT, S* qdT) {
+                  S* gtau, S* qT, S* qdT, S* gframe) {
   Sys<S> s = make_sys<S>(n, parent, jtype, cf, g);
   const S dt = (S)dt_;
   int nq = 0, nv = 0, nu = 0;
@@ -245,10 +254,20 @@ void rollout_grad(int n, const int* parent, const int* jtype, const double* cf, 
   std::copy(last, last + nq, qT);
   std::copy(last + nq, last + nq + nv, qdT);
   std::vector<S> qb(gqT, gqT + nq), qdb(gqdT, gqdT + nv);
+  std::vector<ParamBar<S>> pg(n);
+  for (auto& x : pg) param_bar_zero(x);
   for (int t = T - 1; t >= 0; --t) {
     const S* cur = xs.data() + (size_t)t * (nq + nv);
-    bwd_seq(s, cur, cur + nq, tau + (size_t)t * nu, dt, qb.data(), qdb.data(), gtau + (size_t)t * nu);
+    bwd_seq(s, cur, cur + nq, tau + (size_t)t * nu, dt, qb.data(), qdb.data(), gtau + (size_t)t * nu,
+            gframe ? &pg : nullptr);
   }
+  // placement and axis accumulators in the kernels' frames: xi (6), w (3)
+  if (gframe)
+    for (int i = 0; i < n; ++i) {
+      const ParamBar<S>& x = pg[i];
+      const S v[9] = {x.xi.a.x, x.xi.a.y, x.xi.a.z, x.xi.l.x, x.xi.l.y, x.xi.l.z, x.w.x, x.w.y, x.w.z};
+      for (int k = 0; k < 9; ++k) gframe[9 * i + k] = v[k];
+    }
   std::copy(qb.begin(), qb.end(), gq0);
   std::copy(qdb.begin(), qdb.end(), gqd0);
 }
@@ -271,12 +290,14 @@ void emu_fd_f(int n, const int* parent, const int* jtype, const double* cf, cons
 }
 void emu_rollout_grad_d(int n, const int* parent, const int* jtype, const double* cf, const double* g,
                         const double* q0, const double* qd0, const double* tau, double dt, int T, const double* gqT,
-                        const double* gqdT, double* gq0, double* gqd0, double* gtau, double* qT, double* qdT) {
-  rollout_grad<double>(n, parent, jtype, cf, g, q0, qd0, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, qT, qdT);
+                        const double* gqdT, double* gq0, double* gqd0, double* gtau, double* qT, double* qdT,
+                        double* gframe) {
+  rollout_grad<double>(n, parent, jtype, cf, g, q0, qd0, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, qT, qdT, gframe);
 }
 void emu_rollout_grad_f(int n, const int* parent, const int* jtype, const double* cf, const double* g,
                         const float* q0, const float* qd0, const float* tau, double dt, int T, const float* gqT,
-                        const float* gqdT, float* gq0, float* gqd0, float* gtau, float* qT, float* qdT) {
-  rollout_grad<float>(n, parent, jtype, cf, g, q0, qd0, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, qT, qdT);
+                        const float* gqdT, float* gq0, float* gqd0, float* gtau, float* qT, float* qdT,
+                        float* gframe) {
+  rollout_grad<float>(n, parent, jtype, cf, g, q0, qd0, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, qT, qdT, gframe);
 }
 }

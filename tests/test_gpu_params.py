@@ -1,10 +1,12 @@
-"""GPU parity of the inertial-parameter gradients (every link's mass, first
-moment and rotational inertia about the link origin, summed over the
-rollout) against the FP64 oracle, in every kernel variant: general trees
-with random frames, free-floating quadrupeds, serial chains with random
-axes (the library rotates link frames internally and must turn the
-gradient back into the caller's frames), and every adjoint schedule
-(pipelined K = 1, one-wave K = 1, segment replay K > 1, store-all K = 0).
+"""GPU parity of the model-parameter gradients against the FP64 oracle:
+every link's inertial parameters (mass, first moment, rotational inertia
+about the link origin) and every 1-dof link's placement and axis (joint-frame
+rotation, joint origin, axis along the unit sphere), summed over the
+rollout.  Every kernel variant: general trees with random frames,
+free-floating quadrupeds, serial chains with random axes (the library rotates
+link frames internally and must turn the gradients back into the caller's
+frames), and every adjoint schedule (pipelined K = 1, one-wave K = 1, segment
+replay K > 1, store-all K = 0).
 """
 import numpy as np
 import pytest
@@ -58,40 +60,45 @@ def _oracle(b):
         q0, qd0 = b.q0[qo[i]:qo[i + 1]], b.qd0[vo[i]:vo[i + 1]]
         tau = np.asarray(b.tau[:, uo[i]:uo[i + 1]], dtype=np.float64)
         qT, qdT = O.rollout(m, q0, qd0, tau, b.dt)
-        return O.rollout_grad_params(m, q0, qd0, tau, b.dt, 2 * qT, qdT)[3]
+        return O.rollout_grad_params(m, q0, qd0, tau, b.dt, 2 * qT, qdT)[3:5]
 
     return O.map_threads(one, range(len(b.systems)))
 
 
-def _compare(b, gp, ref, tol, floor):
+def _compare(b, out, ref, tol, floor):
     off = np.cumsum([0] + [s.n for s in b.systems])
-    errs = [rel(gp[off[i]:off[i + 1]], ref[i], floor) for i in range(len(b.systems))]
-    print(b.name, "parameter-gradient rel errs", ["%.1e" % e for e in errs])
-    assert max(errs) < tol, errs
+    for k, what in ((3, "inertial"), (4, "placement/axis")):
+        errs = [rel(out[k][off[i]:off[i + 1]], ref[i][k - 3], floor) for i in range(len(b.systems))]
+        print(b.name, what, "parameter-gradient rel errs", ["%.1e" % e for e in errs])
+        assert max(errs) < tol, (what, errs)
 
 
 @pytest.mark.parametrize("K", [1, 3, 0])
 @pytest.mark.parametrize("kind", ["mixed", "chains"])
 def test_param_gradients_fp64_round_off(kind, K):
     b = _batch(kind, 150, f32=False)
-    gp = _gpu(b, K, torch.float64)[3]
-    _compare(b, gp, _oracle(b), 1e-9, FLOOR_F64)
+    _compare(b, _gpu(b, K, torch.float64), _oracle(b), 1e-9, FLOOR_F64)
 
 
 @pytest.mark.parametrize("kind", ["mixed", "chains"])
 def test_param_gradients_fp32(kind):
     b = _batch(kind, 300, f32=True)
-    gp = _gpu(b, 1, torch.float32)[3]
-    _compare(b, gp, _oracle(b), TOL_GRAD_F32, 1e-6)
+    _compare(b, _gpu(b, 1, torch.float32), _oracle(b), TOL_GRAD_F32, 1e-6)
+
+
+def test_param_gradients_one_wave_fp64():
+    b = _batch("mixed", 90, f32=False)
+    _compare(b, _gpu(b, 1, torch.float64, (2, 1, 0)), _oracle(b), 1e-9, FLOOR_F64)
 
 
 def test_param_gradients_one_wave_and_pipelined_agree():
     b = _batch("mixed", 120, f32=True)
-    a = _gpu(b, 1, torch.float32, (4, 2, 1))[3]
-    c = _gpu(b, 1, torch.float32, (1, 1, 0))[3]
-    d = _gpu(b, 1, torch.float32, (2, 1, 1))[3]
-    assert rel(c, a) < 1e-5
-    assert np.array_equal(a, d)
+    for k in (3, 4):
+        a = _gpu(b, 1, torch.float32, (4, 2, 1))[k]
+        c = _gpu(b, 1, torch.float32, (1, 1, 0))[k]
+        d = _gpu(b, 1, torch.float32, (2, 1, 1))[k]
+        assert rel(c, a) < 1e-5
+        assert np.array_equal(a, d)
 
 
 def test_param_gradients_optional():
@@ -107,3 +114,10 @@ def test_param_gradients_optional():
     for x, y in zip(g1, g2[:3]):
         assert torch.equal(x, y)
     assert g2[3].shape == (sum(s.n for s in b.systems), 10)
+    assert g2[4].shape == (sum(s.n for s in b.systems), 9)
+    # a free root has no placement or axis
+    off = np.cumsum([0] + [s.n for s in b.systems])
+    gf = g2[4].cpu().numpy()
+    for i, s in enumerate(b.systems):
+        if s.jtype[0] == synth.FREE:
+            assert not np.any(gf[off[i]])

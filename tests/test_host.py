@@ -84,7 +84,7 @@ def test_null_arguments_are_rejected():
     assert L.sim_workspace_bytes(None, 10, 1, ctypes.byref(b)) == N.SIM_ERR_INVALID_ARG
     assert L.sim_forward(None, None, None, None, 1e-3, 1, 1, None, None, None, None, 0, None) == \
         N.SIM_ERR_INVALID_ARG
-    assert L.sim_backward(None, None, 1e-3, 1, 1, None, None, None, None, None, None, None, None, 0, None) == \
+    assert L.sim_backward(None, None, 1e-3, 1, 1, None, None, None, None, None, None, None, None, None, 0, None) == \
         N.SIM_ERR_INVALID_ARG
     assert L.sim_aba(None, None, None, None, None, None) == N.SIM_ERR_INVALID_ARG
     f = ctypes.c_double()
@@ -156,6 +156,31 @@ def test_lane_arithmetic_matches_oracle_fp64(which):
     b = O.rollout_grad(m, q0, qd0, tau, 1e-3, gqT, gqdT)
     for x, y in zip(a, b):
         assert rel(x, y, 1e-12) < 1e-11
+
+
+@pytest.mark.parametrize("which", ["tree", "prismatic_tree", "telescoping_quad", "chain", "cartpole"])
+def test_lane_arithmetic_frame_gradients_match_oracle_fp64(which):
+    """The kernels' per-link placement and axis adjoints (transform adjoint
+    G, motion-subspace adjoint, frame_bar_add), accumulated link by link on
+    the host in FP64 and turned into the caller's frames, reproduce the
+    oracle's dense placement and axis gradients to round-off."""
+    from helpers import emu_rollout_grad
+    if which == "tree":
+        s, q0, qd0, tau = synth.tree_system(2014, 80, random_frames=True)
+    elif which == "prismatic_tree":
+        s, q0, qd0, tau = synth.tree_system(2015, 80, random_frames=True, prismatic=0.4)
+    elif which == "telescoping_quad":
+        s, q0, qd0, tau = synth.telescoping_quadruped_system(3011, 80)
+    elif which == "chain":
+        s, q0, qd0, tau = synth.chain_system(7, 1003, 80)
+    else:
+        s, q0, qd0, tau = synth.cartpole_system(7, 80)
+    m = O.Model(s)
+    rng = np.random.default_rng(2)
+    gqT, gqdT = rng.normal(size=s.nq), rng.normal(size=s.nv)
+    got = emu_rollout_grad(s, q0, qd0, tau, 1e-3, gqT, gqdT, frame=True)[5]
+    ref = O.rollout_grad_params(m, q0, qd0, tau, 1e-3, gqT, gqdT)[4]
+    assert rel(got, ref, 1e-12) < 1e-11, (got, ref)
 
 
 def test_lane_arithmetic_fp32_forward_dynamics_error():
