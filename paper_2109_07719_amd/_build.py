@@ -20,12 +20,10 @@ HIPCC_FLAGS = [
     # keeps IEEE semantics (its input validation tests for non-finite numbers)
     "-Xarch_device", "-fno-signed-zeros", "-Xarch_device", "-ffinite-math-only",
 ]
-# Translation units and their own options.  The serial-chain kernels run one
-# wavefront per SIMD, so their schedule is built for instruction-level
-# parallelism rather than occupancy.
+# Translation units (compiled in parallel) and any options of their own.
 UNITS = [
     ("abadj_kernels.hip", []),
-    ("abadj_kernels_chain.hip", ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]),
+    ("abadj_kernels_chain.hip", []),
     ("abadj_runtime.hip", []),
 ]
 SOURCES = [os.path.join(CSRC, u) for u, _ in UNITS]

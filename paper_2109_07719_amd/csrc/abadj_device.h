@@ -3,7 +3,7 @@
 // (backward rollout with per-step recompute).  Included by the two kernel
 // translation units (abadj_kernels.hip: trees and free roots;
 // abadj_kernels_chain.hip: serial chains), which instantiate disjoint sets
-// of variants and are compiled with their own scheduling options.
+// of variants.
 //
 // Layout on the GPU:
 //   * one wavefront (64 lanes) per workgroup; several systems are packed

@@ -1,9 +1,7 @@
 // Kernel variants for batches of fixed-base serial chains of revolute
-// joints (parent/child exchange between neighbouring lanes' registers).
-// These kernels run one wavefront per SIMD on the serial per-level sweeps,
-// so their instruction latencies are exposed; the build compiles this
-// translation unit with the scheduler's instruction-level-parallelism
-// strategy.
+// joints (parent/child exchange between neighbouring lanes' registers),
+// in a translation unit of their own so that the build compiles them in
+// parallel with the other variants.
 #include "abadj_device.h"
 
 namespace aba {

@@ -102,7 +102,10 @@ def test_param_gradients_one_wave_and_pipelined_agree():
 
 
 def test_param_gradients_optional():
-    """Without the parameter output the other gradients are unchanged."""
+    """Without the parameter outputs the other gradients are the same up to
+    rounding: the two are separate kernel instantiations, and the compiler
+    may fuse multiplies and adds differently where the parameter adjoints
+    reuse an intermediate."""
     from paper_2109_07719_amd.sim import Sim
     b = _batch("mixed", 60, f32=True)
     sim = Sim(b.systems, b.gravity, dtype=torch.float32)
@@ -112,7 +115,7 @@ def test_param_gradients_optional():
     g1 = sim.backward(tau, b.dt, 1, ws, 2 * qT, qdT)
     g2 = sim.backward(tau, b.dt, 1, ws, 2 * qT, qdT, params=True)
     for x, y in zip(g1, g2[:3]):
-        assert torch.equal(x, y)
+        assert rel(x.cpu().numpy(), y.cpu().numpy()) < 1e-5
     assert g2[3].shape == (sum(s.n for s in b.systems), 10)
     assert g2[4].shape == (sum(s.n for s in b.systems), 9)
     # a free root has no placement or axis
