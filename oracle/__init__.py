@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = [os.path.join(_HERE, "aba_oracle.c")]
+SOURCES = [os.path.join(_HERE, "aba_oracle.c"), os.path.join(_HERE, "pgs_oracle.c")]
 DEPS = SOURCES + [os.path.join(_HERE, "aba_fwd.inc"), os.path.join(_HERE, "oracle.h")]
 
 
@@ -59,6 +59,13 @@ def _configure(L):
     L.orc_rollout_grad_params.restype = ctypes.c_int
     L.orc_adjoint_along_params.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P, P, P, P]
     L.orc_adjoint_along_params.restype = ctypes.c_int
+    I = ctypes.c_int
+    L.orc_pgs_solve.argtypes = [I, I, P, P, P, P, P, P, P]
+    L.orc_pgs_solve.restype = None
+    L.orc_pgs_solve_c.argtypes = [I, I, P, P, P, P, P, P]
+    L.orc_pgs_solve_c.restype = None
+    L.orc_pgs_adjoint.argtypes = [I, I, P, P, P, P, P, P, P, P, P, P, P]
+    L.orc_pgs_adjoint.restype = None
     return L
 
 
@@ -288,3 +295,47 @@ def map_threads(fn, items, threads: int | None = None):
         return [fn(x) for x in items]
     with ThreadPoolExecutor(max_workers=threads) as ex:
         return list(ex.map(fn, items))
+
+
+# ---------------------------------------------------------------- contact solver
+
+def _vec(x, n, dtype=np.float64):
+    return np.ascontiguousarray(np.asarray(x, dtype=dtype).reshape(n))
+
+
+def pgs_solve(A, b, lo, hi, x0, niter, sweeps=False):
+    """Projected Gauss-Seidel on a = A x + b, lo <= x <= hi (one problem,
+    A [n, n]).  Returns x, or (x, sweeps [niter + 1, n]) with the vector at
+    the start of every sweep and the result."""
+    n = int(np.asarray(b).size)
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64).reshape(n, n))
+    b, lo, hi, x0 = (_vec(v, n) for v in (b, lo, hi, x0))
+    x = np.zeros(n)
+    sw = np.zeros((niter + 1, n)) if sweeps else None
+    lib().orc_pgs_solve(n, int(niter), _p(A), _p(b), _p(lo), _p(hi), _p(x0), _p(x),
+                        _p(sw) if sweeps else None)
+    return (x, sw) if sweeps else x
+
+
+def pgs_solve_complex(A, b, lo, hi, x0, niter):
+    """pgs_solve in complex arithmetic (complex-step checks)."""
+    n = int(np.asarray(b).size)
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.complex128).reshape(n, n))
+    b, lo, hi, x0 = (_vec(v, n, np.complex128) for v in (b, lo, hi, x0))
+    x = np.zeros(n, np.complex128)
+    lib().orc_pgs_solve_c(n, int(niter), _p(A), _p(b), _p(lo), _p(hi), _p(x0), _p(x))
+    return x
+
+
+def pgs_adjoint(A, b, lo, hi, sweeps, xbar):
+    """Reverse of pgs_solve from its stored sweeps: returns A_bar [n, n],
+    b_bar, lo_bar, hi_bar, x0_bar."""
+    n = int(np.asarray(b).size)
+    niter = int(np.asarray(sweeps).shape[0]) - 1
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64).reshape(n, n))
+    b, lo, hi, xbar = (_vec(v, n) for v in (b, lo, hi, xbar))
+    sw = np.ascontiguousarray(np.asarray(sweeps, dtype=np.float64).reshape(niter + 1, n))
+    Ab, bb, lb, hb, x0b = np.zeros((n, n)), np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
+    lib().orc_pgs_adjoint(n, niter, _p(A), _p(b), _p(lo), _p(hi), _p(sw), _p(xbar), _p(Ab), _p(bb), _p(lb),
+                          _p(hb), _p(x0b))
+    return Ab, bb, lb, hb, x0b

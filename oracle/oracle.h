@@ -142,6 +142,22 @@ int orc_adjoint_along_params(const orc_model *m, const double *states, const dou
                              const double *gtraj, double *gq0, double *gqd0, double *gtau,
                              double *gparam, double *gframe);
 
+/* ---- contact solver (pgs_oracle.c) ---------------------------------
+ * Projected Gauss-Seidel on the MLCP a = A x + b, lo <= x <= hi (Sec. 4.1,
+ * Eq. mlcp; App. C), n rows, niter sweeps from x0; A is [n][n] row-major.
+ * sweeps (nullable) [niter + 1][n] receives x at the start of every sweep
+ * and the result.  orc_pgs_adjoint reverses the solve from those stored
+ * vectors: given x_bar it returns A_bar [n][n], b_bar, lo_bar, hi_bar and
+ * x0_bar [n] (overwritten).  orc_pgs_solve_c: the solve in complex
+ * arithmetic (inputs and output double complex), for complex-step checks. */
+void orc_pgs_solve(int n, int niter, const double *A, const double *b, const double *lo,
+                   const double *hi, const double *x0, double *x, double *sweeps);
+void orc_pgs_solve_c(int n, int niter, const void *A, const void *b, const void *lo,
+                     const void *hi, const void *x0, void *x);
+void orc_pgs_adjoint(int n, int niter, const double *A, const double *b, const double *lo,
+                     const double *hi, const double *sweeps, const double *xbar, double *Abar,
+                     double *bbar, double *lobar, double *hibar, double *x0bar);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,6 +12,7 @@ import subprocess
 import pytest
 
 import oracle as O
+import test_oracle_pgs as pgs
 import test_oracle_pins as pins
 
 SRC = os.path.dirname(os.path.abspath(O.__file__))
@@ -60,6 +61,15 @@ MUTATIONS = [
      "dropped translation term of the frame-rotation derivative"),
     ("aba_oracle.c", "      for (int c = 0; c < 6; ++c) b->S[c] += l->IA[6 * r + c] * b->U[r];",
      "      for (int c = 0; c < 6; ++c) b->S[c] += 0.0;", "dropped U = IA S term of the motion-subspace adjoint"),
+    ("pgs_oracle.c", "        if (j != i) d += A[(size_t)i * n + j] * x[j];\n      const double y = -(b[i] + d)",
+     "        if (j != i) d += A[(size_t)i * n + i] * x[j];\n      const double y = -(b[i] + d)",
+     "PGS row sum with the diagonal entry (as the printed listing reads)"),
+    ("pgs_oracle.c", "      if (st < 0) lobar[i] += xb[i];\n      else if (st > 0) hibar[i] += xb[i];",
+     "      if (st < 0) hibar[i] += xb[i];\n      else if (st > 0) lobar[i] += xb[i];", "PGS bound adjoints swapped"),
+    ("pgs_oracle.c", "      xb[i] = 0;\n", "", "PGS adjoint keeps the overwritten row's adjoint"),
+    ("pgs_oracle.c", "for (int j = 0; j < n; ++j) cur[j] = (j < i) ? xe[j] : xs[j];",
+     "for (int j = 0; j < n; ++j) cur[j] = (j > i) ? xe[j] : xs[j];", "PGS adjoint with old and new values swapped"),
+    ("pgs_oracle.c", "Abar[(size_t)i * n + i] += db * y;", "Abar[(size_t)i * n + i] -= db * y;", "PGS diagonal adjoint sign"),
 ]
 
 PINS = [
@@ -80,12 +90,17 @@ PINS = [
     pins.test_rollout_gradient_complex_step_with_prismatic_joints,
     pins.test_frame_gradient_invariances_of_a_fixed_base_tree,
     lambda: pins.test_frame_and_axis_gradients_central_differences(0),
+    pgs.test_unbounded_converges_to_the_linear_solve,
+    pgs.test_one_sweep_by_hand,
+    lambda: pgs.test_adjoint_against_complex_step(3, 12),
+    lambda: pgs.test_adjoint_against_complex_step(9, 2),
+    pgs.test_adjoint_of_the_converged_linear_solve,
 ]
 
 
 @pytest.mark.parametrize("fname,old,new,what", MUTATIONS, ids=[m[3] for m in MUTATIONS])
 def test_pins_catch_planted_mistake(tmp_path, fname, old, new, what):
-    for f in ("aba_oracle.c", "aba_fwd.inc", "oracle.h"):
+    for f in ("aba_oracle.c", "aba_fwd.inc", "oracle.h", "pgs_oracle.c"):
         shutil.copy(os.path.join(SRC, f), tmp_path / f)
     path = tmp_path / fname
     text = path.read_text()
@@ -93,7 +108,7 @@ def test_pins_catch_planted_mistake(tmp_path, fname, old, new, what):
     path.write_text(text.replace(old, new))
     so = tmp_path / "libmutant.so"
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", str(so),
-                           str(tmp_path / "aba_oracle.c"), "-lm"])
+                           str(tmp_path / "aba_oracle.c"), str(tmp_path / "pgs_oracle.c"), "-lm"])
     caught = None
     with O.use_library(str(so)):
         for pin in PINS:
