@@ -309,6 +309,47 @@ int sim_flops(sim_t h, int kind, double *flops_per_step);
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *sim_last_error(void);
 
+/* ---- contact solver ------------------------------------------------------
+ * Projected Gauss-Seidel (PGS) on a batch of independent mixed linear
+ * complementarity problems, and its adjoint (Sec. 4.1 "Collision
+ * resolution", Eq. mlcp; App. C).  Problem p: find x with
+ *   a = A x + b,  lo <= x <= hi,
+ *   a_i >= 0 where x_i = lo_i, a_i <= 0 where x_i = hi_i, a_i = 0 between
+ * (lo = 0, hi = +inf gives 0 <= a perp x >= 0).  The solve runs exactly
+ * niter sweeps from x0; a sweep sets the rows in order,
+ *   y_i = -(b_i + sum_{j != i} A_ij x_j) / A_ii,  x_i = min(max(y_i, lo_i), hi_i)
+ * (the bounds are fixed inputs and must be finite: an unbounded side takes
+ * a large finite value such as +-FLT_MAX; A_ii must be nonzero).
+ * Arrays are DEVICE pointers of the dtype (SIM_F32 or SIM_F64), caller-owned:
+ * A [batch][n][n] row-major, b, lo, hi, x0, x [batch][n]; 1 <= n <=
+ * SIM_PGS_MAX_ROWS.  Calls only enqueue work on `stream` (NULL = default):
+ * no allocation, no synchronisation.  Errors: SIM_ERR_INVALID_ARG (sizes,
+ * null arrays), SIM_ERR_UNSUPPORTED_DTYPE, SIM_ERR_WORKSPACE_TOO_SMALL,
+ * SIM_ERR_HIP; sim_last_error() describes the failure. */
+#define SIM_PGS_MAX_ROWS 16
+
+/* Bytes of the workspace that keeps x at the start of every sweep (and the
+ * result) for the adjoint: (niter + 1) * n * batch * sizeof(dtype). */
+int sim_pgs_workspace_bytes(int dtype, int batch, int n, int niter, size_t *bytes);
+
+/* Solve.  workspace (nullable): when given (workspace_bytes at least
+ * sim_pgs_workspace_bytes), the sweep vectors are stored there for
+ * sim_pgs_adjoint. */
+int sim_pgs_solve(int dtype, int batch, int n, int niter, const void *A, const void *b,
+                  const void *lo, const void *hi, const void *x0, void *x, void *workspace,
+                  size_t workspace_bytes, void *stream);
+
+/* Adjoint of sim_pgs_solve, from the workspace of that solve (same A, b,
+ * lo, hi, batch, n, niter): given xbar = dL/dx [batch][n], writes
+ * Abar [batch][n][n], bbar, lobar, hibar and x0bar [batch][n] (overwritten).
+ * The sweeps are reversed row by row: a clamped row sends its adjoint to
+ * the active bound (a value exactly on a bound counts as inside), a free
+ * row to b, A and the other rows' values it was computed from. */
+int sim_pgs_adjoint(int dtype, int batch, int n, int niter, const void *A, const void *b,
+                    const void *lo, const void *hi, const void *xbar, const void *workspace,
+                    size_t workspace_bytes, void *Abar, void *bbar, void *lobar, void *hibar,
+                    void *x0bar, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

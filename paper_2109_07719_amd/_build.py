@@ -25,6 +25,7 @@ UNITS = [
     ("abadj_kernels.hip", []),
     ("abadj_kernels_chain.hip", []),
     ("abadj_runtime.hip", []),
+    ("pgs.hip", []),
 ]
 SOURCES = [os.path.join(CSRC, u) for u, _ in UNITS]
 

@@ -27,7 +27,9 @@ SIM_MAX_LINKS = 64
 EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_status", "sim_get_tiling", "sim_set_tiling", "sim_autotune",
             "sim_workspace_bytes",
             "sim_checkpoint_schedule", "sim_forward", "sim_forward_jvp",
-            "sim_backward", "sim_aba", "sim_flops", "sim_last_error")
+            "sim_backward", "sim_aba", "sim_flops", "sim_last_error",
+            "sim_pgs_workspace_bytes", "sim_pgs_solve", "sim_pgs_adjoint")
+SIM_PGS_MAX_ROWS = 16
 
 
 class SimTopology(ctypes.Structure):
@@ -90,6 +92,12 @@ def lib():
         L.sim_forward.restype = I
         L.sim_backward.argtypes = [P, P, D, I, I, P, P, P, P, P, P, P, P, P, Z, P]
         L.sim_backward.restype = I
+        L.sim_pgs_workspace_bytes.argtypes = [I, I, I, I, ctypes.POINTER(Z)]
+        L.sim_pgs_workspace_bytes.restype = I
+        L.sim_pgs_solve.argtypes = [I, I, I, I, P, P, P, P, P, P, P, Z, P]
+        L.sim_pgs_solve.restype = I
+        L.sim_pgs_adjoint.argtypes = [I, I, I, I, P, P, P, P, P, P, Z, P, P, P, P, P, P]
+        L.sim_pgs_adjoint.restype = I
         L.sim_checkpoint_schedule.argtypes = [I, I, P, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_longlong)]
         L.sim_checkpoint_schedule.restype = I
         L.sim_forward_jvp.argtypes = [P, P, P, P, P, P, P, D, I, P, P, P, P, P, P, P]

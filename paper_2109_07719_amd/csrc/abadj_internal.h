@@ -1,6 +1,8 @@
 // Internal launch interface between the host runtime and the kernels.
 #pragma once
 
+#include <string>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -149,6 +151,11 @@ struct Tiling {
 // E_T, every joint revolute; kFrPrismatic: any E_T, and prismatic joints
 // among the revolute ones (the joint type becomes a per-lane value).
 enum : int { kFrIdentity = 0, kFrGeneral = 1, kFrPrismatic = 2 };
+
+// The library's error channel (sim_last_error; abadj_runtime.hip): sets the
+// thread's message and returns code / clears it.
+int report_error(int code, const std::string& msg);
+void clear_error();
 
 // Launchers: pick the kernel variant for the handle's shape and launch it on
 // `stream` (abadj_kernels.hip).  The serial-chain variants live in their own

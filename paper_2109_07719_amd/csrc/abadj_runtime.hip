@@ -25,6 +25,16 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+namespace aba {
+// the library's one error channel (sim_last_error), for the other units
+int report_error(int code, const std::string& msg) { return fail(code, msg); }
+void clear_error() { g_err.clear(); }
+}  // namespace aba
+
+namespace {
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr int kMaxSnapshots = 4096;
 

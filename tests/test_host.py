@@ -96,6 +96,17 @@ def test_null_arguments_are_rejected():
     assert L.sim_set_tiling(None, ctypes.byref(t)) == N.SIM_ERR_INVALID_ARG
     assert L.sim_autotune(None, 1, 10, None, None, None) == N.SIM_ERR_INVALID_ARG
     L.sim_destroy(None)
+    # contact solver: sizes and null arrays are rejected before any launch
+    z = ctypes.c_size_t()
+    assert L.sim_pgs_workspace_bytes(0, 4, 3, 10, None) == N.SIM_ERR_INVALID_ARG
+    assert L.sim_pgs_workspace_bytes(0, 4, 17, 10, ctypes.byref(z)) == N.SIM_ERR_INVALID_ARG
+    assert L.sim_pgs_workspace_bytes(0, 4, 0, 10, ctypes.byref(z)) == N.SIM_ERR_INVALID_ARG
+    assert L.sim_pgs_workspace_bytes(7, 4, 3, 10, ctypes.byref(z)) == N.SIM_ERR_UNSUPPORTED_DTYPE
+    assert L.sim_pgs_workspace_bytes(1, 4, 3, 10, ctypes.byref(z)) == N.SIM_OK and z.value == 11 * 3 * 4 * 8
+    assert L.sim_pgs_solve(0, 4, 3, 10, None, None, None, None, None, None, None, 0, None) == N.SIM_ERR_INVALID_ARG
+    assert L.sim_pgs_solve(0, 4, 17, 10, None, None, None, None, None, None, None, 0, None) == N.SIM_ERR_INVALID_ARG
+    assert L.sim_pgs_adjoint(0, 4, 3, 10, *([None] * 6), 0, *([None] * 6)) == N.SIM_ERR_INVALID_ARG
+    assert b"sim_pgs_adjoint" in L.sim_last_error()
 
 
 # ---------------------------------------------------------------- generators
