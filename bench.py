@@ -308,6 +308,105 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-6))
 
 
+def pgs_bench(args, torch, dev):
+    """Contact solver (Sec. 4.1 "Collision resolution", Eq. mlcp; App. C):
+    a batch of independent MLCPs a = A x + b, lo <= x <= hi solved by a fixed
+    number of projected Gauss-Seidel sweeps, and the adjoint sweep.  Inputs:
+    Delassus-like A = Q diag(1..8) Q^T plus a small non-symmetric part,
+    b ~ N(0, 1.5^2), box half-widths U(0.05, 0.6) (30 % of rows one-sided,
+    lo = 0), x0 ~ N(0, 0.3^2), FP32.  Times the solve (keeping the sweep
+    vectors) and the adjoint as graph replays with HIP events; checks 64
+    problems against the FP64 oracle; times the oracle on the host."""
+    import oracle as O
+    from paper_2109_07719_amd import pgs
+
+    B, n, niter = (int(v) for v in args.pgs.split(","))
+    rng = np.random.default_rng(21)
+    nb = min(B, 1024)   # distinct problems, tiled through the batch
+    A = np.empty((nb, n, n))
+    for p in range(nb):
+        Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+        A[p] = Q @ np.diag(np.linspace(1.0, 8.0, n)) @ Q.T + 0.2 * rng.normal(size=(n, n))
+        A[p][np.diag_indices(n)] = np.abs(A[p][np.diag_indices(n)]) + 1.0
+    half = rng.uniform(0.05, 0.6, (nb, n))
+    lo, hi = -half, half.copy()
+    one = rng.uniform(size=(nb, n)) < 0.3
+    lo[one], hi[one] = 0.0, 3e38
+    b, x0 = rng.normal(0, 1.5, (nb, n)), rng.normal(0, 0.3, (nb, n))
+    idx = np.arange(B) % nb
+    r32 = lambda x: x.astype(np.float32).astype(np.float64)
+    A, b, lo, hi, x0 = (r32(v[idx]) for v in (A, b, lo, hi, x0))
+    xbar = r32(rng.normal(size=(B, n)))
+    f = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
+    tA, tb, tlo, thi, tx0, txb = f(A), f(b), f(lo), f(hi), f(x0), f(xbar)
+    ws = pgs.new_workspace(B, n, niter)
+    x = torch.empty_like(tb)
+    gout = tuple(torch.empty_like(t) for t in (tA, tb, tb, tb, tb))
+    solve = lambda: pgs.solve(tA, tb, tlo, thi, tx0, niter, workspace=ws, out=x)
+    adj = lambda: pgs.adjoint(tA, tb, tlo, thi, txb, niter, ws, out=gout)
+    solve(), adj()
+    torch.cuda.synchronize()
+    graphs = {}
+    for k, fn in (("solve", solve), ("adjoint", adj)):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        graphs[k] = g
+    ms = {}
+    for k, g in graphs.items():
+        for _ in range(max(args.warmup, 2)):
+            g.replay()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for e0, e1 in evs:
+            e0.record()
+            g.replay()
+            e1.record()
+        torch.cuda.synchronize()
+        ms[k] = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+    # algorithmic work per problem (FP32): a row update is the (n-1)-term
+    # dot product, the add of b and the division; the adjoint row recomputes
+    # it and adds the b, A and x adjoints
+    fl_solve = niter * n * (2 * (n - 1) + 2)
+    fl_adj = niter * n * (6 * (n - 1) + 7)
+    by_solve = 4 * (n * n + 4 * n + n + (niter + 1) * n)
+    by_adj = 4 * (n * n + 4 * n + 2 * niter * n + n * n + 4 * n)
+    gx, gg = x.cpu().numpy(), [t.cpu().numpy() for t in gout]
+    errs = []
+    for p in rng.choice(B, 64, replace=False):
+        xr, sw = O.pgs_solve(A[p], b[p], lo[p], hi[p], x0[p], niter, sweeps=True)
+        gr = O.pgs_adjoint(A[p], b[p], lo[p], hi[p], sw, xbar[p])
+        errs.append(max(_rel(gx[p], xr), max(_rel(gg[k][p], gr[k]) for k in range(5))))
+    # the FP64 oracle on the host, one thread, solve + adjoint per problem
+    t0, k = time.perf_counter(), 0
+    while time.perf_counter() - t0 < min(args.cpu_sample_seconds, 5.0):
+        p = k % nb
+        xr, sw = O.pgs_solve(A[p], b[p], lo[p], hi[p], x0[p], niter, sweeps=True)
+        O.pgs_adjoint(A[p], b[p], lo[p], hi[p], sw, xbar[p])
+        k += 1
+    cpu_rate = k / (time.perf_counter() - t0)
+    total = ms["solve"] + ms["adjoint"]
+    res = {"metric": "MLCP solve+adjoint problems/s (projected Gauss-Seidel, FP32, 1 GPU)",
+           "value": B / (total * 1e-3), "unit": "problems/s", "higher_is_better": True,
+           "ms_per_step": total, "steps": args.steps, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{B} MLCPs of {n} rows (Delassus-like A, box and one-sided bounds), "
+                                  f"{niter} sweeps, solve keeping the sweep vectors + adjoint",
+                      "batch": B, "rows": n, "sweeps": niter, "lanes_per_problem": 1},
+           "solve_ms": ms["solve"], "adjoint_ms": ms["adjoint"],
+           "roofline": {"bound": "alu", "unit": "TFLOP/s", "peak": FP32_PEAK_TFLOPS,
+                        "solve_achieved": fl_solve * B / (ms["solve"] * 1e-3) / 1e12,
+                        "adjoint_achieved": fl_adj * B / (ms["adjoint"] * 1e-3) / 1e12,
+                        "solve_hbm_gb_per_s": by_solve * B / (ms["solve"] * 1e-3) / 1e9,
+                        "adjoint_hbm_gb_per_s": by_adj * B / (ms["adjoint"] * 1e-3) / 1e9,
+                        "flops_per_problem": {"solve": fl_solve, "adjoint": fl_adj},
+                        "bytes_per_problem": {"solve": by_solve, "adjoint": by_adj}},
+           "fp64_oracle_rel_err_64_problems": {"max": max(errs), "median": float(np.median(errs))},
+           "cpu_baseline": {"value": cpu_rate, "unit": "problems/s", "cores": 1, "kind": "oracle",
+                            "sample": f"{k} problems, FP64 C oracle solve + adjoint, one thread"}}
+    res["roofline"]["frac"] = res["roofline"]["adjoint_achieved"] / FP32_PEAK_TFLOPS
+    print(json.dumps(res))
+
+
 def trajopt_bench(args, torch, dev):
     """Trajectory optimisation: 2048 chains of 5-50 links, T=1000, Adam on
     tau; reports DOF-steps/s per iteration (forward+adjoint of every chain),
@@ -398,6 +497,8 @@ def main():
                     help="run this many Adam iterations of trajectory optimisation (chains_2048 workload)")
     ap.add_argument("--rl", type=int, default=0,
                     help="one-step JVP/VJP throughput for RL on this many quadruped samples (Sec. 5)")
+    ap.add_argument("--pgs", default="",
+                    help="B,n,niter: time the contact solver (MLCP projected Gauss-Seidel) and its adjoint instead")
     ap.add_argument("--T", type=int, default=None, help="override the horizon (reduced runs only)")
     ap.add_argument("--tiling", default="auto",
                     help="launch geometry: 'auto' (the library's autotuner, before the timed region), 'default' "
@@ -434,6 +535,8 @@ def main():
         return trajopt_bench(args, torch, dev)
     if args.rl:
         return rl_bench(args, torch, dev)
+    if args.pgs:
+        return pgs_bench(args, torch, dev)
 
     t_gen = time.perf_counter()
     b = synth.workload(args.workload, T=args.T, tau_dtype=np.float32)
