@@ -104,7 +104,7 @@ class _CModel(ctypes.Structure):
                 ("E_T", ctypes.c_void_p), ("r_T", ctypes.c_void_p),
                 ("axis", ctypes.c_void_p), ("mass", ctypes.c_void_p),
                 ("com", ctypes.c_void_p), ("Ic", ctypes.c_void_p),
-                ("gravity", ctypes.c_void_p)]
+                ("gravity", ctypes.c_void_p), ("limits", ctypes.c_void_p)]
 
 
 def _p(a):
@@ -127,9 +127,13 @@ class Model:
         self.com = f(system.com).reshape(-1)
         self.Ic = f(system.Ic).reshape(-1)
         self.gravity = f(gravity).reshape(3)
+        # optional joint limits [n, 4]: lo, hi, stiffness, damping
+        lim = getattr(system, "limits", None)
+        self.limits = None if lim is None else f(lim).reshape(-1)
         self.c = _CModel(int(self.parent.shape[0]), _p(self.parent), _p(self.jtype),
                          _p(self.E_T), _p(self.r_T), _p(self.axis), _p(self.mass),
-                         _p(self.com), _p(self.Ic), _p(self.gravity))
+                         _p(self.com), _p(self.Ic), _p(self.gravity),
+                         _p(self.limits) if self.limits is not None else None)
         self.ref = ctypes.byref(self.c)
         L = lib()
         self.nq, self.nv, self.nu = L.orc_nq(self.ref), L.orc_nv(self.ref), L.orc_nu(self.ref)

@@ -43,25 +43,30 @@ int orc_nu(const orc_model *m) {
 #define SSIN sin
 #define SCOS cos
 #define SSQRT sqrt
+#define SREAL(x) (x)
 #include "aba_fwd.inc"
 #undef S
 #undef FN
 #undef SSIN
 #undef SCOS
 #undef SSQRT
+#undef SREAL
 
-/* complex instantiation (analytic continuation; no abs, no comparisons) */
+/* complex instantiation (analytic continuation; no abs; the joint-limit
+   switch decides on real parts) */
 #define S double complex
 #define FN(name) CAT(name, _c)
 #define SSIN csin
 #define SCOS ccos
 #define SSQRT csqrt
+#define SREAL(x) creal(x)
 #include "aba_fwd.inc"
 #undef S
 #undef FN
 #undef SSIN
 #undef SCOS
 #undef SSQRT
+#undef SREAL
 
 typedef link_tape_r tape_t;
 
@@ -175,6 +180,23 @@ static void inertia_params_add(const double *Ibar, double *pbar) {
   pbar[7] += Ibar[1] + Ibar[6];
   pbar[8] += Ibar[2] + Ibar[12];
   pbar[9] += Ibar[8] + Ibar[13];
+}
+
+/* Partial derivatives of the joint-limit torque (see limit_torque in
+ * aba_fwd.inc) with respect to q and qd; returns whether a limit is
+ * active. */
+static int limit_slopes(const orc_model *m, int i, double q, double qd, double *dq, double *dqd) {
+  (void)qd;
+  *dq = 0;
+  *dqd = 0;
+  if (!m->limits || m->jtype[i] == ORC_FREE) return 0;
+  const double *L = m->limits + 4 * i;
+  if (q > L[1] || q < L[0]) {
+    *dq = -L[2];
+    *dqd = -L[3];
+    return 1;
+  }
+  return 0;
 }
 
 /* Adjoint of one 1-dof link's placement and axis, ADDED into fb[9], from
@@ -369,8 +391,15 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
         }
       b->D += UIU / (l->D * l->D);
     }
-    /* u = tau - S^T pA */
+    /* u = tau + tau_limit(q, qd) - S^T pA */
     tau_bar[ui[i]] += b->u;
+    {
+      double dq, dqd;
+      if (limit_slopes(m, i, q[qi[i]], qd[vi[i]], &dq, &dqd)) {
+        q_bar[qi[i]] += dq * b->u;
+        qd_bar[vi[i]] += dqd * b->u;
+      }
+    }
     for (int k = 0; k < 6; ++k) b->pA[k] -= Sv[k] * b->u;
     for (int k = 0; k < 6; ++k) b->S[k] -= b->u * l->pA[k];
     /* D = S^T U */

@@ -60,6 +60,12 @@ typedef struct {
   const double *com;     /* 3n: centre of mass in the link frame            */
   const double *Ic;      /* 6n: inertia about the COM: xx yy zz xy xz yz    */
   const double *gravity; /* 3                                               */
+  const double *limits;  /* nullable [n][4]: joint limits lo, hi and the
+                            stiffness k and damping d of the one-sided
+                            spring-damper that acts outside [lo, hi]:
+                            tau_l = -k (q - hi) - d qd above hi,
+                            -k (q - lo) - d qd below lo, added to the
+                            joint's control (1-dof joints only)           */
 } orc_model;
 
 #ifdef __cplusplus

@@ -47,6 +47,9 @@ class System:
     mass: np.ndarray
     com: np.ndarray
     Ic: np.ndarray
+    # optional joint limits [n, 4]: lo, hi, stiffness k, damping d of the
+    # one-sided spring-damper that acts outside [lo, hi] (1-dof joints)
+    limits: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -296,6 +299,26 @@ def prismatic_chain_system(n: int, seed: int, T: int):
     return replace(sys_, jtype=jtype, axis=axis), q0, qd0, tau
 
 
+def with_joint_limits(draw, seed: int, half_range=(0.05, 0.3), k=(100.0, 400.0), d=(0.5, 3.0)):
+    """The same (system, q0, qd0, tau) with limits on every 1-dof joint: a
+    range [q0_i - w_i, q0_i + w_i] around its start, w ~ U(half_range),
+    stiffness k ~ U(k), damping d ~ U(d) (drawn from seed), so that
+    rollouts under gravity and the random torques run into them."""
+    s, q0, qd0, tau = draw
+    rng = np.random.default_rng(seed)
+    lim = np.zeros((s.n, 4))
+    qi = 0
+    for i in range(s.n):
+        if s.jtype[i] == FREE:
+            lim[i] = [-1e30, 1e30, 0.0, 0.0]
+            qi += 7
+            continue
+        w = rng.uniform(*half_range)
+        lim[i] = [q0[qi] - w, q0[qi] + w, rng.uniform(*k), rng.uniform(*d)]
+        qi += 1
+    return replace(s, limits=lim), q0, qd0, tau
+
+
 # --------------------------------------------------------------------------
 # batches
 # --------------------------------------------------------------------------
@@ -320,7 +343,8 @@ def round_to_f32(b: Batch) -> Batch:
     def r(x):
         return np.asarray(x, dtype=np.float32).astype(np.float64)
     systems = [System(parent=s.parent, jtype=s.jtype, E_T=r(s.E_T), r_T=r(s.r_T),
-                      axis=r(s.axis), mass=r(s.mass), com=r(s.com), Ic=r(s.Ic))
+                      axis=r(s.axis), mass=r(s.mass), com=r(s.com), Ic=r(s.Ic),
+                      limits=None if s.limits is None else r(s.limits))
                for s in b.systems]
     return Batch(systems=systems, q0=r(b.q0), qd0=r(b.qd0), tau=r(b.tau), dt=b.dt,
                  gravity=r(b.gravity), name=b.name)

@@ -70,6 +70,10 @@ MUTATIONS = [
     ("pgs_oracle.c", "for (int j = 0; j < n; ++j) cur[j] = (j < i) ? xe[j] : xs[j];",
      "for (int j = 0; j < n; ++j) cur[j] = (j > i) ? xe[j] : xs[j];", "PGS adjoint with old and new values swapped"),
     ("pgs_oracle.c", "Abar[(size_t)i * n + i] += db * y;", "Abar[(size_t)i * n + i] -= db * y;", "PGS diagonal adjoint sign"),
+    ("aba_oracle.c", "    *dq = -L[2];", "    *dq = L[2];", "joint-limit stiffness adjoint sign"),
+    ("aba_oracle.c", "    *dqd = -L[3];", "    *dqd = 0;", "dropped joint-limit damping adjoint"),
+    ("aba_fwd.inc", "if (SREAL(q) < L[0]) return -L[2] * (q - L[0]) - L[3] * qd;",
+     "if (SREAL(q) < L[0]) return -L[2] * (q - L[1]) - L[3] * qd;", "lower joint limit measured from the upper one"),
 ]
 
 PINS = [
@@ -90,6 +94,8 @@ PINS = [
     pins.test_rollout_gradient_complex_step_with_prismatic_joints,
     pins.test_frame_gradient_invariances_of_a_fixed_base_tree,
     lambda: pins.test_frame_and_axis_gradients_central_differences(0),
+    pins.test_joint_limit_torque_is_added_to_the_control,
+    pins.test_rollout_gradient_with_joint_limits_complex_step,
     pgs.test_unbounded_converges_to_the_linear_solve,
     pgs.test_one_sweep_by_hand,
     lambda: pgs.test_adjoint_against_complex_step(3, 12),

@@ -710,3 +710,85 @@ def test_frame_gradients_checkpointing_and_along():
     _, _, traj = O.rollout(m, q0, qd0, tau, 1e-3, traj=True)
     states = np.concatenate([np.r_[q0, qd0][None], traj[:-1]])
     assert np.array_equal(O.adjoint_along_params(m, states, tau, 1e-3, 2 * qT, qdT)[4], ref)
+
+
+# ------------------------------------------------------------- joint limits
+
+def test_joint_limit_torque_is_added_to_the_control():
+    """By definition the limit acts as an extra joint torque: forward dynamics
+    with limits equals forward dynamics without them under tau + tau_limit,
+    with tau_limit = -k (q - hi) - d qd above hi, -k (q - lo) - d qd below
+    lo and 0 inside, on a tree with random frames and prismatic joints and a
+    free-floating quadruped."""
+    rng = np.random.default_rng(30)
+    for draw in (synth.tree_system(2016, 1, nmax=12, random_frames=True, prismatic=0.4),
+                 synth.quadruped_system(3012, 1)):
+        s, q0, qd0, _ = synth.with_joint_limits(draw, 31)
+        free = s.jtype == synth.FREE
+        plain = synth.System(parent=s.parent, jtype=s.jtype, E_T=s.E_T, r_T=s.r_T, axis=s.axis, mass=s.mass,
+                             com=s.com, Ic=s.Ic)
+        ml, mp = O.Model(s), O.Model(plain)
+        qo = np.cumsum([0] + [7 if f else 1 for f in free])
+        vo = np.cumsum([0] + [6 if f else 1 for f in free])
+        for _ in range(10):
+            q = q0 + rng.normal(0, 0.4, q0.size)
+            if free[0]:
+                q[3:7] = [0, 0, 0, 1]
+            qd, tau = rng.normal(0, 1, s.nv), rng.normal(0, 1, s.nu)
+            tl = np.zeros(s.nu)
+            u = 0
+            active = 0
+            for i in range(s.n):
+                if free[i]:
+                    continue
+                lo, hi, k, d = s.limits[i]
+                qq, vv = q[qo[i]], qd[vo[i]]
+                if qq > hi:
+                    tl[u] = -k * (qq - hi) - d * vv
+                elif qq < lo:
+                    tl[u] = -k * (qq - lo) - d * vv
+                active += qq > hi or qq < lo
+                u += 1
+            assert active > 0
+            assert _rel(O.fd(ml, q, qd, tau), O.fd(mp, q, qd, tau + tl)) < 1e-13
+
+
+def test_rollout_gradient_with_joint_limits_complex_step():
+    """The adjoint of the limit torque (q_bar += -k u_bar, qd_bar += -d u_bar
+    where a limit is active) against complex-step derivatives of rollouts
+    that run into the limits, on a chain and a tree with prismatic joints."""
+    for draw, dt in ((synth.chain_system(5, 14, 300), 1e-3),
+                     (synth.tree_system(2017, 200, nmax=10, random_frames=True, prismatic=0.3), 1e-3)):
+        s, q0, qd0, tau = synth.with_joint_limits(draw, 32)
+        m = O.Model(s)
+        _, _, traj = O.rollout(m, q0, qd0, tau, dt, traj=True)
+        lo, hi = s.limits[:, 0], s.limits[:, 1]
+        hits = np.sum((traj[:, :s.n] > hi) | (traj[:, :s.n] < lo))
+        assert hits > 20, hits
+        qT, qdT = O.rollout(m, q0, qd0, tau, dt)
+        gq0, gqd0, gtau, _, _ = O.rollout_grad(m, q0, qd0, tau, dt, 2 * qT, qdT)
+        h = 1e-30
+
+        def L(a, b_, t):
+            cq, cqd = O.rollout_complex(m, a, b_, t, dt)
+            return np.sum(cq ** 2) + 0.5 * np.sum(cqd ** 2)
+
+        for j in range(s.n):
+            e = np.zeros(s.n, complex)
+            e[j] = 1j * h
+            assert abs(L(q0 + e, qd0.astype(complex), tau.astype(complex)).imag / h - gq0[j]) < 1e-9 * max(1, abs(gq0[j]))
+            assert abs(L(q0.astype(complex), qd0 + e, tau.astype(complex)).imag / h - gqd0[j]) < 1e-9 * max(1, abs(gqd0[j]))
+        for t in (0, len(tau) // 3, len(tau) - 1):
+            t0 = np.zeros_like(tau, dtype=complex)
+            t0[t, s.n // 2] = 1j * h
+            ref = L(q0.astype(complex), qd0.astype(complex), tau + t0).imag / h
+            assert abs(ref - gtau[t, s.n // 2]) < 1e-9 * max(1, np.abs(gtau).max())
+
+
+def test_joint_limits_inside_the_range_change_nothing():
+    s, q0, qd0, tau = synth.with_joint_limits(synth.chain_system(4, 15, 30), 33, half_range=(50.0, 60.0))
+    plain = synth.System(parent=s.parent, jtype=s.jtype, E_T=s.E_T, r_T=s.r_T, axis=s.axis, mass=s.mass,
+                         com=s.com, Ic=s.Ic)
+    a = O.rollout(O.Model(s), q0, qd0, tau, 1e-3)
+    b = O.rollout(O.Model(plain), q0, qd0, tau, 1e-3)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
