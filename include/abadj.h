@@ -105,6 +105,15 @@ typedef struct {
   const double *Ic;       /* [6 n_links] inertia about the COM:
                              xx yy zz xy xz yz                              */
   const double *gravity;  /* [3] e.g. (0, -9.81, 0)                         */
+  const double *limits;   /* nullable [4 n_links]: joint limits (lo, hi, k, d)
+                             per link; outside [lo, hi] a one-sided spring
+                             and damper adds tau_l = -k (q - hi) - d qd
+                             (above hi) or -k (q - lo) - d qd (below lo) to
+                             the joint's control; ignored for a free root.
+                             Finite, lo <= hi, k >= 0, d >= 0; an unlimited
+                             joint takes lo, hi = -+1e30 (or k = d = 0).
+                             The paper names joint limits without a model
+                             (Sec. 2); this is the model used.            */
 } sim_params;
 
 typedef struct {

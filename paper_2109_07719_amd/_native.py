@@ -40,7 +40,7 @@ class SimTopology(ctypes.Structure):
 class SimParams(ctypes.Structure):
     _fields_ = [("E_T", ctypes.c_void_p), ("r_T", ctypes.c_void_p), ("axis", ctypes.c_void_p),
                 ("mass", ctypes.c_void_p), ("com", ctypes.c_void_p), ("Ic", ctypes.c_void_p),
-                ("gravity", ctypes.c_void_p)]
+                ("gravity", ctypes.c_void_p), ("limits", ctypes.c_void_p)]
 
 
 class SimInfo(ctypes.Structure):

@@ -431,6 +431,43 @@ __device__ __forceinline__ int store_frame_bar(const ParamBar<S>& g, const Packe
   return n;
 }
 
+// Value part of a plain or dual scalar (branch decisions of the tangent
+// rollout follow the value, as in the plain rollout).
+__device__ __forceinline__ float val_(float x) { return x; }
+__device__ __forceinline__ double val_(double x) { return x; }
+template <typename S>
+__device__ __forceinline__ S val_(const Dual<S>& x) {
+  return x.v;
+}
+
+// A 1-dof lane's control with its joint-limit torque added: outside
+// [lo, hi] a one-sided spring and damper, tau_l = -k (q - hi) - d qd above
+// hi, -k (q - lo) - d qd below lo (the limits model of sim_params).
+template <typename S, typename T, bool FREE>
+__device__ __forceinline__ T limit_tau(const Packed<S>& P, const Lane& l, const State<T, FREE>& st, T tau) {
+  if (!P.has_limits || !l.onedof()) return tau;
+  const int ns = P.nslots;
+  const S lo = P.cf[(CF_LIM + 0) * ns + l.slot], hi = P.cf[(CF_LIM + 1) * ns + l.slot];
+  const S k = P.cf[(CF_LIM + 2) * ns + l.slot], d = P.cf[(CF_LIM + 3) * ns + l.slot];
+  const T q = st.q[0], qd = st.qd[0];
+  if (val_(q) > hi) return tau - T(k) * (q - T(hi)) - T(d) * qd;
+  if (val_(q) < lo) return tau - T(k) * (q - T(lo)) - T(d) * qd;
+  return tau;
+}
+// its partial derivatives with respect to q and qd (zero inside the range)
+template <typename S, bool FREE>
+__device__ __forceinline__ void limit_slopes(const Packed<S>& P, const Lane& l, const State<S, FREE>& st, S& dq,
+                                             S& dqd) {
+  dq = dqd = S(0);
+  if (!P.has_limits || !l.onedof()) return;
+  const int ns = P.nslots;
+  const S q = st.q[0];
+  if (q > P.cf[(CF_LIM + 1) * ns + l.slot] || q < P.cf[(CF_LIM + 0) * ns + l.slot]) {
+    dq = -P.cf[(CF_LIM + 2) * ns + l.slot];
+    dqd = -P.cf[(CF_LIM + 3) * ns + l.slot];
+  }
+}
+
 // Everything one ABA evaluation leaves in a lane.
 template <typename S>
 struct Step {
@@ -621,7 +658,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A)
     if (l.onedof()) tau = A.tau[l.uidx];
   }
   Step<S> o;
-  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
+  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
   int nonfin = 0;
   if (l.onedof()) {
     A.qdd[l.vidx] = o.t.qdd;
@@ -665,7 +702,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
     const S tau = tau_next;
     if (has_tau && t + 1 < A.T) tau_next = A.tau[(size_t)(t + 1) * nu + l.uidx];
     Step<S> o;
-    aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
+    aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
     if constexpr (MODE == 2) {
       if (l.active()) {
         S* row = A.ck + (size_t)t * (RW + (size_t)kTapeFields * ns);
@@ -821,10 +858,13 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
       frame_bar_add(pg, L, tp, b);
     }
   }
-  // adjoint of the step's initial state; tau_bar
+  // adjoint of the step's initial state; tau_bar (the joint-limit torque
+  // adds its slopes times u_bar)
   if (rev) {
-    xb1.q[0] = acc_q + b.q;
-    xb1.qd[0] = acc_qd + b.qd;
+    S lq, lqd;
+    limit_slopes(A.P, l, st, lq, lqd);
+    xb1.q[0] = acc_q + b.q + lq * taub;
+    xb1.qd[0] = acc_qd + b.qd + lqd * taub;
     A.gtau[(size_t)t * A.P.nu + l.uidx] = taub;
     nonfin += nonfinite(taub);
   } else if constexpr (FREE) {
@@ -851,7 +891,7 @@ __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, con
                                          S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1,
                                          int& nonfin, ParamBar<S>& pg) {
   Step<S> o;
-  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
+  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
   bwd_reverse<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
 }
 
@@ -938,7 +978,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         for (int j = 0; j < arg; ++j, ++tc) {
           const S tau = rev ? A.tau[(size_t)tc * nu + l.uidx] : S(0);
           Step<S> o;
-          aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, cur, tau, maxd, xb, o);
+          aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, cur, limit_tau(A.P, l, cur, tau), maxd, xb, o);
           if (act) integrate_lane(cur, l, o, A.dt);
         }
       } else if (what == SCH_TAKESHOT) {
@@ -964,7 +1004,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         const S tau = tau_nxt;
         if (rev && j + 1 < t1 - t0) tau_nxt = A.tau[(size_t)(t0 + j) * nu + l.uidx];
         Step<S> o;
-        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
+        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
         if (act) {
           integrate_lane(st, l, o, A.dt);
           put_slot(st, A.scratch + (size_t)j * RW, ns, nf, l.slot, l.fidx);
@@ -1046,7 +1086,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
         Step<S> o;
-        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, tau, maxd, xb, o);
+        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
         S* tb = tbuf[k & 1];
 #pragma unroll
         for (int j = 0; j < (FREE ? 7 : 1); ++j) tb[(size_t)j * kWave + l.lane] = st.q[j];
@@ -1164,7 +1204,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward_jvp(JvpAr
   for (int t = 0; t < A.T; ++t) {
     const D tau = has_tau ? D(A.tau[(size_t)t * nu + l.uidx], A.dtau[(size_t)t * nu + l.uidx]) : D(S(0), S(0));
     Step<D> o;
-    aba_wave<D, FREE, CHAIN>(g, l, L, st, tau, maxd, xb, o);
+    aba_wave<D, FREE, CHAIN>(g, l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
     if (l.active()) integrate_lane(st, l, o, dt);
     if (A.traj != nullptr && l.active()) {
       split_state(st, sv, sd);

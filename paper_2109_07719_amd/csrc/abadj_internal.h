@@ -25,7 +25,8 @@ enum CfField {
   CF_MC = 16,         // 3
   CF_IB = 19,         // 6: xx yy zz xy xz yz
   CF_RL = 25,         // 9: rotation from the caller's link frame to the kernels' (joint axis = z)
-  CF_COUNT = 34
+  CF_LIM = 34,        // 4: joint limits lo, hi, stiffness k, damping d (read when has_limits)
+  CF_COUNT = 38
 };
 
 template <typename S>
@@ -39,6 +40,7 @@ struct Packed {
   S g[3];                // gravity
   int nq, nv, nu;        // totals over the batch
   int* status;           // device counter of non-finite numbers written to outputs
+  int has_limits;        // some joint has limits (CF_LIM)
 };
 
 template <typename S>

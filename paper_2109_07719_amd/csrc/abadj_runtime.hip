@@ -48,6 +48,7 @@ struct sim_handle {
   bool eti = false;  // every joint frame is the identity after canonicalisation
   bool chain = false;  // every system is a fixed-base serial chain of revolute joints
   bool has_prism = false;  // some joint is prismatic
+  bool has_limits = false;  // joint limits were given
   aba::Tiling tiling;  // launch geometry
   // binomial checkpointing schedule cached on the device for (sched_T, sched_s)
   int32_t* d_sched = nullptr;
@@ -107,6 +108,7 @@ aba::Packed<S> packed(const sim_handle* h) {
   P.nq = h->nq;
   P.nv = h->nv;
   P.nu = h->nu;
+  P.has_limits = h->has_limits ? 1 : 0;
   return P;
 }
 
@@ -295,8 +297,15 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
   const int nl = off[ns];
   if (!finite_all(prm->E_T, 9 * (size_t)nl) || !finite_all(prm->r_T, 3 * (size_t)nl) ||
       !finite_all(prm->axis, 3 * (size_t)nl) || !finite_all(prm->mass, nl) || !finite_all(prm->com, 3 * (size_t)nl) ||
-      !finite_all(prm->Ic, 6 * (size_t)nl) || !finite_all(prm->gravity, 3))
+      !finite_all(prm->Ic, 6 * (size_t)nl) || !finite_all(prm->gravity, 3) ||
+      (prm->limits && !finite_all(prm->limits, 4 * (size_t)nl)))
     return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: non-finite parameter");
+  if (prm->limits)
+    for (int L = 0; L < nl; ++L) {
+      const double* lm = prm->limits + 4 * (size_t)L;
+      if (!(lm[0] <= lm[1]) || lm[2] < 0 || lm[3] < 0)
+        return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: joint limits need lo <= hi, k >= 0, d >= 0");
+    }
 
   sim_handle* h = new (std::nothrow) sim_handle();
   if (!h) return fail(SIM_ERR_INVALID_ARG, "sim_create: out of host memory");
@@ -501,9 +510,15 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       CF(aba::CF_IB + 4) = I[4] - m * c[0] * c[2];
       CF(aba::CF_IB + 5) = I[5] - m * c[1] * c[2];
       for (int k = 0; k < 9; ++k) CF(aba::CF_RL + k) = Rl[k];
+      const double* lm = prm->limits ? prm->limits + 4 * (size_t)L : nullptr;
+      CF(aba::CF_LIM + 0) = lm ? lm[0] : -1e30;
+      CF(aba::CF_LIM + 1) = lm ? lm[1] : 1e30;
+      CF(aba::CF_LIM + 2) = lm ? lm[2] : 0.0;
+      CF(aba::CF_LIM + 3) = lm ? lm[3] : 0.0;
     }
   }
   h->eti = eti;
+  h->has_limits = prm->limits != nullptr;
   if (eti) {  // make the identity exact
     for (int slot = 0; slot < NS; ++slot)
       if (ci[(size_t)aba::CI_JTYPE * NS + slot] == SIM_JOINT_REVOLUTE ||

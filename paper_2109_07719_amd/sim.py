@@ -63,10 +63,18 @@ class Sim:
         self._com = cat("com", (3,))
         self._Ic = cat("Ic", (6,))
         self._g = np.ascontiguousarray(np.asarray(gravity, dtype=np.float64).reshape(3))
+        # optional joint limits [n, 4] per system (lo, hi, stiffness, damping)
+        if any(getattr(s, "limits", None) is not None for s in systems):
+            none = lambda s: np.tile([-1e30, 1e30, 0.0, 0.0], (len(s.parent), 1))
+            self._lim = np.ascontiguousarray(np.concatenate(
+                [np.asarray(s.limits if getattr(s, "limits", None) is not None else none(s),
+                            dtype=np.float64).reshape(-1, 4) for s in systems]).reshape(-1))
+        else:
+            self._lim = None
         p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         topo = N.SimTopology(len(systems), p(self._off), p(self._parent), p(self._jtype))
         prm = N.SimParams(p(self._E_T), p(self._r_T), p(self._axis), p(self._mass), p(self._com),
-                          p(self._Ic), p(self._g))
+                          p(self._Ic), p(self._g), p(self._lim) if self._lim is not None else None)
         h = ctypes.c_void_p()
         N.check(L.sim_create(ctypes.byref(topo), ctypes.byref(prm),
                              N.SIM_F64 if dtype == torch.float64 else N.SIM_F32, ctypes.byref(h)))
