@@ -146,7 +146,7 @@ __device__ __forceinline__ LinkC<S> load_linkc(const Packed<S>& P, const Lane& l
     for (int k = 0; k < 9; ++k) L.ET.m[k] = cf[(CF_ET + k) * ns + slot];
   }
   L.rT = v3<S>(cf[(CF_RT + 0) * ns + slot], cf[(CF_RT + 1) * ns + slot], cf[(CF_RT + 2) * ns + slot]);
-  if constexpr (FR == kFrPrismatic) {
+  if constexpr (FR == kFrGeneralJoints) {
     L.prism = l.jtype == 2;
     const S ang = L.prism ? S(0) : S(1);
     L.sm = v6<S>(v3<S>(S(0), S(0), ang), v3<S>(S(0), S(0), S(1) - ang));
@@ -442,9 +442,12 @@ __device__ __forceinline__ S val_(const Dual<S>& x) {
 
 // A 1-dof lane's control with its joint-limit torque added: outside
 // [lo, hi] a one-sided spring and damper, tau_l = -k (q - hi) - d qd above
-// hi, -k (q - lo) - d qd below lo (the limits model of sim_params).
-template <typename S, typename T, bool FREE>
+// hi, -k (q - lo) - d qd below lo (the limits model of sim_params).  Only
+// the general-joints variant carries it (handles with limits take that
+// variant); the others compile it away.
+template <int FR, typename S, typename T, bool FREE>
 __device__ __forceinline__ T limit_tau(const Packed<S>& P, const Lane& l, const State<T, FREE>& st, T tau) {
+  if constexpr (FR != kFrGeneralJoints) return tau;
   if (!P.has_limits || !l.onedof()) return tau;
   const int ns = P.nslots;
   const S lo = P.cf[(CF_LIM + 0) * ns + l.slot], hi = P.cf[(CF_LIM + 1) * ns + l.slot];
@@ -455,10 +458,11 @@ __device__ __forceinline__ T limit_tau(const Packed<S>& P, const Lane& l, const 
   return tau;
 }
 // its partial derivatives with respect to q and qd (zero inside the range)
-template <typename S, bool FREE>
+template <int FR, typename S, bool FREE>
 __device__ __forceinline__ void limit_slopes(const Packed<S>& P, const Lane& l, const State<S, FREE>& st, S& dq,
                                              S& dqd) {
   dq = dqd = S(0);
+  if constexpr (FR != kFrGeneralJoints) return;
   if (!P.has_limits || !l.onedof()) return;
   const int ns = P.nslots;
   const S q = st.q[0];
@@ -658,7 +662,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A)
     if (l.onedof()) tau = A.tau[l.uidx];
   }
   Step<S> o;
-  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
+  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
   int nonfin = 0;
   if (l.onedof()) {
     A.qdd[l.vidx] = o.t.qdd;
@@ -702,7 +706,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
     const S tau = tau_next;
     if (has_tau && t + 1 < A.T) tau_next = A.tau[(size_t)(t + 1) * nu + l.uidx];
     Step<S> o;
-    aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
+    aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
     if constexpr (MODE == 2) {
       if (l.active()) {
         S* row = A.ck + (size_t)t * (RW + (size_t)kTapeFields * ns);
@@ -730,7 +734,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
 // initial state st, then run the adjoints of the integrator, pass 3, pass 2
 // and pass 1.  xb1 holds the adjoint of x^{t+1} on entry and that of x^t on
 // exit; tau_bar^t is written to gtau.
-template <typename S, bool FREE, bool CHAIN, bool PARAMS>
+template <typename S, bool FREE, int FR, bool CHAIN, bool PARAMS>
 __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, const LinkC<S>& L, int maxd,
                                             S* xb, const State<S, FREE>& st, const Step<S>& o, int t,
                                             State<S, FREE>& xb1, int& nonfin, ParamBar<S>& pg) {
@@ -862,7 +866,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
   // adds its slopes times u_bar)
   if (rev) {
     S lq, lqd;
-    limit_slopes(A.P, l, st, lq, lqd);
+    limit_slopes<FR>(A.P, l, st, lq, lqd);
     xb1.q[0] = acc_q + b.q + lq * taub;
     xb1.qd[0] = acc_qd + b.qd + lqd * taub;
     A.gtau[(size_t)t * A.P.nu + l.uidx] = taub;
@@ -886,13 +890,13 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
   }
 }
 
-template <typename S, bool FREE, bool CHAIN, bool PARAMS>
+template <typename S, bool FREE, int FR, bool CHAIN, bool PARAMS>
 __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, const LinkC<S>& L, int maxd,
                                          S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1,
                                          int& nonfin, ParamBar<S>& pg) {
   Step<S> o;
-  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
-  bwd_reverse<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
+  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
+  bwd_reverse<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
 }
 
 // Backward (adjoint) rollout, reverse time.  K == 1 reloads every step's
@@ -945,7 +949,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         get_slot(st, row, ns, nf, l.slot, l.fidx);
         get_tape(o, row + RW, ns, l.slot, L, st.qd[0], rev);
       }
-      bwd_reverse<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
+      bwd_reverse<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
     }
   } else if (A.K == 1) {
     State<S, FREE> nxt = {};
@@ -961,7 +965,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
         if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
       }
-      bwd_step<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, st, tau, t, xb1, nonfin, pg);
+      bwd_step<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, st, tau, t, xb1, nonfin, pg);
     }
   } else if (A.K < 0) {
     // binomial checkpointing: every wave runs the same host-built schedule
@@ -978,14 +982,14 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         for (int j = 0; j < arg; ++j, ++tc) {
           const S tau = rev ? A.tau[(size_t)tc * nu + l.uidx] : S(0);
           Step<S> o;
-          aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, cur, limit_tau(A.P, l, cur, tau), maxd, xb, o);
+          aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, cur, limit_tau<FR>(A.P, l, cur, tau), maxd, xb, o);
           if (act) integrate_lane(cur, l, o, A.dt);
         }
       } else if (what == SCH_TAKESHOT) {
         if (act) put_slot(cur, A.ck + (size_t)slot * RW, ns, nf, l.slot, l.fidx);
       } else {
         const S tau = rev ? A.tau[(size_t)arg * nu + l.uidx] : S(0);
-        bwd_step<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, cur, tau, arg, xb1, nonfin, pg);
+        bwd_step<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, cur, tau, arg, xb1, nonfin, pg);
       }
     }
   } else {
@@ -1004,7 +1008,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         const S tau = tau_nxt;
         if (rev && j + 1 < t1 - t0) tau_nxt = A.tau[(size_t)(t0 + j) * nu + l.uidx];
         Step<S> o;
-        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
+        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
         if (act) {
           integrate_lane(st, l, o, A.dt);
           put_slot(st, A.scratch + (size_t)j * RW, ns, nf, l.slot, l.fidx);
@@ -1020,7 +1024,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
           if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
-        bwd_step<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, cur, tau, t, xb1, nonfin, pg);
+        bwd_step<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, cur, tau, t, xb1, nonfin, pg);
       }
     }
   }
@@ -1086,7 +1090,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
         Step<S> o;
-        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
+        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
         S* tb = tbuf[k & 1];
 #pragma unroll
         for (int j = 0; j < (FREE ? 7 : 1); ++j) tb[(size_t)j * kWave + l.lane] = st.q[j];
@@ -1124,7 +1128,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
         for (int j = 0; j < (FREE ? 6 : 1); ++j) st.qd[j] = tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane];
         Step<S> o;
         get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, L, st.qd[0], rev);
-        bwd_reverse<S, FREE, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
+        bwd_reverse<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
       }
       __syncthreads();
     }
@@ -1204,7 +1208,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward_jvp(JvpAr
   for (int t = 0; t < A.T; ++t) {
     const D tau = has_tau ? D(A.tau[(size_t)t * nu + l.uidx], A.dtau[(size_t)t * nu + l.uidx]) : D(S(0), S(0));
     Step<D> o;
-    aba_wave<D, FREE, CHAIN>(g, l, L, st, limit_tau(A.P, l, st, tau), maxd, xb, o);
+    aba_wave<D, FREE, CHAIN>(g, l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
     if (l.active()) integrate_lane(st, l, o, dt);
     if (A.traj != nullptr && l.active()) {
       split_state(st, sv, sd);

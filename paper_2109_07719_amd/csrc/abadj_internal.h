@@ -132,6 +132,7 @@ struct Shape {
   bool eti = false;
   bool chain = false;
   bool has_prism = false;  // some joint is prismatic
+  bool has_limits = false; // joint limits were given
 };
 
 // Launch geometry.  waves_per_block: wavefronts per workgroup in the
@@ -150,9 +151,10 @@ struct Tiling {
 
 // Link-frame kinds of a kernel variant.  kFrIdentity: every E_T the
 // identity after canonicalisation, every joint revolute; kFrGeneral: any
-// E_T, every joint revolute; kFrPrismatic: any E_T, and prismatic joints
-// among the revolute ones (the joint type becomes a per-lane value).
-enum : int { kFrIdentity = 0, kFrGeneral = 1, kFrPrismatic = 2 };
+// E_T, every joint revolute; kFrGeneralJoints: any E_T, prismatic joints
+// among the revolute ones (the joint type becomes a per-lane value) and
+// joint limits.
+enum : int { kFrIdentity = 0, kFrGeneral = 1, kFrGeneralJoints = 2 };
 
 // The library's error channel (sim_last_error; abadj_runtime.hip): sets the
 // thread's message and returns code / clears it.

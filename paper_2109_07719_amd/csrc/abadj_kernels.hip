@@ -9,14 +9,15 @@ namespace {
 
 // Kernel variants: FREE (some system has a free-floating root), the
 // link-frame kind FR (kFrIdentity: every joint frame the identity after
-// canonicalisation; kFrPrismatic: some joint is prismatic), CHAIN (every
-// system is a fixed-base serial chain of revolute joints; register exchange
-// between lanes).  Batches with prismatic joints take the one general
-// variant (FREE, kFrPrismatic), which handles every joint type.
+// canonicalisation; kFrGeneralJoints: prismatic joints or joint limits),
+// CHAIN (every system is a fixed-base serial chain of revolute joints;
+// register exchange between lanes).  Batches with prismatic joints or
+// joint limits take the one general variant (FREE, kFrGeneralJoints),
+// which handles every joint type and the limits.
 enum class Variant { kFree, kFreeEti, kTree, kTreeEti, kChain, kChainEti, kGeneral };
 
 Variant variant(const Shape& sh) {
-  if (sh.has_prism) return Variant::kGeneral;
+  if (sh.has_prism || sh.has_limits) return Variant::kGeneral;
   if (sh.has_free) return sh.eti ? Variant::kFreeEti : Variant::kFree;
   if (sh.chain) return sh.eti ? Variant::kChainEti : Variant::kChain;
   return sh.eti ? Variant::kTreeEti : Variant::kTree;
@@ -34,7 +35,7 @@ Variant variant(const Shape& sh) {
     case Variant::kTreeEti: return L<S, false, kFrIdentity, false>(a, tl, st); \
     case Variant::kChain: return LC<S, kFrGeneral>(a, tl, st);                \
     case Variant::kChainEti: return LC<S, kFrIdentity>(a, tl, st);            \
-    case Variant::kGeneral: return L<S, true, kFrPrismatic, false>(a, tl, st); \
+    case Variant::kGeneral: return L<S, true, kFrGeneralJoints, false>(a, tl, st); \
   }                                                                      \
   return hipErrorInvalidValue;
 

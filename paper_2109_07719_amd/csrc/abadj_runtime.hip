@@ -91,6 +91,7 @@ aba::Shape shape(const sim_handle* h) {
   sh.eti = h->eti;
   sh.chain = h->chain;
   sh.has_prism = h->has_prism;
+  sh.has_limits = h->has_limits;
   return sh;
 }
 
@@ -542,7 +543,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
   // in the previous lane, a lane's only possible child is the next lane, and
   // the kernels exchange parent/child quantities between neighbouring lanes'
   // registers
-  bool chain = !h->has_free && !h->has_prism;
+  bool chain = !h->has_free && !h->has_prism && !h->has_limits;
   for (int slot = 0; chain && slot < NS; ++slot) {
     const int p = ci[(size_t)aba::CI_PARENT * NS + slot];
     if (ci[(size_t)aba::CI_JTYPE * NS + slot] >= 0 && p >= 0 && p != slot % aba::kWave - 1) chain = false;
