@@ -440,6 +440,17 @@ __device__ __forceinline__ S val_(const Dual<S>& x) {
   return x.v;
 }
 
+// The lane's slot index hidden from loop-invariant code motion: the limit
+// constants are then re-read (from cache) where they are used instead of
+// being hoisted out of the time loop into registers, which would cost the
+// general-joints forward a wave of occupancy.  An empty asm statement on a
+// register value, no memory access.
+__device__ __forceinline__ int opaque_slot(const Lane& l) {
+  int s = l.slot;
+  asm volatile("" : "+v"(s));
+  return s;
+}
+
 // A 1-dof lane's control with its joint-limit torque added: outside
 // [lo, hi] a one-sided spring and damper, tau_l = -k (q - hi) - d qd above
 // hi, -k (q - lo) - d qd below lo (the limits model of sim_params).  Only
@@ -450,8 +461,9 @@ __device__ __forceinline__ T limit_tau(const Packed<S>& P, const Lane& l, const 
   if constexpr (FR != kFrGeneralJoints) return tau;
   if (!P.has_limits || !l.onedof()) return tau;
   const int ns = P.nslots;
-  const S lo = P.cf[(CF_LIM + 0) * ns + l.slot], hi = P.cf[(CF_LIM + 1) * ns + l.slot];
-  const S k = P.cf[(CF_LIM + 2) * ns + l.slot], d = P.cf[(CF_LIM + 3) * ns + l.slot];
+  const int slot = opaque_slot(l);
+  const S lo = P.cf[(CF_LIM + 0) * ns + slot], hi = P.cf[(CF_LIM + 1) * ns + slot];
+  const S k = P.cf[(CF_LIM + 2) * ns + slot], d = P.cf[(CF_LIM + 3) * ns + slot];
   const T q = st.q[0], qd = st.qd[0];
   if (val_(q) > hi) return tau - T(k) * (q - T(hi)) - T(d) * qd;
   if (val_(q) < lo) return tau - T(k) * (q - T(lo)) - T(d) * qd;
@@ -466,9 +478,10 @@ __device__ __forceinline__ void limit_slopes(const Packed<S>& P, const Lane& l, 
   if (!P.has_limits || !l.onedof()) return;
   const int ns = P.nslots;
   const S q = st.q[0];
-  if (q > P.cf[(CF_LIM + 1) * ns + l.slot] || q < P.cf[(CF_LIM + 0) * ns + l.slot]) {
-    dq = -P.cf[(CF_LIM + 2) * ns + l.slot];
-    dqd = -P.cf[(CF_LIM + 3) * ns + l.slot];
+  const int slot = opaque_slot(l);
+  if (q > P.cf[(CF_LIM + 1) * ns + slot] || q < P.cf[(CF_LIM + 0) * ns + slot]) {
+    dq = -P.cf[(CF_LIM + 2) * ns + slot];
+    dqd = -P.cf[(CF_LIM + 3) * ns + slot];
   }
 }
 
