@@ -121,8 +121,10 @@ class Model:
         self.E_T = f(system.E_T).reshape(-1)
         self.r_T = f(system.r_T).reshape(-1)
         # a joint axis is a direction: the joint rotates about a / |a|
+        # (a spherical joint has none; its entry is not read)
         ax = f(system.axis).reshape(-1, 3)
-        self.axis = np.ascontiguousarray((ax / np.linalg.norm(ax, axis=1, keepdims=True)).reshape(-1))
+        nrm = np.linalg.norm(ax, axis=1, keepdims=True)
+        self.axis = np.ascontiguousarray(np.where(nrm > 0, ax / np.where(nrm > 0, nrm, 1.0), 0.0).reshape(-1))
         self.mass = f(system.mass).reshape(-1)
         self.com = f(system.com).reshape(-1)
         self.Ic = f(system.Ic).reshape(-1)

@@ -20,17 +20,17 @@
 
 int orc_nq(const orc_model *m) {
   int s = 0;
-  for (int i = 0; i < m->n; ++i) s += (m->jtype[i] == ORC_FREE) ? 7 : 1;
+  for (int i = 0; i < m->n; ++i) s += (m->jtype[i] == ORC_FREE) ? 7 : (m->jtype[i] == ORC_SPHERICAL) ? 4 : 1;
   return s;
 }
 int orc_nv(const orc_model *m) {
   int s = 0;
-  for (int i = 0; i < m->n; ++i) s += (m->jtype[i] == ORC_FREE) ? 6 : 1;
+  for (int i = 0; i < m->n; ++i) s += (m->jtype[i] == ORC_FREE) ? 6 : (m->jtype[i] == ORC_SPHERICAL) ? 3 : 1;
   return s;
 }
 int orc_nu(const orc_model *m) {
   int s = 0;
-  for (int i = 0; i < m->n; ++i) s += (m->jtype[i] == ORC_FREE) ? 0 : 1;
+  for (int i = 0; i < m->n; ++i) s += (m->jtype[i] == ORC_FREE) ? 0 : (m->jtype[i] == ORC_SPHERICAL) ? 3 : 1;
   return s;
 }
 
@@ -111,8 +111,8 @@ int orc_rollout_c(const orc_model *m, const void *q0, const void *qd0,
 
 typedef struct {
   double X[36], v[6], vJ[6], c[6], h[6];
-  double IA[36], pA[6], U[6], D, u, Ia[36], pa[6], ap[6], a[6], qdd;
-  double S[6]; /* adjoint of the motion subspace */
+  double IA[36], pA[6], U[18], D[9], Di[9], u[3], Ia[36], pa[6], ap[6], a[6], qdd[3];
+  double S[18]; /* adjoint of the motion subspace (its nd columns) */
 } link_bar;
 
 /* y += A^T x */
@@ -189,7 +189,7 @@ static int limit_slopes(const orc_model *m, int i, double q, double qd, double *
   (void)qd;
   *dq = 0;
   *dqd = 0;
-  if (!m->limits || m->jtype[i] == ORC_FREE) return 0;
+  if (!m->limits || (m->jtype[i] != ORC_REVOLUTE && m->jtype[i] != ORC_PRISMATIC)) return 0;
   const double *L = m->limits + 4 * i;
   if (q > L[1] || q < L[0]) {
     *dq = -L[2];
@@ -210,13 +210,22 @@ static int limit_slopes(const orc_model *m, int i, double q, double qd, double *
  *       dEJ = -sin q [da]x + (1 - cos q)([da]x [a]x + [a]x [da]x);
  *     prismatic XJ = [I 0; -[q a]x I], S = [0; a], dXJ = [0 0; -q [da]x 0];
  *   and the axis output is w_bar x a, the gradient with respect to the axis
- *   vector along the unit sphere. */
-static void frame_params_add(const orc_model *m, int i, double q, const double *Xbar, const double *Sbar,
+ *   vector along the unit sphere.  A spherical joint has no axis: its three
+ *   axis entries stay zero, and its XJ is the rotation of its quaternion.
+ * ql points to the link's joint coordinates. */
+static void frame_params_add(const orc_model *m, int i, const double *ql, const double *Xbar, const double *Sbar,
                              double *fb) {
   const double *ax = m->axis + 3 * i, *ET = m->E_T + 9 * i, *rT = m->r_T + 3 * i;
-  const int prism = m->jtype[i] == ORC_PRISMATIC;
+  const int prism = m->jtype[i] == ORC_PRISMATIC, sph = m->jtype[i] == ORC_SPHERICAL;
+  const double q = ql[0];
   double XJ[36], XT[36], zero3[3] = {0, 0, 0}, I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
-  if (prism) {
+  if (sph) {
+    double R[9], EJ[9];
+    quat_R_r(ql, R);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) EJ[3 * a + b] = R[3 * b + a];
+    plucker_r(EJ, zero3, XJ);
+  } else if (prism) {
     double ra[3] = {q * ax[0], q * ax[1], q * ax[2]};
     plucker_r(I3, ra, XJ);
   } else {
@@ -257,6 +266,7 @@ static void frame_params_add(const orc_model *m, int i, double q, const double *
     for (int j = 0; j < 36; ++j) sp += Xbar[j] * dX[j];
     fb[k] += sp;
   }
+  if (sph) return;
   /* axis: w_bar_k = <Xbar, dXJ_k XT> + Sbar . dS_k */
   double wb[3];
   for (int k = 0; k < 3; ++k) {
@@ -305,7 +315,8 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
   double E0bar[9] = {0};
 
   for (int i = 0; i < n; ++i)
-    if (m->jtype[i] != ORC_FREE) B[i].qdd = qdd_bar[vi[i]];
+    if (m->jtype[i] != ORC_FREE)
+      for (int k = 0; k < ndof_r(m, i); ++k) B[i].qdd[k] = qdd_bar[vi[i] + k];
 
   /* reverse of pass 3, leaves -> root */
   for (int i = n - 1; i >= 0; --i) {
@@ -327,17 +338,35 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
         for (int c = 0; c < 6; ++c) b->IA[6 * r + c] -= w[r] * l->ap[c];
       continue;
     }
-    double Sv[6];
+    const int nd = ndof_r(m, i);
+    double Sv[18];
     motion_subspace_r(m, i, Sv);
     /* a = ap + S qdd */
     for (int k = 0; k < 6; ++k) b->ap[k] += b->a[k];
-    for (int k = 0; k < 6; ++k) b->qdd += Sv[k] * b->a[k];
-    for (int k = 0; k < 6; ++k) b->S[k] += b->a[k] * l->qdd;
-    /* qdd = (u - U^T ap) / D */
-    const double gq = b->qdd / l->D;
-    b->u += gq;
-    for (int k = 0; k < 6; ++k) { b->U[k] -= gq * l->ap[k]; b->ap[k] -= gq * l->U[k]; }
-    b->D -= gq * l->qdd;
+    for (int j = 0; j < nd; ++j)
+      for (int r = 0; r < 6; ++r) {
+        b->qdd[j] += Sv[6 * j + r] * b->a[r];
+        b->S[6 * j + r] += b->a[r] * l->qdd[j];
+      }
+    /* qdd = D^-1 w, w = u - U^T ap */
+    double w[3], wb[3];
+    for (int j = 0; j < nd; ++j) {
+      w[j] = l->u[j];
+      for (int r = 0; r < 6; ++r) w[j] -= l->U[6 * j + r] * l->ap[r];
+    }
+    for (int k = 0; k < nd; ++k)
+      for (int j = 0; j < nd; ++j) b->Di[3 * k + j] += b->qdd[k] * w[j];
+    for (int j = 0; j < nd; ++j) {
+      wb[j] = 0;
+      for (int k = 0; k < nd; ++k) wb[j] += l->Di[3 * k + j] * b->qdd[k];
+    }
+    for (int j = 0; j < nd; ++j) {
+      b->u[j] += wb[j];
+      for (int r = 0; r < 6; ++r) {
+        b->U[6 * j + r] -= l->ap[r] * wb[j];
+        b->ap[r] -= l->U[6 * j + r] * wb[j];
+      }
+    }
     /* ap = X a_lam + c */
     const double *al = (lam < 0) ? a0 : L[lam].a;
     if (lam >= 0) tvec_add(l->X, b->ap, B[lam].a);
@@ -351,7 +380,8 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
     const tape_t *l = &L[i];
     link_bar *b = &B[i];
     const int lam = m->parent[i];
-    double Sv[6];
+    const int nd = ndof_r(m, i);
+    double Sv[18];
     motion_subspace_r(m, i, Sv);
     if (lam >= 0) {
       const link_bar *bl = &B[lam];
@@ -373,43 +403,82 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
       mat6_mul_r(Iat, l->X, T1);
       mat6_mul_r(T1, bl->IA, T2);
       for (int k = 0; k < 36; ++k) b->X[k] += T2[k];
-      /* pa = pA + Ia c + U u / D */
+      /* pa = pA + Ia c + U y, y = D^-1 u */
       for (int k = 0; k < 6; ++k) b->pA[k] += b->pa[k];
       outer_add(b->pa, l->c, b->Ia);
       tvec_add(l->Ia, b->pa, b->c);
-      double Upa = 0;
-      for (int k = 0; k < 6; ++k) { b->U[k] += b->pa[k] * l->u / l->D; Upa += l->U[k] * b->pa[k]; }
-      b->u += Upa / l->D;
-      b->D -= Upa * l->u / (l->D * l->D);
-      /* Ia = IA - U U^T / D */
-      for (int k = 0; k < 36; ++k) b->IA[k] += b->Ia[k];
-      double UIU = 0;
-      for (int r = 0; r < 6; ++r)
-        for (int c = 0; c < 6; ++c) {
-          b->U[r] -= (b->Ia[6 * r + c] + b->Ia[6 * c + r]) * l->U[c] / l->D;
-          UIU += l->U[r] * b->Ia[6 * r + c] * l->U[c];
+      double y[3], yb[3];
+      for (int k = 0; k < nd; ++k) {
+        y[k] = 0;
+        for (int j = 0; j < nd; ++j) y[k] += l->Di[3 * k + j] * l->u[j];
+      }
+      for (int k = 0; k < nd; ++k) {
+        yb[k] = 0;
+        for (int r = 0; r < 6; ++r) {
+          yb[k] += l->U[6 * k + r] * b->pa[r];
+          b->U[6 * k + r] += b->pa[r] * y[k];
         }
-      b->D += UIU / (l->D * l->D);
+      }
+      for (int k = 0; k < nd; ++k)
+        for (int j = 0; j < nd; ++j) {
+          b->Di[3 * k + j] += yb[k] * l->u[j];
+          b->u[j] += l->Di[3 * k + j] * yb[k];
+        }
+      /* Ia = IA - U D^-1 U^T:  U_bar -= Ia_bar U D^-T + Ia_bar^T U D^-1,
+         Di_bar -= U^T Ia_bar U */
+      for (int k = 0; k < 36; ++k) b->IA[k] += b->Ia[k];
+      for (int k = 0; k < nd; ++k)
+        for (int r = 0; r < 6; ++r) {
+          double s_ = 0;
+          for (int c = 0; c < 6; ++c)
+            for (int j = 0; j < nd; ++j)
+              s_ += (b->Ia[6 * r + c] * l->Di[3 * k + j] + b->Ia[6 * c + r] * l->Di[3 * j + k]) * l->U[6 * j + c];
+          b->U[6 * k + r] -= s_;
+        }
+      for (int j = 0; j < nd; ++j)
+        for (int k = 0; k < nd; ++k) {
+          double s_ = 0;
+          for (int r = 0; r < 6; ++r)
+            for (int c = 0; c < 6; ++c) s_ += l->U[6 * j + r] * b->Ia[6 * r + c] * l->U[6 * k + c];
+          b->Di[3 * j + k] -= s_;
+        }
     }
+    /* Di = D^-1:  D_bar -= D^-T Di_bar D^-T */
+    for (int j = 0; j < nd; ++j)
+      for (int k = 0; k < nd; ++k) {
+        double s_ = 0;
+        for (int p = 0; p < nd; ++p)
+          for (int r = 0; r < nd; ++r) s_ += l->Di[3 * p + j] * b->Di[3 * p + r] * l->Di[3 * k + r];
+        b->D[3 * j + k] -= s_;
+      }
     /* u = tau + tau_limit(q, qd) - S^T pA */
-    tau_bar[ui[i]] += b->u;
-    {
+    for (int j = 0; j < nd; ++j) tau_bar[ui[i] + j] += b->u[j];
+    if (nd == 1) {
       double dq, dqd;
       if (limit_slopes(m, i, q[qi[i]], qd[vi[i]], &dq, &dqd)) {
-        q_bar[qi[i]] += dq * b->u;
-        qd_bar[vi[i]] += dqd * b->u;
+        q_bar[qi[i]] += dq * b->u[0];
+        qd_bar[vi[i]] += dqd * b->u[0];
       }
     }
-    for (int k = 0; k < 6; ++k) b->pA[k] -= Sv[k] * b->u;
-    for (int k = 0; k < 6; ++k) b->S[k] -= b->u * l->pA[k];
+    for (int j = 0; j < nd; ++j)
+      for (int r = 0; r < 6; ++r) {
+        b->pA[r] -= Sv[6 * j + r] * b->u[j];
+        b->S[6 * j + r] -= b->u[j] * l->pA[r];
+      }
     /* D = S^T U */
-    for (int k = 0; k < 6; ++k) b->U[k] += Sv[k] * b->D;
-    for (int k = 0; k < 6; ++k) b->S[k] += b->D * l->U[k];
+    for (int j = 0; j < nd; ++j)
+      for (int k = 0; k < nd; ++k)
+        for (int r = 0; r < 6; ++r) {
+          b->U[6 * k + r] += Sv[6 * j + r] * b->D[3 * j + k];
+          b->S[6 * j + r] += b->D[3 * j + k] * l->U[6 * k + r];
+        }
     /* U = IA S */
-    for (int r = 0; r < 6; ++r)
-      for (int c = 0; c < 6; ++c) b->IA[6 * r + c] += b->U[r] * Sv[c];
-    for (int r = 0; r < 6; ++r)
-      for (int c = 0; c < 6; ++c) b->S[c] += l->IA[6 * r + c] * b->U[r];
+    for (int k = 0; k < nd; ++k)
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+          b->IA[6 * r + c] += b->U[6 * k + r] * Sv[6 * k + c];
+          b->S[6 * k + c] += l->IA[6 * r + c] * b->U[6 * k + r];
+        }
   }
 
   /* reverse of pass 1, leaves -> root */
@@ -457,14 +526,34 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
     }
     for (int k = 0; k < 6; ++k) b->vJ[k] += b->v[k];
     /* vJ = S qd */
-    double Sv[6];
+    const int nd = ndof_r(m, i);
+    double Sv[18];
     motion_subspace_r(m, i, Sv);
-    for (int k = 0; k < 6; ++k) qd_bar[vi[i]] += Sv[k] * b->vJ[k];
-    for (int k = 0; k < 6; ++k) b->S[k] += b->vJ[k] * qd[vi[i]];
+    for (int k = 0; k < nd; ++k)
+      for (int r = 0; r < 6; ++r) {
+        qd_bar[vi[i] + k] += Sv[6 * k + r] * b->vJ[r];
+        b->S[6 * k + r] += b->vJ[r] * qd[vi[i] + k];
+      }
     /* X = XJ(q) XT.  Revolute: dX/dq = plucker(dEJ/dq, 0) XT with
        dEJ/dq = -cos q [a]x + sin q [a]x^2.  Prismatic: XJ = [I 0; -[q a]x I],
-       dXJ/dq = [0 0; -[a]x 0]. */
-    {
+       dXJ/dq = [0 0; -[a]x 0].  Spherical: XJ = [E 0; 0 E], E = R(quat)^T,
+       so XJ_bar = X_bar XT^T, E_bar = the sum of its diagonal blocks, and
+       R_bar = E_bar^T goes to the quaternion. */
+    if (m->jtype[i] == ORC_SPHERICAL) {
+      double ET[9], rT[3], XT[36], XJb[36], Rbar[9];
+      for (int k = 0; k < 9; ++k) ET[k] = m->E_T[9 * i + k];
+      for (int k = 0; k < 3; ++k) rT[k] = m->r_T[3 * i + k];
+      plucker_r(ET, rT, XT);
+      for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c) {
+          double s_ = 0;
+          for (int k = 0; k < 6; ++k) s_ += b->X[6 * r + k] * XT[6 * c + k];
+          XJb[6 * r + c] = s_;
+        }
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Rbar[3 * c + r] = XJb[6 * r + c] + XJb[6 * (3 + r) + 3 + c];
+      quat_R_grad(q + qi[i], Rbar, q_bar + qi[i]);
+    } else {
       double axx[9], ax2[9], dE[9], zero3[3] = {0, 0, 0}, dXJ[36], XT[36], dX[36];
       double qq = q[qi[i]], s = sin(qq), c = cos(qq);
       skew3_r(ax, axx);
@@ -486,7 +575,7 @@ static int aba_vjp(const orc_model *m, const double *q, const double *qd,
       for (int k = 0; k < 36; ++k) sdot += b->X[k] * dX[k];
       q_bar[qi[i]] += sdot;
     }
-    if (frame_bar) frame_params_add(m, i, q[qi[i]], b->X, b->S, frame_bar + 9 * i);
+    if (frame_bar) frame_params_add(m, i, q + qi[i], b->X, b->S, frame_bar + 9 * i);
   }
   free(B);
   return 0;
@@ -502,6 +591,31 @@ void orc_fd_vjp(const orc_model *m, const double *q, const double *qd,
   aba_vjp(m, q, qd, L, qdd_bar, q_bar, qd_bar, tau_bar, NULL, NULL);
   free(qdd);
   free(L);
+}
+
+/* Adjoint of quat_step (orientation step by a body-frame angular velocity
+ * w1): given the adjoint q1b of quat1, ADD into qtb (4) and w1b (3). */
+static void quat_step_vjp(const double *qt, const double *w1, double dt, const double *q1b, double *qtb,
+                          double *w1b) {
+  double wq[4] = {w1[0], w1[1], w1[2], 0}, dq[4], qr[4], q1[4];
+  quat_mul_r(qt, wq, dq);
+  for (int k = 0; k < 4; ++k) qr[k] = qt[k] + 0.5 * dt * dq[k];
+  const double nrm = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+  for (int k = 0; k < 4; ++k) q1[k] = qr[k] / nrm;
+  /* quat1 = qr / |qr| */
+  double dotq = 0, ob[4];
+  for (int k = 0; k < 4; ++k) dotq += q1[k] * q1b[k];
+  for (int k = 0; k < 4; ++k) ob[k] = (q1b[k] - q1[k] * dotq) / nrm;
+  /* qr = qt + dt/2 * qt (x) (w1, 0):  o_v = qt_w w1 + qt_v x w1, o_w = -qt_v . w1 */
+  const double h = 0.5 * dt;
+  for (int k = 0; k < 4; ++k) qtb[k] += ob[k];
+  const double cr[3] = {w1[1] * ob[2] - w1[2] * ob[1], w1[2] * ob[0] - w1[0] * ob[2],
+                        w1[0] * ob[1] - w1[1] * ob[0]}; /* w1 x ob_v */
+  for (int k = 0; k < 3; ++k) qtb[k] += h * (cr[k] - w1[k] * ob[3]);
+  qtb[3] += h * (w1[0] * ob[0] + w1[1] * ob[1] + w1[2] * ob[2]);
+  const double axo[3] = {qt[1] * ob[2] - qt[2] * ob[1], qt[2] * ob[0] - qt[0] * ob[2],
+                         qt[0] * ob[1] - qt[1] * ob[0]}; /* qt_v x ob_v */
+  for (int k = 0; k < 3; ++k) w1b[k] += h * (qt[3] * ob[k] - axo[k] - qt[k] * ob[3]);
 }
 
 /* Adjoint of one semi-implicit Euler step taken from x^t = (q, qd) with
@@ -524,32 +638,11 @@ static int step_vjp(const orc_model *m, const double *q, const double *qd,
       for (int k = 0; k < 6; ++k) v1[k] = qd[vi[i] + k] + dt * qdd[vi[i] + k];
       double R[9];
       quat_R_r(qt, R);
-      double wq[4] = {v1[0], v1[1], v1[2], 0}, dq[4], qr[4], q1[4];
-      quat_mul_r(qt, wq, dq);
-      for (int k = 0; k < 4; ++k) qr[k] = qt[k] + 0.5 * dt * dq[k];
-      double nrm = sqrt(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
-      for (int k = 0; k < 4; ++k) q1[k] = qr[k] / nrm;
-      /* quat1 = qr / |qr| */
-      const double *q1b = q1bar + qi[i] + 3;
-      double dotq = 0, qrbar[4];
-      for (int k = 0; k < 4; ++k) dotq += q1[k] * q1b[k];
-      for (int k = 0; k < 4; ++k) qrbar[k] = (q1b[k] - q1[k] * dotq) / nrm;
-      /* qr = qt + dt/2 * qt (x) (w1, 0) */
       double *qtb = qbar + qi[i] + 3;
-      for (int k = 0; k < 4; ++k) qtb[k] = qrbar[k];
-      const double h = 0.5 * dt;
-      const double *ob = qrbar; /* ob[0..2] vector part, ob[3] scalar part */
-      const double *w1 = v1;
-      /* o_v = a3 w1 + av x w1; o_w = -av . w1   (a = qt) */
-      double cr[3] = {w1[1] * ob[2] - w1[2] * ob[1], w1[2] * ob[0] - w1[0] * ob[2],
-                      w1[0] * ob[1] - w1[1] * ob[0]}; /* w1 x ob_v */
-      for (int k = 0; k < 3; ++k) qtb[k] += h * (cr[k] - w1[k] * ob[3]);
-      qtb[3] += h * (w1[0] * ob[0] + w1[1] * ob[1] + w1[2] * ob[2]);
+      for (int k = 0; k < 4; ++k) qtb[k] = 0;
       double v1bar[6];
       for (int k = 0; k < 6; ++k) v1bar[k] = qd1bar[vi[i] + k];
-      double axo[3] = {qt[1] * ob[2] - qt[2] * ob[1], qt[2] * ob[0] - qt[0] * ob[2],
-                       qt[0] * ob[1] - qt[1] * ob[0]}; /* av x ob_v */
-      for (int k = 0; k < 3; ++k) v1bar[k] += h * (qt[3] * ob[k] - axo[k] - qt[k] * ob[3]);
+      quat_step_vjp(qt, v1, dt, q1bar + qi[i] + 3, qtb, v1bar);
       /* p1 = p + dt R(qt) v1_lin */
       const double *p1b = q1bar + qi[i];
       for (int k = 0; k < 3; ++k) qbar[qi[i] + k] = p1b[k];
@@ -563,6 +656,21 @@ static int step_vjp(const orc_model *m, const double *q, const double *qd,
       for (int k = 0; k < 6; ++k) {
         qdbar[vi[i] + k] = v1bar[k];
         qddbar[vi[i] + k] = dt * v1bar[k];
+      }
+    } else if (m->jtype[i] == ORC_SPHERICAL) {
+      /* w1 = w + dt wdot; quat1 = quat_step(quat, w1) */
+      const double *qt = q + qi[i];
+      double w1[3], w1bar[3];
+      for (int k = 0; k < 3; ++k) {
+        w1[k] = qd[vi[i] + k] + dt * qdd[vi[i] + k];
+        w1bar[k] = qd1bar[vi[i] + k];
+        qbar[qi[i] + k] = 0;
+      }
+      qbar[qi[i] + 3] = 0;
+      quat_step_vjp(qt, w1, dt, q1bar + qi[i], qbar + qi[i], w1bar);
+      for (int k = 0; k < 3; ++k) {
+        qdbar[vi[i] + k] = w1bar[k];
+        qddbar[vi[i] + k] = dt * w1bar[k];
       }
     } else {
       const double tot = qd1bar[vi[i]] + dt * q1bar[qi[i]];
@@ -582,7 +690,7 @@ static void tape_qdd(const orc_model *m, const tape_t *L, double *qdd) {
     if (m->jtype[i] == ORC_FREE)
       for (int k = 0; k < 6; ++k) qdd[vi[i] + k] = L[i].abase[k];
     else
-      qdd[vi[i]] = L[i].qdd;
+      for (int k = 0; k < ndof_r(m, i); ++k) qdd[vi[i] + k] = L[i].qdd[k];
   }
 }
 

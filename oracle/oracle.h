@@ -32,6 +32,12 @@
  * Prismatic joint (type 2): the link slides by q along the unit axis a of
  * the joint frame, X_J(q) = [I 0; -[q a]x I], motion subspace S = [0; a].
  *
+ * Spherical joint (type 3): a ball joint at the joint frame's origin.
+ * q = quat[4] (x, y, z, w) of the link frame relative to the joint frame,
+ * velocity = the link's angular velocity relative to its parent in link
+ * coordinates (3), control = the joint torque in link coordinates (3);
+ * X_J = [E 0; 0 E] with E = R(quat)^T, motion subspace S = [1; 0] (6x3).
+ *
  * Free-floating root (joint type 1, only at link 0): q = (p_world[3],
  * quat[4] stored x,y,z,w), velocity = body-frame spatial velocity [w_b; v_b].
  * The root is unactuated; tau holds one entry per revolute or prismatic
@@ -45,13 +51,14 @@
 #define ORC_REVOLUTE 0
 #define ORC_FREE 1
 #define ORC_PRISMATIC 2
+#define ORC_SPHERICAL 3
 
 typedef struct {
   int n;                 /* number of links */
   const int *parent;     /* parent[i] < i; -1 = attached to the fixed base
                             (or, for a free root, no parent)               */
-  const int *jtype;      /* ORC_REVOLUTE, ORC_PRISMATIC, or ORC_FREE (link 0
-                            only)                                          */
+  const int *jtype;      /* ORC_REVOLUTE, ORC_PRISMATIC, ORC_SPHERICAL, or
+                            ORC_FREE (link 0 only)                         */
   const double *E_T;     /* 9n: fixed rotation parent->joint frame, rowmajor */
   const double *r_T;     /* 3n: joint origin in parent coordinates          */
   const double *axis;    /* 3n: joint axis in the link frame, unit length

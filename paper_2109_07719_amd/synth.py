@@ -32,6 +32,7 @@ import numpy as np
 REVOLUTE = 0
 FREE = 1
 PRISMATIC = 2
+SPHERICAL = 3
 GRAVITY = np.array([0.0, -9.81, 0.0])
 
 
@@ -57,15 +58,15 @@ class System:
 
     @property
     def nq(self) -> int:
-        return int(np.sum(np.where(self.jtype == FREE, 7, 1)))
+        return int(np.sum(np.select([self.jtype == FREE, self.jtype == SPHERICAL], [7, 4], 1)))
 
     @property
     def nv(self) -> int:
-        return int(np.sum(np.where(self.jtype == FREE, 6, 1)))
+        return int(np.sum(np.select([self.jtype == FREE, self.jtype == SPHERICAL], [6, 3], 1)))
 
     @property
     def nu(self) -> int:
-        return int(np.sum(self.jtype != FREE))
+        return int(np.sum(np.select([self.jtype == FREE, self.jtype == SPHERICAL], [0, 3], 1)))
 
     def depth(self) -> np.ndarray:
         d = np.zeros(self.n, dtype=np.int64)
@@ -285,6 +286,55 @@ def telescoping_quadruped_system(seed: int, T: int):
         jtype[calf] = PRISMATIC
         axis[calf] = [0.0, 1.0, 0.0]
     return replace(sys_, jtype=jtype, axis=axis), q0, v, tau
+
+
+def with_spherical_joints(sys_: System, q0, qd0, tau, links, seed: int):
+    """The system with the joints of the given links turned into spherical
+    (ball) joints, and its state and controls re-laid out: such a joint's q
+    entry becomes a unit quaternion (x, y, z, w) of a rotation vector ~
+    N(0, 0.3^2), its qd entry a link-frame angular velocity ~ N(0, 0.3^2)
+    (3), its tau entry three torques ~ N(0, 1).  The new draws come from
+    their own stream (seed); every other entry keeps its value."""
+    rng = np.random.default_rng(seed)
+    links = set(int(i) for i in links)
+    jtype = sys_.jtype.copy()
+    T = tau.shape[0]
+    q, qd, u = [], [], []
+    qi = vi = ui = 0
+    for i in range(sys_.n):
+        if jtype[i] == FREE:
+            q.append(q0[qi:qi + 7]); qd.append(qd0[vi:vi + 6])
+            qi += 7; vi += 6
+            continue
+        if i in links:
+            w = rng.normal(0.0, 0.3, 3)
+            th = float(np.linalg.norm(w))
+            quat = np.r_[np.sin(th / 2) * w / th, np.cos(th / 2)] if th > 0 else np.array([0.0, 0.0, 0.0, 1.0])
+            q.append(quat); qd.append(rng.normal(0.0, 0.3, 3)); u.append(rng.normal(0.0, 1.0, (T, 3)))
+            jtype[i] = SPHERICAL
+        else:
+            q.append(q0[qi:qi + 1]); qd.append(qd0[vi:vi + 1]); u.append(tau[:, ui:ui + 1])
+        qi += 1; vi += 1; ui += 1
+    tau_new = np.concatenate(u, axis=1) if u else np.zeros((T, 0))
+    return replace(sys_, jtype=jtype), np.concatenate(q), np.concatenate(qd), tau_new
+
+
+def ball_tree_system(seed: int, T: int, spherical: float = 0.3, **kw):
+    """tree_system(seed, T, **kw) with every joint spherical with the given
+    probability (drawn from the stream seed + 2 * 10^6, which also draws the
+    new joints' states and torques)."""
+    sys_, q0, qd0, tau = tree_system(seed, T, **kw)
+    pick = np.random.default_rng(seed + 2_000_000).uniform(size=sys_.n) < spherical
+    return with_spherical_joints(sys_, q0, qd0, tau, np.nonzero(pick)[0], seed + 3_000_000)
+
+
+def ball_quadruped_system(seed: int, T: int):
+    """quadruped_system(seed, T) with every hip a ball joint: a free-floating
+    base over spherical hips and revolute thighs and knees (n_q = 31, n_v =
+    26, 20 controls).  Same draws as quadruped_system, then the ball joints'
+    from the stream seed + 3 * 10^6."""
+    sys_, q0, v, tau = quadruped_system(seed, T)
+    return with_spherical_joints(sys_, q0, v, tau, (1, 4, 7, 10), seed + 3_000_000)
 
 
 def prismatic_chain_system(n: int, seed: int, T: int):

@@ -16,7 +16,10 @@ Joint kinematics follow the package convention: a link frame is reached from
 its parent by the fixed rotation E_T and offset r_T, then a rotation by q
 about the unit axis a (coordinates map by E = E_J(q) E_T, so the
 link-to-parent rotation matrix is E^T), or, for a prismatic joint (type 2),
-a translation by q along a.
+a translation by q along a, or, for a spherical joint (type 3), the rotation
+of the unit quaternion q (x, y, z, w) with the link's angular velocity
+relative to its parent given in link coordinates (3 velocity entries and 3
+torque entries, the torque about the link origin in link coordinates).
 """
 from __future__ import annotations
 
@@ -84,6 +87,20 @@ def kinematics(sys_, q, qd, qdd, gravity):
         a = np.asarray(sys_.axis[i], dtype=float)
         Rpre = Rl @ ET.T                # pre-joint frame -> world
         zi = Rpre @ a                   # world joint axis
+        if sys_.jtype[i] == 3:
+            # spherical: a ball joint at the joint origin
+            rij = Rl @ np.asarray(sys_.r_T[i], dtype=float)
+            oi = ol + rij
+            Ri = Rpre @ _quat_R(q[k:k + 4])
+            wrel = Ri @ qd[kv:kv + 3]
+            wi = wl + wrel
+            wdi = wdl + Ri @ qdd[kv:kv + 3] + np.cross(wl, wrel)
+            voi = vl + np.cross(wl, rij)
+            aoi = al + np.cross(wdl, rij) + np.cross(wl, np.cross(wl, rij))
+            R[i], o[i], w[i], wd[i], vo[i], ao[i], z[i] = Ri, oi, wi, wdi, voi, aoi, None
+            k += 4
+            kv += 3
+            continue
         if sys_.jtype[i] == 2:
             # prismatic: the link origin slides by q along the axis, no rotation
             rij = Rl @ np.asarray(sys_.r_T[i], dtype=float) + zi * q[k]
@@ -133,6 +150,8 @@ def inverse_dynamics(sys_, q, qd, qdd, gravity=(0.0, -9.81, 0.0)):
     for i in range(n):
         if sys_.jtype[i] == 1:
             out.extend(list(R[i].T @ nm[i]) + list(R[i].T @ f[i]))
+        elif sys_.jtype[i] == 3:
+            out.extend(list(R[i].T @ nm[i]))
         elif sys_.jtype[i] == 2:
             out.append(z[i] @ f[i])
         else:

@@ -20,17 +20,17 @@ SRC = os.path.dirname(os.path.abspath(O.__file__))
 MUTATIONS = [
     ("aba_fwd.inc", "- s * ax[k] + (1.0 - c) * ax2[k]", "+ s * ax[k] + (1.0 - c) * ax2[k]", "joint rotation sign"),
     ("aba_fwd.inc", "J[3 * i + j] - m * cx2[3 * i + j]", "J[3 * i + j] + m * cx2[3 * i + j]", "inertia shift sign"),
-    ("aba_fwd.inc", "l->qdd = (l->u - Uap) / l->D;", "l->qdd = (l->u + Uap) / l->D;", "pass-3 sign"),
-    ("aba_fwd.inc", "l->pa[k] = l->pA[k] + Iac[k] + l->U[k] * l->u / l->D;",
-     "l->pa[k] = l->pA[k] + l->U[k] * l->u / l->D;", "dropped I^a c term"),
+    ("aba_fwd.inc", "w[j] = l->u[j] - Uap;", "w[j] = l->u[j] + Uap;", "pass-3 sign"),
+    ("aba_fwd.inc", "S s_ = l->pA[r] + Iac[r];", "S s_ = l->pA[r];", "dropped I^a c term"),
     ("aba_fwd.inc", "FN(mat6_mul)(XT_, l->Ia, T1);\n      FN(mat6_mul)(T1, l->X, T2);",
      "FN(mat6_mul)(l->X, l->Ia, T1);\n      FN(mat6_mul)(T1, XT_, T2);", "transposed congruence"),
     ("aba_fwd.inc", "q1[qi[i]] = q[qi[i]] + dt * qd1[vi[i]];", "q1[qi[i]] = q[qi[i]] + dt * qd[vi[i]];",
      "explicit instead of semi-implicit Euler"),
     ("aba_fwd.inc", "l->abase[k + 3] = l->ap[k + 3] + Eg[k];", "l->abase[k + 3] = l->ap[k + 3] - Eg[k];",
      "free-root gravity sign"),
-    ("aba_oracle.c", "b->U[k] -= gq * l->ap[k];", "b->U[k] += gq * l->ap[k];", "adjoint sign (U_bar)"),
-    ("aba_oracle.c", "b->D -= Upa * l->u / (l->D * l->D);", "b->D -= 0.0;", "dropped D_bar term"),
+    ("aba_oracle.c", "b->U[6 * j + r] -= l->ap[r] * wb[j];", "b->U[6 * j + r] += l->ap[r] * wb[j];",
+     "adjoint sign (U_bar)"),
+    ("aba_oracle.c", "          b->Di[3 * k + j] += yb[k] * l->u[j];\n", "", "dropped D_bar term"),
     ("aba_oracle.c", "tvec_add(F, b->pA, b->h);", "vec_add(F, b->pA, b->h);", "transposed crf adjoint"),
     ("aba_oracle.c", "const double tot = qd1bar[vi[i]] + dt * q1bar[qi[i]];", "const double tot = qd1bar[vi[i]];",
      "dropped integrator coupling"),
@@ -59,8 +59,8 @@ MUTATIONS = [
     ("aba_oracle.c", "mat3_mul_r(ET, ekx, Ee);", "mat3_mul_r(ekx, ET, Ee);", "transposed joint-origin derivative"),
     ("aba_oracle.c", "        dXT[6 * (3 + r) + c] = -dErx[3 * r + c];\n", "",
      "dropped translation term of the frame-rotation derivative"),
-    ("aba_oracle.c", "      for (int c = 0; c < 6; ++c) b->S[c] += l->IA[6 * r + c] * b->U[r];",
-     "      for (int c = 0; c < 6; ++c) b->S[c] += 0.0;", "dropped U = IA S term of the motion-subspace adjoint"),
+    ("aba_oracle.c", "          b->S[6 * k + c] += l->IA[6 * r + c] * b->U[6 * k + r];\n", "",
+     "dropped U = IA S term of the motion-subspace adjoint"),
     ("pgs_oracle.c", "        if (j != i) d += A[(size_t)i * n + j] * x[j];\n      const double y = -(b[i] + d)",
      "        if (j != i) d += A[(size_t)i * n + i] * x[j];\n      const double y = -(b[i] + d)",
      "PGS row sum with the diagonal entry (as the printed listing reads)"),
@@ -74,6 +74,20 @@ MUTATIONS = [
     ("aba_oracle.c", "    *dqd = -L[3];", "    *dqd = 0;", "dropped joint-limit damping adjoint"),
     ("aba_fwd.inc", "if (SREAL(q) < L[0]) return -L[2] * (q - L[0]) - L[3] * qd;",
      "if (SREAL(q) < L[0]) return -L[2] * (q - L[1]) - L[3] * qd;", "lower joint limit measured from the upper one"),
+    ("aba_fwd.inc", "for (int b = 0; b < 3; ++b) EJ[3 * a + b] = R[3 * b + a];",
+     "for (int b = 0; b < 3; ++b) EJ[3 * a + b] = R[3 * a + b];", "ball-joint rotation not transposed"),
+    ("aba_fwd.inc", "for (int k = 0; k < 3; ++k) { l->vJ[k] = qd[vi[i] + k]; l->vJ[k + 3] = 0; }",
+     "for (int k = 0; k < 3; ++k) { l->vJ[k] = 0; l->vJ[k + 3] = qd[vi[i] + k]; }", "ball-joint velocity as a translation"),
+    ("aba_fwd.inc", "Di[1] = -(b * k - c * h) / det;", "Di[1] = (b * k - c * h) / det;", "3x3 inverse cofactor sign"),
+    ("aba_fwd.inc", "FN(quat_step)(q + qi[i], w1, dt, q1 + qi[i]);", "FN(quat_step)(q + qi[i], qd + vi[i], dt, q1 + qi[i]);",
+     "ball joint turned by the old angular velocity"),
+    ("aba_oracle.c", "Rbar[3 * c + r] = XJb[6 * r + c] + XJb[6 * (3 + r) + 3 + c];",
+     "Rbar[3 * r + c] = XJb[6 * r + c] + XJb[6 * (3 + r) + 3 + c];", "ball-joint rotation adjoint transposed"),
+    ("aba_oracle.c", "quat_step_vjp(qt, w1, dt, q1bar + qi[i], qbar + qi[i], w1bar);",
+     "quat_step_vjp(qt, qd + vi[i], dt, q1bar + qi[i], qbar + qi[i], w1bar);",
+     "ball-joint orientation adjoint at the old angular velocity"),
+    ("aba_oracle.c", "qddbar[vi[i] + k] = dt * w1bar[k];", "qddbar[vi[i] + k] = w1bar[k];",
+     "ball-joint integrator adjoint without dt"),
 ]
 
 PINS = [
@@ -96,6 +110,9 @@ PINS = [
     lambda: pins.test_frame_and_axis_gradients_central_differences(0),
     pins.test_joint_limit_torque_is_added_to_the_control,
     pins.test_rollout_gradient_with_joint_limits_complex_step,
+    pins.test_aba_equals_dense_solve_every_tree_with_spherical_joints,
+    pins.test_single_body_on_a_ball_joint_obeys_eulers_equations,
+    lambda: pins.test_rollout_gradient_complex_step_with_spherical_joints(0),
     pgs.test_unbounded_converges_to_the_linear_solve,
     pgs.test_one_sweep_by_hand,
     lambda: pgs.test_adjoint_against_complex_step(3, 12),

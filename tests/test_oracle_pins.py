@@ -8,6 +8,7 @@ operand anywhere in the oracle's ABA, integrator or adjoint fails one of
 them.
 """
 import itertools
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -792,3 +793,191 @@ def test_joint_limits_inside_the_range_change_nothing():
     a = O.rollout(O.Model(s), q0, qd0, tau, 1e-3)
     b = O.rollout(O.Model(plain), q0, qd0, tau, 1e-3)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ------------------------------------------------------------- spherical joints
+
+def _random_quat(rng):
+    qt = rng.normal(size=4)
+    return qt / np.linalg.norm(qt)
+
+
+def _random_state(s, rng, scale=1.0):
+    """q (unit quaternions for ball joints and a free root), qd, tau."""
+    q = []
+    for i in range(s.n):
+        if s.jtype[i] == synth.FREE:
+            q += list(rng.normal(size=3)) + list(_random_quat(rng))
+        elif s.jtype[i] == synth.SPHERICAL:
+            q += list(_random_quat(rng))
+        else:
+            q.append(rng.normal(0, scale))
+    return np.array(q), rng.normal(0, scale, s.nv), rng.normal(0, 1, s.nu)
+
+
+def test_aba_equals_dense_solve_every_tree_with_spherical_joints():
+    """ABA with ball joints (S = [1; 0], a 3x3 joint-space inertia per joint)
+    reaches M^-1 (tau - C) of the independent world-frame Newton-Euler on
+    every parent array of up to 4 links, each joint spherical, prismatic or
+    revolute at random, with random frames, offsets and inertias."""
+    rng = np.random.default_rng(31)
+    count = nsph = 0
+    for n in range(1, 5):
+        for parent in all_parent_arrays(n):
+            u = rng.uniform(size=n)
+            jt = np.where(u < 0.5, synth.SPHERICAL, np.where(u < 0.7, synth.PRISMATIC, synth.REVOLUTE))
+            s = replace(_random_tree(parent, rng), jtype=jt.astype(np.int32))
+            m = O.Model(s)
+            for _ in range(3):
+                q, qd, tau = _random_state(s, rng)
+                assert _rel(O.fd(m, q, qd, tau), R.forward_dynamics(s, q, qd, tau)) < 1e-12
+            count += 1
+            nsph += int(np.sum(jt == synth.SPHERICAL))
+    assert count == 33 and nsph > 30
+
+
+def test_ball_joint_quadruped_dense_solve_and_momentum_balance():
+    """Free-floating base over ball-joint hips: inverse dynamics at the
+    oracle's accelerations returns tau on the joints and a zero net wrench
+    on the base."""
+    for seed in range(3000, 3003):
+        s, _, _, tau = synth.ball_quadruped_system(seed, 1)
+        assert (s.nq, s.nv, s.nu) == (31, 26, 20)
+        q, qd, _ = _random_state(s, np.random.default_rng(seed))
+        qdd = O.fd(O.Model(s), q, qd, tau[0])
+        res = R.inverse_dynamics(s, q, qd, qdd)
+        scale = np.abs(R.inverse_dynamics(s, q, qd, np.zeros(26))).max()
+        assert np.abs(res[:6]).max() < 1e-12 * scale
+        assert np.abs(res[6:] - tau[0]).max() < 1e-12 * scale
+
+
+def test_single_body_on_a_ball_joint_obeys_eulers_equations():
+    """A rigid body on a ball joint fixed in space turns by Euler's equations
+    about the pivot, in body coordinates:
+    I_O wdot + w x (I_O w) = tau + c x (m g_b), with I_O = I_c + m (|c|^2 1 -
+    c c^T) and g_b the gravity vector in body coordinates (the body-to-world
+    rotation is E_T^T R(quat))."""
+    rng = np.random.default_rng(41)
+    for _ in range(10):
+        s = replace(_random_tree((-1,), rng), jtype=np.array([synth.SPHERICAL], np.int32))
+        q, w, tau = _random_state(s, rng)
+        m_, c = float(s.mass[0]), np.asarray(s.com[0])
+        xx, yy, zz, xy, xz, yz = s.Ic[0]
+        IO = np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]]) + m_ * (c @ c * np.eye(3) - np.outer(c, c))
+        gb = (s.E_T[0].T @ R._quat_R(q)).T @ np.asarray(synth.GRAVITY)
+        ref = np.linalg.solve(IO, tau + np.cross(c, m_ * gb) - np.cross(w, IO @ w))
+        assert _rel(O.fd(O.Model(s), q, w, tau), ref) < 1e-13
+
+
+def _ball_problems():
+    quad = synth.ball_quadruped_system(3001, 80)
+    tree = synth.ball_tree_system(2005, 60, nmax=14, random_frames=True, prismatic=0.2, spherical=0.4)
+    return [("quad", quad, 1e-3), ("tree", tree, 5e-4)]
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_rollout_gradient_complex_step_with_spherical_joints(k):
+    """Rollouts through ball joints (quaternion integration and normalisation
+    at every ball joint, a free root on the quadruped): the adjoint gradient
+    of a random linear loss against complex-step derivatives of every q0
+    entry (quaternions included) and qd0 entry, and of sampled tau entries."""
+    name, (s, q0, qd0, tau), dt = _ball_problems()[k]
+    assert np.sum(s.jtype == synth.SPHERICAL) >= 2
+    m = O.Model(s)
+    rng = np.random.default_rng(5 + k)
+    wq, wv = rng.normal(size=s.nq), rng.normal(size=s.nv)
+    gq0, gqd0, gtau, _, _ = O.rollout_grad(m, q0, qd0, tau, dt, wq, wv)
+    h = 1e-30
+
+    def Lc(a, b_, t):
+        qT, qdT = O.rollout_complex(m, a, b_, t, dt)
+        return wq @ qT + wv @ qdT
+
+    scale = max(np.abs(gq0).max(), np.abs(gqd0).max())
+    for j in range(s.nq):
+        d = Lc(q0 + 1j * h * np.eye(s.nq)[j], qd0.astype(complex), tau.astype(complex)).imag / h
+        assert abs(d - gq0[j]) < 1e-11 * scale, (name, j)
+    for j in range(s.nv):
+        d = Lc(q0.astype(complex), qd0 + 1j * h * np.eye(s.nv)[j], tau.astype(complex)).imag / h
+        assert abs(d - gqd0[j]) < 1e-11 * scale, (name, j)
+    for _ in range(10):
+        t, j = int(rng.integers(0, tau.shape[0])), int(rng.integers(0, s.nu))
+        tc = tau.astype(complex)
+        tc[t, j] += 1j * h
+        d = Lc(q0.astype(complex), qd0.astype(complex), tc).imag / h
+        assert abs(d - gtau[t, j]) < 1e-11 * np.abs(gtau).max(), (name, t, j)
+
+
+def test_ball_joint_parameter_and_placement_gradients_central_differences():
+    """Inertial-parameter and joint-placement gradients of ball-joint links
+    against central differences of the forward rollout; a ball joint has no
+    axis, so its three axis entries are zero."""
+    s, q0, qd0, tau = synth.ball_tree_system(2014, 80, nmax=12, random_frames=True, prismatic=0.2, spherical=0.5)
+    dt = 5e-4
+    _, qT, qdT = _param_loss(s, q0, qd0, tau, dt)
+    out = O.rollout_grad_params(O.Model(s), q0, qd0, tau, dt, 2 * qT, qdT)
+    g, gf = out[3], out[4]
+    sph = [i for i in range(s.n) if s.jtype[i] == synth.SPHERICAL]
+    assert len(sph) >= 2
+    th = _inertial_params(s)
+    scale = max(np.abs(gf).max(), np.abs(g).max())
+    for i in sph[:3]:
+        assert not np.any(gf[i, 6:9])
+        for which, off in (("phi", 0), ("r", 3)):
+            for j in range(3):
+                d = np.zeros(3)
+                d[j] = 1e-6
+                fd = (_param_loss(_with_frame(s, i, which, d), q0, qd0, tau, dt)[0] -
+                      _param_loss(_with_frame(s, i, which, -d), q0, qd0, tau, dt)[0]) / 2e-6
+                assert abs(fd - gf[i, off + j]) < 2e-6 * max(1.0, scale), (i, which, j, fd, gf[i, off + j])
+        for j in range(10):
+            hh = 1e-6 * max(1.0, abs(th[i, j]))
+            tp, tm = th.copy(), th.copy()
+            tp[i, j] += hh
+            tm[i, j] -= hh
+            fd = (_param_loss(_with_inertial_params(s, tp), q0, qd0, tau, dt)[0] -
+                  _param_loss(_with_inertial_params(s, tm), q0, qd0, tau, dt)[0]) / (2 * hh)
+            assert abs(fd - g[i, j]) < 2e-6 * max(1.0, scale), (i, j, fd, g[i, j])
+
+
+def test_ball_joint_integrator_keeps_unit_quaternions_and_first_order_energy_drift():
+    """Every ball joint's quaternion stays of unit length after every step,
+    and on a passive tree the largest energy deviation over 0.5 s shrinks
+    linearly with dt (semi-implicit Euler is first order)."""
+    s, q0, qd0, _ = synth.ball_tree_system(2016, 1, nmax=8, spherical=0.6)
+    assert np.sum(s.jtype == synth.SPHERICAL) >= 2
+    m = O.Model(s)
+    qd0 = 3 * qd0
+    E0 = R.energy(s, q0, qd0)
+    qoff = np.cumsum([0] + [4 if j == synth.SPHERICAL else 1 for j in s.jtype])
+    drifts = []
+    for dt in (1e-3, 5e-4, 2.5e-4):
+        T = int(round(0.5 / dt))
+        _, _, tr = O.rollout(m, q0, qd0, np.zeros((T, s.nu)), dt, traj=True)
+        for i in np.nonzero(s.jtype == synth.SPHERICAL)[0]:
+            nrm = np.linalg.norm(tr[:, qoff[i]:qoff[i] + 4], axis=1)
+            assert np.abs(nrm - 1).max() < 1e-14
+        idx = np.linspace(0, T - 1, 100).astype(int)
+        drifts.append(max(abs(R.energy(s, tr[k, :s.nq], tr[k, s.nq:]) - E0) for k in idx))
+    for a, b in zip(drifts, drifts[1:]):
+        assert 0.35 < b / a < 0.65, drifts
+
+
+def test_ball_joint_checkpointing_changes_no_arithmetic():
+    """Checkpoint interval and store-all give bitwise-identical gradients
+    (inputs, inertial parameters and placements) on the ball-joint
+    quadruped, and the sweep along the oracle's own trajectory reproduces
+    them."""
+    s, q0, qd0, tau = synth.ball_quadruped_system(3011, 50)
+    m = O.Model(s)
+    qT, qdT = O.rollout(m, q0, qd0, tau, 1e-3)
+    ref = O.rollout_grad_params(m, q0, qd0, tau, 1e-3, 2 * qT, qdT, K=1)
+    for K in (0, 7, 50):
+        out = O.rollout_grad_params(m, q0, qd0, tau, 1e-3, 2 * qT, qdT, K=K)
+        for a, b in zip(out[:5], ref[:5]):
+            assert np.array_equal(a, b)
+    _, _, traj = O.rollout(m, q0, qd0, tau, 1e-3, traj=True)
+    states = np.concatenate([np.r_[q0, qd0][None], traj[:-1]])
+    along = O.adjoint_along_params(m, states, tau, 1e-3, 2 * qT, qdT)
+    for a, b in zip(along[:5], ref[:5]):
+        assert np.array_equal(a, b)
