@@ -595,7 +595,13 @@ __device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const Li
         const V6<S> vp = (l.par >= 0) ? get6(xb, 0, l.par) : zero6<S>();
         t.v = p1_velocity(L, t, st.qd[0], vp);
       } else {
-        t.v = st_vel6(st);
+        // free root: the ABA runs in the inertial frame that moves with the
+        // root's current linear velocity (a Galilean shift, exact: joint
+        // accelerations and the root's angular acceleration do not change,
+        // its linear acceleration changes by w x v_lin, added back in pass 3).
+        // A fast-moving base (a long free fall) otherwise puts large
+        // cancelling terms into every link's bias force and acceleration.
+        t.v = v6<S>(st_vel6(st).a, zero3<S>());
       }
       put6(xb, 0, l.lane, t.v);
     }
@@ -632,6 +638,8 @@ __device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const Li
         put6(xb, 0, l.lane, p3_accel(L, t, ap));
       } else if constexpr (FREE) {
         root_accel(t.IA, t.pA, st_quat(st), g, t.ap, o.abase);
+        const V6<S> v = st_vel6(st);
+        o.abase.l = o.abase.l - cross(v.a, v.l);
         put6(xb, 0, l.lane, t.ap);
       }
     }
@@ -772,7 +780,11 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
       pb = v3<S>(xb1.q[0], xb1.q[1], xb1.q[2]);
       quatb.x = xb1.q[3]; quatb.y = xb1.q[4]; quatb.z = xb1.q[5]; quatb.w = xb1.q[6];
       vb6 = st_vel6(xb1);
-      qddb6 = integrate_root_adj(st_quat(st), st_vel6(st), o.abase, A.dt, pb, quatb, vb6);
+      const V6<S> v = st_vel6(st);
+      qddb6 = integrate_root_adj(st_quat(st), v, o.abase, A.dt, pb, quatb, vb6);
+      // the Galilean shift's term of the root acceleration, -w x v_lin
+      vb6.a = vb6.a + cross(qddb6.l, v.l);
+      vb6.l = vb6.l + cross(v.a, qddb6.l);
     }
   }
   Bar<S> b;
@@ -861,7 +873,8 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
         if (rev) {
           if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, joint_r(L, tp), vbar));
         } else if constexpr (FREE) {
-          vb6 = vb6 + vbar;
+          // the ABA saw the root velocity [w; 0]
+          vb6.a = vb6.a + vbar.a;
         }
       }
       wave_sync();

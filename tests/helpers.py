@@ -73,8 +73,12 @@ def emu():
                                                                   ("aba_lane.h", "spatial.h")]
         if not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(f) for f in srcs):
             import subprocess
+            # parallel test workers may rebuild at once: each writes its own
+            # file and renames it into place
+            tmp = f"{path}.{os.getpid()}.tmp"
             subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wno-unknown-pragmas",
-                                   "-o", path, os.path.join(HERE, "hostemu", "hostemu.cpp")])
+                                   "-o", tmp, os.path.join(HERE, "hostemu", "hostemu.cpp")])
+            os.replace(tmp, path)
         L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         L.emu_fd_d.argtypes = [ctypes.c_int] + [P] * 8

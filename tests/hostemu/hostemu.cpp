@@ -89,8 +89,9 @@ void fd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, Out<S>& o, S
       const V6<S> vp = s.parent[i] >= 0 ? o.t[s.parent[i]].v : zero6<S>();
       t.v = p1_velocity(L, t, qd[s.vi[i]], vp);
     } else {
+      // free root: the kernels' Galilean shift (the ABA sees [w; 0])
       const S* v = qd + s.vi[i];
-      t.v = v6<S>(v3<S>(v[0], v[1], v[2]), v3<S>(v[3], v[4], v[5]));
+      t.v = v6<S>(v3<S>(v[0], v[1], v[2]), zero3<S>());
     }
     p1_bias(L, t.v, s.jtype[i] != 1 ? qd[s.vi[i]] : S(0), s.jtype[i] != 1, t.c, t.pA, t.IA);
   }
@@ -115,6 +116,8 @@ void fd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, Out<S>& o, S
       qdd[s.vi[i]] = t.qdd;
     } else {
       root_accel(t.IA, t.pA, quat_of(q + s.qi[i]), v3<S>(s.g[0], s.g[1], s.g[2]), t.ap, o.abase);
+      const S* v = qd + s.vi[i];
+      o.abase.l = o.abase.l - cross(v3<S>(v[0], v[1], v[2]), v3<S>(v[3], v[4], v[5]));
       acc[i] = t.ap;
       const S a[6] = {o.abase.a.x, o.abase.a.y, o.abase.a.z, o.abase.l.x, o.abase.l.y, o.abase.l.z};
       for (int k = 0; k < 6; ++k) qdd[s.vi[i] + k] = a[k];
@@ -175,8 +178,10 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
       const S* y = qdb + s.vi[i];
       vb6 = v6<S>(v3<S>(y[0], y[1], y[2]), v3<S>(y[3], y[4], y[5]));
       const S* v = qd + s.vi[i];
-      qddb6 = integrate_root_adj(quat_of(q + s.qi[i]), v6<S>(v3<S>(v[0], v[1], v[2]), v3<S>(v[3], v[4], v[5])),
-                                 o.abase, dt, pb, quatb, vb6);
+      const V6<S> vv = v6<S>(v3<S>(v[0], v[1], v[2]), v3<S>(v[3], v[4], v[5]));
+      qddb6 = integrate_root_adj(quat_of(q + s.qi[i]), vv, o.abase, dt, pb, quatb, vb6);
+      vb6.a = vb6.a + cross(qddb6.l, vv.l);
+      vb6.l = vb6.l + cross(vv.a, qddb6.l);
     }
   }
   std::vector<V6<S>> ab(n, zero6<S>()), vb(n, zero6<S>()), pAb(n, zero6<S>());
@@ -202,7 +207,7 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
       const V6<S> up = r1_link(s.L[i], o.t[i], b[i], vb[i], pAb[i], qd[s.vi[i]]);
       if (s.parent[i] >= 0) vb[s.parent[i]] = vb[s.parent[i]] + up;
     } else {
-      vb6 = vb6 + r1_root(s.L[i], o.t[i].v, vb[i], pAb[i]);
+      vb6.a = vb6.a + r1_root(s.L[i], o.t[i].v, vb[i], pAb[i]).a;
     }
   }
   if (pg)

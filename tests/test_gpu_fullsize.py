@@ -21,10 +21,8 @@
 * Over 50 s the quadrupeds' exact gradients (FP64) grow to 1e40 - 1e70,
   beyond the FP32 range, because the adjoint of a chaotic rollout grows
   exponentially backward in time; the FP32 adjoint then overflows.  For such
-  systems the control gradient of the final 500 steps is compared: it
-  agrees to about 1e-3 (asserted below 5e-3) at the 450-490 m/s body-frame
-  base speed that 50 s of free fall reaches; over the final 2000 steps the
-  figure is printed, not asserted.
+  systems the control gradient of the final 500 steps is held to the FP32
+  bar; over the final 2000 steps the figure is printed.
 """
 import numpy as np
 import pytest
@@ -165,8 +163,6 @@ def _sampled_along(b, sample, K=1, extra_K=(), diverging=0):
                 worst_window = max(worst_window, *e)
             note = ""
             if not fits:
-                # reported, not asserted: over 2 s the adjoint grows 50-400x and
-                # amplifies FP32 round-off with it
                 note = " (last 2000 steps: %.1e)" % rel(g[2][-2000:, uo[i]:uo[i + 1]], ga[2][-2000:])
             print("system", i, f"({nvi} DOF), K={K2}:", "gradient error along the GPU trajectory" if fits else
                   f"exact gradient {size:.1e} beyond FP32; control-gradient error over the last {W} steps",
@@ -191,7 +187,6 @@ def test_full_size_quadrupeds_1024_sampled():
     worst_step, worst_grad, worst_window = _sampled_along(b, [0, 511, 1023], extra_K=(10, 100), diverging=2)
     assert worst_step < 1e-6
     assert worst_grad < TOL_GRAD_F32
-    # at the end of 50 s of free fall the base moves at 450-490 m/s in its own
-    # frame; there the FP32 control gradient of the final 0.5 s agrees with the
-    # FP64 adjoint along the same trajectory to about 1e-3 (measured 0.7 - 1.4e-3)
-    assert worst_window < 5e-3
+    # the final 0.5 s of control gradients, at the 450-490 m/s body-frame base
+    # speed that 50 s of free fall reaches, hold the FP32 bar
+    assert worst_window < TOL_GRAD_F32
