@@ -16,6 +16,7 @@ state of each step checkpointed and the step recomputed in the backward pass
 from __future__ import annotations
 
 import ctypes
+import weakref
 
 import numpy as np
 import torch
@@ -79,16 +80,20 @@ class Sim:
         N.check(L.sim_create(ctypes.byref(topo), ctypes.byref(prm),
                              N.SIM_F64 if dtype == torch.float64 else N.SIM_F32, ctypes.byref(h)))
         self._h = h
+        # released when the object is collected, or at interpreter exit while
+        # the ctypes library is still loaded
+        self._release = weakref.finalize(self, L.sim_destroy, h)
         info = N.SimInfo()
         N.check(L.sim_get_info(h, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in N.SimInfo._fields_}
         self.nq, self.nv, self.nu = info.nq, info.nv, info.nu
 
-    def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            N.lib().sim_destroy(h)
-            self._h = None
+    def close(self):
+        """Release the handle now (also done when the object is collected)."""
+        release = getattr(self, "_release", None)
+        if release is not None:
+            release()
+            self._h = ctypes.c_void_p()   # later calls see a null handle and fail cleanly
 
     # ------------------------------------------------------------------ checks
     def _t(self, x, n, name, allow_none=False):

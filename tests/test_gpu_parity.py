@@ -314,6 +314,25 @@ def test_invalid_calls_raise():
         sim.forward(q0, qd0, tau, b.dt, K=1, workspace=small)
 
 
+def test_closed_handle_fails_cleanly():
+    """close() releases the handle once; later calls report an error
+    instead of touching freed memory, and many short-lived handles leave the
+    library in a working state."""
+    from paper_2109_07719_amd._native import SimError
+    b = _batch("chain7_4096", 2, 10)
+    for _ in range(20):
+        _sim(b)
+    sim = _sim(b)
+    q0, qd0, tau = _t(b.q0), _t(b.qd0), _t(b.tau)
+    qT, _, _ = sim.forward(q0, qd0, tau, b.dt)
+    sim.close()
+    sim.close()
+    with pytest.raises(SimError):
+        sim.forward(q0, qd0, tau, b.dt)
+    qT2, _, _ = _sim(b).forward(q0, qd0, tau, b.dt)
+    assert torch.equal(qT, qT2)
+
+
 # ------------------------------------------------------------- full size
 
 def test_full_size_chain7_4096_sampled():
