@@ -404,7 +404,7 @@ def test_trajectory_optimisation_gradients_match_fp64_oracle():
         opt.opt.zero_grad()
         L, _ = opt.loss()
         L.backward()
-        losses.append(float(L))
+        losses.append(float(L.detach()))
         if it in (0, 6, 11):
             tau = opt.tau.detach().double().cpu().numpy()
             g = opt.tau.grad.detach().cpu().numpy()
