@@ -430,6 +430,40 @@ def pgs_bench(args, torch, dev):
     print(json.dumps(res))
 
 
+def fp64_leg(args, torch, dev, b, K, T, dt):
+    """The same rollouts with the FP64 handle (context for accuracy-critical
+    uses; not the headline): forward with checkpoints and adjoint, timed with
+    HIP events like the FP32 legs.  Skipped when the workspace would not
+    fit."""
+    from paper_2109_07719_amd.sim import Sim
+    sim = Sim(b.systems, b.gravity, dtype=torch.float64)
+    need = sim.workspace_bytes(T, K)
+    if K < 1 or need > 0.5 * torch.cuda.mem_get_info()[0]:
+        return {"skipped": f"needs {need / 2**30:.1f} GiB of workspace (K={K})"}
+    tune = sim.autotune(K=K, T_probe=min(T, 200)) if args.tiling == "auto" else None
+    f = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+    q0, qd0 = f(b.q0), f(b.qd0)
+    tau = torch.from_numpy(b.tau).to(dev).double()
+    ws = sim.new_workspace(T, K)
+    times = []
+    for k in range(args.warmup + args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        qT, qdT, _ = sim.forward(q0, qd0, tau, dt, K=K, workspace=ws)
+        e[1].record()
+        sim.backward(tau, dt, K, ws, 2 * qT, torch.zeros_like(qdT))
+        e[2].record()
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            times.append((e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])))
+    fw, bw = float(np.mean([t[0] for t in times])), float(np.mean([t[1] for t in times]))
+    del ws, tau
+    return {"fwd_adjoint_dof_steps_per_s": b.total_dof * T / ((fw + bw) * 1e-3), "fwd_kernel_ms": fw,
+            "adjoint_kernel_ms": bw, "tiling": sim.tiling, "autotune": tune,
+            "what": "the same rollouts in FP64 (the library's FP64 handle): the price of full accuracy, where the "
+                    "FP32 gradients of long or chaotic rollouts lose digits; not the headline value"}
+
+
 def trajopt_bench(args, torch, dev):
     """Trajectory optimisation: 2048 chains of 5-50 links, T=1000, Adam on
     tau; reports DOF-steps/s per iteration (forward+adjoint of every chain),
@@ -513,6 +547,7 @@ def main():
     ap.add_argument("--workload", default="chain7_4096", choices=sorted(WORKLOADS))
     ap.add_argument("--K", type=int, default=1, help="checkpoint interval")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 context leg")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--memory-sweep", action="store_true",
                     help="time forward+adjoint and record peak memory for K in 1,10,100 and store-all")
@@ -666,6 +701,8 @@ def main():
     graphs["bwd"].replay()
     torch.cuda.synchronize()
 
+    fp64 = None if args.no_fp64 else fp64_leg(args, torch, dev, b, K, T, dt)
+
     grads = (gq0.cpu().numpy(), gqd0.cpu().numpy(), gtau.cpu().numpy(), gparam.cpu().numpy(), gframe.cpu().numpy())
     finite = all(np.all(np.isfinite(g)) for g in grads) and bool(torch.isfinite(qT).all())
     nonfinite_outputs = sim.status()
@@ -704,6 +741,7 @@ def main():
                                         "what": "gradients with respect to every link's 10 inertial parameters "
                                                 "and its joint placement and axis (9) as well, summed over the "
                                                 "rollout"}, "fwd_adjoint_over_plain_fwd_time": value and plain_rate / value,
+           "fp64_handle": fp64,
            "peak_mem_bytes": int(peak_mem), "results_finite": finite, "nonfinite_outputs": nonfinite_outputs, "roofline": roofline,
            "wall_s_timed": wall, "input_gen_s": t_gen}
     if not args.no_cpu_baseline:
