@@ -472,7 +472,9 @@ def trajopt_bench(args, torch, dev):
 
     T = args.T or 1000
     b, targets = chains_problem(n_systems=2048, T=T)
-    opt = TrajOpt(b, targets, [s.n - 1 for s in b.systems], np.tile([0.5, 0, 0], (2048, 1)), K=args.K)
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    opt = TrajOpt(b, targets, [s.n - 1 for s in b.systems], np.tile([0.5, 0, 0], (2048, 1)), K=args.K,
+                  dtype=dtype)
     tune = opt.sim.autotune(K=args.K, T_probe=min(T, 200)) if args.tiling == "auto" else None
     checks = {0, args.trajopt // 2, args.trajopt - 1}
     losses, it_ms, spot = [], [], []
@@ -491,10 +493,10 @@ def trajopt_bench(args, torch, dev):
         opt.opt.step()
     torch.cuda.synchronize()
     ms = float(np.mean(it_ms[1:] if len(it_ms) > 1 else it_ms))
-    print(json.dumps({"metric": "fwd+adjoint DOF-steps/sec (FP32, 1 GPU) in trajectory optimisation",
+    print(json.dumps({"metric": f"fwd+adjoint DOF-steps/sec ({args.dtype.upper()}, 1 GPU) in trajectory optimisation",
                       "value": b.total_dof * T / (ms * 1e-3), "unit": "DOF-steps/s", "ms_per_iteration": ms,
                       "iterations": args.trajopt, "loss_first": losses[0], "loss_last": losses[-1],
-                      "loss_every_10": losses[::10], "fp64_spot_checks": spot, "dtype": "f32",
+                      "loss_every_10": losses[::10], "fp64_spot_checks": spot, "dtype": args.dtype,
                       "config": {"workload": WORKLOADS["chains_2048"], "systems": 2048, "dof": b.total_dof,
                                  "T": T, "K": args.K, "tiling": opt.sim.tiling, "autotune": tune}}))
 
@@ -548,6 +550,8 @@ def main():
     ap.add_argument("--K", type=int, default=1, help="checkpoint interval")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 context leg")
+    ap.add_argument("--dtype", choices=("f32", "f64"), default="f32",
+                    help="compute type of the trajectory-optimisation leg (the benchmark line is FP32)")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--memory-sweep", action="store_true",
                     help="time forward+adjoint and record peak memory for K in 1,10,100 and store-all")
