@@ -66,6 +66,17 @@ def _configure(L):
     L.orc_pgs_solve_c.restype = None
     L.orc_pgs_adjoint.argtypes = [I, I, P, P, P, P, P, P, P, P, P, P, P]
     L.orc_pgs_adjoint.restype = None
+    D = ctypes.c_double
+    L.orc_contact_assembly.argtypes = [P, P, P, P, P, P, P]
+    L.orc_contact_assembly.restype = I
+    L.orc_step_contact.argtypes = [P, P, P, P, P, D, P, P, P]
+    L.orc_step_contact.restype = I
+    L.orc_step_contact_c.argtypes = [P, P, P, P, P, D, P, P]
+    L.orc_step_contact_c.restype = I
+    L.orc_rollout_contact.argtypes = [P, P, P, P, P, D, I, P, P, P, P]
+    L.orc_rollout_contact.restype = I
+    L.orc_rollout_contact_grad.argtypes = [P, P, P, P, P, D, I, P, P, P, P, P]
+    L.orc_rollout_contact_grad.restype = I
     return L
 
 
@@ -345,3 +356,82 @@ def pgs_adjoint(A, b, lo, hi, sweeps, xbar):
     lib().orc_pgs_adjoint(n, niter, _p(A), _p(b), _p(lo), _p(hi), _p(sw), _p(xbar), _p(Ab), _p(bb), _p(lb),
                           _p(hb), _p(x0b))
     return Ab, bb, lb, hb, x0b
+
+
+# ---------------------------------------------------------------- contact in the step
+
+class _CContacts(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("link", ctypes.c_void_p), ("center", ctypes.c_void_p),
+                ("radius", ctypes.c_void_p), ("mu", ctypes.c_double), ("beta", ctypes.c_double),
+                ("niter", ctypes.c_int)]
+
+
+class Contacts:
+    """Contact spheres against the ground plane y = 0 (contact.inc): per
+    sphere its link, centre (link coordinates) and radius; box friction mu,
+    Baumgarte factor beta, PGS sweeps niter per solve."""
+
+    def __init__(self, link, center, radius, mu=0.5, beta=0.0, niter=50):
+        self.link = np.ascontiguousarray(np.asarray(link, dtype=np.int32).reshape(-1))
+        self.n = int(self.link.size)
+        self.center = np.ascontiguousarray(np.asarray(center, dtype=np.float64).reshape(self.n, 3))
+        self.radius = np.ascontiguousarray(np.asarray(radius, dtype=np.float64).reshape(self.n))
+        self.c = _CContacts(self.n, _p(self.link), _p(self.center), _p(self.radius), float(mu), float(beta),
+                            int(niter))
+        self.ref = ctypes.byref(self.c)
+
+
+def contact_assembly(m: Model, C: Contacts, q):
+    """Active contacts, gaps, J [3m, nv] and M^-1 J^T [nv, 3m] at q."""
+    q = _f64(q, m.nq)
+    cap = max(C.n, 1)
+    act, phi = np.zeros(cap, np.int32), np.zeros(cap)
+    J, MJ = np.zeros(3 * cap * m.nv), np.zeros(3 * cap * m.nv)
+    na = lib().orc_contact_assembly(m.ref, C.ref, _p(q), _p(act), _p(phi), _p(J), _p(MJ))
+    return act[:na], phi[:na], J[:3 * na * m.nv].reshape(3 * na, m.nv), MJ[:3 * na * m.nv].reshape(m.nv, 3 * na)
+
+
+def step_contact(m: Model, C: Contacts, q, qd, tau, dt):
+    """One step with contact: returns q1, qd1, the active-contact count and
+    their impulses [3m] (normal, tangent x, tangent z per contact)."""
+    q, qd, tau = _f64(q, m.nq), _f64(qd, m.nv), _f64(tau, m.nu)
+    q1, qd1, lam = np.zeros(m.nq), np.zeros(m.nv), np.zeros(3 * max(C.n, 1))
+    na = lib().orc_step_contact(m.ref, C.ref, _p(q), _p(qd), _p(tau), float(dt), _p(q1), _p(qd1), _p(lam))
+    return q1, qd1, na, lam[:3 * na]
+
+
+def step_contact_complex(m: Model, C: Contacts, q, qd, tau, dt):
+    q, qd, tau = _c128(q, m.nq), _c128(qd, m.nv), _c128(tau, m.nu)
+    q1, qd1 = np.zeros(m.nq, np.complex128), np.zeros(m.nv, np.complex128)
+    lib().orc_step_contact_c(m.ref, C.ref, _p(q), _p(qd), _p(tau), float(dt), _p(q1), _p(qd1))
+    return q1, qd1
+
+
+def rollout_contact(m: Model, C: Contacts, q0, qd0, tau, dt, traj: bool = False):
+    """Rollout with contact; returns qT, qdT, the per-step active-contact
+    counts, and with traj=True the states x^{t+1} [T, nq+nv]."""
+    tau = np.ascontiguousarray(np.asarray(tau, dtype=np.float64).reshape(-1, m.nu) if m.nu else
+                               np.zeros((np.asarray(tau).shape[0], 0)))
+    T = tau.shape[0]
+    q0, qd0 = _f64(q0, m.nq), _f64(qd0, m.nv)
+    qT, qdT, nc = np.zeros(m.nq), np.zeros(m.nv), np.zeros(T, np.int32)
+    tr = np.zeros((T, m.nq + m.nv)) if traj else None
+    rc = lib().orc_rollout_contact(m.ref, C.ref, _p(q0), _p(qd0), _p(tau), float(dt), T, _p(qT), _p(qdT),
+                                   _p(tr) if traj else None, _p(nc))
+    if rc != 0:
+        raise RuntimeError("orc_rollout_contact failed")
+    return (qT, qdT, nc, tr) if traj else (qT, qdT, nc)
+
+
+def rollout_contact_grad(m: Model, C: Contacts, q0, qd0, tau, dt, gqT, gqdT):
+    """Gradient of <gqT, qT> + <gqdT, qdT> through a rollout with contact:
+    returns gq0, gqd0, gtau [T, nu]."""
+    tau = np.ascontiguousarray(np.asarray(tau, dtype=np.float64).reshape(-1, m.nu))
+    T = tau.shape[0]
+    q0, qd0, gqT, gqdT = _f64(q0, m.nq), _f64(qd0, m.nv), _f64(gqT, m.nq), _f64(gqdT, m.nv)
+    gq0, gqd0, gtau = np.zeros(m.nq), np.zeros(m.nv), np.zeros((T, m.nu))
+    rc = lib().orc_rollout_contact_grad(m.ref, C.ref, _p(q0), _p(qd0), _p(tau), float(dt), T, _p(gqT), _p(gqdT),
+                                        _p(gq0), _p(gqd0), _p(gtau))
+    if rc != 0:
+        raise RuntimeError("orc_rollout_contact_grad failed")
+    return gq0, gqd0, gtau

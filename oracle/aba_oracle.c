@@ -44,7 +44,10 @@ int orc_nu(const orc_model *m) {
 #define SCOS cos
 #define SSQRT sqrt
 #define SREAL(x) (x)
+#define PGS_SOLVE(n, it, A, b, lo, hi, x0, x) orc_pgs_solve((n), (it), (A), (b), (lo), (hi), (x0), (x), NULL)
 #include "aba_fwd.inc"
+#include "contact.inc"
+#undef PGS_SOLVE
 #undef S
 #undef FN
 #undef SSIN
@@ -60,7 +63,10 @@ int orc_nu(const orc_model *m) {
 #define SCOS ccos
 #define SSQRT csqrt
 #define SREAL(x) creal(x)
+#define PGS_SOLVE(n, it, A, b, lo, hi, x0, x) orc_pgs_solve_c((n), (it), (A), (b), (lo), (hi), (x0), (x))
 #include "aba_fwd.inc"
+#include "contact.inc"
+#undef PGS_SOLVE
 #undef S
 #undef FN
 #undef SSIN
@@ -841,4 +847,91 @@ int orc_adjoint_along(const orc_model *m, const double *states, const double *ta
                       double dt, int T, const double *gqT, const double *gqdT,
                       const double *gtraj, double *gq0, double *gqd0, double *gtau) {
   return orc_adjoint_along_params(m, states, tau, dt, T, gqT, gqdT, gtraj, gq0, gqd0, gtau, NULL, NULL);
+}
+
+/* ---- contact (contact.inc) --------------------------------------------- */
+
+int orc_contact_assembly(const orc_model *m, const orc_contacts *C, const double *q, int *act, double *phi,
+                         double *J, double *MJ) {
+  return contact_assembly_r(m, C, q, act, phi, J, MJ);
+}
+
+int orc_step_contact(const orc_model *m, const orc_contacts *C, const double *q, const double *qd,
+                     const double *tau, double dt, double *q1, double *qd1, double *lam) {
+  return step_contact_r(m, C, q, qd, tau, dt, q1, qd1, lam);
+}
+
+int orc_step_contact_c(const orc_model *m, const orc_contacts *C, const void *q, const void *qd, const void *tau,
+                       double dt, void *q1, void *qd1) {
+  return step_contact_c(m, C, (const double complex *)q, (const double complex *)qd,
+                        (const double complex *)tau, dt, (double complex *)q1, (double complex *)qd1, NULL);
+}
+
+int orc_rollout_contact(const orc_model *m, const orc_contacts *C, const double *q0, const double *qd0,
+                        const double *tau, double dt, int T, double *qT, double *qdT, double *traj, int *n_contacts) {
+  if (T < 0) return -1;
+  const int nq = orc_nq(m), nv = orc_nv(m), nu = orc_nu(m);
+  double *x = (double *)malloc(sizeof(double) * (size_t)(2 * (nq + nv)));
+  if (!x) return -1;
+  double *x1 = x + nq + nv;
+  memcpy(x, q0, sizeof(double) * nq);
+  memcpy(x + nq, qd0, sizeof(double) * nv);
+  for (int t = 0; t < T; ++t) {
+    const int na = step_contact_r(m, C, x, x + nq, tau + (size_t)t * nu, dt, x1, x1 + nq, NULL);
+    if (n_contacts) n_contacts[t] = na;
+    memcpy(x, x1, sizeof(double) * (nq + nv));
+    if (traj) memcpy(traj + (size_t)t * (nq + nv), x, sizeof(double) * (nq + nv));
+  }
+  memcpy(qT, x, sizeof(double) * nq);
+  memcpy(qdT, x + nq, sizeof(double) * nv);
+  free(x);
+  return 0;
+}
+
+/* Gradient of a loss on the final state through a rollout with contact:
+ * the step map's exact derivative (complex step, h = 1e-30, one input
+ * direction at a time, at the stored states) applied in reverse time
+ * (Eq. adj_r).  Valid where no contact switches on or off and no solver
+ * bound changes activity under an infinitesimal change, i.e. away from the
+ * kinks of the piecewise-smooth step map. */
+int orc_rollout_contact_grad(const orc_model *m, const orc_contacts *C, const double *q0, const double *qd0,
+                             const double *tau, double dt, int T, const double *gqT, const double *gqdT,
+                             double *gq0, double *gqd0, double *gtau) {
+  if (T < 0) return -1;
+  const int nq = orc_nq(m), nv = orc_nv(m), nu = orc_nu(m), nx = nq + nv;
+  double *xs = (double *)malloc(sizeof(double) * (size_t)(T + 1) * nx);
+  double complex *xc = (double complex *)malloc(sizeof(double complex) * (size_t)(nx + nu));
+  double *xb = (double *)malloc(sizeof(double) * (size_t)(2 * nx));
+  if (!xs || !xc || !xb) { free(xs); free(xc); free(xb); return -1; }
+  memcpy(xs, q0, sizeof(double) * nq);
+  memcpy(xs + nq, qd0, sizeof(double) * nv);
+  for (int t = 0; t < T; ++t) {
+    double *cur = xs + (size_t)t * nx, *nxt = cur + nx;
+    step_contact_r(m, C, cur, cur + nq, tau + (size_t)t * nu, dt, nxt, nxt + nq, NULL);
+  }
+  double *xb1 = xb + nx;
+  memcpy(xb, gqT, sizeof(double) * nq);
+  memcpy(xb + nq, gqdT, sizeof(double) * nv);
+  const double h = 1e-30;
+  double complex *in = xc, *uc = xc + nx;
+  double complex out1[nx];
+  for (int t = T - 1; t >= 0; --t) {
+    const double *cur = xs + (size_t)t * nx;
+    for (int j = 0; j < nx + nu; ++j) {
+      for (int k = 0; k < nx; ++k) in[k] = cur[k];
+      for (int k = 0; k < nu; ++k) uc[k] = tau[(size_t)t * nu + k];
+      if (j < nx) in[j] += I * h;
+      else uc[j - nx] += I * h;
+      step_contact_c(m, C, in, in + nq, uc, dt, out1, out1 + nq, NULL);
+      double s = 0;
+      for (int k = 0; k < nx; ++k) s += xb[k] * cimag(out1[k]) / h;
+      if (j < nx) xb1[j] = s;
+      else gtau[(size_t)t * nu + (j - nx)] = s;
+    }
+    memcpy(xb, xb1, sizeof(double) * nx);
+  }
+  memcpy(gq0, xb, sizeof(double) * nq);
+  memcpy(gqd0, xb + nq, sizeof(double) * nv);
+  free(xs); free(xc); free(xb);
+  return 0;
 }

@@ -155,6 +155,40 @@ int orc_adjoint_along_params(const orc_model *m, const double *states, const dou
                              const double *gtraj, double *gq0, double *gqd0, double *gtau,
                              double *gparam, double *gframe);
 
+/* ---- contact resolution inside a step (contact.inc) -----------------
+ * Contact spheres against the ground plane y = 0 (see contact.inc for the
+ * model): link[k], centre[k][3] in link coordinates, radius[k]; box
+ * friction coefficient mu; Baumgarte factor beta on the gap; PGS sweeps
+ * niter for each of the two solves. */
+typedef struct {
+  int n;
+  const int *link;
+  const double *center;
+  const double *radius;
+  double mu, beta;
+  int niter;
+} orc_contacts;
+
+/* Detection and assembly at q: active contacts act[], gaps phi[], J
+ * ([3m][nv], rows normal e_y, tangents e_x, e_z per contact) and M^-1 J^T
+ * ([nv][3m]); returns m.  Arrays sized for C->n contacts. */
+int orc_contact_assembly(const orc_model *m, const orc_contacts *C, const double *q, int *act, double *phi,
+                         double *J, double *MJ);
+/* One step with contact resolution; returns the number of active contacts,
+ * lam (nullable, [3 C->n]) their impulses.  _c: complex inputs. */
+int orc_step_contact(const orc_model *m, const orc_contacts *C, const double *q, const double *qd,
+                     const double *tau, double dt, double *q1, double *qd1, double *lam);
+int orc_step_contact_c(const orc_model *m, const orc_contacts *C, const void *q, const void *qd, const void *tau,
+                       double dt, void *q1, void *qd1);
+/* Rollout with contact (traj, n_contacts nullable: [T][nq+nv], [T]). */
+int orc_rollout_contact(const orc_model *m, const orc_contacts *C, const double *q0, const double *qd0,
+                        const double *tau, double dt, int T, double *qT, double *qdT, double *traj, int *n_contacts);
+/* Gradient of <gqT, qT> + <gqdT, qdT> through a rollout with contact (the
+ * step map's exact derivative by complex step, in reverse time). */
+int orc_rollout_contact_grad(const orc_model *m, const orc_contacts *C, const double *q0, const double *qd0,
+                             const double *tau, double dt, int T, const double *gqT, const double *gqdT,
+                             double *gq0, double *gqd0, double *gtau);
+
 /* ---- contact solver (pgs_oracle.c) ---------------------------------
  * Projected Gauss-Seidel on the MLCP a = A x + b, lo <= x <= hi (Sec. 4.1,
  * Eq. mlcp; App. C), n rows, niter sweeps from x0; A is [n][n] row-major.

@@ -12,6 +12,7 @@ import subprocess
 import pytest
 
 import oracle as O
+import test_oracle_contact as contact
 import test_oracle_pgs as pgs
 import test_oracle_pins as pins
 
@@ -24,7 +25,7 @@ MUTATIONS = [
     ("aba_fwd.inc", "S s_ = l->pA[r] + Iac[r];", "S s_ = l->pA[r];", "dropped I^a c term"),
     ("aba_fwd.inc", "FN(mat6_mul)(XT_, l->Ia, T1);\n      FN(mat6_mul)(T1, l->X, T2);",
      "FN(mat6_mul)(l->X, l->Ia, T1);\n      FN(mat6_mul)(T1, XT_, T2);", "transposed congruence"),
-    ("aba_fwd.inc", "q1[qi[i]] = q[qi[i]] + dt * qd1[vi[i]];", "q1[qi[i]] = q[qi[i]] + dt * qd[vi[i]];",
+    ("aba_fwd.inc", "FN(integrate_pos)(m, q, qd1, dt, q1);", "FN(integrate_pos)(m, q, qd, dt, q1);",
      "explicit instead of semi-implicit Euler"),
     ("aba_fwd.inc", "l->abase[k + 3] = l->ap[k + 3] + Eg[k];", "l->abase[k + 3] = l->ap[k + 3] - Eg[k];",
      "free-root gravity sign"),
@@ -79,8 +80,8 @@ MUTATIONS = [
     ("aba_fwd.inc", "for (int k = 0; k < 3; ++k) { l->vJ[k] = qd[vi[i] + k]; l->vJ[k + 3] = 0; }",
      "for (int k = 0; k < 3; ++k) { l->vJ[k] = 0; l->vJ[k + 3] = qd[vi[i] + k]; }", "ball-joint velocity as a translation"),
     ("aba_fwd.inc", "Di[1] = -(b * k - c * h) / det;", "Di[1] = (b * k - c * h) / det;", "3x3 inverse cofactor sign"),
-    ("aba_fwd.inc", "FN(quat_step)(q + qi[i], w1, dt, q1 + qi[i]);", "FN(quat_step)(q + qi[i], qd + vi[i], dt, q1 + qi[i]);",
-     "ball joint turned by the old angular velocity"),
+    ("aba_fwd.inc", "FN(quat_step)(q + qi[i], qd1 + vi[i], dt, q1 + qi[i]);",
+     "FN(quat_step)(q + qi[i], qd1 + vi[i], 0.5 * dt, q1 + qi[i]);", "ball joint turned by half a step"),
     ("aba_oracle.c", "Rbar[3 * c + r] = XJb[6 * r + c] + XJb[6 * (3 + r) + 3 + c];",
      "Rbar[3 * r + c] = XJb[6 * r + c] + XJb[6 * (3 + r) + 3 + c];", "ball-joint rotation adjoint transposed"),
     ("aba_oracle.c", "quat_step_vjp(qt, w1, dt, q1bar + qi[i], qbar + qi[i], w1bar);",
@@ -88,6 +89,20 @@ MUTATIONS = [
      "ball-joint orientation adjoint at the old angular velocity"),
     ("aba_oracle.c", "qddbar[vi[i] + k] = dt * w1bar[k];", "qddbar[vi[i] + k] = w1bar[k];",
      "ball-joint integrator adjoint without dt"),
+    ("contact.inc", "dirs[3] = {1, 0, 2};", "dirs[3] = {0, 1, 2};", "contact normal along x"),
+    ("contact.inc", "cl[3 * na + a] = c[a] - C->radius[k] * Ew[9 * l + 3 * a + 1];",
+     "cl[3 * na + a] = c[a] + C->radius[k] * Ew[9 * l + 3 * a + 1];", "contact point at the sphere's top"),
+    ("contact.inc", "fe[0] = cl[3 * c + 1] * f[2] - cl[3 * c + 2] * f[1];",
+     "fe[0] = cl[3 * c + 2] * f[1] - cl[3 * c + 1] * f[2];", "contact moment arm sign"),
+    ("contact.inc", "C->beta / dt * phi[i / 3]", "-C->beta / dt * phi[i / 3]", "Baumgarte sign"),
+    ("contact.inc", "lok[i] = -C->mu * lamn[ri / 3];\n        hik[i] = C->mu * lamn[ri / 3];",
+     "lok[i] = -C->mu;\n        hik[i] = C->mu;", "friction box not scaled by the normal impulse"),
+    ("contact.inc", "s_ += J[(size_t)i * nv + k] * qd1[k];", "s_ += J[(size_t)i * nv + k] * qd[k];",
+     "contact velocity before the smooth update"),
+    ("contact.inc", "> 1e-12 * dmax) keep[nk++] = i;", ">= 0) keep[nk++] = i;", "zero rows kept in the solve"),
+    ("aba_oracle.c", "    const double *cur = xs + (size_t)t * nx;\n    for (int j = 0; j < nx + nu; ++j) {",
+     "    const double *cur = xs + (size_t)(t + 1) * nx;\n    for (int j = 0; j < nx + nu; ++j) {",
+     "contact step Jacobian at the step's output state"),
 ]
 
 PINS = [
@@ -118,12 +133,18 @@ PINS = [
     lambda: pgs.test_adjoint_against_complex_step(3, 12),
     lambda: pgs.test_adjoint_against_complex_step(9, 2),
     pgs.test_adjoint_of_the_converged_linear_solve,
+    contact.test_frictionless_ball_impact_closed_form,
+    lambda: contact.test_sliding_point_mass_friction(2.0, 0.001),
+    contact.test_assembly_against_newton_euler_kinematics_and_mass_matrix,
+    contact.test_struck_pendulum_impulse_is_the_effective_mass_law,
+    contact.test_baumgarte_pushes_out_at_beta_phi_over_dt,
+    lambda: contact.test_rollout_gradient_with_contact_central_differences(0.8),
 ]
 
 
 @pytest.mark.parametrize("fname,old,new,what", MUTATIONS, ids=[m[3] for m in MUTATIONS])
 def test_pins_catch_planted_mistake(tmp_path, fname, old, new, what):
-    for f in ("aba_oracle.c", "aba_fwd.inc", "oracle.h", "pgs_oracle.c"):
+    for f in ("aba_oracle.c", "aba_fwd.inc", "contact.inc", "oracle.h", "pgs_oracle.c"):
         shutil.copy(os.path.join(SRC, f), tmp_path / f)
     path = tmp_path / fname
     text = path.read_text()
