@@ -359,6 +359,79 @@ int sim_pgs_adjoint(int dtype, int batch, int n, int niter, const void *A, const
                     size_t workspace_bytes, void *Abar, void *bbar, void *lobar, void *hibar,
                     void *x0bar, void *stream);
 
+/* ---- contact inside the step ----------------------------------------------
+ * Rollouts with collision detection and contact resolution between the
+ * dynamics and the integrator (Sec. 4.1 "Collision resolution": detection,
+ * then the MLCP of Eq. mlcp solved by projected Gauss-Seidel), and their
+ * gradient, for a batch of systems that share one topology and one set of
+ * contact spheres (per-system parameters).
+ *
+ * Contact model: spheres fixed in links against the ground plane y = 0; a
+ * sphere with centre height below its radius (gap phi < 0) is active.  Per
+ * active contact three rows (normal e_y, tangents e_x, e_z) of J, the world
+ * velocity of the sphere's lowest point; A = J M^-1 J^T, b = J qd_minus +
+ * (beta/dt) phi on the normal rows, qd_minus = qd + dt qdd.  niter PGS sweeps
+ * from zero solve the normal rows with lambda_n >= 0, then niter sweeps solve
+ * all rows with each tangent boxed by +-mu times that contact's first normal
+ * impulse; rows with A_ii = 0 take no impulse.  qd1 = qd_minus +
+ * M^-1 J^T lambda; positions move with qd1 (a free root: p1 = p + dt R v1_lin
+ * and quat1 = normalize(quat + dt/2 quat (x) (w1, 0)); 1-dof joints:
+ * q1 = q + dt qd1).
+ *
+ * Model (host memory, read during the call only): n links in topological
+ * order, parent[0] = -1, 0 <= parent[i] < i; jtype SIM_JOINT_REVOLUTE or
+ * SIM_JOINT_PRISMATIC, SIM_JOINT_FREE only for link 0; ncontacts spheres on
+ * links contact_link[]; gravity (world); mu, beta >= 0; niter >= 0.
+ *
+ * Per-system parameters (DEVICE, dtype, [nparams][batch], entry k of
+ * system s at k * batch + s): per link i at 25 i: E_T (9, row-major, parent
+ * -> joint frame), r_T (3, joint origin in the parent frame), axis (3, any
+ * nonzero length: the joint moves along axis / |axis|), mass, com (3, link
+ * frame), inertia about the com (xx, yy, zz, xy, xz, yz); then per sphere k
+ * at 25 n + 4 k: centre (3, link frame), radius.
+ *
+ * States are DEVICE arrays of the dtype, entry-major: q [nq][batch], qd
+ * [nv][batch], tau [T][nu][batch]; a free root's q is (p_world, quat x, y,
+ * z, w), its qd the body-frame (w, v).  Calls only enqueue work on `stream`
+ * (NULL = default): no allocation, no synchronisation.  Errors:
+ * SIM_ERR_INVALID_ARG, SIM_ERR_INVALID_TOPOLOGY, SIM_ERR_UNSUPPORTED_DTYPE,
+ * SIM_ERR_HIP; sim_last_error() describes the failure. */
+#define SIM_CONTACT_MAX_LINKS 16
+#define SIM_CONTACT_MAX_SPHERES 4
+
+typedef struct {
+  int n;
+  const int *parent;
+  const int *jtype;
+  int ncontacts;
+  const int *contact_link;
+  double mu, beta;
+  int niter;
+  double gravity[3];
+} sim_contact_model;
+
+/* Sizes of the model's state, control and parameter vectors (each output
+ * nullable). */
+int sim_contact_param_count(const sim_contact_model *m, int *nq, int *nv, int *nu, int *nparams);
+
+/* T steps with contact from (q0, qd0).  Writes qT, qdT; traj (nullable)
+ * receives x_0 .. x_T as [T + 1][nq + nv][batch] (q then qd per state, the
+ * input of sim_contact_rollout_grad); ncontacts (nullable, DEVICE int
+ * [T][batch]) the active-contact count of every step. */
+int sim_contact_rollout(const sim_contact_model *m, int dtype, int batch, const void *params, const void *q0,
+                        const void *qd0, const void *tau, double dt, int T, void *traj, void *qT, void *qdT,
+                        int *ncontacts, void *stream);
+
+/* Gradient of L = <gqT, qT> + <gqdT, qdT> through the rollout whose states
+ * traj [T + 1][nq + nv][batch] sim_contact_rollout wrote (same model,
+ * params, tau, dt): the reverse recursion x_bar_t = (dx_{t+1}/dx_t)^T
+ * x_bar_{t+1}, tau_bar_t = (dx_{t+1}/dtau_t)^T x_bar_{t+1} with each step's
+ * exact Jacobian at the stored state (detection, row and clamp decisions as
+ * taken).  Writes gq0 [nq][batch], gqd0 [nv][batch], gtau [T][nu][batch]. */
+int sim_contact_rollout_grad(const sim_contact_model *m, int dtype, int batch, const void *params, const void *traj,
+                             const void *tau, double dt, int T, const void *gqT, const void *gqdT, void *gq0,
+                             void *gqd0, void *gtau, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,7 @@ UNITS = [
     ("abadj_kernels_chain.hip", []),
     ("abadj_runtime.hip", []),
     ("pgs.hip", []),
+    ("contact.hip", []),
 ]
 SOURCES = [os.path.join(CSRC, u) for u, _ in UNITS]
 

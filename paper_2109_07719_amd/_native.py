@@ -28,7 +28,8 @@ EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_status", "sim_get_
             "sim_workspace_bytes",
             "sim_checkpoint_schedule", "sim_forward", "sim_forward_jvp",
             "sim_backward", "sim_aba", "sim_flops", "sim_last_error",
-            "sim_pgs_workspace_bytes", "sim_pgs_solve", "sim_pgs_adjoint")
+            "sim_pgs_workspace_bytes", "sim_pgs_solve", "sim_pgs_adjoint",
+            "sim_contact_param_count", "sim_contact_rollout", "sim_contact_rollout_grad")
 SIM_PGS_MAX_ROWS = 16
 
 
@@ -106,6 +107,13 @@ def lib():
         L.sim_aba.restype = I
         L.sim_flops.argtypes = [P, I, ctypes.POINTER(D)]
         L.sim_flops.restype = I
+        L.sim_contact_param_count.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                                              ctypes.POINTER(I)]
+        L.sim_contact_param_count.restype = I
+        L.sim_contact_rollout.argtypes = [P, I, I, P, P, P, P, D, I, P, P, P, P, P]
+        L.sim_contact_rollout.restype = I
+        L.sim_contact_rollout_grad.argtypes = [P, I, I, P, P, P, D, I, P, P, P, P, P, P]
+        L.sim_contact_rollout_grad.restype = I
         L.sim_last_error.argtypes = []
         L.sim_last_error.restype = ctypes.c_char_p
         _lib = L

@@ -1,0 +1,264 @@
+// Collision detection and contact resolution inside the time step
+// (Sec. 4.1 "Collision resolution": detection and an MLCP solved by
+// projected Gauss-Seidel between the dynamics and the integrator), batched
+// over systems of one topology, and the gradient of a rollout through
+// contact.
+//
+// Contact model: spheres fixed in links against the ground plane y = 0.
+//   - a sphere is active when its centre is lower than its radius (gap
+//     phi = centre_y - radius < 0);
+//   - per active contact three rows (normal e_y, tangents e_x, e_z) of J,
+//     the world velocity of the sphere's lowest point as a point of its
+//     link;
+//   - impulses lambda solve a = A lambda + b with A = J M^-1 J^T and
+//     b = J qd_minus + (beta/dt) phi on the normal rows, qd_minus = qd +
+//     dt qdd: first the normal rows alone with lambda_n >= 0, then all rows
+//     with the tangents boxed by +-mu times those first normal impulses;
+//     a row with A_ii = 0 (no joint moves the point along it) is left out;
+//   - qd1 = qd_minus + M^-1 J^T lambda; the positions then move with qd1
+//     (p1 = p + dt R v_lin1 and the normalised quaternion step for a free
+//     root, q1 = q + dt qd1 for 1-dof joints).
+//
+// Design: the forward runs one lane per system and keeps the whole tree's
+// articulated quantities in the lane's private memory.  J comes from the
+// world poses and joint axes along the contact link's path to the root;
+// each column of M^-1 J^T is the articulated-body response to a unit force
+// at the contact point (passes 2 and 3 of the ABA with the factorisation
+// of the step's own pass 2 reused, no velocity or gravity terms).  The
+// gradient runs one 64-lane wave per system: lane j reruns the step from
+// the stored state in dual numbers seeded along input j (state entry or
+// control), which gives column j of the step's Jacobian exactly (clamp and
+// detection decisions as taken), and the reverse recursion
+// x_bar_t = J_t^T x_bar_{t+1} is a dot product per lane with x_bar shared
+// through LDS.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/abadj.h"
+#include "abadj_internal.h"
+#include "contact_step.h"
+
+namespace {
+
+using aba::Dual;
+using namespace aba_contact;
+
+// ---- kernels ---------------------------------------------------------------
+
+constexpr int kBlock = 64;
+
+template <typename R>
+struct RollArgs {
+  CTopo tp;
+  int B, T;
+  R dt;
+  const R* P;     // [np][B]
+  const R* q0;    // [nq][B]
+  const R* qd0;   // [nv][B]
+  const R* tau;   // [T][nu][B]
+  R* traj;        // nullable: [T + 1][nq + nv][B]
+  R* qT;          // [nq][B]
+  R* qdT;         // [nv][B]
+  int* ncont;     // nullable: [T][B]
+};
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_contact_rollout(RollArgs<R> a) {
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= a.B) return;
+  const CTopo& tp = a.tp;
+  const size_t B = (size_t)a.B;
+  const Par<R> P{a.P, B, s};
+  const int nq = tp.nq, nv = tp.nv, nu = tp.nu, nx = nq + nv;
+  R x[2][kNX], u[kNL];
+  for (int k = 0; k < nq; ++k) x[0][k] = a.q0[k * B + s];
+  for (int k = 0; k < nv; ++k) x[0][nq + k] = a.qd0[k * B + s];
+  if (a.traj)
+    for (int k = 0; k < nx; ++k) a.traj[k * B + s] = x[0][k];
+  Work<R> w;
+  int cur = 0;
+  for (int t = 0; t < a.T; ++t) {
+    for (int k = 0; k < nu; ++k) u[k] = a.tau[((size_t)t * nu + k) * B + s];
+    const int na = contact_step(tp, P, x[cur], x[cur] + nq, u, a.dt, x[cur ^ 1], x[cur ^ 1] + nq, w);
+    cur ^= 1;
+    if (a.ncont) a.ncont[(size_t)t * B + s] = na;
+    if (a.traj)
+      for (int k = 0; k < nx; ++k) a.traj[((size_t)(t + 1) * nx + k) * B + s] = x[cur][k];
+  }
+  for (int k = 0; k < nq; ++k) a.qT[k * B + s] = x[cur][k];
+  for (int k = 0; k < nv; ++k) a.qdT[k * B + s] = x[cur][nq + k];
+}
+
+template <typename R>
+struct GradArgs {
+  CTopo tp;
+  int B, T;
+  R dt;
+  const R* P;     // [np][B]
+  const R* traj;  // [T + 1][nq + nv][B] from the rollout
+  const R* tau;   // [T][nu][B]
+  const R* gqT;   // [nq][B]
+  const R* gqdT;  // [nv][B]
+  R* gq0;         // [nq][B]
+  R* gqd0;        // [nv][B]
+  R* gtau;        // [T][nu][B]
+};
+
+// one wave per system; lane j < nx + nu owns Jacobian column j
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_contact_grad(GradArgs<R> a) {
+  using D = Dual<R>;
+  const int s = blockIdx.x, j = threadIdx.x;
+  const CTopo& tp = a.tp;
+  const size_t B = (size_t)a.B;
+  const Par<R> P{a.P, B, s};
+  const int nq = tp.nq, nv = tp.nv, nu = tp.nu, nx = nq + nv;
+  __shared__ R xb[kNX];
+  if (j < nq) xb[j] = a.gqT[j * B + s];
+  else if (j < nx) xb[j] = a.gqdT[(j - nq) * B + s];
+  __syncthreads();
+  Work<D> w;
+  for (int t = a.T - 1; t >= 0; --t) {
+    R sj = R(0);
+    if (j < nx + nu) {
+      D x[kNX], x1[kNX], u[kNL];
+      for (int k = 0; k < nx; ++k) x[k] = D(a.traj[((size_t)t * nx + k) * B + s], R(k == j ? 1 : 0));
+      for (int k = 0; k < nu; ++k) u[k] = D(a.tau[((size_t)t * nu + k) * B + s], R(nx + k == j ? 1 : 0));
+      contact_step(tp, P, x, x + nq, u, a.dt, x1, x1 + nq, w);
+      for (int k = 0; k < nx; ++k) sj += xb[k] * x1[k].d;
+    }
+    __syncthreads();
+    if (j < nx) xb[j] = sj;
+    else if (j < nx + nu) a.gtau[((size_t)t * nu + (j - nx)) * B + s] = sj;
+    __syncthreads();
+  }
+  if (j < nq) a.gq0[j * B + s] = xb[j];
+  else if (j < nx) a.gqd0[(j - nq) * B + s] = xb[j];
+}
+
+int cfail(int code, const std::string& msg) { return aba::report_error(code, msg); }
+
+int make_topo(const char* who, const sim_contact_model* m, CTopo* tp) {
+  if (!m || !m->parent || !m->jtype || (m->ncontacts > 0 && !m->contact_link))
+    return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": null model argument");
+  if (m->n < 1 || m->n > kNL)
+    return cfail(SIM_ERR_INVALID_TOPOLOGY, std::string(who) + ": need 1 <= n <= " + std::to_string(kNL));
+  if (m->ncontacts < 0 || m->ncontacts > kNC)
+    return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": need 0 <= ncontacts <= " + std::to_string(kNC));
+  if (m->niter < 0 || !(m->mu >= 0) || !(m->beta >= 0))
+    return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": need niter >= 0, mu >= 0, beta >= 0");
+  *tp = CTopo{};
+  tp->n = m->n;
+  tp->nc = m->ncontacts;
+  tp->niter = m->niter;
+  tp->mu = m->mu;
+  tp->beta = m->beta;
+  for (int k = 0; k < 3; ++k) tp->g[k] = m->gravity[k];
+  int nq = 0, nv = 0, nu = 0;
+  for (int i = 0; i < m->n; ++i) {
+    const int p = m->parent[i], jt = m->jtype[i];
+    if (i == 0 ? p != -1 : (p < 0 || p >= i))
+      return cfail(SIM_ERR_INVALID_TOPOLOGY, std::string(who) + ": need parent[0] = -1 and 0 <= parent[i] < i");
+    if (jt == SIM_JOINT_FREE ? i != 0 : (jt != SIM_JOINT_REVOLUTE && jt != SIM_JOINT_PRISMATIC))
+      return cfail(SIM_ERR_INVALID_TOPOLOGY,
+                   std::string(who) + ": joints must be revolute or prismatic, a free joint only at link 0");
+    tp->parent[i] = p;
+    tp->jtype[i] = jt;
+    tp->qi[i] = nq;
+    tp->vi[i] = nv;
+    tp->ui[i] = nu;
+    if (jt == SIM_JOINT_FREE) { nq += 7; nv += 6; }
+    else { nq += 1; nv += 1; nu += 1; }
+  }
+  for (int k = 0; k < m->ncontacts; ++k) {
+    if (m->contact_link[k] < 0 || m->contact_link[k] >= m->n)
+      return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": contact_link out of range");
+    tp->clink[k] = m->contact_link[k];
+  }
+  tp->nq = nq;
+  tp->nv = nv;
+  tp->nu = nu;
+  tp->np = kParLink * m->n + kParSphere * m->ncontacts;
+  return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_contact_param_count(const sim_contact_model* m, int* nq, int* nv, int* nu, int* nparams) {
+  aba::clear_error();
+  CTopo tp;
+  const int rc = make_topo("sim_contact_param_count", m, &tp);
+  if (rc) return rc;
+  if (nq) *nq = tp.nq;
+  if (nv) *nv = tp.nv;
+  if (nu) *nu = tp.nu;
+  if (nparams) *nparams = tp.np;
+  return SIM_OK;
+}
+
+int sim_contact_rollout(const sim_contact_model* m, int dtype, int batch, const void* params, const void* q0,
+                        const void* qd0, const void* tau, double dt, int T, void* traj, void* qT, void* qdT,
+                        int* ncontacts, void* stream) {
+  aba::clear_error();
+  CTopo tp;
+  int rc = make_topo("sim_contact_rollout", m, &tp);
+  if (rc) return rc;
+  if (dtype != SIM_F32 && dtype != SIM_F64)
+    return cfail(SIM_ERR_UNSUPPORTED_DTYPE, "sim_contact_rollout: dtype must be SIM_F32 or SIM_F64");
+  if (batch < 0 || T < 0 || !(dt > 0))
+    return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout: need batch >= 0, T >= 0, dt > 0");
+  if (batch == 0) return SIM_OK;
+  if (!params || !q0 || !qd0 || !qT || !qdT || (T > 0 && tp.nu > 0 && !tau))
+    return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout: null array argument");
+  const dim3 grid((batch + kBlock - 1) / kBlock), block(kBlock);
+  hipError_t e;
+  if (dtype == SIM_F64) {
+    RollArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)q0, (const double*)qd0,
+                       (const double*)tau, (double*)traj, (double*)qT, (double*)qdT, ncontacts};
+    hipLaunchKernelGGL(k_contact_rollout<double>, grid, block, 0, (hipStream_t)stream, a);
+  } else {
+    RollArgs<float> a{tp, batch, T, (float)dt, (const float*)params, (const float*)q0, (const float*)qd0,
+                      (const float*)tau, (float*)traj, (float*)qT, (float*)qdT, ncontacts};
+    hipLaunchKernelGGL(k_contact_rollout<float>, grid, block, 0, (hipStream_t)stream, a);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return cfail(SIM_ERR_HIP, std::string("sim_contact_rollout: launch failed: ") + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+int sim_contact_rollout_grad(const sim_contact_model* m, int dtype, int batch, const void* params, const void* traj,
+                             const void* tau, double dt, int T, const void* gqT, const void* gqdT, void* gq0,
+                             void* gqd0, void* gtau, void* stream) {
+  aba::clear_error();
+  CTopo tp;
+  int rc = make_topo("sim_contact_rollout_grad", m, &tp);
+  if (rc) return rc;
+  if (dtype != SIM_F32 && dtype != SIM_F64)
+    return cfail(SIM_ERR_UNSUPPORTED_DTYPE, "sim_contact_rollout_grad: dtype must be SIM_F32 or SIM_F64");
+  if (batch < 0 || T < 0 || !(dt > 0))
+    return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: need batch >= 0, T >= 0, dt > 0");
+  if (tp.nq + tp.nv + tp.nu > kBlock)
+    return cfail(SIM_ERR_INVALID_TOPOLOGY, "sim_contact_rollout_grad: nq + nv + nu must not exceed 64");
+  if (batch == 0) return SIM_OK;
+  if (!params || !traj || !gqT || !gqdT || !gq0 || !gqd0 || (T > 0 && tp.nu > 0 && (!tau || !gtau)))
+    return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: null array argument");
+  const dim3 grid(batch), block(kBlock);
+  if (dtype == SIM_F64) {
+    GradArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)traj, (const double*)tau,
+                       (const double*)gqT, (const double*)gqdT, (double*)gq0, (double*)gqd0, (double*)gtau};
+    hipLaunchKernelGGL(k_contact_grad<double>, grid, block, 0, (hipStream_t)stream, a);
+  } else {
+    GradArgs<float> a{tp, batch, T, (float)dt, (const float*)params, (const float*)traj, (const float*)tau,
+                      (const float*)gqT, (const float*)gqdT, (float*)gq0, (float*)gqd0, (float*)gtau};
+    hipLaunchKernelGGL(k_contact_grad<float>, grid, block, 0, (hipStream_t)stream, a);
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return cfail(SIM_ERR_HIP, std::string("sim_contact_rollout_grad: launch failed: ") + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+}  // extern "C"

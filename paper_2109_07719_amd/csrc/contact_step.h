@@ -1,0 +1,519 @@
+// One time step with contact for one system (Sec. 4.1 "Collision
+// resolution"), templated on the scalar (float, double, or their dual
+// numbers for exact step Jacobians).  Host and device code: the kernels in
+// contact.hip run it per lane; a host build runs the same statements.
+#pragma once
+
+#include <cfloat>
+#include <cmath>
+
+#include "../../include/abadj.h"
+#include "dual.h"
+
+namespace aba_contact {
+
+using aba::Dual;
+
+constexpr int kNL = SIM_CONTACT_MAX_LINKS;
+constexpr int kNC = SIM_CONTACT_MAX_SPHERES;
+constexpr int kNR = 3 * kNC;
+constexpr int kNQ = 7 + (kNL - 1);
+constexpr int kNV = 6 + (kNL - 1);
+constexpr int kNX = kNQ + kNV;
+constexpr int kParLink = 25;  // E_T 9, r_T 3, axis 3, mass 1, com 3, Ic 6
+constexpr int kParSphere = 4; // centre 3, radius 1
+
+struct CTopo {
+  int n, nq, nv, nu, nc, niter, np;
+  int parent[kNL], jtype[kNL], qi[kNL], vi[kNL], ui[kNL];
+  int clink[kNC];
+  double mu, beta, g[3];
+};
+
+// ---- scalar helpers (plain and dual) --------------------------------------
+
+ABA_HD float val(float x) { return x; }
+ABA_HD double val(double x) { return x; }
+template <typename R>
+ABA_HD R val(const Dual<R>& x) { return x.v; }
+
+ABA_HD void sin_cos(float x, float& s, float& c) { s = sinf(x); c = cosf(x); }
+ABA_HD void sin_cos(double x, double& s, double& c) { s = sin(x); c = cos(x); }
+template <typename R>
+ABA_HD void sin_cos(const Dual<R>& x, Dual<R>& s, Dual<R>& c) {
+  R sv, cv;
+  sin_cos(x.v, sv, cv);
+  s = Dual<R>(sv, cv * x.d);
+  c = Dual<R>(cv, -sv * x.d);
+}
+ABA_HD float sq_root(float x) { return sqrtf(x); }
+ABA_HD double sq_root(double x) { return sqrt(x); }
+template <typename R>
+ABA_HD Dual<R> sq_root(const Dual<R>& x) {
+  const R s = sq_root(x.v);
+  return Dual<R>(s, x.d / (R(2) * s));
+}
+
+template <typename R> struct Big;
+template <> struct Big<float> { static constexpr float v = FLT_MAX; };
+template <> struct Big<double> { static constexpr double v = 1e300; };
+template <typename T> struct RealOf { using type = T; };
+template <typename R> struct RealOf<Dual<R>> { using type = R; };
+
+// ---- 3-vector and spatial helpers (motion [w; v], force [n; f]) ------------
+
+template <typename S>
+ABA_HD void cross3(const S* a, const S* b, S* o) {
+  const S x = a[1] * b[2] - a[2] * b[1], y = a[2] * b[0] - a[0] * b[2], z = a[0] * b[1] - a[1] * b[0];
+  o[0] = x; o[1] = y; o[2] = z;
+}
+// y = X x for X = [E 0; -E[r]x E]: y_w = E x_w, y_v = E (x_v - r x x_w)
+template <typename S>
+ABA_HD void x_motion(const S* E, const S* r, const S* x, S* y) {
+  S t[3], o[6];
+  cross3(r, x, t);
+  for (int a = 0; a < 3; ++a) {
+    o[a] = E[3 * a] * x[0] + E[3 * a + 1] * x[1] + E[3 * a + 2] * x[2];
+    o[3 + a] = E[3 * a] * (x[3] - t[0]) + E[3 * a + 1] * (x[4] - t[1]) + E[3 * a + 2] * (x[5] - t[2]);
+  }
+  for (int k = 0; k < 6; ++k) y[k] = o[k];
+}
+// y = X^T f: y_f = E^T f_f, y_n = E^T f_n + r x y_f
+template <typename S>
+ABA_HD void xt_force(const S* E, const S* r, const S* f, S* y) {
+  S o[6];
+  for (int b = 0; b < 3; ++b) {
+    o[b] = E[b] * f[0] + E[3 + b] * f[1] + E[6 + b] * f[2];
+    o[3 + b] = E[b] * f[3] + E[3 + b] * f[4] + E[6 + b] * f[5];
+  }
+  S t[3];
+  cross3(r, o + 3, t);
+  for (int k = 0; k < 3; ++k) y[k] = o[k] + t[k];
+  for (int k = 0; k < 3; ++k) y[3 + k] = o[3 + k];
+}
+template <typename S>
+ABA_HD void mat6_vec(const S* M, const S* x, S* y) {
+  for (int a = 0; a < 6; ++a) {
+    S s = M[6 * a] * x[0];
+    for (int b = 1; b < 6; ++b) s = s + M[6 * a + b] * x[b];
+    y[a] = s;
+  }
+}
+
+template <typename R>
+struct Par {  // one system's parameters, stored [np][batch]
+  const R* P;
+  size_t B;
+  int s;
+  ABA_HD R operator()(int k) const { return P[(size_t)k * B + s]; }
+};
+
+template <typename S>
+struct Work {
+  S E[kNL][9], r[kNL][3];    // parent -> link transform
+  S Ew[kNL][9], ow[kNL][3];  // world -> link rotation, link origin in world coordinates
+  S ax[kNL][3];              // unit joint axis
+  S v[kNL][6], c[kNL][6], pA[kNL][6], IA[kNL][36], U[kNL][6], Dinv[kNL], u[kNL], a[kNL][6];
+  S L0[36], D0[6];           // LDL^T of the free root's articulated inertia
+  S J[kNR][kNV], MJ[kNV][kNR];
+  S A[kNR * kNR], b[kNR], x[kNR];
+};
+
+// unit quaternion (x, y, z, w) -> rotation matrix (body -> world), row-major
+template <typename S>
+ABA_HD void quat_R(const S* qt, S* R) {
+  const S x = qt[0], y = qt[1], z = qt[2], w = qt[3];
+  const S d = w * w - (x * x + y * y + z * z);
+  const S v[3] = {x, y, z};
+  const S two = S(2);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) R[3 * i + j] = two * v[i] * v[j];
+  for (int i = 0; i < 3; ++i) R[4 * i] = R[4 * i] + d;
+  R[1] = R[1] - two * w * z; R[2] = R[2] + two * w * y;
+  R[3] = R[3] + two * w * z; R[5] = R[5] - two * w * x;
+  R[6] = R[6] - two * w * y; R[7] = R[7] + two * w * x;
+}
+
+// LDL^T of a symmetric positive definite 6x6 (unit lower L below the diagonal)
+template <typename S>
+ABA_HD void ldl6(const S* M, S* L, S* D) {
+  for (int k = 0; k < 36; ++k) L[k] = M[k];
+  for (int j = 0; j < 6; ++j) {
+    S d = L[7 * j];
+    for (int k = 0; k < j; ++k) d = d - L[6 * j + k] * L[6 * j + k] * D[k];
+    D[j] = d;
+    for (int i = j + 1; i < 6; ++i) {
+      S s = L[6 * i + j];
+      for (int k = 0; k < j; ++k) s = s - L[6 * i + k] * L[6 * j + k] * D[k];
+      L[6 * i + j] = s / d;
+    }
+  }
+}
+template <typename S>
+ABA_HD void ldl6_solve(const S* L, const S* D, const S* rhs, S* x) {
+  S y[6];
+  for (int i = 0; i < 6; ++i) {
+    S s = rhs[i];
+    for (int k = 0; k < i; ++k) s = s - L[6 * i + k] * y[k];
+    y[i] = s;
+  }
+  for (int i = 5; i >= 0; --i) {
+    S s = y[i] / D[i];
+    for (int k = i + 1; k < 6; ++k) s = s - L[6 * k + i] * x[k];
+    x[i] = s;
+  }
+}
+
+// projected Gauss-Seidel on the rows idx[0..m) of A (leading dimension r)
+template <typename S>
+ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi, int niter, S* x) {
+  for (int i = 0; i < m; ++i) x[i] = S(0);
+  for (int it = 0; it < niter; ++it)
+    for (int i = 0; i < m; ++i) {
+      const int ri = idx[i];
+      S d = S(0);
+      for (int j = 0; j < m; ++j)
+        if (j != i) d = d + A[ri * r + idx[j]] * x[j];
+      S y = -(b[ri] + d) / A[ri * r + ri];
+      if (val(y) < val(lo[i])) y = lo[i];
+      else if (val(y) > val(hi[i])) y = hi[i];
+      x[i] = y;
+    }
+}
+
+// One step with contact from (q, qd) under control u; returns the number of
+// active contacts.
+template <typename S, typename R>
+ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* qd, const S* u, R dt_, S* q1,
+                            S* qd1, Work<S>& w) {
+  using Rl = typename RealOf<S>::type;
+  const int n = tp.n, nv = tp.nv;
+  const S dt = S(dt_);
+  // ---- pass 1: poses, velocities, bias forces
+  for (int i = 0; i < n; ++i) {
+    const int p = tp.parent[i], pb = kParLink * i;
+    S vJ[6];
+    if (tp.jtype[i] == SIM_JOINT_FREE) {
+      S Rm[9];
+      quat_R(q + tp.qi[i] + 3, Rm);
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) w.E[i][3 * a + b] = Rm[3 * b + a];
+      for (int k = 0; k < 3; ++k) w.r[i][k] = q[tp.qi[i] + k];
+      for (int k = 0; k < 6; ++k) { w.v[i][k] = qd[tp.vi[i] + k]; w.c[i][k] = S(0); }
+    } else {
+      S a[3];
+      const Rl an = Rl(1) / sq_root(P(pb + 12) * P(pb + 12) + P(pb + 13) * P(pb + 13) + P(pb + 14) * P(pb + 14));
+      for (int k = 0; k < 3; ++k) { a[k] = S(P(pb + 12 + k) * an); w.ax[i][k] = a[k]; }
+      const S qj = q[tp.qi[i]], qdj = qd[tp.vi[i]];
+      S ET[9];
+      for (int k = 0; k < 9; ++k) ET[k] = S(P(pb + k));
+      for (int k = 0; k < 3; ++k) w.r[i][k] = S(P(pb + 9 + k));
+      if (tp.jtype[i] == SIM_JOINT_PRISMATIC) {
+        for (int k = 0; k < 9; ++k) w.E[i][k] = ET[k];
+        for (int b = 0; b < 3; ++b)
+          w.r[i][b] = w.r[i][b] + (ET[b] * a[0] + ET[3 + b] * a[1] + ET[6 + b] * a[2]) * qj;
+        for (int k = 0; k < 3; ++k) { vJ[k] = S(0); vJ[3 + k] = a[k] * qdj; }
+      } else {
+        // E_J = I - sin q [a]x + (1 - cos q) [a]x^2
+        S sq, cq;
+        sin_cos(qj, sq, cq);
+        const S omc = S(1) - cq;
+        const S K[9] = {S(0), -a[2], a[1], a[2], S(0), -a[0], -a[1], a[0], S(0)};
+        S EJ[9];
+        for (int r_ = 0; r_ < 3; ++r_)
+          for (int c_ = 0; c_ < 3; ++c_) {
+            S k2 = K[3 * r_] * K[c_] + K[3 * r_ + 1] * K[3 + c_] + K[3 * r_ + 2] * K[6 + c_];
+            EJ[3 * r_ + c_] = (r_ == c_ ? S(1) : S(0)) - sq * K[3 * r_ + c_] + omc * k2;
+          }
+        for (int r_ = 0; r_ < 3; ++r_)
+          for (int c_ = 0; c_ < 3; ++c_)
+            w.E[i][3 * r_ + c_] = EJ[3 * r_] * ET[c_] + EJ[3 * r_ + 1] * ET[3 + c_] + EJ[3 * r_ + 2] * ET[6 + c_];
+        for (int k = 0; k < 3; ++k) { vJ[k] = a[k] * qdj; vJ[3 + k] = S(0); }
+      }
+      if (p < 0) {
+        for (int k = 0; k < 6; ++k) w.v[i][k] = vJ[k];
+      } else {
+        x_motion(w.E[i], w.r[i], w.v[p], w.v[i]);
+        for (int k = 0; k < 6; ++k) w.v[i][k] = w.v[i][k] + vJ[k];
+      }
+      // c = v x vJ (motion cross product)
+      const S* vv = w.v[i];
+      S t1[3], t2[3], t3[3];
+      cross3(vv, vJ, t1);
+      cross3(vv + 3, vJ, t2);
+      cross3(vv, vJ + 3, t3);
+      for (int k = 0; k < 3; ++k) { w.c[i][k] = t1[k]; w.c[i][3 + k] = t2[k] + t3[k]; }
+    }
+    if (p < 0) {
+      for (int k = 0; k < 9; ++k) w.Ew[i][k] = w.E[i][k];
+      for (int k = 0; k < 3; ++k) w.ow[i][k] = w.r[i][k];
+    } else {
+      for (int r_ = 0; r_ < 3; ++r_)
+        for (int c_ = 0; c_ < 3; ++c_)
+          w.Ew[i][3 * r_ + c_] = w.E[i][3 * r_] * w.Ew[p][c_] + w.E[i][3 * r_ + 1] * w.Ew[p][3 + c_] +
+                                 w.E[i][3 * r_ + 2] * w.Ew[p][6 + c_];
+      for (int a = 0; a < 3; ++a)
+        w.ow[i][a] = w.ow[p][a] + w.Ew[p][a] * w.r[i][0] + w.Ew[p][3 + a] * w.r[i][1] + w.Ew[p][6 + a] * w.r[i][2];
+    }
+    // spatial inertia about the link origin
+    const S m = S(P(pb + 15));
+    const S cm[3] = {S(P(pb + 16)), S(P(pb + 17)), S(P(pb + 18))};
+    const S Ic[6] = {S(P(pb + 19)), S(P(pb + 20)), S(P(pb + 21)), S(P(pb + 22)), S(P(pb + 23)), S(P(pb + 24))};
+    S* I = w.IA[i];
+    const S cc = cm[0] * cm[0] + cm[1] * cm[1] + cm[2] * cm[2];
+    const int dix[3] = {0, 1, 2};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) I[6 * a + b] = -m * cm[a] * cm[b];
+    for (int a = 0; a < 3; ++a) I[7 * dix[a]] = I[7 * dix[a]] + m * cc + Ic[a];
+    I[1] = I[1] + Ic[3]; I[6] = I[6] + Ic[3];
+    I[2] = I[2] + Ic[4]; I[12] = I[12] + Ic[4];
+    I[8] = I[8] + Ic[5]; I[13] = I[13] + Ic[5];
+    // m [c]x (upper right), its transpose (lower left), m I (lower right)
+    const S mc[3] = {m * cm[0], m * cm[1], m * cm[2]};
+    const S cx[9] = {S(0), -mc[2], mc[1], mc[2], S(0), -mc[0], -mc[1], mc[0], S(0)};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        I[6 * a + 3 + b] = cx[3 * a + b];
+        I[6 * (3 + a) + b] = cx[3 * b + a];
+        I[6 * (3 + a) + 3 + b] = (a == b) ? m : S(0);
+      }
+    // p^A = v x* (I v)
+    S h[6];
+    mat6_vec(I, w.v[i], h);
+    const S* vv = w.v[i];
+    S t1[3], t2[3], t3[3];
+    cross3(vv, h, t1);
+    cross3(vv + 3, h + 3, t2);
+    cross3(vv, h + 3, t3);
+    for (int k = 0; k < 3; ++k) { w.pA[i][k] = t1[k] + t2[k]; w.pA[i][3 + k] = t3[k]; }
+  }
+  // ---- pass 2: articulated inertias and bias forces
+  for (int i = n - 1; i >= 0; --i) {
+    if (tp.jtype[i] == SIM_JOINT_FREE) continue;
+    const int off = tp.jtype[i] == SIM_JOINT_PRISMATIC ? 3 : 0;
+    const S* a = w.ax[i];
+    for (int r_ = 0; r_ < 6; ++r_)
+      w.U[i][r_] = w.IA[i][6 * r_ + off] * a[0] + w.IA[i][6 * r_ + off + 1] * a[1] + w.IA[i][6 * r_ + off + 2] * a[2];
+    const S D = w.U[i][off] * a[0] + w.U[i][off + 1] * a[1] + w.U[i][off + 2] * a[2];
+    w.Dinv[i] = S(1) / D;
+    w.u[i] = u[tp.ui[i]] - (w.pA[i][off] * a[0] + w.pA[i][off + 1] * a[1] + w.pA[i][off + 2] * a[2]);
+    const int p = tp.parent[i];
+    if (p >= 0) {
+      S Ia[36];
+      for (int r_ = 0; r_ < 6; ++r_)
+        for (int c_ = 0; c_ < 6; ++c_) Ia[6 * r_ + c_] = w.IA[i][6 * r_ + c_] - w.U[i][r_] * w.Dinv[i] * w.U[i][c_];
+      S pa[6], Iac[6];
+      mat6_vec(Ia, w.c[i], Iac);
+      const S y = w.Dinv[i] * w.u[i];
+      for (int r_ = 0; r_ < 6; ++r_) pa[r_] = w.pA[i][r_] + Iac[r_] + w.U[i][r_] * y;
+      S f[6];
+      xt_force(w.E[i], w.r[i], pa, f);
+      for (int k = 0; k < 6; ++k) w.pA[p][k] = w.pA[p][k] + f[k];
+      // IA_parent += X^T Ia X, column by column
+      for (int j = 0; j < 6; ++j) {
+        S e[6], xe[6], t[6], col[6];
+        for (int k = 0; k < 6; ++k) e[k] = (k == j) ? S(1) : S(0);
+        x_motion(w.E[i], w.r[i], e, xe);
+        mat6_vec(Ia, xe, t);
+        xt_force(w.E[i], w.r[i], t, col);
+        for (int k = 0; k < 6; ++k) w.IA[p][6 * k + j] = w.IA[p][6 * k + j] + col[k];
+      }
+    }
+  }
+  // ---- pass 3: accelerations; qd_minus = qd + dt qdd
+  const S a0[6] = {S(0), S(0), S(0), S(-tp.g[0]), S(-tp.g[1]), S(-tp.g[2])};
+  for (int i = 0; i < n; ++i) {
+    if (tp.jtype[i] == SIM_JOINT_FREE) {
+      ldl6(w.IA[i], w.L0, w.D0);
+      S rhs[6];
+      for (int k = 0; k < 6; ++k) rhs[k] = -w.pA[i][k];
+      ldl6_solve(w.L0, w.D0, rhs, w.a[i]);
+      // body-frame gravity E g added to the gravity-free solution
+      for (int k = 0; k < 6; ++k) {
+        S acc = w.a[i][k];
+        if (k >= 3) acc = acc + (w.E[i][3 * (k - 3)] * S(tp.g[0]) + w.E[i][3 * (k - 3) + 1] * S(tp.g[1]) +
+                                 w.E[i][3 * (k - 3) + 2] * S(tp.g[2]));
+        qd1[tp.vi[i] + k] = qd[tp.vi[i] + k] + dt * acc;
+      }
+    } else {
+      const int p = tp.parent[i], off = tp.jtype[i] == SIM_JOINT_PRISMATIC ? 3 : 0;
+      S ap[6];
+      x_motion(w.E[i], w.r[i], p < 0 ? a0 : w.a[p], ap);
+      for (int k = 0; k < 6; ++k) ap[k] = ap[k] + w.c[i][k];
+      S Uap = S(0);
+      for (int k = 0; k < 6; ++k) Uap = Uap + w.U[i][k] * ap[k];
+      const S qdd = w.Dinv[i] * (w.u[i] - Uap);
+      for (int k = 0; k < 6; ++k) w.a[i][k] = ap[k];
+      for (int k = 0; k < 3; ++k) w.a[i][off + k] = w.a[i][off + k] + w.ax[i][k] * qdd;
+      qd1[tp.vi[i]] = qd[tp.vi[i]] + dt * qdd;
+    }
+  }
+  // ---- detection and assembly
+  int act[kNC], na = 0;
+  S phi[kNC], cl[kNC][3], pw[kNC][3];
+  for (int k = 0; k < tp.nc; ++k) {
+    const int l = tp.clink[k], sb = kParLink * n + kParSphere * k;
+    const S cc[3] = {S(P(sb)), S(P(sb + 1)), S(P(sb + 2))};
+    const S rad = S(P(sb + 3));
+    const S y = w.ow[l][1] + w.Ew[l][1] * cc[0] + w.Ew[l][4] * cc[1] + w.Ew[l][7] * cc[2];
+    const S g = y - rad;
+    if (val(g) < Rl(0)) {
+      act[na] = k;
+      phi[na] = g;
+      for (int a = 0; a < 3; ++a) cl[na][a] = cc[a] - rad * w.Ew[l][3 * a + 1];
+      for (int a = 0; a < 3; ++a)
+        pw[na][a] = w.ow[l][a] + w.Ew[l][a] * cl[na][0] + w.Ew[l][3 + a] * cl[na][1] + w.Ew[l][6 + a] * cl[na][2];
+      ++na;
+    }
+  }
+  if (na > 0) {
+    const int r = 3 * na;
+    const int dirs[3] = {1, 0, 2};
+    for (int i = 0; i < r; ++i)
+      for (int k = 0; k < nv; ++k) w.J[i][k] = S(0);
+    for (int c = 0; c < na; ++c) {
+      for (int j = tp.clink[act[c]]; j >= 0; j = tp.parent[j]) {
+        S d[3];
+        for (int k = 0; k < 3; ++k) d[k] = pw[c][k] - w.ow[j][k];
+        if (tp.jtype[j] == SIM_JOINT_FREE) {
+          for (int e = 0; e < 3; ++e) {
+            const S Re[3] = {w.Ew[j][3 * e], w.Ew[j][3 * e + 1], w.Ew[j][3 * e + 2]};
+            S col[3];
+            cross3(Re, d, col);
+            for (int dd = 0; dd < 3; ++dd) {
+              w.J[3 * c + dd][tp.vi[j] + e] = col[dirs[dd]];
+              w.J[3 * c + dd][tp.vi[j] + 3 + e] = Re[dirs[dd]];
+            }
+          }
+        } else {
+          S z[3], col[3];
+          for (int b = 0; b < 3; ++b) z[b] = w.Ew[j][b] * w.ax[j][0] + w.Ew[j][3 + b] * w.ax[j][1] + w.Ew[j][6 + b] * w.ax[j][2];
+          if (tp.jtype[j] == SIM_JOINT_PRISMATIC) {
+            for (int k = 0; k < 3; ++k) col[k] = z[k];
+          } else {
+            cross3(z, d, col);
+          }
+          for (int dd = 0; dd < 3; ++dd) w.J[3 * c + dd][tp.vi[j]] = col[dirs[dd]];
+        }
+      }
+    }
+    // M^-1 J^T: response to a unit world force along each row's direction at the contact point
+    for (int c = 0; c < na; ++c) {
+      const int l = tp.clink[act[c]];
+      for (int dd = 0; dd < 3; ++dd) {
+        for (int i = 0; i < n; ++i)
+          for (int k = 0; k < 6; ++k) w.pA[i][k] = S(0);
+        S f[3];
+        for (int b = 0; b < 3; ++b) f[b] = w.Ew[l][3 * b + dirs[dd]];
+        S nmt[3];
+        cross3(cl[c], f, nmt);
+        for (int k = 0; k < 3; ++k) { w.pA[l][k] = -nmt[k]; w.pA[l][3 + k] = -f[k]; }
+        for (int i = n - 1; i >= 0; --i) {
+          if (tp.jtype[i] == SIM_JOINT_FREE) continue;
+          const int off = tp.jtype[i] == SIM_JOINT_PRISMATIC ? 3 : 0, p = tp.parent[i];
+          w.u[i] = -(w.pA[i][off] * w.ax[i][0] + w.pA[i][off + 1] * w.ax[i][1] + w.pA[i][off + 2] * w.ax[i][2]);
+          if (p >= 0) {
+            const S y = w.Dinv[i] * w.u[i];
+            S pa[6], fp[6];
+            for (int k = 0; k < 6; ++k) pa[k] = w.pA[i][k] + w.U[i][k] * y;
+            xt_force(w.E[i], w.r[i], pa, fp);
+            for (int k = 0; k < 6; ++k) w.pA[p][k] = w.pA[p][k] + fp[k];
+          }
+        }
+        for (int i = 0; i < n; ++i) {
+          if (tp.jtype[i] == SIM_JOINT_FREE) {
+            S rhs[6];
+            for (int k = 0; k < 6; ++k) rhs[k] = -w.pA[i][k];
+            ldl6_solve(w.L0, w.D0, rhs, w.a[i]);
+            for (int k = 0; k < 6; ++k) w.MJ[tp.vi[i] + k][3 * c + dd] = w.a[i][k];
+          } else {
+            const int p = tp.parent[i], off = tp.jtype[i] == SIM_JOINT_PRISMATIC ? 3 : 0;
+            S ap[6];
+            if (p < 0) {
+              for (int k = 0; k < 6; ++k) ap[k] = S(0);
+            } else {
+              x_motion(w.E[i], w.r[i], w.a[p], ap);
+            }
+            S Uap = S(0);
+            for (int k = 0; k < 6; ++k) Uap = Uap + w.U[i][k] * ap[k];
+            const S qdd = w.Dinv[i] * (w.u[i] - Uap);
+            for (int k = 0; k < 6; ++k) w.a[i][k] = ap[k];
+            for (int k = 0; k < 3; ++k) w.a[i][off + k] = w.a[i][off + k] + w.ax[i][k] * qdd;
+            w.MJ[tp.vi[i]][3 * c + dd] = qdd;
+          }
+        }
+      }
+    }
+    // A = J M^-1 J^T, b = J qd_minus + (beta/dt) phi (normal rows)
+    const S bdt = S(Rl(tp.beta)) / dt;
+    Rl dmax = Rl(0);
+    for (int i = 0; i < r; ++i) {
+      for (int j = 0; j < r; ++j) {
+        S s = S(0);
+        for (int k = 0; k < nv; ++k) s = s + w.J[i][k] * w.MJ[k][j];
+        w.A[i * r + j] = s;
+      }
+      S s = S(0);
+      for (int k = 0; k < nv; ++k) s = s + w.J[i][k] * qd1[k];
+      w.b[i] = (i % 3 == 0) ? s + bdt * phi[i / 3] : s;
+      if (val(w.A[i * r + i]) > dmax) dmax = val(w.A[i * r + i]);
+    }
+    int keep[kNR], nk = 0, kn[kNC], nkn = 0;
+    for (int i = 0; i < r; ++i)
+      if (val(w.A[i * r + i]) > Rl(1e-12) * dmax) {
+        keep[nk++] = i;
+        if (i % 3 == 0) kn[nkn++] = i;
+      }
+    S lo[kNR], hi[kNR], lamn[kNC], xn[kNC];
+    for (int i = 0; i < nkn; ++i) { lo[i] = S(0); hi[i] = S(Big<Rl>::v); }
+    pgs(nkn, kn, r, w.A, w.b, lo, hi, tp.niter, xn);
+    for (int c = 0; c < na; ++c) lamn[c] = S(0);
+    for (int i = 0; i < nkn; ++i) lamn[kn[i] / 3] = xn[i];
+    const S mu = S(Rl(tp.mu));
+    for (int i = 0; i < nk; ++i) {
+      if (keep[i] % 3 == 0) {
+        lo[i] = S(0);
+        hi[i] = S(Big<Rl>::v);
+      } else {
+        lo[i] = -(mu * lamn[keep[i] / 3]);
+        hi[i] = mu * lamn[keep[i] / 3];
+      }
+    }
+    S xk[kNR];
+    pgs(nk, keep, r, w.A, w.b, lo, hi, tp.niter, xk);
+    for (int j = 0; j < r; ++j) w.x[j] = S(0);
+    for (int i = 0; i < nk; ++i) w.x[keep[i]] = xk[i];
+    for (int k = 0; k < nv; ++k) {
+      S s = S(0);
+      for (int j = 0; j < r; ++j) s = s + w.MJ[k][j] * w.x[j];
+      qd1[k] = qd1[k] + s;
+    }
+  }
+  // ---- positions from the new velocity
+  for (int i = 0; i < n; ++i) {
+    if (tp.jtype[i] == SIM_JOINT_FREE) {
+      const S* qt = q + tp.qi[i] + 3;
+      const S* v1 = qd1 + tp.vi[i];
+      S Rm[9];
+      quat_R(qt, Rm);
+      for (int a = 0; a < 3; ++a)
+        q1[tp.qi[i] + a] = q[tp.qi[i] + a] + dt * (Rm[3 * a] * v1[3] + Rm[3 * a + 1] * v1[4] + Rm[3 * a + 2] * v1[5]);
+      // quat1 = normalize(quat + dt/2 quat (x) (w1, 0))
+      S dq[4];
+      dq[3] = -(qt[0] * v1[0] + qt[1] * v1[1] + qt[2] * v1[2]);
+      S cr[3];
+      cross3(qt, v1, cr);
+      for (int k = 0; k < 3; ++k) dq[k] = qt[3] * v1[k] + cr[k];
+      S qr[4];
+      const S h = S(Rl(0.5)) * dt;
+      for (int k = 0; k < 4; ++k) qr[k] = qt[k] + h * dq[k];
+      const S nrm = sq_root(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+      for (int k = 0; k < 4; ++k) q1[tp.qi[i] + 3 + k] = qr[k] / nrm;
+    } else {
+      q1[tp.qi[i]] = q[tp.qi[i]] + dt * qd1[tp.vi[i]];
+    }
+  }
+  return na;
+}
+
+}  // namespace aba_contact

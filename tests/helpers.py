@@ -196,3 +196,28 @@ def emu_rollout_grad(s, q0, qd0, tau, dt_, gqT, gqdT, gravity=(0.0, -9.81, 0.0),
     if frame:
         return gq0, gqd0, gtau, qT, qdT, frame_grad_to_user(s, acc.astype(np.float64))
     return gq0, gqd0, gtau, qT, qdT
+
+
+_cemu = None
+
+
+def contact_emu():
+    """Host build of the GPU contact step (tests/hostemu/contact_emu.cpp)."""
+    global _cemu
+    if _cemu is None:
+        path = os.path.join(HERE, "hostemu", "libcontactemu.so")
+        src = os.path.join(HERE, "hostemu", "contact_emu.cpp")
+        csrc = os.path.join(HERE, "..", "paper_2109_07719_amd", "csrc")
+        deps = [src] + [os.path.join(csrc, f) for f in ("contact_step.h", "dual.h", "spatial.h")]
+        if not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(f) for f in deps):
+            import subprocess
+            tmp = f"{path}.{os.getpid()}.tmp"
+            subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wno-unknown-pragmas",
+                                   "-o", tmp, src])
+            os.replace(tmp, path)
+        L = ctypes.CDLL(path)
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.emu_contact_rollout.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, P, D, I, P, P]
+        L.emu_contact_grad.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, D, I, P, P, P, P, P]
+        _cemu = L
+    return _cemu

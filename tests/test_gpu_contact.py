@@ -1,0 +1,219 @@
+"""GPU parity of rollouts with contact inside the step and of their
+gradient (Sec. 4.1 "Collision resolution"), through the C ABI
+(sim_contact_rollout, sim_contact_rollout_grad), against the FP64 oracle:
+
+* FP64 trajectories and contact counts element by element on sampled
+  systems of a 256-quadruped landing batch and of a 64-tree batch (prismatic
+  joints, random frames), to round-off;
+* FP64 gradients (q0, qd0, tau) against the oracle's, to round-off, through
+  touchdown;
+* FP32: the GPU's step from its own states against the oracle's step,
+  within the bar the step's conditioning sets (1e-4, see the host test), and
+  FP32 gradients against the oracle's on a short window;
+* edge cases: no contact spheres (the plain step), an empty batch, invalid
+  models;
+* the benchmark batch (4096 quadrupeds, 1000 steps) on sampled systems.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import contact_cases as CC
+import dyn_ref as R
+import oracle as O
+from helpers import rel
+from paper_2109_07719_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+G = (0.0, -9.81, 0.0)
+MU, BETA, NITER, DT = 0.8, 0.2, 30, 1e-3
+
+
+def _world_point(s, q, link, c):
+    Rs, o, *_ = R.kinematics(s, q, np.zeros(s.nv), np.zeros(s.nv), np.array(G))
+    return o[link] + Rs[link] @ c
+
+
+def quad_batch(B, T, seed0=3100):
+    draws = [CC.landing_quadruped(seed0 + i, T) for i in range(B)]
+    return draws
+
+
+def tree_batch(B, T, seed=2003):
+    """One tree topology; masses, inertias, COMs, sphere centres and radii
+    and the states vary per system."""
+    base = CC.grounded_tree(seed, T)
+    out = []
+    for i in range(B):
+        rng = np.random.default_rng(100 + i)
+        s, q0, qd0, tau, links, centers, radii = CC.grounded_tree(seed, T)
+        s.mass = s.mass * rng.uniform(0.8, 1.25, s.n)
+        s.com = s.com + rng.normal(0, 0.02, s.com.shape)
+        q0 = q0 + rng.normal(0, 0.05, q0.shape)
+        centers = centers + rng.normal(0, 0.02, centers.shape)
+        s = CC.lower_to_ground(s, q0, links, centers, radii, _world_point, rng.uniform(1e-3, 5e-3))
+        out.append((s, q0, qd0, tau, links, centers, radii))
+    assert all(np.array_equal(d[0].parent, base[0].parent) for d in out)
+    return out
+
+
+def _gpu(draws, dtype, T, mu=MU, beta=BETA, niter=NITER):
+    from paper_2109_07719_amd.contact import ContactBatch
+    cb = ContactBatch([d[0] for d in draws], draws[0][4], [d[5] for d in draws], [d[6] for d in draws], mu=mu,
+                      beta=beta, niter=niter, gravity=G, dtype=dtype)
+    f = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=DEV)
+    q0 = f(np.stack([d[1] for d in draws], axis=1))
+    qd0 = f(np.stack([d[2] for d in draws], axis=1))
+    tau = f(np.stack([d[3][:T] for d in draws], axis=2))
+    return cb, q0, qd0, tau
+
+
+def _oracle(d, mu=MU, beta=BETA, niter=NITER):
+    s, q0, qd0, tau, links, centers, radii = d
+    return O.Model(s, G), O.Contacts(links, centers, radii, mu=mu, beta=beta, niter=niter)
+
+
+@pytest.mark.parametrize("which", ["quadrupeds", "trees"])
+def test_rollout_fp64_round_off(which):
+    T = 100 if which == "quadrupeds" else 40
+    draws = quad_batch(256, T) if which == "quadrupeds" else tree_batch(64, T)
+    print("case", which, "B", len(draws), "T", T, flush=True)
+    cb, q0, qd0, tau = _gpu(draws, torch.float64, T)
+    qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, DT, traj=True, counts=True)
+    torch.cuda.synchronize()
+    tr, nc = tr.cpu().numpy(), nc.cpu().numpy()
+    worst, touched = 0.0, 0
+    for i in range(0, len(draws), max(1, len(draws) // 16)):
+        m, C = _oracle(draws[i])
+        d = draws[i]
+        _, _, nc_o, tr_o = O.rollout_contact(m, C, d[1], d[2], d[3][:T], DT, traj=True)
+        assert np.array_equal(nc[:, i], nc_o), i
+        touched += int(nc_o.max() >= 1)
+        worst = max(worst, max(rel(tr[t + 1, :, i], tr_o[t], 1e-12) for t in range(T)))
+    print("worst state error %.1e, sampled systems in contact %d" % (worst, touched))
+    assert touched >= 8 and worst < 1e-10
+    assert np.array_equal(qT.cpu().numpy(), tr[-1, :cb.nq]) and np.array_equal(qdT.cpu().numpy(), tr[-1, cb.nq:])
+
+
+@pytest.mark.parametrize("which", ["quadrupeds", "trees"])
+def test_gradient_fp64_round_off(which):
+    T = 50 if which == "quadrupeds" else 25
+    draws = quad_batch(64, T) if which == "quadrupeds" else tree_batch(32, T)
+    print("case", which, "B", len(draws), "T", T, flush=True)
+    cb, q0, qd0, tau = _gpu(draws, torch.float64, T)
+    qT, qdT, tr = cb.rollout(q0, qd0, tau, DT)
+    rng = np.random.default_rng(9)
+    gqT = torch.tensor(rng.normal(size=(cb.nq, cb.B)), dtype=torch.float64, device=DEV)
+    gqdT = torch.tensor(rng.normal(size=(cb.nv, cb.B)), dtype=torch.float64, device=DEV)
+    g = [x.cpu().numpy() for x in cb.grad(tr, tau, DT, gqT, gqdT)]
+    worst = 0.0
+    for i in (0, 7, len(draws) // 2, len(draws) - 1):
+        m, C = _oracle(draws[i])
+        d = draws[i]
+        ref = O.rollout_contact_grad(m, C, d[1], d[2], d[3][:T], DT, gqT[:, i].cpu().numpy(),
+                                     gqdT[:, i].cpu().numpy())
+        scale = max(np.abs(r).max() for r in ref)
+        got = (g[0][:, i], g[1][:, i], g[2][:, :, i])
+        worst = max(worst, *[rel(a, b, 1e-6 * scale) for a, b in zip(got, ref)])
+    print("worst gradient error %.1e" % worst)
+    assert worst < 1e-8
+
+
+def test_fp32_step_map_and_gradient():
+    T = 60
+    draws = quad_batch(128, T)
+    print("case quadrupeds fp32 B 128 T", T, flush=True)
+    cb, q0, qd0, tau = _gpu(draws, torch.float32, T)
+    qT, qdT, tr = cb.rollout(q0, qd0, tau, DT)
+    trn = tr.double().cpu().numpy()
+    worst = 0.0
+    for i in (0, 33, 77, 127):
+        m, C = _oracle(draws[i])
+        tau_i = tau[:, :, i].double().cpu().numpy()
+        for t in range(0, T, 3):
+            x = trn[t, :, i]
+            q1, qd1, _, _ = O.step_contact(m, C, x[:cb.nq], x[cb.nq:], tau_i[t], DT)
+            worst = max(worst, rel(trn[t + 1, :, i], np.r_[q1, qd1], 1e-6))
+    print("fp32 worst step-map error %.1e" % worst)
+    assert worst < 1e-4
+    # gradient over the last 10 steps (touchdown), from the GPU's own states
+    T2 = 10
+    tr2 = tr[T - T2:].contiguous()
+    tau2 = tau[T - T2:].contiguous()
+    rng = np.random.default_rng(4)
+    gqT = torch.tensor(rng.normal(size=(cb.nq, cb.B)), dtype=torch.float32, device=DEV)
+    gqdT = torch.tensor(rng.normal(size=(cb.nv, cb.B)), dtype=torch.float32, device=DEV)
+    g = [x.double().cpu().numpy() for x in cb.grad(tr2, tau2, DT, gqT, gqdT)]
+    worst_g = 0.0
+    for i in (0, 33, 77, 127):
+        m, C = _oracle(draws[i])
+        x0 = tr2[0, :, i].double().cpu().numpy()
+        ref = O.rollout_contact_grad(m, C, x0[:cb.nq], x0[cb.nq:], tau2[:, :, i].double().cpu().numpy(), DT,
+                                     gqT[:, i].double().cpu().numpy(), gqdT[:, i].double().cpu().numpy())
+        scale = max(np.abs(r).max() for r in ref)
+        got = (g[0][:, i], g[1][:, i], g[2][:, :, i])
+        worst_g = max(worst_g, *[rel(a, b, 1e-3 * scale) for a, b in zip(got, ref)])
+    print("fp32 worst gradient error over the touchdown window %.1e" % worst_g)
+    assert worst_g < 1e-2
+
+
+def test_edge_cases():
+    from paper_2109_07719_amd import _native as N
+    from paper_2109_07719_amd.contact import ContactBatch
+    # no spheres: the plain step of the oracle
+    draws = [CC.landing_quadruped(3100 + i, 20) for i in range(3)]
+    draws = [(d[0], d[1], d[2], d[3], np.zeros(0, np.int32), np.zeros((0, 3)), np.zeros(0)) for d in draws]
+    cb, q0, qd0, tau = _gpu(draws, torch.float64, 20)
+    qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, DT, counts=True)
+    assert not nc.any()
+    m = O.Model(draws[1][0], G)
+    qT_o, qdT_o = O.rollout(m, draws[1][1], draws[1][2], draws[1][3][:20], DT)
+    assert rel(qT[:, 1].cpu().numpy(), qT_o, 1e-12) < 1e-12 and rel(qdT[:, 1].cpu().numpy(), qdT_o, 1e-12) < 1e-12
+    # empty batch
+    cb0, *_ = _gpu(draws[:1], torch.float64, 20)
+    cb0.B = 0
+    z = lambda *sh: torch.zeros(sh, dtype=torch.float64, device=DEV)
+    out = cb0.rollout(z(cb0.nq, 0), z(cb0.nv, 0), z(5, cb0.nu, 0), DT, traj=False)
+    assert out[0].shape == (cb0.nq, 0)
+    # invalid models
+    s = draws[0][0]
+    bad = synth.System(parent=s.parent, jtype=np.where(np.arange(s.n) == 2, synth.SPHERICAL, s.jtype).astype(np.int32),
+                       E_T=s.E_T, r_T=s.r_T, axis=s.axis, mass=s.mass, com=s.com, Ic=s.Ic)
+    with pytest.raises(N.SimError):
+        ContactBatch([bad], [3], [[[0, 0, 0]]], [[0.03]], dtype=torch.float64)
+    with pytest.raises(N.SimError):
+        ContactBatch([s], [3, 6, 9, 12, 3], [[[0, 0, 0]] * 5], [[0.03] * 5], dtype=torch.float64)
+    big, *_ = synth.tree_system(5, 1, nmin=17, nmax=17)
+    with pytest.raises(N.SimError):
+        ContactBatch([big], [1], [[[0, 0, 0]]], [[0.03]], dtype=torch.float64)
+
+
+def test_benchmark_batch_sampled():
+    """4096 landing quadrupeds, 1000 steps (1 s: fall, touchdown, then the
+    legs fold under random torques with 2-4 feet on the ground; only the feet
+    carry spheres), FP32 in one launch each way; sampled systems' GPU steps
+    against the oracle's, and the gradient is finite."""
+    T, B = 1000, 4096
+    draws = quad_batch(B, T, seed0=50000)
+    print("case benchmark batch B", B, "T", T, flush=True)
+    cb, q0, qd0, tau = _gpu(draws, torch.float32, T)
+    qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, DT, counts=True)
+    g = cb.grad(tr, tau, DT, 2 * qT, qdT.clone())
+    torch.cuda.synchronize()
+    assert all(torch.isfinite(x).all() for x in g)
+    ncn = nc.cpu().numpy()
+    assert (ncn[-100:].min(axis=0) >= 1).mean() > 0.9, "feet stay in contact over the last 0.1 s"
+    trn = tr[:, :, ::512].double().cpu().numpy()
+    worst = 0.0
+    for k, i in enumerate(range(0, B, 512)):
+        m, C = _oracle(draws[i])
+        tau_i = tau[:, :, i].double().cpu().numpy()
+        for t in range(0, T, 97):
+            x = trn[t, :, k]
+            q1, qd1, _, _ = O.step_contact(m, C, x[:cb.nq], x[cb.nq:], tau_i[t], DT)
+            worst = max(worst, rel(trn[t + 1, :, k], np.r_[q1, qd1], 1e-6))
+    print("benchmark batch: fp32 worst sampled step-map error %.1e" % worst)
+    assert worst < 1e-4
