@@ -331,6 +331,115 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-6))
 
 
+def contact_bench(args, torch, dev):
+    """Rollouts with contact inside the step and their gradient (Sec. 4.1
+    "Collision resolution"): B landing quadrupeds (spheres on the four feet),
+    T steps, one launch each way, timed with HIP events on the launch stream.
+    FLOPs per step are counted by the library at sampled states of the
+    timed trajectory; the FP64 oracle (step with contact and its complex-step
+    gradient) is timed on the host on whole systems over a short window."""
+    import ctypes
+
+    import oracle as O
+    from paper_2109_07719_amd import _native as N
+    from paper_2109_07719_amd import synth
+    from paper_2109_07719_amd.contact import ContactBatch, pack_params
+
+    B, T = (int(v) for v in args.contact.split(","))
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    mu, beta, niter, dt, G = 0.8, 0.2, 30, 1e-3, (0.0, -9.81, 0.0)
+    draws = [synth.landing_quadruped(50000 + i, T) for i in range(B)]
+    cb = ContactBatch([d[0] for d in draws], draws[0][4], [d[5] for d in draws], [d[6] for d in draws], mu=mu,
+                      beta=beta, niter=niter, gravity=G, dtype=dtype)
+    f = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=dev)
+    q0 = f(np.stack([d[1] for d in draws], axis=1))
+    qd0 = f(np.stack([d[2] for d in draws], axis=1))
+    tau = f(np.stack([d[3] for d in draws], axis=2))
+    gqT = torch.ones_like(q0)
+    gqdT = torch.ones_like(qd0)
+    for _ in range(max(args.warmup, 1)):
+        qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, dt, counts=True)
+        g = cb.grad(tr, tau, dt, gqT, gqdT)
+    torch.cuda.synchronize()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    fwd_ms, grad_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, dt, counts=True)
+        e1.record()
+        g = cb.grad(tr, tau, dt, gqT, gqdT)
+        e2.record()
+        torch.cuda.synchronize()
+        fwd_ms.append(e0.elapsed_time(e1))
+        grad_ms.append(e1.elapsed_time(e2))
+        print(f"contact step: rollout {fwd_ms[-1]:.2f} ms, gradient {grad_ms[-1]:.2f} ms", file=sys.stderr, flush=True)
+    wall = (time.perf_counter() - t0) / args.steps
+    fwd, grd = float(np.mean(fwd_ms)), float(np.mean(grad_ms))
+    ncn = nc.cpu().numpy()
+    # FLOPs at sampled (system, step) states of the timed trajectory
+    rng = np.random.default_rng(3)
+    trn = tr.double().cpu().numpy()
+    taun = tau.double().cpu().numpy()
+    par, jt = (np.ascontiguousarray(x, np.int32) for x in (draws[0][0].parent, draws[0][0].jtype))
+    sf, gf = [], []
+    for _ in range(48):
+        i, t = int(rng.integers(B)), int(rng.integers(T))
+        P = np.ascontiguousarray(pack_params(draws[i][0], draws[i][5], draws[i][6]))
+        x = np.ascontiguousarray(trn[t, :, i])
+        u = np.ascontiguousarray(taun[t, :, i])
+        a, b = ctypes.c_double(), ctypes.c_double()
+        N.check(N.lib().sim_contact_flops(ctypes.byref(cb.m), P.ctypes.data, x.ctypes.data,
+                                          x[cb.nq:].ctypes.data, u.ctypes.data, dt, ctypes.byref(a), ctypes.byref(b)))
+        sf.append(a.value)
+        gf.append(b.value)
+    fl_fwd, fl_grad = float(np.mean(sf)) * B * T, float(np.mean(gf)) * B * T
+    # parity sample: the GPU's steps from its own states against the oracle's
+    worst = 0.0
+    for i in range(0, B, max(1, B // 8)):
+        m = O.Model(draws[i][0], G)
+        C = O.Contacts(draws[i][4], draws[i][5], draws[i][6], mu=mu, beta=beta, niter=niter)
+        for t in range(0, T, max(1, T // 10)):
+            x = trn[t, :, i]
+            q1, qd1, _, _ = O.step_contact(m, C, x[:cb.nq], x[cb.nq:], taun[t, :, i], dt)
+            worst = max(worst, _rel(trn[t + 1, :, i], np.r_[q1, qd1]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        Tw = min(T, 40)
+        t0, dof_steps, k = time.perf_counter(), 0, 0
+        while time.perf_counter() - t0 < min(args.cpu_sample_seconds, 15.0):
+            d = draws[k % B]
+            m = O.Model(d[0], G)
+            C = O.Contacts(d[4], d[5], d[6], mu=mu, beta=beta, niter=niter)
+            O.rollout_contact(m, C, d[1], d[2], d[3][:Tw], dt)
+            O.rollout_contact_grad(m, C, d[1], d[2], d[3][:Tw], dt, np.ones(cb.nq), np.ones(cb.nv))
+            dof_steps += cb.nv * Tw
+            k += 1
+        cpu = {"value": dof_steps / (time.perf_counter() - t0), "unit": "DOF-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} whole quadrupeds x {Tw} steps (fall and touchdown), FP64 step with contact + "
+                         f"complex-step gradient, one host thread"}
+    total = fwd + grd
+    res = {"metric": "contact rollout forward+gradient DOF-steps/s (1 GPU)", "value": B * cb.nv * T / (total * 1e-3),
+           "unit": "DOF-steps/s", "higher_is_better": True, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": total, "wall_ms_per_step": wall * 1e3, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+           "config": {"workload": f"{B} landing quadrupeds (18 DOF, contact spheres on 4 feet), T={T}, dt=1e-3, "
+                                  f"PGS {niter} sweeps x 2 solves, mu {mu}, beta {beta}",
+                      "batch": B, "T": T},
+           "rollout_ms": fwd, "gradient_ms": grd,
+           "active_contacts_per_step": {str(k): int(v) for k, v in enumerate(np.bincount(ncn.reshape(-1), minlength=5))},
+           "roofline": {"bound": "alu", "kernel": "k_contact_grad", "achieved": fl_grad / (grd * 1e-3) / 1e12,
+                        "peak": FP32_PEAK_TFLOPS if dtype == torch.float32 else 78.6, "unit": "TFLOP/s",
+                        "frac": fl_grad / (grd * 1e-3) / 1e12 / (FP32_PEAK_TFLOPS if dtype == torch.float32 else 78.6),
+                        "traffic": None, "flops_per_launch": fl_grad,
+                        "rollout_achieved": fl_fwd / (fwd * 1e-3) / 1e12, "rollout_flops_per_launch": fl_fwd,
+                        "flops_per_step_mean": float(np.mean(sf)), "grad_flops_per_step_mean": float(np.mean(gf))},
+           "step_map_error_vs_oracle_max": worst,
+           "cpu_baseline": cpu}
+    print(json.dumps(res))
+
+
 def pgs_bench(args, torch, dev):
     """Contact solver (Sec. 4.1 "Collision resolution", Eq. mlcp; App. C):
     a batch of independent MLCPs a = A x + b, lo <= x <= hi solved by a fixed
@@ -559,6 +668,7 @@ def main():
                     help="run this many Adam iterations of trajectory optimisation (chains_2048 workload)")
     ap.add_argument("--rl", type=int, default=0,
                     help="one-step JVP/VJP throughput for RL on this many quadruped samples (Sec. 5)")
+    ap.add_argument("--contact", default="", help="B,T: rollouts with contact and their gradient")
     ap.add_argument("--pgs", default="",
                     help="B,n,niter: time the contact solver (MLCP projected Gauss-Seidel) and its adjoint instead")
     ap.add_argument("--T", type=int, default=None, help="override the horizon (reduced runs only)")
@@ -599,6 +709,8 @@ def main():
         return rl_bench(args, torch, dev)
     if args.pgs:
         return pgs_bench(args, torch, dev)
+    if args.contact:
+        return contact_bench(args, torch, dev)
 
     t_gen = time.perf_counter()
     b = synth.workload(args.workload, T=args.T, tau_dtype=np.float32)

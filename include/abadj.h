@@ -414,6 +414,17 @@ typedef struct {
  * nullable). */
 int sim_contact_param_count(const sim_contact_model *m, int *nq, int *nv, int *nu, int *nparams);
 
+/* Algorithmic floating-point operations of one step with contact at the
+ * state (q, qd) under tau (HOST double arrays of one system; params [nparams]
+ * in the order above): step_flops for the plain step, grad_flops for one
+ * reverse step of sim_contact_rollout_grad (nq + nv + nu dual-number steps
+ * and their dot products).  Counted on the host by running the step's
+ * statements with a counting scalar that keeps its value, so detection,
+ * dropped rows and clamps decide as on the device; every +, -, *, /, sqrt,
+ * sin and cos counts 1. */
+int sim_contact_flops(const sim_contact_model *m, const double *params, const double *q, const double *qd,
+                      const double *tau, double dt, double *step_flops, double *grad_flops);
+
 /* T steps with contact from (q0, qd0).  Writes qT, qdT; traj (nullable)
  * receives x_0 .. x_T as [T + 1][nq + nv][batch] (q then qd per state, the
  * input of sim_contact_rollout_grad); ncontacts (nullable, DEVICE int

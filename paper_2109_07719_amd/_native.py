@@ -29,7 +29,7 @@ EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_status", "sim_get_
             "sim_checkpoint_schedule", "sim_forward", "sim_forward_jvp",
             "sim_backward", "sim_aba", "sim_flops", "sim_last_error",
             "sim_pgs_workspace_bytes", "sim_pgs_solve", "sim_pgs_adjoint",
-            "sim_contact_param_count", "sim_contact_rollout", "sim_contact_rollout_grad")
+            "sim_contact_param_count", "sim_contact_flops", "sim_contact_rollout", "sim_contact_rollout_grad")
 SIM_PGS_MAX_ROWS = 16
 
 
@@ -110,6 +110,8 @@ def lib():
         L.sim_contact_param_count.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                               ctypes.POINTER(I)]
         L.sim_contact_param_count.restype = I
+        L.sim_contact_flops.argtypes = [P, P, P, P, P, D, ctypes.POINTER(D), ctypes.POINTER(D)]
+        L.sim_contact_flops.restype = I
         L.sim_contact_rollout.argtypes = [P, I, I, P, P, P, P, D, I, P, P, P, P, P]
         L.sim_contact_rollout.restype = I
         L.sim_contact_rollout_grad.argtypes = [P, I, I, P, P, P, D, I, P, P, P, P, P, P]

@@ -33,7 +33,9 @@
 // through LDS.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
+#include <type_traits>
 
 #include "../../include/abadj.h"
 #include "abadj_internal.h"
@@ -43,6 +45,42 @@ namespace {
 
 using aba::Dual;
 using namespace aba_contact;
+
+
+// ---- operation count (host) --------------------------------------------------
+// A counting scalar that carries its value, so that every data-dependent
+// decision (detection, dropped rows, clamps) is taken as on the device:
+// every +, -, *, /, sqrt, sin and cos counts 1.
+thread_local long long g_cops = 0;
+struct CD {
+  double v = 0;
+  CD() = default;
+  template <typename T, typename = std::enable_if_t<std::is_arithmetic_v<T>>>
+  CD(T x) : v(double(x)) {}
+};
+inline CD cd_(double x) { ++g_cops; return CD(x); }
+inline CD operator+(CD a, CD b) { return cd_(a.v + b.v); }
+inline CD operator-(CD a, CD b) { return cd_(a.v - b.v); }
+inline CD operator*(CD a, CD b) { return cd_(a.v * b.v); }
+inline CD operator/(CD a, CD b) { return cd_(a.v / b.v); }
+inline CD operator-(CD a) { return CD(-a.v); }
+inline CD& operator+=(CD& a, CD b) { a = a + b; return a; }
+inline bool operator<(CD a, CD b) { return a.v < b.v; }
+inline bool operator>(CD a, CD b) { return a.v > b.v; }
+inline CD val(CD x) { return x; }
+inline CD sq_root(CD x) { return cd_(std::sqrt(x.v)); }
+inline void sin_cos(CD x, CD& s, CD& c) { s = cd_(std::sin(x.v)); c = cd_(std::cos(x.v)); }
+
+}  // namespace
+
+namespace aba_contact {
+template <>
+struct Big<CD> { static constexpr double v = 1e300; };
+template <>
+struct RealOf<CD> { using type = CD; };
+}  // namespace aba_contact
+
+namespace {
 
 // ---- kernels ---------------------------------------------------------------
 
@@ -196,6 +234,43 @@ int sim_contact_param_count(const sim_contact_model* m, int* nq, int* nv, int* n
   if (nv) *nv = tp.nv;
   if (nu) *nu = tp.nu;
   if (nparams) *nparams = tp.np;
+  return SIM_OK;
+}
+
+int sim_contact_flops(const sim_contact_model* m, const double* params, const double* q, const double* qd,
+                      const double* tau, double dt, double* step_flops, double* grad_flops) {
+  aba::clear_error();
+  CTopo tp;
+  const int rc = make_topo("sim_contact_flops", m, &tp);
+  if (rc) return rc;
+  if (!params || !q || !qd || (tp.nu > 0 && !tau) || !step_flops || !grad_flops)
+    return cfail(SIM_ERR_INVALID_ARG, "sim_contact_flops: null argument");
+  const Par<double> P{params, 1, 0};
+  const int nx = tp.nq + tp.nv;
+  {
+    auto* w = new Work<CD>;
+    CD x[kNX], x1[kNX], u[kNL];
+    for (int k = 0; k < tp.nq; ++k) x[k] = CD(q[k]);
+    for (int k = 0; k < tp.nv; ++k) x[tp.nq + k] = CD(qd[k]);
+    for (int k = 0; k < tp.nu; ++k) u[k] = CD(tau[k]);
+    g_cops = 0;
+    contact_step(tp, P, x, x + tp.nq, u, dt, x1, x1 + tp.nq, *w);
+    *step_flops = (double)g_cops;
+    delete w;
+  }
+  {
+    using D = Dual<CD>;
+    auto* w = new Work<D>;
+    D x[kNX], x1[kNX], u[kNL];
+    for (int k = 0; k < tp.nq; ++k) x[k] = D(CD(q[k]), CD(k == 0 ? 1 : 0));
+    for (int k = 0; k < tp.nv; ++k) x[tp.nq + k] = D(CD(qd[k]), CD(0));
+    for (int k = 0; k < tp.nu; ++k) u[k] = D(CD(tau[k]), CD(0));
+    g_cops = 0;
+    contact_step(tp, P, x, x + tp.nq, u, dt, x1, x1 + tp.nq, *w);
+    // one dual step and one nx-term dot product per Jacobian column
+    *grad_flops = (double)(g_cops + 2 * nx) * (double)(nx + tp.nu);
+    delete w;
+  }
   return SIM_OK;
 }
 

@@ -202,7 +202,7 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       for (int k = 0; k < 6; ++k) { w.v[i][k] = qd[tp.vi[i] + k]; w.c[i][k] = S(0); }
     } else {
       S a[3];
-      const Rl an = Rl(1) / sq_root(P(pb + 12) * P(pb + 12) + P(pb + 13) * P(pb + 13) + P(pb + 14) * P(pb + 14));
+      const R an = R(1) / sq_root(P(pb + 12) * P(pb + 12) + P(pb + 13) * P(pb + 13) + P(pb + 14) * P(pb + 14));
       for (int k = 0; k < 3; ++k) { a[k] = S(P(pb + 12 + k) * an); w.ax[i][k] = a[k]; }
       const S qj = q[tp.qi[i]], qdj = qd[tp.vi[i]];
       S ET[9];
@@ -445,7 +445,7 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       }
     }
     // A = J M^-1 J^T, b = J qd_minus + (beta/dt) phi (normal rows)
-    const S bdt = S(Rl(tp.beta)) / dt;
+    const S bdt = S(tp.beta) / dt;
     Rl dmax = Rl(0);
     for (int i = 0; i < r; ++i) {
       for (int j = 0; j < r; ++j) {
@@ -469,7 +469,7 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
     pgs(nkn, kn, r, w.A, w.b, lo, hi, tp.niter, xn);
     for (int c = 0; c < na; ++c) lamn[c] = S(0);
     for (int i = 0; i < nkn; ++i) lamn[kn[i] / 3] = xn[i];
-    const S mu = S(Rl(tp.mu));
+    const S mu = S(tp.mu);
     for (int i = 0; i < nk; ++i) {
       if (keep[i] % 3 == 0) {
         lo[i] = S(0);
@@ -505,7 +505,7 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       cross3(qt, v1, cr);
       for (int k = 0; k < 3; ++k) dq[k] = qt[3] * v1[k] + cr[k];
       S qr[4];
-      const S h = S(Rl(0.5)) * dt;
+      const S h = S(0.5) * dt;
       for (int k = 0; k < 4; ++k) qr[k] = qt[k] + h * dq[k];
       const S nrm = sq_root(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
       for (int k = 0; k < 4; ++k) q1[tp.qi[i] + 3 + k] = qr[k] / nrm;

@@ -275,6 +275,23 @@ def quadruped_system(seed: int, T: int):
     return sys_, q0, v, tau
 
 
+
+def landing_quadruped(seed: int, T: int, drop: float = 0.005):
+    """Contact workload: quadruped_system(seed, T) with a contact sphere of
+    radius 0.03 at each calf's end (0, -0.25, 0), the base lowered so that
+    the feet start `drop` above the ground plane y = 0, torques scaled by
+    0.3.  It falls, lands on its feet, and the legs then fold under the
+    random torques with 2-4 feet on the ground (only the feet carry
+    spheres).  Returns (system, q0, qd0, tau, contact links, centres,
+    radii)."""
+    s, q0, qd0, tau = quadruped_system(seed, T)
+    q0 = q0.copy()
+    q0[1] = 0.5 + 0.03 + drop
+    links = np.array([3, 6, 9, 12], np.int32)
+    centers = np.tile([0.0, -0.25, 0.0], (4, 1))
+    radii = np.full(4, 0.03)
+    return s, q0, qd0, 0.3 * tau, links, centers, radii
+
 def telescoping_quadruped_system(seed: int, T: int):
     """quadruped_system(seed, T) with every knee replaced by a prismatic
     joint sliding along the leg (axis (0, 1, 0)): a free-floating base over

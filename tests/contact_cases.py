@@ -7,16 +7,7 @@ from paper_2109_07719_amd import synth
 
 
 def landing_quadruped(seed, T, drop=0.005):
-    """The benchmark quadruped with a sphere (radius 0.03) at each calf's end
-    (0, -0.25, 0), the base lowered so that the feet start `drop` above the
-    ground: it falls, lands on four feet and stands on them."""
-    s, q0, qd0, tau = synth.quadruped_system(seed, T)
-    q0 = q0.copy()
-    q0[1] = 0.5 + 0.03 + drop
-    links = np.array([3, 6, 9, 12], np.int32)
-    centers = np.tile([0.0, -0.25, 0.0], (4, 1))
-    radii = np.full(4, 0.03)
-    return s, q0, qd0, 0.3 * tau, links, centers, radii
+    return synth.landing_quadruped(seed, T, drop)
 
 
 def grounded_tree(seed, T, rng_seed=None):

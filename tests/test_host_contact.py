@@ -139,3 +139,30 @@ def test_gradient_fp64_matches_the_oracle(k):
     print(name, "gradient errors (q0, qd0, tau)", ["%.1e" % x for x in e], "contacts", np.bincount(nc))
     assert nc.max() >= 1
     assert max(e) < 1e-8
+
+
+def test_flop_count_grows_with_active_contacts():
+    """sim_contact_flops (host code, no GPU): the count rises with each
+    active contact and the reverse step costs one dual-number step per
+    Jacobian column."""
+    from paper_2109_07719_amd import _native as N
+    from paper_2109_07719_amd import synth
+    from paper_2109_07719_amd.contact import _Model
+    s, q0, qd0, tau, links, centers, radii = synth.landing_quadruped(3100, 2)
+    par, jt, cl = (np.ascontiguousarray(x, np.int32) for x in (s.parent, s.jtype, links))
+    m = _Model(s.n, par.ctypes.data, jt.ctypes.data, 4, cl.ctypes.data, 0.8, 0.2, 30,
+               (ctypes.c_double * 3)(*G))
+    P = np.ascontiguousarray(pack_params(s, centers, radii))
+    counts = []
+    for y in (1.0, 0.53, 0.5):          # none, some, all four feet below the plane
+        q = np.array(q0)
+        q[1] = y
+        q[7:] = 0.0
+        a, b = ctypes.c_double(), ctypes.c_double()
+        N.check(N.lib().sim_contact_flops(ctypes.byref(m), _p(P), _p(q), _p(np.ascontiguousarray(qd0)),
+                                          _p(np.ascontiguousarray(tau[0])), 1e-3, ctypes.byref(a), ctypes.byref(b)))
+        counts.append((a.value, b.value))
+    print(counts)
+    assert counts[0][0] < counts[2][0] and counts[0][1] < counts[2][1]
+    nx, nu = s.nq + s.nv, s.nu
+    assert all(b % (nx + nu) == 0 and b / (nx + nu) > 2 * a for a, b in counts)
