@@ -101,10 +101,24 @@ struct RollArgs {
   int* ncont;     // nullable: [T][B]
 };
 
+// Systems per workgroup of the rollout: each keeps its Work record in LDS
+// (16 x 9.7 KB in FP32, 8 x 19.4 KB in FP64), so the step's many dependent
+// accesses to the tree's articulated quantities see LDS rather than scratch
+// latency, and a batch spreads over four times as many CUs as at one system
+// per lane of a full wave.
+template <typename R> struct RollSpw;
+template <> struct RollSpw<float> { static constexpr int v = 16; };
+template <> struct RollSpw<double> { static constexpr int v = 8; };
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_contact_rollout(RollArgs<R> a) {
-  const int s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= a.B) return;
+  constexpr int SPW = RollSpw<R>::v;
+  static_assert(SPW * sizeof(Work<R>) <= 160 * 1024, "LDS budget");
+  static_assert((sizeof(Work<R>) / sizeof(R)) % 2 == 1, "odd Work stride");
+  __shared__ Work<R> wsh[SPW];
+  const int lane = threadIdx.x;
+  const int s = blockIdx.x * SPW + lane;
+  if (lane >= SPW || s >= a.B) return;
   const CTopo& tp = a.tp;
   const size_t B = (size_t)a.B;
   const Par<R> P{a.P, B, s};
@@ -114,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_contact_rollout(RollArgs<R> a) {
   for (int k = 0; k < nv; ++k) x[0][nq + k] = a.qd0[k * B + s];
   if (a.traj)
     for (int k = 0; k < nx; ++k) a.traj[k * B + s] = x[0][k];
-  Work<R> w;
+  Work<R>& w = wsh[lane];
   int cur = 0;
   for (int t = 0; t < a.T; ++t) {
     for (int k = 0; k < nu; ++k) u[k] = a.tau[((size_t)t * nu + k) * B + s];
@@ -288,7 +302,8 @@ int sim_contact_rollout(const sim_contact_model* m, int dtype, int batch, const 
   if (batch == 0) return SIM_OK;
   if (!params || !q0 || !qd0 || !qT || !qdT || (T > 0 && tp.nu > 0 && !tau))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout: null array argument");
-  const dim3 grid((batch + kBlock - 1) / kBlock), block(kBlock);
+  const int spw = dtype == SIM_F64 ? RollSpw<double>::v : RollSpw<float>::v;
+  const dim3 grid((batch + spw - 1) / spw), block(kBlock);
   hipError_t e;
   if (dtype == SIM_F64) {
     RollArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)q0, (const double*)qd0,

@@ -117,6 +117,9 @@ struct Work {
   S L0[36], D0[6];           // LDL^T of the free root's articulated inertia
   S J[kNR][kNV], MJ[kNV][kNR];
   S A[kNR * kNR], b[kNR], x[kNR];
+  // pads the struct to an odd number of scalars, so that lanes holding
+  // consecutive Work records in LDS fall on distinct banks
+  S pad_;
 };
 
 // unit quaternion (x, y, z, w) -> rotation matrix (body -> world), row-major
