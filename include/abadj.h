@@ -438,10 +438,13 @@ int sim_contact_rollout(const sim_contact_model *m, int dtype, int batch, const 
  * params, tau, dt): the reverse recursion x_bar_t = (dx_{t+1}/dx_t)^T
  * x_bar_{t+1}, tau_bar_t = (dx_{t+1}/dtau_t)^T x_bar_{t+1} with each step's
  * exact Jacobian at the stored state (detection, row and clamp decisions as
- * taken).  Writes gq0 [nq][batch], gqd0 [nv][batch], gtau [T][nu][batch]. */
+ * taken).  Writes gq0 [nq][batch], gqd0 [nv][batch], gtau [T][nu][batch]
+ * and, when gmu (DEVICE [batch]) is not NULL, dL/dmu of every system (the
+ * friction coefficient as a model parameter, Sec. 4.1 "other parameters").
+ * Needs nq + nv + nu <= 63. */
 int sim_contact_rollout_grad(const sim_contact_model *m, int dtype, int batch, const void *params, const void *traj,
                              const void *tau, double dt, int T, const void *gqT, const void *gqdT, void *gq0,
-                             void *gqd0, void *gtau, void *stream);
+                             void *gqd0, void *gtau, void *gmu, void *stream);
 
 #ifdef __cplusplus
 }

@@ -75,7 +75,7 @@ def _configure(L):
     L.orc_step_contact_c.restype = I
     L.orc_rollout_contact.argtypes = [P, P, P, P, P, D, I, P, P, P, P]
     L.orc_rollout_contact.restype = I
-    L.orc_rollout_contact_grad.argtypes = [P, P, P, P, P, D, I, P, P, P, P, P]
+    L.orc_rollout_contact_grad.argtypes = [P, P, P, P, P, D, I, P, P, P, P, P, P]
     L.orc_rollout_contact_grad.restype = I
     return L
 
@@ -423,15 +423,19 @@ def rollout_contact(m: Model, C: Contacts, q0, qd0, tau, dt, traj: bool = False)
     return (qT, qdT, nc, tr) if traj else (qT, qdT, nc)
 
 
-def rollout_contact_grad(m: Model, C: Contacts, q0, qd0, tau, dt, gqT, gqdT):
+def rollout_contact_grad(m: Model, C: Contacts, q0, qd0, tau, dt, gqT, gqdT, mu_grad: bool = False):
     """Gradient of <gqT, qT> + <gqdT, qdT> through a rollout with contact:
-    returns gq0, gqd0, gtau [T, nu]."""
-    tau = np.ascontiguousarray(np.asarray(tau, dtype=np.float64).reshape(-1, m.nu))
+    returns gq0, gqd0, gtau [T, nu], and with mu_grad the derivative with
+    respect to the friction coefficient."""
+    tau = np.ascontiguousarray(np.asarray(tau, dtype=np.float64).reshape(-1, m.nu) if m.nu else
+                               np.zeros((np.asarray(tau).shape[0], 0)))
     T = tau.shape[0]
     q0, qd0, gqT, gqdT = _f64(q0, m.nq), _f64(qd0, m.nv), _f64(gqT, m.nq), _f64(gqdT, m.nv)
     gq0, gqd0, gtau = np.zeros(m.nq), np.zeros(m.nv), np.zeros((T, m.nu))
+    gmu = ctypes.c_double()
     rc = lib().orc_rollout_contact_grad(m.ref, C.ref, _p(q0), _p(qd0), _p(tau), float(dt), T, _p(gqT), _p(gqdT),
-                                        _p(gq0), _p(gqd0), _p(gtau))
+                                        _p(gq0), _p(gqd0), _p(gtau),
+                                        ctypes.byref(gmu) if mu_grad else None)
     if rc != 0:
         raise RuntimeError("orc_rollout_contact_grad failed")
-    return gq0, gqd0, gtau
+    return (gq0, gqd0, gtau, gmu.value) if mu_grad else (gq0, gqd0, gtau)

@@ -896,7 +896,7 @@ int orc_rollout_contact(const orc_model *m, const orc_contacts *C, const double 
  * kinks of the piecewise-smooth step map. */
 int orc_rollout_contact_grad(const orc_model *m, const orc_contacts *C, const double *q0, const double *qd0,
                              const double *tau, double dt, int T, const double *gqT, const double *gqdT,
-                             double *gq0, double *gqd0, double *gtau) {
+                             double *gq0, double *gqd0, double *gtau, double *gmu) {
   if (T < 0) return -1;
   const int nq = orc_nq(m), nv = orc_nv(m), nu = orc_nu(m), nx = nq + nv;
   double *xs = (double *)malloc(sizeof(double) * (size_t)(T + 1) * nx);
@@ -915,6 +915,7 @@ int orc_rollout_contact_grad(const orc_model *m, const orc_contacts *C, const do
   const double h = 1e-30;
   double complex *in = xc, *uc = xc + nx;
   double complex out1[nx];
+  double mu_acc = 0;
   for (int t = T - 1; t >= 0; --t) {
     const double *cur = xs + (size_t)t * nx;
     for (int j = 0; j < nx + nu; ++j) {
@@ -928,8 +929,18 @@ int orc_rollout_contact_grad(const orc_model *m, const orc_contacts *C, const do
       if (j < nx) xb1[j] = s;
       else gtau[(size_t)t * nu + (j - nx)] = s;
     }
+    if (gmu) {
+      /* the friction coefficient's column of this step's Jacobian */
+      for (int k = 0; k < nx; ++k) in[k] = cur[k];
+      for (int k = 0; k < nu; ++k) uc[k] = tau[(size_t)t * nu + k];
+      step_contact_mu_c(m, C, in, in + nq, uc, dt, C->mu + I * h, out1, out1 + nq, NULL);
+      double s = 0;
+      for (int k = 0; k < nx; ++k) s += xb[k] * cimag(out1[k]) / h;
+      mu_acc += s;
+    }
     memcpy(xb, xb1, sizeof(double) * nx);
   }
+  if (gmu) *gmu = mu_acc;
   memcpy(gq0, xb, sizeof(double) * nq);
   memcpy(gqd0, xb + nq, sizeof(double) * nv);
   free(xs); free(xc); free(xb);

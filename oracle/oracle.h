@@ -184,10 +184,12 @@ int orc_step_contact_c(const orc_model *m, const orc_contacts *C, const void *q,
 int orc_rollout_contact(const orc_model *m, const orc_contacts *C, const double *q0, const double *qd0,
                         const double *tau, double dt, int T, double *qT, double *qdT, double *traj, int *n_contacts);
 /* Gradient of <gqT, qT> + <gqdT, qdT> through a rollout with contact (the
- * step map's exact derivative by complex step, in reverse time). */
+ * step map's exact derivative by complex step, in reverse time); gmu
+ * (nullable) receives the derivative with respect to the friction
+ * coefficient mu. */
 int orc_rollout_contact_grad(const orc_model *m, const orc_contacts *C, const double *q0, const double *qd0,
                              const double *tau, double dt, int T, const double *gqT, const double *gqdT,
-                             double *gq0, double *gqd0, double *gtau);
+                             double *gq0, double *gqd0, double *gtau, double *gmu);
 
 /* ---- contact solver (pgs_oracle.c) ---------------------------------
  * Projected Gauss-Seidel on the MLCP a = A x + b, lo <= x <= hi (Sec. 4.1,

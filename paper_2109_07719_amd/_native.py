@@ -114,7 +114,7 @@ def lib():
         L.sim_contact_flops.restype = I
         L.sim_contact_rollout.argtypes = [P, I, I, P, P, P, P, D, I, P, P, P, P, P]
         L.sim_contact_rollout.restype = I
-        L.sim_contact_rollout_grad.argtypes = [P, I, I, P, P, P, D, I, P, P, P, P, P, P]
+        L.sim_contact_rollout_grad.argtypes = [P, I, I, P, P, P, D, I, P, P, P, P, P, P, P]
         L.sim_contact_rollout_grad.restype = I
         L.sim_last_error.argtypes = []
         L.sim_last_error.restype = ctypes.c_char_p

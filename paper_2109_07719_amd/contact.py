@@ -94,17 +94,19 @@ class ContactBatch:
             out += (nc,)
         return out
 
-    def grad(self, traj, tau, dt, gqT, gqdT):
+    def grad(self, traj, tau, dt, gqT, gqdT, mu_grad=False):
         """Gradient of <gqT, qT> + <gqdT, qdT> through the rollout that wrote
-        traj: returns gq0 [nq][B], gqd0 [nv][B], gtau [T][nu][B]."""
+        traj: returns gq0 [nq][B], gqd0 [nv][B], gtau [T][nu][B] and, with
+        mu_grad, dL/dmu per system [B]."""
         T = int(tau.shape[0])
         self._check(traj, (T + 1, self.nq + self.nv, self.B), "traj")
         self._check(tau, (T, self.nu, self.B), "tau")
         self._check(gqT, (self.nq, self.B), "gqT")
         self._check(gqdT, (self.nv, self.B), "gqdT")
         gq0, gqd0, gtau = torch.empty_like(gqT), torch.empty_like(gqdT), torch.empty_like(tau)
+        gmu = torch.empty(self.B, dtype=self.dtype, device=gqT.device) if mu_grad else None
         N.check(N.lib().sim_contact_rollout_grad(ctypes.byref(self.m), _DT[self.dtype], self.B, _ptr(self.P),
                                                  _ptr(traj), _ptr(tau), float(dt), T, _ptr(gqT), _ptr(gqdT),
-                                                 _ptr(gq0), _ptr(gqd0), _ptr(gtau),
+                                                 _ptr(gq0), _ptr(gqd0), _ptr(gtau), _ptr(gmu),
                                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
-        return gq0, gqd0, gtau
+        return (gq0, gqd0, gtau, gmu) if mu_grad else (gq0, gqd0, gtau)

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_contact_rollout(RollArgs<R> a) {
   int cur = 0;
   for (int t = 0; t < a.T; ++t) {
     for (int k = 0; k < nu; ++k) u[k] = a.tau[((size_t)t * nu + k) * B + s];
-    const int na = contact_step(tp, P, x[cur], x[cur] + nq, u, a.dt, x[cur ^ 1], x[cur ^ 1] + nq, w);
+    const int na = contact_step(tp, P, x[cur], x[cur] + nq, u, a.dt, R(tp.mu), x[cur ^ 1], x[cur ^ 1] + nq, w);
     cur ^= 1;
     if (a.ncont) a.ncont[(size_t)t * B + s] = na;
     if (a.traj)
@@ -155,9 +155,11 @@ struct GradArgs {
   R* gq0;         // [nq][B]
   R* gqd0;        // [nv][B]
   R* gtau;        // [T][nu][B]
+  R* gmu;         // nullable: [B]
 };
 
-// one wave per system; lane j < nx + nu owns Jacobian column j
+// one wave per system; lane j < nx + nu owns Jacobian column j, lane nx + nu
+// the friction coefficient's column (when gmu is asked for)
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_contact_grad(GradArgs<R> a) {
   using D = Dual<R>;
@@ -171,22 +173,26 @@ __global__ __launch_bounds__(kBlock) void k_contact_grad(GradArgs<R> a) {
   else if (j < nx) xb[j] = a.gqdT[(j - nq) * B + s];
   __syncthreads();
   Work<D> w;
+  const int ncol = nx + nu + (a.gmu ? 1 : 0);
+  R mu_acc = R(0);
   for (int t = a.T - 1; t >= 0; --t) {
     R sj = R(0);
-    if (j < nx + nu) {
+    if (j < ncol) {
       D x[kNX], x1[kNX], u[kNL];
       for (int k = 0; k < nx; ++k) x[k] = D(a.traj[((size_t)t * nx + k) * B + s], R(k == j ? 1 : 0));
       for (int k = 0; k < nu; ++k) u[k] = D(a.tau[((size_t)t * nu + k) * B + s], R(nx + k == j ? 1 : 0));
-      contact_step(tp, P, x, x + nq, u, a.dt, x1, x1 + nq, w);
+      contact_step(tp, P, x, x + nq, u, a.dt, D(R(tp.mu), R(j == nx + nu ? 1 : 0)), x1, x1 + nq, w);
       for (int k = 0; k < nx; ++k) sj += xb[k] * x1[k].d;
     }
     __syncthreads();
     if (j < nx) xb[j] = sj;
     else if (j < nx + nu) a.gtau[((size_t)t * nu + (j - nx)) * B + s] = sj;
+    else if (j == nx + nu) mu_acc += sj;
     __syncthreads();
   }
   if (j < nq) a.gq0[j * B + s] = xb[j];
   else if (j < nx) a.gqd0[(j - nq) * B + s] = xb[j];
+  else if (j == nx + nu && a.gmu) a.gmu[s] = mu_acc;
 }
 
 int cfail(int code, const std::string& msg) { return aba::report_error(code, msg); }
@@ -268,7 +274,7 @@ int sim_contact_flops(const sim_contact_model* m, const double* params, const do
     for (int k = 0; k < tp.nv; ++k) x[tp.nq + k] = CD(qd[k]);
     for (int k = 0; k < tp.nu; ++k) u[k] = CD(tau[k]);
     g_cops = 0;
-    contact_step(tp, P, x, x + tp.nq, u, dt, x1, x1 + tp.nq, *w);
+    contact_step(tp, P, x, x + tp.nq, u, dt, CD(tp.mu), x1, x1 + tp.nq, *w);
     *step_flops = (double)g_cops;
     delete w;
   }
@@ -280,7 +286,7 @@ int sim_contact_flops(const sim_contact_model* m, const double* params, const do
     for (int k = 0; k < tp.nv; ++k) x[tp.nq + k] = D(CD(qd[k]), CD(0));
     for (int k = 0; k < tp.nu; ++k) u[k] = D(CD(tau[k]), CD(0));
     g_cops = 0;
-    contact_step(tp, P, x, x + tp.nq, u, dt, x1, x1 + tp.nq, *w);
+    contact_step(tp, P, x, x + tp.nq, u, dt, D(CD(tp.mu), CD(0)), x1, x1 + tp.nq, *w);
     // one dual step and one nx-term dot product per Jacobian column
     *grad_flops = (double)(g_cops + 2 * nx) * (double)(nx + tp.nu);
     delete w;
@@ -321,7 +327,7 @@ int sim_contact_rollout(const sim_contact_model* m, int dtype, int batch, const 
 
 int sim_contact_rollout_grad(const sim_contact_model* m, int dtype, int batch, const void* params, const void* traj,
                              const void* tau, double dt, int T, const void* gqT, const void* gqdT, void* gq0,
-                             void* gqd0, void* gtau, void* stream) {
+                             void* gqd0, void* gtau, void* gmu, void* stream) {
   aba::clear_error();
   CTopo tp;
   int rc = make_topo("sim_contact_rollout_grad", m, &tp);
@@ -330,19 +336,21 @@ int sim_contact_rollout_grad(const sim_contact_model* m, int dtype, int batch, c
     return cfail(SIM_ERR_UNSUPPORTED_DTYPE, "sim_contact_rollout_grad: dtype must be SIM_F32 or SIM_F64");
   if (batch < 0 || T < 0 || !(dt > 0))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: need batch >= 0, T >= 0, dt > 0");
-  if (tp.nq + tp.nv + tp.nu > kBlock)
-    return cfail(SIM_ERR_INVALID_TOPOLOGY, "sim_contact_rollout_grad: nq + nv + nu must not exceed 64");
+  if (tp.nq + tp.nv + tp.nu + 1 > kBlock)
+    return cfail(SIM_ERR_INVALID_TOPOLOGY, "sim_contact_rollout_grad: nq + nv + nu must not exceed 63");
   if (batch == 0) return SIM_OK;
   if (!params || !traj || !gqT || !gqdT || !gq0 || !gqd0 || (T > 0 && tp.nu > 0 && (!tau || !gtau)))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: null array argument");
   const dim3 grid(batch), block(kBlock);
   if (dtype == SIM_F64) {
     GradArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)traj, (const double*)tau,
-                       (const double*)gqT, (const double*)gqdT, (double*)gq0, (double*)gqd0, (double*)gtau};
+                       (const double*)gqT, (const double*)gqdT, (double*)gq0, (double*)gqd0, (double*)gtau,
+                       (double*)gmu};
     hipLaunchKernelGGL(k_contact_grad<double>, grid, block, 0, (hipStream_t)stream, a);
   } else {
     GradArgs<float> a{tp, batch, T, (float)dt, (const float*)params, (const float*)traj, (const float*)tau,
-                      (const float*)gqT, (const float*)gqdT, (float*)gq0, (float*)gqd0, (float*)gtau};
+                      (const float*)gqT, (const float*)gqdT, (float*)gq0, (float*)gqd0, (float*)gtau,
+                      (float*)gmu};
     hipLaunchKernelGGL(k_contact_grad<float>, grid, block, 0, (hipStream_t)stream, a);
   }
   const hipError_t e = hipGetLastError();

@@ -184,11 +184,12 @@ ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* l
     }
 }
 
-// One step with contact from (q, qd) under control u; returns the number of
+// One step with contact from (q, qd) under control u and friction
+// coefficient mu (a dual number for its derivative); returns the number of
 // active contacts.
 template <typename S, typename R>
-ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* qd, const S* u, R dt_, S* q1,
-                            S* qd1, Work<S>& w) {
+ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* qd, const S* u, R dt_, S mu,
+                            S* q1, S* qd1, Work<S>& w) {
   using Rl = typename RealOf<S>::type;
   const int n = tp.n, nv = tp.nv;
   const S dt = S(dt_);
@@ -472,7 +473,6 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
     pgs(nkn, kn, r, w.A, w.b, lo, hi, tp.niter, xn);
     for (int c = 0; c < na; ++c) lamn[c] = S(0);
     for (int i = 0; i < nkn; ++i) lamn[kn[i] / 3] = xn[i];
-    const S mu = S(tp.mu);
     for (int i = 0; i < nk; ++i) {
       if (keep[i] % 3 == 0) {
         lo[i] = S(0);

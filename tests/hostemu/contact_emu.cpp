@@ -52,7 +52,8 @@ void rollout(const CTopo& tp, const double* Pd, const double* q0, const double* 
   auto* w = new Work<R>;
   for (int t = 0; t < T; ++t) {
     for (int k = 0; k < tp.nu; ++k) u[k] = R(tau[t * tp.nu + k]);
-    ncont[t] = contact_step(tp, P, x.data(), x.data() + tp.nq, u.data(), R(dt), x1.data(), x1.data() + tp.nq, *w);
+    ncont[t] = contact_step(tp, P, x.data(), x.data() + tp.nq, u.data(), R(dt), R(tp.mu), x1.data(),
+                            x1.data() + tp.nq, *w);
     x = x1;
     for (int k = 0; k < nx; ++k) traj[(t + 1) * nx + k] = double(x[k]);
   }
@@ -61,7 +62,7 @@ void rollout(const CTopo& tp, const double* Pd, const double* q0, const double* 
 
 template <typename R>
 void grad(const CTopo& tp, const double* Pd, const double* traj, const double* tau, double dt, int T,
-          const double* gqT, const double* gqdT, double* gq0, double* gqd0, double* gtau) {
+          const double* gqT, const double* gqdT, double* gq0, double* gqd0, double* gtau, double* gmu) {
   using D = Dual<R>;
   std::vector<R> Pv(Pd, Pd + tp.np);
   const Par<R> P{Pv.data(), 1, 0};
@@ -71,21 +72,25 @@ void grad(const CTopo& tp, const double* Pd, const double* traj, const double* t
   for (int k = 0; k < tp.nv; ++k) xb[nq + k] = R(gqdT[k]);
   auto* w = new Work<D>;
   std::vector<D> x(nx), x1(nx), u(nu > 0 ? nu : 1);
+  R mu_acc = R(0);
   for (int t = T - 1; t >= 0; --t) {
-    for (int j = 0; j < nx + nu; ++j) {
+    for (int j = 0; j < nx + nu + 1; ++j) {
       for (int k = 0; k < nx; ++k) x[k] = D(R(traj[t * nx + k]), R(k == j ? 1 : 0));
       for (int k = 0; k < nu; ++k) u[k] = D(R(tau[t * nu + k]), R(nx + k == j ? 1 : 0));
-      contact_step(tp, P, x.data(), x.data() + nq, u.data(), R(dt), x1.data(), x1.data() + nq, *w);
+      contact_step(tp, P, x.data(), x.data() + nq, u.data(), R(dt), D(R(tp.mu), R(j == nx + nu ? 1 : 0)),
+                   x1.data(), x1.data() + nq, *w);
       R s = R(0);
       for (int k = 0; k < nx; ++k) s += xb[k] * x1[k].d;
       if (j < nx) xn[j] = s;
-      else gtau[t * nu + (j - nx)] = double(s);
+      else if (j < nx + nu) gtau[t * nu + (j - nx)] = double(s);
+      else mu_acc += s;
     }
     xb = xn;
   }
   delete w;
   for (int k = 0; k < nq; ++k) gq0[k] = double(xb[k]);
   for (int k = 0; k < tp.nv; ++k) gqd0[k] = double(xb[nq + k]);
+  *gmu = double(mu_acc);
 }
 
 }  // namespace
@@ -104,10 +109,10 @@ void emu_contact_rollout(int fp64, int n, const int* parent, const int* jtype, i
 void emu_contact_grad(int fp64, int n, const int* parent, const int* jtype, int nc, const int* clink, double mu,
                       double beta, int niter, const double* g, const double* P, const double* traj,
                       const double* tau, double dt, int T, const double* gqT, const double* gqdT, double* gq0,
-                      double* gqd0, double* gtau) {
+                      double* gqd0, double* gtau, double* gmu) {
   const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g);
-  if (fp64) grad<double>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau);
-  else grad<float>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau);
+  if (fp64) grad<double>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
+  else grad<float>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
 }
 
 }  // extern "C"

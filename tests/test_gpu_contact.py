@@ -5,8 +5,8 @@ gradient (Sec. 4.1 "Collision resolution"), through the C ABI
 * FP64 trajectories and contact counts element by element on sampled
   systems of a 256-quadruped landing batch and of a 64-tree batch (prismatic
   joints, random frames), to round-off;
-* FP64 gradients (q0, qd0, tau) against the oracle's, to round-off, through
-  touchdown;
+* FP64 gradients (q0, qd0, tau and the friction coefficient mu) against the
+  oracle's, to round-off, through touchdown;
 * FP32: the GPU's step from its own states against the oracle's step,
   within the bar the step's conditioning sets (1e-4, see the host test), and
   FP32 gradients against the oracle's on a short window;
@@ -108,15 +108,16 @@ def test_gradient_fp64_round_off(which):
     rng = np.random.default_rng(9)
     gqT = torch.tensor(rng.normal(size=(cb.nq, cb.B)), dtype=torch.float64, device=DEV)
     gqdT = torch.tensor(rng.normal(size=(cb.nv, cb.B)), dtype=torch.float64, device=DEV)
-    g = [x.cpu().numpy() for x in cb.grad(tr, tau, DT, gqT, gqdT)]
+    g = [x.cpu().numpy() for x in cb.grad(tr, tau, DT, gqT, gqdT, mu_grad=True)]
     worst = 0.0
     for i in (0, 7, len(draws) // 2, len(draws) - 1):
         m, C = _oracle(draws[i])
         d = draws[i]
         ref = O.rollout_contact_grad(m, C, d[1], d[2], d[3][:T], DT, gqT[:, i].cpu().numpy(),
-                                     gqdT[:, i].cpu().numpy())
+                                     gqdT[:, i].cpu().numpy(), mu_grad=True)
+        ref = ref[:3] + (np.array([ref[3]]),)
         scale = max(np.abs(r).max() for r in ref)
-        got = (g[0][:, i], g[1][:, i], g[2][:, :, i])
+        got = (g[0][:, i], g[1][:, i], g[2][:, :, i], g[3][i:i + 1])
         worst = max(worst, *[rel(a, b, 1e-6 * scale) for a, b in zip(got, ref)])
     print("worst gradient error %.1e" % worst)
     assert worst < 1e-8

@@ -51,10 +51,10 @@ def emu_grad(s, links, centers, radii, mu, beta, niter, tr, tau, dt, gqT, gqdT, 
     keep, a = _emu_args(s, links, centers, radii, mu, beta, niter)
     T = tau.shape[0]
     tau, gqT, gqdT = (np.ascontiguousarray(v, np.float64) for v in (tau, gqT, gqdT))
-    gq0, gqd0, gtau = np.zeros(s.nq), np.zeros(s.nv), np.zeros((T, s.nu))
+    gq0, gqd0, gtau, gmu = np.zeros(s.nq), np.zeros(s.nv), np.zeros((T, s.nu)), np.zeros(1)
     contact_emu().emu_contact_grad(int(fp64), *a, _p(np.ascontiguousarray(tr)), _p(tau), dt, T, _p(gqT), _p(gqdT),
-                                   _p(gq0), _p(gqd0), _p(gtau))
-    return gq0, gqd0, gtau
+                                   _p(gq0), _p(gqd0), _p(gtau), _p(gmu))
+    return gq0, gqd0, gtau, gmu
 
 
 def _scenes():
@@ -129,14 +129,15 @@ def test_gradient_fp64_matches_the_oracle(k):
     C = O.Contacts(links, centers, radii, mu=mu, beta=beta, niter=niter)
     rng = np.random.default_rng(k)
     gqT, gqdT = rng.normal(size=s.nq), rng.normal(size=s.nv)
-    ref = O.rollout_contact_grad(m, C, q0, qd0, tau, dt, gqT, gqdT)
+    ref = O.rollout_contact_grad(m, C, q0, qd0, tau, dt, gqT, gqdT, mu_grad=True)
+    ref = ref[:3] + (np.array([ref[3]]),)
     tr, nc = emu_rollout(s, links, centers, radii, mu, beta, niter, q0, qd0, tau, dt)
     got = emu_grad(s, links, centers, radii, mu, beta, niter, tr, tau, dt, gqT, gqdT)
     # an exactly zero block (a sticking inelastic contact erases qd0) is
     # compared against the gradient's overall scale
     scale = max(np.abs(r).max() for r in ref if r.size)
     e = [rel(g, r, 1e-6 * scale) for g, r in zip(got, ref)]
-    print(name, "gradient errors (q0, qd0, tau)", ["%.1e" % x for x in e], "contacts", np.bincount(nc))
+    print(name, "gradient errors (q0, qd0, tau, mu)", ["%.1e" % x for x in e], "contacts", np.bincount(nc))
     assert nc.max() >= 1
     assert max(e) < 1e-8
 

@@ -247,3 +247,47 @@ def test_rollout_gradient_with_contact_central_differences(mu):
         up[t, j] += h
         dn[t, j] -= h
         assert abs((L(q0, qd0, up) - L(q0, qd0, dn)) / (2 * h) - gtau[t, j]) < 1e-8 * scale
+
+
+def test_friction_gradient_of_a_sliding_point_mass_closed_form():
+    """A point mass sliding along x on the ground (contact at the centre of
+    mass, frictional box bound active every step) loses mu g dt of speed per
+    step: v_T = v_0 - T mu g dt and x_T = x_0 + dt sum_t v_t, so
+    dv_T/dmu = -T g dt and dx_T/dmu = -g dt^2 T (T + 1) / 2."""
+    T, dt, mu = 30, 1e-3, 0.4
+    m = O.Model(_ball(1.5))
+    C = O.Contacts([0], [[0.0, 0.0, 0.0]], [0.0], mu=mu, beta=0.0, niter=40)
+    q0 = np.array([0.0, -1e-4, 0.0, 0.0, 0.0, 0.0, 1.0])
+    qd0 = np.array([0.0, 0.0, 0.0, 2.0, 0.0, 0.0])
+    for k, expect in ((3, -T * G * dt), (0, -G * dt * dt * T * (T + 1) / 2)):
+        gq, gv = np.zeros(7), np.zeros(6)
+        if k == 3:
+            gv[3] = 1.0
+        else:
+            gq[0] = 1.0
+        *_, gmu = O.rollout_contact_grad(m, C, q0, qd0, np.zeros((T, 0)), dt, gq, gv, mu_grad=True)
+        assert abs(gmu - expect) < 1e-10 * abs(expect), (k, gmu, expect)
+
+
+def test_friction_gradient_central_differences():
+    """dL/dmu through a landing with friction against central differences
+    of the rollout in mu (persistent contact set over the window)."""
+    from paper_2109_07719_amd import synth
+    s, q0, qd0, tau, links, centers, radii = synth.landing_quadruped(3100, 60, drop=-0.002)
+    m = O.Model(s)
+    rng = np.random.default_rng(8)
+    wq, wv = rng.normal(size=s.nq), rng.normal(size=s.nv)
+    mu, h = 0.3, 1e-6
+
+    def L(mu_):
+        C_ = O.Contacts(links, centers, radii, mu=mu_, beta=0.2, niter=30)
+        x, y, n_ = O.rollout_contact(m, C_, q0, qd0, tau, 1e-3)
+        return wq @ x + wv @ y, n_
+
+    C = O.Contacts(links, centers, radii, mu=mu, beta=0.2, niter=30)
+    *_, gmu = O.rollout_contact_grad(m, C, q0, qd0, tau, 1e-3, wq, wv, mu_grad=True)
+    (lp, n1), (lm, n2) = L(mu + h), L(mu - h)
+    assert np.array_equal(n1, n2)
+    fd = (lp - lm) / (2 * h)
+    print("dL/dmu", gmu, "central differences", fd)
+    assert abs(gmu) > 1e-3 and abs(fd - gmu) < 1e-6 * max(1.0, abs(gmu))

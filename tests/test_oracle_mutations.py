@@ -95,8 +95,10 @@ MUTATIONS = [
     ("contact.inc", "fe[0] = cl[3 * c + 1] * f[2] - cl[3 * c + 2] * f[1];",
      "fe[0] = cl[3 * c + 2] * f[1] - cl[3 * c + 1] * f[2];", "contact moment arm sign"),
     ("contact.inc", "C->beta / dt * phi[i / 3]", "-C->beta / dt * phi[i / 3]", "Baumgarte sign"),
-    ("contact.inc", "lok[i] = -C->mu * lamn[ri / 3];\n        hik[i] = C->mu * lamn[ri / 3];",
-     "lok[i] = -C->mu;\n        hik[i] = C->mu;", "friction box not scaled by the normal impulse"),
+    ("contact.inc", "lok[i] = -mu * lamn[ri / 3];\n        hik[i] = mu * lamn[ri / 3];",
+     "lok[i] = -mu;\n        hik[i] = mu;", "friction box not scaled by the normal impulse"),
+    ("contact.inc", "lok[i] = -mu * lamn[ri / 3];", "lok[i] = -C->mu * lamn[ri / 3];",
+     "friction gradient misses the lower bound"),
     ("contact.inc", "s_ += J[(size_t)i * nv + k] * qd1[k];", "s_ += J[(size_t)i * nv + k] * qd[k];",
      "contact velocity before the smooth update"),
     ("contact.inc", "> 1e-12 * dmax) keep[nk++] = i;", ">= 0) keep[nk++] = i;", "zero rows kept in the solve"),
@@ -139,6 +141,7 @@ PINS = [
     contact.test_struck_pendulum_impulse_is_the_effective_mass_law,
     contact.test_baumgarte_pushes_out_at_beta_phi_over_dt,
     lambda: contact.test_rollout_gradient_with_contact_central_differences(0.8),
+    contact.test_friction_gradient_of_a_sliding_point_mass_closed_form,
 ]
 
 
