@@ -161,7 +161,7 @@ struct GradArgs {
 // one wave per system; lane j < nx + nu owns Jacobian column j, lane nx + nu
 // the friction coefficient's column (when gmu is asked for)
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_contact_grad(GradArgs<R> a) {
+__global__ __launch_bounds__(kBlock, 4) void k_contact_grad(GradArgs<R> a) {
   using D = Dual<R>;
   const int s = blockIdx.x, j = threadIdx.x;
   const CTopo& tp = a.tp;
