@@ -43,7 +43,8 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak (dual-issue); 78.6 without 
 
 
 KERNEL_SOURCES = ("csrc/spatial.h", "csrc/aba_lane.h", "csrc/dual.h", "csrc/abadj_device.h", "csrc/abadj_kernels.hip",
-                  "csrc/abadj_kernels_chain.hip", "_build.py")
+                  "csrc/abadj_kernels_bwd.hip", "csrc/abadj_kernels_bwd64.hip", "csrc/abadj_kernels_chain.hip",
+                  "_build.py")
 
 
 def kernel_source_hash():
@@ -69,7 +70,90 @@ def traffic_entry(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
+def host_threads():
+    """Host threads for the CPU legs: the cores this process may run on,
+    capped by the host's thread budget for the job (OMP_NUM_THREADS, which
+    the GPU host sets to its CPU share per GPU)."""
+    avail = len(os.sched_getaffinity(0))
+    cap = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return max(1, min(avail, cap) if cap > 0 else avail), avail
+
+
+def host_cpu():
+    import platform
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return cpu
+
+
+def along_errors(batch, grads, idx, trajs, threads, window=2000):
+    """Gradient errors of the GPU result on sampled systems against the FP64
+    oracle's adjoint sweep along the GPU's own trajectory (its states used
+    as the per-step checkpoints).  Returns per-system tuples (state/control
+    error, parameter-gradient error, largest exact gradient entry, error of
+    the control gradient over the last `window` steps, elementwise error of
+    the control gradient) or None for a diverged rollout."""
+    import oracle as O
+
+    qo, vo, uo = batch.offsets()
+    gq0, gqd0, gtau, gparam, gframe = grads
+    lo = np.cumsum([0] + [s.n for s in batch.systems])
+    window = min(batch.T, window)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-6))
+
+    def along(k):
+        i = idx[k]
+        if not np.isfinite(trajs[k]).all():
+            return None   # the rollout itself diverged (see the note)
+        m = O.Model(batch.systems[i], batch.gravity)
+        x0 = np.r_[batch.q0[qo[i]:qo[i + 1]], batch.qd0[vo[i]:vo[i + 1]]]
+        states = np.concatenate([x0[None], trajs[k][:-1]])
+        nqi = qo[i + 1] - qo[i]
+        tau = np.asarray(batch.tau[:, uo[i]:uo[i + 1]], dtype=np.float64)
+        g = O.adjoint_along_params(m, states, tau, batch.dt, 2 * trajs[k][-1, :nqi], np.zeros(vo[i + 1] - vo[i]))
+        size = max(float(np.abs(x).max()) if x.size else 0.0 for x in g[:3])
+        gt = gtau[:, uo[i]:uo[i + 1]]
+        e_win = rel(gt[-window:], g[2][-window:]) if gt.size else 0.0
+        e_elem = float(np.abs(gt - g[2]).max() / max(np.abs(g[2]).max(), 1e-30)) if gt.size else 0.0
+        e_par = (max(rel(gparam[lo[i]:lo[i + 1]], g[3]), rel(gframe[lo[i]:lo[i + 1]], g[4]))
+                 if gparam is not None else float("nan"))
+        return (max(rel(gq0[qo[i]:qo[i + 1]], g[0]), rel(gqd0[vo[i]:vo[i + 1]], g[1]), rel(gt, g[2])),
+                e_par, size, e_win, e_elem)
+
+    return O.map_threads(along, range(len(idx)), threads=threads)
+
+
+def summarise_along(both, window):
+    """Statistics of along_errors over the sample."""
+    diverged = sum(r is None for r in both)
+    # the exact gradient of a long chaotic rollout can exceed the FP32 range
+    fp32_max = float(np.finfo(np.float32).max)
+    fits = [r for r in both if r is not None and r[2] < 1e-3 * fp32_max]
+    beyond = sum(r is not None and r[2] >= 1e-3 * fp32_max for r in both)
+    e_along = np.asarray([r[0] for r in fits] or [float("nan")])
+    e_elem = [r[4] for r in fits] or [float("nan")]
+    e_window = [r[3] for r in both if r is not None and np.isfinite(r[3])] or [float("nan")]
+    return {"along_gpu_trajectory_max": float(e_along.max()),
+            "along_gpu_trajectory_median": float(np.median(e_along)),
+            "along_gpu_trajectory_p99": float(np.percentile(e_along, 99)),
+            "along_gpu_trajectory_frac_above_1e-3": float(np.mean(e_along > 1e-3)),
+            "along_gpu_trajectory_frac_above_1e-4": float(np.mean(e_along > 1e-4)),
+            "gtau_elementwise_along_gpu_trajectory_max": float(max(e_elem)),
+            "systems_compared": len(fits), "systems_diverged": diverged,
+            "systems_gradient_beyond_fp32_range": beyond,
+            f"gtau_last_{window}_steps_along_gpu_trajectory_max": float(max(e_window)),
+            f"gtau_last_{window}_steps_along_gpu_trajectory_median": float(np.median(e_window))}, fits
+
+
+def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads, avail):
     """The FP64 CPU oracle timed on this host's cores on a bounded sample of
     the same workload (whole systems, the full horizon, forward + adjoint).
     The same sampled systems give the gradient error of the GPU result:
@@ -95,16 +179,17 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
 
     # calibrate on one system, then size the sample to ~sample_seconds of wall time; the second
     # single-threaded run of system 0 gives the single-core figure
-    _, t1 = one(0)
-    _, t1 = one(0)
-    single_core = batch.systems[0].nv * batch.T / t1
-    per_round = max(t1, 1e-3)
-    n_sample = int(max(threads, min(n, threads * max(1, int(sample_seconds / per_round)))))
-    rng = np.random.default_rng(0)
-    idx = sorted(set([0, n - 1] + list(rng.choice(n, size=n_sample, replace=False))))[:n_sample]
-    t0 = time.perf_counter()
-    res = O.map_threads(one, idx, threads=threads)
-    wall = time.perf_counter() - t0
+    with O.use_library(O.build_native()):
+        _, t1 = one(0)
+        _, t1 = one(0)
+        single_core = batch.systems[0].nv * batch.T / t1
+        per_round = max(t1, 1e-3)
+        n_sample = int(max(threads, min(n, threads * max(1, int(sample_seconds / per_round)))))
+        rng = np.random.default_rng(0)
+        idx = sorted(set([0, n - 1] + list(rng.choice(n, size=n_sample, replace=False))))[:n_sample]
+        t0 = time.perf_counter()
+        res = O.map_threads(one, idx, threads=threads)
+        wall = time.perf_counter() - t0
     dof_steps = sum(batch.systems[i].nv for i in idx) * batch.T
 
     def rel(a, b):
@@ -118,72 +203,35 @@ def cpu_baseline_leg(batch, grads, gpu_traj_fn, sample_seconds, threads):
     e2e = e2e or [float("nan")]
     # adjoint along the GPU trajectory (not part of the timed baseline)
     trajs = gpu_traj_fn(idx)
-
     window = min(batch.T, 2000)
-
-    def along(k):
-        i = idx[k]
-        if not np.isfinite(trajs[k]).all():
-            return None   # the rollout itself diverged (see the note)
-        m = O.Model(batch.systems[i], batch.gravity)
-        x0 = np.r_[batch.q0[qo[i]:qo[i + 1]], batch.qd0[vo[i]:vo[i + 1]]]
-        states = np.concatenate([x0[None], trajs[k][:-1]])
-        nqi = qo[i + 1] - qo[i]
-        tau = np.asarray(batch.tau[:, uo[i]:uo[i + 1]], dtype=np.float64)
-        g = O.adjoint_along_params(m, states, tau, batch.dt, 2 * trajs[k][-1, :nqi], np.zeros(vo[i + 1] - vo[i]))
-        size = max(float(np.abs(x).max()) if x.size else 0.0 for x in g[:3])
-        gt = gtau[:, uo[i]:uo[i + 1]]
-        e_win = rel(gt[-window:], g[2][-window:]) if gt.size else 0.0
-        return (max(rel(gq0[qo[i]:qo[i + 1]], g[0]), rel(gqd0[vo[i]:vo[i + 1]], g[1]), rel(gt, g[2])),
-                max(rel(gparam[lo[i]:lo[i + 1]], g[3]), rel(gframe[lo[i]:lo[i + 1]], g[4])), size, e_win)
-
-    both = O.map_threads(along, range(len(idx)), threads=threads)
-    diverged = sum(r is None for r in both)
-    # the exact gradient of a long chaotic rollout can exceed the FP32 range
-    fp32_max = float(np.finfo(np.float32).max)
-    fits = [r for r in both if r is not None and r[2] < 1e-3 * fp32_max]
-    beyond = sum(r is not None and r[2] >= 1e-3 * fp32_max for r in both)
-    e_along = [r[0] for r in fits] or [float("nan")]
+    both = along_errors(batch, grads, idx, trajs, threads, window)
+    summ, fits = summarise_along(both, window)
     e_param = [r[1] for r in fits] or [float("nan")]
-    e_window = [r[3] for r in both if r is not None and np.isfinite(r[3])] or [float("nan")]
-    import platform
-    cpu = platform.processor() or platform.machine()
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    cpu = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
+    cpu = host_cpu()
     base = {"value": dof_steps / wall, "unit": "DOF-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(idx)} of {n} systems, full {batch.T}-step forward+adjoint each "
-                      f"(plain dense FP64 C oracle, K=1), {wall:.1f} s wall on {threads} threads, "
-                      f"host CPU: {cpu}",
+                      f"(plain dense FP64 C oracle built -O3 -march=native on this host, K=1), {wall:.1f} s wall "
+                      f"on {threads} threads of {avail} available, host CPU: {cpu}",
+            "host_cpu": cpu, "nproc": os.cpu_count(), "cores_available": avail,
             "single_core_value": single_core,
             "single_core_sample": f"system 0 ({batch.systems[0].nv} DOF), full {batch.T}-step forward+adjoint, "
                                   f"one thread, {t1:.2f} s"}
-    err = {"along_gpu_trajectory_max": max(e_along), "along_gpu_trajectory_median": float(np.median(e_along)),
-           "along_gpu_trajectory_p99": float(np.percentile(e_along, 99)),
-           "along_gpu_trajectory_frac_above_1e-3": float(np.mean(np.asarray(e_along) > 1e-3)),
-           "end_to_end_vs_fp64_max": max(e2e), "end_to_end_vs_fp64_median": float(np.median(e2e)),
-           "param_grads_along_gpu_trajectory_max": max(e_param),
-           "param_grads_what": "max over the inertial-parameter and the placement/axis gradients",
-           "param_grads_along_gpu_trajectory_median": float(np.median(e_param)),
-           "systems": len(idx), "norm": "per system ||g - g_ref|| / ||g_ref||, max over (gq0, gqd0, gtau)",
-           "systems_compared": len(fits), "systems_diverged": diverged,
-           "systems_gradient_beyond_fp32_range": beyond,
-           f"gtau_last_{window}_steps_along_gpu_trajectory_max": max(e_window),
-           f"gtau_last_{window}_steps_along_gpu_trajectory_median": float(np.median(e_window)),
-           "note": "end-to-end differences on long horizons come from chaotic divergence of FP32 and FP64 "
-                   "trajectories; along the GPU's own trajectory what remains is FP32 round-off of the "
-                   "adjoint recursion, amplified on the few systems whose adjoint grows fastest.  Systems whose "
-                   "rollout diverged under the integrator (the FP64 oracle's diverge alike) and systems whose "
-                   "exact gradient (FP64, along the GPU trajectory) exceeds the FP32 range are counted, not "
-                   "compared: the adjoint of a chaotic rollout grows exponentially backward in time.  The "
-                   "last-window figure compares the control gradient over the final steps, which every finite "
-                   "system can represent"}
-    return base, err
+    err = dict(summ)
+    err.update({"end_to_end_vs_fp64_max": max(e2e), "end_to_end_vs_fp64_median": float(np.median(e2e)),
+                "param_grads_along_gpu_trajectory_max": max(e_param),
+                "param_grads_what": "max over the inertial-parameter and the placement/axis gradients",
+                "param_grads_along_gpu_trajectory_median": float(np.median(e_param)),
+                "systems": len(idx), "norm": "per system ||g - g_ref|| / ||g_ref||, max over (gq0, gqd0, gtau); "
+                                             "elementwise: max |gtau - ref| / max |ref| per system",
+                "note": "end-to-end differences on long horizons come from chaotic divergence of FP32 and FP64 "
+                        "trajectories; along the GPU's own trajectory what remains is the rounding of the FP32 "
+                        "tape (the reverse passes run in FP64 unless adjoint_dtype says f32).  Systems whose "
+                        "rollout diverged under the integrator (the FP64 oracle's diverge alike) and systems whose "
+                        "exact gradient (FP64, along the GPU trajectory) exceeds the FP32 range are counted, not "
+                        "compared: the adjoint of a chaotic rollout grows exponentially backward in time.  The "
+                        "last-window figure compares the control gradient over the final steps, which every finite "
+                        "system can represent"})
+    return base, err, idx, trajs
 
 
 def memory_sweep(args, torch, dev, sim, b):
@@ -659,6 +707,8 @@ def main():
     ap.add_argument("--K", type=int, default=1, help="checkpoint interval")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 context leg")
+    ap.add_argument("--no-fp32-adjoint", action="store_true",
+                    help="skip the context leg with the adjoint's reverse passes in FP32")
     ap.add_argument("--dtype", choices=("f32", "f64"), default="f32",
                     help="compute type of the trajectory-optimisation leg (the benchmark line is FP32)")
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
@@ -813,6 +863,31 @@ def main():
         pev[k][1].record()
     torch.cuda.synchronize()
     bwd_params_ms = [pev[k][0].elapsed_time(pev[k][1]) for k in range(args.steps)]
+    # the same adjoint with its reverse passes in FP32 (context: faster, but
+    # it loses digits on long or chaotic rollouts; the headline runs them in
+    # FP64 from the FP32 tape)
+    adj32 = None
+    if not args.no_fp32_adjoint:
+        sim.set_adjoint_dtype(torch.float32)
+        g32 = [torch.empty_like(x) for x in (gq0, gqd0, gtau)]
+        graphs["fwd"].replay()
+        sim.backward(tau, dt, K, ws, gqT, gqdT, out=tuple(g32))
+        torch.cuda.synchronize()
+        gb32 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gb32):
+            sim.backward(tau, dt, K, ws, gqT, gqdT, out=tuple(g32))
+        for k in range(args.steps):
+            pev[k][0].record()
+            gb32.replay()
+            pev[k][1].record()
+        torch.cuda.synchronize()
+        b32_ms = float(np.mean([pev[k][0].elapsed_time(pev[k][1]) for k in range(args.steps)]))
+        adj32 = {"kernel_ms": b32_ms,
+                 "fwd_adjoint_dof_steps_per_s": b.total_dof * T / ((float(np.mean(fwd_ms)) + b32_ms) * 1e-3),
+                 "achieved_tflops": sim.flops(2) * T / (b32_ms * 1e-3) / 1e12,
+                 "grads": [x.cpu().numpy() for x in g32]}
+        sim.set_adjoint_dtype(torch.float64)
+        del gb32
     # leave the graphs' gradient buffers as the plain adjoint wrote them
     graphs["bwd"].replay()
     torch.cuda.synchronize()
@@ -845,7 +920,10 @@ def main():
     out = {"metric": "fwd+adjoint DOF-steps/sec (FP32, 1 GPU) vs plain fwd; grad rel err",
            "value": value, "unit": "DOF-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "ms_per_step_median": float(np.median(step_ms)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
+           "dtype": "f32", "adjoint_dtype": "f64" if sim.adjoint_dtype == torch.float64 else "f32",
+           "precision": "FP32 inputs, outputs, checkpoints, forward rollout and per-step recompute; the adjoint's "
+                        "reverse passes and the adjoint state carried between steps in FP64",
+           "data": "synthetic",
            "config": {"workload": WORKLOADS[args.workload], "systems": len(b.systems), "dof": b.total_dof,
                       "T": T, "dt": dt, "K": K, "lanes": sim.info["n_slots"], "waves": sim.info["n_waves"],
                       "lanes_per_system": "one lane per link", "tiling": sim.tiling,
@@ -861,7 +939,7 @@ def main():
            "peak_mem_bytes": int(peak_mem), "results_finite": finite, "nonfinite_outputs": nonfinite_outputs, "roofline": roofline,
            "wall_s_timed": wall, "input_gen_s": t_gen}
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
+        threads, avail = host_threads()
         traj_dev = torch.empty((T, sim.nq + sim.nv), dtype=torch.float32, device=dev)
         sim.forward(q0, qd0, tau, dt, K=K, workspace=None, traj=True, out=(pqT, pqdT, traj_dev))
         torch.cuda.synchronize()
@@ -874,12 +952,18 @@ def main():
                 out_.append(traj_dev[:, torch.from_numpy(cols).to(dev)].double().cpu().numpy())
             return out_
 
-        base, err = cpu_baseline_leg(b, grads, gpu_traj, args.cpu_sample_seconds, threads)
+        base, err, idx, trajs = cpu_baseline_leg(b, grads, gpu_traj, args.cpu_sample_seconds, threads, avail)
         del traj_dev
         out["cpu_baseline"] = base
         out["grad_rel_err"] = err
+        if adj32 is not None:
+            g32 = tuple(adj32.pop("grads")) + (None, None)
+            adj32["grad_rel_err"] = summarise_along(along_errors(b, g32, idx, trajs, threads), 2000)[0]
     else:
         out["cpu_baseline"] = None
+    if adj32 is not None:
+        adj32.pop("grads", None)
+    out["fp32_adjoint"] = adj32
     print(json.dumps(out))
 
 

@@ -49,9 +49,10 @@
  *   - The handle owns only its packed per-link constants (device memory
  *     allocated by sim_create, freed by sim_destroy).
  *   - sim_forward / sim_backward / sim_aba only enqueue work on `stream`
- *     (a hipStream_t; NULL = the default stream).  They never allocate,
- *     never synchronise and never memset, so they may be captured into a
- *     HIP graph.  Scratch memory is the caller's workspace.
+ *     (a hipStream_t; NULL = the default stream).  They never synchronise
+ *     and never memset, so they may be captured into a HIP graph; they
+ *     allocate nothing, except sim_backward's first call with a new binomial
+ *     schedule (K < 0, below).  Scratch memory is the caller's workspace.
  *
  * Errors: every entry point returns SIM_OK (0) or a negative code; no C++
  * exception crosses the ABI.  sim_last_error() returns a thread-local
@@ -135,6 +136,9 @@ typedef struct {
                               registers                                   */
   int32_t has_prism;      /* 1 if any joint is prismatic (the kernels then
                               use their general variant)                  */
+  int32_t adjoint_dtype;  /* arithmetic of sim_backward's recompute and
+                              reverse passes: SIM_F64, or SIM_F32 (FP32
+                              handles only; see sim_set_adjoint_dtype)    */
 } sim_info_t;
 
 /* Build a handle: validates the topology and parameters, orders every
@@ -152,6 +156,24 @@ int sim_create(const sim_topology *topo, const sim_params *params, int dtype, si
 void sim_destroy(sim_t h);
 
 int sim_get_info(sim_t h, sim_info_t *out);
+
+/* Arithmetic of the backward pass (Sec. 3, Eq. adj_back; Sec. 4.1, Eq.
+ * adj_r; Sec. 4.2).  An FP32 handle keeps its inputs, outputs, checkpoints
+ * and forward rollout in FP32 (segment replays for K > 1 and binomial
+ * advances also run the FP32 step, so they reproduce the forward's states
+ * bit for bit).  With SIM_F64 (the default) each step's intermediates are
+ * recomputed in FP64 from the exactly widened FP32 state and control, the
+ * reverse sweeps through the adjoints of the integrator and the three ABA
+ * passes run in FP64, and so does the adjoint state carried from step to
+ * step; the outputs are rounded to FP32 once.  The result is the gradient
+ * of the step map along the FP32 trajectory to FP64 round-off (store-all,
+ * K == 0, reverses the FP32 intermediates it stored).  SIM_F32 runs the
+ * whole backward pass in FP32: faster, but on long chains and chaotic
+ * rollouts the reverse recursion loses digits (gradient errors of 1e-3 and
+ * more).  FP64 handles accept SIM_F64 only.  Takes effect for later
+ * sim_backward calls (and graphs captured after the change).  Errors:
+ * SIM_ERR_INVALID_ARG (null handle), SIM_ERR_UNSUPPORTED_DTYPE. */
+int sim_set_adjoint_dtype(sim_t h, int dtype);
 
 /* Health of the results: *nonfinite_count receives the number of
  * non-finite numbers (NaN or infinity) that the kernels enqueued on this
@@ -254,9 +276,12 @@ int sim_forward(sim_t h, const void *q0, const void *qd0, const void *tau, doubl
  * accumulated): gq0 [nq], gqd0 [nv], gtau [T][nu].  Reads the checkpoints
  * in the workspace and, for K > 1, uses the rest of it as replay scratch.
  * For K < 0 it runs the binomial schedule of sim_checkpoint_schedule(T, -K)
- * with the workspace's snapshot slots; the schedule is built and uploaded
- * (synchronously) on the first call with a new (T, K) and cached on the
- * handle, so that first call must not be made during stream capture.
+ * with the workspace's snapshot slots; the schedule is built on the host on
+ * the first call with a new (T, K), uploaded into device memory of the
+ * handle (one allocation, an upload ordered on `stream`) and kept, one
+ * buffer per (T, K), until sim_destroy, so that first call allocates and
+ * must not be made during stream capture; later calls with that (T, K)
+ * allocate nothing and may be captured.
  * For a free root, gq0's quaternion entries are the gradient with respect
  * to the raw components under the rotation formula
  * R = (w^2 - u.u) I + 2 u u^T + 2 w [u]x; only their component tangent to

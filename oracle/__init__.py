@@ -33,6 +33,20 @@ def build(force: bool = True) -> str:
     return LIB_PATH
 
 
+NATIVE_LIB_PATH = os.path.join(_HERE, "liboracle_native.so")
+
+
+def build_native() -> str:
+    """The same oracle sources optimised for the host it is built on (-O3
+    -march=native), for timing the CPU baseline; FP contraction stays off so
+    that its arithmetic rounds as the portable build's does."""
+    tmp = NATIVE_LIB_PATH + f".{os.getpid()}.tmp"
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared",
+                           "-o", tmp, *SOURCES, "-lm"])
+    os.replace(tmp, NATIVE_LIB_PATH)
+    return NATIVE_LIB_PATH
+
+
 _lib = None
 
 

@@ -23,6 +23,8 @@ HIPCC_FLAGS = [
 # Translation units (compiled in parallel) and any options of their own.
 UNITS = [
     ("abadj_kernels.hip", []),
+    ("abadj_kernels_bwd.hip", []),
+    ("abadj_kernels_bwd64.hip", []),
     ("abadj_kernels_chain.hip", []),
     ("abadj_runtime.hip", []),
     ("pgs.hip", []),

@@ -24,7 +24,8 @@ SIM_JOINT_FREE = 1
 SIM_JOINT_PRISMATIC = 2
 SIM_MAX_LINKS = 64
 
-EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_status", "sim_get_tiling", "sim_set_tiling", "sim_autotune",
+EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_set_adjoint_dtype", "sim_status", "sim_get_tiling",
+            "sim_set_tiling", "sim_autotune",
             "sim_workspace_bytes",
             "sim_checkpoint_schedule", "sim_forward", "sim_forward_jvp",
             "sim_backward", "sim_aba", "sim_flops", "sim_last_error",
@@ -47,7 +48,7 @@ class SimParams(ctypes.Structure):
 class SimInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_sys", "n_links", "nq", "nv", "nu", "n_waves",
                                                "n_slots", "max_depth", "has_free", "dtype",
-                                               "frames_identity", "chain", "has_prism")]
+                                               "frames_identity", "chain", "has_prism", "adjoint_dtype")]
 
 
 class SimTiling(ctypes.Structure):
@@ -79,6 +80,8 @@ def lib():
         L.sim_destroy.restype = None
         L.sim_get_info.argtypes = [P, ctypes.POINTER(SimInfo)]
         L.sim_get_info.restype = I
+        L.sim_set_adjoint_dtype.argtypes = [P, I]
+        L.sim_set_adjoint_dtype.restype = I
         L.sim_get_tiling.argtypes = [P, ctypes.POINTER(SimTiling)]
         L.sim_get_tiling.restype = I
         L.sim_set_tiling.argtypes = [P, ctypes.POINTER(SimTiling)]

@@ -67,6 +67,67 @@ struct Tape {
   S qdd;
 };
 
+// Exact conversion of a link's constants and step intermediates to a wider
+// scalar type, for an adjoint that runs in FP64 from an FP32 forward: the
+// reverse passes then see exactly the numbers the forward computed.
+template <typename R, typename S>
+ABA_HD V3<R> widen(const V3<S>& v) {
+  return v3<R>(R(v.x), R(v.y), R(v.z));
+}
+template <typename R, typename S>
+ABA_HD V6<R> widen(const V6<S>& v) {
+  return v6<R>(widen<R>(v.a), widen<R>(v.l));
+}
+template <typename R, typename S>
+ABA_HD M3<R> widen(const M3<S>& M) {
+  M3<R> W;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) W.m[k] = R(M.m[k]);
+  return W;
+}
+template <typename R, typename S>
+ABA_HD Sy3<R> widen(const Sy3<S>& M) {
+  return sy3<R>(R(M.xx), R(M.yy), R(M.zz), R(M.xy), R(M.xz), R(M.yz));
+}
+template <typename R, typename S>
+ABA_HD SySp<R> widen(const SySp<S>& M) {
+  SySp<R> W;
+  W.A = widen<R>(M.A);
+  W.B = widen<R>(M.B);
+  W.C = widen<R>(M.C);
+  return W;
+}
+template <typename R, typename S>
+ABA_HD LinkC<R> widen(const LinkC<S>& L) {
+  LinkC<R> W;
+  W.ET = widen<R>(L.ET);
+  W.rT = widen<R>(L.rT);
+  W.sm = widen<R>(L.sm);
+  W.prism = L.prism;
+  W.m = R(L.m);
+  W.mc = widen<R>(L.mc);
+  W.Ib = widen<R>(L.Ib);
+  return W;
+}
+template <typename R, typename S>
+ABA_HD Tape<R> widen(const Tape<S>& t) {
+  Tape<R> W;
+  W.sq = R(t.sq);
+  W.cq = R(t.cq);
+  W.E = widen<R>(t.E);
+  W.v = widen<R>(t.v);
+  W.c = widen<R>(t.c);
+  W.IA = widen<R>(t.IA);
+  W.pA = widen<R>(t.pA);
+  W.U = widen<R>(t.U);
+  W.Dinv = R(t.Dinv);
+  W.u = R(t.u);
+  W.pa = widen<R>(t.pa);
+  W.ap = widen<R>(t.ap);
+  W.qdd = R(t.qdd);
+  return W;
+}
+
 // X = X_J(q) X_T = (E, r) for a joint about or along the link's z axis
 // (the host rotates every link frame so that its joint axis is e_z), from
 // the tape's joint coordinate.

@@ -370,23 +370,23 @@ __device__ __forceinline__ void get_slot(State<S, FREE>& s, const S* base, int n
 // mc' = Rl mc and Ib' = Rl Ib Rl^T, so mc_bar = Rl^T mc'_bar and, with the
 // symmetric matrix G of the Ib adjoint (off-diagonals halved), G = Rl^T G' Rl.
 // Returns the number of non-finite values written.
-template <typename S>
-__device__ __forceinline__ int store_param_bar(const ParamBar<S>& g, const Packed<S>& P, const Lane& l,
-                                               S* out) {
+template <typename Sp, typename S>
+__device__ __forceinline__ int store_param_bar(const ParamBar<S>& g, const Packed<Sp>& P, const Lane& l,
+                                               Sp* out) {
   const int ns = P.nslots;
   M3<S> Rl;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) Rl.m[k] = P.cf[(CF_RL + k) * ns + l.slot];
+  for (int k = 0; k < 9; ++k) Rl.m[k] = S(P.cf[(CF_RL + k) * ns + l.slot]);
   const V3<S> mc = mulT(Rl, g.mc);
   const Sy3<S> G = congT(Rl, sy3<S>(g.Ib.xx, g.Ib.yy, g.Ib.zz, S(0.5) * g.Ib.xy, S(0.5) * g.Ib.xz,
                                       S(0.5) * g.Ib.yz));
   const S v[10] = {g.m, mc.x, mc.y, mc.z, G.xx, G.yy, G.zz, S(2) * G.xy, S(2) * G.xz, S(2) * G.yz};
-  S* o = out + (size_t)l.link * 10;
+  Sp* o = out + (size_t)l.link * 10;
   int n = 0;
 #pragma unroll
   for (int k = 0; k < 10; ++k) {
-    o[k] = v[k];
-    n += nonfinite(v[k]);
+    o[k] = Sp(v[k]);
+    n += nonfinite(o[k]);
   }
   return n;
 }
@@ -399,9 +399,9 @@ __device__ __forceinline__ int store_param_bar(const ParamBar<S>& g, const Packe
 // Rp^T E_T'^T xi'_l.  The axis rotation adjoint is w = Rl^T (xi'_a + w'),
 // and the gradient along the unit sphere is w x a = Rl^T ((xi'_a + w') x e_z).
 // A free root has none: zeros.  Returns the number of non-finite values.
-template <typename S>
-__device__ __forceinline__ int store_frame_bar(const ParamBar<S>& g, const Packed<S>& P, const Lane& l,
-                                               const LinkC<S>& L, S* out) {
+template <typename Sp, typename S>
+__device__ __forceinline__ int store_frame_bar(const ParamBar<S>& g, const Packed<Sp>& P, const Lane& l,
+                                               const LinkC<S>& L, Sp* out) {
   const int ns = P.nslots;
   S v[9];
 #pragma unroll
@@ -409,10 +409,10 @@ __device__ __forceinline__ int store_frame_bar(const ParamBar<S>& g, const Packe
   if (l.onedof()) {
     M3<S> Rl, Rp;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Rl.m[k] = P.cf[(CF_RL + k) * ns + l.slot];
+    for (int k = 0; k < 9; ++k) Rl.m[k] = S(P.cf[(CF_RL + k) * ns + l.slot]);
     const int ps = l.slot - l.lane + l.par;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Rp.m[k] = (l.par >= 0) ? P.cf[(CF_RL + k) * ns + ps] : ((k % 4 == 0) ? S(1) : S(0));
+    for (int k = 0; k < 9; ++k) Rp.m[k] = (l.par >= 0) ? S(P.cf[(CF_RL + k) * ns + ps]) : ((k % 4 == 0) ? S(1) : S(0));
     const V3<S> phi = mulT(Rl, g.xi.a);
     const V3<S> rb = mulT(Rp, mulT(L.ET, g.xi.l));
     const V3<S> w = g.xi.a + g.w;
@@ -421,12 +421,12 @@ __device__ __forceinline__ int store_frame_bar(const ParamBar<S>& g, const Packe
     v[3] = rb.x; v[4] = rb.y; v[5] = rb.z;
     v[6] = ab.x; v[7] = ab.y; v[8] = ab.z;
   }
-  S* o = out + (size_t)l.link * 9;
+  Sp* o = out + (size_t)l.link * 9;
   int n = 0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
-    o[k] = v[k];
-    n += nonfinite(v[k]);
+    o[k] = Sp(v[k]);
+    n += nonfinite(o[k]);
   }
   return n;
 }
@@ -470,18 +470,20 @@ __device__ __forceinline__ T limit_tau(const Packed<S>& P, const Lane& l, const 
   return tau;
 }
 // its partial derivatives with respect to q and qd (zero inside the range)
-template <int FR, typename S, bool FREE>
-__device__ __forceinline__ void limit_slopes(const Packed<S>& P, const Lane& l, const State<S, FREE>& st, S& dq,
-                                             S& dqd) {
-  dq = dqd = S(0);
+// (T: the adjoint's scalar type; the switch compares the same values as the
+// forward's, widened exactly)
+template <int FR, typename S, typename T, bool FREE>
+__device__ __forceinline__ void limit_slopes(const Packed<S>& P, const Lane& l, const State<T, FREE>& st, T& dq,
+                                             T& dqd) {
+  dq = dqd = T(0);
   if constexpr (FR != kFrGeneralJoints) return;
   if (!P.has_limits || !l.onedof()) return;
   const int ns = P.nslots;
-  const S q = st.q[0];
+  const T q = st.q[0];
   const int slot = opaque_slot(l);
-  if (q > P.cf[(CF_LIM + 1) * ns + slot] || q < P.cf[(CF_LIM + 0) * ns + slot]) {
-    dq = -P.cf[(CF_LIM + 2) * ns + slot];
-    dqd = -P.cf[(CF_LIM + 3) * ns + slot];
+  if (q > T(P.cf[(CF_LIM + 1) * ns + slot]) || q < T(P.cf[(CF_LIM + 0) * ns + slot])) {
+    dq = -T(P.cf[(CF_LIM + 2) * ns + slot]);
+    dqd = -T(P.cf[(CF_LIM + 3) * ns + slot]);
   }
 }
 
@@ -491,6 +493,23 @@ struct Step {
   Tape<S> t;
   V6<S> abase;  // free root: true body-frame acceleration
 };
+template <typename R, typename S>
+__device__ __forceinline__ Step<R> cvt_step(const Step<S>& o) {
+  Step<R> w;
+  w.t = widen<R>(o.t);
+  w.abase = widen<R>(o.abase);
+  return w;
+}
+// (also narrows the adjoint state back to the I/O type at the end)
+template <typename R, typename S, bool FREE>
+__device__ __forceinline__ State<R, FREE> cvt_state(const State<S, FREE>& x) {
+  State<R, FREE> w;
+#pragma unroll
+  for (int k = 0; k < (FREE ? 7 : 1); ++k) w.q[k] = R(x.q[k]);
+#pragma unroll
+  for (int k = 0; k < (FREE ? 6 : 1); ++k) w.qd[k] = R(x.qd[k]);
+  return w;
+}
 
 // Step intermediates handed to the reverse passes (store-all records in HBM
 // and the pipelined adjoint's LDS tape), per lane slot, [field][stride]:
@@ -753,54 +772,57 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
 
 // One reverse step: recompute the ABA intermediates of step t from its
 // initial state st, then run the adjoints of the integrator, pass 3, pass 2
-// and pass 1.  xb1 holds the adjoint of x^{t+1} on entry and that of x^t on
+// and pass 1, in the scalar type R (S, or FP64 for an FP32 forward: in FP32
+// the reverse sweeps lose digits on long chains, and the rounding of FP32
+// intermediates is amplified by the adjoints of chaotic rollouts).  xb1 holds the adjoint of x^{t+1} on entry and that of x^t on
 // exit; tau_bar^t is written to gtau.
-template <typename S, bool FREE, int FR, bool CHAIN, bool PARAMS>
-__device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, const LinkC<S>& L, int maxd,
-                                            S* xb, const State<S, FREE>& st, const Step<S>& o, int t,
-                                            State<S, FREE>& xb1, int& nonfin, ParamBar<S>& pg) {
+template <typename S, typename R, bool FREE, int FR, bool CHAIN, bool PARAMS>
+__device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, const LinkC<R>& L, int maxd,
+                                            R* xb, const State<R, FREE>& st, const Step<R>& o, int t,
+                                            State<R, FREE>& xb1, int& nonfin, ParamBar<R>& pg) {
   const bool act = l.active();
   const bool rev = l.onedof();
-  const V3<S> g = v3<S>(A.P.g[0], A.P.g[1], A.P.g[2]);
-  const Tape<S>& tp = o.t;
+  const V3<R> g = v3<R>(R(A.P.g[0]), R(A.P.g[1]), R(A.P.g[2]));
+  const R dt = R(A.dt);
+  const Tape<R>& tp = o.t;
 
   // adjoint of the integrator
-  S acc_q = S(0), acc_qd = S(0), qddb = S(0);
-  V6<S> qddb6 = zero6<S>();
-  V3<S> pb = zero3<S>();
-  Q4<S> quatb = {S(0), S(0), S(0), S(0)};
-  V6<S> vb6 = zero6<S>();
+  R acc_q = R(0), acc_qd = R(0), qddb = R(0);
+  V6<R> qddb6 = zero6<R>();
+  V3<R> pb = zero3<R>();
+  Q4<R> quatb = {R(0), R(0), R(0), R(0)};
+  V6<R> vb6 = zero6<R>();
   if (rev) {
-    const S tot = xb1.qd[0] + A.dt * xb1.q[0];
-    qddb = A.dt * tot;
+    const R tot = xb1.qd[0] + dt * xb1.q[0];
+    qddb = dt * tot;
     acc_q = xb1.q[0];
     acc_qd = tot;
   } else if constexpr (FREE) {
     if (l.jtype == 1) {
-      pb = v3<S>(xb1.q[0], xb1.q[1], xb1.q[2]);
+      pb = v3<R>(xb1.q[0], xb1.q[1], xb1.q[2]);
       quatb.x = xb1.q[3]; quatb.y = xb1.q[4]; quatb.z = xb1.q[5]; quatb.w = xb1.q[6];
       vb6 = st_vel6(xb1);
-      const V6<S> v = st_vel6(st);
-      qddb6 = integrate_root_adj(st_quat(st), v, o.abase, A.dt, pb, quatb, vb6);
+      const V6<R> v = st_vel6(st);
+      qddb6 = integrate_root_adj(st_quat(st), v, o.abase, dt, pb, quatb, vb6);
       // the Galilean shift's term of the root acceleration, -w x v_lin
       vb6.a = vb6.a + cross(qddb6.l, v.l);
       vb6.l = vb6.l + cross(v.a, qddb6.l);
     }
   }
-  Bar<S> b;
+  Bar<R> b;
   bar_zero(b, PARAMS);
   // Each reverse sweep keeps only what a parent or child needs inside the
   // level loop; the statements that update a link's own accumulators run
   // once for all lanes outside it.
   // reverse of pass 3, leaves -> root
-  SySp<S> IAb = zero_sysp<S>();
-  V6<S> pAb = zero6<S>();
-  V6<S> apb = zero6<S>();
-  S g3 = S(0);
+  SySp<R> IAb = zero_sysp<R>();
+  V6<R> pAb = zero6<R>();
+  V6<R> apb = zero6<R>();
+  R g3 = R(0);
   if constexpr (CHAIN) {
-    V6<S> up = zero6<S>();
+    V6<R> up = zero6<R>();
     for (int d = maxd; d >= 0; --d) {
-      const V6<S> ab = from_next(up);
+      const V6<R> ab = from_next(up);
       if (act && l.depth == d) {
         apb = r3_path(L, tp, ab, qddb, g3);
         if (l.par >= 0) up = xformT(tp.E, joint_r(L, tp), apb);
@@ -809,7 +831,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
   } else {
     for (int d = maxd; d >= 0; --d) {
       if (act && l.depth == d) {
-        V6<S> ab = zero6<S>();
+        V6<R> ab = zero6<R>();
         for (int k = 0; k < l.ccount; ++k) ab = ab + get6(xb, 0, l.cfirst + k);
         if (rev) {
           apb = r3_path(L, tp, ab, qddb, g3);
@@ -823,13 +845,13 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
   }
   if (rev) r3_local(L, tp, b, apb, g3);
   // reverse of pass 2, root -> leaves
-  S taub = S(0);
-  SySp<S> N = zero_sysp<S>();
-  V6<S> pab = zero6<S>();
+  R taub = R(0);
+  SySp<R> N = zero_sysp<R>();
+  V6<R> pab = zero6<R>();
   if constexpr (CHAIN) {
     for (int d = 0; d <= maxd; ++d) {
-      const SySp<S> IAbp = from_prev(IAb);
-      const V6<S> pAbp = from_prev(pAb);
+      const SySp<R> IAbp = from_prev(IAb);
+      const V6<R> pAbp = from_prev(pAb);
       if (act && l.depth == d) taub = r2_path(L, tp, b, l.par >= 0, IAbp, pAbp, N, pab, IAb, pAb);
     }
   } else {
@@ -837,8 +859,8 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
       if (act && l.depth == d) {
         if (rev) {
           const bool hp = l.par >= 0;
-          const SySp<S> IAbp = hp ? get21(xb, 0, l.par) : zero_sysp<S>();
-          const V6<S> pAbp = hp ? get6(xb, 21, l.par) : zero6<S>();
+          const SySp<R> IAbp = hp ? get21(xb, 0, l.par) : zero_sysp<R>();
+          const V6<R> pAbp = hp ? get6(xb, 21, l.par) : zero6<R>();
           taub = r2_path(L, tp, b, hp, IAbp, pAbp, N, pab, IAb, pAb);
         }
         put21(xb, 0, l.lane, IAb);
@@ -853,12 +875,12 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
     if (A.gparam != nullptr && act) param_bar_add(pg, IAb, tp.v, pAb);
   }
   // reverse of pass 1, leaves -> root
-  const V6<S> own = act ? r1_own(L, tp.v, b, pAb, st.qd[0], rev) : zero6<S>();
-  V6<S> vbar = zero6<S>();
+  const V6<R> own = act ? r1_own(L, tp.v, b, pAb, st.qd[0], rev) : zero6<R>();
+  V6<R> vbar = zero6<R>();
   if constexpr (CHAIN) {
-    V6<S> up = zero6<S>();
+    V6<R> up = zero6<R>();
     for (int d = maxd; d >= 0; --d) {
-      const V6<S> vb = from_next(up);
+      const V6<R> vb = from_next(up);
       if (act && l.depth == d) {
         vbar = vb + own;
         if (l.par >= 0) up = xformT(tp.E, joint_r(L, tp), vbar);
@@ -867,7 +889,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
   } else {
     for (int d = maxd; d >= 0; --d) {
       if (act && l.depth == d) {
-        V6<S> vb = zero6<S>();
+        V6<R> vb = zero6<R>();
         for (int k = 0; k < l.ccount; ++k) vb = vb + get6(xb, 0, l.cfirst + k);
         vbar = vb + own;
         if (rev) {
@@ -891,12 +913,13 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
   // adjoint of the step's initial state; tau_bar (the joint-limit torque
   // adds its slopes times u_bar)
   if (rev) {
-    S lq, lqd;
+    R lq, lqd;
     limit_slopes<FR>(A.P, l, st, lq, lqd);
     xb1.q[0] = acc_q + b.q + lq * taub;
     xb1.qd[0] = acc_qd + b.qd + lqd * taub;
-    A.gtau[(size_t)t * A.P.nu + l.uidx] = taub;
-    nonfin += nonfinite(taub);
+    const S taub_out = S(taub);
+    A.gtau[(size_t)t * A.P.nu + l.uidx] = taub_out;
+    nonfin += nonfinite(taub_out);
   } else if constexpr (FREE) {
     if (l.jtype == 1) {
       xb1.q[0] = pb.x; xb1.q[1] = pb.y; xb1.q[2] = pb.z;
@@ -910,19 +933,60 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
     const S* row = A.gtraj + (size_t)(t - 1) * (A.P.nq + A.P.nv);
     load_state(gt, l, row, row + A.P.nq);
 #pragma unroll
-    for (int k = 0; k < (FREE ? 7 : 1); ++k) xb1.q[k] += gt.q[k];
+    for (int k = 0; k < (FREE ? 7 : 1); ++k) xb1.q[k] += R(gt.q[k]);
 #pragma unroll
-    for (int k = 0; k < (FREE ? 6 : 1); ++k) xb1.qd[k] += gt.qd[k];
+    for (int k = 0; k < (FREE ? 6 : 1); ++k) xb1.qd[k] += R(gt.qd[k]);
   }
 }
 
-template <typename S, bool FREE, int FR, bool CHAIN, bool PARAMS>
-__device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, const LinkC<S>& L, int maxd,
-                                         S* xb, const State<S, FREE>& st, S tau, int t, State<S, FREE>& xb1,
-                                         int& nonfin, ParamBar<S>& pg) {
-  Step<S> o;
-  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
-  bwd_reverse<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
+// One adjoint step from the stored state st (in the forward's type S): the
+// step's intermediates are recomputed in R from the exactly widened state
+// and control, then reversed in R.  With R = double for an FP32 forward the
+// gradient is that of the step map at the FP32 trajectory's states to FP64
+// round-off; only the outputs are rounded to FP32.  xb is sized for R.
+template <typename S, typename R, bool FREE, int FR, bool CHAIN, bool PARAMS>
+__device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, const LinkC<R>& LR, int maxd,
+                                         S* xb, const State<S, FREE>& st, S tau, int t, State<R, FREE>& xb1,
+                                         int& nonfin, ParamBar<R>& pg) {
+  R* const xr = reinterpret_cast<R*>(xb);
+  const State<R, FREE> sr = cvt_state<R>(st);
+  Step<R> o;
+  aba_wave<R, FREE, CHAIN>(widen<R>(gravity(A.P)), l, LR, sr, limit_tau<FR>(A.P, l, sr, R(tau)), maxd, xr, o);
+  bwd_reverse<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xr, sr, o, t, xb1, nonfin, pg);
+}
+
+// Adjoint of x^T (plus the trajectory seed of the last step) in R.
+template <typename S, typename R, bool FREE>
+__device__ __forceinline__ State<R, FREE> seed_state(const BwdArgs<S>& A, const Lane& l) {
+  State<S, FREE> x = {};
+  if (l.active()) {
+    load_state(x, l, A.gqT, A.gqdT);
+    if (A.gtraj != nullptr && A.T > 0) {
+      State<S, FREE> gt;
+      const S* row = A.gtraj + (size_t)(A.T - 1) * (A.P.nq + A.P.nv);
+      load_state(gt, l, row, row + A.P.nq);
+#pragma unroll
+      for (int k = 0; k < (FREE ? 7 : 1); ++k) x.q[k] += gt.q[k];
+#pragma unroll
+      for (int k = 0; k < (FREE ? 6 : 1); ++k) x.qd[k] += gt.qd[k];
+    }
+  }
+  return cvt_state<R>(x);
+}
+
+// Writes the adjoints of x^0 and the model-parameter gradients; returns the
+// number of non-finite values written.
+template <typename S, typename R, bool FREE, bool PARAMS>
+__device__ __forceinline__ int store_adjoint(const BwdArgs<S>& A, const Lane& l, const LinkC<S>& L,
+                                             const State<R, FREE>& xb1, const ParamBar<R>& pg) {
+  const State<S, FREE> x0 = cvt_state<S>(xb1);
+  store_state(x0, l, A.gq0, A.gqd0);
+  int n = nonfinite_state(x0, l);
+  if constexpr (PARAMS) {
+    if (A.gparam != nullptr) n += store_param_bar(pg, A.P, l, A.gparam);
+    if (A.gframe != nullptr) n += store_frame_bar(pg, A.P, l, widen<R>(L), A.gframe);
+  }
+  return n;
 }
 
 // Backward (adjoint) rollout, reverse time.  K == 1 reloads every step's
@@ -935,10 +999,12 @@ __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, con
 // Free-root batches pack few lanes per system and run at most one
 // wavefront per SIMD; FP64 would spill heavily under the limit.
 // PARAMS: the variant that also accumulates model-parameter gradients.
-template <typename S, bool FREE, int FR, bool CHAIN, bool PARAMS>
+// R: the scalar type of the reverse passes (see bwd_reverse); the exchange
+// buffer is sized for it.
+template <typename S, typename R, bool FREE, int FR, bool CHAIN, bool PARAMS>
 __global__ __launch_bounds__(kWave * kMaxWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_backward(BwdArgs<S> A) {
-  S* xb = CHAIN ? nullptr : lds<S>() + wave_in_block() * (XB * kWave);
+__attribute__((amdgpu_waves_per_eu((FREE || sizeof(R) > 4) ? 1 : 2))) void k_backward(BwdArgs<S> A) {
+  S* xb = CHAIN ? nullptr : reinterpret_cast<S*>(lds<R>() + wave_in_block() * (XB * kWave));
   const int wb = wave_batch();
   const Lane l = load_lane(A.P, wb);
   const int maxd = A.P.wmaxd[wb];
@@ -949,22 +1015,11 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
   const LinkC<S> L = load_linkc<S, FR>(A.P, l);
+  const LinkC<R> LR = widen<R>(L);
   int nonfin = 0;  // non-finite outputs
-  ParamBar<S> pg;
+  ParamBar<R> pg;
   param_bar_zero(pg);
-  State<S, FREE> xb1 = {};
-  if (act) {
-    load_state(xb1, l, A.gqT, A.gqdT);
-    if (A.gtraj != nullptr && A.T > 0) {
-      State<S, FREE> gt;
-      const S* row = A.gtraj + (size_t)(A.T - 1) * (A.P.nq + A.P.nv);
-      load_state(gt, l, row, row + A.P.nq);
-#pragma unroll
-      for (int k = 0; k < (FREE ? 7 : 1); ++k) xb1.q[k] += gt.q[k];
-#pragma unroll
-      for (int k = 0; k < (FREE ? 6 : 1); ++k) xb1.qd[k] += gt.qd[k];
-    }
-  }
+  State<R, FREE> xb1 = seed_state<S, R, FREE>(A, l);
   if (A.K == 0) {
     // store-all: read every step's intermediates instead of recomputing
     for (int t = A.T - 1; t >= 0; --t) {
@@ -975,7 +1030,9 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         get_slot(st, row, ns, nf, l.slot, l.fidx);
         get_tape(o, row + RW, ns, l.slot, L, st.qd[0], rev);
       }
-      bwd_reverse<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
+      // the stored intermediates are the forward's (type S), widened
+      bwd_reverse<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, reinterpret_cast<R*>(xb), cvt_state<R>(st),
+                                                 cvt_step<R>(o), t, xb1, nonfin, pg);
     }
   } else if (A.K == 1) {
     State<S, FREE> nxt = {};
@@ -991,7 +1048,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
         if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
       }
-      bwd_step<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, st, tau, t, xb1, nonfin, pg);
+      bwd_step<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xb, st, tau, t, xb1, nonfin, pg);
     }
   } else if (A.K < 0) {
     // binomial checkpointing: every wave runs the same host-built schedule
@@ -1015,7 +1072,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
         if (act) put_slot(cur, A.ck + (size_t)slot * RW, ns, nf, l.slot, l.fidx);
       } else {
         const S tau = rev ? A.tau[(size_t)arg * nu + l.uidx] : S(0);
-        bwd_step<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, cur, tau, arg, xb1, nonfin, pg);
+        bwd_step<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xb, cur, tau, arg, xb1, nonfin, pg);
       }
     }
   } else {
@@ -1050,21 +1107,11 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
           if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
-        bwd_step<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, cur, tau, t, xb1, nonfin, pg);
+        bwd_step<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xb, cur, tau, t, xb1, nonfin, pg);
       }
     }
   }
-  if (act) {
-    store_state(xb1, l, A.gq0, A.gqd0);
-    nonfin += nonfinite_state(xb1, l);
-    if constexpr (PARAMS) {
-      if constexpr (PARAMS) {
-        if (A.gparam != nullptr) nonfin += store_param_bar(pg, A.P, l, A.gparam);
-        if (A.gframe != nullptr) nonfin += store_frame_bar(pg, A.P, l, L, A.gframe);
-      }
-      if (A.gframe != nullptr) nonfin += store_frame_bar(pg, A.P, l, L, A.gframe);
-    }
-  }
+  if (act) nonfin += store_adjoint<S, R, FREE, PARAMS>(A, l, L, xb1, pg);
   report_nonfinite(A.P.status, nonfin);
 }
 
@@ -1075,20 +1122,23 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(S) > 4) ? 1 : 2))) void k_bac
 // k: the producer recomputes step T-1-k into buffer k%2 while the consumer
 // reverses step T-k from buffer (k-1)%2; one workgroup barrier ends every
 // phase (both waves execute exactly T+1 of them).
-template <typename S, bool FREE, int FR, bool CHAIN>
+// LDS of one pair: the producer's and the consumer's exchange buffers, then
+// the two tape buffers (all in the adjoint's type R: the producer
+// recomputes in R).
+template <typename S, typename R, bool FREE, int FR, bool CHAIN>
 __host__ __device__ constexpr size_t pipe_lds_per_pair() {
   constexpr int TW = kTapeFields + (FREE ? 13 : 2);  // tape + state per lane
-  return (size_t)((CHAIN ? 0 : 2 * XB) + 2 * TW) * kWave * sizeof(S);
+  return (size_t)((CHAIN ? 0 : 2 * XB) + 2 * TW) * kWave * sizeof(R);
 }
 
-template <typename S, bool FREE, int FR, bool CHAIN, bool PARAMS>
+template <typename S, typename R, bool FREE, int FR, bool CHAIN, bool PARAMS>
 __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe(BwdArgs<S> A) {
   constexpr int TW = kTapeFields + (FREE ? 13 : 2);
   const int pair = threadIdx.x / (2 * kWave);
   const int wid = (threadIdx.x / kWave) & 1;
-  S* const base = lds<S>() + pair * (pipe_lds_per_pair<S, FREE, FR, CHAIN>() / sizeof(S));
-  S* const xb = CHAIN ? nullptr : base + wid * (XB * kWave);
-  S* const tbuf[2] = {base + (CHAIN ? 0 : 2 * XB * kWave), base + (CHAIN ? 0 : 2 * XB * kWave) + TW * kWave};
+  R* const base = reinterpret_cast<R*>(abadj_lds + pair * pipe_lds_per_pair<S, R, FREE, FR, CHAIN>());
+  R* const xb = CHAIN ? nullptr : base + wid * (XB * kWave);
+  R* const tbuf[2] = {base + (CHAIN ? 0 : 2 * XB * kWave), base + (CHAIN ? 0 : 2 * XB * kWave) + TW * kWave};
   const int wb = blockIdx.x * (blockDim.x / (2 * kWave)) + pair;
   const Lane l = load_lane(A.P, wb);
   const int maxd = A.P.wmaxd[wb];
@@ -1099,6 +1149,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
   const LinkC<S> L = load_linkc<S, FR>(A.P, l);
+  const LinkC<R> LR = widen<R>(L);
   if (wid == 0) {
     State<S, FREE> nxt = {};
     S tau_nxt = S(0);
@@ -1109,15 +1160,15 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
     for (int k = 0; k <= A.T; ++k) {
       if (k < A.T) {
         const int t = A.T - 1 - k;
-        const State<S, FREE> st = nxt;
-        const S tau = tau_nxt;
+        const State<R, FREE> st = cvt_state<R>(nxt);
+        const R tau = R(tau_nxt);
         if (t > 0) {
           if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
           if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
         }
-        Step<S> o;
-        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
-        S* tb = tbuf[k & 1];
+        Step<R> o;
+        aba_wave<R, FREE, CHAIN>(widen<R>(gravity(A.P)), l, LR, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
+        R* tb = tbuf[k & 1];
 #pragma unroll
         for (int j = 0; j < (FREE ? 7 : 1); ++j) tb[(size_t)j * kWave + l.lane] = st.q[j];
 #pragma unroll
@@ -1128,47 +1179,25 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
     }
   } else {
     int nonfin = 0;  // non-finite outputs
-    ParamBar<S> pg;
+    ParamBar<R> pg;
     param_bar_zero(pg);
-    State<S, FREE> xb1 = {};
-    if (act) {
-      load_state(xb1, l, A.gqT, A.gqdT);
-      if (A.gtraj != nullptr && A.T > 0) {
-        State<S, FREE> gt;
-        const S* row = A.gtraj + (size_t)(A.T - 1) * (A.P.nq + A.P.nv);
-        load_state(gt, l, row, row + A.P.nq);
-#pragma unroll
-        for (int k = 0; k < (FREE ? 7 : 1); ++k) xb1.q[k] += gt.q[k];
-#pragma unroll
-        for (int k = 0; k < (FREE ? 6 : 1); ++k) xb1.qd[k] += gt.qd[k];
-      }
-    }
+    State<R, FREE> xb1 = seed_state<S, R, FREE>(A, l);
     for (int k = 0; k <= A.T; ++k) {
       if (k >= 1) {
         const int t = A.T - k;
-        const S* tb = tbuf[(k - 1) & 1];
-        State<S, FREE> st;
+        const R* tb = tbuf[(k - 1) & 1];
+        State<R, FREE> st;
 #pragma unroll
         for (int j = 0; j < (FREE ? 7 : 1); ++j) st.q[j] = tb[(size_t)j * kWave + l.lane];
 #pragma unroll
         for (int j = 0; j < (FREE ? 6 : 1); ++j) st.qd[j] = tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane];
-        Step<S> o;
-        get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, L, st.qd[0], rev);
-        bwd_reverse<S, FREE, FR, CHAIN, PARAMS>(A, l, L, maxd, xb, st, o, t, xb1, nonfin, pg);
+        Step<R> o;
+        get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, LR, st.qd[0], rev);
+        bwd_reverse<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xb, st, o, t, xb1, nonfin, pg);
       }
       __syncthreads();
     }
-    if (act) {
-      store_state(xb1, l, A.gq0, A.gqd0);
-      nonfin += nonfinite_state(xb1, l);
-      if constexpr (PARAMS) {
-      if constexpr (PARAMS) {
-        if (A.gparam != nullptr) nonfin += store_param_bar(pg, A.P, l, A.gparam);
-        if (A.gframe != nullptr) nonfin += store_frame_bar(pg, A.P, l, L, A.gframe);
-      }
-      if (A.gframe != nullptr) nonfin += store_frame_bar(pg, A.P, l, L, A.gframe);
-    }
-    }
+    if (act) nonfin += store_adjoint<S, R, FREE, PARAMS>(A, l, L, xb1, pg);
     report_nonfinite(A.P.status, nonfin);
   }
 }
@@ -1301,27 +1330,28 @@ hipError_t launch_forward_v(const FwdArgs<S>& a, const Tiling& tl, hipStream_t s
   return hipGetLastError();
 }
 
-template <typename S, bool F, int E, bool C, bool PARAMS>
+template <typename S, typename R, bool F, int E, bool C, bool PARAMS>
 hipError_t launch_backward_p(const BwdArgs<S>& a, const Tiling& tl, hipStream_t st) {
   if (a.K == 1 && tl.pipelined) {
-    const size_t per = pipe_lds_per_pair<S, F, E, C>();
+    const size_t per = pipe_lds_per_pair<S, R, F, E, C>();
     int p = tl.pairs_per_block == 2 ? 2 : 1;
     while (p > 1 && (per * p > lds_limit() || a.P.nwaves % p != 0)) p /= 2;
-    hipLaunchKernelGGL((k_backward_pipe<S, F, E, C, PARAMS>), dim3(a.P.nwaves / p), dim3(2 * kWave * p), per * p,
-                       st, a);
+    hipLaunchKernelGGL((k_backward_pipe<S, R, F, E, C, PARAMS>), dim3(a.P.nwaves / p), dim3(2 * kWave * p),
+                       per * p, st, a);
   } else {
     size_t lds = 0;
-    const int w = single_wpb<S, C>(tl, a.P.nwaves, lds);
-    hipLaunchKernelGGL((k_backward<S, F, E, C, PARAMS>), dim3(a.P.nwaves / w), dim3(kWave * w), lds, st, a);
+    const int w = single_wpb<R, C>(tl, a.P.nwaves, lds);
+    hipLaunchKernelGGL((k_backward<S, R, F, E, C, PARAMS>), dim3(a.P.nwaves / w), dim3(kWave * w), lds, st, a);
   }
   return hipGetLastError();
 }
-// the kernels that accumulate model-parameter gradients only when asked for
-template <typename S, bool F, int E, bool C>
+// the kernels that accumulate model-parameter gradients only when asked for;
+// R: the reverse passes' scalar type
+template <typename S, typename R, bool F, int E, bool C>
 hipError_t launch_backward_v(const BwdArgs<S>& a, const Tiling& tl, hipStream_t st) {
   if (a.P.nwaves == 0) return hipSuccess;
-  if (a.gparam != nullptr || a.gframe != nullptr) return launch_backward_p<S, F, E, C, true>(a, tl, st);
-  return launch_backward_p<S, F, E, C, false>(a, tl, st);
+  if (a.gparam != nullptr || a.gframe != nullptr) return launch_backward_p<S, R, F, E, C, true>(a, tl, st);
+  return launch_backward_p<S, R, F, E, C, false>(a, tl, st);
 }
 
 template <typename S, bool F, int E, bool C>
@@ -1334,6 +1364,37 @@ hipError_t launch_forward_jvp_v(const JvpArgs<S>& a, const Tiling& tl, hipStream
   return hipGetLastError();
 }
 
+// Kernel variants: FREE (some system has a free-floating root), the
+// link-frame kind FR (kFrIdentity: every joint frame the identity after
+// canonicalisation; kFrGeneralJoints: prismatic joints or joint limits),
+// CHAIN (every system is a fixed-base serial chain of revolute joints;
+// register exchange between lanes).  Batches with prismatic joints or
+// joint limits take the one general variant (FREE, kFrGeneralJoints),
+// which handles every joint type and the limits.
+enum class Variant { kFree, kFreeEti, kTree, kTreeEti, kChain, kChainEti, kGeneral };
+
+inline Variant variant(const Shape& sh) {
+  if (sh.has_prism || sh.has_limits) return Variant::kGeneral;
+  if (sh.has_free) return sh.eti ? Variant::kFreeEti : Variant::kFree;
+  if (sh.chain) return sh.eti ? Variant::kChainEti : Variant::kChain;
+  return sh.eti ? Variant::kTreeEti : Variant::kTree;
+}
+
 }  // namespace
+
+// One switch per entry: L<FREE, FR, CHAIN> is the per-variant launcher of
+// the including translation unit (with scalar types TS...), LC<FR> the
+// chain launcher of abadj_kernels_chain.hip.
+#define ABADJ_DISPATCH(L, LC, ...)                                                 \
+  switch (variant(sh)) {                                                          \
+    case Variant::kFree: return L<__VA_ARGS__, true, kFrGeneral, false>(a, tl, st);     \
+    case Variant::kFreeEti: return L<__VA_ARGS__, true, kFrIdentity, false>(a, tl, st); \
+    case Variant::kTree: return L<__VA_ARGS__, false, kFrGeneral, false>(a, tl, st);    \
+    case Variant::kTreeEti: return L<__VA_ARGS__, false, kFrIdentity, false>(a, tl, st); \
+    case Variant::kChain: return LC<S, kFrGeneral>(a, tl, st);                    \
+    case Variant::kChainEti: return LC<S, kFrIdentity>(a, tl, st);                \
+    case Variant::kGeneral: return L<__VA_ARGS__, true, kFrGeneralJoints, false>(a, tl, st); \
+  }                                                                               \
+  return hipErrorInvalidValue;
 
 }  // namespace aba

@@ -77,6 +77,8 @@ struct BwdArgs {
   S* gframe;       // nullable: [n_links][9] placement and axis gradients
   const int32_t* sched;  // K < 0: binomial checkpointing actions, (op, arg) pairs
   int nsched;
+  int adj64;       // S = float only: recompute each step and run the reverse passes in FP64 (inputs,
+                   // outputs, checkpoints and replays stay FP32)
 };
 
 // Actions of a binomial checkpointing schedule (K < 0, s = -K snapshots).
@@ -162,7 +164,7 @@ int report_error(int code, const std::string& msg);
 void clear_error();
 
 // Launchers: pick the kernel variant for the handle's shape and launch it on
-// `stream` (abadj_kernels.hip).  The serial-chain variants live in their own
+// `stream` (abadj_kernels.hip; the adjoint in abadj_kernels_bwd.hip).  The serial-chain variants live in their own
 // translation unit (abadj_kernels_chain.hip), reached through the *_chain
 // launchers for frame kinds kFrIdentity and kFrGeneral.
 template <typename S>
@@ -173,6 +175,9 @@ template <typename S>
 hipError_t launch_aba(const AbaArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
 template <typename S>
 hipError_t launch_forward_jvp(const JvpArgs<S>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
+// FP32 handles whose adjoint runs in FP64 (BwdArgs::adj64), non-chain
+// variants (abadj_kernels_bwd64.hip)
+hipError_t launch_backward_adj64(const BwdArgs<float>& a, const Shape& sh, const Tiling& tl, hipStream_t st);
 template <typename S, int FR>
 hipError_t launch_forward_chain(const FwdArgs<S>& a, const Tiling& tl, hipStream_t st);
 template <typename S, int FR>

@@ -16,7 +16,10 @@ hipError_t launch_forward_chain(const FwdArgs<S>& a, const Tiling& tl, hipStream
 }
 template <typename S, int FR>
 hipError_t launch_backward_chain(const BwdArgs<S>& a, const Tiling& tl, hipStream_t st) {
-  return launch_backward_v<S, false, FR, true>(a, tl, st);
+  if constexpr (sizeof(S) == sizeof(float)) {
+    if (a.adj64) return launch_backward_v<S, double, false, FR, true>(a, tl, st);
+  }
+  return launch_backward_v<S, S, false, FR, true>(a, tl, st);
 }
 template <typename S, int FR>
 hipError_t launch_forward_jvp_chain(const JvpArgs<S>& a, const Tiling& tl, hipStream_t st) {

@@ -50,10 +50,15 @@ struct sim_handle {
   bool has_prism = false;  // some joint is prismatic
   bool has_limits = false;  // joint limits were given
   aba::Tiling tiling;  // launch geometry
-  // binomial checkpointing schedule cached on the device for (sched_T, sched_s)
-  int32_t* d_sched = nullptr;
-  size_t d_sched_cap = 0;
-  int sched_T = -1, sched_s = -1, sched_n = 0;
+  int adj_dtype = SIM_F64;  // arithmetic of the reverse passes (FP32 handles: SIM_F32 or SIM_F64)
+  // binomial checkpointing schedules, one device copy per (T, s) used, kept
+  // until sim_destroy (a captured graph may replay any of them)
+  struct Sched {
+    int T, s, n;
+    std::vector<int32_t> host;  // source of the asynchronous upload, kept alive
+    int32_t* dev;
+  };
+  std::vector<Sched> scheds;
   double g[3] = {0, 0, 0};
   int32_t* d_ci = nullptr;
   void* d_cf = nullptr;
@@ -263,8 +268,9 @@ void release(sim_handle* h) {
   if (h->d_wmaxd) (void)hipFree(h->d_wmaxd);
   if (h->d_status) (void)hipFree(h->d_status);
   h->d_status = nullptr;
-  if (h->d_sched) (void)hipFree(h->d_sched);
-  h->d_sched = nullptr;
+  for (auto& c : h->scheds)
+    if (c.dev) (void)hipFree(c.dev);
+  h->scheds.clear();
   h->d_ci = nullptr;
   h->d_cf = nullptr;
   h->d_wmaxd = nullptr;
@@ -582,6 +588,18 @@ int sim_get_info(sim_t h, sim_info_t* o) {
   o->chain = h->chain ? 1 : 0;
   o->has_prism = h->has_prism ? 1 : 0;
   o->dtype = h->dtype;
+  o->adjoint_dtype = h->adj_dtype;
+  return SIM_OK;
+}
+
+int sim_set_adjoint_dtype(sim_t h, int dtype) {
+  g_err.clear();
+  if (!h) return fail(SIM_ERR_INVALID_ARG, "sim_set_adjoint_dtype: null handle");
+  if (dtype != SIM_F32 && dtype != SIM_F64)
+    return fail(SIM_ERR_UNSUPPORTED_DTYPE, "sim_set_adjoint_dtype: dtype must be SIM_F32 or SIM_F64");
+  if (h->dtype == SIM_F64 && dtype != SIM_F64)
+    return fail(SIM_ERR_UNSUPPORTED_DTYPE, "sim_set_adjoint_dtype: an FP64 handle's adjoint runs in FP64");
+  h->adj_dtype = dtype;
   return SIM_OK;
 }
 
@@ -625,29 +643,40 @@ int sim_workspace_bytes(sim_t h, int T, int K, size_t* bytes) {
   return SIM_OK;
 }
 
-// The device copy of the binomial schedule for (T, s), built and uploaded
-// (synchronously) the first time that pair is used; later calls, and graph
-// captures of them, reuse it.
-static int ensure_schedule(sim_handle* h, int T, int s, hipStream_t stream) {
-  if (h->sched_T == T && h->sched_s == s) return SIM_OK;
+// The device copy of the binomial schedule for (T, s): built and uploaded
+// the first time that pair is used (an allocation and an upload ordered on
+// `stream`), then reused by later calls and graph captures of them.  Every
+// pair keeps its own buffer until sim_destroy, so a schedule in use by an
+// earlier launch or a captured graph is never overwritten.
+static int ensure_schedule(sim_handle* h, int T, int s, hipStream_t stream, const int32_t** dev, int* n) {
+  for (const auto& c : h->scheds)
+    if (c.T == T && c.s == s) {
+      *dev = c.dev;
+      *n = c.n;
+      return SIM_OK;
+    }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
     return fail(SIM_ERR_INVALID_ARG, "sim_backward: the first call with a new (T, K < 0) uploads its checkpointing "
                                      "schedule and cannot be captured; run it once outside the capture");
-  const Schedule S = make_schedule(T, s);
-  const size_t bytes = std::max<size_t>(S.a.size(), 2) * sizeof(int32_t);
-  if (bytes > h->d_sched_cap) {
-    if (h->d_sched) (void)hipFree(h->d_sched);
-    h->d_sched = nullptr;
-    h->d_sched_cap = 0;
-    if (hipMalloc(&h->d_sched, bytes) != hipSuccess) return fail(SIM_ERR_HIP, "sim_backward: schedule allocation failed");
-    h->d_sched_cap = bytes;
-  }
-  if (!S.a.empty() && hipMemcpy(h->d_sched, S.a.data(), S.a.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+  Schedule S = make_schedule(T, s);
+  sim_handle::Sched c;
+  c.T = T;
+  c.s = s;
+  c.n = (int)(S.a.size() / 2);
+  c.host = std::move(S.a);
+  c.dev = nullptr;
+  const size_t bytes = std::max<size_t>(c.host.size(), 2) * sizeof(int32_t);
+  if (hipMalloc(&c.dev, bytes) != hipSuccess) return fail(SIM_ERR_HIP, "sim_backward: schedule allocation failed");
+  if (!c.host.empty() &&
+      hipMemcpyAsync(c.dev, c.host.data(), c.host.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream) !=
+          hipSuccess) {
+    (void)hipFree(c.dev);
     return fail(SIM_ERR_HIP, "sim_backward: schedule upload failed");
-  h->sched_T = T;
-  h->sched_s = s;
-  h->sched_n = (int)(S.a.size() / 2);
+  }
+  h->scheds.push_back(std::move(c));
+  *dev = h->scheds.back().dev;
+  *n = h->scheds.back().n;
   return SIM_OK;
 }
 
@@ -738,8 +767,10 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     return fail(SIM_ERR_WORKSPACE_TOO_SMALL, "sim_backward: workspace of " + std::to_string(workspace_bytes) +
                                                  " bytes, need " + std::to_string(need));
   const size_t ck = ckpt_bytes(h, T, K);
+  const int32_t* sched = nullptr;
+  int nsched = 0;
   if (K < 0) {
-    rc = ensure_schedule(h, T, -K, (hipStream_t)stream);
+    rc = ensure_schedule(h, T, -K, (hipStream_t)stream, &sched, &nsched);
     if (rc) return rc;
   }
   hipError_t e;
@@ -758,8 +789,9 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (double*)gtau;
     a.ck = (double*)workspace;
     a.scratch = (K > 1) ? (double*)((char*)workspace + ck) : nullptr;
-    a.sched = (K < 0) ? h->d_sched : nullptr;
-    a.nsched = (K < 0) ? h->sched_n : 0;
+    a.sched = sched;
+    a.nsched = nsched;
+    a.adj64 = 0;
     a.gparam = (double*)gparam;
     a.gframe = (double*)gframe;
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
@@ -778,8 +810,9 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gtau = (float*)gtau;
     a.ck = (float*)workspace;
     a.scratch = (K > 1) ? (float*)((char*)workspace + ck) : nullptr;
-    a.sched = (K < 0) ? h->d_sched : nullptr;
-    a.nsched = (K < 0) ? h->sched_n : 0;
+    a.sched = sched;
+    a.nsched = nsched;
+    a.adj64 = h->adj_dtype == SIM_F64 ? 1 : 0;
     a.gparam = (float*)gparam;
     a.gframe = (float*)gframe;
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);

@@ -5,8 +5,10 @@ are ordinary differentiable torch code; their gradient with respect to q^T
 becomes the seed of the adjoint pass (Sec. 3, Eq. diff_u: dPhi/dx^T enters
 the adjoint recursion).  This module computes world positions of chosen
 points on chosen links for a whole batch, one tree level at a time, with the
-package's joint convention (link -> parent rotation E^T = E_T^T Rot(a, q),
-Rot the rotation by +q about a; free root: R(quat) and p).
+package's joint convention (revolute: link -> parent rotation
+E^T = E_T^T Rot(a, q), Rot the rotation by +q about a, origin at r_T;
+prismatic: E^T = E_T^T, origin at r_T + q E_T^T a; free root: R(quat) and
+p).  Other joint types are rejected.
 """
 from __future__ import annotations
 
@@ -41,6 +43,9 @@ class LinkPoints(torch.nn.Module):
             d = sy.depth()
             qo = 0
             for i in range(sy.n):
+                if int(sy.jtype[i]) not in (0, 1, 2):
+                    raise ValueError(f"LinkPoints: system {s} link {i} has joint type {int(sy.jtype[i])}; "
+                                     "only revolute (0), free root (1) and prismatic (2) joints are supported")
                 glob_par.append(-1 if sy.parent[i] < 0 else base + int(sy.parent[i]))
                 dep.append(int(d[i]))
                 qidx.append(qbase + qo)
@@ -63,6 +68,8 @@ class LinkPoints(torch.nn.Module):
         self.ETt = f(np.stack(ET)).transpose(-1, -2).contiguous()
         self.rT = f(np.stack(rT))
         self.K = _skew(f(np.stack(ax)))
+        self.ax = f(np.stack(ax))
+        self.prism = torch.tensor(np.asarray(jt) == 2, device=device)
         self.target = i64(target)
         self.pts = f(np.asarray(pts))
         self.levels = [torch.tensor(np.nonzero(self.depth == d)[0], dtype=torch.long, device=device)
@@ -79,15 +86,19 @@ class LinkPoints(torch.nn.Module):
             m = idx.numel()
             qi = q[self.qidx[idx]]
             K = self.K[idx]
+            pr = self.prism[idx]
             s, c = torch.sin(qi)[:, None, None], torch.cos(qi)[:, None, None]
-            Rj = I3 + s * K + (1 - c) * (K @ K)
+            Rj = torch.where(pr[:, None, None], I3.expand(m, 3, 3), I3 + s * K + (1 - c) * (K @ K))
             par = self.parent[idx]
             has_par = par >= 0
             parc = par.clamp(min=0)
             Rp = torch.where(has_par[:, None, None], Rw[parc], I3.expand(m, 3, 3))
             pp = torch.where(has_par[:, None], pw[parc], torch.zeros((m, 3), dtype=q.dtype, device=q.device))
             Rl = Rp @ self.ETt[idx] @ Rj
-            pl = pp + (Rp @ self.rT[idx][..., None])[..., 0]
+            # a prismatic link's origin slides by q a (joint frame) from r_T
+            slide = torch.where(pr[:, None], qi[:, None] * self.ax[idx], torch.zeros_like(self.ax[idx]))
+            r = self.rT[idx] + (self.ETt[idx] @ slide[..., None])[..., 0]
+            pl = pp + (Rp @ r[..., None])[..., 0]
             if len(free):
                 rows_R, rows_p = list(Rl.unbind(0)), list(pl.unbind(0))
                 for k in free:

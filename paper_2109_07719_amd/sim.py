@@ -88,6 +88,22 @@ class Sim:
         self.info = {f: getattr(info, f) for f, _ in N.SimInfo._fields_}
         self.nq, self.nv, self.nu = info.nq, info.nv, info.nu
 
+    @property
+    def adjoint_dtype(self):
+        """Arithmetic of the backward pass: each step's recompute and reverse
+        passes (torch.float64 by default; an FP32 handle may select
+        torch.float32)."""
+        return torch.float64 if self.info["adjoint_dtype"] == N.SIM_F64 else torch.float32
+
+    def set_adjoint_dtype(self, dtype) -> None:
+        """FP32 handles: run the backward pass's per-step recompute and
+        reverse passes in FP64 (default; inputs, outputs, checkpoints and
+        the forward stay FP32) or in FP32."""
+        if dtype not in (torch.float32, torch.float64):
+            raise TypeError("dtype must be torch.float32 or torch.float64")
+        N.check(N.lib().sim_set_adjoint_dtype(self._h, N.SIM_F64 if dtype == torch.float64 else N.SIM_F32))
+        self.info["adjoint_dtype"] = N.SIM_F64 if dtype == torch.float64 else N.SIM_F32
+
     def close(self):
         """Release the handle now (also done when the object is collected)."""
         release = getattr(self, "_release", None)
