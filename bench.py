@@ -766,7 +766,7 @@ def main():
     b = synth.workload(args.workload, T=args.T, tau_dtype=np.float32)
     # the oracle and the GPU see the same float32-rounded inputs
     r = synth.round_to_f32(synth.Batch(systems=b.systems, q0=b.q0, qd0=b.qd0, tau=b.tau[:1], dt=b.dt))
-    b = synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=b.dt, name=b.name)
+    b = synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=r.dt, gravity=r.gravity, name=b.name)
     t_gen = time.perf_counter() - t_gen
 
     sim = Sim(b.systems, b.gravity, dtype=torch.float32)

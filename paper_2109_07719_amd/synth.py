@@ -406,14 +406,15 @@ def make_batch(draws, dt: float, name: str = "", tau_dtype=np.float64) -> Batch:
 
 def round_to_f32(b: Batch) -> Batch:
     """Round every floating input to float32 and widen back (the oracle's view
-    of what the float32 GPU path consumes)."""
+    of what the float32 GPU path consumes), the step size and gravity
+    included."""
     def r(x):
         return np.asarray(x, dtype=np.float32).astype(np.float64)
     systems = [System(parent=s.parent, jtype=s.jtype, E_T=r(s.E_T), r_T=r(s.r_T),
                       axis=r(s.axis), mass=r(s.mass), com=r(s.com), Ic=r(s.Ic),
                       limits=None if s.limits is None else r(s.limits))
                for s in b.systems]
-    return Batch(systems=systems, q0=r(b.q0), qd0=r(b.qd0), tau=r(b.tau), dt=b.dt,
+    return Batch(systems=systems, q0=r(b.q0), qd0=r(b.qd0), tau=r(b.tau), dt=float(np.float32(b.dt)),
                  gravity=r(b.gravity), name=b.name)
 
 

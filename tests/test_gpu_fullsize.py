@@ -73,7 +73,7 @@ def test_autograd_adjoint_matches_central_differences_fp64(K):
 def _full_batch(name):
     b = synth.workload(name, tau_dtype=np.float32)
     r = synth.round_to_f32(synth.Batch(systems=b.systems, q0=b.q0, qd0=b.qd0, tau=b.tau[:1], dt=b.dt))
-    return synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=b.dt, name=b.name)
+    return synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=r.dt, gravity=r.gravity, name=b.name)
 
 
 def _sampled_along(b, sample, K=1, extra_K=(), diverging=0):

@@ -2,11 +2,13 @@
 switch, the non-finite counter's accounting of parameter gradients, and
 binomial schedules replayed from several captured graphs.
 
-FP32 handles run the adjoint's reverse passes in FP64 by default (inputs,
-outputs, checkpoints and the per-step recompute stay FP32).  The gradients
-are compared with the FP64 oracle's adjoint sweep along the GPU's own
-trajectory (its states used as the per-step checkpoints), which holds at any
-horizon; the end-to-end FP32-vs-FP64 difference is printed beside it.
+FP32 handles run the backward pass in FP64 by default (each step recomputed
+from its widened FP32 checkpoint and reversed in FP64; inputs, outputs,
+checkpoints and the forward stay FP32).  The gradients are compared with the
+FP64 oracle's adjoint sweep along the GPU's own trajectory (its states used
+as the per-step checkpoints), which holds at any horizon.  The oracle sees
+the inputs the GPU sees, rounded to FP32: parameters, states, controls,
+gravity and the step size.
 Errors are per system and norm-wise (bar 1e-3); the elementwise maximum
 |g - ref| / max|ref| is reported with them.
 """
@@ -193,7 +195,7 @@ def test_full_size_chain7_4096_gradient_tail():
     elementwise maximum are printed."""
     b = synth.workload("chain7_4096", T=5000, tau_dtype=np.float32)
     r = synth.round_to_f32(synth.Batch(systems=b.systems, q0=b.q0, qd0=b.qd0, tau=b.tau[:1], dt=b.dt))
-    b = synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=b.dt, name=b.name)
+    b = synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=r.dt, gravity=r.gravity, name=b.name)
     sim = _sim(b)
     q0, qd0 = _t(b.q0), _t(b.qd0)
     tau = torch.from_numpy(b.tau).to(DEV)

@@ -389,7 +389,7 @@ def test_full_size_chain7_4096_sampled():
     import oracle as O
     b = synth.workload("chain7_4096", T=5000, tau_dtype=np.float32)
     r = synth.round_to_f32(synth.Batch(systems=b.systems, q0=b.q0, qd0=b.qd0, tau=b.tau[:1], dt=b.dt))
-    b = synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=b.dt, name=b.name)
+    b = synth.Batch(systems=r.systems, q0=r.q0, qd0=r.qd0, tau=b.tau, dt=r.dt, gravity=r.gravity, name=b.name)
     sim = _sim(b)
     q0, qd0 = _t(b.q0), _t(b.qd0)
     tau = torch.from_numpy(b.tau).to(DEV)
