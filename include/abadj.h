@@ -311,6 +311,27 @@ int sim_backward(sim_t h, const void *tau, double dt, int T, int K, const void *
                  void *gparam, void *gframe, void *workspace, size_t workspace_bytes,
                  void *stream);
 
+/* sim_backward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, but the K > 1 replay buffer
+ * lives in a static device array of the library (64 MiB, one per GPU, held
+ * until the process ends) instead of the caller's workspace.  checkpoints
+ * is the workspace of the matching sim_forward call; only its checkpoint
+ * part is read (checkpoint_bytes at least sim_workspace_bytes for the same
+ * T and K minus the replay buffer, i.e. the full size for K <= 1).  K >= 0
+ * only (binomial schedules need a device copy of the schedule).  Every call
+ * on one GPU shares that array: calls that overlap in time on one GPU (on
+ * different streams, or from several threads) race and give wrong results;
+ * serialise them.  Calls no allocating routine.  Errors: as sim_backward;
+ * SIM_ERR_INVALID_ARG for K < 0; SIM_ERR_WORKSPACE_TOO_SMALL when the
+ * replay buffer (K state records, see sim_workspace_bytes) exceeds 64 MiB or
+ * checkpoint_bytes is too small; SIM_ERR_HIP if the array's device address
+ * cannot be obtained. */
+int sim_backward_noalloc(sim_t h, const void *tau, double dt, int T, int K, const void *gqT,
+                         const void *gqdT, const void *gtraj, void *gq0, void *gqd0, void *gtau,
+                         void *gparam, void *gframe, void *checkpoints, size_t checkpoint_bytes,
+                         void *stream);
+
 /* Forward-mode (tangent) rollout: the T-step rollout of sim_forward with
  * one input direction (dq0 [nq], dqd0 [nv], dtau [T][nu]) carried along,
  * giving the final state and its directional derivative

@@ -28,7 +28,7 @@ EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_set_adjoint_dtype"
             "sim_set_tiling", "sim_autotune",
             "sim_workspace_bytes",
             "sim_checkpoint_schedule", "sim_forward", "sim_forward_jvp",
-            "sim_backward", "sim_aba", "sim_flops", "sim_last_error",
+            "sim_backward", "sim_backward_noalloc", "sim_aba", "sim_flops", "sim_last_error",
             "sim_pgs_workspace_bytes", "sim_pgs_solve", "sim_pgs_adjoint",
             "sim_contact_param_count", "sim_contact_flops", "sim_contact_rollout", "sim_contact_rollout_grad")
 SIM_PGS_MAX_ROWS = 16
@@ -96,6 +96,8 @@ def lib():
         L.sim_forward.restype = I
         L.sim_backward.argtypes = [P, P, D, I, I, P, P, P, P, P, P, P, P, P, Z, P]
         L.sim_backward.restype = I
+        L.sim_backward_noalloc.argtypes = [P, P, D, I, I, P, P, P, P, P, P, P, P, P, Z, P]
+        L.sim_backward_noalloc.restype = I
         L.sim_pgs_workspace_bytes.argtypes = [I, I, I, I, ctypes.POINTER(Z)]
         L.sim_pgs_workspace_bytes.restype = I
         L.sim_pgs_solve.argtypes = [I, I, I, I, P, P, P, P, P, P, P, Z, P]

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -753,26 +754,34 @@ int sim_forward(sim_t h, const void* q0, const void* qd0, const void* tau, doubl
   return SIM_OK;
 }
 
-int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* gqT, const void* gqdT,
-                 const void* gtraj, void* gq0, void* gqd0, void* gtau, void* gparam, void* gframe,
-                 void* workspace, size_t workspace_bytes, void* stream) {
-  g_err.clear();
-  int rc = check_run(h, dt, T, K, "sim_backward");
+}  // extern "C"
+
+// The adjoint pass behind sim_backward and sim_backward_noalloc.  replay:
+// nullptr = the K > 1 replay buffer follows the checkpoints in the
+// workspace; otherwise the device buffer to use for it (the workspace then
+// needs only the checkpoints).
+static int backward_impl(const char* who, sim_t h, const void* tau, double dt, int T, int K, const void* gqT,
+                         const void* gqdT, const void* gtraj, void* gq0, void* gqd0, void* gtau, void* gparam,
+                         void* gframe, void* workspace, size_t workspace_bytes, void* replay, void* stream) {
+  int rc = check_run(h, dt, T, K, who);
   if (rc) return rc;
   if (!gqT || !gqdT || !gq0 || !gqd0 || (T > 0 && h->nu > 0 && (!tau || !gtau)) || (T > 0 && !workspace))
-    return fail(SIM_ERR_INVALID_ARG, "sim_backward: null array argument");
+    return fail(SIM_ERR_INVALID_ARG, std::string(who) + ": null array argument");
+  const size_t ck = ckpt_bytes(h, T, K);
   size_t need = 0;
   sim_workspace_bytes(h, T, K, &need);
+  if (replay) need = ck;
   if (T > 0 && workspace_bytes < need)
-    return fail(SIM_ERR_WORKSPACE_TOO_SMALL, "sim_backward: workspace of " + std::to_string(workspace_bytes) +
-                                                 " bytes, need " + std::to_string(need));
-  const size_t ck = ckpt_bytes(h, T, K);
+    return fail(SIM_ERR_WORKSPACE_TOO_SMALL, std::string(who) + ": workspace of " +
+                                                 std::to_string(workspace_bytes) + " bytes, need " +
+                                                 std::to_string(need));
   const int32_t* sched = nullptr;
   int nsched = 0;
   if (K < 0) {
     rc = ensure_schedule(h, T, -K, (hipStream_t)stream, &sched, &nsched);
     if (rc) return rc;
   }
+  void* const rbuf = replay ? replay : (void*)((char*)workspace + ck);
   hipError_t e;
   if (h->dtype == SIM_F64) {
     aba::BwdArgs<double> a;
@@ -788,7 +797,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gqd0 = (double*)gqd0;
     a.gtau = (double*)gtau;
     a.ck = (double*)workspace;
-    a.scratch = (K > 1) ? (double*)((char*)workspace + ck) : nullptr;
+    a.scratch = (K > 1) ? (double*)rbuf : nullptr;
     a.sched = sched;
     a.nsched = nsched;
     a.adj64 = 0;
@@ -809,7 +818,7 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gqd0 = (float*)gqd0;
     a.gtau = (float*)gtau;
     a.ck = (float*)workspace;
-    a.scratch = (K > 1) ? (float*)((char*)workspace + ck) : nullptr;
+    a.scratch = (K > 1) ? (float*)rbuf : nullptr;
     a.sched = sched;
     a.nsched = nsched;
     a.adj64 = h->adj_dtype == SIM_F64 ? 1 : 0;
@@ -817,8 +826,71 @@ int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* 
     a.gframe = (float*)gframe;
     e = aba::launch_backward(a, shape(h), h->tiling, (hipStream_t)stream);
   }
-  if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string("sim_backward: launch failed: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return fail(SIM_ERR_HIP, std::string(who) + ": launch failed: " + hipGetErrorString(e));
   return SIM_OK;
+}
+
+// ---- the adjoint pass without allocation.  The K > 1 replay buffer lives
+// in a file-scope device array, one copy per GPU, kept until the process
+// ends.  In host code `scratch` only names the symbol: its device address
+// on each GPU comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address is handed to kernels.
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (looked up on first use).
+static int noalloc_scratch(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(SIM_ERR_HIP, "sim_backward_noalloc: no current device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SIM_ERR_HIP, std::string("sim_backward_noalloc: scratch address lookup failed: ") +
+                                   hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SIM_OK;
+}
+
+extern "C" {
+
+int sim_backward(sim_t h, const void* tau, double dt, int T, int K, const void* gqT, const void* gqdT,
+                 const void* gtraj, void* gq0, void* gqd0, void* gtau, void* gparam, void* gframe,
+                 void* workspace, size_t workspace_bytes, void* stream) {
+  g_err.clear();
+  return backward_impl("sim_backward", h, tau, dt, T, K, gqT, gqdT, gtraj, gq0, gqd0, gtau, gparam, gframe,
+                       workspace, workspace_bytes, nullptr, stream);
+}
+
+int sim_backward_noalloc(sim_t h, const void* tau, double dt, int T, int K, const void* gqT, const void* gqdT,
+                         const void* gtraj, void* gq0, void* gqd0, void* gtau, void* gparam, void* gframe,
+                         void* checkpoints, size_t checkpoint_bytes, void* stream) {
+  g_err.clear();
+  if (!h) return fail(SIM_ERR_INVALID_ARG, "sim_backward_noalloc: null handle");
+  if (K < 0)
+    return fail(SIM_ERR_INVALID_ARG, "sim_backward_noalloc: binomial checkpointing (K < 0) is not available "
+                                     "without allocation; use K >= 0");
+  const size_t rep = scratch_bytes(h, K);
+  if (rep > kNoAllocScratchBytes)
+    return fail(SIM_ERR_WORKSPACE_TOO_SMALL, "sim_backward_noalloc: the K = " + std::to_string(K) +
+                                                 " replay buffer needs " + std::to_string(rep) +
+                                                 " bytes, above the library's static scratch of " +
+                                                 std::to_string(kNoAllocScratchBytes) + " bytes");
+  void* buf = nullptr;
+  const int rc = noalloc_scratch(&buf);
+  if (rc) return rc;
+  return backward_impl("sim_backward_noalloc", h, tau, dt, T, K, gqT, gqdT, gtraj, gq0, gqd0, gtau, gparam,
+                       gframe, checkpoints, checkpoint_bytes, buf, stream);
 }
 
 int sim_forward_jvp(sim_t h, const void* q0, const void* qd0, const void* tau, const void* dq0, const void* dqd0,
