@@ -25,12 +25,10 @@
 // each column of M^-1 J^T is the articulated-body response to a unit force
 // at the contact point (passes 2 and 3 of the ABA with the factorisation
 // of the step's own pass 2 reused, no velocity or gravity terms).  The
-// gradient runs one 64-lane wave per system: lane j reruns the step from
-// the stored state in dual numbers seeded along input j (state entry or
-// control), which gives column j of the step's Jacobian exactly (clamp and
-// detection decisions as taken), and the reverse recursion
-// x_bar_t = J_t^T x_bar_{t+1} is a dot product per lane with x_bar shared
-// through LDS.
+// gradient runs backwards in time, one lane per system: each step is
+// recomputed from the stored state, then its statements are reversed
+// (contact_adjoint.h), and the adjoint of the state is carried to the
+// previous step (Sec. 3, Eq. adj_back; Sec. 4.1, Eq. adj_r).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -39,11 +37,10 @@
 
 #include "../../include/abadj.h"
 #include "abadj_internal.h"
-#include "contact_step.h"
+#include "contact_adjoint.h"
 
 namespace {
 
-using aba::Dual;
 using namespace aba_contact;
 
 
@@ -158,41 +155,52 @@ struct GradArgs {
   R* gmu;         // nullable: [B]
 };
 
-// one wave per system; lane j < nx + nu owns Jacobian column j, lane nx + nu
-// the friction coefficient's column (when gmu is asked for)
-template <typename R>
-__global__ __launch_bounds__(kBlock, 4) void k_contact_grad(GradArgs<R> a) {
-  using D = Dual<R>;
-  const int s = blockIdx.x, j = threadIdx.x;
-  const CTopo& tp = a.tp;
+// The rollout gradient by the step's reverse statements, backwards in time:
+// per step, contact_step_vjp recomputes the step from the stored state and
+// runs the adjoints of the integrator, the impulse update, both
+// Gauss-Seidel solves (from their recorded sweep vectors), A and b, the
+// unit-impulse responses, the contact geometry and the smooth ABA step.
+// One lane per system; R is the arithmetic (FP64 for FP32 I/O: the
+// recompute and the reverse sweeps start from the widened FP32 states, so
+// the gradient is that of the step map along the FP32 trajectory), each
+// lane's Work record in LDS as in the rollout, its sweep record and
+// adjoint arrays in private memory.
+template <typename R> struct AdjSpw;
+template <> struct AdjSpw<float> { static constexpr int v = 16; };
+template <> struct AdjSpw<double> { static constexpr int v = 8; };
+
+template <typename S, typename R>
+__global__ __launch_bounds__(kBlock) void k_contact_adj(GradArgs<S> a) {
+  constexpr int SPW = AdjSpw<R>::v;
+  static_assert(SPW * sizeof(Work<R>) <= 160 * 1024, "LDS budget");
+  __shared__ Work<R> wsh[SPW];
+  const int lane = threadIdx.x;
+  const int s = blockIdx.x * SPW + lane;
+  if (lane >= SPW || s >= a.B) return;
+  // the model's constants as the forward rollout saw them (rounded to S)
+  CTopo tp = a.tp;
+  for (int k = 0; k < 3; ++k) tp.g[k] = double(S(tp.g[k]));
+  tp.mu = double(S(tp.mu));
+  tp.beta = double(S(tp.beta));
   const size_t B = (size_t)a.B;
-  const Par<R> P{a.P, B, s};
+  const Par<S> P{a.P, B, s};
   const int nq = tp.nq, nv = tp.nv, nu = tp.nu, nx = nq + nv;
-  __shared__ R xb[kNX];
-  if (j < nq) xb[j] = a.gqT[j * B + s];
-  else if (j < nx) xb[j] = a.gqdT[(j - nq) * B + s];
-  __syncthreads();
-  Work<D> w;
-  const int ncol = nx + nu + (a.gmu ? 1 : 0);
-  R mu_acc = R(0);
+  Rec<R> rc;
+  Adj<R> ad;
+  R xb[kNX], x[kNX], u[kNL], ub[kNL];
+  for (int k = 0; k < nq; ++k) xb[k] = R(a.gqT[k * B + s]);
+  for (int k = 0; k < nv; ++k) xb[nq + k] = R(a.gqdT[k * B + s]);
+  R mub = R(0);
+  Work<R>& w = wsh[lane];
   for (int t = a.T - 1; t >= 0; --t) {
-    R sj = R(0);
-    if (j < ncol) {
-      D x[kNX], x1[kNX], u[kNL];
-      for (int k = 0; k < nx; ++k) x[k] = D(a.traj[((size_t)t * nx + k) * B + s], R(k == j ? 1 : 0));
-      for (int k = 0; k < nu; ++k) u[k] = D(a.tau[((size_t)t * nu + k) * B + s], R(nx + k == j ? 1 : 0));
-      contact_step(tp, P, x, x + nq, u, a.dt, D(R(tp.mu), R(j == nx + nu ? 1 : 0)), x1, x1 + nq, w);
-      for (int k = 0; k < nx; ++k) sj += xb[k] * x1[k].d;
-    }
-    __syncthreads();
-    if (j < nx) xb[j] = sj;
-    else if (j < nx + nu) a.gtau[((size_t)t * nu + (j - nx)) * B + s] = sj;
-    else if (j == nx + nu) mu_acc += sj;
-    __syncthreads();
+    for (int k = 0; k < nx; ++k) x[k] = R(a.traj[((size_t)t * nx + k) * B + s]);
+    for (int k = 0; k < nu; ++k) u[k] = R(a.tau[((size_t)t * nu + k) * B + s]);
+    contact_step_vjp(tp, P, x, x + nq, u, a.dt, R(tp.mu), xb, ub, mub, w, rc, ad);
+    for (int k = 0; k < nu; ++k) a.gtau[((size_t)t * nu + k) * B + s] = S(ub[k]);
   }
-  if (j < nq) a.gq0[j * B + s] = xb[j];
-  else if (j < nx) a.gqd0[(j - nq) * B + s] = xb[j];
-  else if (j == nx + nu && a.gmu) a.gmu[s] = mu_acc;
+  for (int k = 0; k < nq; ++k) a.gq0[k * B + s] = S(xb[k]);
+  for (int k = 0; k < nv; ++k) a.gqd0[k * B + s] = S(xb[nq + k]);
+  if (a.gmu) a.gmu[s] = S(mub);
 }
 
 int cfail(int code, const std::string& msg) { return aba::report_error(code, msg); }
@@ -279,17 +287,21 @@ int sim_contact_flops(const sim_contact_model* m, const double* params, const do
     delete w;
   }
   {
-    using D = Dual<CD>;
-    auto* w = new Work<D>;
-    D x[kNX], x1[kNX], u[kNL];
-    for (int k = 0; k < tp.nq; ++k) x[k] = D(CD(q[k]), CD(k == 0 ? 1 : 0));
-    for (int k = 0; k < tp.nv; ++k) x[tp.nq + k] = D(CD(qd[k]), CD(0));
-    for (int k = 0; k < tp.nu; ++k) u[k] = D(CD(tau[k]), CD(0));
+    // one reverse step: the recompute and the reverse statements
+    auto* w = new Work<CD>;
+    auto* rc = new Rec<CD>;
+    auto* ad = new Adj<CD>;
+    CD x[kNX], xb[kNX], u[kNL], ub[kNL], mub(0.0);
+    for (int k = 0; k < tp.nq; ++k) x[k] = CD(q[k]);
+    for (int k = 0; k < tp.nv; ++k) x[tp.nq + k] = CD(qd[k]);
+    for (int k = 0; k < tp.nu; ++k) u[k] = CD(tau[k]);
+    for (int k = 0; k < nx; ++k) xb[k] = CD(1.0);
     g_cops = 0;
-    contact_step(tp, P, x, x + tp.nq, u, dt, D(CD(tp.mu), CD(0)), x1, x1 + tp.nq, *w);
-    // one dual step and one nx-term dot product per Jacobian column
-    *grad_flops = (double)(g_cops + 2 * nx) * (double)(nx + tp.nu);
+    contact_step_vjp(tp, P, x, x + tp.nq, u, dt, CD(tp.mu), xb, ub, mub, *w, *rc, *ad);
+    *grad_flops = (double)g_cops;
     delete w;
+    delete rc;
+    delete ad;
   }
   return SIM_OK;
 }
@@ -336,22 +348,24 @@ int sim_contact_rollout_grad(const sim_contact_model* m, int dtype, int batch, c
     return cfail(SIM_ERR_UNSUPPORTED_DTYPE, "sim_contact_rollout_grad: dtype must be SIM_F32 or SIM_F64");
   if (batch < 0 || T < 0 || !(dt > 0))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: need batch >= 0, T >= 0, dt > 0");
-  if (tp.nq + tp.nv + tp.nu + 1 > kBlock)
-    return cfail(SIM_ERR_INVALID_TOPOLOGY, "sim_contact_rollout_grad: nq + nv + nu must not exceed 63");
+  if (m->niter > kSweepMax)
+    return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: at most " + std::to_string(kSweepMax) +
+                                          " PGS sweeps (niter) are recorded for the adjoint");
   if (batch == 0) return SIM_OK;
   if (!params || !traj || !gqT || !gqdT || !gq0 || !gqd0 || (T > 0 && tp.nu > 0 && (!tau || !gtau)))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: null array argument");
-  const dim3 grid(batch), block(kBlock);
+  const int spw = AdjSpw<double>::v;  // both dtypes reverse in FP64
+  const dim3 grid((batch + spw - 1) / spw), block(kBlock);
   if (dtype == SIM_F64) {
     GradArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)traj, (const double*)tau,
                        (const double*)gqT, (const double*)gqdT, (double*)gq0, (double*)gqd0, (double*)gtau,
                        (double*)gmu};
-    hipLaunchKernelGGL(k_contact_grad<double>, grid, block, 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL((k_contact_adj<double, double>), grid, block, 0, (hipStream_t)stream, a);
   } else {
     GradArgs<float> a{tp, batch, T, (float)dt, (const float*)params, (const float*)traj, (const float*)tau,
                       (const float*)gqT, (const float*)gqdT, (float*)gq0, (float*)gqd0, (float*)gtau,
                       (float*)gmu};
-    hipLaunchKernelGGL(k_contact_grad<float>, grid, block, 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL((k_contact_adj<float, double>), grid, block, 0, (hipStream_t)stream, a);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess)

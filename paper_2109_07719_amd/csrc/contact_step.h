@@ -122,6 +122,22 @@ struct Work {
   S pad_;
 };
 
+// What the step's adjoint needs beyond Work: the accelerations, the
+// contact set and the two solves' sweep vectors (filled when contact_step
+// gets a record).
+constexpr int kSweepMax = 64;  // PGS sweeps a recorded step may run
+template <typename S>
+struct Rec {
+  S qdd[kNV];               // accelerations (a free root's: true body-frame)
+  S qdm[kNV];               // qd_minus = qd + dt qdd
+  int na, r, nk, nkn;       // active contacts, rows, kept rows, kept normal rows
+  int act[kNC], keep[kNR], kn[kNC];
+  S phi[kNC], cl[kNC][3], pw[kNC][3];
+  S lamn[kNC];              // normal impulses of the first solve, per active contact
+  S x1[kSweepMax + 1][kNC]; // first solve: x at the start of every sweep (and the result)
+  S x2[kSweepMax + 1][kNR]; // second solve
+};
+
 // unit quaternion (x, y, z, w) -> rotation matrix (body -> world), row-major
 template <typename S>
 ABA_HD void quat_R(const S* qt, S* R) {
@@ -167,11 +183,15 @@ ABA_HD void ldl6_solve(const S* L, const S* D, const S* rhs, S* x) {
   }
 }
 
-// projected Gauss-Seidel on the rows idx[0..m) of A (leading dimension r)
+// projected Gauss-Seidel on the rows idx[0..m) of A (leading dimension r);
+// sweeps (nullable, stride ld): x at the start of every sweep and the result
 template <typename S>
-ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi, int niter, S* x) {
+ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi, int niter, S* x,
+                S* sweeps = nullptr, int ld = 0) {
   for (int i = 0; i < m; ++i) x[i] = S(0);
-  for (int it = 0; it < niter; ++it)
+  for (int it = 0; it < niter; ++it) {
+    if (sweeps)
+      for (int i = 0; i < m; ++i) sweeps[it * ld + i] = x[i];
     for (int i = 0; i < m; ++i) {
       const int ri = idx[i];
       S d = S(0);
@@ -182,14 +202,18 @@ ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* l
       else if (val(y) > val(hi[i])) y = hi[i];
       x[i] = y;
     }
+  }
+  if (sweeps)
+    for (int i = 0; i < m; ++i) sweeps[niter * ld + i] = x[i];
 }
 
 // One step with contact from (q, qd) under control u and friction
 // coefficient mu (a dual number for its derivative); returns the number of
-// active contacts.
+// active contacts.  rec (nullable, niter <= kSweepMax) keeps what the
+// step's adjoint needs.
 template <typename S, typename R>
 ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* qd, const S* u, R dt_, S mu,
-                            S* q1, S* qd1, Work<S>& w) {
+                            S* q1, S* qd1, Work<S>& w, Rec<S>* rec = nullptr) {
   using Rl = typename RealOf<S>::type;
   const int n = tp.n, nv = tp.nv;
   const S dt = S(dt_);
@@ -338,6 +362,7 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
         if (k >= 3) acc = acc + (w.E[i][3 * (k - 3)] * S(tp.g[0]) + w.E[i][3 * (k - 3) + 1] * S(tp.g[1]) +
                                  w.E[i][3 * (k - 3) + 2] * S(tp.g[2]));
         qd1[tp.vi[i] + k] = qd[tp.vi[i] + k] + dt * acc;
+        if (rec) rec->qdd[tp.vi[i] + k] = acc;
       }
     } else {
       const int p = tp.parent[i], off = tp.jtype[i] == SIM_JOINT_PRISMATIC ? 3 : 0;
@@ -350,8 +375,11 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       for (int k = 0; k < 6; ++k) w.a[i][k] = ap[k];
       for (int k = 0; k < 3; ++k) w.a[i][off + k] = w.a[i][off + k] + w.ax[i][k] * qdd;
       qd1[tp.vi[i]] = qd[tp.vi[i]] + dt * qdd;
+      if (rec) rec->qdd[tp.vi[i]] = qdd;
     }
   }
+  if (rec)
+    for (int k = 0; k < nv; ++k) rec->qdm[k] = qd1[k];
   // ---- detection and assembly
   int act[kNC], na = 0;
   S phi[kNC], cl[kNC][3], pw[kNC][3];
@@ -368,6 +396,20 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       for (int a = 0; a < 3; ++a)
         pw[na][a] = w.ow[l][a] + w.Ew[l][a] * cl[na][0] + w.Ew[l][3 + a] * cl[na][1] + w.Ew[l][6 + a] * cl[na][2];
       ++na;
+    }
+  }
+  if (rec) {
+    rec->na = na;
+    rec->r = 3 * na;
+    rec->nk = rec->nkn = 0;
+    for (int c = 0; c < na; ++c) {
+      rec->act[c] = act[c];
+      rec->phi[c] = phi[c];
+      rec->lamn[c] = S(0);
+      for (int a = 0; a < 3; ++a) {
+        rec->cl[c][a] = cl[c][a];
+        rec->pw[c][a] = pw[c][a];
+      }
     }
   }
   if (na > 0) {
@@ -470,7 +512,7 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       }
     S lo[kNR], hi[kNR], lamn[kNC], xn[kNC];
     for (int i = 0; i < nkn; ++i) { lo[i] = S(0); hi[i] = S(Big<Rl>::v); }
-    pgs(nkn, kn, r, w.A, w.b, lo, hi, tp.niter, xn);
+    pgs(nkn, kn, r, w.A, w.b, lo, hi, tp.niter, xn, rec ? &rec->x1[0][0] : nullptr, kNC);
     for (int c = 0; c < na; ++c) lamn[c] = S(0);
     for (int i = 0; i < nkn; ++i) lamn[kn[i] / 3] = xn[i];
     for (int i = 0; i < nk; ++i) {
@@ -483,7 +525,14 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       }
     }
     S xk[kNR];
-    pgs(nk, keep, r, w.A, w.b, lo, hi, tp.niter, xk);
+    pgs(nk, keep, r, w.A, w.b, lo, hi, tp.niter, xk, rec ? &rec->x2[0][0] : nullptr, kNR);
+    if (rec) {
+      rec->nk = nk;
+      rec->nkn = nkn;
+      for (int i = 0; i < nk; ++i) rec->keep[i] = keep[i];
+      for (int i = 0; i < nkn; ++i) rec->kn[i] = kn[i];
+      for (int c = 0; c < na; ++c) rec->lamn[c] = lamn[c];
+    }
     for (int j = 0; j < r; ++j) w.x[j] = S(0);
     for (int i = 0; i < nk; ++i) w.x[keep[i]] = xk[i];
     for (int k = 0; k < nv; ++k) {

@@ -208,7 +208,7 @@ def contact_emu():
         path = os.path.join(HERE, "hostemu", "libcontactemu.so")
         src = os.path.join(HERE, "hostemu", "contact_emu.cpp")
         csrc = os.path.join(HERE, "..", "paper_2109_07719_amd", "csrc")
-        deps = [src] + [os.path.join(csrc, f) for f in ("contact_step.h", "dual.h", "spatial.h")]
+        deps = [src] + [os.path.join(csrc, f) for f in ("contact_step.h", "contact_adjoint.h", "dual.h", "spatial.h")]
         if not os.path.exists(path) or os.path.getmtime(path) < max(os.path.getmtime(f) for f in deps):
             import subprocess
             tmp = f"{path}.{os.getpid()}.tmp"
@@ -219,5 +219,6 @@ def contact_emu():
         P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         L.emu_contact_rollout.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, P, D, I, P, P]
         L.emu_contact_grad.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, D, I, P, P, P, P, P, P]
+        L.emu_contact_grad_adj.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, D, I, P, P, P, P, P, P]
         _cemu = L
     return _cemu

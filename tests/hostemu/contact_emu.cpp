@@ -5,7 +5,7 @@
 // package.
 #include <vector>
 
-#include "../../paper_2109_07719_amd/csrc/contact_step.h"
+#include "../../paper_2109_07719_amd/csrc/contact_adjoint.h"
 
 using namespace aba_contact;
 using aba::Dual;
@@ -93,9 +93,48 @@ void grad(const CTopo& tp, const double* Pd, const double* traj, const double* t
   *gmu = double(mu_acc);
 }
 
+// the same gradient by the step's reverse statements (contact_step_vjp)
+template <typename R>
+void grad_adj(const CTopo& tp, const double* Pd, const double* traj, const double* tau, double dt, int T,
+              const double* gqT, const double* gqdT, double* gq0, double* gqd0, double* gtau, double* gmu) {
+  std::vector<R> Pv(Pd, Pd + tp.np);
+  const Par<R> P{Pv.data(), 1, 0};
+  const int nq = tp.nq, nx = tp.nq + tp.nv, nu = tp.nu;
+  std::vector<R> xb(nx), x(nx), u(nu > 0 ? nu : 1), ub(nu > 0 ? nu : 1);
+  for (int k = 0; k < nq; ++k) xb[k] = R(gqT[k]);
+  for (int k = 0; k < tp.nv; ++k) xb[nq + k] = R(gqdT[k]);
+  auto* w = new Work<R>;
+  auto* rc = new Rec<R>;
+  auto* ad = new Adj<R>;
+  R mu_acc = R(0);
+  for (int t = T - 1; t >= 0; --t) {
+    for (int k = 0; k < nx; ++k) x[k] = R(traj[t * nx + k]);
+    for (int k = 0; k < nu; ++k) u[k] = R(tau[t * nu + k]);
+    contact_step_vjp(tp, P, x.data(), x.data() + nq, u.data(), R(dt), R(tp.mu), xb.data(), ub.data(), mu_acc, *w,
+                     *rc, *ad);
+    for (int k = 0; k < nu; ++k) gtau[t * nu + k] = double(ub[k]);
+  }
+  delete w;
+  delete rc;
+  delete ad;
+  for (int k = 0; k < nq; ++k) gq0[k] = double(xb[k]);
+  for (int k = 0; k < tp.nv; ++k) gqd0[k] = double(xb[nq + k]);
+  *gmu = double(mu_acc);
+}
+
 }  // namespace
 
 extern "C" {
+
+void emu_contact_grad_adj(int fp64, int n, const int* parent, const int* jtype, int nc, const int* clink, double mu,
+                          double beta, int niter, const double* g, const double* P, const double* traj,
+                          const double* tau, double dt, int T, const double* gqT, const double* gqdT, double* gq0,
+                          double* gqd0, double* gtau, double* gmu) {
+  const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g);
+  if (fp64) grad_adj<double>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
+  else grad_adj<float>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
+}
+
 
 // fp64 = 1: double arithmetic, 0: float (inputs and outputs are double either way)
 void emu_contact_rollout(int fp64, int n, const int* parent, const int* jtype, int nc, const int* clink, double mu,

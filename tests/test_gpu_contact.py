@@ -9,10 +9,12 @@ gradient (Sec. 4.1 "Collision resolution"), through the C ABI
   oracle's, to round-off, through touchdown;
 * FP32: the GPU's step from its own states against the oracle's step,
   within the bar the step's conditioning sets (1e-4, see the host test), and
-  FP32 gradients against the oracle's on a short window;
+  the FP32 rollout's gradient (recomputed and reversed in FP64) against the
+  oracle's gradient along the GPU's own trajectory;
 * edge cases: no contact spheres (the plain step), an empty batch, invalid
   models;
-* the benchmark batch (4096 quadrupeds, 1000 steps) on sampled systems.
+* the benchmark batch (4096 quadrupeds, 1000 steps) on sampled systems:
+  steps and the full-horizon gradient along the GPU trajectory.
 """
 import numpy as np
 import pytest
@@ -22,7 +24,7 @@ torch = pytest.importorskip("torch")
 import contact_cases as CC
 import dyn_ref as R
 import oracle as O
-from helpers import rel
+from helpers import TOL_GRAD_F32, rel
 from paper_2109_07719_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -74,6 +76,36 @@ def _gpu(draws, dtype, T, mu=MU, beta=BETA, niter=NITER):
 def _oracle(d, mu=MU, beta=BETA, niter=NITER):
     s, q0, qd0, tau, links, centers, radii = d
     return O.Model(s, G), O.Contacts(links, centers, radii, mu=mu, beta=beta, niter=niter)
+
+
+def _r32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def _oracle32(d, mu=MU, beta=BETA, niter=NITER):
+    """The oracle's model of an FP32 batch: parameters, sphere geometry,
+    gravity and the solver constants rounded to FP32 as the GPU holds them."""
+    s, q0, qd0, tau, links, centers, radii = d
+    s32 = synth.System(parent=s.parent, jtype=s.jtype, E_T=_r32(s.E_T), r_T=_r32(s.r_T), axis=_r32(s.axis),
+                       mass=_r32(s.mass), com=_r32(s.com), Ic=_r32(s.Ic))
+    return (O.Model(s32, _r32(G)),
+            O.Contacts(links, _r32(centers), _r32(radii), mu=float(_r32(mu)), beta=float(_r32(beta)), niter=niter))
+
+
+def _oracle_grad_along(m, C, nq, traj_i, tau_i, dt, gqT, gqdT):
+    """The oracle's rollout gradient along a given trajectory: its one-step
+    gradient at every stored state x^t (traj_i [T + 1, nq + nv]), applied
+    backwards in time.  Returns gq0, gqd0, gtau [T, nu], gmu."""
+    T = tau_i.shape[0]
+    gq, gqd = np.asarray(gqT, np.float64), np.asarray(gqdT, np.float64)
+    gtau = np.zeros(tau_i.shape)
+    gmu = 0.0
+    for t in range(T - 1, -1, -1):
+        x = traj_i[t]
+        gq, gqd, gt, gm = O.rollout_contact_grad(m, C, x[:nq], x[nq:], tau_i[t:t + 1], dt, gq, gqd, mu_grad=True)
+        gtau[t] = gt[0]
+        gmu += gm
+    return gq, gqd, gtau, gmu
 
 
 @pytest.mark.parametrize("which", ["quadrupeds", "trees"])
@@ -132,7 +164,7 @@ def test_fp32_step_map_and_gradient():
     trn = tr.double().cpu().numpy()
     worst = 0.0
     for i in (0, 33, 77, 127):
-        m, C = _oracle(draws[i])
+        m, C = _oracle32(draws[i])
         tau_i = tau[:, :, i].double().cpu().numpy()
         for t in range(0, T, 3):
             x = trn[t, :, i]
@@ -140,25 +172,44 @@ def test_fp32_step_map_and_gradient():
             worst = max(worst, rel(trn[t + 1, :, i], np.r_[q1, qd1], 1e-6))
     print("fp32 worst step-map error %.1e" % worst)
     assert worst < 1e-4
-    # gradient over the last 10 steps (touchdown), from the GPU's own states
-    T2 = 10
-    tr2 = tr[T - T2:].contiguous()
-    tau2 = tau[T - T2:].contiguous()
+    # the gradient of the whole FP32 rollout (fall and touchdown) against the
+    # oracle's gradient along the GPU's own trajectory
     rng = np.random.default_rng(4)
     gqT = torch.tensor(rng.normal(size=(cb.nq, cb.B)), dtype=torch.float32, device=DEV)
     gqdT = torch.tensor(rng.normal(size=(cb.nv, cb.B)), dtype=torch.float32, device=DEV)
-    g = [x.double().cpu().numpy() for x in cb.grad(tr2, tau2, DT, gqT, gqdT)]
-    worst_g = 0.0
-    for i in (0, 33, 77, 127):
-        m, C = _oracle(draws[i])
-        x0 = tr2[0, :, i].double().cpu().numpy()
-        ref = O.rollout_contact_grad(m, C, x0[:cb.nq], x0[cb.nq:], tau2[:, :, i].double().cpu().numpy(), DT,
-                                     gqT[:, i].double().cpu().numpy(), gqdT[:, i].double().cpu().numpy())
-        scale = max(np.abs(r).max() for r in ref)
-        got = (g[0][:, i], g[1][:, i], g[2][:, :, i])
-        worst_g = max(worst_g, *[rel(a, b, 1e-3 * scale) for a, b in zip(got, ref)])
-    print("fp32 worst gradient error over the touchdown window %.1e" % worst_g)
-    assert worst_g < 1e-2
+    g = [x.double().cpu().numpy() for x in cb.grad(tr, tau, DT, gqT, gqdT, mu_grad=True)]
+    worst_g = _along_errors(cb, draws, trn, tau, gqT, gqdT, g, (0, 33, 77, 127))
+    print("fp32 worst gradient error along the GPU trajectory %.1e" % worst_g)
+    assert worst_g < TOL_CONTACT_ALONG
+
+
+# The FP32 contact gradient recomputes and reverses every step in FP64 from
+# the GPU's own FP32 states, with the constants the forward rollout used; the
+# oracle's one-step gradients at the same states, chained backwards, differ
+# from it only by FP64 rounding of two different evaluation orders (and by
+# the FP32 rounding of the outputs, 6e-8).  Over the 60-step landing that
+# keeps them within 1e-6.  Over 1000 steps of persistent contact the
+# backward recursion amplifies those roundings (measured 1e-5 to 2e-5 on
+# the benchmark batch); there the FP32 gradient bar applies.
+TOL_CONTACT_ALONG = 1e-6
+
+
+def _along_errors(cb, draws, trn, tau, gqT, gqdT, g, sample):
+    """Largest per-system error (q0, qd0, tau, mu) of the GPU gradient g
+    against the oracle's gradient along the GPU trajectory trn."""
+    dt32 = float(_r32(DT))
+    worst = 0.0
+    for i in sample:
+        m, C = _oracle32(draws[i])
+        ref = _oracle_grad_along(m, C, cb.nq, trn[:, :, i], tau[:, :, i].double().cpu().numpy(), dt32,
+                                 gqT[:, i].double().cpu().numpy(), gqdT[:, i].double().cpu().numpy())
+        got = (g[0][:, i], g[1][:, i], g[2][:, :, i], g[3][i])
+        scale = max(np.abs(r).max() for r in ref[:3])
+        e = [rel(a, b, 1e-6 * scale) for a, b in zip(got, ref)]
+        print(f"system {i}: gradient errors along the GPU trajectory (q0, qd0, tau, mu) "
+              + " ".join("%.1e" % x for x in e), flush=True)
+        worst = max(worst, *e)
+    return worst
 
 
 def test_edge_cases():
@@ -202,7 +253,7 @@ def test_benchmark_batch_sampled():
     print("case benchmark batch B", B, "T", T, flush=True)
     cb, q0, qd0, tau = _gpu(draws, torch.float32, T)
     qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, DT, counts=True)
-    g = cb.grad(tr, tau, DT, 2 * qT, qdT.clone())
+    g = cb.grad(tr, tau, DT, 2 * qT, qdT.clone(), mu_grad=True)
     torch.cuda.synchronize()
     assert all(torch.isfinite(x).all() for x in g)
     ncn = nc.cpu().numpy()
@@ -218,3 +269,12 @@ def test_benchmark_batch_sampled():
             worst = max(worst, rel(trn[t + 1, :, k], np.r_[q1, qd1], 1e-6))
     print("benchmark batch: fp32 worst sampled step-map error %.1e" % worst)
     assert worst < 1e-4
+    # the gradient of the full 1000-step rollout along the GPU trajectory
+    sample = list(range(0, B, 512))
+    gn = [x.double().cpu().numpy() for x in g]
+    gn = [gn[0][:, sample], gn[1][:, sample], gn[2][:, :, sample], gn[3][sample]]
+    gq, gqd = (2 * qT)[:, sample], qdT[:, sample]
+    worst_g = _along_errors(cb, [draws[i] for i in sample], trn, tau[:, :, sample], gq, gqd, gn,
+                            list(range(len(sample))))
+    print("benchmark batch: fp32 worst gradient error along the GPU trajectory %.1e" % worst_g)
+    assert worst_g < TOL_GRAD_F32

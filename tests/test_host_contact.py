@@ -47,13 +47,16 @@ def emu_rollout(s, links, centers, radii, mu, beta, niter, q0, qd0, tau, dt, fp6
     return tr, nc
 
 
-def emu_grad(s, links, centers, radii, mu, beta, niter, tr, tau, dt, gqT, gqdT, fp64=True):
+def emu_grad(s, links, centers, radii, mu, beta, niter, tr, tau, dt, gqT, gqdT, fp64=True, adjoint=False):
+    """adjoint=False: each step's Jacobian in dual numbers applied in
+    reverse time; adjoint=True: the step's reverse statements."""
     keep, a = _emu_args(s, links, centers, radii, mu, beta, niter)
     T = tau.shape[0]
     tau, gqT, gqdT = (np.ascontiguousarray(v, np.float64) for v in (tau, gqT, gqdT))
     gq0, gqd0, gtau, gmu = np.zeros(s.nq), np.zeros(s.nv), np.zeros((T, s.nu)), np.zeros(1)
-    contact_emu().emu_contact_grad(int(fp64), *a, _p(np.ascontiguousarray(tr)), _p(tau), dt, T, _p(gqT), _p(gqdT),
-                                   _p(gq0), _p(gqd0), _p(gtau), _p(gmu))
+    fn = contact_emu().emu_contact_grad_adj if adjoint else contact_emu().emu_contact_grad
+    fn(int(fp64), *a, _p(np.ascontiguousarray(tr)), _p(tau), dt, T, _p(gqT), _p(gqdT), _p(gq0), _p(gqd0), _p(gtau),
+       _p(gmu))
     return gq0, gqd0, gtau, gmu
 
 
@@ -119,8 +122,9 @@ def test_step_map_fp32_within_bar(k):
     assert worst < 1e-4
 
 
+@pytest.mark.parametrize("adjoint", [False, True], ids=["dual-jacobians", "reverse-statements"])
 @pytest.mark.parametrize("k", range(len(SCENES)), ids=[sc[0] for sc in SCENES])
-def test_gradient_fp64_matches_the_oracle(k):
+def test_gradient_fp64_matches_the_oracle(k, adjoint):
     name, s, q0, qd0, tau, links, centers, radii, mu, beta = SCENES[k]
     dt, niter = 1e-3, 30
     T = 50 if name.startswith("quadruped") else 25   # the quadruped touches down after ~30 steps
@@ -132,7 +136,7 @@ def test_gradient_fp64_matches_the_oracle(k):
     ref = O.rollout_contact_grad(m, C, q0, qd0, tau, dt, gqT, gqdT, mu_grad=True)
     ref = ref[:3] + (np.array([ref[3]]),)
     tr, nc = emu_rollout(s, links, centers, radii, mu, beta, niter, q0, qd0, tau, dt)
-    got = emu_grad(s, links, centers, radii, mu, beta, niter, tr, tau, dt, gqT, gqdT)
+    got = emu_grad(s, links, centers, radii, mu, beta, niter, tr, tau, dt, gqT, gqdT, adjoint=adjoint)
     # an exactly zero block (a sticking inelastic contact erases qd0) is
     # compared against the gradient's overall scale
     scale = max(np.abs(r).max() for r in ref if r.size)
@@ -144,8 +148,8 @@ def test_gradient_fp64_matches_the_oracle(k):
 
 def test_flop_count_grows_with_active_contacts():
     """sim_contact_flops (host code, no GPU): the count rises with each
-    active contact and the reverse step costs one dual-number step per
-    Jacobian column."""
+    active contact, and the reverse step (recompute plus the reverse
+    statements) costs more than the step and a small multiple of it."""
     from paper_2109_07719_amd import _native as N
     from paper_2109_07719_amd import synth
     from paper_2109_07719_amd.contact import _Model
@@ -165,5 +169,4 @@ def test_flop_count_grows_with_active_contacts():
         counts.append((a.value, b.value))
     print(counts)
     assert counts[0][0] < counts[2][0] and counts[0][1] < counts[2][1]
-    nx, nu = s.nq + s.nv, s.nu
-    assert all(b % (nx + nu) == 0 and b / (nx + nu) > 2 * a for a, b in counts)
+    assert all(a < b < 12 * a for a, b in counts)
