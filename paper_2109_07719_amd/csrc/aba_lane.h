@@ -65,6 +65,11 @@ struct Tape {
   V6<S> pa;    // bias force handed to the parent
   V6<S> ap;    // X a_parent + c
   S qdd;
+  // ball joint only: the joint-space blocks of pass 2 (ball_p2_local; not
+  // carried by widen or the stored tapes: the reverse pass rebuilds them)
+  Sy3<S> Ai;   // A^-1, A the angular block of IA
+  M3<S> W;     // A^-1 B
+  V3<S> y;     // A^-1 u
 };
 
 // Exact conversion of a link's constants and step intermediates to a wider
@@ -260,6 +265,88 @@ ABA_HD void root_accel(const SySp<S>& IA, const V6<S>& pA, const Q4<S>& quat, co
   abase = v6<S>(ap.a, ap.l + quat_rotate_T(quat, g));
 }
 
+// ------------------------------------------------------------- ball joint
+// A spherical joint: X_J = rot(R(quat)^T) (a rotation, no translation),
+// S = [1; 0] (the three angular unit vectors of the link frame), state
+// (quat, w) with w the joint's angular velocity in link coordinates, three
+// torques; R(quat) = (w^2 - u.u) 1 + 2 u u^T + 2 w [u]x for quat = (u, w),
+// so a quaternion off the unit sphere scales X_J by |quat|^2 (the joint
+// model of Sec. 2 and the quaternion operators of App. G).  With S = [1; 0]
+// the 3x3 joint-space blocks of pass 2 are blocks of IA = [A B; B^T C]:
+// U = IA S = [A; B^T] and D = S^T U = A, hence
+//   Ia = IA - U D^-1 U^T = [0 0; 0 C - B^T W],   W = A^-1 B,
+//   pa = pA + Ia c + U D^-1 u = [tau; pA_l + Ia_C c_l + B^T y],  y = A^-1 u,
+// and pass 3's qdd = D^-1 (u - U^T a') = y - a'_a - W a'_l with
+// a = a' + S qdd = [y - W a'_l; a'_l].
+template <typename S>
+ABA_HD M3<S> ball_E(const Q4<S>& q, const M3<S>& ET) {
+  M3<S> E;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const V3<S> c = quat_rotate_T(q, col(ET, j));
+    E.m[j] = c.x;
+    E.m[3 + j] = c.y;
+    E.m[6 + j] = c.z;
+  }
+  return E;
+}
+// inverse of a symmetric 3x3 matrix (adjugate over the determinant)
+template <typename S>
+ABA_HD Sy3<S> sy3_inv(const Sy3<S>& A) {
+  const S c00 = A.yy * A.zz - A.yz * A.yz;
+  const S c01 = A.xz * A.yz - A.xy * A.zz;
+  const S c02 = A.xy * A.yz - A.xz * A.yy;
+  const S c11 = A.xx * A.zz - A.xz * A.xz;
+  const S c12 = A.xy * A.xz - A.xx * A.yz;
+  const S c22 = A.xx * A.yy - A.xy * A.xy;
+  const S id = rcp(A.xx * c00 + A.xy * c01 + A.xz * c02);
+  return sy3<S>(c00 * id, c11 * id, c22 * id, c01 * id, c02 * id, c12 * id);
+}
+// Ia_C = C - B^T W
+template <typename S>
+ABA_HD Sy3<S> ball_IaC(const Tape<S>& t) {
+  const M3<S>& B = t.IA.B;
+  const V3<S> b0 = col(B, 0), b1 = col(B, 1), b2 = col(B, 2);
+  const V3<S> w0 = col(t.W, 0), w1 = col(t.W, 1), w2 = col(t.W, 2);
+  const Sy3<S>& C = t.IA.C;
+  return sy3<S>(C.xx - dot(b0, w0), C.yy - dot(b1, w1), C.zz - dot(b2, w2), C.xy - dot(b0, w1),
+                C.xz - dot(b0, w2), C.yz - dot(b1, w2));
+}
+// pass 1 (ball): E from the quaternion; v = X v_parent + [w; 0]; c = v x [w; 0]
+template <typename S>
+ABA_HD void ball_p1(const LinkC<S>& L, Tape<S>& t, const Q4<S>& quat, const V3<S>& w, const V6<S>& vpar) {
+  t.E = ball_E(quat, L.ET);
+  const V6<S> vJ = v6<S>(w, zero3<S>());
+  t.v = xform(t.E, L.rT, vpar) + vJ;
+}
+// pass 2 (ball): the joint-space blocks; returns u = tau - pA_a
+template <typename S>
+ABA_HD V3<S> ball_p2_local(Tape<S>& t, const V3<S>& tau) {
+  const V3<S> u = tau - t.pA.a;
+  t.Ai = sy3_inv(t.IA.A);
+  t.y = mul(t.Ai, u);
+  t.W = mul(sy_to_m3(t.Ai), t.IA.B);
+  return u;
+}
+// pass 2 (ball with a parent link): pa, and the parent's shares X^T Ia X, X^T pa
+template <typename S>
+ABA_HD void ball_p2_push(const LinkC<S>& L, Tape<S>& t, const V3<S>& tau, SySp<S>& IA_up, V6<S>& pA_up) {
+  const Sy3<S> IaC = ball_IaC(t);
+  t.pa = v6<S>(tau, t.pA.l + mul(IaC, t.c.l) + mulT(t.IA.B, t.y));
+  SySp<S> Ia = zero_sysp<S>();
+  Ia.C = IaC;
+  IA_up = congruence_XT(t.E, L.rT, Ia);
+  pA_up = xformT(t.E, L.rT, t.pa);
+}
+// pass 3 (ball): a' = X a_parent + c; qdd = y - a'_a - W a'_l; returns a
+template <typename S>
+ABA_HD V6<S> ball_p3(const LinkC<S>& L, Tape<S>& t, const V6<S>& apar, V3<S>& qdd) {
+  t.ap = xform(t.E, L.rT, apar) + t.c;
+  const V3<S> Wl = mul(t.W, t.ap.l);
+  qdd = t.y - t.ap.a - Wl;
+  return v6<S>(t.y - Wl, t.ap.l);
+}
+
 // ----------------------------------------------------------------- integrator
 // 1-dof joint: qd1 = qd + dt qdd; q1 = q + dt qd1
 template <typename S>
@@ -267,15 +354,13 @@ ABA_HD void integrate_joint(S& q, S& qd, S qdd, S dt) {
   qd = qd + dt * qdd;
   q = q + dt * qd;
 }
-// free root: v1 = v + dt a; p1 = p + dt R(quat) v1_lin;
-// quat1 = normalize(quat + dt/2 quat (x) (w1, 0))
+// quaternion step of a free root or ball joint with the new angular
+// velocity w1 (body frame): normalize(quat + dt/2 quat (x) (w1, 0))
 template <typename S>
-ABA_HD void integrate_root(V3<S>& p, Q4<S>& quat, V6<S>& v, const V6<S>& abase, S dt) {
-  v = v + dt * abase;
-  p = axpy(p, dt, quat_rotate(quat, v.l));
+ABA_HD Q4<S> quat_step(const Q4<S>& quat, const V3<S>& w1, S dt) {
   const V3<S> u = v3<S>(quat.x, quat.y, quat.z);
-  const V3<S> ov = axpy(cross(u, v.a), quat.w, v.a);
-  const S ow = -dot(u, v.a);
+  const V3<S> ov = axpy(cross(u, w1), quat.w, w1);
+  const S ow = -dot(u, w1);
   const S h = S(0.5) * dt;
   Q4<S> r;
   r.x = quat.x + h * ov.x;
@@ -283,10 +368,20 @@ ABA_HD void integrate_root(V3<S>& p, Q4<S>& quat, V6<S>& v, const V6<S>& abase, 
   r.z = quat.z + h * ov.z;
   r.w = quat.w + h * ow;
   const S inv = S(1) / sqrt(r.x * r.x + r.y * r.y + r.z * r.z + r.w * r.w);
-  quat.x = r.x * inv;
-  quat.y = r.y * inv;
-  quat.z = r.z * inv;
-  quat.w = r.w * inv;
+  Q4<S> o;
+  o.x = r.x * inv;
+  o.y = r.y * inv;
+  o.z = r.z * inv;
+  o.w = r.w * inv;
+  return o;
+}
+// free root: v1 = v + dt a; p1 = p + dt R(quat) v1_lin;
+// quat1 = normalize(quat + dt/2 quat (x) (w1, 0))
+template <typename S>
+ABA_HD void integrate_root(V3<S>& p, Q4<S>& quat, V6<S>& v, const V6<S>& abase, S dt) {
+  v = v + dt * abase;
+  p = axpy(p, dt, quat_rotate(quat, v.l));
+  quat = quat_step(quat, v.a, dt);
 }
 
 // ----------------------------------------------------------------- adjoint
@@ -563,18 +658,154 @@ ABA_HD V6<S> r1_root(const LinkC<S>& L, const V6<S>& v, const V6<S>& vbar, const
   return vbar + r1_own(L, v, b, pAb, S(0), false);
 }
 
-// adjoint of integrate_root.  Inputs: state at the start of the step (p,
-// quat, v), the base acceleration, and the adjoints of the new state (pb,
-// quatb, vb: overwritten with the adjoints of the old state's integrator
-// share).  Returns the base-acceleration seed dt * v1_bar.
+// ----------------------------------------------------- ball joint adjoint
+// Accumulators of a ball lane beyond Bar (whose c, G it shares: G collects
+// the pairings of X with rotations, X -> exp(-crm([d; 0])) X changing the
+// loss by G_a . d, for every step, as the joint's quaternion needs them).
 template <typename S>
-ABA_HD V6<S> integrate_root_adj(const Q4<S>& quat, const V6<S>& v, const V6<S>& abase, S dt, V3<S>& pb,
-                                Q4<S>& quatb, V6<S>& vb) {
-  (void)pb;  // p1 = p + ...: the position adjoint passes through unchanged
-  const V6<S> v1 = v + dt * abase;
+struct BallBar {
+  V3<S> y;  // y_bar
+  M3<S> W;  // W_bar (all nine entries)
+};
+template <typename S>
+ABA_HD void ball_bar_zero(BallBar<S>& bb) {
+  bb.y = zero3<S>();
+#pragma unroll
+  for (int k = 0; k < 9; ++k) bb.W.m[k] = S(0);
+}
+// reverse of pass 3 (ball), serial part: abar with the children's shares,
+// qddb the integrator's seed; returns ap_bar and sets s = a_bar_a + qdd_bar.
+template <typename S>
+ABA_HD V6<S> ball_r3_path(const Tape<S>& t, const V6<S>& abar, const V3<S>& qddb, V3<S>& s) {
+  // a = [y - W a'_l; a'_l], qdd = y - a'_a - W a'_l
+  s = abar.a + qddb;
+  return v6<S>(-qddb, abar.l - mulT(t.W, s));
+}
+template <typename S>
+ABA_HD void ball_r3_local(const Tape<S>& t, Bar<S>& b, BallBar<S>& bb, const V6<S>& apb, const V3<S>& s) {
+  bb.y = bb.y + s;
+  bb.W = bb.W + outer(s, t.ap.l, S(-1));
+  // ap = X a_parent + c
+  b.G = b.G + qvec(apb, t.ap - t.c);
+  b.c = b.c + apb;
+}
+// reverse of pass 2 (ball), serial part: as r2_path for a 1-dof joint; u is
+// the forward's tau - pA_a.  Returns tau_bar.  IAb follows the symmetric
+// convention of IA's adjoints (its B block is half of the adjoint of B as
+// one matrix that appears as B and B^T).
+template <typename S>
+ABA_HD V3<S> ball_r2_path(const LinkC<S>& L, const Tape<S>& t, BallBar<S>& bb, const V3<S>& u, bool has_parent,
+                          const SySp<S>& IAbp, const V6<S>& pAbp, SySp<S>& N, V6<S>& pab, SySp<S>& IAb,
+                          V6<S>& pAb) {
+  V3<S> taub = zero3<S>();
+  pAb = zero6<S>();
+  M3<S> Bb;  // adjoint of B (all nine entries, B and B^T counted once each)
+  Sy3<S> Cb = sy3<S>(S(0), S(0), S(0), S(0), S(0), S(0));
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Bb.m[k] = S(0);
+  if (has_parent) {
+    pab = xform(t.E, L.rT, pAbp);
+    N = congruence_X(t.E, L.rT, IAbp);
+    // pa = [tau; pA_l + Ia_C c_l + B^T y]
+    taub = pab.a;
+    pAb.l = pab.l;
+    const Sy3<S> IaCb = N.C + sym_outer(pab.l, t.c.l, S(0.5));
+    Bb = outer(t.y, pab.l, S(1));
+    bb.y = bb.y + mul(t.IA.B, pab.l);
+    // Ia_C = C - B^T W
+    Cb = IaCb;
+    const M3<S> Ic = sy_to_m3(IaCb);
+    const M3<S> WI = mul(t.W, Ic), BI = mul(t.IA.B, Ic);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      Bb.m[k] = Bb.m[k] - WI.m[k];
+      bb.W.m[k] = bb.W.m[k] - BI.m[k];
+    }
+  }
+  // W = A^-1 B, y = A^-1 u
+  const M3<S> Aim = sy_to_m3(t.Ai);
+  const M3<S> AiW = mul(Aim, bb.W);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Bb.m[k] = Bb.m[k] + AiW.m[k];
+  const V3<S> ub = mul(t.Ai, bb.y);
+  // A^-1 bar = W_bar B^T + y_bar u^T, symmetric part
+  const M3<S> WBt = mul(bb.W, transpose(t.IA.B));
+  const Sy3<S> Aib = sy3<S>(WBt.m[0] + bb.y.x * u.x, WBt.m[4] + bb.y.y * u.y, WBt.m[8] + bb.y.z * u.z,
+                            S(0.5) * (WBt.m[1] + WBt.m[3] + bb.y.x * u.y + bb.y.y * u.x),
+                            S(0.5) * (WBt.m[2] + WBt.m[6] + bb.y.x * u.z + bb.y.z * u.x),
+                            S(0.5) * (WBt.m[5] + WBt.m[7] + bb.y.y * u.z + bb.y.z * u.y));
+  // u = tau - pA_a
+  taub = taub + ub;
+  pAb.a = -ub;
+  // A^-1 = inv(A): A_bar = -A^-1 sym(A^-1 bar) A^-1
+  const Sy3<S> Ab = cong(Aim, Aib);
+  IAb.A = sy3<S>(-Ab.xx, -Ab.yy, -Ab.zz, -Ab.xy, -Ab.xz, -Ab.yz);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) IAb.B.m[k] = S(0.5) * Bb.m[k];
+  IAb.C = Cb;
+  return taub;
+}
+// reverse of pass 2 (ball with a parent), local part: the pairings of the
+// shift statements and the Ia c term's share of c_bar
+template <typename S>
+ABA_HD void ball_r2_local(const Tape<S>& t, Bar<S>& b, const SySp<S>& N, const V6<S>& pab) {
+  SySp<S> Ia = zero_sysp<S>();
+  Ia.C = ball_IaC(t);
+  b.G = b.G + qvec(t.pa, pab) - S(2) * crmS_vec(Ia, N);
+  b.c = b.c + mul(Ia, pab);
+}
+// reverse of pass 1 (ball): the link's own share of its velocity adjoint
+template <typename S>
+ABA_HD V6<S> ball_r1_own(const LinkC<S>& L, const V6<S>& v, const Bar<S>& b, const V6<S>& pAb, const V3<S>& w) {
+  // c = v x vJ = -crm(vJ) v, vJ = [w; 0]
+  return r1_own(L, v, b, pAb, S(0), false) - crmT(v6<S>(w, zero3<S>()), b.c);
+}
+// local part: returns the joint-rate adjoint; v_bar is complete
+template <typename S>
+ABA_HD V3<S> ball_r1_local(const Tape<S>& t, Bar<S>& b, const V6<S>& vbar, const V3<S>& w) {
+  const V6<S> vJ = v6<S>(w, zero3<S>());
+  const V6<S> vJb = crmT(t.v, b.c) + vbar;
+  // v = X v_parent + vJ
+  b.G = b.G + qvec(vbar, t.v - vJ);
+  return vJb.a;
+}
+// The quaternion's adjoint from the rotation pairings, along the unit
+// sphere.  A change dq = q (x) (d/2, 0) turns E_J = R(q)^T into
+// (1 - [d]x) E_J, i.e. X into X - crm([d; 0]) X, so dL = G_a . d with
+// d/2 = vec(q^-1 (x) dq), hence q_bar = 2 / |q|^2 q (x) (G_a, 0), which is
+// orthogonal to q.  The radial part is left out on purpose: it depends only
+// on how the step is continued off the unit sphere (where R(q) is scaled,
+// and the free root's Galilean shift no longer leaves the dynamics
+// unchanged), the integrator's normalisation removes it from every earlier
+// step's adjoint, and the integrator's own share is tangent as well.
+template <typename S>
+ABA_HD Q4<S> ball_quat_bar(const Q4<S>& q, const V3<S>& Ga) {
+  const S k = S(2) / (q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+  const V3<S> u = v3<S>(q.x, q.y, q.z);
+  const V3<S> rv = axpy(cross(u, Ga), q.w, Ga);
+  Q4<S> o;
+  o.x = k * rv.x;
+  o.y = k * rv.y;
+  o.z = k * rv.z;
+  o.w = -k * dot(u, Ga);
+  return o;
+}
+// Placement adjoint of a ball link (no axis): X_T -> exp(-crm(xi)) X_T
+// moves X by -crm(Xh_J xi) X with Xh_J = X_J / |q|^2 the joint's rotation,
+// so xi_bar += Xh_J^T G = [R G_a; R G_l] / |q|^2.
+template <typename S>
+ABA_HD void ball_frame_bar_add(ParamBar<S>& g, const Q4<S>& q, const Bar<S>& b) {
+  const S k = S(1) / (q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+  g.xi = g.xi + v6<S>(k * quat_rotate(q, b.G.a), k * quat_rotate(q, b.G.l));
+}
+
+// adjoint of quat_step: from the adjoint q1b of the new quaternion, returns
+// the quaternion's share of the adjoint of quat and adds w1's to w1b.
+template <typename S>
+ABA_HD Q4<S> quat_step_adj(const Q4<S>& quat, const V3<S>& w1, S dt, const Q4<S>& q1b, V3<S>& w1b) {
   const V3<S> u = v3<S>(quat.x, quat.y, quat.z);
-  const V3<S> ov = axpy(cross(u, v1.a), quat.w, v1.a);
-  const S ow = -dot(u, v1.a);
+  const V3<S> ov = axpy(cross(u, w1), quat.w, w1);
+  const S ow = -dot(u, w1);
   const S h = S(0.5) * dt;
   Q4<S> r;
   r.x = quat.x + h * ov.x;
@@ -584,20 +815,38 @@ ABA_HD V6<S> integrate_root_adj(const Q4<S>& quat, const V6<S>& v, const V6<S>& 
   const S inv = S(1) / sqrt(r.x * r.x + r.y * r.y + r.z * r.z + r.w * r.w);
   const Q4<S> q1 = {r.x * inv, r.y * inv, r.z * inv, r.w * inv};
   // quat1 = r / |r|
-  const S d = q1.x * quatb.x + q1.y * quatb.y + q1.z * quatb.z + q1.w * quatb.w;
-  const V3<S> rbv = v3<S>((quatb.x - q1.x * d) * inv, (quatb.y - q1.y * d) * inv, (quatb.z - q1.z * d) * inv);
-  const S rbw = (quatb.w - q1.w * d) * inv;
+  const S d = q1.x * q1b.x + q1.y * q1b.y + q1.z * q1b.z + q1.w * q1b.w;
+  const V3<S> rbv = v3<S>((q1b.x - q1.x * d) * inv, (q1b.y - q1.y * d) * inv, (q1b.z - q1.z * d) * inv);
+  const S rbw = (q1b.w - q1.w * d) * inv;
   // r = quat + h * quat (x) (w1, 0):  o_v = qw w1 + u x w1, o_w = -u . w1
+  const V3<S> qvb = rbv + h * (cross(w1, rbv) - rbw * w1);
+  const S qwb = rbw + h * dot(w1, rbv);
+  w1b = w1b + h * (quat.w * rbv - cross(u, rbv) - rbw * u);
+  Q4<S> o;
+  o.x = qvb.x;
+  o.y = qvb.y;
+  o.z = qvb.z;
+  o.w = qwb;
+  return o;
+}
+
+// adjoint of integrate_root.  Inputs: state at the start of the step (p,
+// quat, v), the base acceleration, and the adjoints of the new state (pb,
+// quatb, vb: overwritten with the adjoints of the old state's integrator
+// share).  Returns the base-acceleration seed dt * v1_bar.
+template <typename S>
+ABA_HD V6<S> integrate_root_adj(const Q4<S>& quat, const V6<S>& v, const V6<S>& abase, S dt, V3<S>& pb,
+                                Q4<S>& quatb, V6<S>& vb) {
+  (void)pb;  // p1 = p + ...: the position adjoint passes through unchanged
+  const V6<S> v1 = v + dt * abase;
   V6<S> v1b = vb;
-  const V3<S> qvb = rbv + h * (cross(v1.a, rbv) - rbw * v1.a);
-  const S qwb = rbw + h * dot(v1.a, rbv);
-  v1b.a = v1b.a + h * (quat.w * rbv - cross(u, rbv) - rbw * u);
+  const Q4<S> qs = quat_step_adj(quat, v1.a, dt, quatb, v1b.a);
   // p1 = p + dt R(quat) v1_lin
   const Q4<S> gq = quat_rot_grad(quat, dt * pb, v1.l);
-  quatb.x = qvb.x + gq.x;
-  quatb.y = qvb.y + gq.y;
-  quatb.z = qvb.z + gq.z;
-  quatb.w = qwb + gq.w;
+  quatb.x = qs.x + gq.x;
+  quatb.y = qs.y + gq.y;
+  quatb.z = qs.z + gq.z;
+  quatb.w = qs.w + gq.w;
   v1b.l = v1b.l + quat_rotate_T(quat, dt * pb);
   // v1 = v + dt abase
   vb = v1b;

@@ -19,13 +19,13 @@
 //     (p1 = p + dt R v_lin1 and the normalised quaternion step for a free
 //     root, q1 = q + dt qd1 for 1-dof joints).
 //
-// Design: the forward runs one lane per system and keeps the whole tree's
-// articulated quantities in the lane's private memory.  J comes from the
+// Design: the forward runs one lane per system, a few systems to a wave, and
+// keeps the whole tree's articulated quantities in LDS.  J comes from the
 // world poses and joint axes along the contact link's path to the root;
 // each column of M^-1 J^T is the articulated-body response to a unit force
 // at the contact point (passes 2 and 3 of the ABA with the factorisation
 // of the step's own pass 2 reused, no velocity or gravity terms).  The
-// gradient runs backwards in time, one lane per system: each step is
+// gradient runs backwards in time, also one lane per system: each step is
 // recomputed from the stored state, then its statements are reversed
 // (contact_adjoint.h), and the adjoint of the state is carried to the
 // previous step (Sec. 3, Eq. adj_back; Sec. 4.1, Eq. adj_r).
@@ -81,7 +81,7 @@ namespace {
 
 // ---- kernels ---------------------------------------------------------------
 
-constexpr int kBlock = 64;
+constexpr int kWave = 64;
 
 template <typename R>
 struct RollArgs {
@@ -101,21 +101,29 @@ struct RollArgs {
 // Systems per workgroup of the rollout: each keeps its Work record in LDS
 // (16 x 9.7 KB in FP32, 8 x 19.4 KB in FP64), so the step's many dependent
 // accesses to the tree's articulated quantities see LDS rather than scratch
-// latency, and a batch spreads over four times as many CUs as at one system
-// per lane of a full wave.
+// latency.  A system is one lane; SPL systems share a wave (the workgroup's
+// SPW / SPL waves spread over the CU's SIMDs).  Systems in one wave advance
+// in lockstep and serialise wherever their contact sets differ, while a
+// wave per system pays a full issue slot, and a full private-memory
+// request, for one lane's work.  On the landing quadrupeds (4096 x 200
+// steps) the rollout took 141, 134, 114, 110 and about 156 ms at 1, 2, 4, 8
+// and 16 systems per wave, the FP64 reverse 4560 (scaled from 1000 steps),
+// 2173, 1858 and 1578 ms at 1, 2, 4 and 8.
 template <typename R> struct RollSpw;
-template <> struct RollSpw<float> { static constexpr int v = 16; };
-template <> struct RollSpw<double> { static constexpr int v = 8; };
+template <> struct RollSpw<float> { static constexpr int v = 16, spl = 8; };
+template <> struct RollSpw<double> { static constexpr int v = 8, spl = 8; };
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_contact_rollout(RollArgs<R> a) {
-  constexpr int SPW = RollSpw<R>::v;
+__global__ __launch_bounds__(kWave * RollSpw<R>::v / RollSpw<R>::spl) void k_contact_rollout(RollArgs<R> a) {
+  constexpr int SPW = RollSpw<R>::v, SPL = RollSpw<R>::spl;
   static_assert(SPW * sizeof(Work<R>) <= 160 * 1024, "LDS budget");
+  static_assert(SPW % SPL == 0 && SPL <= kWave, "whole waves");
   static_assert((sizeof(Work<R>) / sizeof(R)) % 2 == 1, "odd Work stride");
   __shared__ Work<R> wsh[SPW];
-  const int lane = threadIdx.x;
-  const int s = blockIdx.x * SPW + lane;
-  if (lane >= SPW || s >= a.B) return;
+  const int ln = threadIdx.x % kWave;
+  const int sw = (threadIdx.x / kWave) * SPL + ln;
+  const int s = blockIdx.x * SPW + sw;
+  if (ln >= SPL || s >= a.B) return;
   const CTopo& tp = a.tp;
   const size_t B = (size_t)a.B;
   const Par<R> P{a.P, B, s};
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_contact_rollout(RollArgs<R> a) {
   for (int k = 0; k < nv; ++k) x[0][nq + k] = a.qd0[k * B + s];
   if (a.traj)
     for (int k = 0; k < nx; ++k) a.traj[k * B + s] = x[0][k];
-  Work<R>& w = wsh[lane];
+  Work<R>& w = wsh[sw];
   int cur = 0;
   for (int t = 0; t < a.T; ++t) {
     for (int k = 0; k < nu; ++k) u[k] = a.tau[((size_t)t * nu + k) * B + s];
@@ -160,23 +168,25 @@ struct GradArgs {
 // runs the adjoints of the integrator, the impulse update, both
 // Gauss-Seidel solves (from their recorded sweep vectors), A and b, the
 // unit-impulse responses, the contact geometry and the smooth ABA step.
-// One lane per system; R is the arithmetic (FP64 for FP32 I/O: the
-// recompute and the reverse sweeps start from the widened FP32 states, so
-// the gradient is that of the step map along the FP32 trajectory), each
-// lane's Work record in LDS as in the rollout, its sweep record and
-// adjoint arrays in private memory.
+// One lane per system, SPL systems to a wave, as in the rollout; R is the
+// arithmetic (FP64 for FP32 I/O: the recompute and the reverse sweeps start
+// from the widened FP32 states, so the gradient is that of the step map
+// along the FP32 trajectory), each lane's Work record in LDS as in the
+// rollout, its sweep record and adjoint arrays in private memory.
 template <typename R> struct AdjSpw;
-template <> struct AdjSpw<float> { static constexpr int v = 16; };
-template <> struct AdjSpw<double> { static constexpr int v = 8; };
+template <> struct AdjSpw<float> { static constexpr int v = 16, spl = 8; };
+template <> struct AdjSpw<double> { static constexpr int v = 8, spl = 8; };
 
 template <typename S, typename R>
-__global__ __launch_bounds__(kBlock) void k_contact_adj(GradArgs<S> a) {
-  constexpr int SPW = AdjSpw<R>::v;
+__global__ __launch_bounds__(kWave * AdjSpw<R>::v / AdjSpw<R>::spl) void k_contact_adj(GradArgs<S> a) {
+  constexpr int SPW = AdjSpw<R>::v, SPL = AdjSpw<R>::spl;
   static_assert(SPW * sizeof(Work<R>) <= 160 * 1024, "LDS budget");
+  static_assert(SPW % SPL == 0 && SPL <= kWave, "whole waves");
   __shared__ Work<R> wsh[SPW];
-  const int lane = threadIdx.x;
-  const int s = blockIdx.x * SPW + lane;
-  if (lane >= SPW || s >= a.B) return;
+  const int ln = threadIdx.x % kWave;
+  const int sw = (threadIdx.x / kWave) * SPL + ln;
+  const int s = blockIdx.x * SPW + sw;
+  if (ln >= SPL || s >= a.B) return;
   // the model's constants as the forward rollout saw them (rounded to S)
   CTopo tp = a.tp;
   for (int k = 0; k < 3; ++k) tp.g[k] = double(S(tp.g[k]));
@@ -191,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_contact_adj(GradArgs<S> a) {
   for (int k = 0; k < nq; ++k) xb[k] = R(a.gqT[k * B + s]);
   for (int k = 0; k < nv; ++k) xb[nq + k] = R(a.gqdT[k * B + s]);
   R mub = R(0);
-  Work<R>& w = wsh[lane];
+  Work<R>& w = wsh[sw];
   for (int t = a.T - 1; t >= 0; --t) {
     for (int k = 0; k < nx; ++k) x[k] = R(a.traj[((size_t)t * nx + k) * B + s]);
     for (int k = 0; k < nu; ++k) u[k] = R(a.tau[((size_t)t * nu + k) * B + s]);
@@ -321,7 +331,8 @@ int sim_contact_rollout(const sim_contact_model* m, int dtype, int batch, const 
   if (!params || !q0 || !qd0 || !qT || !qdT || (T > 0 && tp.nu > 0 && !tau))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout: null array argument");
   const int spw = dtype == SIM_F64 ? RollSpw<double>::v : RollSpw<float>::v;
-  const dim3 grid((batch + spw - 1) / spw), block(kBlock);
+  const int spl = dtype == SIM_F64 ? RollSpw<double>::spl : RollSpw<float>::spl;
+  const dim3 grid((batch + spw - 1) / spw), block(kWave * (spw / spl));
   hipError_t e;
   if (dtype == SIM_F64) {
     RollArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)q0, (const double*)qd0,
@@ -354,8 +365,8 @@ int sim_contact_rollout_grad(const sim_contact_model* m, int dtype, int batch, c
   if (batch == 0) return SIM_OK;
   if (!params || !traj || !gqT || !gqdT || !gq0 || !gqd0 || (T > 0 && tp.nu > 0 && (!tau || !gtau)))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: null array argument");
-  const int spw = AdjSpw<double>::v;  // both dtypes reverse in FP64
-  const dim3 grid((batch + spw - 1) / spw), block(kBlock);
+  const int spw = AdjSpw<double>::v, spl = AdjSpw<double>::spl;  // both dtypes reverse in FP64
+  const dim3 grid((batch + spw - 1) / spw), block(kWave * (spw / spl));
   if (dtype == SIM_F64) {
     GradArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)traj, (const double*)tau,
                        (const double*)gqT, (const double*)gqdT, (double*)gq0, (double*)gqd0, (double*)gtau,

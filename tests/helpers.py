@@ -24,6 +24,23 @@ def rel(x, ref, floor=FLOOR_F32):
     return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref), floor))
 
 
+def ball_tangent(s, q, gq):
+    """gq with the radial part of every ball joint's quaternion adjoint
+    removed (g - (g . qh) qh, qh = q / |q|): the library returns a ball
+    joint's quaternion gradient along the unit sphere.  q, gq: one system's
+    [nq] (or [..., nq]) arrays."""
+    g = np.array(gq, dtype=np.float64, copy=True)
+    qi = 0
+    for i in range(s.n):
+        if s.jtype[i] == 3:
+            qh = np.asarray(q[..., qi:qi + 4], dtype=np.float64)
+            qh = qh / np.linalg.norm(qh, axis=-1, keepdims=True)
+            gi = g[..., qi:qi + 4]
+            g[..., qi:qi + 4] = gi - np.sum(gi * qh, axis=-1, keepdims=True) * qh
+        qi += 7 if s.jtype[i] == 1 else 4 if s.jtype[i] == 3 else 1
+    return g
+
+
 def split(vec, off):
     return [vec[..., off[i]:off[i + 1]] for i in range(len(off) - 1)]
 
@@ -107,8 +124,8 @@ def _axis_to_z(a):
 
 def canonical_rotations(s):
     """Per link, the rotation Rl of the library's joint-axis canonicalisation
-    (identity for a free root)."""
-    return [np.eye(3) if s.jtype[i] == 1 else _axis_to_z(s.axis[i]) for i in range(s.n)]
+    (identity for a free root and a ball joint)."""
+    return [np.eye(3) if s.jtype[i] in (1, 3) else _axis_to_z(s.axis[i]) for i in range(s.n)]
 
 
 def frame_grad_to_user(s, acc):
@@ -123,6 +140,10 @@ def frame_grad_to_user(s, acc):
         if s.jtype[i] == 1:
             continue
         R = Rs[i]
+        if s.jtype[i] == 3:  # no axis: placement only
+            out[i, 0:3] = acc[i, 0:3]
+            out[i, 3:6] = np.asarray(s.E_T[i]).T @ acc[i, 3:6]
+            continue
         xa, xl = R.T @ acc[i, 0:3], R.T @ acc[i, 3:6]
         a = np.asarray(s.axis[i], dtype=np.float64)
         a = a / np.linalg.norm(a)
@@ -139,7 +160,7 @@ def link_constants(s):
     inertia about the link origin (xx yy zz xy xz yz) with c' = Rl c,
     Ic' = Rl Ic Rl^T."""
     n = s.n
-    Rs = [np.eye(3) if s.jtype[i] == 1 else _axis_to_z(s.axis[i]) for i in range(n)]
+    Rs = canonical_rotations(s)
     cf = np.zeros((n, 25))
     for i in range(n):
         Rl = Rs[i]

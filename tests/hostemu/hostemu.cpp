@@ -54,6 +54,10 @@ Sys<S> make_sys(int n, const int* parent, const int* jtype, const double* cf, co
     if (jtype[i] == 1) {
       q += 7;
       v += 6;
+    } else if (jtype[i] == 3) {
+      q += 4;
+      v += 3;
+      u += 3;
     } else {
       q += 1;
       v += 1;
@@ -66,8 +70,18 @@ Sys<S> make_sys(int n, const int* parent, const int* jtype, const double* cf, co
 template <typename S>
 struct Out {
   std::vector<Tape<S>> t;
+  std::vector<V3<S>> u3, qdd3;  // ball joints: tau - pA_a and the joint acceleration
   V6<S> abase;
 };
+
+template <typename S>
+V3<S> vec3_of(const S* x) {
+  return v3<S>(x[0], x[1], x[2]);
+}
+template <typename S>
+Q4<S> quat4_of(const S* x) {
+  return Q4<S>{x[0], x[1], x[2], x[3]};
+}
 
 template <typename S>
 Q4<S> quat_of(const S* q) {
@@ -78,9 +92,19 @@ template <typename S>
 void fd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, Out<S>& o, S* qdd) {
   const int n = s.n;
   o.t.assign(n, Tape<S>{});
+  o.u3.assign(n, zero3<S>());
+  o.qdd3.assign(n, zero3<S>());
   for (int i = 0; i < n; ++i) {
     Tape<S>& t = o.t[i];
     const LinkC<S>& L = s.L[i];
+    if (s.jtype[i] == 3) {
+      const V6<S> vp = s.parent[i] >= 0 ? o.t[s.parent[i]].v : zero6<S>();
+      const V3<S> w = vec3_of(qd + s.vi[i]);
+      ball_p1(L, t, quat4_of(q + s.qi[i]), w, vp);
+      p1_bias(L, t.v, S(0), false, t.c, t.pA, t.IA);
+      t.c = crm(t.v, v6<S>(w, zero3<S>()));
+      continue;
+    }
     if (s.jtype[i] != 1) {
       const S qq = q[s.qi[i]];
       t.sq = L.prism ? qq : (S)std::sin(qq);
@@ -98,6 +122,18 @@ void fd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, Out<S>& o, S
   for (int i = n - 1; i >= 0; --i) {
     Tape<S>& t = o.t[i];
     if (s.jtype[i] == 1) continue;
+    if (s.jtype[i] == 3) {
+      const V3<S> tau3 = vec3_of(tau + s.ui[i]);
+      o.u3[i] = ball_p2_local(t, tau3);
+      if (s.parent[i] >= 0) {
+        SySp<S> IAu;
+        V6<S> pAu;
+        ball_p2_push(s.L[i], t, tau3, IAu, pAu);
+        o.t[s.parent[i]].IA = o.t[s.parent[i]].IA + IAu;
+        o.t[s.parent[i]].pA = o.t[s.parent[i]].pA + pAu;
+      }
+      continue;
+    }
     p2_local(s.L[i], t, tau[s.ui[i]]);
     if (s.parent[i] >= 0) {
       SySp<S> IAu;
@@ -111,7 +147,12 @@ void fd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, Out<S>& o, S
   std::vector<V6<S>> acc(n);
   for (int i = 0; i < n; ++i) {
     Tape<S>& t = o.t[i];
-    if (s.jtype[i] != 1) {
+    if (s.jtype[i] == 3) {
+      acc[i] = ball_p3(s.L[i], t, s.parent[i] >= 0 ? acc[s.parent[i]] : a0, o.qdd3[i]);
+      qdd[s.vi[i]] = o.qdd3[i].x;
+      qdd[s.vi[i] + 1] = o.qdd3[i].y;
+      qdd[s.vi[i] + 2] = o.qdd3[i].z;
+    } else if (s.jtype[i] != 1) {
       acc[i] = p3_accel(s.L[i], t, s.parent[i] >= 0 ? acc[s.parent[i]] : a0);
       qdd[s.vi[i]] = t.qdd;
     } else {
@@ -128,7 +169,13 @@ void fd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, Out<S>& o, S
 template <typename S>
 void integrate_seq(const Sys<S>& s, S* q, S* qd, const S* qdd, const Out<S>& o, S dt) {
   for (int i = 0; i < s.n; ++i) {
-    if (s.jtype[i] != 1) {
+    if (s.jtype[i] == 3) {
+      S* w = qd + s.vi[i];
+      for (int k = 0; k < 3; ++k) w[k] = w[k] + dt * qdd[s.vi[i] + k];
+      const Q4<S> q1 = quat_step(quat4_of(q + s.qi[i]), vec3_of(w), dt);
+      S* qq = q + s.qi[i];
+      qq[0] = q1.x; qq[1] = q1.y; qq[2] = q1.z; qq[3] = q1.w;
+    } else if (s.jtype[i] != 1) {
       integrate_joint(q[s.qi[i]], qd[s.vi[i]], qdd[s.vi[i]], dt);
     } else {
       S* qq = q + s.qi[i];
@@ -154,7 +201,7 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
   Out<S> o;
   std::vector<S> qdd(qdb ? 0 : 0);
   int nv = 0;
-  for (int i = 0; i < n; ++i) nv += (s.jtype[i] == 1) ? 6 : 1;
+  for (int i = 0; i < n; ++i) nv += (s.jtype[i] == 1) ? 6 : (s.jtype[i] == 3) ? 3 : 1;
   qdd.assign(nv, S(0));
   fd_seq(s, q, qd, tau, o, qdd.data());
   std::vector<Bar<S>> b(n);
@@ -164,7 +211,19 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
   V3<S> pb = zero3<S>();
   Q4<S> quatb{};
   int root = -1;
+  std::vector<BallBar<S>> bb(n);
+  for (auto& x : bb) ball_bar_zero(x);
+  std::vector<V3<S>> qddb3(n, zero3<S>()), wb3(n, zero3<S>()), taub3(n, zero3<S>());
+  std::vector<Q4<S>> qtb(n, Q4<S>{});
   for (int i = 0; i < n; ++i) {
+    if (s.jtype[i] == 3) {
+      // w1 = w + dt qdd; quat1 = quat_step(quat, w1)
+      const V3<S> w1 = vec3_of(qd + s.vi[i]) + dt * o.qdd3[i];
+      wb3[i] = vec3_of(qdb + s.vi[i]);
+      qtb[i] = quat_step_adj(quat4_of(q + s.qi[i]), w1, dt, quat4_of(qb + s.qi[i]), wb3[i]);
+      qddb3[i] = dt * wb3[i];
+      continue;
+    }
     if (s.jtype[i] != 1) {
       const S tot = qdb[s.vi[i]] + dt * qb[s.qi[i]];
       qddb[i] = dt * tot;
@@ -188,7 +247,12 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
   std::vector<SySp<S>> IAb(n, zero_sysp<S>());
   const V3<S> g = v3<S>(s.g[0], s.g[1], s.g[2]);
   for (int i = n - 1; i >= 0; --i) {
-    if (s.jtype[i] != 1) {
+    if (s.jtype[i] == 3) {
+      V3<S> sv;
+      const V6<S> apb = ball_r3_path(o.t[i], ab[i], qddb3[i], sv);
+      ball_r3_local(o.t[i], b[i], bb[i], apb, sv);
+      if (s.parent[i] >= 0) ab[s.parent[i]] = ab[s.parent[i]] + xformT(o.t[i].E, s.L[i].rT, apb);
+    } else if (s.jtype[i] != 1) {
       const V6<S> apb = r3_link(s.L[i], o.t[i], b[i], ab[i], qddb[i]);
       if (s.parent[i] >= 0) ab[s.parent[i]] = ab[s.parent[i]] + xformT(o.t[i].E, joint_r(s.L[i], o.t[i]), apb);
     } else {
@@ -199,11 +263,27 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
     if (s.jtype[i] == 1) continue;
     const int p = s.parent[i];
     const bool hp = p >= 0;
+    if (s.jtype[i] == 3) {
+      SySp<S> N;
+      V6<S> pab;
+      const V3<S> tb = ball_r2_path(s.L[i], o.t[i], bb[i], o.u3[i], hp, hp ? IAb[p] : zero_sysp<S>(),
+                                    hp ? pAb[p] : zero6<S>(), N, pab, IAb[i], pAb[i]);
+      if (hp) ball_r2_local(o.t[i], b[i], N, pab);
+      taub[s.ui[i]] = tb.x;
+      taub[s.ui[i] + 1] = tb.y;
+      taub[s.ui[i] + 2] = tb.z;
+      continue;
+    }
     taub[s.ui[i]] = r2_link(s.L[i], o.t[i], b[i], hp, hp ? IAb[p] : zero_sysp<S>(), hp ? pAb[p] : zero6<S>(),
                             IAb[i], pAb[i]);
   }
   for (int i = n - 1; i >= 0; --i) {
-    if (s.jtype[i] != 1) {
+    if (s.jtype[i] == 3) {
+      const V3<S> w = vec3_of(qd + s.vi[i]);
+      const V6<S> vbar = vb[i] + ball_r1_own(s.L[i], o.t[i].v, b[i], pAb[i], w);
+      wb3[i] = wb3[i] + ball_r1_local(o.t[i], b[i], vbar, w);
+      if (s.parent[i] >= 0) vb[s.parent[i]] = vb[s.parent[i]] + xformT(o.t[i].E, s.L[i].rT, vbar);
+    } else if (s.jtype[i] != 1) {
       const V6<S> up = r1_link(s.L[i], o.t[i], b[i], vb[i], pAb[i], qd[s.vi[i]]);
       if (s.parent[i] >= 0) vb[s.parent[i]] = vb[s.parent[i]] + up;
     } else {
@@ -212,11 +292,21 @@ void bwd_seq(const Sys<S>& s, const S* q, const S* qd, const S* tau, S dt, S* qb
   }
   if (pg)
     for (int i = 0; i < n; ++i)
-      if (s.jtype[i] != 1) {
+      if (s.jtype[i] == 3) {
+        ball_frame_bar_add((*pg)[i], quat4_of(q + s.qi[i]), b[i]);
+      } else if (s.jtype[i] != 1) {
         r2_sbar(o.t[i], b[i]);
         frame_bar_add((*pg)[i], s.L[i], o.t[i], b[i]);
       }
   for (int i = 0; i < n; ++i) {
+    if (s.jtype[i] == 3) {
+      const Q4<S> qa = ball_quat_bar(quat4_of(q + s.qi[i]), b[i].G.a);
+      S* x = qb + s.qi[i];
+      x[0] = qtb[i].x + qa.x; x[1] = qtb[i].y + qa.y; x[2] = qtb[i].z + qa.z; x[3] = qtb[i].w + qa.w;
+      S* y = qdb + s.vi[i];
+      y[0] = wb3[i].x; y[1] = wb3[i].y; y[2] = wb3[i].z;
+      continue;
+    }
     if (s.jtype[i] != 1) {
       qb[s.qi[i]] = acc_q[i] + b[i].q;
       qdb[s.vi[i]] = acc_qd[i] + b[i].qd;
@@ -239,9 +329,9 @@ void rollout_grad(int n, const int* parent, const int* jtype, const double* cf, 
   const S dt = (S)dt_;
   int nq = 0, nv = 0, nu = 0;
   for (int i = 0; i < n; ++i) {
-    nq += jtype[i] == 1 ? 7 : 1;
-    nv += jtype[i] == 1 ? 6 : 1;
-    nu += jtype[i] == 1 ? 0 : 1;
+    nq += jtype[i] == 1 ? 7 : jtype[i] == 3 ? 4 : 1;
+    nv += jtype[i] == 1 ? 6 : jtype[i] == 3 ? 3 : 1;
+    nu += jtype[i] == 1 ? 0 : jtype[i] == 3 ? 3 : 1;
   }
   std::vector<S> xs((size_t)(T + 1) * (nq + nv));
   std::copy(q0, q0 + nq, xs.begin());

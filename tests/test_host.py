@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from helpers import emu_fd, emu_rollout_grad, rel
+from helpers import ball_tangent, emu_fd, emu_rollout_grad, rel
 from paper_2109_07719_amd import synth
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -139,11 +139,13 @@ def test_tree_generator_respects_size_and_depth():
 # ---------------------------------------------------------------- host emulation
 
 @pytest.mark.parametrize("which", ["chain", "tree", "quad", "prismatic_tree", "cartpole", "telescoping_quad",
-                                   "prismatic_chain"])
+                                   "prismatic_chain", "ball_tree", "ball_quad"])
 def test_lane_arithmetic_matches_oracle_fp64(which):
     """The per-link functions the kernels call, driven link by link on the
     host in FP64, reproduce the oracle's accelerations and rollout gradients
-    to round-off (independent dense 6x6 arithmetic on the oracle side)."""
+    to round-off (independent dense 6x6 arithmetic on the oracle side).  A
+    ball joint's quaternion gradient is compared along the unit sphere (the
+    oracle's radial part removed)."""
     if which == "chain":
         s, q0, qd0, tau = synth.chain_system(7, 1000, 120)
     elif which == "tree":
@@ -157,6 +159,11 @@ def test_lane_arithmetic_matches_oracle_fp64(which):
         s, q0, qd0, tau = synth.cartpole_system(5, 120)
     elif which == "telescoping_quad":
         s, q0, qd0, tau = synth.telescoping_quadruped_system(3004, 120)
+    elif which == "ball_tree":
+        s, q0, qd0, tau = synth.ball_tree_system(2021, 120, random_frames=True, spherical=0.6)
+        assert (s.jtype == synth.SPHERICAL).sum() >= 10
+    elif which == "ball_quad":
+        s, q0, qd0, tau = synth.ball_quadruped_system(3020, 120)
     else:
         s, q0, qd0, tau = synth.prismatic_chain_system(8, 1001, 120)
     m = O.Model(s)
@@ -164,12 +171,14 @@ def test_lane_arithmetic_matches_oracle_fp64(which):
     rng = np.random.default_rng(1)
     gqT, gqdT = rng.normal(size=s.nq), rng.normal(size=s.nv)
     a = emu_rollout_grad(s, q0, qd0, tau, 1e-3, gqT, gqdT)
-    b = O.rollout_grad(m, q0, qd0, tau, 1e-3, gqT, gqdT)
+    b = list(O.rollout_grad(m, q0, qd0, tau, 1e-3, gqT, gqdT))
+    b[0] = ball_tangent(s, q0, b[0])
     for x, y in zip(a, b):
         assert rel(x, y, 1e-12) < 1e-11
 
 
-@pytest.mark.parametrize("which", ["tree", "prismatic_tree", "telescoping_quad", "chain", "cartpole"])
+@pytest.mark.parametrize("which", ["tree", "prismatic_tree", "telescoping_quad", "chain", "cartpole", "ball_tree",
+                                   "ball_quad"])
 def test_lane_arithmetic_frame_gradients_match_oracle_fp64(which):
     """The kernels' per-link placement and axis adjoints (transform adjoint
     G, motion-subspace adjoint, frame_bar_add), accumulated link by link on
@@ -184,6 +193,10 @@ def test_lane_arithmetic_frame_gradients_match_oracle_fp64(which):
         s, q0, qd0, tau = synth.telescoping_quadruped_system(3011, 80)
     elif which == "chain":
         s, q0, qd0, tau = synth.chain_system(7, 1003, 80)
+    elif which == "ball_tree":
+        s, q0, qd0, tau = synth.ball_tree_system(2022, 80, random_frames=True, spherical=0.5)
+    elif which == "ball_quad":
+        s, q0, qd0, tau = synth.ball_quadruped_system(3021, 80)
     else:
         s, q0, qd0, tau = synth.cartpole_system(7, 80)
     m = O.Model(s)
