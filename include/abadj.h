@@ -29,14 +29,26 @@
  *       E = E_T, r = r_T + q E_T^T a.
  *     Both are X = X_J(q) X_T with X_J(q) = exp(-q crm(S))   (Sec. 3; the
  *     joint models of Featherstone's spatial algebra, which Sec. 3 follows).
+ *     Spherical (ball) joint (S = [1; 0], the link frame's three angular
+ *     unit vectors): E = R(quat)^T E_T, r = r_T, with
+ *     R(quat) = (w^2 - u.u) I + 2 u u^T + 2 w [u]x for quat = (u, w)
+ *     (the quaternion operators of App. G).  It has no axis (its axis entry
+ *     is not read) and no joint limits.
  *   - Revolute or prismatic joint: one q, one qdot, one control (torque or
- *     force).  Free root:
+ *     force).  Spherical joint: q = quat[4] stored x, y, z, w, qdot = the
+ *     joint's angular velocity in link coordinates (3), three torques (link
+ *     coordinates).  Free root:
  *     q = (p_world[3], quat[4] stored x, y, z, w), velocity = body-frame
  *     spatial velocity [w; v] (6 entries), unactuated.
  *   - Gravity enters as a fictitious base acceleration; for a free root the
  *     base acceleration reported is the true body-frame acceleration.
  *   - Semi-implicit Euler: qd1 = qd + dt qdd, q1 = q + dt qd1; free root:
- *     p1 = p + dt R(quat) v1_lin, quat1 = normalize(quat + dt/2 quat x (w1, 0)).
+ *     p1 = p + dt R(quat) v1_lin, quat1 = normalize(quat + dt/2 quat x (w1, 0));
+ *     spherical joint: w1 = w + dt wdot, quat1 as for the free root.
+ *   - Gradients with respect to a spherical joint's quaternion are the
+ *     gradient along the unit sphere (orthogonal to the quaternion): the
+ *     radial part depends only on how the step is continued off the sphere
+ *     and is removed by the next step's normalisation anyway.
  *   - Batched vectors are system-concatenated in the order of the
  *     topology: q [sum nq], qd [sum nv], control rows [sum nu]; a control
  *     sequence is [T][sum nu], a trajectory [T][sum nq + sum nv] whose row t
@@ -81,6 +93,7 @@ extern "C" {
 #define SIM_JOINT_REVOLUTE 0
 #define SIM_JOINT_FREE 1
 #define SIM_JOINT_PRISMATIC 2
+#define SIM_JOINT_SPHERICAL 3
 
 /* Largest number of links in one system (one wavefront of 64 lanes). */
 #define SIM_MAX_LINKS 64
@@ -139,6 +152,8 @@ typedef struct {
   int32_t adjoint_dtype;  /* arithmetic of sim_backward's recompute and
                               reverse passes: SIM_F64, or SIM_F32 (FP32
                               handles only; see sim_set_adjoint_dtype)    */
+  int32_t has_ball;       /* 1 if any joint is spherical (the kernels then
+                              use their general variant)                  */
 } sim_info_t;
 
 /* Build a handle: validates the topology and parameters, orders every

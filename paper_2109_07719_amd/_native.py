@@ -22,6 +22,7 @@ SIM_F64 = 1
 SIM_JOINT_REVOLUTE = 0
 SIM_JOINT_FREE = 1
 SIM_JOINT_PRISMATIC = 2
+SIM_JOINT_SPHERICAL = 3
 SIM_MAX_LINKS = 64
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_set_adjoint_dtype", "sim_status", "sim_get_tiling",
@@ -48,7 +49,8 @@ class SimParams(ctypes.Structure):
 class SimInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_sys", "n_links", "nq", "nv", "nu", "n_waves",
                                                "n_slots", "max_depth", "has_free", "dtype",
-                                               "frames_identity", "chain", "has_prism", "adjoint_dtype")]
+                                               "frames_identity", "chain", "has_prism", "adjoint_dtype",
+                                               "has_ball")]
 
 
 class SimTiling(ctypes.Structure):

@@ -103,8 +103,10 @@ struct Lane {
   int lane, slot;
   int par, depth, cfirst, ccount, jtype, qidx, vidx, uidx, fidx, link;
   __device__ bool active() const { return jtype >= 0; }
-  // revolute or prismatic (jtype 0 or 2; -1 marks an idle lane, 1 a free root)
+  // revolute or prismatic (jtype 0 or 2; -1 marks an idle lane, 1 a free
+  // root, 3 a ball joint)
   __device__ bool onedof() const { return (jtype & 1) == 0; }
+  __device__ bool ball() const { return jtype == 3; }
 };
 
 // wb: the wave batch (64 lane slots) this wavefront works on
@@ -146,7 +148,7 @@ __device__ __forceinline__ LinkC<S> load_linkc(const Packed<S>& P, const Lane& l
     for (int k = 0; k < 9; ++k) L.ET.m[k] = cf[(CF_ET + k) * ns + slot];
   }
   L.rT = v3<S>(cf[(CF_RT + 0) * ns + slot], cf[(CF_RT + 1) * ns + slot], cf[(CF_RT + 2) * ns + slot]);
-  if constexpr (FR == kFrGeneralJoints) {
+  if constexpr (FR >= kFrGeneralJoints) {
     L.prism = l.jtype == 2;
     const S ang = L.prism ? S(0) : S(1);
     L.sm = v6<S>(v3<S>(S(0), S(0), ang), v3<S>(S(0), S(0), S(1) - ang));
@@ -226,7 +228,8 @@ __device__ __forceinline__ SySp<S> get21(const S* xb, int f0, int lane) {
 }
 
 // per-lane state: 1-dof lanes use q[0], qd[0]; a free root uses
-// q = (p, quat) and qd = body velocity [w; v]
+// q = (p, quat) and qd = body velocity [w; v]; a ball joint (only in the
+// general variant, which has FREE set) q[0..3] = quat, qd[0..2] = w
 template <typename S, bool FREE>
 struct State {
   S q[FREE ? 7 : 1];
@@ -248,6 +251,25 @@ __device__ __forceinline__ Q4<S> st_quat(const State<S, FREE>& s) {
   return r;
 }
 template <typename S, bool FREE>
+__device__ __forceinline__ Q4<S> st_ball_quat(const State<S, FREE>& s) {
+  Q4<S> r;
+  if constexpr (FREE) {
+    r.x = s.q[0];
+    r.y = s.q[1];
+    r.z = s.q[2];
+    r.w = s.q[3];
+  } else {
+    r.x = r.y = r.z = S(0);
+    r.w = S(1);
+  }
+  return r;
+}
+template <typename S, bool FREE>
+__device__ __forceinline__ V3<S> st_ball_w(const State<S, FREE>& s) {
+  if constexpr (FREE) return v3<S>(s.qd[0], s.qd[1], s.qd[2]);
+  return zero3<S>();
+}
+template <typename S, bool FREE>
 __device__ __forceinline__ V6<S> st_vel6(const State<S, FREE>& s) {
   if constexpr (FREE) return v6<S>(v3<S>(s.qd[0], s.qd[1], s.qd[2]), v3<S>(s.qd[3], s.qd[4], s.qd[5]));
   return zero6<S>();
@@ -259,11 +281,11 @@ __device__ __forceinline__ V6<S> st_vel6(const State<S, FREE>& s) {
 template <typename S, bool FREE>
 __device__ __forceinline__ void load_state(State<S, FREE>& s, const Lane& l, const S* q, const S* qd) {
   if constexpr (FREE) {
-    const bool rev = l.onedof(), fr = l.jtype == 1;
+    const bool rev = l.onedof(), fr = l.jtype == 1, bl = l.ball();
 #pragma unroll
-    for (int k = 0; k < 7; ++k) s.q[k] = ((k == 0 && rev) || fr) ? q[l.qidx + k] : s.q[k];
+    for (int k = 0; k < 7; ++k) s.q[k] = ((k == 0 && rev) || fr || (k < 4 && bl)) ? q[l.qidx + k] : s.q[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) s.qd[k] = ((k == 0 && rev) || fr) ? qd[l.vidx + k] : s.qd[k];
+    for (int k = 0; k < 6; ++k) s.qd[k] = ((k == 0 && rev) || fr || (k < 3 && bl)) ? qd[l.vidx + k] : s.qd[k];
   } else {
     if (l.onedof()) {
       s.q[0] = q[l.qidx];
@@ -282,6 +304,11 @@ __device__ __forceinline__ void store_state(const State<S, FREE>& s, const Lane&
       for (int k = 0; k < 7; ++k) q[l.qidx + k] = s.q[k];
 #pragma unroll
       for (int k = 0; k < 6; ++k) qd[l.vidx + k] = s.qd[k];
+    } else if (l.ball()) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) q[l.qidx + k] = s.q[k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) qd[l.vidx + k] = s.qd[k];
     }
   }
 }
@@ -314,6 +341,11 @@ __device__ __forceinline__ int nonfinite_state(const State<S, FREE>& s, const La
       for (int k = 0; k < 7; ++k) n += nonfinite(s.q[k]);
 #pragma unroll
       for (int k = 0; k < 6; ++k) n += nonfinite(s.qd[k]);
+    } else if (l.ball()) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) n += nonfinite(s.q[k]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) n += nonfinite(s.qd[k]);
     }
   }
   return n;
@@ -322,8 +354,9 @@ __device__ __forceinline__ void report_nonfinite(int* status, int n) {
   if (n > 0) atomicAdd(status, n);
 }
 
-// stored state records (see state_record): [2][nslots] then [11][nfree].
-// The second row holds p.y of a free root or qd of a 1-dof link; it is
+// stored state records (see state_record): [2][nslots] then [11][nfree]
+// (nfree: free roots and ball joints, which keep q[0..6], qd[0..5] alike).
+// The second row holds q[1] of such a lane or qd of a 1-dof link; it is
 // chosen by value selects, not by selecting which member to address, so
 // that the state stays in registers.
 template <typename S, bool FREE>
@@ -398,7 +431,8 @@ __device__ __forceinline__ int store_param_bar(const ParamBar<S>& g, const Packe
 // xi = [Rl^T xi'_a; Rl^T xi'_l], phi_bar = xi_a and r_T_bar = E_T^T xi_l =
 // Rp^T E_T'^T xi'_l.  The axis rotation adjoint is w = Rl^T (xi'_a + w'),
 // and the gradient along the unit sphere is w x a = Rl^T ((xi'_a + w') x e_z).
-// A free root has none: zeros.  Returns the number of non-finite values.
+// A ball joint has placement gradients only; a free root has none: zeros.
+// Returns the number of non-finite values.
 template <typename Sp, typename S>
 __device__ __forceinline__ int store_frame_bar(const ParamBar<S>& g, const Packed<Sp>& P, const Lane& l,
                                                const LinkC<S>& L, Sp* out) {
@@ -406,7 +440,7 @@ __device__ __forceinline__ int store_frame_bar(const ParamBar<S>& g, const Packe
   S v[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) v[k] = S(0);
-  if (l.onedof()) {
+  if (l.onedof() || l.ball()) {
     M3<S> Rl, Rp;
 #pragma unroll
     for (int k = 0; k < 9; ++k) Rl.m[k] = S(P.cf[(CF_RL + k) * ns + l.slot]);
@@ -415,7 +449,8 @@ __device__ __forceinline__ int store_frame_bar(const ParamBar<S>& g, const Packe
     for (int k = 0; k < 9; ++k) Rp.m[k] = (l.par >= 0) ? S(P.cf[(CF_RL + k) * ns + ps]) : ((k % 4 == 0) ? S(1) : S(0));
     const V3<S> phi = mulT(Rl, g.xi.a);
     const V3<S> rb = mulT(Rp, mulT(L.ET, g.xi.l));
-    const V3<S> w = g.xi.a + g.w;
+    // a ball joint has no axis (and Rl = 1)
+    const V3<S> w = l.ball() ? zero3<S>() : g.xi.a + g.w;
     const V3<S> ab = mulT(Rl, v3<S>(w.y, -w.x, S(0)));
     v[0] = phi.x; v[1] = phi.y; v[2] = phi.z;
     v[3] = rb.x; v[4] = rb.y; v[5] = rb.z;
@@ -457,17 +492,33 @@ __device__ __forceinline__ int opaque_slot(const Lane& l) {
 // the general-joints variant carries it (handles with limits take that
 // variant); the others compile it away.
 template <int FR, typename S, typename T, bool FREE>
-__device__ __forceinline__ T limit_tau(const Packed<S>& P, const Lane& l, const State<T, FREE>& st, T tau) {
-  if constexpr (FR != kFrGeneralJoints) return tau;
+__device__ __forceinline__ V3<T> limit_tau(const Packed<S>& P, const Lane& l, const State<T, FREE>& st, V3<T> tau) {
+  if constexpr (FR < kFrGeneralJoints) return tau;
   if (!P.has_limits || !l.onedof()) return tau;
   const int ns = P.nslots;
   const int slot = opaque_slot(l);
   const S lo = P.cf[(CF_LIM + 0) * ns + slot], hi = P.cf[(CF_LIM + 1) * ns + slot];
   const S k = P.cf[(CF_LIM + 2) * ns + slot], d = P.cf[(CF_LIM + 3) * ns + slot];
   const T q = st.q[0], qd = st.qd[0];
-  if (val_(q) > hi) return tau - T(k) * (q - T(hi)) - T(d) * qd;
-  if (val_(q) < lo) return tau - T(k) * (q - T(lo)) - T(d) * qd;
+  if (val_(q) > hi) tau.x = tau.x - T(k) * (q - T(hi)) - T(d) * qd;
+  else if (val_(q) < lo) tau.x = tau.x - T(k) * (q - T(lo)) - T(d) * qd;
   return tau;
+}
+// A lane's controls at one step (row: the step's [nu] controls): a 1-dof
+// joint's torque in x, a ball joint's three torques (BALL: the general
+// variant, the only one that takes ball joints).
+template <bool BALL, typename S>
+__device__ __forceinline__ V3<S> load_ctl(const S* row, const Lane& l) {
+  V3<S> u = zero3<S>();
+  if (l.onedof()) u.x = row[l.uidx];
+  if constexpr (BALL) {
+    if (l.ball()) u = v3<S>(row[l.uidx], row[l.uidx + 1], row[l.uidx + 2]);
+  }
+  return u;
+}
+template <typename R, typename S>
+__device__ __forceinline__ V3<R> cvt3(const V3<S>& v) {
+  return v3<R>(R(v.x), R(v.y), R(v.z));
 }
 // its partial derivatives with respect to q and qd (zero inside the range)
 // (T: the adjoint's scalar type; the switch compares the same values as the
@@ -476,7 +527,7 @@ template <int FR, typename S, typename T, bool FREE>
 __device__ __forceinline__ void limit_slopes(const Packed<S>& P, const Lane& l, const State<T, FREE>& st, T& dq,
                                              T& dqd) {
   dq = dqd = T(0);
-  if constexpr (FR != kFrGeneralJoints) return;
+  if constexpr (FR < kFrGeneralJoints) return;
   if (!P.has_limits || !l.onedof()) return;
   const int ns = P.nslots;
   const T q = st.q[0];
@@ -491,7 +542,8 @@ __device__ __forceinline__ void limit_slopes(const Packed<S>& P, const Lane& l, 
 template <typename S>
 struct Step {
   Tape<S> t;
-  V6<S> abase;  // free root: true body-frame acceleration
+  V6<S> abase;  // free root: true body-frame acceleration; ball joint:
+                // [joint acceleration; u = tau - pA_a]
 };
 template <typename R, typename S>
 __device__ __forceinline__ Step<R> cvt_step(const Step<S>& o) {
@@ -593,26 +645,36 @@ __device__ __forceinline__ void aba_wave_chain(const V3<S>& g, const Lane& l, co
   }
 }
 
-// One ABA evaluation for the whole wave (all three passes).
-template <typename S, bool FREE, bool CHAIN>
+// One ABA evaluation for the whole wave (all three passes).  tau: the
+// lane's controls (load_ctl).  BALL: the variant that also takes ball joints.
+template <typename S, bool FREE, bool CHAIN, bool BALL = false>
 __device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const LinkC<S>& L,
-                                         const State<S, FREE>& st, S tau, int maxd, S* xb, Step<S>& o) {
+                                         const State<S, FREE>& st, const V3<S>& tau, int maxd, S* xb,
+                                         Step<S>& o) {
   if constexpr (CHAIN) {
     static_assert(!FREE, "the chain variant has fixed bases only");
-    aba_wave_chain<S>(g, l, L, st, tau, maxd, o);
+    aba_wave_chain<S>(g, l, L, st, tau.x, maxd, o);
     return;
   }
+  static_assert(!BALL || FREE, "ball joints run in the general (FREE) variant");
   Tape<S>& t = o.t;
   const bool act = l.active();
   const bool rev = l.onedof();
+  const bool ball = BALL && l.ball();
   // pass 1: joint transforms (parallel over links)
   if (rev) joint_transform(L, st.q[0], t);
+  if constexpr (BALL) {
+    if (ball) t.E = ball_E(st_ball_quat(st), L.ET);
+  }
   // pass 1: velocities, root -> leaves
   for (int d = 0; d <= maxd; ++d) {
     if (act && l.depth == d) {
       if (rev) {
         const V6<S> vp = (l.par >= 0) ? get6(xb, 0, l.par) : zero6<S>();
         t.v = p1_velocity(L, t, st.qd[0], vp);
+      } else if (ball) {
+        const V6<S> vp = (l.par >= 0) ? get6(xb, 0, l.par) : zero6<S>();
+        t.v = xform(t.E, L.rT, vp) + v6<S>(st_ball_w(st), zero3<S>());
       } else {
         // free root: the ABA runs in the inertial frame that moves with the
         // root's current linear velocity (a Galilean shift, exact: joint
@@ -628,6 +690,9 @@ __device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const Li
   }
   // pass 1: bias terms (parallel over links)
   if (act) p1_bias(L, t.v, st.qd[0], rev, t.c, t.pA, t.IA);
+  if constexpr (BALL) {
+    if (ball) t.c = crm(t.v, v6<S>(st_ball_w(st), zero3<S>()));
+  }
   // pass 2: articulated inertias, leaves -> root
   for (int d = maxd; d >= 0; --d) {
     if (act && l.depth == d) {
@@ -636,11 +701,20 @@ __device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const Li
         t.pA = t.pA + get6(xb, 21, l.cfirst + k);
       }
       if (rev) {
-        p2_local(L, t, tau);
+        p2_local(L, t, tau.x);
         if (l.par >= 0) {
           SySp<S> IAu;
           V6<S> pAu;
           p2_push(L, t, IAu, pAu);
+          put21(xb, 0, l.lane, IAu);
+          put6(xb, 21, l.lane, pAu);
+        }
+      } else if (ball) {
+        o.abase.l = ball_p2_local(t, tau);
+        if (l.par >= 0) {
+          SySp<S> IAu;
+          V6<S> pAu;
+          ball_p2_push(L, t, tau, IAu, pAu);
           put21(xb, 0, l.lane, IAu);
           put6(xb, 21, l.lane, pAu);
         }
@@ -655,6 +729,9 @@ __device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const Li
       if (rev) {
         const V6<S> ap = (l.par >= 0) ? get6(xb, 0, l.par) : a0;
         put6(xb, 0, l.lane, p3_accel(L, t, ap));
+      } else if (ball) {
+        const V6<S> ap = (l.par >= 0) ? get6(xb, 0, l.par) : a0;
+        put6(xb, 0, l.lane, ball_p3(L, t, ap, o.abase.a));
       } else if constexpr (FREE) {
         root_accel(t.IA, t.pA, st_quat(st), g, t.ap, o.abase);
         const V6<S> v = st_vel6(st);
@@ -666,10 +743,18 @@ __device__ __forceinline__ void aba_wave(const V3<S>& g, const Lane& l, const Li
   }
 }
 
-template <typename S, bool FREE>
+template <typename S, bool FREE, bool BALL = false>
 __device__ __forceinline__ void integrate_lane(State<S, FREE>& st, const Lane& l, const Step<S>& o, S dt) {
   if (l.onedof()) {
     integrate_joint(st.q[0], st.qd[0], o.t.qdd, dt);
+  } else if (BALL && l.ball()) {
+    if constexpr (FREE) {
+      // w1 = w + dt wdot; quat1 = normalize(quat + dt/2 quat (x) (w1, 0))
+      const V3<S> w1 = st_ball_w(st) + dt * o.abase.a;
+      const Q4<S> q1 = quat_step(st_ball_quat(st), w1, dt);
+      st.q[0] = q1.x; st.q[1] = q1.y; st.q[2] = q1.z; st.q[3] = q1.w;
+      st.qd[0] = w1.x; st.qd[1] = w1.y; st.qd[2] = w1.z;
+    }
   } else if constexpr (FREE) {
     if (l.jtype == 1) {
       V3<S> p = v3<S>(st.q[0], st.q[1], st.q[2]);
@@ -694,19 +779,27 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_aba(AbaArgs<S> A)
   const int maxd = A.P.wmaxd[wb];
   // every lane slot holds valid constants, so load them unconditionally
   // (keeps the compile-time axis and frame constants visible to folding)
+  constexpr bool BALL = FREE && FR == kFrBall;
   const LinkC<S> L = load_linkc<S, FR>(A.P, l);
   State<S, FREE> st = {};
-  S tau = S(0);
+  V3<S> tau = zero3<S>();
   if (l.active()) {
     load_state(st, l, A.q, A.qd);
-    if (l.onedof()) tau = A.tau[l.uidx];
+    tau = load_ctl<BALL>(A.tau, l);
   }
   Step<S> o;
-  aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
+  aba_wave<S, FREE, CHAIN, BALL>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
   int nonfin = 0;
   if (l.onedof()) {
     A.qdd[l.vidx] = o.t.qdd;
     nonfin = nonfinite(o.t.qdd);
+  } else if (BALL && l.ball()) {
+    const S a[3] = {o.abase.a.x, o.abase.a.y, o.abase.a.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      A.qdd[l.vidx + k] = a[k];
+      nonfin += nonfinite(a[k]);
+    }
   } else if constexpr (FREE) {
     if (l.jtype == 1) {
       const S a[6] = {o.abase.a.x, o.abase.a.y, o.abase.a.z, o.abase.l.x, o.abase.l.y, o.abase.l.z};
@@ -731,11 +824,11 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
   const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
+  constexpr bool BALL = FREE && FR == kFrBall;
   const LinkC<S> L = load_linkc<S, FR>(A.P, l);
   State<S, FREE> st = {};
   if (l.active()) load_state(st, l, A.q0, A.qd0);
-  const bool has_tau = l.onedof();
-  S tau_next = (has_tau && A.T > 0) ? A.tau[l.uidx] : S(0);
+  V3<S> tau_next = (l.active() && A.T > 0) ? load_ctl<BALL>(A.tau, l) : zero3<S>();
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
   int nonfin = 0;  // non-finite outputs
@@ -743,10 +836,10 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
     if constexpr (MODE == 1) {
       if (l.active() && (t % A.K) == 0) put_slot(st, A.ck + (size_t)(t / A.K) * RW, ns, nf, l.slot, l.fidx);
     }
-    const S tau = tau_next;
-    if (has_tau && t + 1 < A.T) tau_next = A.tau[(size_t)(t + 1) * nu + l.uidx];
+    const V3<S> tau = tau_next;
+    if (l.active() && t + 1 < A.T) tau_next = load_ctl<BALL>(A.tau + (size_t)(t + 1) * nu, l);
     Step<S> o;
-    aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
+    aba_wave<S, FREE, CHAIN, BALL>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
     if constexpr (MODE == 2) {
       if (l.active()) {
         S* row = A.ck + (size_t)t * (RW + (size_t)kTapeFields * ns);
@@ -754,7 +847,7 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
         put_tape(o, row + RW, ns, l.slot);
       }
     }
-    if (l.active()) integrate_lane(st, l, o, A.dt);
+    if (l.active()) integrate_lane<S, FREE, BALL>(st, l, o, A.dt);
     if (A.traj != nullptr) {
       if (l.active()) {
         S* row = A.traj + (size_t)t * (A.P.nq + A.P.nv);
@@ -778,13 +871,39 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward(FwdArgs<S
 // exit; tau_bar^t is written to gtau.
 template <typename S, typename R, bool FREE, int FR, bool CHAIN, bool PARAMS>
 __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, const LinkC<R>& L, int maxd,
-                                            R* xb, const State<R, FREE>& st, const Step<R>& o, int t,
+                                            R* xb, const State<R, FREE>& st, Step<R> o, int t,
                                             State<R, FREE>& xb1, int& nonfin, ParamBar<R>& pg) {
+  constexpr bool BALL = FREE && FR == kFrBall;
   const bool act = l.active();
   const bool rev = l.onedof();
+  const bool ball = BALL && l.ball();
   const V3<R> g = v3<R>(R(A.P.g[0]), R(A.P.g[1]), R(A.P.g[2]));
   const R dt = R(A.dt);
-  const Tape<R>& tp = o.t;
+  Tape<R>& tp = o.t;
+  // ball joint: what the stored tapes leave out (E from the quaternion,
+  // c = v x [w; 0], the joint-space blocks from IA and u)
+  Q4<R> bq = {R(0), R(0), R(0), R(1)};
+  V3<R> bw = zero3<R>();
+  Q4<R> bqb = {R(0), R(0), R(0), R(0)};
+  V3<R> bwb = zero3<R>(), bqddb = zero3<R>(), bs = zero3<R>();
+  BallBar<R> bb;
+  ball_bar_zero(bb);
+  if constexpr (BALL) {
+    if (ball) {
+      bq = st_ball_quat(st);
+      bw = st_ball_w(st);
+      tp.E = ball_E(bq, L.ET);
+      tp.c = crm(tp.v, v6<R>(bw, zero3<R>()));
+      tp.Ai = sy3_inv(tp.IA.A);
+      tp.y = mul(tp.Ai, o.abase.l);
+      tp.W = mul(sy_to_m3(tp.Ai), tp.IA.B);
+      // integrator: w1 = w + dt wdot, quat1 = quat_step(quat, w1)
+      const Q4<R> q1b = st_ball_quat(xb1);
+      bwb = st_ball_w(xb1);
+      bqb = quat_step_adj(bq, bw + dt * o.abase.a, dt, q1b, bwb);
+      bqddb = dt * bwb;
+    }
+  }
 
   // adjoint of the integrator
   R acc_q = R(0), acc_qd = R(0), qddb = R(0);
@@ -836,6 +955,9 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
         if (rev) {
           apb = r3_path(L, tp, ab, qddb, g3);
           if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, joint_r(L, tp), apb));
+        } else if (ball) {
+          apb = ball_r3_path(tp, ab, bqddb, bs);
+          if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, L.rT, apb));
         } else if constexpr (FREE) {
           r3_root(tp.IA, tp.ap, st_quat(st), g, ab, qddb6, quatb, IAb, pAb);
         }
@@ -844,8 +966,12 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
     }
   }
   if (rev) r3_local(L, tp, b, apb, g3);
+  if constexpr (BALL) {
+    if (ball) ball_r3_local(tp, b, bb, apb, bs);
+  }
   // reverse of pass 2, root -> leaves
   R taub = R(0);
+  V3<R> btaub = zero3<R>();
   SySp<R> N = zero_sysp<R>();
   V6<R> pab = zero6<R>();
   if constexpr (CHAIN) {
@@ -857,11 +983,12 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
   } else {
     for (int d = 0; d <= maxd; ++d) {
       if (act && l.depth == d) {
-        if (rev) {
+        if (rev || ball) {
           const bool hp = l.par >= 0;
           const SySp<R> IAbp = hp ? get21(xb, 0, l.par) : zero_sysp<R>();
           const V6<R> pAbp = hp ? get6(xb, 21, l.par) : zero6<R>();
-          taub = r2_path(L, tp, b, hp, IAbp, pAbp, N, pab, IAb, pAb);
+          if (rev) taub = r2_path(L, tp, b, hp, IAbp, pAbp, N, pab, IAb, pAb);
+          else btaub = ball_r2_path(L, tp, bb, o.abase.l, hp, IAbp, pAbp, N, pab, IAb, pAb);
         }
         put21(xb, 0, l.lane, IAb);
         put6(xb, 21, l.lane, pAb);
@@ -870,12 +997,18 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
     }
   }
   if (rev && l.par >= 0) r2_local(L, tp, b, N, pab);
+  if constexpr (BALL) {
+    if (ball && l.par >= 0) ball_r2_local(tp, b, N, pab);
+  }
   // inertial-parameter adjoint of this step: IAb and pAb are final here
   if constexpr (PARAMS) {
     if (A.gparam != nullptr && act) param_bar_add(pg, IAb, tp.v, pAb);
   }
   // reverse of pass 1, leaves -> root
-  const V6<R> own = act ? r1_own(L, tp.v, b, pAb, st.qd[0], rev) : zero6<R>();
+  V6<R> own = act ? r1_own(L, tp.v, b, pAb, st.qd[0], rev) : zero6<R>();
+  if constexpr (BALL) {
+    if (ball) own = ball_r1_own(L, tp.v, b, pAb, bw);
+  }
   V6<R> vbar = zero6<R>();
   if constexpr (CHAIN) {
     V6<R> up = zero6<R>();
@@ -892,7 +1025,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
         V6<R> vb = zero6<R>();
         for (int k = 0; k < l.ccount; ++k) vb = vb + get6(xb, 0, l.cfirst + k);
         vbar = vb + own;
-        if (rev) {
+        if (rev || ball) {
           if (l.par >= 0) put6(xb, 0, l.lane, xformT(tp.E, joint_r(L, tp), vbar));
         } else if constexpr (FREE) {
           // the ABA saw the root velocity [w; 0]
@@ -903,11 +1036,18 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
     }
   }
   if (rev) r1_local(L, tp, b, vbar, st.qd[0]);
-  // placement and axis adjoint of this step (every 1-dof link)
+  if constexpr (BALL) {
+    if (ball) bwb = bwb + ball_r1_local(tp, b, vbar, bw);
+  }
+  // placement and axis adjoint of this step (every 1-dof link; a ball
+  // link's placement)
   if constexpr (PARAMS) {
     if (A.gframe != nullptr && rev) {
       r2_sbar(tp, b);
       frame_bar_add(pg, L, tp, b);
+    }
+    if constexpr (BALL) {
+      if (A.gframe != nullptr && ball) ball_frame_bar_add(pg, bq, b);
     }
   }
   // adjoint of the step's initial state; tau_bar (the joint-limit torque
@@ -920,6 +1060,18 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
     const S taub_out = S(taub);
     A.gtau[(size_t)t * A.P.nu + l.uidx] = taub_out;
     nonfin += nonfinite(taub_out);
+  } else if (ball) {
+    if constexpr (BALL) {
+      const Q4<R> qa = ball_quat_bar(bq, b.G.a);
+      xb1.q[0] = bqb.x + qa.x; xb1.q[1] = bqb.y + qa.y; xb1.q[2] = bqb.z + qa.z; xb1.q[3] = bqb.w + qa.w;
+      xb1.qd[0] = bwb.x; xb1.qd[1] = bwb.y; xb1.qd[2] = bwb.z;
+      const S tb[3] = {S(btaub.x), S(btaub.y), S(btaub.z)};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        A.gtau[(size_t)t * A.P.nu + l.uidx + k] = tb[k];
+        nonfin += nonfinite(tb[k]);
+      }
+    }
   } else if constexpr (FREE) {
     if (l.jtype == 1) {
       xb1.q[0] = pb.x; xb1.q[1] = pb.y; xb1.q[2] = pb.z;
@@ -929,7 +1081,7 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
     }
   }
   if (act && A.gtraj != nullptr && t >= 1) {
-    State<S, FREE> gt;
+    State<S, FREE> gt = {};
     const S* row = A.gtraj + (size_t)(t - 1) * (A.P.nq + A.P.nv);
     load_state(gt, l, row, row + A.P.nq);
 #pragma unroll
@@ -946,12 +1098,13 @@ __device__ __forceinline__ void bwd_reverse(const BwdArgs<S>& A, const Lane& l, 
 // round-off; only the outputs are rounded to FP32.  xb is sized for R.
 template <typename S, typename R, bool FREE, int FR, bool CHAIN, bool PARAMS>
 __device__ __forceinline__ void bwd_step(const BwdArgs<S>& A, const Lane& l, const LinkC<R>& LR, int maxd,
-                                         S* xb, const State<S, FREE>& st, S tau, int t, State<R, FREE>& xb1,
-                                         int& nonfin, ParamBar<R>& pg) {
+                                         S* xb, const State<S, FREE>& st, const V3<S>& tau, int t,
+                                         State<R, FREE>& xb1, int& nonfin, ParamBar<R>& pg) {
   R* const xr = reinterpret_cast<R*>(xb);
   const State<R, FREE> sr = cvt_state<R>(st);
   Step<R> o;
-  aba_wave<R, FREE, CHAIN>(widen<R>(gravity(A.P)), l, LR, sr, limit_tau<FR>(A.P, l, sr, R(tau)), maxd, xr, o);
+  aba_wave<R, FREE, CHAIN, FREE && FR == kFrBall>(widen<R>(gravity(A.P)), l, LR, sr,
+                                                          limit_tau<FR>(A.P, l, sr, cvt3<R>(tau)), maxd, xr, o);
   bwd_reverse<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xr, sr, o, t, xb1, nonfin, pg);
 }
 
@@ -962,7 +1115,7 @@ __device__ __forceinline__ State<R, FREE> seed_state(const BwdArgs<S>& A, const 
   if (l.active()) {
     load_state(x, l, A.gqT, A.gqdT);
     if (A.gtraj != nullptr && A.T > 0) {
-      State<S, FREE> gt;
+      State<S, FREE> gt = {};
       const S* row = A.gtraj + (size_t)(A.T - 1) * (A.P.nq + A.P.nv);
       load_state(gt, l, row, row + A.P.nq);
 #pragma unroll
@@ -1010,8 +1163,8 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(R) > 4) ? 1 : 2))) void k_bac
   const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
+  constexpr bool BALL = FREE && FR == kFrBall;
   const bool act = l.active();
-  const bool rev = l.onedof();
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
   const LinkC<S> L = load_linkc<S, FR>(A.P, l);
@@ -1028,7 +1181,7 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(R) > 4) ? 1 : 2))) void k_bac
       if (act) {
         const S* row = A.ck + (size_t)t * (RW + (size_t)kTapeFields * ns);
         get_slot(st, row, ns, nf, l.slot, l.fidx);
-        get_tape(o, row + RW, ns, l.slot, L, st.qd[0], rev);
+        get_tape(o, row + RW, ns, l.slot, L, st.qd[0], l.onedof());
       }
       // the stored intermediates are the forward's (type S), widened
       bwd_reverse<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, reinterpret_cast<R*>(xb), cvt_state<R>(st),
@@ -1036,17 +1189,17 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(R) > 4) ? 1 : 2))) void k_bac
     }
   } else if (A.K == 1) {
     State<S, FREE> nxt = {};
-    S tau_nxt = S(0);
-    if (A.T > 0) {
-      if (act) get_slot(nxt, A.ck + (size_t)(A.T - 1) * RW, ns, nf, l.slot, l.fidx);
-      if (rev) tau_nxt = A.tau[(size_t)(A.T - 1) * nu + l.uidx];
+    V3<S> tau_nxt = zero3<S>();
+    if (A.T > 0 && act) {
+      get_slot(nxt, A.ck + (size_t)(A.T - 1) * RW, ns, nf, l.slot, l.fidx);
+      tau_nxt = load_ctl<BALL>(A.tau + (size_t)(A.T - 1) * nu, l);
     }
     for (int t = A.T - 1; t >= 0; --t) {
       const State<S, FREE> st = nxt;
-      const S tau = tau_nxt;
-      if (t > 0) {
-        if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
-        if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
+      const V3<S> tau = tau_nxt;
+      if (t > 0 && act) {
+        get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
+        tau_nxt = load_ctl<BALL>(A.tau + (size_t)(t - 1) * nu, l);
       }
       bwd_step<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xb, st, tau, t, xb1, nonfin, pg);
     }
@@ -1063,15 +1216,15 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(R) > 4) ? 1 : 2))) void k_bac
         tc = arg;
       } else if (what == SCH_ADVANCE) {
         for (int j = 0; j < arg; ++j, ++tc) {
-          const S tau = rev ? A.tau[(size_t)tc * nu + l.uidx] : S(0);
+          const V3<S> tau = act ? load_ctl<BALL>(A.tau + (size_t)tc * nu, l) : zero3<S>();
           Step<S> o;
-          aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, cur, limit_tau<FR>(A.P, l, cur, tau), maxd, xb, o);
-          if (act) integrate_lane(cur, l, o, A.dt);
+          aba_wave<S, FREE, CHAIN, BALL>(gravity(A.P), l, L, cur, limit_tau<FR>(A.P, l, cur, tau), maxd, xb, o);
+          if (act) integrate_lane<S, FREE, BALL>(cur, l, o, A.dt);
         }
       } else if (what == SCH_TAKESHOT) {
         if (act) put_slot(cur, A.ck + (size_t)slot * RW, ns, nf, l.slot, l.fidx);
       } else {
-        const S tau = rev ? A.tau[(size_t)arg * nu + l.uidx] : S(0);
+        const V3<S> tau = act ? load_ctl<BALL>(A.tau + (size_t)arg * nu, l) : zero3<S>();
         bwd_step<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xb, cur, tau, arg, xb1, nonfin, pg);
       }
     }
@@ -1086,26 +1239,26 @@ __attribute__((amdgpu_waves_per_eu((FREE || sizeof(R) > 4) ? 1 : 2))) void k_bac
         get_slot(st, A.ck + (size_t)s * RW, ns, nf, l.slot, l.fidx);
         put_slot(st, A.scratch, ns, nf, l.slot, l.fidx);
       }
-      S tau_nxt = (rev && t1 - t0 > 1) ? A.tau[(size_t)t0 * nu + l.uidx] : S(0);
+      V3<S> tau_nxt = (act && t1 - t0 > 1) ? load_ctl<BALL>(A.tau + (size_t)t0 * nu, l) : zero3<S>();
       for (int j = 1; j < t1 - t0; ++j) {
-        const S tau = tau_nxt;
-        if (rev && j + 1 < t1 - t0) tau_nxt = A.tau[(size_t)(t0 + j) * nu + l.uidx];
+        const V3<S> tau = tau_nxt;
+        if (act && j + 1 < t1 - t0) tau_nxt = load_ctl<BALL>(A.tau + (size_t)(t0 + j) * nu, l);
         Step<S> o;
-        aba_wave<S, FREE, CHAIN>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
+        aba_wave<S, FREE, CHAIN, BALL>(gravity(A.P), l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
         if (act) {
-          integrate_lane(st, l, o, A.dt);
+          integrate_lane<S, FREE, BALL>(st, l, o, A.dt);
           put_slot(st, A.scratch + (size_t)j * RW, ns, nf, l.slot, l.fidx);
         }
       }
       State<S, FREE> nxt = {};
       if (act) get_slot(nxt, A.scratch + (size_t)(t1 - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
-      tau_nxt = rev ? A.tau[(size_t)(t1 - 1) * nu + l.uidx] : S(0);
+      tau_nxt = act ? load_ctl<BALL>(A.tau + (size_t)(t1 - 1) * nu, l) : zero3<S>();
       for (int t = t1 - 1; t >= t0; --t) {
         const State<S, FREE> cur = nxt;
-        const S tau = tau_nxt;
-        if (t > t0) {
-          if (act) get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
-          if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
+        const V3<S> tau = tau_nxt;
+        if (t > t0 && act) {
+          get_slot(nxt, A.scratch + (size_t)(t - 1 - t0) * RW, ns, nf, l.slot, l.fidx);
+          tau_nxt = load_ctl<BALL>(A.tau + (size_t)(t - 1) * nu, l);
         }
         bwd_step<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xb, cur, tau, t, xb1, nonfin, pg);
       }
@@ -1144,30 +1297,31 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
   const int maxd = A.P.wmaxd[wb];
   const int ns = A.P.nslots;
   const int nu = A.P.nu;
+  constexpr bool BALL = FREE && FR == kFrBall;
   const bool act = l.active();
-  const bool rev = l.onedof();
   const size_t RW = state_record(ns, A.P.nfree);
   const int nf = A.P.nfree;
   const LinkC<S> L = load_linkc<S, FR>(A.P, l);
   const LinkC<R> LR = widen<R>(L);
   if (wid == 0) {
     State<S, FREE> nxt = {};
-    S tau_nxt = S(0);
-    if (A.T > 0) {
-      if (act) get_slot(nxt, A.ck + (size_t)(A.T - 1) * RW, ns, nf, l.slot, l.fidx);
-      if (rev) tau_nxt = A.tau[(size_t)(A.T - 1) * nu + l.uidx];
+    V3<S> tau_nxt = zero3<S>();
+    if (A.T > 0 && act) {
+      get_slot(nxt, A.ck + (size_t)(A.T - 1) * RW, ns, nf, l.slot, l.fidx);
+      tau_nxt = load_ctl<BALL>(A.tau + (size_t)(A.T - 1) * nu, l);
     }
     for (int k = 0; k <= A.T; ++k) {
       if (k < A.T) {
         const int t = A.T - 1 - k;
         const State<R, FREE> st = cvt_state<R>(nxt);
-        const R tau = R(tau_nxt);
-        if (t > 0) {
-          if (act) get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
-          if (rev) tau_nxt = A.tau[(size_t)(t - 1) * nu + l.uidx];
+        const V3<R> tau = cvt3<R>(tau_nxt);
+        if (t > 0 && act) {
+          get_slot(nxt, A.ck + (size_t)(t - 1) * RW, ns, nf, l.slot, l.fidx);
+          tau_nxt = load_ctl<BALL>(A.tau + (size_t)(t - 1) * nu, l);
         }
         Step<R> o;
-        aba_wave<R, FREE, CHAIN>(widen<R>(gravity(A.P)), l, LR, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
+        aba_wave<R, FREE, CHAIN, BALL>(widen<R>(gravity(A.P)), l, LR, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb,
+                                       o);
         R* tb = tbuf[k & 1];
 #pragma unroll
         for (int j = 0; j < (FREE ? 7 : 1); ++j) tb[(size_t)j * kWave + l.lane] = st.q[j];
@@ -1192,7 +1346,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
 #pragma unroll
         for (int j = 0; j < (FREE ? 6 : 1); ++j) st.qd[j] = tb[(size_t)((FREE ? 7 : 1) + j) * kWave + l.lane];
         Step<R> o;
-        get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, LR, st.qd[0], rev);
+        get_tape(o, tb + (size_t)(FREE ? 13 : 2) * kWave, kWave, l.lane, LR, st.qd[0], l.onedof());
         bwd_reverse<S, R, FREE, FR, CHAIN, PARAMS>(A, l, LR, maxd, xb, st, o, t, xb1, nonfin, pg);
       }
       __syncthreads();
@@ -1258,13 +1412,18 @@ __global__ __launch_bounds__(kWave * kMaxWavesPerBlock) void k_forward_jvp(JvpAr
   for (int k = 0; k < (FREE ? 7 : 1); ++k) st.q[k] = D(sv.q[k], sd.q[k]);
 #pragma unroll
   for (int k = 0; k < (FREE ? 6 : 1); ++k) st.qd[k] = D(sv.qd[k], sd.qd[k]);
-  const bool has_tau = l.onedof();
+  constexpr bool BALL = FREE && FR == kFrBall;
   int nonfin = 0;
   for (int t = 0; t < A.T; ++t) {
-    const D tau = has_tau ? D(A.tau[(size_t)t * nu + l.uidx], A.dtau[(size_t)t * nu + l.uidx]) : D(S(0), S(0));
+    V3<S> tv = zero3<S>(), td = zero3<S>();
+    if (l.active()) {
+      tv = load_ctl<BALL>(A.tau + (size_t)t * nu, l);
+      td = load_ctl<BALL>(A.dtau + (size_t)t * nu, l);
+    }
+    const V3<D> tau = v3<D>(D(tv.x, td.x), D(tv.y, td.y), D(tv.z, td.z));
     Step<D> o;
-    aba_wave<D, FREE, CHAIN>(g, l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
-    if (l.active()) integrate_lane(st, l, o, dt);
+    aba_wave<D, FREE, CHAIN, BALL>(g, l, L, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb, o);
+    if (l.active()) integrate_lane<D, FREE, BALL>(st, l, o, dt);
     if (A.traj != nullptr && l.active()) {
       split_state(st, sv, sd);
       S* row = A.traj + (size_t)t * (A.P.nq + A.P.nv);
@@ -1369,11 +1528,14 @@ hipError_t launch_forward_jvp_v(const JvpArgs<S>& a, const Tiling& tl, hipStream
 // canonicalisation; kFrGeneralJoints: prismatic joints or joint limits),
 // CHAIN (every system is a fixed-base serial chain of revolute joints;
 // register exchange between lanes).  Batches with prismatic joints or
-// joint limits take the one general variant (FREE, kFrGeneralJoints),
-// which handles every joint type and the limits.
-enum class Variant { kFree, kFreeEti, kTree, kTreeEti, kChain, kChainEti, kGeneral };
+// joint limits take the general variant (FREE, kFrGeneralJoints), which
+// handles every 1-dof joint type, free roots and the limits; batches with
+// ball joints the ball variant (FREE, kFrBall), which adds them (a variant
+// of its own, so that the others keep their register budgets).
+enum class Variant { kFree, kFreeEti, kTree, kTreeEti, kChain, kChainEti, kGeneral, kBall };
 
 inline Variant variant(const Shape& sh) {
+  if (sh.has_ball) return Variant::kBall;
   if (sh.has_prism || sh.has_limits) return Variant::kGeneral;
   if (sh.has_free) return sh.eti ? Variant::kFreeEti : Variant::kFree;
   if (sh.chain) return sh.eti ? Variant::kChainEti : Variant::kChain;
@@ -1394,6 +1556,7 @@ inline Variant variant(const Shape& sh) {
     case Variant::kChain: return LC<S, kFrGeneral>(a, tl, st);                    \
     case Variant::kChainEti: return LC<S, kFrIdentity>(a, tl, st);                \
     case Variant::kGeneral: return L<__VA_ARGS__, true, kFrGeneralJoints, false>(a, tl, st); \
+    case Variant::kBall: return L<__VA_ARGS__, true, kFrBall, false>(a, tl, st);   \
   }                                                                               \
   return hipErrorInvalidValue;
 

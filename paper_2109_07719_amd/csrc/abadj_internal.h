@@ -135,6 +135,7 @@ struct Shape {
   bool chain = false;
   bool has_prism = false;  // some joint is prismatic
   bool has_limits = false; // joint limits were given
+  bool has_ball = false;   // some joint is spherical
 };
 
 // Launch geometry.  waves_per_block: wavefronts per workgroup in the
@@ -155,8 +156,8 @@ struct Tiling {
 // identity after canonicalisation, every joint revolute; kFrGeneral: any
 // E_T, every joint revolute; kFrGeneralJoints: any E_T, prismatic joints
 // among the revolute ones (the joint type becomes a per-lane value) and
-// joint limits.
-enum : int { kFrIdentity = 0, kFrGeneral = 1, kFrGeneralJoints = 2 };
+// joint limits; kFrBall: as kFrGeneralJoints, and ball joints.
+enum : int { kFrIdentity = 0, kFrGeneral = 1, kFrGeneralJoints = 2, kFrBall = 3 };
 
 // The library's error channel (sim_last_error; abadj_runtime.hip): sets the
 // thread's message and returns code / clears it.

@@ -50,6 +50,7 @@ struct sim_handle {
   bool chain = false;  // every system is a fixed-base serial chain of revolute joints
   bool has_prism = false;  // some joint is prismatic
   bool has_limits = false;  // joint limits were given
+  bool has_ball = false;  // some joint is spherical
   aba::Tiling tiling;  // launch geometry
   int adj_dtype = SIM_F64;  // arithmetic of the reverse passes (FP32 handles: SIM_F32 or SIM_F64)
   // binomial checkpointing schedules, one device copy per (T, s) used, kept
@@ -98,6 +99,7 @@ aba::Shape shape(const sim_handle* h) {
   sh.chain = h->chain;
   sh.has_prism = h->has_prism;
   sh.has_limits = h->has_limits;
+  sh.has_ball = h->has_ball;
   return sh;
 }
 
@@ -338,7 +340,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
         return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: system " + std::to_string(s) + " link " + std::to_string(i) +
                                                   ": parent must satisfy -1 <= parent < index");
       }
-      if (jt != SIM_JOINT_REVOLUTE && jt != SIM_JOINT_FREE && jt != SIM_JOINT_PRISMATIC) {
+      if (jt != SIM_JOINT_REVOLUTE && jt != SIM_JOINT_FREE && jt != SIM_JOINT_PRISMATIC && jt != SIM_JOINT_SPHERICAL) {
         delete h;
         return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: unknown joint type");
       }
@@ -355,7 +357,8 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
         return fail(SIM_ERR_INVALID_TOPOLOGY, "sim_create: mass must be positive");
       }
       if (jt == SIM_JOINT_PRISMATIC) h->has_prism = true;
-      if (jt != SIM_JOINT_FREE) {
+      if (jt == SIM_JOINT_SPHERICAL) h->has_ball = true;
+      if (jt != SIM_JOINT_FREE && jt != SIM_JOINT_SPHERICAL) {
         const double* a = prm->axis + 3 * (size_t)(b + i);
         const double nrm = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
         if (std::fabs(nrm - 1.0) > 1e-6) {
@@ -373,6 +376,10 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
         q += 7;
         v += 6;
         h->has_free = true;
+      } else if (jt == SIM_JOINT_SPHERICAL) {
+        q += 4;
+        v += 3;
+        u += 3;
       } else {
         q += 1;
         v += 1;
@@ -442,7 +449,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
   static const double I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   std::vector<double> Rcan(9 * (size_t)nl);
   for (int L = 0; L < nl; ++L) {
-    if (topo->jtype[L] != SIM_JOINT_FREE)
+    if (topo->jtype[L] != SIM_JOINT_FREE && topo->jtype[L] != SIM_JOINT_SPHERICAL)
       axis_to_z(prm->axis + 3 * (size_t)L, Rcan.data() + 9 * (size_t)L);
     else
       for (int k = 0; k < 9; ++k) Rcan[9 * (size_t)L + k] = I3[k];
@@ -478,10 +485,12 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
       CI(aba::CI_QIDX) = sys_q[s] + loc_q[L];
       CI(aba::CI_VIDX) = sys_v[s] + loc_v[L];
       CI(aba::CI_UIDX) = (loc_u[L] < 0) ? -1 : sys_u[s] + loc_u[L];
-      if (topo->jtype[L] == SIM_JOINT_FREE) CI(aba::CI_FIDX) = h->nfree++;
+      // free roots and ball joints keep their state in the extended records
+      if (topo->jtype[L] == SIM_JOINT_FREE || topo->jtype[L] == SIM_JOINT_SPHERICAL) CI(aba::CI_FIDX) = h->nfree++;
       CI(aba::CI_LINK) = L;
       // joint-axis canonicalisation: rotate the link frame by Rl so that its
-      // axis becomes e_z (the parent frame was rotated by Rp):
+      // axis becomes e_z (Rl = 1 for a free root or ball joint, which have
+      // no axis; the parent frame was rotated by Rp):
       //   E_T' = Rl E_T Rp^T, r_T' = Rp r_T, c' = Rl c, Ic' = Rl Ic Rl^T.
       // Joint angles, velocities, torques and everything the caller sees are
       // unchanged.
@@ -550,7 +559,7 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
   // in the previous lane, a lane's only possible child is the next lane, and
   // the kernels exchange parent/child quantities between neighbouring lanes'
   // registers
-  bool chain = !h->has_free && !h->has_prism && !h->has_limits;
+  bool chain = !h->has_free && !h->has_prism && !h->has_limits && !h->has_ball;
   for (int slot = 0; chain && slot < NS; ++slot) {
     const int p = ci[(size_t)aba::CI_PARENT * NS + slot];
     if (ci[(size_t)aba::CI_JTYPE * NS + slot] >= 0 && p >= 0 && p != slot % aba::kWave - 1) chain = false;
@@ -590,6 +599,7 @@ int sim_get_info(sim_t h, sim_info_t* o) {
   o->has_prism = h->has_prism ? 1 : 0;
   o->dtype = h->dtype;
   o->adjoint_dtype = h->adj_dtype;
+  o->has_ball = h->has_ball ? 1 : 0;
   return SIM_OK;
 }
 
@@ -985,6 +995,9 @@ int sim_autotune(sim_t h, int K, int T_probe, void* stream, sim_tiling_t* chosen
     if (h->jtype[L] == SIM_JOINT_FREE) {
       q0h[qi + 6] = 1.0;
       qi += 7;
+    } else if (h->jtype[L] == SIM_JOINT_SPHERICAL) {
+      q0h[qi + 3] = 1.0;
+      qi += 4;
     } else {
       qi += 1;
     }
