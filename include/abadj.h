@@ -198,8 +198,8 @@ int sim_set_adjoint_dtype(sim_t h, int dtype);
  * sim_forward + sim_backward means every output is finite.  Synchronises
  * `stream` (the stream the kernels were enqueued on); not for use during
  * stream capture.  Kernels of one handle running concurrently on several
- * streams share the counter.  Errors: SIM_ERR_INVALID_ARG (null handle or
- * pointer), SIM_ERR_HIP. */
+ * streams share the counter.  Counts above INT_MAX are reported as INT_MAX.
+ * Errors: SIM_ERR_INVALID_ARG (null handle or pointer), SIM_ERR_HIP. */
 int sim_status(sim_t h, void *stream, int *nonfinite_count);
 
 /* Launch geometry of the handle's kernels (the autotuner's knobs; they

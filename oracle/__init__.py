@@ -21,6 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SOURCES = [os.path.join(_HERE, "aba_oracle.c"), os.path.join(_HERE, "pgs_oracle.c")]
 DEPS = SOURCES + [os.path.join(_HERE, "aba_fwd.inc"), os.path.join(_HERE, "oracle.h")]
+# joint types (oracle.h)
+ORC_REVOLUTE, ORC_FREE, ORC_PRISMATIC, ORC_SPHERICAL = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -317,6 +319,27 @@ def adjoint_along(m: Model, states, tau, dt, gqT, gqdT, gtraj=None):
     if rc != 0:
         raise RuntimeError("oracle adjoint_along failed")
     return gq0, gqd0, gtau
+
+
+def ball_tangent(system, q, gq):
+    """gq with the radial part of every spherical joint's quaternion adjoint
+    removed: g - (g . qh) qh, qh = q / |q|, i.e. the gradient along the unit
+    sphere.  On the sphere the step map is the same for every continuation
+    of R(quat) off it, so only this part is defined by the joint model (our
+    reading: a ball joint's state is a unit quaternion, Sec. 2 and App. G;
+    the integrator renormalises it every step).  q, gq: one system's [nq]
+    (or [..., nq]) arrays."""
+    g = np.array(gq, dtype=np.float64, copy=True)
+    qi = 0
+    for i in range(system.n):
+        jt = int(system.jtype[i])
+        if jt == ORC_SPHERICAL:
+            qh = np.asarray(q[..., qi:qi + 4], dtype=np.float64)
+            qh = qh / np.linalg.norm(qh, axis=-1, keepdims=True)
+            gi = g[..., qi:qi + 4]
+            g[..., qi:qi + 4] = gi - np.sum(gi * qh, axis=-1, keepdims=True) * qh
+        qi += 7 if jt == ORC_FREE else 4 if jt == ORC_SPHERICAL else 1
+    return g
 
 
 def map_threads(fn, items, threads: int | None = None):

@@ -350,8 +350,8 @@ __device__ __forceinline__ int nonfinite_state(const State<S, FREE>& s, const La
   }
   return n;
 }
-__device__ __forceinline__ void report_nonfinite(int* status, int n) {
-  if (n > 0) atomicAdd(status, n);
+__device__ __forceinline__ void report_nonfinite(unsigned long long* status, int n) {
+  if (n > 0) atomicAdd(status, (unsigned long long)n);
 }
 
 // stored state records (see state_record): [2][nslots] then [11][nfree]

@@ -39,7 +39,7 @@ struct Packed {
   int nfree;             // number of free-floating roots in the batch
   S g[3];                // gravity
   int nq, nv, nu;        // totals over the batch
-  int* status;           // device counter of non-finite numbers written to outputs
+  unsigned long long* status;  // device counter of non-finite numbers written to outputs
   int has_limits;        // some joint has limits (CF_LIM)
 };
 

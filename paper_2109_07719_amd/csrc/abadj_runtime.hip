@@ -65,7 +65,7 @@ struct sim_handle {
   int32_t* d_ci = nullptr;
   void* d_cf = nullptr;
   int32_t* d_wmaxd = nullptr;
-  int* d_status = nullptr;  // non-finite outputs written since the last sim_status
+  unsigned long long* d_status = nullptr;  // non-finite outputs written since the last sim_status
   // host-side structure summary for operation counting
   std::vector<int32_t> jtype, parent, nchild;
 };
@@ -253,13 +253,13 @@ int upload(sim_handle* h, const std::vector<int32_t>& ci, const std::vector<doub
   if (hipMalloc(&h->d_ci, ci.size() * sizeof(int32_t)) != hipSuccess ||
       hipMalloc(&h->d_cf, cfs.size() * sizeof(S)) != hipSuccess ||
       hipMalloc(&h->d_wmaxd, wmaxd.size() * sizeof(int32_t)) != hipSuccess ||
-      hipMalloc(&h->d_status, sizeof(int)) != hipSuccess)
+      hipMalloc(&h->d_status, sizeof(unsigned long long)) != hipSuccess)
     return fail(SIM_ERR_HIP, "sim_create: device allocation failed");
-  const int zero = 0;
+  const unsigned long long zero = 0;
   if (hipMemcpy(h->d_ci, ci.data(), ci.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->d_cf, cfs.data(), cfs.size() * sizeof(S), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(h->d_wmaxd, wmaxd.data(), wmaxd.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(h->d_status, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(h->d_status, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
     return fail(SIM_ERR_HIP, "sim_create: upload failed");
   return SIM_OK;
 }
@@ -618,11 +618,12 @@ int sim_status(sim_t h, void* stream, int* nonfinite_count) {
   g_err.clear();
   if (!h || !nonfinite_count) return fail(SIM_ERR_INVALID_ARG, "sim_status: null argument");
   hipStream_t st = (hipStream_t)stream;
-  int v = 0;
-  if (hipMemcpyAsync(&v, h->d_status, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess || hipMemsetAsync(h->d_status, 0, sizeof(int), st) != hipSuccess)
+  unsigned long long v = 0;
+  if (hipMemcpyAsync(&v, h->d_status, sizeof(v), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess || hipMemsetAsync(h->d_status, 0, sizeof(v), st) != hipSuccess)
     return fail(SIM_ERR_HIP, "sim_status: could not read the counter");
-  *nonfinite_count = v;
+  // a 64-bit device counter, reported saturated at INT_MAX
+  *nonfinite_count = v > 2147483647ull ? 2147483647 : (int)v;
   return SIM_OK;
 }
 
@@ -1160,6 +1161,7 @@ struct LinkOps {
   long long fd_free, integ_free;
   long long bwd_rev, bwd_rev_push, child_bwd, integ_adj_rev;
   long long bwd_free;
+  long long fd_ball, fd_ball_push, integ_ball, bwd_ball, bwd_ball_push;
 };
 
 // prism: count a prismatic joint's link instead of a revolute one
@@ -1220,6 +1222,59 @@ LinkOps link_ops(bool eti, bool prism) {
     r3_root(M, v, qt, g, v, w, qb, M2, w);
     (void)r1_root(L, v, w, w);
   });
+  // ball joint: pass 1 (E from the quaternion), 2 and 3; the push to the
+  // parent; the integrator; the reverse step (with the rebuild of E, c and
+  // the joint-space blocks the stored tapes leave out)
+  {
+    V3<Op> w3{}, a3{};
+    o.fd_ball = count([&] {
+      ball_p1(L, t, qt, w3, v);
+      p1_bias(L, t.v, Op(), false, t.c, t.pA, t.IA);
+      t.c = crm(t.v, v6<Op>(w3, zero3<Op>()));
+      (void)ball_p2_local(t, w3);
+      (void)ball_p3(L, t, v, a3);
+    });
+    o.fd_ball_push = count([&] { ball_p2_push(L, t, w3, M, w); });
+    o.integ_ball = 3 + count([&] {
+                     V3<Op> w1 = w3 + Op() * a3;
+                     (void)quat_step(qt, w1, Op());
+                   });
+    auto rebuild = [&] {
+      t.E = ball_E(qt, L.ET);
+      t.c = crm(t.v, v6<Op>(w3, zero3<Op>()));
+      t.Ai = sy3_inv(t.IA.A);
+      t.y = mul(t.Ai, a3);
+      t.W = mul(sy_to_m3(t.Ai), t.IA.B);
+    };
+    o.bwd_ball = count([&] {
+      rebuild();
+      V3<Op> wb{}, s3{};
+      (void)quat_step_adj(qt, w3 + Op() * a3, Op(), qt, wb);
+      BallBar<Op> bb{};
+      SySp<Op> N{};
+      V6<Op> pab{};
+      const V6<Op> apb = ball_r3_path(t, v, w3, s3);
+      ball_r3_local(t, b, bb, apb, s3);
+      (void)ball_r2_path(L, t, bb, a3, false, M, v, N, pab, M2, w);
+      (void)ball_r1_own(L, t.v, b, w, w3);
+      (void)ball_r1_local(t, b, v, w3);
+      (void)ball_quat_bar(qt, b.G.a);
+    });
+    o.bwd_ball_push = count([&] {
+                        BallBar<Op> bb{};
+                        SySp<Op> N{};
+                        V6<Op> pab{};
+                        (void)xformT(t.E, L.rT, v);  // a_bar to the parent
+                        (void)ball_r2_path(L, t, bb, a3, true, M, v, N, pab, M2, w);
+                        ball_r2_local(t, b, N, pab);
+                      }) -
+                      count([&] {
+                        BallBar<Op> bb{};
+                        SySp<Op> N{};
+                        V6<Op> pab{};
+                        (void)ball_r2_path(L, t, bb, a3, false, M, v, N, pab, M2, w);
+                      });
+  }
   return o;
 }
 
@@ -1236,6 +1291,12 @@ extern "C" int sim_flops(sim_t h, int kind, double* flops) {
       fd += (double)o.fd_free;
       fwd += (double)(o.fd_free + o.integ_free);
       bwd += (double)o.bwd_free;
+    } else if (h->jtype[i] == SIM_JOINT_SPHERICAL) {
+      const bool push = h->parent[i] >= 0;
+      const double f = (double)(o.fd_ball + (push ? o.fd_ball_push : 0));
+      fd += f;
+      fwd += f + (double)o.integ_ball;
+      bwd += (double)(o.bwd_ball + (push ? o.bwd_ball_push : 0));
     } else {
       const bool push = h->parent[i] >= 0;
       const double f = (double)(o.fd_rev + (push ? o.fd_rev_push : 0));

@@ -7,8 +7,9 @@ the adjoint recursion).  This module computes world positions of chosen
 points on chosen links for a whole batch, one tree level at a time, with the
 package's joint convention (revolute: link -> parent rotation
 E^T = E_T^T Rot(a, q), Rot the rotation by +q about a, origin at r_T;
-prismatic: E^T = E_T^T, origin at r_T + q E_T^T a; free root: R(quat) and
-p).  Other joint types are rejected.
+prismatic: E^T = E_T^T, origin at r_T + q E_T^T a; spherical: E^T =
+E_T^T R(quat), origin at r_T; free root: R(quat) and p).  Other joint types
+are rejected.
 """
 from __future__ import annotations
 
@@ -43,9 +44,10 @@ class LinkPoints(torch.nn.Module):
             d = sy.depth()
             qo = 0
             for i in range(sy.n):
-                if int(sy.jtype[i]) not in (0, 1, 2):
+                if int(sy.jtype[i]) not in (0, 1, 2, 3):
                     raise ValueError(f"LinkPoints: system {s} link {i} has joint type {int(sy.jtype[i])}; "
-                                     "only revolute (0), free root (1) and prismatic (2) joints are supported")
+                                     "only revolute (0), free root (1), prismatic (2) and spherical (3) "
+                                     "joints are supported")
                 glob_par.append(-1 if sy.parent[i] < 0 else base + int(sy.parent[i]))
                 dep.append(int(d[i]))
                 qidx.append(qbase + qo)
@@ -53,7 +55,7 @@ class LinkPoints(torch.nn.Module):
                 ET.append(np.asarray(sy.E_T[i]))
                 rT.append(np.asarray(sy.r_T[i]))
                 ax.append(np.asarray(sy.axis[i]))
-                qo += 7 if sy.jtype[i] == 1 else 1
+                qo += 7 if sy.jtype[i] == 1 else 4 if sy.jtype[i] == 3 else 1
             target.append(base + int(links[s]))
             base += sy.n
             qbase += qo
@@ -76,19 +78,27 @@ class LinkPoints(torch.nn.Module):
                        for d in range(int(self.depth.max()) + 1)]
         self.level_free = [np.nonzero(self.jtype[np.nonzero(self.depth == d)[0]] == 1)[0]
                            for d in range(int(self.depth.max()) + 1)]
+        self.level_ball = [np.nonzero(self.jtype[np.nonzero(self.depth == d)[0]] == 3)[0]
+                           for d in range(int(self.depth.max()) + 1)]
 
     def forward(self, q):
         n = self.n_links
         Rw = torch.zeros((n, 3, 3), dtype=q.dtype, device=q.device)
         pw = torch.zeros((n, 3), dtype=q.dtype, device=q.device)
         I3 = torch.eye(3, dtype=q.dtype, device=q.device)
-        for idx, free in zip(self.levels, self.level_free):
+        for idx, free, ball in zip(self.levels, self.level_free, self.level_ball):
             m = idx.numel()
             qi = q[self.qidx[idx]]
             K = self.K[idx]
             pr = self.prism[idx]
             s, c = torch.sin(qi)[:, None, None], torch.cos(qi)[:, None, None]
             Rj = torch.where(pr[:, None, None], I3.expand(m, 3, 3), I3 + s * K + (1 - c) * (K @ K))
+            if len(ball):
+                rows = list(Rj.unbind(0))
+                for k in ball:
+                    qo = int(self.qidx_np[int(idx[k])])
+                    rows[k] = _quat_R(q[qo:qo + 4])
+                Rj = torch.stack(rows)
             par = self.parent[idx]
             has_par = par >= 0
             parc = par.clamp(min=0)

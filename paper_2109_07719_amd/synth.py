@@ -431,6 +431,11 @@ def workload(name: str, n_systems: int | None = None, T: int | None = None,
       trees_prismatic_8192
                     the trees_8192 systems with each joint prismatic with
                     probability 0.3 (same shapes and draws otherwise)
+      ball_quad_1024
+                    1024 quadrupeds on ball hips (ball_quadruped_system,
+                    seed 3000+i), dt 1e-3, T 2000 (under these random
+                    torques the ball hips spin up and the rollouts diverge
+                    after 5000-20000 steps, in the oracle alike)
     n_systems / T shrink a workload for tests (the seeds stay the same)."""
     if name == "chain7_fp64":
         ns, TT, dt = 1, 1000, 1e-3
@@ -452,6 +457,10 @@ def workload(name: str, n_systems: int | None = None, T: int | None = None,
         ns, TT, dt = 1024, 50000, 1e-3
         ns, TT = n_systems or ns, T or TT
         draws = [quadruped_system(3000 + i, TT) for i in range(ns)]
+    elif name == "ball_quad_1024":
+        ns, TT, dt = 1024, 2000, 1e-3
+        ns, TT = n_systems or ns, T or TT
+        draws = [ball_quadruped_system(3000 + i, TT) for i in range(ns)]
     elif name == "chains_2048":
         ns, TT, dt = 2048, 1000, 1e-3
         ns, TT = n_systems or ns, T or TT

@@ -25,20 +25,9 @@ def rel(x, ref, floor=FLOOR_F32):
 
 
 def ball_tangent(s, q, gq):
-    """gq with the radial part of every ball joint's quaternion adjoint
-    removed (g - (g . qh) qh, qh = q / |q|): the library returns a ball
-    joint's quaternion gradient along the unit sphere.  q, gq: one system's
-    [nq] (or [..., nq]) arrays."""
-    g = np.array(gq, dtype=np.float64, copy=True)
-    qi = 0
-    for i in range(s.n):
-        if s.jtype[i] == 3:
-            qh = np.asarray(q[..., qi:qi + 4], dtype=np.float64)
-            qh = qh / np.linalg.norm(qh, axis=-1, keepdims=True)
-            gi = g[..., qi:qi + 4]
-            g[..., qi:qi + 4] = gi - np.sum(gi * qh, axis=-1, keepdims=True) * qh
-        qi += 7 if s.jtype[i] == 1 else 4 if s.jtype[i] == 3 else 1
-    return g
+    """The oracle's gradient gq along the unit sphere of every ball joint's
+    quaternion (the form the library returns; oracle.ball_tangent)."""
+    return O.ball_tangent(s, q, gq)
 
 
 def split(vec, off):

@@ -300,20 +300,28 @@ def test_fast_free_base_keeps_fp32_joint_accelerations():
 # ---------------------------------------------------------------- forward kinematics helper
 
 def test_link_points_match_world_kinematics_with_prismatic_joints():
-    """The loss-side FK helper (revolute, prismatic, free-root links) against
-    the independent world-frame kinematics of the Newton-Euler reference, on
-    trees with random frames and prismatic joints, a cart-pole and a
-    quadruped; spherical joints are rejected instead of mis-handled."""
+    """The loss-side FK helper (revolute, prismatic, spherical and free-root
+    links) against the independent world-frame kinematics of the
+    Newton-Euler reference, on trees with random frames, prismatic and ball
+    joints, a cart-pole and quadrupeds (one on ball hips); an unknown joint
+    type is rejected instead of mis-handled."""
     import torch
     from dyn_ref import kinematics
     from paper_2109_07719_amd.fk import LinkPoints
     rng = np.random.default_rng(5)
     draws = [synth.tree_system(2100 + i, 1, random_frames=True, prismatic=0.4) for i in range(4)]
     draws += [synth.cartpole_system(7, 1), synth.quadruped_system(3007, 1), synth.prismatic_chain_system(5, 9, 1)]
+    draws += [synth.ball_tree_system(2200 + i, 1, random_frames=True, spherical=0.5) for i in range(2)]
+    draws += [synth.ball_quadruped_system(3008, 1)]
     for sys_, q0, qd0, _ in draws:
         q = np.asarray(q0, dtype=np.float64) + rng.normal(0, 0.3, len(q0))
-        if sys_.jtype[0] == 1:
-            q[3:7] /= np.linalg.norm(q[3:7])
+        qo = 0
+        for i in range(sys_.n):
+            if sys_.jtype[i] == 1:
+                q[qo + 3:qo + 7] /= np.linalg.norm(q[qo + 3:qo + 7])
+            elif sys_.jtype[i] == 3:
+                q[qo:qo + 4] /= np.linalg.norm(q[qo:qo + 4])
+            qo += 7 if sys_.jtype[i] == 1 else 4 if sys_.jtype[i] == 3 else 1
         pts = rng.normal(0, 0.3, (sys_.n, 3))
         R, o, *_ = kinematics(sys_, q, np.zeros(sys_.nv), np.zeros(sys_.nv), (0.0, -9.81, 0.0))
         for link in range(sys_.n):
@@ -321,6 +329,7 @@ def test_link_points_match_world_kinematics_with_prismatic_joints():
             got = fk(torch.tensor(q))[0].numpy()
             ref = o[link] + R[link] @ pts[link]
             assert np.allclose(got, ref, rtol=0, atol=1e-12), (link, got, ref)
-    ball, *_ = synth.ball_tree_system(2200, 1)
-    with pytest.raises(ValueError, match="joint type 3"):
-        LinkPoints([ball], [ball.n - 1], [[0.5, 0.0, 0.0]], dtype=torch.float64, device="cpu")
+    bad, *_ = synth.tree_system(2200, 1)
+    bad = synth.replace(bad, jtype=np.where(np.arange(bad.n) == bad.n - 1, 7, bad.jtype).astype(np.int32))
+    with pytest.raises(ValueError, match="joint type 7"):
+        LinkPoints([bad], [bad.n - 1], [[0.5, 0.0, 0.0]], dtype=torch.float64, device="cpu")

@@ -908,6 +908,46 @@ def test_rollout_gradient_complex_step_with_spherical_joints(k):
         assert abs(d - gtau[t, j]) < 1e-11 * np.abs(gtau).max(), (name, t, j)
 
 
+def _qmul(a, b):
+    """Hamilton product of quaternions stored (x, y, z, w) (complex-safe)."""
+    av, aw, bv, bw = a[:3], a[3], b[:3], b[3]
+    return np.r_[aw * bv + bw * av + np.cross(av, bv), aw * bw - av @ bv]
+
+
+def test_ball_tangent_gradient_is_the_derivative_along_the_sphere():
+    """oracle.ball_tangent (the form of a ball joint's quaternion gradient the
+    kernels return): orthogonal to each quaternion, and its pairing with the
+    velocity of a curve on the unit sphere, q(t) = q (x) (sin(t/2) d, cos(t/2)),
+    equals the complex-step derivative of the loss along that curve."""
+    name, (s, q0, qd0, tau), dt = _ball_problems()[0]
+    m = O.Model(s)
+    rng = np.random.default_rng(17)
+    wq, wv = rng.normal(size=s.nq), rng.normal(size=s.nv)
+    g = O.rollout_grad(m, q0, qd0, tau[:30], dt, wq, wv)[0]
+    gt = O.ball_tangent(s, q0, g)
+    balls, qi = [], 0
+    for i in range(s.n):
+        if s.jtype[i] == synth.SPHERICAL:
+            balls.append(qi)
+        qi += 7 if s.jtype[i] == synth.FREE else 4 if s.jtype[i] == synth.SPHERICAL else 1
+    assert len(balls) == 4
+    h = 1e-30
+    for k in balls:
+        q = q0[k:k + 4]
+        assert abs(gt[k:k + 4] @ q) < 1e-14 * np.linalg.norm(g[k:k + 4])
+        assert abs(g[k:k + 4] @ q) > 1e-3 * np.linalg.norm(g[k:k + 4])  # the full gradient has a radial part
+        for _ in range(3):
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            th = 1j * h
+            qc = q0.astype(complex)
+            qc[k:k + 4] = _qmul(q, np.r_[np.sin(th / 2) * d, np.cos(th / 2)])
+            qT, qdT = O.rollout_complex(m, qc, qd0.astype(complex), tau[:30].astype(complex), dt)
+            deriv = (wq @ qT + wv @ qdT).imag / h
+            vel = _qmul(q, np.r_[0.5 * d, 0.0])
+            assert abs(gt[k:k + 4] @ vel - deriv) < 1e-11 * max(1.0, abs(deriv)), (k, deriv)
+
+
 def test_ball_joint_parameter_and_placement_gradients_central_differences():
     """Inertial-parameter and joint-placement gradients of ball-joint links
     against central differences of the forward rollout; a ball joint has no
