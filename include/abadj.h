@@ -399,7 +399,9 @@ const char *sim_last_error(void);
 #define SIM_PGS_MAX_ROWS 16
 
 /* Bytes of the workspace that keeps x at the start of every sweep (and the
- * result) for the adjoint: (niter + 1) * n * batch * sizeof(dtype). */
+ * result) for the adjoint: (niter + 1) * n * batch * sizeof(dtype), and for
+ * n >= 13 another niter * n * batch elements after them, which
+ * sim_pgs_adjoint uses as scratch (the sweep vectors stay as they are). */
 int sim_pgs_workspace_bytes(int dtype, int batch, int n, int niter, size_t *bytes);
 
 /* Solve.  workspace (nullable): when given (workspace_bytes at least
@@ -416,7 +418,7 @@ int sim_pgs_solve(int dtype, int batch, int n, int niter, const void *A, const v
  * the active bound (a value exactly on a bound counts as inside), a free
  * row to b, A and the other rows' values it was computed from. */
 int sim_pgs_adjoint(int dtype, int batch, int n, int niter, const void *A, const void *b,
-                    const void *lo, const void *hi, const void *xbar, const void *workspace,
+                    const void *lo, const void *hi, const void *xbar, void *workspace,
                     size_t workspace_bytes, void *Abar, void *bbar, void *lobar, void *hibar,
                     void *x0bar, void *stream);
 

@@ -13,9 +13,10 @@
 // y_i, and x_bar_i is reset.
 //
 // Layout on the GPU: one lane per problem.  A problem of n <= 16 rows is
-// held in registers (A, and in the adjoint A_bar as well) by a kernel
-// compiled for NMAX rows (4, 8, 12 or 16; rows past n are skipped), so the
-// row and column loops are unrolled and every operand has a fixed register.
+// held in registers (A, and in the adjoint A_bar as well up to 12 rows) by a
+// kernel compiled for NMAX rows (4, 8, 12 or 16; rows past n are skipped), so
+// the row and column loops are unrolled and every operand has a fixed
+// register.
 // The sweep vectors go to the workspace as [niter + 1][n][batch], one
 // coalesced row per wave and entry.  Problems are independent: no
 // cross-lane traffic, no barriers.
@@ -158,10 +159,128 @@ __global__ __launch_bounds__(kBlock) void k_pgs_adjoint(PgsArgs<S> P) {
     }
 }
 
+// The adjoint for the largest row bucket.  A and A_bar together (2 * 16^2
+// per lane) do not fit the registers next to the vectors, so A_bar is formed
+// in a second phase: the reverse sweeps keep A, the diagonal of A_bar and
+// the vectors, and write each row's y_bar / (-A_ii) = db_{t,i} to the
+// workspace after the sweep vectors; then, since
+//   A_bar_ij = sum_t db_{t,i} x_j(t, i)  (j != i),
+// with x_j(t, i) the value row i read in sweep t (the end-of-sweep value for
+// j < i, the start-of-sweep one for j > i), RC rows of A_bar at a time are
+// summed from db and the sweep vectors.  Each lane reads back only what it
+// wrote itself.
+constexpr int kSplitRows = 13;  // row counts from this up take the split adjoint
+constexpr int kRC = 8;          // rows of A_bar per pass of the second phase
+
+template <typename S, int N>
+__global__ __launch_bounds__(kBlock) void k_pgs_adjoint_split(PgsArgs<S> P) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= P.batch) return;
+  const int n = P.n;
+  const size_t B = (size_t)P.batch;
+  S* db = P.ws + (size_t)(P.niter + 1) * n * B;  // [niter][n][batch]
+  S A[N][N], Ad[N], b[N], lo[N], hi[N], xb[N], bb[N], lb[N], hb[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) A[i][j] = (i < n && j < n) ? P.A[((size_t)p * n + i) * n + j] : S(0);
+    Ad[i] = S(0);
+    b[i] = (i < n) ? P.b[(size_t)p * n + i] : S(0);
+    lo[i] = (i < n) ? P.lo[(size_t)p * n + i] : S(0);
+    hi[i] = (i < n) ? P.hi[(size_t)p * n + i] : S(0);
+    xb[i] = (i < n) ? P.xbar[(size_t)p * n + i] : S(0);
+    bb[i] = lb[i] = hb[i] = S(0);
+  }
+  for (int t = P.niter - 1; t >= 0; --t) {
+    S xs[N], xe[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      xs[j] = (j < n) ? P.ws[((size_t)t * n + j) * B + p] : S(0);
+      xe[j] = (j < n) ? P.ws[((size_t)(t + 1) * n + j) * B + p] : S(0);
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+      if (i < n) {
+        S d = S(0);
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+          if (j != i) d += A[i][j] * ((j < i) ? xe[j] : xs[j]);
+        const S y = -(b[i] + d) / A[i][i];
+        S yb = S(0);
+        if (y < lo[i]) lb[i] += xb[i];
+        else if (y > hi[i]) hb[i] += xb[i];
+        else yb = xb[i];
+        xb[i] = S(0);
+        const S dbi = -yb / A[i][i];
+        bb[i] += dbi;
+        Ad[i] += dbi * y;
+        db[((size_t)t * n + i) * B + p] = dbi;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+          if (j != i) xb[j] += dbi * A[i][j];
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (i < n) {
+      P.bbar[(size_t)p * n + i] = bb[i];
+      P.lobar[(size_t)p * n + i] = lb[i];
+      P.hibar[(size_t)p * n + i] = hb[i];
+      P.x0bar[(size_t)p * n + i] = xb[i];
+    }
+  // second phase: the off-diagonal entries of A_bar, kRC rows at a time
+#pragma unroll 1
+  for (int r0 = 0; r0 < n; r0 += kRC) {
+    S acc[kRC][N];
+#pragma unroll
+    for (int r = 0; r < kRC; ++r)
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc[r][j] = S(0);
+    for (int t = 0; t < P.niter; ++t) {
+      S xs[N], xe[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        xs[j] = (j < n) ? P.ws[((size_t)t * n + j) * B + p] : S(0);
+        xe[j] = (j < n) ? P.ws[((size_t)(t + 1) * n + j) * B + p] : S(0);
+      }
+#pragma unroll
+      for (int r = 0; r < kRC; ++r) {
+        const int i = r0 + r;
+        if (i < n) {
+          const S dbi = db[((size_t)t * n + i) * B + p];
+#pragma unroll
+          for (int j = 0; j < N; ++j) acc[r][j] += dbi * ((j < i) ? xe[j] : xs[j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRC; ++r) {
+      const int i = r0 + r;
+      if (i < n) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          if (j < n) {
+            // the diagonal is y's own term from the first phase
+            S v = acc[r][j];
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+              if (k == i && j == k) v = Ad[k];
+            P.Abar[((size_t)p * n + i) * n + j] = v;
+          }
+        }
+      }
+    }
+  }
+}
+
 int pgs_fail(int code, const std::string& msg) { return aba::report_error(code, msg); }
 
+// the sweep vectors [niter + 1][n][batch], and for the split adjoint's rows
+// db [niter][n][batch] after them
 size_t pgs_ws_bytes(int dtype, int batch, int n, int niter) {
-  return (size_t)(niter + 1) * (size_t)n * (size_t)batch * (dtype == SIM_F64 ? sizeof(double) : sizeof(float));
+  const size_t rows = (size_t)(niter + 1) + (n >= kSplitRows ? (size_t)niter : 0);
+  return rows * (size_t)n * (size_t)batch * (dtype == SIM_F64 ? sizeof(double) : sizeof(float));
 }
 
 int pgs_check(const char* who, int dtype, int batch, int n, int niter) {
@@ -173,11 +292,17 @@ int pgs_check(const char* who, int dtype, int batch, int n, int niter) {
   return SIM_OK;
 }
 
-// one kernel per row bucket NMAX (4, 8, 12, 16)
+// one kernel per row bucket NMAX (4, 8, 12, 16); the largest bucket's
+// adjoint is the split one
 template <typename S, int N>
 void launch_n(const PgsArgs<S>& a, hipStream_t st, bool adjoint, dim3 grid) {
-  if (adjoint) hipLaunchKernelGGL((k_pgs_adjoint<S, N>), grid, dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_pgs_solve<S, N>), grid, dim3(kBlock), 0, st, a);
+  static_assert(N < kSplitRows || N == 16, "row buckets");
+  if (adjoint) {
+    if constexpr (N >= kSplitRows) hipLaunchKernelGGL((k_pgs_adjoint_split<S, N>), grid, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_pgs_adjoint<S, N>), grid, dim3(kBlock), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((k_pgs_solve<S, N>), grid, dim3(kBlock), 0, st, a);
+  }
 }
 template <typename S>
 hipError_t launch(const PgsArgs<S>& a, hipStream_t st, bool adjoint) {
@@ -231,7 +356,7 @@ int sim_pgs_solve(int dtype, int batch, int n, int niter, const void* A, const v
 }
 
 int sim_pgs_adjoint(int dtype, int batch, int n, int niter, const void* A, const void* b, const void* lo,
-                    const void* hi, const void* xbar, const void* workspace, size_t workspace_bytes, void* Abar,
+                    const void* hi, const void* xbar, void* workspace, size_t workspace_bytes, void* Abar,
                     void* bbar, void* lobar, void* hibar, void* x0bar, void* stream) {
   aba::clear_error();
   int rc = pgs_check("sim_pgs_adjoint", dtype, batch, n, niter);

@@ -103,6 +103,9 @@ def test_null_arguments_are_rejected():
     assert L.sim_pgs_workspace_bytes(0, 4, 0, 10, ctypes.byref(z)) == N.SIM_ERR_INVALID_ARG
     assert L.sim_pgs_workspace_bytes(7, 4, 3, 10, ctypes.byref(z)) == N.SIM_ERR_UNSUPPORTED_DTYPE
     assert L.sim_pgs_workspace_bytes(1, 4, 3, 10, ctypes.byref(z)) == N.SIM_OK and z.value == 11 * 3 * 4 * 8
+    # from 13 rows the adjoint keeps its per-row coefficients after the sweep vectors
+    assert L.sim_pgs_workspace_bytes(0, 4, 12, 10, ctypes.byref(z)) == N.SIM_OK and z.value == 11 * 12 * 4 * 4
+    assert L.sim_pgs_workspace_bytes(0, 4, 13, 10, ctypes.byref(z)) == N.SIM_OK and z.value == 21 * 13 * 4 * 4
     assert L.sim_pgs_solve(0, 4, 3, 10, None, None, None, None, None, None, None, 0, None) == N.SIM_ERR_INVALID_ARG
     assert L.sim_pgs_solve(0, 4, 17, 10, None, None, None, None, None, None, None, 0, None) == N.SIM_ERR_INVALID_ARG
     assert L.sim_pgs_adjoint(0, 4, 3, 10, *([None] * 6), 0, *([None] * 6)) == N.SIM_ERR_INVALID_ARG
