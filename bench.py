@@ -394,6 +394,10 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-6))
 
 
+def _rel_floor(a, b, floor):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), floor))
+
+
 def contact_bench(args, torch, dev):
     """Rollouts with contact inside the step and their gradient (Sec. 4.1
     "Collision resolution"): B landing quadrupeds (spheres on the four feet),
@@ -467,6 +471,33 @@ def contact_bench(args, torch, dev):
             x = trn[t, :, i]
             q1, qd1, _, _ = O.step_contact(m, C, x[:cb.nq], x[cb.nq:], taun[t, :, i], dt)
             worst = max(worst, _rel(trn[t + 1, :, i], np.r_[q1, qd1]))
+    # the FP32 gradient of the whole rollout against the oracle's one-step
+    # gradients chained backwards along the GPU's own trajectory, on sampled
+    # systems, with the model as the GPU holds it (rounded to FP32)
+    r32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)
+    gn = [x.double().cpu().numpy() for x in g[:3]]
+    sample = list(range(0, B, max(1, B // 8)))
+    dt32 = float(r32(dt))
+
+    def along(i):
+        s = draws[i][0]
+        s32 = synth.System(parent=s.parent, jtype=s.jtype, E_T=r32(s.E_T), r_T=r32(s.r_T), axis=r32(s.axis),
+                           mass=r32(s.mass), com=r32(s.com), Ic=r32(s.Ic))
+        m = O.Model(s32, r32(G))
+        C = O.Contacts(draws[i][4], r32(draws[i][5]), r32(draws[i][6]), mu=float(r32(mu)), beta=float(r32(beta)),
+                       niter=niter)
+        gq, gqd = np.ones(cb.nq), np.ones(cb.nv)
+        gt = np.zeros((T, cb.nu))
+        for t in range(T - 1, -1, -1):
+            x = trn[t, :, i]
+            gq, gqd, gtt = O.rollout_contact_grad(m, C, x[:cb.nq], x[cb.nq:], taun[t:t + 1, :, i], dt32, gq, gqd)
+            gt[t] = gtt[0]
+        got = (gn[0][:, i], gn[1][:, i], gn[2][:, :, i])
+        scale = max(float(np.abs(r).max()) for r in (gq, gqd, gt))
+        return max(_rel_floor(a, b, 1e-6 * scale) for a, b in zip(got, (gq, gqd, gt)))
+
+    grad_err = O.map_threads(along, sample, threads=host_threads()[0])
+    progress(f"contact gradient along the GPU trajectory on {len(sample)} systems: max {max(grad_err):.2e}")
     cpu = None
     if not args.no_cpu_baseline:
         Tw = min(T, 40)
@@ -500,6 +531,12 @@ def contact_bench(args, torch, dev):
                         "rollout_achieved": fl_fwd / (fwd * 1e-3) / 1e12, "rollout_flops_per_launch": fl_fwd,
                         "flops_per_step_mean": float(np.mean(sf)), "grad_flops_per_step_mean": float(np.mean(gf))},
            "step_map_error_vs_oracle_max": worst,
+           "grad_rel_err": {"along_gpu_trajectory_max": max(grad_err),
+                            "along_gpu_trajectory_median": float(np.median(grad_err)), "systems": len(sample),
+                            "what": "per system max over (q0_bar, qd0_bar, tau_bar) of ||g - ref|| / ||ref|| "
+                                    "(floor 1e-6 x the largest entry), ref = the FP64 oracle's one-step gradients "
+                                    "chained backwards along the GPU's own FP32 trajectory over all T steps; "
+                                    "bar 1e-3 (FP32 gradients)"},
            "cpu_baseline": cpu}
     print(json.dumps(res))
 

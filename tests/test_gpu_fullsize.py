@@ -152,11 +152,13 @@ def _sampled_along(b, sample, K=1, extra_K=(), diverging=0):
         size = max(np.abs(x).max() for x in ga[:3] if x.size)
         fits = size < 1e-3 * float(np.finfo(np.float32).max)
         W = b.T if fits else min(b.T, 500)
+        # a ball joint's quaternion gradient is compared along the unit sphere
+        ga0 = O.ball_tangent(b.systems[i], x0[:nqi], ga[0])
         for K2, g in [(K, (gq0, gqd0, gt_all))] + list(zip(extra_K, g_extra)):
             gt_i = g[2][-W:, uo[i]:uo[i + 1]]
             e = [rel(gt_i, ga[2][-W:])] if gt_i.size else []
             if fits:
-                e += [rel(g[0][qo[i]:qo[i + 1]], ga[0]), rel(g[1][vo[i]:vo[i + 1]], ga[1])]
+                e += [rel(g[0][qo[i]:qo[i + 1]], ga0), rel(g[1][vo[i]:vo[i + 1]], ga[1])]
             if fits:
                 worst_grad = max(worst_grad, *e)
             else:
@@ -177,6 +179,17 @@ def test_full_size_trees_8192_sampled():
     assert len(b.systems) == 8192 and b.T == 2000
     sample = [0, 1, 777, 4096, 6000, 8191]
     worst_step, worst_grad, worst_window = _sampled_along(b, sample)
+    assert worst_step < 1e-6
+    assert worst_grad < TOL_GRAD_F32 and worst_window == 0.0
+
+
+def test_full_size_ball_quadrupeds_1024_sampled():
+    """1024 quadrupeds on ball hips, 2000 steps (11 rollouts diverge under
+    the integrator, the FP64 oracle's the same 11): sampled step maps and
+    gradients along the GPU trajectory, K = 1 and 10."""
+    b = _full_batch("ball_quad_1024")
+    assert len(b.systems) == 1024 and b.T == 2000
+    worst_step, worst_grad, worst_window = _sampled_along(b, [0, 300, 511, 777, 1023], extra_K=(10,), diverging=0)
     assert worst_step < 1e-6
     assert worst_grad < TOL_GRAD_F32 and worst_window == 0.0
 
