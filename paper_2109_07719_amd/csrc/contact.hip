@@ -20,7 +20,8 @@
 //     root, q1 = q + dt qd1 for 1-dof joints).
 //
 // Design: the forward runs one lane per system, a few systems to a wave, and
-// keeps the whole tree's articulated quantities in LDS.  J comes from the
+// keeps the whole tree's articulated quantities in LDS (the gradient keeps
+// them in private memory, see k_contact_adj).  J comes from the
 // world poses and joint axes along the contact link's path to the root;
 // each column of M^-1 J^T is the articulated-body response to a unit force
 // at the contact point (passes 2 and 3 of the ABA with the factorisation
@@ -168,21 +169,25 @@ struct GradArgs {
 // runs the adjoints of the integrator, the impulse update, both
 // Gauss-Seidel solves (from their recorded sweep vectors), A and b, the
 // unit-impulse responses, the contact geometry and the smooth ABA step.
-// One lane per system, SPL systems to a wave, as in the rollout; R is the
-// arithmetic (FP64 for FP32 I/O: the recompute and the reverse sweeps start
-// from the widened FP32 states, so the gradient is that of the step map
-// along the FP32 trajectory), each lane's Work record in LDS as in the
-// rollout, its sweep record and adjoint arrays in private memory.
+// One lane per system; R is the arithmetic (FP64 for FP32 I/O: the
+// recompute and the reverse sweeps start from the widened FP32 states, so
+// the gradient is that of the step map along the FP32 trajectory).  Unlike
+// the rollout, every record (Work, the sweep record, the adjoint arrays)
+// stays in private memory: in FP64 the Work records alone would hold the LDS
+// to 8 systems per CU, two rounds of 4096 systems, and having all systems in
+// flight at once pays more than LDS latency.  16 systems share a wave, so a
+// private-memory access of the 16 lanes is one 128-byte line of FP64 values.
+// Measured on the landing quadrupeds (4096 x 200 steps, FP64 reverse): Work
+// in LDS, 8 per wave, 1581 ms; private, 8 per wave 1353, 16 per wave 964,
+// 32 per wave 993 ms.
 template <typename R> struct AdjSpw;
-template <> struct AdjSpw<float> { static constexpr int v = 16, spl = 8; };
-template <> struct AdjSpw<double> { static constexpr int v = 8, spl = 8; };
+template <> struct AdjSpw<float> { static constexpr int v = 16, spl = 16; };
+template <> struct AdjSpw<double> { static constexpr int v = 16, spl = 16; };
 
 template <typename S, typename R>
 __global__ __launch_bounds__(kWave * AdjSpw<R>::v / AdjSpw<R>::spl) void k_contact_adj(GradArgs<S> a) {
   constexpr int SPW = AdjSpw<R>::v, SPL = AdjSpw<R>::spl;
-  static_assert(SPW * sizeof(Work<R>) <= 160 * 1024, "LDS budget");
   static_assert(SPW % SPL == 0 && SPL <= kWave, "whole waves");
-  __shared__ Work<R> wsh[SPW];
   const int ln = threadIdx.x % kWave;
   const int sw = (threadIdx.x / kWave) * SPL + ln;
   const int s = blockIdx.x * SPW + sw;
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(kWave * AdjSpw<R>::v / AdjSpw<R>::spl) void k_conta
   for (int k = 0; k < nq; ++k) xb[k] = R(a.gqT[k * B + s]);
   for (int k = 0; k < nv; ++k) xb[nq + k] = R(a.gqdT[k * B + s]);
   R mub = R(0);
-  Work<R>& w = wsh[sw];
+  Work<R> w;
   for (int t = a.T - 1; t >= 0; --t) {
     for (int k = 0; k < nx; ++k) x[k] = R(a.traj[((size_t)t * nx + k) * B + s]);
     for (int k = 0; k < nu; ++k) u[k] = R(a.tau[((size_t)t * nu + k) * B + s]);
