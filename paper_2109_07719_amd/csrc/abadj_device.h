@@ -1291,7 +1291,10 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
   const int wid = (threadIdx.x / kWave) & 1;
   R* const base = reinterpret_cast<R*>(abadj_lds + pair * pipe_lds_per_pair<S, R, FREE, FR, CHAIN>());
   R* const xb = CHAIN ? nullptr : base + wid * (XB * kWave);
-  R* const tbuf[2] = {base + (CHAIN ? 0 : 2 * XB * kWave), base + (CHAIN ? 0 : 2 * XB * kWave) + TW * kWave};
+  // the two tape buffers: tape(k) = tbuf0 + (k & 1) * TW * kWave.  Offsets
+  // from the LDS base (not a pointer picked from an array) keep the accesses
+  // ds_* instructions rather than flat ones.
+  R* const tbuf0 = base + (CHAIN ? 0 : 2 * XB * kWave);
   const int wb = blockIdx.x * (blockDim.x / (2 * kWave)) + pair;
   const Lane l = load_lane(A.P, wb);
   const int maxd = A.P.wmaxd[wb];
@@ -1322,7 +1325,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
         Step<R> o;
         aba_wave<R, FREE, CHAIN, BALL>(widen<R>(gravity(A.P)), l, LR, st, limit_tau<FR>(A.P, l, st, tau), maxd, xb,
                                        o);
-        R* tb = tbuf[k & 1];
+        R* tb = tbuf0 + (size_t)(k & 1) * (TW * kWave);
 #pragma unroll
         for (int j = 0; j < (FREE ? 7 : 1); ++j) tb[(size_t)j * kWave + l.lane] = st.q[j];
 #pragma unroll
@@ -1339,7 +1342,7 @@ __global__ __launch_bounds__(2 * kWave * kMaxPairsPerBlock) void k_backward_pipe
     for (int k = 0; k <= A.T; ++k) {
       if (k >= 1) {
         const int t = A.T - k;
-        const R* tb = tbuf[(k - 1) & 1];
+        const R* tb = tbuf0 + (size_t)((k - 1) & 1) * (TW * kWave);
         State<R, FREE> st;
 #pragma unroll
         for (int j = 0; j < (FREE ? 7 : 1); ++j) st.q[j] = tb[(size_t)j * kWave + l.lane];

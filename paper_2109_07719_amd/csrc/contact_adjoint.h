@@ -322,6 +322,79 @@ ABA_HD void id_vjp(const CTopo& tp, const Par<R>& P, const Work<S>& w, const S* 
   }
 }
 
+// The q-adjoint of <wv, M(q) acc>: id_vjp at zero velocity without gravity,
+// where every velocity-product and gravity term of the recursive
+// Newton-Euler statements vanishes, written without them (A = X A_parent +
+// S acc, F = I A, F_parent += X^T F, and the reverse of those).  The free
+// root's row is body-frame, so M does not depend on its pose.
+template <typename S, typename R>
+ABA_HD void id_vjp_static(const CTopo& tp, const Par<R>& P, const Work<S>& w, const S* acc, const S* wv, S* gq) {
+  const int n = tp.n;
+  S A[kNL][6], F[kNL][6], Ap[kNL][6];
+  for (int i = 0; i < n; ++i) {
+    const int p = tp.parent[i];
+    if (tp.jtype[i] == SIM_JOINT_FREE) {
+      for (int k = 0; k < 6; ++k) {
+        A[i][k] = acc[tp.vi[i] + k];
+        Ap[i][k] = S(0);
+      }
+    } else {
+      S s6[6];
+      scol(tp.jtype[i] == SIM_JOINT_PRISMATIC, w.ax[i], s6);
+      if (p < 0) {
+        for (int k = 0; k < 6; ++k) Ap[i][k] = S(0);
+      } else {
+        x_motion(w.E[i], w.r[i], A[p], Ap[i]);
+      }
+      for (int k = 0; k < 6; ++k) A[i][k] = Ap[i][k] + s6[k] * acc[tp.vi[i]];
+    }
+    inertia_apply(P, i, A[i], F[i]);
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    const int p = tp.parent[i];
+    if (p >= 0) {
+      S f[6];
+      xt_force(w.E[i], w.r[i], F[i], f);
+      for (int k = 0; k < 6; ++k) F[p][k] = F[p][k] + f[k];
+    }
+  }
+  // reverse: force adjoints root -> leaves (F[p] += X^T F[i]); A is reused
+  // for them
+  S (&Fb)[kNL][6] = A;
+  for (int i = 0; i < n; ++i) {
+    const int p = tp.parent[i];
+    if (tp.jtype[i] == SIM_JOINT_FREE) {
+      for (int k = 0; k < 6; ++k) Fb[i][k] = wv[tp.vi[i] + k];
+    } else {
+      const bool pr = tp.jtype[i] == SIM_JOINT_PRISMATIC;
+      S s6[6];
+      scol(pr, w.ax[i], s6);
+      for (int k = 0; k < 6; ++k) Fb[i][k] = s6[k] * wv[tp.vi[i]];
+      if (p >= 0) {
+        S y[6];
+        x_motion(w.E[i], w.r[i], Fb[p], y);
+        gq[tp.qi[i]] = gq[tp.qi[i]] + spair(pr, w.ax[i], F[i], y);
+        for (int k = 0; k < 6; ++k) Fb[i][k] = Fb[i][k] + y[k];
+      }
+    }
+  }
+  // F = I A: A_bar = I F_bar (in place; F is no longer needed)
+  S (&Ab)[kNL][6] = F;
+  for (int i = 0; i < n; ++i) inertia_apply(P, i, Fb[i], Ab[i]);
+  // reverse of A = X A_parent + S acc, leaves -> root
+  for (int i = n - 1; i >= 0; --i) {
+    if (tp.jtype[i] == SIM_JOINT_FREE) continue;
+    const int p = tp.parent[i];
+    const bool pr = tp.jtype[i] == SIM_JOINT_PRISMATIC;
+    gq[tp.qi[i]] = gq[tp.qi[i]] + spair(pr, w.ax[i], Ab[i], Ap[i]);
+    if (p >= 0) {
+      S f[6];
+      xt_force(w.E[i], w.r[i], Ab[i], f);
+      for (int k = 0; k < 6; ++k) Ab[p][k] = Ab[p][k] + f[k];
+    }
+  }
+}
+
 // One reversed projected Gauss-Seidel solve on the rows idx[0..m) of A
 // (leading dimension r): from xb (adjoint of the result, [m], consumed) and
 // the stored sweep vectors (stride ld), adds the adjoints of A, b (full
@@ -503,7 +576,7 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
       for (int k = 0; k < nv; ++k) ad.Jb[j][k] = ad.Jb[j][k] + Wj[k];
       S gqj[kNQ];
       for (int k = 0; k < nq; ++k) gqj[k] = S(0);
-      id_vjp(tp, P, w, q, (const S*)nullptr, mj, false, Wj, gqj, (S*)nullptr);
+      id_vjp_static(tp, P, w, mj, Wj, gqj);
       for (int k = 0; k < nq; ++k) qb[k] = qb[k] - gqj[k];
     }
     // ---- contact rows and gaps through the world poses

@@ -11,7 +11,7 @@ for the quadruped).
 
 Conventions shared with the rest of the package:
   * per link: parent index local to the system (-1 = fixed base / none),
-    joint type (0 revolute, 1 free, 2 prismatic; free only at local index 0), fixed
+    joint type (0 revolute, 1 free, 2 prismatic, 3 spherical; free only at local index 0), fixed
     rotation E_T (3x3, parent -> joint frame), joint origin r_T in parent
     coordinates, unit joint axis, mass, centre of mass, rotational inertia
     about the COM as (xx, yy, zz, xy, xz, yz);
