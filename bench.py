@@ -932,7 +932,13 @@ def main():
     # FP64 from the FP32 tape)
     adj32 = None
     if not args.no_fp32_adjoint:
+        # the launch geometry is tuned for the FP64 reverse passes; the FP32
+        # ones get their own tuning (two producer/consumer pairs per
+        # workgroup matter there), and the FP64 choice is restored after
+        tiling64 = sim.tiling
         sim.set_adjoint_dtype(torch.float32)
+        if args.tiling == "auto":
+            sim.autotune(K)
         g32 = [torch.empty_like(x) for x in (gq0, gqd0, gtau)]
         graphs["fwd"].replay()
         sim.backward(tau, dt, K, ws, gqT, gqdT, out=tuple(g32))
@@ -949,8 +955,9 @@ def main():
         adj32 = {"kernel_ms": b32_ms,
                  "fwd_adjoint_dof_steps_per_s": b.total_dof * T / ((float(np.mean(fwd_ms)) + b32_ms) * 1e-3),
                  "achieved_tflops": sim.flops(2) * T / (b32_ms * 1e-3) / 1e12,
-                 "grads": [x.cpu().numpy() for x in g32]}
+                 "tiling": sim.tiling, "grads": [x.cpu().numpy() for x in g32]}
         sim.set_adjoint_dtype(torch.float64)
+        sim.set_tiling(**tiling64)
         del gb32
     # leave the graphs' gradient buffers as the plain adjoint wrote them
     graphs["bwd"].replay()
