@@ -424,6 +424,17 @@ def contact_bench(args, torch, dev):
     tau = f(np.stack([d[3] for d in draws], axis=2))
     gqT = torch.ones_like(q0)
     gqdT = torch.ones_like(qd0)
+    # launch geometry (systems per wave of both kernels), tuned on 50 probe
+    # steps from the middle of an untimed rollout, where the feet are on the
+    # ground (the first ~30 steps are free fall, much cheaper per step)
+    tune = None
+    if args.tiling == "auto" and T > 0:
+        _, _, tr = cb.rollout(q0, qd0, tau, dt)
+        t0 = T // 2
+        x0 = tr[t0].contiguous()
+        tune = cb.autotune(x0[:cb.nq].contiguous(), x0[cb.nq:].contiguous(), tau[t0:t0 + 50].contiguous(), dt)
+        tune["probe"] = f"steps {t0}..{min(T, t0 + 50)} of an untimed rollout"
+        del tr
     for _ in range(max(args.warmup, 1)):
         qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, dt, counts=True)
         g = cb.grad(tr, tau, dt, gqT, gqdT)
@@ -520,7 +531,7 @@ def contact_bench(args, torch, dev):
            "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
            "config": {"workload": f"{B} landing quadrupeds (18 DOF, contact spheres on 4 feet), T={T}, dt=1e-3, "
                                   f"PGS {niter} sweeps x 2 solves, mu {mu}, beta {beta}",
-                      "batch": B, "T": T},
+                      "batch": B, "T": T, "tiling": cb.tiling, "autotune": tune},
            "rollout_ms": fwd, "gradient_ms": grd,
            "active_contacts_per_step": {str(k): int(v) for k, v in enumerate(np.bincount(ncn.reshape(-1), minlength=5))},
            # the gradient kernel recomputes and reverses every step in FP64 (both dtypes)

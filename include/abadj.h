@@ -462,6 +462,18 @@ int sim_pgs_adjoint(int dtype, int batch, int n, int niter, const void *A, const
 #define SIM_CONTACT_MAX_LINKS 16
 #define SIM_CONTACT_MAX_SPHERES 4
 
+/* Launch geometry of the contact kernels.  Every system is one lane; this
+ * chooses how many share a wavefront: rollout_systems_per_wave in {8, 4, 2}
+ * (two wavefronts per workgroup in FP32, one in FP64; each system's
+ * articulated quantities sit in LDS), grad_systems_per_wave in {16, 8, 4}
+ * (one wavefront per workgroup).  Fewer per wavefront spread a small batch
+ * over more CUs.  Every geometry computes the same results bit for bit;
+ * sim_contact_autotune picks the fastest for a batch. */
+typedef struct {
+  int rollout_systems_per_wave;
+  int grad_systems_per_wave;
+} sim_contact_tiling_t;
+
 typedef struct {
   int n;
   const int *parent;
@@ -471,6 +483,7 @@ typedef struct {
   double mu, beta;
   int niter;
   double gravity[3];
+  const sim_contact_tiling_t *tiling; /* nullable: 8 and 16 systems per wavefront */
 } sim_contact_model;
 
 /* Sizes of the model's state, control and parameter vectors (each output
@@ -480,8 +493,8 @@ int sim_contact_param_count(const sim_contact_model *m, int *nq, int *nv, int *n
 /* Algorithmic floating-point operations of one step with contact at the
  * state (q, qd) under tau (HOST double arrays of one system; params [nparams]
  * in the order above): step_flops for the plain step, grad_flops for one
- * reverse step of sim_contact_rollout_grad (nq + nv + nu dual-number steps
- * and their dot products).  Counted on the host by running the step's
+ * reverse step of sim_contact_rollout_grad (the step's recompute and its
+ * reverse statements).  Counted on the host by running the step's
  * statements with a counting scalar that keeps its value, so detection,
  * dropped rows and clamps decide as on the device; every +, -, *, /, sqrt,
  * sin and cos counts 1. */
@@ -504,10 +517,29 @@ int sim_contact_rollout(const sim_contact_model *m, int dtype, int batch, const 
  * taken).  Writes gq0 [nq][batch], gqd0 [nv][batch], gtau [T][nu][batch]
  * and, when gmu (DEVICE [batch]) is not NULL, dL/dmu of every system (the
  * friction coefficient as a model parameter, Sec. 4.1 "other parameters").
- * Needs nq + nv + nu <= 63. */
+ * Each reverse step recomputes the step from its stored state and runs its
+ * statements backwards (Sec. 4.1 "Collision resolution", App. C): the
+ * integrator, the impulse, both Gauss-Seidel solves from their recorded
+ * sweeps, A and b, M^-1 J^T, the contact geometry, the smooth ABA step.
+ * At most 64 PGS sweeps (niter) are recorded. */
 int sim_contact_rollout_grad(const sim_contact_model *m, int dtype, int batch, const void *params, const void *traj,
                              const void *tau, double dt, int T, const void *gqT, const void *gqdT, void *gq0,
                              void *gqd0, void *gtau, void *gmu, void *stream);
+
+/* Launch-geometry autotuner for the contact kernels: times T_probe steps of
+ * sim_contact_rollout from (q0, qd0) under tau (DEVICE [T_probe][nu][batch])
+ * and their sim_contact_rollout_grad at every geometry of
+ * sim_contact_tiling_t, on the caller's model, parameters and batch, and
+ * writes the fastest of each to *chosen (m->tiling is ignored) and their
+ * ms per probe step (nullable).  The probe should start from a state like
+ * the ones the calls will see: a step in contact costs several times one in
+ * free flight.  A set-up call, unlike the others: it
+ * allocates its probe buffers with hipMalloc, frees them, and synchronises
+ * `stream`.  Errors as for the rollout, SIM_ERR_HIP when the probe buffers
+ * cannot be allocated. */
+int sim_contact_autotune(const sim_contact_model *m, int dtype, int batch, const void *params, const void *q0,
+                         const void *qd0, const void *tau, double dt, int T_probe, void *stream,
+                         sim_contact_tiling_t *chosen, double *rollout_ms, double *grad_ms);
 
 #ifdef __cplusplus
 }

@@ -31,7 +31,8 @@ EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_set_adjoint_dtype"
             "sim_checkpoint_schedule", "sim_forward", "sim_forward_jvp",
             "sim_backward", "sim_backward_noalloc", "sim_aba", "sim_flops", "sim_last_error",
             "sim_pgs_workspace_bytes", "sim_pgs_solve", "sim_pgs_adjoint",
-            "sim_contact_param_count", "sim_contact_flops", "sim_contact_rollout", "sim_contact_rollout_grad")
+            "sim_contact_param_count", "sim_contact_flops", "sim_contact_rollout", "sim_contact_rollout_grad",
+            "sim_contact_autotune")
 SIM_PGS_MAX_ROWS = 16
 
 
@@ -123,6 +124,8 @@ def lib():
         L.sim_contact_rollout.restype = I
         L.sim_contact_rollout_grad.argtypes = [P, I, I, P, P, P, D, I, P, P, P, P, P, P, P]
         L.sim_contact_rollout_grad.restype = I
+        L.sim_contact_autotune.argtypes = [P, I, I, P, P, P, P, D, I, P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
+        L.sim_contact_autotune.restype = I
         L.sim_last_error.argtypes = []
         L.sim_last_error.restype = ctypes.c_char_p
         _lib = L

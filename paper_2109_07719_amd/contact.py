@@ -21,10 +21,15 @@ from . import _native as N
 _DT = {torch.float32: N.SIM_F32, torch.float64: N.SIM_F64}
 
 
+class _Tiling(ctypes.Structure):
+    _fields_ = [("rollout_systems_per_wave", ctypes.c_int), ("grad_systems_per_wave", ctypes.c_int)]
+
+
 class _Model(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("parent", ctypes.c_void_p), ("jtype", ctypes.c_void_p),
                 ("ncontacts", ctypes.c_int), ("contact_link", ctypes.c_void_p), ("mu", ctypes.c_double),
-                ("beta", ctypes.c_double), ("niter", ctypes.c_int), ("gravity", ctypes.c_double * 3)]
+                ("beta", ctypes.c_double), ("niter", ctypes.c_int), ("gravity", ctypes.c_double * 3),
+                ("tiling", ctypes.c_void_p)]
 
 
 def pack_params(system, centers, radii) -> np.ndarray:
@@ -57,9 +62,11 @@ class ContactBatch:
         self.parent = np.ascontiguousarray(s0.parent, dtype=np.int32)
         self.jtype = np.ascontiguousarray(s0.jtype, dtype=np.int32)
         self.clink = np.ascontiguousarray(np.asarray(contact_link, dtype=np.int32).reshape(-1))
+        # launch geometry (sim_contact_tiling_t), kept alive with the model that points at it
+        self._tiling = _Tiling(8, 16)
         self.m = _Model(int(s0.n), self.parent.ctypes.data, self.jtype.ctypes.data, int(self.clink.size),
                         self.clink.ctypes.data if self.clink.size else None, float(mu), float(beta), int(niter),
-                        (ctypes.c_double * 3)(*[float(g) for g in gravity]))
+                        (ctypes.c_double * 3)(*[float(g) for g in gravity]), ctypes.addressof(self._tiling))
         nq, nv, nu, npar = (ctypes.c_int() for _ in range(4))
         N.check(N.lib().sim_contact_param_count(ctypes.byref(self.m), ctypes.byref(nq), ctypes.byref(nv),
                                                 ctypes.byref(nu), ctypes.byref(npar)))
@@ -69,6 +76,34 @@ class ContactBatch:
         self.B = len(systems)
         self.dtype = dtype
         self.P = torch.tensor(P, dtype=dtype, device=device)
+
+    @property
+    def tiling(self) -> dict:
+        """Systems per wavefront of the rollout and of the gradient kernels."""
+        return {"rollout_systems_per_wave": self._tiling.rollout_systems_per_wave,
+                "grad_systems_per_wave": self._tiling.grad_systems_per_wave}
+
+    def set_tiling(self, rollout_systems_per_wave: int = 8, grad_systems_per_wave: int = 16) -> None:
+        """Launch geometry of the next calls (rollout: 8, 4 or 2; gradient: 16,
+        8 or 4; the library rejects other values at the call)."""
+        self._tiling.rollout_systems_per_wave = int(rollout_systems_per_wave)
+        self._tiling.grad_systems_per_wave = int(grad_systems_per_wave)
+
+    def autotune(self, q0, qd0, tau, dt) -> dict:
+        """Times T = tau.shape[0] probe steps of the rollout and its gradient at
+        every launch geometry (sim_contact_autotune), keeps the fastest and
+        returns it with the ms per probe step of each kernel."""
+        T = int(tau.shape[0])
+        self._check(q0, (self.nq, self.B), "q0")
+        self._check(qd0, (self.nv, self.B), "qd0")
+        self._check(tau, (T, self.nu, self.B), "tau")
+        chosen, rms, gms = _Tiling(), ctypes.c_double(), ctypes.c_double()
+        N.check(N.lib().sim_contact_autotune(ctypes.byref(self.m), _DT[self.dtype], self.B, _ptr(self.P), _ptr(q0),
+                                             _ptr(qd0), _ptr(tau), float(dt), T,
+                                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                             ctypes.byref(chosen), ctypes.byref(rms), ctypes.byref(gms)))
+        self.set_tiling(chosen.rollout_systems_per_wave, chosen.grad_systems_per_wave)
+        return dict(self.tiling, rollout_ms_per_probe_step=rms.value, grad_ms_per_probe_step=gms.value)
 
     def _check(self, t, shape, name):
         if t.dtype != self.dtype or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):

@@ -109,14 +109,17 @@ struct RollArgs {
 // request, for one lane's work.  On the landing quadrupeds (4096 x 200
 // steps) the rollout took 141, 134, 114, 110 and about 156 ms at 1, 2, 4, 8
 // and 16 systems per wave, the FP64 reverse 4560 (scaled from 1000 steps),
-// 2173, 1858 and 1578 ms at 1, 2, 4 and 8.
-template <typename R> struct RollSpw;
-template <> struct RollSpw<float> { static constexpr int v = 16, spl = 8; };
-template <> struct RollSpw<double> { static constexpr int v = 8, spl = 8; };
-
+// 2173, 1858 and 1578 ms at 1, 2, 4 and 8.  Fewer systems per wave spread a
+// small batch over more CUs, so SPL is a launch choice (sim_contact_tiling_t,
+// sim_contact_autotune): 8 (the default), 4 or 2 systems per wave, two waves
+// per workgroup in FP32 and one in FP64, whose Work records are twice as
+// large.
 template <typename R>
-__global__ __launch_bounds__(kWave * RollSpw<R>::v / RollSpw<R>::spl) void k_contact_rollout(RollArgs<R> a) {
-  constexpr int SPW = RollSpw<R>::v, SPL = RollSpw<R>::spl;
+constexpr int roll_spw(int spl) { return sizeof(R) == 4 ? 2 * spl : spl; }
+
+template <typename R, int SPL>
+__global__ __launch_bounds__(kWave * roll_spw<R>(SPL) / SPL) void k_contact_rollout(RollArgs<R> a) {
+  constexpr int SPW = roll_spw<R>(SPL);
   static_assert(SPW * sizeof(Work<R>) <= 160 * 1024, "LDS budget");
   static_assert(SPW % SPL == 0 && SPL <= kWave, "whole waves");
   static_assert((sizeof(Work<R>) / sizeof(R)) % 2 == 1, "odd Work stride");
@@ -175,19 +178,16 @@ struct GradArgs {
 // the rollout, every record (Work, the sweep record, the adjoint arrays)
 // stays in private memory: in FP64 the Work records alone would hold the LDS
 // to 8 systems per CU, two rounds of 4096 systems, and having all systems in
-// flight at once pays more than LDS latency.  16 systems share a wave, so a
-// private-memory access of the 16 lanes is one 128-byte line of FP64 values.
+// flight at once pays more than LDS latency.
 // Measured on the landing quadrupeds (4096 x 200 steps, FP64 reverse): Work
 // in LDS, 8 per wave, 1581 ms; private, 8 per wave 1353, 16 per wave 964,
 // 32 per wave 993 ms.
-template <typename R> struct AdjSpw;
-template <> struct AdjSpw<float> { static constexpr int v = 16, spl = 16; };
-template <> struct AdjSpw<double> { static constexpr int v = 16, spl = 16; };
-
-template <typename S, typename R>
-__global__ __launch_bounds__(kWave * AdjSpw<R>::v / AdjSpw<R>::spl) void k_contact_adj(GradArgs<S> a) {
-  constexpr int SPW = AdjSpw<R>::v, SPL = AdjSpw<R>::spl;
-  static_assert(SPW % SPL == 0 && SPL <= kWave, "whole waves");
+// SPL is a launch choice here too (16, the default, 8 or 4 systems per wave,
+// one wave per workgroup): a smaller batch reaches more CUs with fewer.
+template <typename S, typename R, int SPL>
+__global__ __launch_bounds__(kWave) void k_contact_adj(GradArgs<S> a) {
+  constexpr int SPW = SPL;
+  static_assert(SPL <= kWave, "one wave per workgroup");
   const int ln = threadIdx.x % kWave;
   const int sw = (threadIdx.x / kWave) * SPL + ln;
   const int s = blockIdx.x * SPW + sw;
@@ -220,6 +220,34 @@ __global__ __launch_bounds__(kWave * AdjSpw<R>::v / AdjSpw<R>::spl) void k_conta
 
 int cfail(int code, const std::string& msg) { return aba::report_error(code, msg); }
 
+// The launch geometry the model asks for (m->tiling, NULL = the defaults).
+constexpr int kRollSplDefault = 8, kGradSplDefault = 16;
+bool roll_spl_ok(int spl) { return spl == 8 || spl == 4 || spl == 2; }
+bool grad_spl_ok(int spl) { return spl == 16 || spl == 8 || spl == 4; }
+
+template <typename R>
+hipError_t launch_rollout(const RollArgs<R>& a, int spl, hipStream_t st) {
+  const int spw = roll_spw<R>(spl);
+  const dim3 grid((a.B + spw - 1) / spw), block(kWave * (spw / spl));
+  switch (spl) {
+    case 8: hipLaunchKernelGGL((k_contact_rollout<R, 8>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_contact_rollout<R, 4>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_contact_rollout<R, 2>), grid, block, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+template <typename S>
+hipError_t launch_grad(const GradArgs<S>& a, int spl, hipStream_t st) {
+  // both dtypes reverse in FP64
+  const dim3 grid((a.B + spl - 1) / spl), block(kWave);
+  switch (spl) {
+    case 16: hipLaunchKernelGGL((k_contact_adj<S, double, 16>), grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_contact_adj<S, double, 8>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_contact_adj<S, double, 4>), grid, block, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
 int make_topo(const char* who, const sim_contact_model* m, CTopo* tp) {
   if (!m || !m->parent || !m->jtype || (m->ncontacts > 0 && !m->contact_link))
     return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": null model argument");
@@ -229,6 +257,10 @@ int make_topo(const char* who, const sim_contact_model* m, CTopo* tp) {
     return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": need 0 <= ncontacts <= " + std::to_string(kNC));
   if (m->niter < 0 || !(m->mu >= 0) || !(m->beta >= 0))
     return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": need niter >= 0, mu >= 0, beta >= 0");
+  if (m->tiling && (!roll_spl_ok(m->tiling->rollout_systems_per_wave) ||
+                    !grad_spl_ok(m->tiling->grad_systems_per_wave)))
+    return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": tiling needs rollout_systems_per_wave in {8, 4, 2} "
+                                                         "and grad_systems_per_wave in {16, 8, 4}");
   *tp = CTopo{};
   tp->n = m->n;
   tp->nc = m->ncontacts;
@@ -335,20 +367,17 @@ int sim_contact_rollout(const sim_contact_model* m, int dtype, int batch, const 
   if (batch == 0) return SIM_OK;
   if (!params || !q0 || !qd0 || !qT || !qdT || (T > 0 && tp.nu > 0 && !tau))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout: null array argument");
-  const int spw = dtype == SIM_F64 ? RollSpw<double>::v : RollSpw<float>::v;
-  const int spl = dtype == SIM_F64 ? RollSpw<double>::spl : RollSpw<float>::spl;
-  const dim3 grid((batch + spw - 1) / spw), block(kWave * (spw / spl));
+  const int spl = m->tiling ? m->tiling->rollout_systems_per_wave : kRollSplDefault;
   hipError_t e;
   if (dtype == SIM_F64) {
     RollArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)q0, (const double*)qd0,
                        (const double*)tau, (double*)traj, (double*)qT, (double*)qdT, ncontacts};
-    hipLaunchKernelGGL(k_contact_rollout<double>, grid, block, 0, (hipStream_t)stream, a);
+    e = launch_rollout(a, spl, (hipStream_t)stream);
   } else {
     RollArgs<float> a{tp, batch, T, (float)dt, (const float*)params, (const float*)q0, (const float*)qd0,
                       (const float*)tau, (float*)traj, (float*)qT, (float*)qdT, ncontacts};
-    hipLaunchKernelGGL(k_contact_rollout<float>, grid, block, 0, (hipStream_t)stream, a);
+    e = launch_rollout(a, spl, (hipStream_t)stream);
   }
-  e = hipGetLastError();
   if (e != hipSuccess) return cfail(SIM_ERR_HIP, std::string("sim_contact_rollout: launch failed: ") + hipGetErrorString(e));
   return SIM_OK;
 }
@@ -370,22 +399,108 @@ int sim_contact_rollout_grad(const sim_contact_model* m, int dtype, int batch, c
   if (batch == 0) return SIM_OK;
   if (!params || !traj || !gqT || !gqdT || !gq0 || !gqd0 || (T > 0 && tp.nu > 0 && (!tau || !gtau)))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: null array argument");
-  const int spw = AdjSpw<double>::v, spl = AdjSpw<double>::spl;  // both dtypes reverse in FP64
-  const dim3 grid((batch + spw - 1) / spw), block(kWave * (spw / spl));
+  const int spl = m->tiling ? m->tiling->grad_systems_per_wave : kGradSplDefault;
+  hipError_t e;
   if (dtype == SIM_F64) {
     GradArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)traj, (const double*)tau,
                        (const double*)gqT, (const double*)gqdT, (double*)gq0, (double*)gqd0, (double*)gtau,
                        (double*)gmu};
-    hipLaunchKernelGGL((k_contact_adj<double, double>), grid, block, 0, (hipStream_t)stream, a);
+    e = launch_grad(a, spl, (hipStream_t)stream);
   } else {
     GradArgs<float> a{tp, batch, T, (float)dt, (const float*)params, (const float*)traj, (const float*)tau,
                       (const float*)gqT, (const float*)gqdT, (float*)gq0, (float*)gqd0, (float*)gtau,
                       (float*)gmu};
-    hipLaunchKernelGGL((k_contact_adj<float, double>), grid, block, 0, (hipStream_t)stream, a);
+    e = launch_grad(a, spl, (hipStream_t)stream);
   }
-  const hipError_t e = hipGetLastError();
   if (e != hipSuccess)
     return cfail(SIM_ERR_HIP, std::string("sim_contact_rollout_grad: launch failed: ") + hipGetErrorString(e));
+  return SIM_OK;
+}
+
+int sim_contact_autotune(const sim_contact_model* m, int dtype, int batch, const void* params, const void* q0,
+                         const void* qd0, const void* tau, double dt, int T_probe, void* stream,
+                         sim_contact_tiling_t* chosen, double* rollout_ms, double* grad_ms) {
+  aba::clear_error();
+  CTopo tp;
+  int rc = make_topo("sim_contact_autotune", m, &tp);
+  if (rc) return rc;
+  if (dtype != SIM_F32 && dtype != SIM_F64)
+    return cfail(SIM_ERR_UNSUPPORTED_DTYPE, "sim_contact_autotune: dtype must be SIM_F32 or SIM_F64");
+  if (batch < 1 || T_probe < 1 || !(dt > 0))
+    return cfail(SIM_ERR_INVALID_ARG, "sim_contact_autotune: need batch >= 1, T_probe >= 1, dt > 0");
+  if (m->niter > kSweepMax)
+    return cfail(SIM_ERR_INVALID_ARG, "sim_contact_autotune: at most " + std::to_string(kSweepMax) +
+                                          " PGS sweeps (niter) are recorded for the adjoint");
+  if (!params || !q0 || !qd0 || (tp.nu > 0 && !tau) || !chosen)
+    return cfail(SIM_ERR_INVALID_ARG, "sim_contact_autotune: null argument");
+  const hipStream_t st = (hipStream_t)stream;
+  const size_t es = dtype == SIM_F64 ? sizeof(double) : sizeof(float);
+  const size_t B = (size_t)batch, T = (size_t)T_probe, nq = tp.nq, nv = tp.nv, nu = tp.nu;
+  // probe buffers: traj, qT, qdT, gq0, gqd0, gtau, and the zero seeds gqT, gqdT
+  const size_t n_traj = (T + 1) * (nq + nv) * B, n_tau = T * nu * B;
+  const size_t total = (n_traj + 2 * (nq + nv) * B + n_tau + (nq + nv) * B) * es;
+  char* buf = nullptr;
+  if (hipMalloc(&buf, total) != hipSuccess) return cfail(SIM_ERR_HIP, "sim_contact_autotune: probe allocation failed");
+  char* p = buf;
+  auto take = [&](size_t n) { char* r = p; p += n * es; return r; };
+  void* traj = take(n_traj);
+  void* qT = take(nq * B);
+  void* qdT = take(nv * B);
+  void* gq0 = take(nq * B);
+  void* gqd0 = take(nv * B);
+  void* gtau = take(n_tau);
+  void* gqT = take(nq * B);
+  void* gqdT = take(nv * B);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  sim_contact_model mm = *m;
+  sim_contact_tiling_t t{kRollSplDefault, kGradSplDefault};
+  mm.tiling = &t;
+  int best_r = kRollSplDefault, best_g = kGradSplDefault;
+  float ms_r = 0.f, ms_g = 0.f;
+  rc = SIM_OK;
+  do {
+    if (hipMemsetAsync(gqT, 0, (nq + nv) * B * es, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+      rc = cfail(SIM_ERR_HIP, "sim_contact_autotune: set-up failed");
+      break;
+    }
+    // each geometry runs once untimed, then once between events
+    auto timed = [&](auto&& run, float* ms) -> int {
+      int r = run();
+      if (r) return r;
+      if (hipEventRecord(e0, st) != hipSuccess) return cfail(SIM_ERR_HIP, "sim_contact_autotune: event failed");
+      r = run();
+      if (r) return r;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+        return cfail(SIM_ERR_HIP, "sim_contact_autotune: timing failed");
+      return SIM_OK;
+    };
+    const int rspl[3] = {8, 4, 2}, gspl[3] = {16, 8, 4};
+    for (int k = 0; k < 3 && !rc; ++k) {
+      t.rollout_systems_per_wave = rspl[k];
+      float ms = 0.f;
+      rc = timed([&] { return sim_contact_rollout(&mm, dtype, batch, params, q0, qd0, tau, dt, T_probe, traj, qT, qdT,
+                                                  nullptr, stream); }, &ms);
+      if (!rc && (k == 0 || ms < ms_r)) { ms_r = ms; best_r = rspl[k]; }
+    }
+    for (int k = 0; k < 3 && !rc; ++k) {
+      t.grad_systems_per_wave = gspl[k];
+      float ms = 0.f;
+      rc = timed([&] { return sim_contact_rollout_grad(&mm, dtype, batch, params, traj, tau, dt, T_probe, gqT, gqdT,
+                                                       gq0, gqd0, gtau, nullptr, stream); }, &ms);
+      if (!rc && (k == 0 || ms < ms_g)) { ms_g = ms; best_g = gspl[k]; }
+    }
+  } while (false);
+  (void)hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  if (rc) return rc;
+  chosen->rollout_systems_per_wave = best_r;
+  chosen->grad_systems_per_wave = best_g;
+  if (rollout_ms) *rollout_ms = ms_r / T_probe;
+  if (grad_ms) *grad_ms = ms_g / T_probe;
   return SIM_OK;
 }
 

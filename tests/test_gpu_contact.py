@@ -13,6 +13,8 @@ gradient (Sec. 4.1 "Collision resolution"), through the C ABI
   oracle's gradient along the GPU's own trajectory;
 * edge cases: no contact spheres (the plain step), an empty batch, invalid
   models;
+* every launch geometry (systems per wave) gives the same bits, and the
+  autotuner picks one of them;
 * the benchmark batch (4096 quadrupeds, 1000 steps) on sampled systems:
   steps and the full-horizon gradient along the GPU trajectory.
 """
@@ -241,6 +243,41 @@ def test_edge_cases():
     big, *_ = synth.tree_system(5, 1, nmin=17, nmax=17)
     with pytest.raises(N.SimError):
         ContactBatch([big], [1], [[[0, 0, 0]]], [[0.03]], dtype=torch.float64)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_every_tiling_gives_the_same_bits(dtype):
+    """Each system is one lane whatever the launch geometry, so every
+    systems-per-wave choice of the rollout and of the gradient gives the same
+    trajectories, contact counts and gradients bit for bit; the autotuner
+    returns one of them.  37 systems: a ragged last workgroup at every
+    geometry."""
+    T = 40
+    draws = quad_batch(37, T)
+    print("case tilings", dtype, "B", len(draws), "T", T, flush=True)
+    cb, q0, qd0, tau = _gpu(draws, dtype, T)
+    rng = np.random.default_rng(4)
+    gqT = torch.tensor(rng.normal(size=(cb.nq, cb.B)), dtype=dtype, device=DEV)
+    gqdT = torch.tensor(rng.normal(size=(cb.nv, cb.B)), dtype=dtype, device=DEV)
+    ref = None
+    for rs, gs in ((8, 16), (4, 8), (2, 4), (8, 4), (2, 16)):
+        cb.set_tiling(rs, gs)
+        qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, DT, counts=True)
+        g = cb.grad(tr, tau, DT, gqT, gqdT, mu_grad=True)
+        out = [x.cpu().numpy() for x in (qT, qdT, tr, nc) + tuple(g)]
+        if ref is None:
+            ref = out
+            assert int(out[3].max()) >= 2
+        else:
+            for a, b in zip(out, ref):
+                assert np.array_equal(a, b), (rs, gs)
+    tune = cb.autotune(q0, qd0, tau[:10], DT)
+    print("autotune", tune)
+    assert tune["rollout_systems_per_wave"] in (8, 4, 2) and tune["grad_systems_per_wave"] in (16, 8, 4)
+    assert tune["rollout_ms_per_probe_step"] > 0 and tune["grad_ms_per_probe_step"] > 0
+    assert cb.tiling == {k: tune[k] for k in ("rollout_systems_per_wave", "grad_systems_per_wave")}
+    qT, qdT, tr = cb.rollout(q0, qd0, tau, DT)
+    assert np.array_equal(tr.cpu().numpy(), ref[2])
 
 
 def test_benchmark_batch_sampled():
