@@ -51,14 +51,27 @@ KERNEL_SOURCES = ("csrc/spatial.h", "csrc/aba_lane.h", "csrc/dual.h", "csrc/abad
                   "_build.py")
 
 
-def kernel_source_hash():
-    """Hash of everything that decides the kernels' machine code (device
-    sources and build options)."""
+CONTACT_SOURCES = ("csrc/spatial.h", "csrc/dual.h", "csrc/contact_step.h", "csrc/contact_adjoint.h",
+                   "csrc/contact.hip", "_build.py")
+
+
+def _hash(sources):
     h = hashlib.sha256()
-    for n in KERNEL_SOURCES:
+    for n in sources:
         with open(os.path.join(ROOT, "paper_2109_07719_amd", n), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def kernel_source_hash():
+    """Hash of everything that decides the articulated-body kernels' machine
+    code (their device sources and the build options)."""
+    return _hash(KERNEL_SOURCES)
+
+
+def contact_source_hash():
+    """The same for the kernels with contact inside the step."""
+    return _hash(CONTACT_SOURCES)
 
 
 def traffic_entry(kernel, workload):
