@@ -238,8 +238,17 @@ int sim_set_tiling(sim_t h, const sim_tiling_t *tiling);
  * forward+backward time per probe step.  Arithmetic is unaffected by the
  * choice.  Errors: SIM_ERR_INVALID_ARG (K < -4096, T_probe outside 1..100000),
  * SIM_ERR_HIP (probe allocation or launch failed; the tiling is left as it
- * was). */
+ * was).
+ * Choices are kept per process, keyed by what decides the run time: the
+ * batch's packed structure (every lane's topology fields and joint types,
+ * the wave depths), the kernel variant, the dtype and adjoint dtype, K,
+ * T_probe and the device.  A later call with the same key (another handle
+ * of the same structure, say) applies the kept choice without probing,
+ * allocating or synchronising, and reports the ms_per_step measured then. */
 int sim_autotune(sim_t h, int K, int T_probe, void *stream, sim_tiling_t *chosen, double *ms_per_step);
+
+/* Forgets every choice sim_autotune kept (the next call probes again). */
+void sim_autotune_cache_clear(void);
 
 /* Bytes of workspace needed by sim_forward/sim_backward for T steps with a
  * checkpoint every K >= 1 steps (K > 1 adds a K-state replay buffer); for

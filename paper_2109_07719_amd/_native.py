@@ -26,7 +26,7 @@ SIM_JOINT_SPHERICAL = 3
 SIM_MAX_LINKS = 64
 
 EXPORTED = ("sim_create", "sim_destroy", "sim_get_info", "sim_set_adjoint_dtype", "sim_status", "sim_get_tiling",
-            "sim_set_tiling", "sim_autotune",
+            "sim_set_tiling", "sim_autotune", "sim_autotune_cache_clear",
             "sim_workspace_bytes",
             "sim_checkpoint_schedule", "sim_forward", "sim_forward_jvp",
             "sim_backward", "sim_backward_noalloc", "sim_aba", "sim_flops", "sim_last_error",
@@ -93,6 +93,8 @@ def lib():
         L.sim_status.restype = I
         L.sim_autotune.argtypes = [P, I, I, P, ctypes.POINTER(SimTiling), ctypes.POINTER(D)]
         L.sim_autotune.restype = I
+        L.sim_autotune_cache_clear.argtypes = []
+        L.sim_autotune_cache_clear.restype = None
         L.sim_workspace_bytes.argtypes = [P, I, I, ctypes.POINTER(Z)]
         L.sim_workspace_bytes.restype = I
         L.sim_forward.argtypes = [P, P, P, P, D, I, I, P, P, P, P, Z, P]

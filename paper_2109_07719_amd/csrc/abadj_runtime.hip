@@ -7,9 +7,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -68,6 +70,9 @@ struct sim_handle {
   unsigned long long* d_status = nullptr;  // non-finite outputs written since the last sim_status
   // host-side structure summary for operation counting
   std::vector<int32_t> jtype, parent, nchild;
+  // what decides the kernels' run time (the packed structure, the variant,
+  // the dtype): the autotuner's cache key, with the adjoint dtype and K
+  unsigned long long signature = 0;
 };
 
 namespace {
@@ -567,6 +572,27 @@ int sim_create(const sim_topology* topo, const sim_params* prm, int dtype, sim_t
   h->chain = chain;
   h->tiling = default_tiling(h->nwaves);
   std::vector<int32_t> wmaxd(wave_depth.begin(), wave_depth.end());
+  {
+    // FNV-1a over the structure: every packed integer field except the
+    // caller's link numbering, the wave depths, the variant flags and the dtype
+    unsigned long long x = 1469598103934665603ull;
+    auto mix = [&](long long v) {
+      for (int b = 0; b < 8; ++b) {
+        x ^= (unsigned long long)((v >> (8 * b)) & 0xff);
+        x *= 1099511628211ull;
+      }
+    };
+    mix(dtype);
+    mix(h->nwaves);
+    mix(NS);
+    mix(h->nfree);
+    mix(h->has_free | h->eti << 1 | h->chain << 2 | h->has_prism << 3 | h->has_limits << 4 | h->has_ball << 5);
+    for (int f = 0; f < aba::CI_COUNT; ++f)
+      if (f != aba::CI_LINK)
+        for (int slot = 0; slot < NS; ++slot) mix(ci[(size_t)f * NS + slot]);
+    for (int32_t d : wmaxd) mix(d);
+    h->signature = x;
+  }
   const int rc = (dtype == SIM_F64) ? upload<double>(h, ci, cf, wmaxd) : upload<float>(h, ci, cf, wmaxd);
   if (rc != SIM_OK) {
     release(h);
@@ -971,12 +997,52 @@ int sim_aba(sim_t h, const void* q, const void* qd, const void* tau, void* qdd, 
   return SIM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The autotuner's choices, per process: (signature, adjoint dtype, K,
+// T_probe, device) -> (tiling, ms per probe step).
+struct TuneKey {
+  unsigned long long sig;
+  int adj, K, T, dev;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(sig, adj, K, T, dev) < std::tie(o.sig, o.adj, o.K, o.T, o.dev);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<aba::Tiling, double>> g_tune;
+}  // namespace
+
+extern "C" {
+
+void sim_autotune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
 int sim_autotune(sim_t h, int K, int T_probe, void* stream, sim_tiling_t* chosen, double* ms_per_step) {
   g_err.clear();
   if (!h) return fail(SIM_ERR_INVALID_ARG, "sim_autotune: null handle");
   if (K < -kMaxSnapshots || T_probe < 1 || T_probe > 100000)
     return fail(SIM_ERR_INVALID_ARG, "sim_autotune: need K >= -" + std::to_string(kMaxSnapshots) +
                                          " and 1 <= T_probe <= 100000");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SIM_ERR_HIP, "sim_autotune: no current device");
+  const TuneKey key{h->signature, h->dtype == SIM_F32 ? h->adj_dtype : SIM_F64, K, T_probe, dev};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      h->tiling = it->second.first;
+      if (chosen) {
+        chosen->waves_per_block = h->tiling.waves_per_block;
+        chosen->pairs_per_block = h->tiling.pairs_per_block;
+        chosen->pipelined = h->tiling.pipelined ? 1 : 0;
+      }
+      if (ms_per_step) *ms_per_step = it->second.second;
+      return SIM_OK;
+    }
+  }
   hipStream_t st = (hipStream_t)stream;
   const size_t es = elem(h);
   // store-all probes are capped at 2 GiB of workspace
@@ -1089,6 +1155,10 @@ int sim_autotune(sim_t h, int K, int T_probe, void* stream, sim_tiling_t* chosen
   }
   h->tiling = win;
   cleanup();
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = {win, best / T};
+  }
   if (chosen) {
     chosen->waves_per_block = win.waves_per_block;
     chosen->pairs_per_block = win.pairs_per_block;

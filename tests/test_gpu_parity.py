@@ -532,6 +532,29 @@ def test_autotune_keeps_a_valid_geometry_and_the_results(K):
         sim.autotune(K=1, T_probe=0)
 
 
+def test_autotune_choices_are_kept_per_structure():
+    """A second handle of the same structure gets the first one's choice
+    without probing (the same ms per probe step, bit for bit); another
+    structure, another adjoint dtype or a cleared cache probes again."""
+    from paper_2109_07719_amd import _native as N
+    N.lib().sim_autotune_cache_clear()
+    b = _mixed_batch(40)
+    s1, s2 = _sim(b), _sim(b)
+    t1 = s1.autotune(K=1, T_probe=30)
+    t2 = s2.autotune(K=1, T_probe=30)
+    assert t2 == t1
+    t3 = _sim(b, adj="f32").autotune(K=1, T_probe=30)
+    chains = synth.round_to_f32(synth.make_batch([synth.chain_system(7, 1000 + i, 40) for i in range(6)], 1e-3,
+                                                 name="chains"))
+    t4 = _sim(chains).autotune(K=1, T_probe=30)
+    t5 = s1.autotune(K=5, T_probe=30)
+    assert len({t1["ms_per_probe_step"], t3["ms_per_probe_step"], t4["ms_per_probe_step"],
+                t5["ms_per_probe_step"]}) == 4
+    N.lib().sim_autotune_cache_clear()
+    t6 = s2.autotune(K=1, T_probe=30)
+    assert t6["ms_per_probe_step"] != t1["ms_per_probe_step"]
+
+
 def test_status_counts_nonfinite_outputs():
     b = _mixed_batch(50)
     sim = _sim(b)
