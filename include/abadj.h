@@ -453,7 +453,9 @@ int sim_pgs_adjoint(int dtype, int batch, int n, int niter, const void *A, const
  * Model (host memory, read during the call only): n links in topological
  * order, parent[0] = -1, 0 <= parent[i] < i; jtype SIM_JOINT_REVOLUTE or
  * SIM_JOINT_PRISMATIC, SIM_JOINT_FREE only for link 0; ncontacts spheres on
- * links contact_link[]; gravity (world); mu, beta >= 0; niter >= 0.
+ * links contact_link[]; gravity (world); mu, beta >= 0; niter >= 0; joint
+ * limits (nullable): the limit torque adds to the control of the step's
+ * forward dynamics, with its slopes in the gradient.
  *
  * Per-system parameters (DEVICE, dtype, [nparams][batch], entry k of
  * system s at k * batch + s): per link i at 25 i: E_T (9, row-major, parent
@@ -492,6 +494,9 @@ typedef struct {
   double mu, beta;
   int niter;
   double gravity[3];
+  const double *limits;               /* nullable [4 n]: joint limits (lo, hi, k, d) of the
+                                         1-dof joints, shared by the batch, as in
+                                         sim_params (ignored for the free root) */
   const sim_contact_tiling_t *tiling; /* nullable: 8 and 16 systems per wavefront */
 } sim_contact_model;
 

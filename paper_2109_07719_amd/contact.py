@@ -29,7 +29,7 @@ class _Model(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("parent", ctypes.c_void_p), ("jtype", ctypes.c_void_p),
                 ("ncontacts", ctypes.c_int), ("contact_link", ctypes.c_void_p), ("mu", ctypes.c_double),
                 ("beta", ctypes.c_double), ("niter", ctypes.c_int), ("gravity", ctypes.c_double * 3),
-                ("tiling", ctypes.c_void_p)]
+                ("limits", ctypes.c_void_p), ("tiling", ctypes.c_void_p)]
 
 
 def pack_params(system, centers, radii) -> np.ndarray:
@@ -57,8 +57,13 @@ class ContactBatch:
         for s in systems:
             if not (np.array_equal(s.parent, s0.parent) and np.array_equal(s.jtype, s0.jtype)):
                 raise ValueError("ContactBatch: every system must share the first one's topology")
-        if getattr(s0, "limits", None) is not None:
-            raise ValueError("ContactBatch: joint limits are not supported with contact")
+        # joint limits (lo, hi, k, d per link) are a model constant shared by the batch
+        lim0 = getattr(s0, "limits", None)
+        for s in systems:
+            lim = getattr(s, "limits", None)
+            if (lim is None) != (lim0 is None) or (lim is not None and not np.array_equal(lim, lim0)):
+                raise ValueError("ContactBatch: every system must share the first one's joint limits")
+        self.limits = None if lim0 is None else np.ascontiguousarray(np.asarray(lim0, np.float64).reshape(-1))
         self.parent = np.ascontiguousarray(s0.parent, dtype=np.int32)
         self.jtype = np.ascontiguousarray(s0.jtype, dtype=np.int32)
         self.clink = np.ascontiguousarray(np.asarray(contact_link, dtype=np.int32).reshape(-1))
@@ -66,7 +71,8 @@ class ContactBatch:
         self._tiling = _Tiling(8, 16)
         self.m = _Model(int(s0.n), self.parent.ctypes.data, self.jtype.ctypes.data, int(self.clink.size),
                         self.clink.ctypes.data if self.clink.size else None, float(mu), float(beta), int(niter),
-                        (ctypes.c_double * 3)(*[float(g) for g in gravity]), ctypes.addressof(self._tiling))
+                        (ctypes.c_double * 3)(*[float(g) for g in gravity]),
+                        self.limits.ctypes.data if self.limits is not None else None, ctypes.addressof(self._tiling))
         nq, nv, nu, npar = (ctypes.c_int() for _ in range(4))
         N.check(N.lib().sim_contact_param_count(ctypes.byref(self.m), ctypes.byref(nq), ctypes.byref(nv),
                                                 ctypes.byref(nu), ctypes.byref(npar)))

@@ -197,6 +197,8 @@ __global__ __launch_bounds__(kWave) void k_contact_adj(GradArgs<S> a) {
   for (int k = 0; k < 3; ++k) tp.g[k] = double(S(tp.g[k]));
   tp.mu = double(S(tp.mu));
   tp.beta = double(S(tp.beta));
+  for (int i = 0; i < kNL; ++i)
+    for (int k = 0; k < 4; ++k) tp.lim[i][k] = double(S(tp.lim[i][k]));
   const size_t B = (size_t)a.B;
   const Par<S> P{a.P, B, s};
   const int nq = tp.nq, nv = tp.nv, nu = tp.nu, nx = nq + nv;
@@ -283,6 +285,17 @@ int make_topo(const char* who, const sim_contact_model* m, CTopo* tp) {
     tp->ui[i] = nu;
     if (jt == SIM_JOINT_FREE) { nq += 7; nv += 6; }
     else { nq += 1; nv += 1; nu += 1; }
+  }
+  if (m->limits) {
+    for (int i = 0; i < m->n; ++i) {
+      if (m->jtype[i] == SIM_JOINT_FREE) continue;
+      const double* L = m->limits + 4 * i;
+      if (!(std::isfinite(L[0]) && std::isfinite(L[1]) && std::isfinite(L[2]) && std::isfinite(L[3])) ||
+          !(L[0] <= L[1]) || !(L[2] >= 0) || !(L[3] >= 0))
+        return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": joint limits need finite lo <= hi, k >= 0, d >= 0");
+      for (int k = 0; k < 4; ++k) tp->lim[i][k] = L[k];
+    }
+    tp->has_limits = 1;
   }
   for (int k = 0; k < m->ncontacts; ++k) {
     if (m->contact_link[k] < 0 || m->contact_link[k] >= m->n)

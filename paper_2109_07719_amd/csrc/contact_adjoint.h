@@ -720,6 +720,18 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
   for (int k = 0; k < nq; ++k) gq[k] = S(0);
   for (int k = 0; k < nv; ++k) gqd[k] = S(0);
   id_vjp(tp, P, w, q, qd, rc.qdd, true, taub, gq, gqd);
+  // joint limits: the limit torque tau_l(q, qd) adds to the control, so its
+  // slopes (-k, -d outside the range) carry tau_bar to q and qd
+  if (tp.has_limits)
+    for (int i = 0; i < n; ++i) {
+      if (tp.jtype[i] == SIM_JOINT_FREE) continue;
+      const double* L = tp.lim[i];
+      const S qv = q[tp.qi[i]];
+      if (val(qv) > val(S(L[1])) || val(qv) < val(S(L[0]))) {
+        qb[tp.qi[i]] = qb[tp.qi[i]] - S(L[2]) * taub[tp.vi[i]];
+        qdb[tp.vi[i]] = qdb[tp.vi[i]] - S(L[3]) * taub[tp.vi[i]];
+      }
+    }
   for (int k = 0; k < nq; ++k) xbar[k] = qb[k] - gq[k];
   for (int k = 0; k < nv; ++k) xbar[nq + k] = qdb[k] - gqd[k];
 }

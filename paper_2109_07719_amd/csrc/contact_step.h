@@ -28,6 +28,8 @@ struct CTopo {
   int parent[kNL], jtype[kNL], qi[kNL], vi[kNL], ui[kNL];
   int clink[kNC];
   double mu, beta, g[3];
+  int has_limits;
+  double lim[kNL][4];  // joint limits of the 1-dof joints: lo, hi, stiffness, damping
 };
 
 // ---- scalar helpers (plain and dual) --------------------------------------
@@ -59,6 +61,18 @@ template <> struct Big<float> { static constexpr float v = FLT_MAX; };
 template <> struct Big<double> { static constexpr double v = 1e300; };
 template <typename T> struct RealOf { using type = T; };
 template <typename R> struct RealOf<Dual<R>> { using type = R; };
+
+// Joint-limit torque of a 1-dof joint: outside [lo, hi] a one-sided spring
+// and damper, -k (q - hi) - d qd above, -k (q - lo) - d qd below; zero
+// inside.  The side is decided on the value of q against the limits as the
+// scalar type holds them.
+template <typename S>
+ABA_HD S limit_torque(const CTopo& tp, int i, const S& q, const S& qd) {
+  const double* L = tp.lim[i];
+  if (val(q) > val(S(L[1]))) return -(S(L[2]) * (q - S(L[1]))) - S(L[3]) * qd;
+  if (val(q) < val(S(L[0]))) return -(S(L[2]) * (q - S(L[0]))) - S(L[3]) * qd;
+  return S(0);
+}
 
 // ---- 3-vector and spatial helpers (motion [w; v], force [n; f]) ------------
 
@@ -324,7 +338,9 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       w.U[i][r_] = w.IA[i][6 * r_ + off] * a[0] + w.IA[i][6 * r_ + off + 1] * a[1] + w.IA[i][6 * r_ + off + 2] * a[2];
     const S D = w.U[i][off] * a[0] + w.U[i][off + 1] * a[1] + w.U[i][off + 2] * a[2];
     w.Dinv[i] = S(1) / D;
-    w.u[i] = u[tp.ui[i]] - (w.pA[i][off] * a[0] + w.pA[i][off + 1] * a[1] + w.pA[i][off + 2] * a[2]);
+    S ui = u[tp.ui[i]];
+    if (tp.has_limits) ui = ui + limit_torque(tp, i, q[tp.qi[i]], qd[tp.vi[i]]);
+    w.u[i] = ui - (w.pA[i][off] * a[0] + w.pA[i][off + 1] * a[1] + w.pA[i][off + 2] * a[2]);
     const int p = tp.parent[i];
     if (p >= 0) {
       S Ia[36];

@@ -13,8 +13,13 @@ using aba::Dual;
 namespace {
 
 CTopo topo(int n, const int* parent, const int* jtype, int nc, const int* clink, double mu, double beta, int niter,
-           const double* g) {
+           const double* g, const double* limits) {
   CTopo tp{};
+  if (limits) {
+    tp.has_limits = 1;
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < 4; ++k) tp.lim[i][k] = limits[4 * i + k];
+  }
   tp.n = n;
   tp.nc = nc;
   tp.mu = mu;
@@ -129,8 +134,8 @@ extern "C" {
 void emu_contact_grad_adj(int fp64, int n, const int* parent, const int* jtype, int nc, const int* clink, double mu,
                           double beta, int niter, const double* g, const double* P, const double* traj,
                           const double* tau, double dt, int T, const double* gqT, const double* gqdT, double* gq0,
-                          double* gqd0, double* gtau, double* gmu) {
-  const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g);
+                          double* gqd0, double* gtau, double* gmu, const double* limits) {
+  const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g, limits);
   if (fp64) grad_adj<double>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
   else grad_adj<float>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
 }
@@ -139,8 +144,9 @@ void emu_contact_grad_adj(int fp64, int n, const int* parent, const int* jtype, 
 // fp64 = 1: double arithmetic, 0: float (inputs and outputs are double either way)
 void emu_contact_rollout(int fp64, int n, const int* parent, const int* jtype, int nc, const int* clink, double mu,
                          double beta, int niter, const double* g, const double* P, const double* q0,
-                         const double* qd0, const double* tau, double dt, int T, double* traj, int* ncont) {
-  const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g);
+                         const double* qd0, const double* tau, double dt, int T, double* traj, int* ncont,
+                         const double* limits) {
+  const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g, limits);
   if (fp64) rollout<double>(tp, P, q0, qd0, tau, dt, T, traj, ncont);
   else rollout<float>(tp, P, q0, qd0, tau, dt, T, traj, ncont);
 }
@@ -148,8 +154,8 @@ void emu_contact_rollout(int fp64, int n, const int* parent, const int* jtype, i
 void emu_contact_grad(int fp64, int n, const int* parent, const int* jtype, int nc, const int* clink, double mu,
                       double beta, int niter, const double* g, const double* P, const double* traj,
                       const double* tau, double dt, int T, const double* gqT, const double* gqdT, double* gq0,
-                      double* gqd0, double* gtau, double* gmu) {
-  const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g);
+                      double* gqd0, double* gtau, double* gmu, const double* limits) {
+  const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g, limits);
   if (fp64) grad<double>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
   else grad<float>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
 }

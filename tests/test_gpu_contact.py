@@ -15,6 +15,7 @@ gradient (Sec. 4.1 "Collision resolution"), through the C ABI
   models;
 * every launch geometry (systems per wave) gives the same bits, and the
   autotuner picks one of them;
+* joint limits inside the step (FP64 states and gradients to round-off);
 * the benchmark batch (4096 quadrupeds, 1000 steps) on sampled systems:
   steps and the full-horizon gradient along the GPU trajectory.
 """
@@ -243,6 +244,44 @@ def test_edge_cases():
     big, *_ = synth.tree_system(5, 1, nmin=17, nmax=17)
     with pytest.raises(N.SimError):
         ContactBatch([big], [1], [[[0, 0, 0]]], [[0.03]], dtype=torch.float64)
+
+
+def test_joint_limits_fp64_round_off():
+    """Joint limits inside the step with contact (one set shared by the
+    batch, tight around the start pose so the legs run into them): FP64
+    states, contact counts and gradients against the oracle's."""
+    from dataclasses import replace
+    T = 50
+    draws = quad_batch(32, T)
+    lim = synth.with_joint_limits(draws[0][:4], 77, half_range=(0.002, 0.02))[0].limits
+    draws = [(replace(d[0], limits=lim),) + tuple(d[1:]) for d in draws]
+    print("case limits B", len(draws), "T", T, flush=True)
+    cb, q0, qd0, tau = _gpu(draws, torch.float64, T)
+    qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, DT, counts=True)
+    rng = np.random.default_rng(12)
+    gqT = torch.tensor(rng.normal(size=(cb.nq, cb.B)), dtype=torch.float64, device=DEV)
+    gqdT = torch.tensor(rng.normal(size=(cb.nv, cb.B)), dtype=torch.float64, device=DEV)
+    g = [x.cpu().numpy() for x in cb.grad(tr, tau, DT, gqT, gqdT, mu_grad=True)]
+    trn, ncn = tr.cpu().numpy(), nc.cpu().numpy()
+    worst_x, worst_g, hit = 0.0, 0.0, False
+    q1 = [k for k in range(draws[0][0].n) if draws[0][0].jtype[k] != 1]
+    for i in (0, 9, 20, 31):
+        m, C = _oracle(draws[i])
+        d = draws[i]
+        _, _, nc_o, tr_o = O.rollout_contact(m, C, d[1], d[2], d[3][:T], DT, traj=True)
+        assert np.array_equal(ncn[:, i], nc_o), i
+        worst_x = max(worst_x, max(rel(trn[t + 1, :, i], tr_o[t], 1e-12) for t in range(T)))
+        qs = trn[:, [6 + k for k in q1], i]
+        hit |= bool(((qs > lim[q1, 1]) | (qs < lim[q1, 0])).any())
+        ref = O.rollout_contact_grad(m, C, d[1], d[2], d[3][:T], DT, gqT[:, i].cpu().numpy(),
+                                     gqdT[:, i].cpu().numpy(), mu_grad=True)
+        ref = ref[:3] + (np.array([ref[3]]),)
+        scale = max(np.abs(r).max() for r in ref)
+        got = (g[0][:, i], g[1][:, i], g[2][:, :, i], g[3][i:i + 1])
+        worst_g = max(worst_g, *[rel(a, b, 1e-6 * scale) for a, b in zip(got, ref)])
+    print("limits: worst state error %.1e, worst gradient error %.1e" % (worst_x, worst_g))
+    assert hit and ncn.max() >= 2
+    assert worst_x < 1e-10 and worst_g < 1e-8
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])

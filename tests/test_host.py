@@ -118,7 +118,7 @@ def test_null_arguments_are_rejected():
                        ((16, 16), False)):
         t = _Tiling(*tiling)
         m = _Model(2, par.ctypes.data, jt.ctypes.data, 1, cl.ctypes.data, 0.5, 0.0, 10,
-                   (ctypes.c_double * 3)(0.0, -9.81, 0.0), ctypes.addressof(t))
+                   (ctypes.c_double * 3)(0.0, -9.81, 0.0), None, ctypes.addressof(t))
         rc = L.sim_contact_param_count(ctypes.byref(m), *[ctypes.byref(x) for x in sizes])
         assert rc == (N.SIM_OK if ok else N.SIM_ERR_INVALID_ARG), tiling
         if ok:
@@ -126,6 +126,14 @@ def test_null_arguments_are_rejected():
     assert b"tiling" in L.sim_last_error()
     m.tiling = None
     assert L.sim_contact_param_count(ctypes.byref(m), None, None, None, None) == N.SIM_OK
+    # joint limits: checked like sim_params' (the free root's entry is not read)
+    for lim, ok in (([9, 9, 9, 9, -0.5, 0.5, 100.0, 1.0], True), ([0, 0, 0, 0, 0.5, -0.5, 100.0, 1.0], False),
+                    ([0, 0, 0, 0, -0.5, 0.5, -1.0, 1.0], False), ([0, 0, 0, 0, -0.5, np.inf, 1.0, 1.0], False)):
+        la = np.array(lim, np.float64)
+        m.limits = la.ctypes.data
+        rc = L.sim_contact_param_count(ctypes.byref(m), None, None, None, None)
+        assert rc == (N.SIM_OK if ok else N.SIM_ERR_INVALID_ARG), lim
+    m.limits = None
     c = _Tiling()
     assert L.sim_contact_autotune(ctypes.byref(m), 0, 4, None, None, None, None, 1e-3, 10, None, ctypes.byref(c),
                                   None, None) == N.SIM_ERR_INVALID_ARG
