@@ -188,10 +188,14 @@ template <typename S, typename R, int SPL>
 __global__ __launch_bounds__(kWave) void k_contact_adj(GradArgs<S> a) {
   constexpr int SPW = SPL;
   static_assert(SPL <= kWave, "one wave per workgroup");
+  // each system's Gauss-Seidel working copies (PgsStage), one LDS column per
+  // lane: the solves' inner loops read LDS instead of private memory
+  __shared__ R stg[kStage * SPW];
   const int ln = threadIdx.x % kWave;
   const int sw = (threadIdx.x / kWave) * SPL + ln;
   const int s = blockIdx.x * SPW + sw;
   if (ln >= SPL || s >= a.B) return;
+  const PgsStage<R> stage{stg + sw, SPW};
   // the model's constants as the forward rollout saw them (rounded to S)
   CTopo tp = a.tp;
   for (int k = 0; k < 3; ++k) tp.g[k] = double(S(tp.g[k]));
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(kWave) void k_contact_adj(GradArgs<S> a) {
   for (int t = a.T - 1; t >= 0; --t) {
     for (int k = 0; k < nx; ++k) x[k] = R(a.traj[((size_t)t * nx + k) * B + s]);
     for (int k = 0; k < nu; ++k) u[k] = R(a.tau[((size_t)t * nu + k) * B + s]);
-    contact_step_vjp(tp, P, x, x + nq, u, a.dt, R(tp.mu), xb, ub, mub, w, rc, ad);
+    contact_step_vjp(tp, P, x, x + nq, u, a.dt, R(tp.mu), xb, ub, mub, w, rc, ad, stage);
     for (int k = 0; k < nu; ++k) a.gtau[((size_t)t * nu + k) * B + s] = S(ub[k]);
   }
   for (int k = 0; k < nq; ++k) a.gq0[k * B + s] = S(xb[k]);

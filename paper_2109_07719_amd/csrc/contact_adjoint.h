@@ -432,6 +432,63 @@ ABA_HD void pgs_reverse(int m, const int* idx, int r, const S* A, const S* b, co
   }
 }
 
+// pgs_reverse on a staged copy (PgsStage): the adjoints are gathered with
+// their current values and written back, and every statement runs in the
+// order of pgs_reverse, so the result is bitwise the same.
+template <typename S>
+ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi,
+                               int niter, const S* sweeps, int ld, S* xb, S* Ab, S* bb, S* lob, S* hib,
+                               const PgsStage<S>& g) {
+  for (int i = 0; i < m; ++i) {
+    const int ri = idx[i];
+    for (int j = 0; j < m; ++j) {
+      g[kStA + i * m + j] = A[ri * r + idx[j]];
+      g[kStAb + i * m + j] = Ab[ri * r + idx[j]];
+    }
+    g[kStB + i] = b[ri];
+    g[kStBb + i] = bb[ri];
+    g[kStLo + i] = lo[i];
+    g[kStHi + i] = hi[i];
+    g[kStXb + i] = xb[i];
+    g[kStLob + i] = lob[i];
+    g[kStHib + i] = hib[i];
+  }
+  for (int it = niter - 1; it >= 0; --it) {
+    // x at the start (xs) and at the end (xe) of sweep it
+    for (int j = 0; j < m; ++j) {
+      g[kStX + j] = sweeps[it * ld + j];
+      g[kStXe + j] = sweeps[(it + 1) * ld + j];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      S d = S(0);
+      for (int j = 0; j < m; ++j)
+        if (j != i) d = d + g[kStA + i * m + j] * (j < i ? g[kStXe + j] : g[kStX + j]);
+      const S y = -(g[kStB + i] + d) / g[kStA + i * m + i];
+      S yb = S(0);
+      if (val(y) < val(g[kStLo + i])) g[kStLob + i] = g[kStLob + i] + g[kStXb + i];
+      else if (val(y) > val(g[kStHi + i])) g[kStHib + i] = g[kStHib + i] + g[kStXb + i];
+      else yb = g[kStXb + i];
+      g[kStXb + i] = S(0);
+      const S db = -yb / g[kStA + i * m + i];
+      g[kStBb + i] = g[kStBb + i] + db;
+      g[kStAb + i * m + i] = g[kStAb + i * m + i] + db * y;
+      for (int j = 0; j < m; ++j)
+        if (j != i) {
+          g[kStAb + i * m + j] = g[kStAb + i * m + j] + db * (j < i ? g[kStXe + j] : g[kStX + j]);
+          g[kStXb + j] = g[kStXb + j] + db * g[kStA + i * m + j];
+        }
+    }
+  }
+  for (int i = 0; i < m; ++i) {
+    const int ri = idx[i];
+    for (int j = 0; j < m; ++j) Ab[ri * r + idx[j]] = g[kStAb + i * m + j];
+    bb[ri] = g[kStBb + i];
+    xb[i] = g[kStXb + i];
+    lob[i] = g[kStLob + i];
+    hib[i] = g[kStHib + i];
+  }
+}
+
 // Adjoint state of one reverse step with contact.
 template <typename S>
 struct Adj {
@@ -445,10 +502,11 @@ struct Adj {
 // mub.
 template <typename S, typename R>
 ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const S* qd, const S* u, R dt_, S mu,
-                             S* xbar, S* ubar, S& mub, Work<S>& w, Rec<S>& rc, Adj<S>& ad) {
+                             S* xbar, S* ubar, S& mub, Work<S>& w, Rec<S>& rc, Adj<S>& ad,
+                             PgsStage<S> stage = {nullptr, 0}) {
   const int n = tp.n, nq = tp.nq, nv = tp.nv;
   S q1[kNQ], qd1[kNV];
-  contact_step(tp, P, q, qd, u, dt_, mu, q1, qd1, w, &rc);
+  contact_step(tp, P, q, qd, u, dt_, mu, q1, qd1, w, &rc, stage);
   const S dt = S(dt_);
   S qb[kNQ], qdb[kNV], qd1b[kNV], qdmb[kNV];
   for (int k = 0; k < nq; ++k) qb[k] = S(0);
@@ -526,7 +584,11 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
       lob[i] = hib[i] = S(0);
       xkb[i] = xb[ri];
     }
-    pgs_reverse(nk, rc.keep, r, w.A, w.b, lo, hi, tp.niter, &rc.x2[0][0], kNR, xkb, ad.Ab, ad.bb, lob, hib);
+    if (stage.p)
+      pgs_reverse_staged(nk, rc.keep, r, w.A, w.b, lo, hi, tp.niter, &rc.x2[0][0], kNR, xkb, ad.Ab, ad.bb, lob, hib,
+                         stage);
+    else
+      pgs_reverse(nk, rc.keep, r, w.A, w.b, lo, hi, tp.niter, &rc.x2[0][0], kNR, xkb, ad.Ab, ad.bb, lob, hib);
     S lamb[kNC];
     for (int c = 0; c < na; ++c) lamb[c] = S(0);
     for (int i = 0; i < nk; ++i) {
@@ -545,7 +607,11 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
       hi1[i] = S(Big<typename RealOf<S>::type>::v);
       lob1[i] = hib1[i] = S(0);
     }
-    pgs_reverse(nkn, rc.kn, r, w.A, w.b, lo1, hi1, tp.niter, &rc.x1[0][0], kNC, xnb, ad.Ab, ad.bb, lob1, hib1);
+    if (stage.p)
+      pgs_reverse_staged(nkn, rc.kn, r, w.A, w.b, lo1, hi1, tp.niter, &rc.x1[0][0], kNC, xnb, ad.Ab, ad.bb, lob1,
+                         hib1, stage);
+    else
+      pgs_reverse(nkn, rc.kn, r, w.A, w.b, lo1, hi1, tp.niter, &rc.x1[0][0], kNC, xnb, ad.Ab, ad.bb, lob1, hib1);
     // ---- A = J MJ, b = J qd_minus + (beta/dt) phi (normal rows)
     const S bdt = S(tp.beta) / dt;
     S phib[kNC];

@@ -221,13 +221,59 @@ ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* l
     for (int i = 0; i < m; ++i) sweeps[niter * ld + i] = x[i];
 }
 
+// A compact working copy of one Gauss-Seidel problem, element k at p[k * st]
+// (the kernels give every lane its own column of an LDS block, the host a
+// plain array): the kept rows' block of A (m x m), b, the bounds, x, the two
+// sweep vectors the reverse reads, and the reverse's adjoints.  Every access
+// of the sweeps then reads this copy directly instead of going through the
+// kept-row index into the full record.
+template <typename S>
+struct PgsStage {
+  S* p;
+  int st;
+  ABA_HD S& operator[](int k) const { return p[(size_t)k * st]; }
+};
+constexpr int kStA = 0, kStB = kNR * kNR, kStLo = kStB + kNR, kStHi = kStLo + kNR, kStX = kStHi + kNR,
+              kStXe = kStX + kNR, kStAb = kStXe + kNR, kStBb = kStAb + kNR * kNR, kStXb = kStBb + kNR,
+              kStLob = kStXb + kNR, kStHib = kStLob + kNR, kStage = kStHib + kNR;
+
+// pgs on a staged copy: the same statements in the same order, so the
+// result is bitwise that of pgs.
+template <typename S>
+ABA_HD void pgs_staged(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi, int niter,
+                       S* x, S* sweeps, int ld, const PgsStage<S>& g) {
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) g[kStA + i * m + j] = A[idx[i] * r + idx[j]];
+    g[kStB + i] = b[idx[i]];
+    g[kStLo + i] = lo[i];
+    g[kStHi + i] = hi[i];
+    g[kStX + i] = S(0);
+  }
+  for (int it = 0; it < niter; ++it) {
+    if (sweeps)
+      for (int i = 0; i < m; ++i) sweeps[it * ld + i] = g[kStX + i];
+    for (int i = 0; i < m; ++i) {
+      S d = S(0);
+      for (int j = 0; j < m; ++j)
+        if (j != i) d = d + g[kStA + i * m + j] * g[kStX + j];
+      S y = -(g[kStB + i] + d) / g[kStA + i * m + i];
+      if (val(y) < val(g[kStLo + i])) y = g[kStLo + i];
+      else if (val(y) > val(g[kStHi + i])) y = g[kStHi + i];
+      g[kStX + i] = y;
+    }
+  }
+  for (int i = 0; i < m; ++i) x[i] = g[kStX + i];
+  if (sweeps)
+    for (int i = 0; i < m; ++i) sweeps[niter * ld + i] = x[i];
+}
+
 // One step with contact from (q, qd) under control u and friction
 // coefficient mu (a dual number for its derivative); returns the number of
 // active contacts.  rec (nullable, niter <= kSweepMax) keeps what the
 // step's adjoint needs.
 template <typename S, typename R>
 ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* qd, const S* u, R dt_, S mu,
-                            S* q1, S* qd1, Work<S>& w, Rec<S>* rec = nullptr) {
+                            S* q1, S* qd1, Work<S>& w, Rec<S>* rec = nullptr, PgsStage<S> stage = {nullptr, 0}) {
   using Rl = typename RealOf<S>::type;
   const int n = tp.n, nv = tp.nv;
   const S dt = S(dt_);
@@ -528,7 +574,8 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       }
     S lo[kNR], hi[kNR], lamn[kNC], xn[kNC];
     for (int i = 0; i < nkn; ++i) { lo[i] = S(0); hi[i] = S(Big<Rl>::v); }
-    pgs(nkn, kn, r, w.A, w.b, lo, hi, tp.niter, xn, rec ? &rec->x1[0][0] : nullptr, kNC);
+    if (stage.p) pgs_staged(nkn, kn, r, w.A, w.b, lo, hi, tp.niter, xn, rec ? &rec->x1[0][0] : nullptr, kNC, stage);
+    else pgs(nkn, kn, r, w.A, w.b, lo, hi, tp.niter, xn, rec ? &rec->x1[0][0] : nullptr, kNC);
     for (int c = 0; c < na; ++c) lamn[c] = S(0);
     for (int i = 0; i < nkn; ++i) lamn[kn[i] / 3] = xn[i];
     for (int i = 0; i < nk; ++i) {
@@ -541,7 +588,8 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       }
     }
     S xk[kNR];
-    pgs(nk, keep, r, w.A, w.b, lo, hi, tp.niter, xk, rec ? &rec->x2[0][0] : nullptr, kNR);
+    if (stage.p) pgs_staged(nk, keep, r, w.A, w.b, lo, hi, tp.niter, xk, rec ? &rec->x2[0][0] : nullptr, kNR, stage);
+    else pgs(nk, keep, r, w.A, w.b, lo, hi, tp.niter, xk, rec ? &rec->x2[0][0] : nullptr, kNR);
     if (rec) {
       rec->nk = nk;
       rec->nkn = nkn;

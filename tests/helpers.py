@@ -227,8 +227,8 @@ def contact_emu():
             os.replace(tmp, path)
         L = ctypes.CDLL(path)
         P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
-        L.emu_contact_rollout.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, P, D, I, P, P, P]
+        L.emu_contact_rollout.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, P, D, I, P, P, P, I]
         L.emu_contact_grad.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, D, I, P, P, P, P, P, P, P]
-        L.emu_contact_grad_adj.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, D, I, P, P, P, P, P, P, P]
+        L.emu_contact_grad_adj.argtypes = [I, I, P, P, I, P, D, D, I, P, P, P, P, D, I, P, P, P, P, P, P, P, I]
         _cemu = L
     return _cemu

@@ -46,7 +46,9 @@ CTopo topo(int n, const int* parent, const int* jtype, int nc, const int* clink,
 
 template <typename R>
 void rollout(const CTopo& tp, const double* Pd, const double* q0, const double* qd0, const double* tau, double dt,
-             int T, double* traj, int* ncont) {
+             int T, double* traj, int* ncont, bool staged) {
+  std::vector<R> stg(kStage);
+  const PgsStage<R> stage{staged ? stg.data() : nullptr, 1};
   std::vector<R> Pv(Pd, Pd + tp.np);
   const Par<R> P{Pv.data(), 1, 0};
   const int nx = tp.nq + tp.nv;
@@ -58,7 +60,7 @@ void rollout(const CTopo& tp, const double* Pd, const double* q0, const double* 
   for (int t = 0; t < T; ++t) {
     for (int k = 0; k < tp.nu; ++k) u[k] = R(tau[t * tp.nu + k]);
     ncont[t] = contact_step(tp, P, x.data(), x.data() + tp.nq, u.data(), R(dt), R(tp.mu), x1.data(),
-                            x1.data() + tp.nq, *w);
+                            x1.data() + tp.nq, *w, (Rec<R>*)nullptr, stage);
     x = x1;
     for (int k = 0; k < nx; ++k) traj[(t + 1) * nx + k] = double(x[k]);
   }
@@ -101,7 +103,10 @@ void grad(const CTopo& tp, const double* Pd, const double* traj, const double* t
 // the same gradient by the step's reverse statements (contact_step_vjp)
 template <typename R>
 void grad_adj(const CTopo& tp, const double* Pd, const double* traj, const double* tau, double dt, int T,
-              const double* gqT, const double* gqdT, double* gq0, double* gqd0, double* gtau, double* gmu) {
+              const double* gqT, const double* gqdT, double* gq0, double* gqd0, double* gtau, double* gmu,
+              bool staged) {
+  std::vector<R> stg(kStage);
+  const PgsStage<R> stage{staged ? stg.data() : nullptr, 1};
   std::vector<R> Pv(Pd, Pd + tp.np);
   const Par<R> P{Pv.data(), 1, 0};
   const int nq = tp.nq, nx = tp.nq + tp.nv, nu = tp.nu;
@@ -116,7 +121,7 @@ void grad_adj(const CTopo& tp, const double* Pd, const double* traj, const doubl
     for (int k = 0; k < nx; ++k) x[k] = R(traj[t * nx + k]);
     for (int k = 0; k < nu; ++k) u[k] = R(tau[t * nu + k]);
     contact_step_vjp(tp, P, x.data(), x.data() + nq, u.data(), R(dt), R(tp.mu), xb.data(), ub.data(), mu_acc, *w,
-                     *rc, *ad);
+                     *rc, *ad, stage);
     for (int k = 0; k < nu; ++k) gtau[t * nu + k] = double(ub[k]);
   }
   delete w;
@@ -134,10 +139,10 @@ extern "C" {
 void emu_contact_grad_adj(int fp64, int n, const int* parent, const int* jtype, int nc, const int* clink, double mu,
                           double beta, int niter, const double* g, const double* P, const double* traj,
                           const double* tau, double dt, int T, const double* gqT, const double* gqdT, double* gq0,
-                          double* gqd0, double* gtau, double* gmu, const double* limits) {
+                          double* gqd0, double* gtau, double* gmu, const double* limits, int staged) {
   const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g, limits);
-  if (fp64) grad_adj<double>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
-  else grad_adj<float>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu);
+  if (fp64) grad_adj<double>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu, staged != 0);
+  else grad_adj<float>(tp, P, traj, tau, dt, T, gqT, gqdT, gq0, gqd0, gtau, gmu, staged != 0);
 }
 
 
@@ -145,10 +150,10 @@ void emu_contact_grad_adj(int fp64, int n, const int* parent, const int* jtype, 
 void emu_contact_rollout(int fp64, int n, const int* parent, const int* jtype, int nc, const int* clink, double mu,
                          double beta, int niter, const double* g, const double* P, const double* q0,
                          const double* qd0, const double* tau, double dt, int T, double* traj, int* ncont,
-                         const double* limits) {
+                         const double* limits, int staged) {
   const CTopo tp = topo(n, parent, jtype, nc, clink, mu, beta, niter, g, limits);
-  if (fp64) rollout<double>(tp, P, q0, qd0, tau, dt, T, traj, ncont);
-  else rollout<float>(tp, P, q0, qd0, tau, dt, T, traj, ncont);
+  if (fp64) rollout<double>(tp, P, q0, qd0, tau, dt, T, traj, ncont, staged != 0);
+  else rollout<float>(tp, P, q0, qd0, tau, dt, T, traj, ncont, staged != 0);
 }
 
 void emu_contact_grad(int fp64, int n, const int* parent, const int* jtype, int nc, const int* clink, double mu,

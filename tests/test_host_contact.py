@@ -40,27 +40,32 @@ def _emu_args(s, links, centers, radii, mu, beta, niter):
         (_p(lim) if lim is not None else None)
 
 
-def emu_rollout(s, links, centers, radii, mu, beta, niter, q0, qd0, tau, dt, fp64=True):
+def emu_rollout(s, links, centers, radii, mu, beta, niter, q0, qd0, tau, dt, fp64=True, staged=False):
     keep, a, lim = _emu_args(s, links, centers, radii, mu, beta, niter)
     T = tau.shape[0]
     nx = s.nq + s.nv
     q0, qd0, tau = (np.ascontiguousarray(v, np.float64) for v in (q0, qd0, tau))
     tr = np.zeros((T + 1, nx))
     nc = np.zeros(T, np.int32)
-    contact_emu().emu_contact_rollout(int(fp64), *a, _p(q0), _p(qd0), _p(tau), dt, T, _p(tr), _p(nc), lim)
+    contact_emu().emu_contact_rollout(int(fp64), *a, _p(q0), _p(qd0), _p(tau), dt, T, _p(tr), _p(nc), lim,
+                                      int(staged))
     return tr, nc
 
 
-def emu_grad(s, links, centers, radii, mu, beta, niter, tr, tau, dt, gqT, gqdT, fp64=True, adjoint=False):
+def emu_grad(s, links, centers, radii, mu, beta, niter, tr, tau, dt, gqT, gqdT, fp64=True, adjoint=False,
+             staged=True):
     """adjoint=False: each step's Jacobian in dual numbers applied in
     reverse time; adjoint=True: the step's reverse statements."""
     keep, a, lim = _emu_args(s, links, centers, radii, mu, beta, niter)
     T = tau.shape[0]
     tau, gqT, gqdT = (np.ascontiguousarray(v, np.float64) for v in (tau, gqT, gqdT))
     gq0, gqd0, gtau, gmu = np.zeros(s.nq), np.zeros(s.nv), np.zeros((T, s.nu)), np.zeros(1)
-    fn = contact_emu().emu_contact_grad_adj if adjoint else contact_emu().emu_contact_grad
-    fn(int(fp64), *a, _p(np.ascontiguousarray(tr)), _p(tau), dt, T, _p(gqT), _p(gqdT), _p(gq0), _p(gqd0), _p(gtau),
-       _p(gmu), lim)
+    args = (int(fp64), *a, _p(np.ascontiguousarray(tr)), _p(tau), dt, T, _p(gqT), _p(gqdT), _p(gq0), _p(gqd0),
+            _p(gtau), _p(gmu), lim)
+    if adjoint:
+        contact_emu().emu_contact_grad_adj(*args, int(staged))
+    else:
+        contact_emu().emu_contact_grad(*args)
     return gq0, gqd0, gtau, gmu
 
 
@@ -163,6 +168,29 @@ def test_gradient_fp64_matches_the_oracle(k, adjoint):
     print(name, "gradient errors (q0, qd0, tau, mu)", ["%.1e" % x for x in e], "contacts", np.bincount(nc))
     assert nc.max() >= 1
     assert max(e) < 1e-8
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("k", range(len(SCENES)), ids=[sc[0] for sc in SCENES])
+def test_staged_gauss_seidel_is_bitwise_the_plain_one(k, fp64):
+    """The kernels run both Gauss-Seidel solves and their reverse sweeps on
+    a compact staged copy (LDS on the GPU); the same statements in the same
+    order give the same bits as the solves on the full records."""
+    name, s, q0, qd0, tau, links, centers, radii, mu, beta = SCENES[k]
+    dt, niter = 1e-3, 30
+    T = 50 if name.startswith("quadruped") else 25
+    tau = tau[:T]
+    tr0, nc0 = emu_rollout(s, links, centers, radii, mu, beta, niter, q0, qd0, tau, dt, fp64=fp64)
+    tr1, nc1 = emu_rollout(s, links, centers, radii, mu, beta, niter, q0, qd0, tau, dt, fp64=fp64, staged=True)
+    assert np.array_equal(tr0, tr1) and np.array_equal(nc0, nc1) and nc0.max() >= 1
+    rng = np.random.default_rng(k)
+    gqT, gqdT = rng.normal(size=s.nq), rng.normal(size=s.nv)
+    g0 = emu_grad(s, links, centers, radii, mu, beta, niter, tr0, tau, dt, gqT, gqdT, fp64=fp64, adjoint=True,
+                  staged=False)
+    g1 = emu_grad(s, links, centers, radii, mu, beta, niter, tr0, tau, dt, gqT, gqdT, fp64=fp64, adjoint=True,
+                  staged=True)
+    for a, b in zip(g0, g1):
+        assert np.array_equal(a, b)
 
 
 def test_flop_count_grows_with_active_contacts():
