@@ -191,6 +191,7 @@ __global__ __launch_bounds__(kWave) void k_contact_adj(GradArgs<S> a) {
   // each system's Gauss-Seidel working copies (PgsStage), one LDS column per
   // lane: the solves' inner loops read LDS instead of private memory
   __shared__ R stg[kStage * SPW];
+  __shared__ Art<R> art_sh[SPW];
   const int ln = threadIdx.x % kWave;
   const int sw = (threadIdx.x / kWave) * SPL + ln;
   const int s = blockIdx.x * SPW + sw;
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(kWave) void k_contact_adj(GradArgs<S> a) {
   for (int t = a.T - 1; t >= 0; --t) {
     for (int k = 0; k < nx; ++k) x[k] = R(a.traj[((size_t)t * nx + k) * B + s]);
     for (int k = 0; k < nu; ++k) u[k] = R(a.tau[((size_t)t * nu + k) * B + s]);
-    contact_step_vjp(tp, P, x, x + nq, u, a.dt, R(tp.mu), xb, ub, mub, w, rc, ad, stage);
+    contact_step_vjp(tp, P, x, x + nq, u, a.dt, R(tp.mu), xb, ub, mub, w, rc, ad, art_sh[sw], stage);
     for (int k = 0; k < nu; ++k) a.gtau[((size_t)t * nu + k) * B + s] = S(ub[k]);
   }
   for (int k = 0; k < nq; ++k) a.gq0[k * B + s] = S(xb[k]);
@@ -355,17 +356,19 @@ int sim_contact_flops(const sim_contact_model* m, const double* params, const do
     auto* w = new Work<CD>;
     auto* rc = new Rec<CD>;
     auto* ad = new Adj<CD>;
+    auto* art = new Art<CD>;
     CD x[kNX], xb[kNX], u[kNL], ub[kNL], mub(0.0);
     for (int k = 0; k < tp.nq; ++k) x[k] = CD(q[k]);
     for (int k = 0; k < tp.nv; ++k) x[tp.nq + k] = CD(qd[k]);
     for (int k = 0; k < tp.nu; ++k) u[k] = CD(tau[k]);
     for (int k = 0; k < nx; ++k) xb[k] = CD(1.0);
     g_cops = 0;
-    contact_step_vjp(tp, P, x, x + tp.nq, u, dt, CD(tp.mu), xb, ub, mub, *w, *rc, *ad);
+    contact_step_vjp(tp, P, x, x + tp.nq, u, dt, CD(tp.mu), xb, ub, mub, *w, *rc, *ad, *art);
     *grad_flops = (double)g_cops;
     delete w;
     delete rc;
     delete ad;
+    delete art;
   }
   return SIM_OK;
 }

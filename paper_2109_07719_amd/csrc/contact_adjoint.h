@@ -134,11 +134,31 @@ ABA_HD void inertia_apply(const Par<R>& P, int i, const S* v, S* o) {
   }
 }
 
+// The same from the link's inertial parameters as stored in an Art copy
+// (mass, centre of mass, inertia about it: the values inertia_apply reads).
+template <typename S>
+ABA_HD void inertia_apply_ib(const S* ib, const S* v, S* o) {
+  const S m = ib[0];
+  const S cm[3] = {ib[1], ib[2], ib[3]};
+  const S Ic[9] = {ib[4], ib[7], ib[8], ib[7], ib[5], ib[9], ib[8], ib[9], ib[6]};
+  S cxv[3], t[3];
+  cross3(cm, v + 3, cxv);
+  cross3(v, cm, t);
+  S wc[3];
+  for (int k = 0; k < 3; ++k) wc[k] = v[3 + k] + t[k];
+  S cwc[3];
+  cross3(cm, wc, cwc);
+  for (int a = 0; a < 3; ++a) {
+    o[a] = Ic[3 * a] * v[0] + Ic[3 * a + 1] * v[1] + Ic[3 * a + 2] * v[2] + m * cwc[a];
+    o[3 + a] = m * wc[a];
+  }
+}
+
 // M^-1 rhs at the step's configuration (zero velocity, no gravity), from
 // the articulated inertias of the step's pass 2 kept in w (U, 1/D, the
 // free root's LDL^T).  rhs and out: [nv].
-template <typename S>
-ABA_HD void minv_apply(const CTopo& tp, const Work<S>& w, const S* rhs, S* out) {
+template <typename S, typename W>
+ABA_HD void minv_apply(const CTopo& tp, const W& w, const S* rhs, S* out) {
   const int n = tp.n;
   S pA[kNL][6], a[kNL][6], uu[kNL];
   for (int i = 0; i < n; ++i)
@@ -327,8 +347,8 @@ ABA_HD void id_vjp(const CTopo& tp, const Par<R>& P, const Work<S>& w, const S* 
 // Newton-Euler statements vanishes, written without them (A = X A_parent +
 // S acc, F = I A, F_parent += X^T F, and the reverse of those).  The free
 // root's row is body-frame, so M does not depend on its pose.
-template <typename S, typename R>
-ABA_HD void id_vjp_static(const CTopo& tp, const Par<R>& P, const Work<S>& w, const S* acc, const S* wv, S* gq) {
+template <typename S>
+ABA_HD void id_vjp_static(const CTopo& tp, const Art<S>& w, const S* acc, const S* wv, S* gq) {
   const int n = tp.n;
   S A[kNL][6], F[kNL][6], Ap[kNL][6];
   for (int i = 0; i < n; ++i) {
@@ -348,7 +368,7 @@ ABA_HD void id_vjp_static(const CTopo& tp, const Par<R>& P, const Work<S>& w, co
       }
       for (int k = 0; k < 6; ++k) A[i][k] = Ap[i][k] + s6[k] * acc[tp.vi[i]];
     }
-    inertia_apply(P, i, A[i], F[i]);
+    inertia_apply_ib(w.Ib[i], A[i], F[i]);
   }
   for (int i = n - 1; i >= 0; --i) {
     const int p = tp.parent[i];
@@ -380,7 +400,7 @@ ABA_HD void id_vjp_static(const CTopo& tp, const Par<R>& P, const Work<S>& w, co
   }
   // F = I A: A_bar = I F_bar (in place; F is no longer needed)
   S (&Ab)[kNL][6] = F;
-  for (int i = 0; i < n; ++i) inertia_apply(P, i, Fb[i], Ab[i]);
+  for (int i = 0; i < n; ++i) inertia_apply_ib(w.Ib[i], Fb[i], Ab[i]);
   // reverse of A = X A_parent + S acc, leaves -> root
   for (int i = n - 1; i >= 0; --i) {
     if (tp.jtype[i] == SIM_JOINT_FREE) continue;
@@ -502,11 +522,11 @@ struct Adj {
 // mub.
 template <typename S, typename R>
 ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const S* qd, const S* u, R dt_, S mu,
-                             S* xbar, S* ubar, S& mub, Work<S>& w, Rec<S>& rc, Adj<S>& ad,
+                             S* xbar, S* ubar, S& mub, Work<S>& w, Rec<S>& rc, Adj<S>& ad, Art<S>& art,
                              PgsStage<S> stage = {nullptr, 0}) {
   const int n = tp.n, nq = tp.nq, nv = tp.nv;
   S q1[kNQ], qd1[kNV];
-  contact_step(tp, P, q, qd, u, dt_, mu, q1, qd1, w, &rc, stage);
+  contact_step(tp, P, q, qd, u, dt_, mu, q1, qd1, w, &rc, stage, &art);
   const S dt = S(dt_);
   S qb[kNQ], qdb[kNV], qd1b[kNV], qdmb[kNV];
   for (int k = 0; k < nq; ++k) qb[k] = S(0);
@@ -638,11 +658,11 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
         col[k] = ad.MJb[k][j];
         mj[k] = w.MJ[k][j];
       }
-      minv_apply(tp, w, col, Wj);
+      minv_apply(tp, art, col, Wj);
       for (int k = 0; k < nv; ++k) ad.Jb[j][k] = ad.Jb[j][k] + Wj[k];
       S gqj[kNQ];
       for (int k = 0; k < nq; ++k) gqj[k] = S(0);
-      id_vjp_static(tp, P, w, mj, Wj, gqj);
+      id_vjp_static(tp, art, mj, Wj, gqj);
       for (int k = 0; k < nq; ++k) qb[k] = qb[k] - gqj[k];
     }
     // ---- contact rows and gaps through the world poses
@@ -779,7 +799,7 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
     qdb[k] = qdb[k] + qdmb[k];
     qddb[k] = dt * qdmb[k];
   }
-  minv_apply(tp, w, qddb, taub);
+  minv_apply(tp, art, qddb, taub);
   for (int i = 0; i < n; ++i)
     if (tp.jtype[i] != SIM_JOINT_FREE) ubar[tp.ui[i]] = taub[tp.vi[i]];
   S gq[kNQ], gqd[kNV];

@@ -152,6 +152,19 @@ struct Rec {
   S x2[kSweepMax + 1][kNR]; // second solve
 };
 
+// The articulated quantities that the unit-impulse responses (M^-1 J^T)
+// and the adjoint's solves with M read, with the responses' scratch: a
+// per-lane copy that the gradient kernel keeps in LDS, where those long
+// sweeps see LDS rather than private-memory latency.  An odd number of
+// scalars, so that consecutive lanes' copies fall on distinct banks.
+template <typename S>
+struct Art {
+  S E[kNL][9], r[kNL][3], ax[kNL][3], U[kNL][6], Dinv[kNL], L0[36], D0[6];
+  S Ib[kNL][10];  // mass, centre of mass (3), inertia about it (xx yy zz xy xz yz)
+  S pA[kNL][6], a[kNL][6], u[kNL];
+  S pad_;
+};
+
 // unit quaternion (x, y, z, w) -> rotation matrix (body -> world), row-major
 template <typename S>
 ABA_HD void quat_R(const S* qt, S* R) {
@@ -267,13 +280,70 @@ ABA_HD void pgs_staged(int m, const int* idx, int r, const S* A, const S* b, con
     for (int i = 0; i < m; ++i) sweeps[niter * ld + i] = x[i];
 }
 
+// M^-1 J^T: the response of the step's articulated system (zero velocity,
+// no gravity) to a unit world force along each contact row's direction at
+// the contact point, one column of w.MJ per row.  v holds the articulated
+// quantities and the scratch (the Work itself, or an Art copy of it).
+template <typename S, typename V>
+ABA_HD void unit_responses(const CTopo& tp, Work<S>& w, V& v, int na, const int* act, const S (*cl)[3]) {
+  const int n = tp.n;
+  const int dirs[3] = {1, 0, 2};
+  for (int c = 0; c < na; ++c) {
+    const int l = tp.clink[act[c]];
+    for (int dd = 0; dd < 3; ++dd) {
+      for (int i = 0; i < n; ++i)
+        for (int k = 0; k < 6; ++k) v.pA[i][k] = S(0);
+      S f[3];
+      for (int b = 0; b < 3; ++b) f[b] = w.Ew[l][3 * b + dirs[dd]];
+      S nmt[3];
+      cross3(cl[c], f, nmt);
+      for (int k = 0; k < 3; ++k) { v.pA[l][k] = -nmt[k]; v.pA[l][3 + k] = -f[k]; }
+      for (int i = n - 1; i >= 0; --i) {
+        if (tp.jtype[i] == SIM_JOINT_FREE) continue;
+        const int off = tp.jtype[i] == SIM_JOINT_PRISMATIC ? 3 : 0, p = tp.parent[i];
+        v.u[i] = -(v.pA[i][off] * v.ax[i][0] + v.pA[i][off + 1] * v.ax[i][1] + v.pA[i][off + 2] * v.ax[i][2]);
+        if (p >= 0) {
+          const S y = v.Dinv[i] * v.u[i];
+          S pa[6], fp[6];
+          for (int k = 0; k < 6; ++k) pa[k] = v.pA[i][k] + v.U[i][k] * y;
+          xt_force(v.E[i], v.r[i], pa, fp);
+          for (int k = 0; k < 6; ++k) v.pA[p][k] = v.pA[p][k] + fp[k];
+        }
+      }
+      for (int i = 0; i < n; ++i) {
+        if (tp.jtype[i] == SIM_JOINT_FREE) {
+          S rhs[6];
+          for (int k = 0; k < 6; ++k) rhs[k] = -v.pA[i][k];
+          ldl6_solve(v.L0, v.D0, rhs, v.a[i]);
+          for (int k = 0; k < 6; ++k) w.MJ[tp.vi[i] + k][3 * c + dd] = v.a[i][k];
+        } else {
+          const int p = tp.parent[i], off = tp.jtype[i] == SIM_JOINT_PRISMATIC ? 3 : 0;
+          S ap[6];
+          if (p < 0) {
+            for (int k = 0; k < 6; ++k) ap[k] = S(0);
+          } else {
+            x_motion(v.E[i], v.r[i], v.a[p], ap);
+          }
+          S Uap = S(0);
+          for (int k = 0; k < 6; ++k) Uap = Uap + v.U[i][k] * ap[k];
+          const S qdd = v.Dinv[i] * (v.u[i] - Uap);
+          for (int k = 0; k < 6; ++k) v.a[i][k] = ap[k];
+          for (int k = 0; k < 3; ++k) v.a[i][off + k] = v.a[i][off + k] + v.ax[i][k] * qdd;
+          w.MJ[tp.vi[i]][3 * c + dd] = qdd;
+        }
+      }
+    }
+  }
+}
+
 // One step with contact from (q, qd) under control u and friction
 // coefficient mu (a dual number for its derivative); returns the number of
 // active contacts.  rec (nullable, niter <= kSweepMax) keeps what the
 // step's adjoint needs.
 template <typename S, typename R>
 ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* qd, const S* u, R dt_, S mu,
-                            S* q1, S* qd1, Work<S>& w, Rec<S>* rec = nullptr, PgsStage<S> stage = {nullptr, 0}) {
+                            S* q1, S* qd1, Work<S>& w, Rec<S>* rec = nullptr, PgsStage<S> stage = {nullptr, 0},
+                            Art<S>* art = nullptr) {
   using Rl = typename RealOf<S>::type;
   const int n = tp.n, nv = tp.nv;
   const S dt = S(dt_);
@@ -442,6 +512,17 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
   }
   if (rec)
     for (int k = 0; k < nv; ++k) rec->qdm[k] = qd1[k];
+  if (art) {
+    for (int i = 0; i < n; ++i) {
+      for (int k = 0; k < 9; ++k) art->E[i][k] = w.E[i][k];
+      for (int k = 0; k < 3; ++k) { art->r[i][k] = w.r[i][k]; art->ax[i][k] = w.ax[i][k]; }
+      for (int k = 0; k < 6; ++k) art->U[i][k] = w.U[i][k];
+      art->Dinv[i] = w.Dinv[i];
+      for (int k = 0; k < 10; ++k) art->Ib[i][k] = S(P(kParLink * i + 15 + k));
+    }
+    for (int k = 0; k < 36; ++k) art->L0[k] = w.L0[k];
+    for (int k = 0; k < 6; ++k) art->D0[k] = w.D0[k];
+  }
   // ---- detection and assembly
   int act[kNC], na = 0;
   S phi[kNC], cl[kNC][3], pw[kNC][3];
@@ -506,52 +587,8 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       }
     }
     // M^-1 J^T: response to a unit world force along each row's direction at the contact point
-    for (int c = 0; c < na; ++c) {
-      const int l = tp.clink[act[c]];
-      for (int dd = 0; dd < 3; ++dd) {
-        for (int i = 0; i < n; ++i)
-          for (int k = 0; k < 6; ++k) w.pA[i][k] = S(0);
-        S f[3];
-        for (int b = 0; b < 3; ++b) f[b] = w.Ew[l][3 * b + dirs[dd]];
-        S nmt[3];
-        cross3(cl[c], f, nmt);
-        for (int k = 0; k < 3; ++k) { w.pA[l][k] = -nmt[k]; w.pA[l][3 + k] = -f[k]; }
-        for (int i = n - 1; i >= 0; --i) {
-          if (tp.jtype[i] == SIM_JOINT_FREE) continue;
-          const int off = tp.jtype[i] == SIM_JOINT_PRISMATIC ? 3 : 0, p = tp.parent[i];
-          w.u[i] = -(w.pA[i][off] * w.ax[i][0] + w.pA[i][off + 1] * w.ax[i][1] + w.pA[i][off + 2] * w.ax[i][2]);
-          if (p >= 0) {
-            const S y = w.Dinv[i] * w.u[i];
-            S pa[6], fp[6];
-            for (int k = 0; k < 6; ++k) pa[k] = w.pA[i][k] + w.U[i][k] * y;
-            xt_force(w.E[i], w.r[i], pa, fp);
-            for (int k = 0; k < 6; ++k) w.pA[p][k] = w.pA[p][k] + fp[k];
-          }
-        }
-        for (int i = 0; i < n; ++i) {
-          if (tp.jtype[i] == SIM_JOINT_FREE) {
-            S rhs[6];
-            for (int k = 0; k < 6; ++k) rhs[k] = -w.pA[i][k];
-            ldl6_solve(w.L0, w.D0, rhs, w.a[i]);
-            for (int k = 0; k < 6; ++k) w.MJ[tp.vi[i] + k][3 * c + dd] = w.a[i][k];
-          } else {
-            const int p = tp.parent[i], off = tp.jtype[i] == SIM_JOINT_PRISMATIC ? 3 : 0;
-            S ap[6];
-            if (p < 0) {
-              for (int k = 0; k < 6; ++k) ap[k] = S(0);
-            } else {
-              x_motion(w.E[i], w.r[i], w.a[p], ap);
-            }
-            S Uap = S(0);
-            for (int k = 0; k < 6; ++k) Uap = Uap + w.U[i][k] * ap[k];
-            const S qdd = w.Dinv[i] * (w.u[i] - Uap);
-            for (int k = 0; k < 6; ++k) w.a[i][k] = ap[k];
-            for (int k = 0; k < 3; ++k) w.a[i][off + k] = w.a[i][off + k] + w.ax[i][k] * qdd;
-            w.MJ[tp.vi[i]][3 * c + dd] = qdd;
-          }
-        }
-      }
-    }
+    if (art) unit_responses(tp, w, *art, na, act, cl);
+    else unit_responses(tp, w, w, na, act, cl);
     // A = J M^-1 J^T, b = J qd_minus + (beta/dt) phi (normal rows)
     const S bdt = S(tp.beta) / dt;
     Rl dmax = Rl(0);

@@ -49,6 +49,7 @@ void rollout(const CTopo& tp, const double* Pd, const double* q0, const double* 
              int T, double* traj, int* ncont, bool staged) {
   std::vector<R> stg(kStage);
   const PgsStage<R> stage{staged ? stg.data() : nullptr, 1};
+  Art<R>* art = staged ? new Art<R> : nullptr;
   std::vector<R> Pv(Pd, Pd + tp.np);
   const Par<R> P{Pv.data(), 1, 0};
   const int nx = tp.nq + tp.nv;
@@ -60,11 +61,12 @@ void rollout(const CTopo& tp, const double* Pd, const double* q0, const double* 
   for (int t = 0; t < T; ++t) {
     for (int k = 0; k < tp.nu; ++k) u[k] = R(tau[t * tp.nu + k]);
     ncont[t] = contact_step(tp, P, x.data(), x.data() + tp.nq, u.data(), R(dt), R(tp.mu), x1.data(),
-                            x1.data() + tp.nq, *w, (Rec<R>*)nullptr, stage);
+                            x1.data() + tp.nq, *w, (Rec<R>*)nullptr, stage, art);
     x = x1;
     for (int k = 0; k < nx; ++k) traj[(t + 1) * nx + k] = double(x[k]);
   }
   delete w;
+  delete art;
 }
 
 template <typename R>
@@ -116,17 +118,19 @@ void grad_adj(const CTopo& tp, const double* Pd, const double* traj, const doubl
   auto* w = new Work<R>;
   auto* rc = new Rec<R>;
   auto* ad = new Adj<R>;
+  auto* art = new Art<R>;
   R mu_acc = R(0);
   for (int t = T - 1; t >= 0; --t) {
     for (int k = 0; k < nx; ++k) x[k] = R(traj[t * nx + k]);
     for (int k = 0; k < nu; ++k) u[k] = R(tau[t * nu + k]);
     contact_step_vjp(tp, P, x.data(), x.data() + nq, u.data(), R(dt), R(tp.mu), xb.data(), ub.data(), mu_acc, *w,
-                     *rc, *ad, stage);
+                     *rc, *ad, *art, stage);
     for (int k = 0; k < nu; ++k) gtau[t * nu + k] = double(ub[k]);
   }
   delete w;
   delete rc;
   delete ad;
+  delete art;
   for (int k = 0; k < nq; ++k) gq0[k] = double(xb[k]);
   for (int k = 0; k < tp.nv; ++k) gqd0[k] = double(xb[nq + k]);
   *gmu = double(mu_acc);

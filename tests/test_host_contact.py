@@ -173,9 +173,10 @@ def test_gradient_fp64_matches_the_oracle(k, adjoint):
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("k", range(len(SCENES)), ids=[sc[0] for sc in SCENES])
 def test_staged_gauss_seidel_is_bitwise_the_plain_one(k, fp64):
-    """The kernels run both Gauss-Seidel solves and their reverse sweeps on
-    a compact staged copy (LDS on the GPU); the same statements in the same
-    order give the same bits as the solves on the full records."""
+    """The gradient kernel runs both Gauss-Seidel solves and their reverse
+    sweeps on a compact staged copy, and the unit-impulse responses on a copy
+    of the articulated quantities (both in LDS on the GPU); the same
+    statements in the same order give the same bits as on the full records."""
     name, s, q0, qd0, tau, links, centers, radii, mu, beta = SCENES[k]
     dt, niter = 1e-3, 30
     T = 50 if name.startswith("quadruped") else 25
