@@ -459,17 +459,24 @@ template <typename S>
 ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi,
                                int niter, const S* sweeps, int ld, S* xb, S* Ab, S* bb, S* lob, S* hib,
                                const PgsStage<S>& g) {
+  // as in pgs_staged: rows at stride kNR, zero beyond m, inner loops over
+  // all kNR columns predicated on j < m
+  for (int i = 0; i < kNR; ++i) {
+    for (int j = 0; j < kNR; ++j) {
+      const bool in = i < m && j < m;
+      g[kStA + i * kNR + j] = in ? A[idx[i] * r + idx[j]] : S(0);
+      g[kStAb + i * kNR + j] = in ? Ab[idx[i] * r + idx[j]] : S(0);
+    }
+    g[kStXb + i] = i < m ? xb[i] : S(0);
+    g[kStX + i] = S(0);
+    g[kStXe + i] = S(0);
+  }
   for (int i = 0; i < m; ++i) {
     const int ri = idx[i];
-    for (int j = 0; j < m; ++j) {
-      g[kStA + i * m + j] = A[ri * r + idx[j]];
-      g[kStAb + i * m + j] = Ab[ri * r + idx[j]];
-    }
     g[kStB + i] = b[ri];
     g[kStBb + i] = bb[ri];
     g[kStLo + i] = lo[i];
     g[kStHi + i] = hi[i];
-    g[kStXb + i] = xb[i];
     g[kStLob + i] = lob[i];
     g[kStHib + i] = hib[i];
   }
@@ -481,27 +488,34 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
     }
     for (int i = m - 1; i >= 0; --i) {
       S d = S(0);
-      for (int j = 0; j < m; ++j)
-        if (j != i) d = d + g[kStA + i * m + j] * (j < i ? g[kStXe + j] : g[kStX + j]);
-      const S y = -(g[kStB + i] + d) / g[kStA + i * m + i];
+#pragma unroll
+      for (int j = 0; j < kNR; ++j) {
+        const S aij = g[kStA + i * kNR + j], xe = g[kStXe + j], xs = g[kStX + j];
+        if (j < m && j != i) d = d + aij * (j < i ? xe : xs);
+      }
+      const S y = -(g[kStB + i] + d) / g[kStA + i * kNR + i];
       S yb = S(0);
       if (val(y) < val(g[kStLo + i])) g[kStLob + i] = g[kStLob + i] + g[kStXb + i];
       else if (val(y) > val(g[kStHi + i])) g[kStHib + i] = g[kStHib + i] + g[kStXb + i];
       else yb = g[kStXb + i];
       g[kStXb + i] = S(0);
-      const S db = -yb / g[kStA + i * m + i];
+      const S db = -yb / g[kStA + i * kNR + i];
       g[kStBb + i] = g[kStBb + i] + db;
-      g[kStAb + i * m + i] = g[kStAb + i * m + i] + db * y;
-      for (int j = 0; j < m; ++j)
-        if (j != i) {
-          g[kStAb + i * m + j] = g[kStAb + i * m + j] + db * (j < i ? g[kStXe + j] : g[kStX + j]);
-          g[kStXb + j] = g[kStXb + j] + db * g[kStA + i * m + j];
+      g[kStAb + i * kNR + i] = g[kStAb + i * kNR + i] + db * y;
+#pragma unroll
+      for (int j = 0; j < kNR; ++j) {
+        const S aij = g[kStA + i * kNR + j], xe = g[kStXe + j], xs = g[kStX + j];
+        const S abij = g[kStAb + i * kNR + j], xbj = g[kStXb + j];
+        if (j < m && j != i) {
+          g[kStAb + i * kNR + j] = abij + db * (j < i ? xe : xs);
+          g[kStXb + j] = xbj + db * aij;
         }
+      }
     }
   }
   for (int i = 0; i < m; ++i) {
     const int ri = idx[i];
-    for (int j = 0; j < m; ++j) Ab[ri * r + idx[j]] = g[kStAb + i * m + j];
+    for (int j = 0; j < m; ++j) Ab[ri * r + idx[j]] = g[kStAb + i * kNR + j];
     bb[ri] = g[kStBb + i];
     xb[i] = g[kStXb + i];
     lob[i] = g[kStLob + i];

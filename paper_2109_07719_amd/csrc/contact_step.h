@@ -255,21 +255,29 @@ constexpr int kStA = 0, kStB = kNR * kNR, kStLo = kStB + kNR, kStHi = kStLo + kN
 template <typename S>
 ABA_HD void pgs_staged(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi, int niter,
                        S* x, S* sweeps, int ld, const PgsStage<S>& g) {
+  // rows of the block at stride kNR, zero beyond m: the inner loops run over
+  // all kNR columns (unrolled, predicated on j < m), so a row's loads issue
+  // together
+  for (int i = 0; i < kNR; ++i) {
+    for (int j = 0; j < kNR; ++j) g[kStA + i * kNR + j] = (i < m && j < m) ? A[idx[i] * r + idx[j]] : S(0);
+    g[kStX + i] = S(0);
+  }
   for (int i = 0; i < m; ++i) {
-    for (int j = 0; j < m; ++j) g[kStA + i * m + j] = A[idx[i] * r + idx[j]];
     g[kStB + i] = b[idx[i]];
     g[kStLo + i] = lo[i];
     g[kStHi + i] = hi[i];
-    g[kStX + i] = S(0);
   }
   for (int it = 0; it < niter; ++it) {
     if (sweeps)
       for (int i = 0; i < m; ++i) sweeps[it * ld + i] = g[kStX + i];
     for (int i = 0; i < m; ++i) {
       S d = S(0);
-      for (int j = 0; j < m; ++j)
-        if (j != i) d = d + g[kStA + i * m + j] * g[kStX + j];
-      S y = -(g[kStB + i] + d) / g[kStA + i * m + i];
+#pragma unroll
+      for (int j = 0; j < kNR; ++j) {
+        const S aij = g[kStA + i * kNR + j], xj = g[kStX + j];
+        if (j < m && j != i) d = d + aij * xj;
+      }
+      S y = -(g[kStB + i] + d) / g[kStA + i * kNR + i];
       if (val(y) < val(g[kStLo + i])) y = g[kStLo + i];
       else if (val(y) > val(g[kStHi + i])) y = g[kStHi + i];
       g[kStX + i] = y;
