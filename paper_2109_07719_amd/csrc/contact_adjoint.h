@@ -156,11 +156,14 @@ ABA_HD void inertia_apply_ib(const S* ib, const S* v, S* o) {
 
 // M^-1 rhs at the step's configuration (zero velocity, no gravity), from
 // the articulated inertias of the step's pass 2 kept in w (U, 1/D, the
-// free root's LDL^T).  rhs and out: [nv].
-template <typename S, typename W>
-ABA_HD void minv_apply(const CTopo& tp, const W& w, const S* rhs, S* out) {
+// free root's LDL^T; an Art copy, whose scratch pA, a, u it uses).  rhs and
+// out: [nv].
+template <typename S>
+ABA_HD void minv_apply(const CTopo& tp, Art<S>& w, const S* rhs, S* out) {
   const int n = tp.n;
-  S pA[kNL][6], a[kNL][6], uu[kNL];
+  S (&pA)[kNL][6] = w.pA;
+  S (&a)[kNL][6] = w.a;
+  S (&uu)[kNL] = w.u;
   for (int i = 0; i < n; ++i)
     for (int k = 0; k < 6; ++k) pA[i][k] = S(0);
   for (int i = n - 1; i >= 0; --i) {
@@ -348,9 +351,12 @@ ABA_HD void id_vjp(const CTopo& tp, const Par<R>& P, const Work<S>& w, const S* 
 // S acc, F = I A, F_parent += X^T F, and the reverse of those).  The free
 // root's row is body-frame, so M does not depend on its pose.
 template <typename S>
-ABA_HD void id_vjp_static(const CTopo& tp, const Art<S>& w, const S* acc, const S* wv, S* gq) {
+ABA_HD void id_vjp_static(const CTopo& tp, Art<S>& w, const S* acc, const S* wv, S* gq) {
   const int n = tp.n;
-  S A[kNL][6], F[kNL][6], Ap[kNL][6];
+  // the copy's scratch (free once minv_apply has returned)
+  S (&A)[kNL][6] = w.pA;
+  S (&F)[kNL][6] = w.a;
+  S (&Ap)[kNL][6] = w.s3;
   for (int i = 0; i < n; ++i) {
     const int p = tp.parent[i];
     if (tp.jtype[i] == SIM_JOINT_FREE) {

@@ -161,7 +161,7 @@ template <typename S>
 struct Art {
   S E[kNL][9], r[kNL][3], ax[kNL][3], U[kNL][6], Dinv[kNL], L0[36], D0[6];
   S Ib[kNL][10];  // mass, centre of mass (3), inertia about it (xx yy zz xy xz yz)
-  S pA[kNL][6], a[kNL][6], u[kNL];
+  S pA[kNL][6], a[kNL][6], u[kNL], s3[kNL][6];  // scratch of the responses and of the adjoint's solves
   S pad_;
 };
 
