@@ -486,11 +486,13 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
     g[kStLob + i] = lob[i];
     g[kStHib + i] = hib[i];
   }
+  for (int j = 0; j < m; ++j) g[kStX + j] = sweeps[niter * ld + j];
   for (int it = niter - 1; it >= 0; --it) {
-    // x at the start (xs) and at the end (xe) of sweep it
+    // x at the start (xs) and at the end (xe) of sweep it; xe is the
+    // previous sweep's xs, already staged
     for (int j = 0; j < m; ++j) {
+      g[kStXe + j] = g[kStX + j];
       g[kStX + j] = sweeps[it * ld + j];
-      g[kStXe + j] = sweeps[(it + 1) * ld + j];
     }
     for (int i = m - 1; i >= 0; --i) {
       S d = S(0);
