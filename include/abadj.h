@@ -477,12 +477,17 @@ int sim_pgs_adjoint(int dtype, int batch, int n, int niter, const void *A, const
  * chooses how many share a wavefront: rollout_systems_per_wave in {8, 4, 2}
  * (two wavefronts per workgroup in FP32, one in FP64; each system's
  * articulated quantities sit in LDS), grad_systems_per_wave in {16, 8, 4}
- * (one wavefront per workgroup).  Fewer per wavefront spread a small batch
- * over more CUs.  Every geometry computes the same results bit for bit;
- * sim_contact_autotune picks the fastest for a batch. */
+ * (one wavefront per workgroup), and where the gradient keeps each
+ * system's Gauss-Seidel and articulated working copies: grad_lds = 1 in LDS
+ * (at most 16 systems per CU at a time), 0 in private memory (every system
+ * in flight at once; only with 16 systems per wavefront).  Fewer per
+ * wavefront spread a small batch over more CUs.  Every geometry computes
+ * the same results bit for bit; sim_contact_autotune picks the fastest for
+ * a batch. */
 typedef struct {
   int rollout_systems_per_wave;
   int grad_systems_per_wave;
+  int grad_lds;
 } sim_contact_tiling_t;
 
 typedef struct {
@@ -497,7 +502,7 @@ typedef struct {
   const double *limits;               /* nullable [4 n]: joint limits (lo, hi, k, d) of the
                                          1-dof joints, shared by the batch, as in
                                          sim_params (ignored for the free root) */
-  const sim_contact_tiling_t *tiling; /* nullable: 8 and 16 systems per wavefront */
+  const sim_contact_tiling_t *tiling; /* nullable: 8 and 16 systems per wavefront, LDS */
 } sim_contact_model;
 
 /* Sizes of the model's state, control and parameter vectors (each output

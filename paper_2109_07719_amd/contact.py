@@ -22,7 +22,8 @@ _DT = {torch.float32: N.SIM_F32, torch.float64: N.SIM_F64}
 
 
 class _Tiling(ctypes.Structure):
-    _fields_ = [("rollout_systems_per_wave", ctypes.c_int), ("grad_systems_per_wave", ctypes.c_int)]
+    _fields_ = [("rollout_systems_per_wave", ctypes.c_int), ("grad_systems_per_wave", ctypes.c_int),
+                ("grad_lds", ctypes.c_int)]
 
 
 class _Model(ctypes.Structure):
@@ -68,7 +69,7 @@ class ContactBatch:
         self.jtype = np.ascontiguousarray(s0.jtype, dtype=np.int32)
         self.clink = np.ascontiguousarray(np.asarray(contact_link, dtype=np.int32).reshape(-1))
         # launch geometry (sim_contact_tiling_t), kept alive with the model that points at it
-        self._tiling = _Tiling(8, 16)
+        self._tiling = _Tiling(8, 16, 1)
         self.m = _Model(int(s0.n), self.parent.ctypes.data, self.jtype.ctypes.data, int(self.clink.size),
                         self.clink.ctypes.data if self.clink.size else None, float(mu), float(beta), int(niter),
                         (ctypes.c_double * 3)(*[float(g) for g in gravity]),
@@ -85,15 +86,19 @@ class ContactBatch:
 
     @property
     def tiling(self) -> dict:
-        """Systems per wavefront of the rollout and of the gradient kernels."""
+        """Systems per wavefront of the rollout and of the gradient kernels,
+        and whether the gradient keeps its working copies in LDS."""
         return {"rollout_systems_per_wave": self._tiling.rollout_systems_per_wave,
-                "grad_systems_per_wave": self._tiling.grad_systems_per_wave}
+                "grad_systems_per_wave": self._tiling.grad_systems_per_wave, "grad_lds": self._tiling.grad_lds}
 
-    def set_tiling(self, rollout_systems_per_wave: int = 8, grad_systems_per_wave: int = 16) -> None:
+    def set_tiling(self, rollout_systems_per_wave: int = 8, grad_systems_per_wave: int = 16,
+                   grad_lds: int = 1) -> None:
         """Launch geometry of the next calls (rollout: 8, 4 or 2; gradient: 16,
-        8 or 4; the library rejects other values at the call)."""
+        8 or 4 with grad_lds 1, or 16 with grad_lds 0; the library rejects
+        other values at the call)."""
         self._tiling.rollout_systems_per_wave = int(rollout_systems_per_wave)
         self._tiling.grad_systems_per_wave = int(grad_systems_per_wave)
+        self._tiling.grad_lds = int(grad_lds)
 
     def autotune(self, q0, qd0, tau, dt) -> dict:
         """Times T = tau.shape[0] probe steps of the rollout and its gradient at
@@ -108,7 +113,7 @@ class ContactBatch:
                                              _ptr(qd0), _ptr(tau), float(dt), T,
                                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
                                              ctypes.byref(chosen), ctypes.byref(rms), ctypes.byref(gms)))
-        self.set_tiling(chosen.rollout_systems_per_wave, chosen.grad_systems_per_wave)
+        self.set_tiling(chosen.rollout_systems_per_wave, chosen.grad_systems_per_wave, chosen.grad_lds)
         return dict(self.tiling, rollout_ms_per_probe_step=rms.value, grad_ms_per_probe_step=gms.value)
 
     def _check(self, t, shape, name):

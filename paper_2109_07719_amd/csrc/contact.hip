@@ -184,19 +184,30 @@ struct GradArgs {
 // 32 per wave 993 ms.
 // SPL is a launch choice here too (16, the default, 8 or 4 systems per wave,
 // one wave per workgroup): a smaller batch reaches more CUs with fewer.
-template <typename S, typename R, int SPL>
+// LDS (the default): each system's Gauss-Seidel working copies (PgsStage,
+// one LDS column per lane) and its copy of the articulated quantities with
+// the solves' scratch (Art) sit in LDS, where the solves' and the
+// responses' inner loops see LDS rather than private-memory latency; that
+// holds a CU to 16 systems at a time (160 KiB).  Without it (the same
+// copies in private memory) every system of a large batch is in flight at
+// once; the autotuner picks.
+template <typename S, typename R, int SPL, bool LDS>
 __global__ __launch_bounds__(kWave) void k_contact_adj(GradArgs<S> a) {
   constexpr int SPW = SPL;
   static_assert(SPL <= kWave, "one wave per workgroup");
-  // each system's Gauss-Seidel working copies (PgsStage), one LDS column per
-  // lane: the solves' inner loops read LDS instead of private memory
-  __shared__ R stg[kStage * SPW];
-  __shared__ Art<R> art_sh[SPW];
+  __shared__ R stg[LDS ? kStage * SPW : 1];
+  __shared__ Art<R> art_sh[LDS ? SPW : 1];
   const int ln = threadIdx.x % kWave;
   const int sw = (threadIdx.x / kWave) * SPL + ln;
   const int s = blockIdx.x * SPW + sw;
   if (ln >= SPL || s >= a.B) return;
-  const PgsStage<R> stage{stg + sw, SPW};
+  // without LDS the same staged statements run on private copies, so the
+  // two placements compile to the same arithmetic (the same multiply-adds
+  // fused) and give the same bits
+  R stg_priv[LDS ? 1 : kStage];
+  const PgsStage<R> stage{LDS ? stg + sw : stg_priv, LDS ? SPW : 1};
+  Art<R> art_priv;
+  Art<R>& art = LDS ? art_sh[sw] : art_priv;
   // the model's constants as the forward rollout saw them (rounded to S)
   CTopo tp = a.tp;
   for (int k = 0; k < 3; ++k) tp.g[k] = double(S(tp.g[k]));
@@ -217,7 +228,7 @@ __global__ __launch_bounds__(kWave) void k_contact_adj(GradArgs<S> a) {
   for (int t = a.T - 1; t >= 0; --t) {
     for (int k = 0; k < nx; ++k) x[k] = R(a.traj[((size_t)t * nx + k) * B + s]);
     for (int k = 0; k < nu; ++k) u[k] = R(a.tau[((size_t)t * nu + k) * B + s]);
-    contact_step_vjp(tp, P, x, x + nq, u, a.dt, R(tp.mu), xb, ub, mub, w, rc, ad, art_sh[sw], stage);
+    contact_step_vjp(tp, P, x, x + nq, u, a.dt, R(tp.mu), xb, ub, mub, w, rc, ad, art, stage);
     for (int k = 0; k < nu; ++k) a.gtau[((size_t)t * nu + k) * B + s] = S(ub[k]);
   }
   for (int k = 0; k < nq; ++k) a.gq0[k * B + s] = S(xb[k]);
@@ -244,13 +255,17 @@ hipError_t launch_rollout(const RollArgs<R>& a, int spl, hipStream_t st) {
   return hipGetLastError();
 }
 template <typename S>
-hipError_t launch_grad(const GradArgs<S>& a, int spl, hipStream_t st) {
+hipError_t launch_grad(const GradArgs<S>& a, int spl, bool lds, hipStream_t st) {
   // both dtypes reverse in FP64
   const dim3 grid((a.B + spl - 1) / spl), block(kWave);
+  if (!lds) {
+    hipLaunchKernelGGL((k_contact_adj<S, double, 16, false>), grid, block, 0, st, a);
+    return hipGetLastError();
+  }
   switch (spl) {
-    case 16: hipLaunchKernelGGL((k_contact_adj<S, double, 16>), grid, block, 0, st, a); break;
-    case 8: hipLaunchKernelGGL((k_contact_adj<S, double, 8>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_contact_adj<S, double, 4>), grid, block, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_contact_adj<S, double, 16, true>), grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_contact_adj<S, double, 8, true>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_contact_adj<S, double, 4, true>), grid, block, 0, st, a); break;
   }
   return hipGetLastError();
 }
@@ -265,9 +280,12 @@ int make_topo(const char* who, const sim_contact_model* m, CTopo* tp) {
   if (m->niter < 0 || !(m->mu >= 0) || !(m->beta >= 0))
     return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": need niter >= 0, mu >= 0, beta >= 0");
   if (m->tiling && (!roll_spl_ok(m->tiling->rollout_systems_per_wave) ||
-                    !grad_spl_ok(m->tiling->grad_systems_per_wave)))
-    return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": tiling needs rollout_systems_per_wave in {8, 4, 2} "
-                                                         "and grad_systems_per_wave in {16, 8, 4}");
+                    !grad_spl_ok(m->tiling->grad_systems_per_wave) ||
+                    (m->tiling->grad_lds != 0 && m->tiling->grad_lds != 1) ||
+                    (m->tiling->grad_lds == 0 && m->tiling->grad_systems_per_wave != 16)))
+    return cfail(SIM_ERR_INVALID_ARG, std::string(who) + ": tiling needs rollout_systems_per_wave in {8, 4, 2}, "
+                                                         "grad_systems_per_wave in {16, 8, 4} and grad_lds 1, "
+                                                         "or grad_systems_per_wave 16 with grad_lds 0");
   *tp = CTopo{};
   tp->n = m->n;
   tp->nc = m->ncontacts;
@@ -420,17 +438,18 @@ int sim_contact_rollout_grad(const sim_contact_model* m, int dtype, int batch, c
   if (!params || !traj || !gqT || !gqdT || !gq0 || !gqd0 || (T > 0 && tp.nu > 0 && (!tau || !gtau)))
     return cfail(SIM_ERR_INVALID_ARG, "sim_contact_rollout_grad: null array argument");
   const int spl = m->tiling ? m->tiling->grad_systems_per_wave : kGradSplDefault;
+  const bool lds = m->tiling ? m->tiling->grad_lds != 0 : true;
   hipError_t e;
   if (dtype == SIM_F64) {
     GradArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)traj, (const double*)tau,
                        (const double*)gqT, (const double*)gqdT, (double*)gq0, (double*)gqd0, (double*)gtau,
                        (double*)gmu};
-    e = launch_grad(a, spl, (hipStream_t)stream);
+    e = launch_grad(a, spl, lds, (hipStream_t)stream);
   } else {
     GradArgs<float> a{tp, batch, T, (float)dt, (const float*)params, (const float*)traj, (const float*)tau,
                       (const float*)gqT, (const float*)gqdT, (float*)gq0, (float*)gqd0, (float*)gtau,
                       (float*)gmu};
-    e = launch_grad(a, spl, (hipStream_t)stream);
+    e = launch_grad(a, spl, lds, (hipStream_t)stream);
   }
   if (e != hipSuccess)
     return cfail(SIM_ERR_HIP, std::string("sim_contact_rollout_grad: launch failed: ") + hipGetErrorString(e));
@@ -473,9 +492,9 @@ int sim_contact_autotune(const sim_contact_model* m, int dtype, int batch, const
   void* gqdT = take(nv * B);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   sim_contact_model mm = *m;
-  sim_contact_tiling_t t{kRollSplDefault, kGradSplDefault};
+  sim_contact_tiling_t t{kRollSplDefault, kGradSplDefault, 1};
   mm.tiling = &t;
-  int best_r = kRollSplDefault, best_g = kGradSplDefault;
+  int best_r = kRollSplDefault, best_g = kGradSplDefault, best_l = 1;
   float ms_r = 0.f, ms_g = 0.f;
   rc = SIM_OK;
   do {
@@ -496,7 +515,7 @@ int sim_contact_autotune(const sim_contact_model* m, int dtype, int batch, const
         return cfail(SIM_ERR_HIP, "sim_contact_autotune: timing failed");
       return SIM_OK;
     };
-    const int rspl[3] = {8, 4, 2}, gspl[3] = {16, 8, 4};
+    const int rspl[3] = {8, 4, 2}, gspl[4] = {16, 8, 4, 16}, glds[4] = {1, 1, 1, 0};
     for (int k = 0; k < 3 && !rc; ++k) {
       t.rollout_systems_per_wave = rspl[k];
       float ms = 0.f;
@@ -504,12 +523,13 @@ int sim_contact_autotune(const sim_contact_model* m, int dtype, int batch, const
                                                   nullptr, stream); }, &ms);
       if (!rc && (k == 0 || ms < ms_r)) { ms_r = ms; best_r = rspl[k]; }
     }
-    for (int k = 0; k < 3 && !rc; ++k) {
+    for (int k = 0; k < 4 && !rc; ++k) {
       t.grad_systems_per_wave = gspl[k];
+      t.grad_lds = glds[k];
       float ms = 0.f;
       rc = timed([&] { return sim_contact_rollout_grad(&mm, dtype, batch, params, traj, tau, dt, T_probe, gqT, gqdT,
                                                        gq0, gqd0, gtau, nullptr, stream); }, &ms);
-      if (!rc && (k == 0 || ms < ms_g)) { ms_g = ms; best_g = gspl[k]; }
+      if (!rc && (k == 0 || ms < ms_g)) { ms_g = ms; best_g = gspl[k]; best_l = glds[k]; }
     }
   } while (false);
   (void)hipStreamSynchronize(st);
@@ -519,6 +539,7 @@ int sim_contact_autotune(const sim_contact_model* m, int dtype, int batch, const
   if (rc) return rc;
   chosen->rollout_systems_per_wave = best_r;
   chosen->grad_systems_per_wave = best_g;
+  chosen->grad_lds = best_l;
   if (rollout_ms) *rollout_ms = ms_r / T_probe;
   if (grad_ms) *grad_ms = ms_g / T_probe;
   return SIM_OK;

@@ -299,8 +299,8 @@ def test_every_tiling_gives_the_same_bits(dtype):
     gqT = torch.tensor(rng.normal(size=(cb.nq, cb.B)), dtype=dtype, device=DEV)
     gqdT = torch.tensor(rng.normal(size=(cb.nv, cb.B)), dtype=dtype, device=DEV)
     ref = None
-    for rs, gs in ((8, 16), (4, 8), (2, 4), (8, 4), (2, 16)):
-        cb.set_tiling(rs, gs)
+    for rs, gs, gl in ((8, 16, 1), (4, 8, 1), (2, 4, 1), (8, 4, 1), (2, 16, 1), (8, 16, 0)):
+        cb.set_tiling(rs, gs, gl)
         qT, qdT, tr, nc = cb.rollout(q0, qd0, tau, DT, counts=True)
         g = cb.grad(tr, tau, DT, gqT, gqdT, mu_grad=True)
         out = [x.cpu().numpy() for x in (qT, qdT, tr, nc) + tuple(g)]
@@ -309,12 +309,13 @@ def test_every_tiling_gives_the_same_bits(dtype):
             assert int(out[3].max()) >= 2
         else:
             for a, b in zip(out, ref):
-                assert np.array_equal(a, b), (rs, gs)
+                assert np.array_equal(a, b), (rs, gs, gl)
     tune = cb.autotune(q0, qd0, tau[:10], DT)
     print("autotune", tune)
     assert tune["rollout_systems_per_wave"] in (8, 4, 2) and tune["grad_systems_per_wave"] in (16, 8, 4)
+    assert tune["grad_lds"] in (0, 1)
     assert tune["rollout_ms_per_probe_step"] > 0 and tune["grad_ms_per_probe_step"] > 0
-    assert cb.tiling == {k: tune[k] for k in ("rollout_systems_per_wave", "grad_systems_per_wave")}
+    assert cb.tiling == {k: tune[k] for k in ("rollout_systems_per_wave", "grad_systems_per_wave", "grad_lds")}
     qT, qdT, tr = cb.rollout(q0, qd0, tau, DT)
     assert np.array_equal(tr.cpu().numpy(), ref[2])
 

@@ -114,8 +114,9 @@ def test_null_arguments_are_rejected():
     from paper_2109_07719_amd.contact import _Model, _Tiling
     par, jt, cl = (np.array(v, np.int32) for v in ([-1, 0], [N.SIM_JOINT_FREE, N.SIM_JOINT_REVOLUTE], [1]))
     sizes = [ctypes.c_int() for _ in range(4)]
-    for tiling, ok in (((8, 16), True), ((2, 4), True), ((4, 8), True), ((3, 16), False), ((8, 32), False),
-                       ((16, 16), False)):
+    for tiling, ok in (((8, 16, 1), True), ((2, 4, 1), True), ((4, 8, 1), True), ((8, 16, 0), True),
+                       ((3, 16, 1), False), ((8, 32, 1), False), ((16, 16, 1), False), ((8, 8, 0), False),
+                       ((8, 16, 2), False)):
         t = _Tiling(*tiling)
         m = _Model(2, par.ctypes.data, jt.ctypes.data, 1, cl.ctypes.data, 0.5, 0.0, 10,
                    (ctypes.c_double * 3)(0.0, -9.81, 0.0), None, ctypes.addressof(t))
