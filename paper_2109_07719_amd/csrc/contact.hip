@@ -208,13 +208,10 @@ __global__ __launch_bounds__(kWave) void k_contact_adj(GradArgs<S> a) {
   const PgsStage<R> stage{LDS ? stg + sw : stg_priv, LDS ? SPW : 1};
   Art<R> art_priv;
   Art<R>& art = LDS ? art_sh[sw] : art_priv;
-  // the model's constants as the forward rollout saw them (rounded to S)
-  CTopo tp = a.tp;
-  for (int k = 0; k < 3; ++k) tp.g[k] = double(S(tp.g[k]));
-  tp.mu = double(S(tp.mu));
-  tp.beta = double(S(tp.beta));
-  for (int i = 0; i < kNL; ++i)
-    for (int k = 0; k < 4; ++k) tp.lim[i][k] = double(S(tp.lim[i][k]));
+  // read in place from the kernel arguments (a uniform scalar load per
+  // topology entry; a local copy would live in scratch, one per lane); its
+  // constants arrive rounded to S (constants_as_seen_by)
+  const CTopo& tp = a.tp;
   const size_t B = (size_t)a.B;
   const Par<S> P{a.P, B, s};
   const int nq = tp.nq, nv = tp.nv, nu = tp.nu, nx = nq + nv;
@@ -254,6 +251,18 @@ hipError_t launch_rollout(const RollArgs<R>& a, int spl, hipStream_t st) {
   }
   return hipGetLastError();
 }
+// The model's constants as a rollout in S saw them (rounded to S), for the
+// reverse pass, which runs in FP64 for both dtypes.
+template <typename S>
+CTopo constants_as_seen_by(CTopo tp) {
+  for (int k = 0; k < 3; ++k) tp.g[k] = double(S(tp.g[k]));
+  tp.mu = double(S(tp.mu));
+  tp.beta = double(S(tp.beta));
+  for (int i = 0; i < kNL; ++i)
+    for (int k = 0; k < 4; ++k) tp.lim[i][k] = double(S(tp.lim[i][k]));
+  return tp;
+}
+
 template <typename S>
 hipError_t launch_grad(const GradArgs<S>& a, int spl, bool lds, hipStream_t st) {
   // both dtypes reverse in FP64
@@ -441,12 +450,12 @@ int sim_contact_rollout_grad(const sim_contact_model* m, int dtype, int batch, c
   const bool lds = m->tiling ? m->tiling->grad_lds != 0 : true;
   hipError_t e;
   if (dtype == SIM_F64) {
-    GradArgs<double> a{tp, batch, T, dt, (const double*)params, (const double*)traj, (const double*)tau,
+    GradArgs<double> a{constants_as_seen_by<double>(tp), batch, T, dt, (const double*)params, (const double*)traj, (const double*)tau,
                        (const double*)gqT, (const double*)gqdT, (double*)gq0, (double*)gqd0, (double*)gtau,
                        (double*)gmu};
     e = launch_grad(a, spl, lds, (hipStream_t)stream);
   } else {
-    GradArgs<float> a{tp, batch, T, (float)dt, (const float*)params, (const float*)traj, (const float*)tau,
+    GradArgs<float> a{constants_as_seen_by<float>(tp), batch, T, (float)dt, (const float*)params, (const float*)traj, (const float*)tau,
                       (const float*)gqT, (const float*)gqdT, (float*)gq0, (float*)gqd0, (float*)gtau,
                       (float*)gmu};
     e = launch_grad(a, spl, lds, (hipStream_t)stream);

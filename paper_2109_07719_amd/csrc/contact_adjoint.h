@@ -603,11 +603,19 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
   if (na > 0) {
     // ---- impulses: qd1 = qd_minus + MJ x
     S xb[kNR];
+    S gv[kNV];
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) gv[k] = k < nv ? qd1b[k] : S(0);
     for (int j = 0; j < r; ++j) {
       S s = S(0);
-      for (int k = 0; k < nv; ++k) s = s + w.MJ[k][j] * qd1b[k];
+      const S xj = w.x[j];
+#pragma unroll
+      for (int k = 0; k < kNV; ++k)
+        if (k < nv) {
+          s = s + w.MJ[k][j] * gv[k];
+          ad.MJb[k][j] = gv[k] * xj;
+        }
       xb[j] = s;
-      for (int k = 0; k < nv; ++k) ad.MJb[k][j] = qd1b[k] * w.x[j];
     }
     for (int k = 0; k < r * r; ++k) ad.Ab[k] = S(0);
     for (int i = 0; i < r; ++i) ad.bb[i] = S(0);
@@ -658,21 +666,36 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
     const S bdt = S(tp.beta) / dt;
     S phib[kNC];
     for (int c = 0; c < na; ++c) phib[c] = S(0);
+    // (row i of A_bar, then column k of J, held in registers; the sums
+    // unrolled and predicated on r so that their loads issue together, in
+    // the same order)
     for (int i = 0; i < r; ++i) {
+      S Abi[kNR];
+#pragma unroll
+      for (int j = 0; j < kNR; ++j) Abi[j] = j < r ? ad.Ab[i * r + j] : S(0);
+      const S bbi = ad.bb[i];
       for (int k = 0; k < nv; ++k) {
-        S s = ad.bb[i] * rc.qdm[k];
-        for (int j = 0; j < r; ++j) s = s + ad.Ab[i * r + j] * w.MJ[k][j];
+        S s = bbi * rc.qdm[k];
+#pragma unroll
+        for (int j = 0; j < kNR; ++j)
+          if (j < r) s = s + Abi[j] * w.MJ[k][j];
         ad.Jb[i][k] = s;
-        qdmb[k] = qdmb[k] + w.J[i][k] * ad.bb[i];
+        qdmb[k] = qdmb[k] + w.J[i][k] * bbi;
       }
-      if (i % 3 == 0) phib[i / 3] = phib[i / 3] + bdt * ad.bb[i];
+      if (i % 3 == 0) phib[i / 3] = phib[i / 3] + bdt * bbi;
     }
-    for (int k = 0; k < nv; ++k)
+    for (int k = 0; k < nv; ++k) {
+      S Jk[kNR];
+#pragma unroll
+      for (int i = 0; i < kNR; ++i) Jk[i] = i < r ? w.J[i][k] : S(0);
       for (int j = 0; j < r; ++j) {
         S s = S(0);
-        for (int i = 0; i < r; ++i) s = s + w.J[i][k] * ad.Ab[i * r + j];
+#pragma unroll
+        for (int i = 0; i < kNR; ++i)
+          if (i < r) s = s + Jk[i] * ad.Ab[i * r + j];
         ad.MJb[k][j] = ad.MJb[k][j] + s;
       }
+    }
     // ---- MJ = M^-1 J^T: W = M^-1 MJ_bar; J_bar += W^T; q_bar -= d/dq <W, M(q) MJ>
     for (int j = 0; j < r; ++j) {
       S col[kNV], Wj[kNV], mj[kNV];

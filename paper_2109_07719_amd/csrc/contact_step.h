@@ -601,13 +601,23 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
     const S bdt = S(tp.beta) / dt;
     Rl dmax = Rl(0);
     for (int i = 0; i < r; ++i) {
+      // row i of J held in registers; the sums over k unrolled and
+      // predicated on nv, so that their loads issue together (the same
+      // operations in the same order)
+      S Ji[kNV];
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) Ji[k] = k < nv ? w.J[i][k] : S(0);
       for (int j = 0; j < r; ++j) {
         S s = S(0);
-        for (int k = 0; k < nv; ++k) s = s + w.J[i][k] * w.MJ[k][j];
+#pragma unroll
+        for (int k = 0; k < kNV; ++k)
+          if (k < nv) s = s + Ji[k] * w.MJ[k][j];
         w.A[i * r + j] = s;
       }
       S s = S(0);
-      for (int k = 0; k < nv; ++k) s = s + w.J[i][k] * qd1[k];
+#pragma unroll
+      for (int k = 0; k < kNV; ++k)
+        if (k < nv) s = s + Ji[k] * qd1[k];
       w.b[i] = (i % 3 == 0) ? s + bdt * phi[i / 3] : s;
       if (val(w.A[i * r + i]) > dmax) dmax = val(w.A[i * r + i]);
     }
@@ -644,9 +654,14 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
     }
     for (int j = 0; j < r; ++j) w.x[j] = S(0);
     for (int i = 0; i < nk; ++i) w.x[keep[i]] = xk[i];
+    S xr[kNR];
+#pragma unroll
+    for (int j = 0; j < kNR; ++j) xr[j] = j < r ? w.x[j] : S(0);
     for (int k = 0; k < nv; ++k) {
       S s = S(0);
-      for (int j = 0; j < r; ++j) s = s + w.MJ[k][j] * w.x[j];
+#pragma unroll
+      for (int j = 0; j < kNR; ++j)
+        if (j < r) s = s + w.MJ[k][j] * xr[j];
       qd1[k] = qd1[k] + s;
     }
   }
