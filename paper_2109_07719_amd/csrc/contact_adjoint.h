@@ -439,7 +439,7 @@ ABA_HD void pgs_reverse(int m, const int* idx, int r, const S* A, const S* b, co
       const int ri = idx[i];
       S d = S(0);
       for (int j = 0; j < m; ++j)
-        if (j != i) d = d + A[ri * r + idx[j]] * (j < i ? xe[j] : xs[j]);
+        if (j != i) d = fmadd(A[ri * r + idx[j]], j < i ? xe[j] : xs[j], d);
       const S y = -(b[ri] + d) / A[ri * r + ri];
       S yb = S(0);
       if (val(y) < val(lo[i])) lob[i] = lob[i] + xb[i];
@@ -448,32 +448,33 @@ ABA_HD void pgs_reverse(int m, const int* idx, int r, const S* A, const S* b, co
       xb[i] = S(0);
       const S db = -yb / A[ri * r + ri];
       bb[ri] = bb[ri] + db;
-      Ab[ri * r + ri] = Ab[ri * r + ri] + db * y;
+      Ab[ri * r + ri] = fmadd(db, y, Ab[ri * r + ri]);
       for (int j = 0; j < m; ++j)
         if (j != i) {
-          Ab[ri * r + idx[j]] = Ab[ri * r + idx[j]] + db * (j < i ? xe[j] : xs[j]);
-          xb[j] = xb[j] + db * A[ri * r + idx[j]];
+          Ab[ri * r + idx[j]] = fmadd(db, j < i ? xe[j] : xs[j], Ab[ri * r + idx[j]]);
+          xb[j] = fmadd(db, A[ri * r + idx[j]], xb[j]);
         }
     }
   }
 }
 
-// pgs_reverse on a staged copy (PgsStage): the adjoints are gathered with
-// their current values and written back, and every statement runs in the
-// order of pgs_reverse, so the result is bitwise the same.
+// pgs_reverse on a staged copy (PgsStage): every statement runs in the
+// order of pgs_reverse, so the result is bitwise the same.  A sweep's row
+// values y_i depend only on the stored sweep vectors, not on the adjoints,
+// so they are computed for all rows first (independent chains), then the
+// adjoint rows run last to first with x_bar held in registers; rows and
+// columns are unrolled over kNR and predicated on m.
 template <typename S>
 ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi,
                                int niter, const S* sweeps, int ld, S* xb, S* Ab, S* bb, S* lob, S* hib,
                                const PgsStage<S>& g) {
-  // as in pgs_staged: rows at stride kNR, zero beyond m, inner loops over
-  // all kNR columns predicated on j < m
+  // as in pgs_staged: rows at stride kNR, zero beyond m
   for (int i = 0; i < kNR; ++i) {
     for (int j = 0; j < kNR; ++j) {
       const bool in = i < m && j < m;
       g[kStA + i * kNR + j] = in ? A[idx[i] * r + idx[j]] : S(0);
       g[kStAb + i * kNR + j] = in ? Ab[idx[i] * r + idx[j]] : S(0);
     }
-    g[kStXb + i] = i < m ? xb[i] : S(0);
     g[kStX + i] = S(0);
     g[kStXe + i] = S(0);
   }
@@ -486,6 +487,9 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
     g[kStLob + i] = lob[i];
     g[kStHib + i] = hib[i];
   }
+  S xbr[kNR];
+#pragma unroll
+  for (int i = 0; i < kNR; ++i) xbr[i] = i < m ? xb[i] : S(0);
   for (int j = 0; j < m; ++j) g[kStX + j] = sweeps[niter * ld + j];
   for (int it = niter - 1; it >= 0; --it) {
     // x at the start (xs) and at the end (xe) of sweep it; xe is the
@@ -494,41 +498,47 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
       g[kStXe + j] = g[kStX + j];
       g[kStX + j] = sweeps[it * ld + j];
     }
-    for (int i = m - 1; i >= 0; --i) {
-      S d = S(0);
+    S y[kNR];
 #pragma unroll
-      for (int j = 0; j < kNR; ++j) {
-        const S aij = g[kStA + i * kNR + j], xe = g[kStXe + j], xs = g[kStX + j];
-        if (j < m && j != i) d = d + aij * (j < i ? xe : xs);
+    for (int i = 0; i < kNR; ++i) {
+      y[i] = S(0);
+      if (i < m) {
+        S d = S(0);
+#pragma unroll
+        for (int j = 0; j < kNR; ++j)
+          if (j < m && j != i) d = fmadd(g[kStA + i * kNR + j], j < i ? g[kStXe + j] : g[kStX + j], d);
+        y[i] = -(g[kStB + i] + d) / g[kStA + i * kNR + i];
       }
-      const S y = -(g[kStB + i] + d) / g[kStA + i * kNR + i];
+    }
+#pragma unroll
+    for (int i = kNR - 1; i >= 0; --i) {
+      if (i >= m) continue;
       S yb = S(0);
-      if (val(y) < val(g[kStLo + i])) g[kStLob + i] = g[kStLob + i] + g[kStXb + i];
-      else if (val(y) > val(g[kStHi + i])) g[kStHib + i] = g[kStHib + i] + g[kStXb + i];
-      else yb = g[kStXb + i];
-      g[kStXb + i] = S(0);
+      if (val(y[i]) < val(g[kStLo + i])) g[kStLob + i] = g[kStLob + i] + xbr[i];
+      else if (val(y[i]) > val(g[kStHi + i])) g[kStHib + i] = g[kStHib + i] + xbr[i];
+      else yb = xbr[i];
+      xbr[i] = S(0);
       const S db = -yb / g[kStA + i * kNR + i];
       g[kStBb + i] = g[kStBb + i] + db;
-      g[kStAb + i * kNR + i] = g[kStAb + i * kNR + i] + db * y;
+      g[kStAb + i * kNR + i] = fmadd(db, y[i], g[kStAb + i * kNR + i]);
 #pragma unroll
-      for (int j = 0; j < kNR; ++j) {
-        const S aij = g[kStA + i * kNR + j], xe = g[kStXe + j], xs = g[kStX + j];
-        const S abij = g[kStAb + i * kNR + j], xbj = g[kStXb + j];
+      for (int j = 0; j < kNR; ++j)
         if (j < m && j != i) {
-          g[kStAb + i * kNR + j] = abij + db * (j < i ? xe : xs);
-          g[kStXb + j] = xbj + db * aij;
+          g[kStAb + i * kNR + j] = fmadd(db, j < i ? g[kStXe + j] : g[kStX + j], g[kStAb + i * kNR + j]);
+          xbr[j] = fmadd(db, g[kStA + i * kNR + j], xbr[j]);
         }
-      }
     }
   }
   for (int i = 0; i < m; ++i) {
     const int ri = idx[i];
     for (int j = 0; j < m; ++j) Ab[ri * r + idx[j]] = g[kStAb + i * kNR + j];
     bb[ri] = g[kStBb + i];
-    xb[i] = g[kStXb + i];
     lob[i] = g[kStLob + i];
     hib[i] = g[kStHib + i];
   }
+#pragma unroll
+  for (int i = 0; i < kNR; ++i)
+    if (i < m) xb[i] = xbr[i];
 }
 
 // Adjoint state of one reverse step with contact.
@@ -612,7 +622,7 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
 #pragma unroll
       for (int k = 0; k < kNV; ++k)
         if (k < nv) {
-          s = s + w.MJ[k][j] * gv[k];
+          s = fmadd(w.MJ[k][j], gv[k], s);
           ad.MJb[k][j] = gv[k] * xj;
         }
       xb[j] = s;
@@ -678,9 +688,9 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
         S s = bbi * rc.qdm[k];
 #pragma unroll
         for (int j = 0; j < kNR; ++j)
-          if (j < r) s = s + Abi[j] * w.MJ[k][j];
+          if (j < r) s = fmadd(Abi[j], w.MJ[k][j], s);
         ad.Jb[i][k] = s;
-        qdmb[k] = qdmb[k] + w.J[i][k] * bbi;
+        qdmb[k] = fmadd(w.J[i][k], bbi, qdmb[k]);
       }
       if (i % 3 == 0) phib[i / 3] = phib[i / 3] + bdt * bbi;
     }
@@ -692,7 +702,7 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
         S s = S(0);
 #pragma unroll
         for (int i = 0; i < kNR; ++i)
-          if (i < r) s = s + Jk[i] * ad.Ab[i * r + j];
+          if (i < r) s = fmadd(Jk[i], ad.Ab[i * r + j], s);
         ad.MJb[k][j] = ad.MJb[k][j] + s;
       }
     }

@@ -56,6 +56,16 @@ ABA_HD Dual<R> sq_root(const Dual<R>& x) {
   return Dual<R>(s, x.d / (R(2) * s));
 }
 
+// a * b + c as one fused multiply-add.  The sums of products written with
+// it round the same way in every kernel variant that runs them: left to the
+// compiler, a sum whose first two terms are products (a b + c d, as an
+// unrolled sum from zero becomes) may be fused either way round, and which
+// way can differ between two builds of the same statements.
+ABA_HD float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+ABA_HD double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T>  // dual numbers, the operation counter
+ABA_HD T fmadd(const T& a, const T& b, const T& c) { return a * b + c; }
+
 template <typename R> struct Big;
 template <> struct Big<float> { static constexpr float v = FLT_MAX; };
 template <> struct Big<double> { static constexpr double v = 1e300; };
@@ -223,7 +233,7 @@ ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* l
       const int ri = idx[i];
       S d = S(0);
       for (int j = 0; j < m; ++j)
-        if (j != i) d = d + A[ri * r + idx[j]] * x[j];
+        if (j != i) d = fmadd(A[ri * r + idx[j]], x[j], d);
       S y = -(b[ri] + d) / A[ri * r + ri];
       if (val(y) < val(lo[i])) y = lo[i];
       else if (val(y) > val(hi[i])) y = hi[i];
@@ -237,7 +247,8 @@ ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* l
 // A compact working copy of one Gauss-Seidel problem, element k at p[k * st]
 // (the kernels give every lane its own column of an LDS block, the host a
 // plain array): the kept rows' block of A (m x m), b, the bounds, x, the two
-// sweep vectors the reverse reads, and the reverse's adjoints.  Every access
+// sweep vectors the reverse reads, and the reverse's adjoints of A, b and
+// the bounds (that of x stays in registers).  Every access
 // of the sweeps then reads this copy directly instead of going through the
 // kept-row index into the full record.
 template <typename S>
@@ -247,43 +258,49 @@ struct PgsStage {
   ABA_HD S& operator[](int k) const { return p[(size_t)k * st]; }
 };
 constexpr int kStA = 0, kStB = kNR * kNR, kStLo = kStB + kNR, kStHi = kStLo + kNR, kStX = kStHi + kNR,
-              kStXe = kStX + kNR, kStAb = kStXe + kNR, kStBb = kStAb + kNR * kNR, kStXb = kStBb + kNR,
-              kStLob = kStXb + kNR, kStHib = kStLob + kNR, kStage = kStHib + kNR;
+              kStXe = kStX + kNR, kStAb = kStXe + kNR, kStBb = kStAb + kNR * kNR, kStLob = kStBb + kNR,
+              kStHib = kStLob + kNR, kStage = kStHib + kNR;
 
 // pgs on a staged copy: the same statements in the same order, so the
 // result is bitwise that of pgs.
 template <typename S>
 ABA_HD void pgs_staged(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi, int niter,
                        S* x, S* sweeps, int ld, const PgsStage<S>& g) {
-  // rows of the block at stride kNR, zero beyond m: the inner loops run over
-  // all kNR columns (unrolled, predicated on j < m), so a row's loads issue
-  // together
-  for (int i = 0; i < kNR; ++i) {
+  // rows of the block at stride kNR, zero beyond m; x in registers, rows and
+  // columns unrolled over kNR and predicated on m, so the loads of A do not
+  // wait behind the sweep's updates of x
+  for (int i = 0; i < kNR; ++i)
     for (int j = 0; j < kNR; ++j) g[kStA + i * kNR + j] = (i < m && j < m) ? A[idx[i] * r + idx[j]] : S(0);
-    g[kStX + i] = S(0);
-  }
   for (int i = 0; i < m; ++i) {
     g[kStB + i] = b[idx[i]];
     g[kStLo + i] = lo[i];
     g[kStHi + i] = hi[i];
   }
+  S xr[kNR];
+#pragma unroll
+  for (int i = 0; i < kNR; ++i) xr[i] = S(0);
   for (int it = 0; it < niter; ++it) {
-    if (sweeps)
-      for (int i = 0; i < m; ++i) sweeps[it * ld + i] = g[kStX + i];
-    for (int i = 0; i < m; ++i) {
+    if (sweeps) {
+#pragma unroll
+      for (int i = 0; i < kNR; ++i)
+        if (i < m) sweeps[it * ld + i] = xr[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kNR; ++i) {
+      if (i >= m) continue;
       S d = S(0);
 #pragma unroll
-      for (int j = 0; j < kNR; ++j) {
-        const S aij = g[kStA + i * kNR + j], xj = g[kStX + j];
-        if (j < m && j != i) d = d + aij * xj;
-      }
+      for (int j = 0; j < kNR; ++j)
+        if (j < m && j != i) d = fmadd(g[kStA + i * kNR + j], xr[j], d);
       S y = -(g[kStB + i] + d) / g[kStA + i * kNR + i];
       if (val(y) < val(g[kStLo + i])) y = g[kStLo + i];
       else if (val(y) > val(g[kStHi + i])) y = g[kStHi + i];
-      g[kStX + i] = y;
+      xr[i] = y;
     }
   }
-  for (int i = 0; i < m; ++i) x[i] = g[kStX + i];
+#pragma unroll
+  for (int i = 0; i < kNR; ++i)
+    if (i < m) x[i] = xr[i];
   if (sweeps)
     for (int i = 0; i < m; ++i) sweeps[niter * ld + i] = x[i];
 }
@@ -611,13 +628,13 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
         S s = S(0);
 #pragma unroll
         for (int k = 0; k < kNV; ++k)
-          if (k < nv) s = s + Ji[k] * w.MJ[k][j];
+          if (k < nv) s = fmadd(Ji[k], w.MJ[k][j], s);
         w.A[i * r + j] = s;
       }
       S s = S(0);
 #pragma unroll
       for (int k = 0; k < kNV; ++k)
-        if (k < nv) s = s + Ji[k] * qd1[k];
+        if (k < nv) s = fmadd(Ji[k], qd1[k], s);
       w.b[i] = (i % 3 == 0) ? s + bdt * phi[i / 3] : s;
       if (val(w.A[i * r + i]) > dmax) dmax = val(w.A[i * r + i]);
     }
@@ -661,7 +678,7 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       S s = S(0);
 #pragma unroll
       for (int j = 0; j < kNR; ++j)
-        if (j < r) s = s + w.MJ[k][j] * xr[j];
+        if (j < r) s = fmadd(w.MJ[k][j], xr[j], s);
       qd1[k] = qd1[k] + s;
     }
   }
