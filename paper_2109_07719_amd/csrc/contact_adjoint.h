@@ -475,6 +475,7 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
       g[kStA + i * kNR + j] = in ? A[idx[i] * r + idx[j]] : S(0);
       g[kStAb + i * kNR + j] = in ? Ab[idx[i] * r + idx[j]] : S(0);
     }
+    g[kStB + i] = S(0);
     g[kStX + i] = S(0);
     g[kStXe + i] = S(0);
   }
@@ -498,17 +499,18 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
       g[kStXe + j] = g[kStX + j];
       g[kStX + j] = sweeps[it * ld + j];
     }
+    // (every row with no condition, so that all their loads issue
+    // together: beyond m the staged block and vectors are zero, the terms
+    // add nothing, and such a row's value, divided by one, is not used)
     S y[kNR];
 #pragma unroll
     for (int i = 0; i < kNR; ++i) {
-      y[i] = S(0);
-      if (i < m) {
-        S d = S(0);
+      S d = S(0);
 #pragma unroll
-        for (int j = 0; j < kNR; ++j)
-          if (j < m && j != i) d = fmadd(g[kStA + i * kNR + j], j < i ? g[kStXe + j] : g[kStX + j], d);
-        y[i] = -(g[kStB + i] + d) / g[kStA + i * kNR + i];
-      }
+      for (int j = 0; j < kNR; ++j)
+        if (j != i) d = fmadd(g[kStA + i * kNR + j], j < i ? g[kStXe + j] : g[kStX + j], d);
+      const S aii = g[kStA + i * kNR + i];
+      y[i] = -(g[kStB + i] + d) / (i < m ? aii : S(1));
     }
 #pragma unroll
     for (int i = kNR - 1; i >= 0; --i) {
@@ -523,7 +525,7 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
       g[kStAb + i * kNR + i] = fmadd(db, y[i], g[kStAb + i * kNR + i]);
 #pragma unroll
       for (int j = 0; j < kNR; ++j)
-        if (j < m && j != i) {
+        if (j != i) {  // beyond m: zero entries, nothing changes
           g[kStAb + i * kNR + j] = fmadd(db, j < i ? g[kStXe + j] : g[kStX + j], g[kStAb + i * kNR + j]);
           xbr[j] = fmadd(db, g[kStA + i * kNR + j], xbr[j]);
         }
@@ -620,14 +622,15 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
       S s = S(0);
       const S xj = w.x[j];
 #pragma unroll
-      for (int k = 0; k < kNV; ++k)
-        if (k < nv) {
-          s = fmadd(w.MJ[k][j], gv[k], s);
-          ad.MJb[k][j] = gv[k] * xj;
-        }
+      for (int k = 0; k < kNV; ++k) {
+        s = fmadd(w.MJ[k][j], gv[k], s);  // gv zero beyond nv
+        ad.MJb[k][j] = gv[k] * xj;
+      }
       xb[j] = s;
     }
-    for (int k = 0; k < r * r; ++k) ad.Ab[k] = S(0);
+    // (all of it: the adjoint of A below reads past r * r, times zero)
+#pragma unroll
+    for (int k = 0; k < kNR * kNR; ++k) ad.Ab[k] = S(0);
     for (int i = 0; i < r; ++i) ad.bb[i] = S(0);
     // ---- second solve (all kept rows; tangent bounds +-mu lambda_n)
     const int nk = rc.nk, nkn = rc.nkn;
@@ -676,34 +679,54 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
     const S bdt = S(tp.beta) / dt;
     S phib[kNC];
     for (int c = 0; c < na; ++c) phib[c] = S(0);
-    // (row i of A_bar, then column k of J, held in registers; the sums
-    // unrolled and predicated on r so that their loads issue together, in
-    // the same order)
+    // (row i of A_bar, then column k of J, held in registers, zero beyond r;
+    // the sums run over all kNR terms with no condition, a term beyond r
+    // being zero times a cleared or finite entry, three columns of MJ (of
+    // A_bar) per pass, so that a pass's loads issue together; each sum runs
+    // in the same order.  Every index stays inside its array: kNV and r are
+    // multiples of 3, and the rows of A_bar at stride r end before
+    // kNR * kNR.)
+    static_assert(kNV % 3 == 0, "column blocks of three");
     for (int i = 0; i < r; ++i) {
       S Abi[kNR];
 #pragma unroll
-      for (int j = 0; j < kNR; ++j) Abi[j] = j < r ? ad.Ab[i * r + j] : S(0);
+      for (int j = 0; j < kNR; ++j) {
+        const S v = ad.Ab[i * r + j];
+        Abi[j] = j < r ? v : S(0);
+      }
       const S bbi = ad.bb[i];
-      for (int k = 0; k < nv; ++k) {
-        S s = bbi * rc.qdm[k];
+      for (int k0 = 0; k0 < nv; k0 += 3) {
 #pragma unroll
-        for (int j = 0; j < kNR; ++j)
-          if (j < r) s = fmadd(Abi[j], w.MJ[k][j], s);
-        ad.Jb[i][k] = s;
-        qdmb[k] = fmadd(w.J[i][k], bbi, qdmb[k]);
+        for (int kk = 0; kk < 3; ++kk) {
+          const int k = k0 + kk;
+          S s = bbi * rc.qdm[k];
+#pragma unroll
+          for (int j = 0; j < kNR; ++j) s = fmadd(Abi[j], w.MJ[k][j], s);
+          const S jik = w.J[i][k];
+          if (k < nv) {
+            ad.Jb[i][k] = s;
+            qdmb[k] = fmadd(jik, bbi, qdmb[k]);
+          }
+        }
       }
       if (i % 3 == 0) phib[i / 3] = phib[i / 3] + bdt * bbi;
     }
     for (int k = 0; k < nv; ++k) {
       S Jk[kNR];
 #pragma unroll
-      for (int i = 0; i < kNR; ++i) Jk[i] = i < r ? w.J[i][k] : S(0);
-      for (int j = 0; j < r; ++j) {
-        S s = S(0);
+      for (int i = 0; i < kNR; ++i) {
+        const S v = w.J[i][k];
+        Jk[i] = i < r ? v : S(0);
+      }
+      for (int j0 = 0; j0 < r; j0 += 3) {
 #pragma unroll
-        for (int i = 0; i < kNR; ++i)
-          if (i < r) s = fmadd(Jk[i], ad.Ab[i * r + j], s);
-        ad.MJb[k][j] = ad.MJb[k][j] + s;
+        for (int jj = 0; jj < 3; ++jj) {
+          const int j = j0 + jj;
+          S s = S(0);
+#pragma unroll
+          for (int i = 0; i < kNR; ++i) s = fmadd(Jk[i], ad.Ab[i * r + j], s);
+          ad.MJb[k][j] = ad.MJb[k][j] + s;
+        }
       }
     }
     // ---- MJ = M^-1 J^T: W = M^-1 MJ_bar; J_bar += W^T; q_bar -= d/dq <W, M(q) MJ>

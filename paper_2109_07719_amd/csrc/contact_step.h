@@ -266,9 +266,10 @@ constexpr int kStA = 0, kStB = kNR * kNR, kStLo = kStB + kNR, kStHi = kStLo + kN
 template <typename S>
 ABA_HD void pgs_staged(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi, int niter,
                        S* x, S* sweeps, int ld, const PgsStage<S>& g) {
-  // rows of the block at stride kNR, zero beyond m; x in registers, rows and
-  // columns unrolled over kNR and predicated on m, so the loads of A do not
-  // wait behind the sweep's updates of x
+  // rows of the block at stride kNR, zero beyond m; x in registers (zero
+  // beyond m), rows unrolled over kNR and predicated on m, every row's sum
+  // over all kNR columns with no condition (the terms beyond m add zero), so
+  // that a row's loads issue together
   for (int i = 0; i < kNR; ++i)
     for (int j = 0; j < kNR; ++j) g[kStA + i * kNR + j] = (i < m && j < m) ? A[idx[i] * r + idx[j]] : S(0);
   for (int i = 0; i < m; ++i) {
@@ -291,7 +292,7 @@ ABA_HD void pgs_staged(int m, const int* idx, int r, const S* A, const S* b, con
       S d = S(0);
 #pragma unroll
       for (int j = 0; j < kNR; ++j)
-        if (j < m && j != i) d = fmadd(g[kStA + i * kNR + j], xr[j], d);
+        if (j != i) d = fmadd(g[kStA + i * kNR + j], xr[j], d);  // zero beyond m
       S y = -(g[kStB + i] + d) / g[kStA + i * kNR + i];
       if (val(y) < val(g[kStLo + i])) y = g[kStLo + i];
       else if (val(y) > val(g[kStHi + i])) y = g[kStHi + i];
@@ -611,30 +612,45 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
         }
       }
     }
-    // M^-1 J^T: response to a unit world force along each row's direction at the contact point
+    // M^-1 J^T: response to a unit world force along each row's direction at
+    // the contact point.  MJ is cleared first: the sums below run over all
+    // kNR columns and kNV rows, their unused terms multiplied by zero, which
+    // needs those entries finite.
+#pragma unroll
+    for (int k = 0; k < kNV; ++k)
+#pragma unroll
+      for (int j = 0; j < kNR; ++j) w.MJ[k][j] = S(0);
     if (art) unit_responses(tp, w, *art, na, act, cl);
     else unit_responses(tp, w, w, na, act, cl);
     // A = J M^-1 J^T, b = J qd_minus + (beta/dt) phi (normal rows)
     const S bdt = S(tp.beta) / dt;
     Rl dmax = Rl(0);
     for (int i = 0; i < r; ++i) {
-      // row i of J held in registers; the sums over k unrolled and
-      // predicated on nv, so that their loads issue together (the same
-      // operations in the same order)
+      // row i of J held in registers, zero beyond nv; the sums over k run
+      // over all kNV terms with no condition (a term beyond nv is zero times
+      // a cleared entry, adding nothing), three columns of MJ per pass (r is
+      // a multiple of 3), so that a pass's loads issue together; a load
+      // under a lane-dependent condition would wait on its own
       S Ji[kNV];
 #pragma unroll
-      for (int k = 0; k < kNV; ++k) Ji[k] = k < nv ? w.J[i][k] : S(0);
-      for (int j = 0; j < r; ++j) {
-        S s = S(0);
+      for (int k = 0; k < kNV; ++k) {
+        const S v = w.J[i][k];
+        Ji[k] = k < nv ? v : S(0);
+      }
+      for (int j0 = 0; j0 < r; j0 += 3) {
 #pragma unroll
-        for (int k = 0; k < kNV; ++k)
-          if (k < nv) s = fmadd(Ji[k], w.MJ[k][j], s);
-        w.A[i * r + j] = s;
+        for (int jj = 0; jj < 3; ++jj) {
+          const int j = j0 + jj;
+          S s = S(0);
+#pragma unroll
+          for (int k = 0; k < kNV; ++k) s = fmadd(Ji[k], w.MJ[k][j], s);
+          w.A[i * r + j] = s;
+        }
       }
       S s = S(0);
 #pragma unroll
       for (int k = 0; k < kNV; ++k)
-        if (k < nv) s = fmadd(Ji[k], qd1[k], s);
+        if (k < nv) s = fmadd(Ji[k], qd1[k], s);  // qd1 may hold only nv entries
       w.b[i] = (i % 3 == 0) ? s + bdt * phi[i / 3] : s;
       if (val(w.A[i * r + i]) > dmax) dmax = val(w.A[i * r + i]);
     }
@@ -673,12 +689,14 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
     for (int i = 0; i < nk; ++i) w.x[keep[i]] = xk[i];
     S xr[kNR];
 #pragma unroll
-    for (int j = 0; j < kNR; ++j) xr[j] = j < r ? w.x[j] : S(0);
+    for (int j = 0; j < kNR; ++j) {
+      const S v = w.x[j];
+      xr[j] = j < r ? v : S(0);
+    }
     for (int k = 0; k < nv; ++k) {
       S s = S(0);
 #pragma unroll
-      for (int j = 0; j < kNR; ++j)
-        if (j < r) s = fmadd(w.MJ[k][j], xr[j], s);
+      for (int j = 0; j < kNR; ++j) s = fmadd(w.MJ[k][j], xr[j], s);
       qd1[k] = qd1[k] + s;
     }
   }
