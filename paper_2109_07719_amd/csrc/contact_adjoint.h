@@ -563,7 +563,8 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
   contact_step(tp, P, q, qd, u, dt_, mu, q1, qd1, w, &rc, stage, &art);
   const S dt = S(dt_);
   S qb[kNQ], qdb[kNV], qd1b[kNV], qdmb[kNV];
-  for (int k = 0; k < nq; ++k) qb[k] = S(0);
+#pragma unroll
+  for (int k = 0; k < kNQ; ++k) qb[k] = S(0);
   for (int k = 0; k < nv; ++k) {
     qdb[k] = S(0);
     qd1b[k] = xbar[nq + k];
@@ -730,18 +731,26 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
       }
     }
     // ---- MJ = M^-1 J^T: W = M^-1 MJ_bar; J_bar += W^T; q_bar -= d/dq <W, M(q) MJ>
+    // (the copies and sums run over all kNV / kNQ entries with no
+    // condition, so that their loads issue together; the entries beyond nv
+    // and nq are zero or never read)
     for (int j = 0; j < r; ++j) {
       S col[kNV], Wj[kNV], mj[kNV];
-      for (int k = 0; k < nv; ++k) {
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) {
         col[k] = ad.MJb[k][j];
         mj[k] = w.MJ[k][j];
+        Wj[k] = S(0);
       }
       minv_apply(tp, art, col, Wj);
-      for (int k = 0; k < nv; ++k) ad.Jb[j][k] = ad.Jb[j][k] + Wj[k];
+#pragma unroll
+      for (int k = 0; k < kNV; ++k) ad.Jb[j][k] = ad.Jb[j][k] + Wj[k];
       S gqj[kNQ];
-      for (int k = 0; k < nq; ++k) gqj[k] = S(0);
+#pragma unroll
+      for (int k = 0; k < kNQ; ++k) gqj[k] = S(0);
       id_vjp_static(tp, art, mj, Wj, gqj);
-      for (int k = 0; k < nq; ++k) qb[k] = qb[k] - gqj[k];
+#pragma unroll
+      for (int k = 0; k < kNQ; ++k) qb[k] = qb[k] - gqj[k];
     }
     // ---- contact rows and gaps through the world poses
     for (int i = 0; i < n; ++i) {
