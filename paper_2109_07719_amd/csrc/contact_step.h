@@ -649,8 +649,8 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
       }
       S s = S(0);
 #pragma unroll
-      for (int k = 0; k < kNV; ++k)
-        if (k < nv) s = fmadd(Ji[k], qd1[k], s);  // qd1 may hold only nv entries
+      for (int k = 0; k < kNV; ++k)  // qd1 may hold only nv entries: past them qd1[0], times zero
+        s = fmadd(Ji[k], qd1[k < nv ? k : 0], s);
       w.b[i] = (i % 3 == 0) ? s + bdt * phi[i / 3] : s;
       if (val(w.A[i * r + i]) > dmax) dmax = val(w.A[i * r + i]);
     }
