@@ -469,11 +469,20 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
                                int niter, const S* sweeps, int ld, S* xb, S* Ab, S* bb, S* lob, S* hib,
                                const PgsStage<S>& g) {
   // as in pgs_staged: rows at stride kNR, zero beyond m
+  // (the kept rows' indices, 0 beyond m, address valid entries of A and
+  // A_bar, so the copies read them with no condition and their loads issue
+  // together)
+  int ix[kNR];
+#pragma unroll
+  for (int i = 0; i < kNR; ++i) ix[i] = i < m ? idx[i] : 0;
+#pragma unroll
   for (int i = 0; i < kNR; ++i) {
+#pragma unroll
     for (int j = 0; j < kNR; ++j) {
       const bool in = i < m && j < m;
-      g[kStA + i * kNR + j] = in ? A[idx[i] * r + idx[j]] : S(0);
-      g[kStAb + i * kNR + j] = in ? Ab[idx[i] * r + idx[j]] : S(0);
+      const S aij = A[ix[i] * r + ix[j]], abij = Ab[ix[i] * r + ix[j]];
+      g[kStA + i * kNR + j] = in ? aij : S(0);
+      g[kStAb + i * kNR + j] = in ? abij : S(0);
     }
     g[kStB + i] = S(0);
     g[kStX + i] = S(0);

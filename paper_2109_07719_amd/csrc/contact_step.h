@@ -270,8 +270,18 @@ ABA_HD void pgs_staged(int m, const int* idx, int r, const S* A, const S* b, con
   // beyond m), rows unrolled over kNR and predicated on m, every row's sum
   // over all kNR columns with no condition (the terms beyond m add zero), so
   // that a row's loads issue together
+  // (the kept rows' indices, 0 beyond m, address a valid entry of A, so the
+  // copy reads A with no condition and its loads issue together)
+  int ix[kNR];
+#pragma unroll
+  for (int i = 0; i < kNR; ++i) ix[i] = i < m ? idx[i] : 0;
+#pragma unroll
   for (int i = 0; i < kNR; ++i)
-    for (int j = 0; j < kNR; ++j) g[kStA + i * kNR + j] = (i < m && j < m) ? A[idx[i] * r + idx[j]] : S(0);
+#pragma unroll
+    for (int j = 0; j < kNR; ++j) {
+      const S aij = A[ix[i] * r + ix[j]];
+      g[kStA + i * kNR + j] = (i < m && j < m) ? aij : S(0);
+    }
   for (int i = 0; i < m; ++i) {
     g[kStB + i] = b[idx[i]];
     g[kStLo + i] = lo[i];
