@@ -225,21 +225,39 @@ ABA_HD void ldl6_solve(const S* L, const S* D, const S* rhs, S* x) {
 template <typename S>
 ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* lo, const S* hi, int niter, S* x,
                 S* sweeps = nullptr, int ld = 0) {
-  for (int i = 0; i < m; ++i) x[i] = S(0);
+  // x in registers, rows and columns unrolled over kNR: the kept rows'
+  // indices, 0 beyond m, address valid entries of A, and x stays zero beyond
+  // m, so every term of a row's sum runs with no condition (past m it adds
+  // zero, the same sum in the same order) and the row's loads issue together
+  int ix[kNR];
+#pragma unroll
+  for (int i = 0; i < kNR; ++i) ix[i] = i < m ? idx[i] : 0;
+  S xr[kNR];
+#pragma unroll
+  for (int i = 0; i < kNR; ++i) xr[i] = S(0);
   for (int it = 0; it < niter; ++it) {
-    if (sweeps)
-      for (int i = 0; i < m; ++i) sweeps[it * ld + i] = x[i];
-    for (int i = 0; i < m; ++i) {
-      const int ri = idx[i];
+    if (sweeps) {
+#pragma unroll
+      for (int i = 0; i < kNR; ++i)
+        if (i < m) sweeps[it * ld + i] = xr[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kNR; ++i) {
+      if (i >= m) continue;
+      const S* Ai = A + ix[i] * r;
       S d = S(0);
-      for (int j = 0; j < m; ++j)
-        if (j != i) d = fmadd(A[ri * r + idx[j]], x[j], d);
-      S y = -(b[ri] + d) / A[ri * r + ri];
+#pragma unroll
+      for (int j = 0; j < kNR; ++j)
+        if (j != i) d = fmadd(Ai[ix[j]], xr[j], d);
+      S y = -(b[ix[i]] + d) / Ai[ix[i]];
       if (val(y) < val(lo[i])) y = lo[i];
       else if (val(y) > val(hi[i])) y = hi[i];
-      x[i] = y;
+      xr[i] = y;
     }
   }
+#pragma unroll
+  for (int i = 0; i < kNR; ++i)
+    if (i < m) x[i] = xr[i];
   if (sweeps)
     for (int i = 0; i < m; ++i) sweeps[niter * ld + i] = x[i];
 }
