@@ -68,6 +68,11 @@ inline bool operator>(CD a, CD b) { return a.v > b.v; }
 inline CD val(CD x) { return x; }
 inline CD sq_root(CD x) { return cd_(std::sqrt(x.v)); }
 inline void sin_cos(CD x, CD& s, CD& c) { s = cd_(std::sin(x.v)); c = cd_(std::cos(x.v)); }
+// the terms of an unrolled sum past its true length are not counted
+inline CD fmadd_pad(CD a, CD b, CD c, bool live) { return live ? a * b + c : c; }
+inline CD mul_pad(CD a, CD b, bool live) { return live ? a * b : CD(0); }
+inline CD add_pad(CD a, CD b, bool live) { return live ? a + b : a; }
+inline CD sub_pad(CD a, CD b, bool live) { return live ? a - b : a; }
 
 }  // namespace
 

@@ -517,7 +517,7 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
       S d = S(0);
 #pragma unroll
       for (int j = 0; j < kNR; ++j)
-        if (j != i) d = fmadd(g[kStA + i * kNR + j], j < i ? g[kStXe + j] : g[kStX + j], d);
+        if (j != i) d = fmadd_pad(g[kStA + i * kNR + j], j < i ? g[kStXe + j] : g[kStX + j], d, i < m && j < m);
       const S aii = g[kStA + i * kNR + i];
       y[i] = -(g[kStB + i] + d) / (i < m ? aii : S(1));
     }
@@ -535,8 +535,8 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
 #pragma unroll
       for (int j = 0; j < kNR; ++j)
         if (j != i) {  // beyond m: zero entries, nothing changes
-          g[kStAb + i * kNR + j] = fmadd(db, j < i ? g[kStXe + j] : g[kStX + j], g[kStAb + i * kNR + j]);
-          xbr[j] = fmadd(db, g[kStA + i * kNR + j], xbr[j]);
+          g[kStAb + i * kNR + j] = fmadd_pad(db, j < i ? g[kStXe + j] : g[kStX + j], g[kStAb + i * kNR + j], j < m);
+          xbr[j] = fmadd_pad(db, g[kStA + i * kNR + j], xbr[j], j < m);
         }
     }
   }
@@ -633,8 +633,8 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
       const S xj = w.x[j];
 #pragma unroll
       for (int k = 0; k < kNV; ++k) {
-        s = fmadd(w.MJ[k][j], gv[k], s);  // gv zero beyond nv
-        ad.MJb[k][j] = gv[k] * xj;
+        s = fmadd_pad(w.MJ[k][j], gv[k], s, k < nv);  // gv zero beyond nv
+        ad.MJb[k][j] = mul_pad(gv[k], xj, k < nv);
       }
       xb[j] = s;
     }
@@ -709,9 +709,9 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
 #pragma unroll
         for (int kk = 0; kk < 3; ++kk) {
           const int k = k0 + kk;
-          S s = bbi * rc.qdm[k];
+          S s = mul_pad(bbi, rc.qdm[k], k < nv);
 #pragma unroll
-          for (int j = 0; j < kNR; ++j) s = fmadd(Abi[j], w.MJ[k][j], s);
+          for (int j = 0; j < kNR; ++j) s = fmadd_pad(Abi[j], w.MJ[k][j], s, j < r && k < nv);
           const S jik = w.J[i][k];
           if (k < nv) {
             ad.Jb[i][k] = s;
@@ -734,7 +734,7 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
           const int j = j0 + jj;
           S s = S(0);
 #pragma unroll
-          for (int i = 0; i < kNR; ++i) s = fmadd(Jk[i], ad.Ab[i * r + j], s);
+          for (int i = 0; i < kNR; ++i) s = fmadd_pad(Jk[i], ad.Ab[i * r + j], s, i < r);
           ad.MJb[k][j] = ad.MJb[k][j] + s;
         }
       }
@@ -753,13 +753,13 @@ ABA_HD void contact_step_vjp(const CTopo& tp, const Par<R>& P, const S* q, const
       }
       minv_apply(tp, art, col, Wj);
 #pragma unroll
-      for (int k = 0; k < kNV; ++k) ad.Jb[j][k] = ad.Jb[j][k] + Wj[k];
+      for (int k = 0; k < kNV; ++k) ad.Jb[j][k] = add_pad(ad.Jb[j][k], Wj[k], k < nv);
       S gqj[kNQ];
 #pragma unroll
       for (int k = 0; k < kNQ; ++k) gqj[k] = S(0);
       id_vjp_static(tp, art, mj, Wj, gqj);
 #pragma unroll
-      for (int k = 0; k < kNQ; ++k) qb[k] = qb[k] - gqj[k];
+      for (int k = 0; k < kNQ; ++k) qb[k] = sub_pad(qb[k], gqj[k], k < nq);
     }
     // ---- contact rows and gaps through the world poses
     for (int i = 0; i < n; ++i) {

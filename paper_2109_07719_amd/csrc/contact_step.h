@@ -65,6 +65,18 @@ ABA_HD float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); 
 ABA_HD double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
 template <typename T>  // dual numbers, the operation counter
 ABA_HD T fmadd(const T& a, const T& b, const T& c) { return a * b + c; }
+// A term of a sum unrolled past its true length: live is false past it.
+// The kernels compute every term (one past the true length multiplies a zero
+// by a finite entry and adds nothing), so no load waits on a condition; the
+// operation counter overloads these to count only the live terms.
+template <typename T>
+ABA_HD T fmadd_pad(const T& a, const T& b, const T& c, bool) { return fmadd(a, b, c); }
+template <typename T>
+ABA_HD T mul_pad(const T& a, const T& b, bool) { return a * b; }
+template <typename T>
+ABA_HD T add_pad(const T& a, const T& b, bool) { return a + b; }
+template <typename T>
+ABA_HD T sub_pad(const T& a, const T& b, bool) { return a - b; }
 
 template <typename R> struct Big;
 template <> struct Big<float> { static constexpr float v = FLT_MAX; };
@@ -248,7 +260,7 @@ ABA_HD void pgs(int m, const int* idx, int r, const S* A, const S* b, const S* l
       S d = S(0);
 #pragma unroll
       for (int j = 0; j < kNR; ++j)
-        if (j != i) d = fmadd(Ai[ix[j]], xr[j], d);
+        if (j != i) d = fmadd_pad(Ai[ix[j]], xr[j], d, j < m);
       S y = -(b[ix[i]] + d) / Ai[ix[i]];
       if (val(y) < val(lo[i])) y = lo[i];
       else if (val(y) > val(hi[i])) y = hi[i];
@@ -320,7 +332,7 @@ ABA_HD void pgs_staged(int m, const int* idx, int r, const S* A, const S* b, con
       S d = S(0);
 #pragma unroll
       for (int j = 0; j < kNR; ++j)
-        if (j != i) d = fmadd(g[kStA + i * kNR + j], xr[j], d);  // zero beyond m
+        if (j != i) d = fmadd_pad(g[kStA + i * kNR + j], xr[j], d, j < m);  // zero beyond m
       S y = -(g[kStB + i] + d) / g[kStA + i * kNR + i];
       if (val(y) < val(g[kStLo + i])) y = g[kStLo + i];
       else if (val(y) > val(g[kStHi + i])) y = g[kStHi + i];
@@ -671,14 +683,14 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
           const int j = j0 + jj;
           S s = S(0);
 #pragma unroll
-          for (int k = 0; k < kNV; ++k) s = fmadd(Ji[k], w.MJ[k][j], s);
+          for (int k = 0; k < kNV; ++k) s = fmadd_pad(Ji[k], w.MJ[k][j], s, k < nv);
           w.A[i * r + j] = s;
         }
       }
       S s = S(0);
 #pragma unroll
       for (int k = 0; k < kNV; ++k)  // qd1 may hold only nv entries: past them qd1[0], times zero
-        s = fmadd(Ji[k], qd1[k < nv ? k : 0], s);
+        s = fmadd_pad(Ji[k], qd1[k < nv ? k : 0], s, k < nv);
       w.b[i] = (i % 3 == 0) ? s + bdt * phi[i / 3] : s;
       if (val(w.A[i * r + i]) > dmax) dmax = val(w.A[i * r + i]);
     }
@@ -724,7 +736,7 @@ ABA_HD int contact_step(const CTopo& tp, const Par<R>& P, const S* q, const S* q
     for (int k = 0; k < nv; ++k) {
       S s = S(0);
 #pragma unroll
-      for (int j = 0; j < kNR; ++j) s = fmadd(w.MJ[k][j], xr[j], s);
+      for (int j = 0; j < kNR; ++j) s = fmadd_pad(w.MJ[k][j], xr[j], s, j < r);
       qd1[k] = qd1[k] + s;
     }
   }
