@@ -500,13 +500,21 @@ ABA_HD void pgs_reverse_staged(int m, const int* idx, int r, const S* A, const S
   S xbr[kNR];
 #pragma unroll
   for (int i = 0; i < kNR; ++i) xbr[i] = i < m ? xb[i] : S(0);
-  for (int j = 0; j < m; ++j) g[kStX + j] = sweeps[niter * ld + j];
+  // (a sweep row is read with the index clamped below m, so its loads carry
+  // no condition and issue together; the staged entries past m stay zero)
+#pragma unroll
+  for (int j = 0; j < kNR; ++j) {
+    const S v = sweeps[niter * ld + (j < m ? j : 0)];
+    g[kStX + j] = j < m ? v : S(0);
+  }
   for (int it = niter - 1; it >= 0; --it) {
     // x at the start (xs) and at the end (xe) of sweep it; xe is the
     // previous sweep's xs, already staged
-    for (int j = 0; j < m; ++j) {
+#pragma unroll
+    for (int j = 0; j < kNR; ++j) {
+      const S v = sweeps[it * ld + (j < m ? j : 0)];
       g[kStXe + j] = g[kStX + j];
-      g[kStX + j] = sweeps[it * ld + j];
+      g[kStX + j] = j < m ? v : S(0);
     }
     // (every row with no condition, so that all their loads issue
     // together: beyond m the staged block and vectors are zero, the terms
